@@ -1,0 +1,611 @@
+/*
+ * FP64 CPU oracle for the separable N-point correlation function estimator of
+ * Philcox & Slepian, "Efficient Computation of N-Point Correlation Functions in
+ * D Dimensions" (arXiv:2106.10278).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, deliberately
+ * unoptimised restatement of the paper's definitions in double precision.  It
+ * shares no code, header, table or constant with the GPU library in
+ * paper_2106_10278_amd/.  Only tests/, __graft_entry__.smoke() and bench.py's
+ * cpu_baseline leg may load it; the product path never calls it.
+ *
+ * What it computes (section "Application to Discrete Data", eq.
+ * NPCF-estimator-discrete):
+ *
+ *   a^b_[l](y_j) = 1/v_b * sum_k w_k conj(Y_[l](unit(y_k - y_j))) Theta^b(|y_k - y_j|)
+ *   zeta^{Lambda,b} = 1/V_D * sum_j w_j sum_{[l^1]..[l^{N-1}]} C^{Lambda;0} prod_i a^{b_i}_{[l^i]}(y_j)
+ *
+ * with
+ *  - Y the hyperspherical harmonics of Appendix A, eq. hypersph-def (Ferrers
+ *    functions of the first kind, DLMF 14.3), azimuth factor e^{+i l1 theta1}
+ *    as in the D=2/D=3 closed forms of section "Hyperspherical Harmonics";
+ *  - index sets |l1| <= l2 <= ... <= l_{D-1} <= lmax (eq. selection-rules,
+ *    read so that it agrees with the state-count formula of section
+ *    "Connection to Angular Momentum Eigenstates");
+ *  - C the coupling coefficient of eq. Coupling-C with vec L = 0, built from
+ *    the Clebsch-Gordan coefficients of eq. CG-examples (D=2: Kronecker delta;
+ *    D=3: Wigner 3-j).  For D>=4 and N=3 only the coupling of two states to
+ *    zero is needed; the paper gives no SO(D) formula for it, so the oracle
+ *    uses (-1)^{l_{D-1}-l1} / sqrt(dim_D(l_{D-1})) * delta([l'], (-l1,l2,..)),
+ *    which reduces to the 3-j value in D=3 (parity of the per-l sign in D>=4 is
+ *    a convention: parity unpinned by the paper for that sign);
+ *  - top-hat bins Theta^b(r) = 1 iff e_b <= r < e_{b+1}, compared on squared
+ *    distances; v_b = |S^{D-1}| (e_{b+1}^D - e_b^D) / D;
+ *  - periodic minimum-image separations when cfg->periodic is set.
+ *
+ * The unrestricted sum over secondaries k runs over all n points for every
+ * primary (brute force, no cell grid); the self pair is excluded because
+ * edges[0] > 0.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int D, N, lmax, nbins;
+    const double *edges;  /* nbins+1, strictly increasing, edges[0] > 0 */
+    double box[4];        /* box side per axis (also V_D = product of sides) */
+    int periodic;         /* 1: minimum-image separations */
+    int btuple_mode;      /* 0: b1 < b2 < ... ; 1: every tuple */
+} oracle_cfg;
+
+enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* Index sets                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* All [l] = (l1, ..., l_{D-1}) with |l1| <= l2 <= ... <= l_{D-1} <= lmax
+ * (D >= 3) or |l1| <= lmax (D = 2).  Order: lexicographic in
+ * (l_{D-1}, l_{D-2}, ..., l1).  Labels are stored l1 first. */
+static int enum_states(int D, int lmax, int *lab)
+{
+    int cnt = 0;
+    if (D == 2) {
+        for (int l1 = -lmax; l1 <= lmax; l1++) {
+            if (lab) lab[cnt] = l1;
+            cnt++;
+        }
+        return cnt;
+    }
+    if (D == 3) {
+        for (int l2 = 0; l2 <= lmax; l2++)
+            for (int l1 = -l2; l1 <= l2; l1++) {
+                if (lab) { lab[2 * cnt] = l1; lab[2 * cnt + 1] = l2; }
+                cnt++;
+            }
+        return cnt;
+    }
+    if (D == 4) {
+        for (int l3 = 0; l3 <= lmax; l3++)
+            for (int l2 = 0; l2 <= l3; l2++)
+                for (int l1 = -l2; l1 <= l2; l1++) {
+                    if (lab) { lab[3 * cnt] = l1; lab[3 * cnt + 1] = l2; lab[3 * cnt + 2] = l3; }
+                    cnt++;
+                }
+        return cnt;
+    }
+    return -1;
+}
+
+int oracle_num_states(int D, int lmax) { return enum_states(D, lmax, NULL); }
+int oracle_state_labels(int D, int lmax, int *lab) { return enum_states(D, lmax, lab); }
+
+/* ------------------------------------------------------------------------ */
+/* Hyperspherical harmonics (Appendix A, eq. hypersph-def)                  */
+/* ------------------------------------------------------------------------ */
+
+static double lfact(int n) { return lgamma((double)n + 1.0); }
+
+/* Ferrers function of the first kind of negative order, divided by
+ * (1-x^2)^{mu/2}:  R(mu, nu, x) = P^{-mu}_nu(x) / (1-x^2)^{mu/2}, for
+ * nu - mu = 0, 1, 2, ...  Uses the closed form at nu = mu,
+ * P^{-mu}_mu(x) = (1-x^2)^{mu/2} / (2^mu Gamma(mu+1)), and the three-term
+ * recurrence in the degree (DLMF 14.10.3 with mu -> -mu):
+ *   (nu+mu+1) P^{-mu}_{nu+1} = (2 nu + 1) x P^{-mu}_nu - (nu - mu) P^{-mu}_{nu-1}.
+ * The common factor (1-x^2)^{mu/2} passes through the linear recurrence. */
+static double ferrers_reduced(double mu, int n, double x)
+{
+    double r_prev = 0.0;
+    double r = exp(-mu * log(2.0) - lgamma(mu + 1.0));
+    double nu = mu;
+    for (int k = 0; k < n; k++) {
+        double r_next = ((2.0 * nu + 1.0) * x * r - (nu - mu) * r_prev) / (nu + mu + 1.0);
+        r_prev = r;
+        r = r_next;
+        nu += 1.0;
+    }
+    return r;
+}
+
+/* P^{-mu}_nu(x) itself, for tests (mu >= 0, nu - mu a non-negative integer). */
+double oracle_ferrers_neg(double mu, int n, double x)
+{
+    return ferrers_reduced(mu, n, x) * pow(1.0 - x * x, 0.5 * mu);
+}
+
+/* Theta_K(theta_K) for K >= 2 of eq. hypersph-def, given cos and sin of the
+ * angle, l_{K-1} = lm (signed only when K = 2) and l_K = l. */
+static double theta_factor(int K, int lm, int l, double c, double s)
+{
+    double norm2 = 0.5 * (2.0 * l + K - 1.0) * exp(lfact(l + lm + K - 2) - lfact(l - lm));
+    double norm = sqrt(norm2);
+    if (lm >= 0) {
+        /* sin^{1-K/2} * P^{-(lm+K/2-1)}_{l+K/2-1}(c)
+         *   = sin^{lm} * R(lm+K/2-1, l-lm, c) */
+        double mu = lm + 0.5 * K - 1.0;
+        return norm * pow(s, (double)lm) * ferrers_reduced(mu, l - lm, c);
+    }
+    /* K = 2 and l1 < 0: positive order |l1|.  DLMF 14.9.3 with integer
+     * order m = |l1|: P^{m}_nu = (-1)^m Gamma(nu+m+1)/Gamma(nu-m+1) P^{-m}_nu. */
+    int m = -lm;
+    double sign = (m & 1) ? -1.0 : 1.0;
+    double ratio = exp(lfact(l + m) - lfact(l - m));
+    return norm * sign * ratio * pow(s, (double)m) * ferrers_reduced((double)m, l - m, c);
+}
+
+/* Y_[l](xhat) for every state of enum_states(D, lmax), for a non-zero vector
+ * x of length D (need not be normalised).  Coordinates (Fig. 1 caption):
+ * cos(theta_K) = x_{K+1} / |x_{1..K+1}|, sin(theta_K) = |x_{1..K}| / |x_{1..K+1}|
+ * for K >= 2 and theta_1 = atan2(x_2, x_1). */
+int oracle_harmonics(int D, int lmax, const double *x, double *yre, double *yim)
+{
+    if (D < 2 || D > 4) return OR_EUNSUP;
+    double rho[5];
+    rho[1] = fabs(x[0]);
+    double acc = x[0] * x[0];
+    for (int k = 2; k <= D; k++) {
+        acc += x[k - 1] * x[k - 1];
+        rho[k] = sqrt(acc);
+    }
+    double c1 = 1.0, s1 = 0.0;
+    if (rho[2] > 0.0) { c1 = x[0] / rho[2]; s1 = x[1] / rho[2]; }
+    double cK[5], sK[5];
+    for (int K = 2; K <= D - 1; K++) {
+        if (rho[K + 1] > 0.0) { cK[K] = x[K] / rho[K + 1]; sK[K] = rho[K] / rho[K + 1]; }
+        else { cK[K] = 1.0; sK[K] = 0.0; }
+    }
+    int nst = enum_states(D, lmax, NULL);
+    int *lab = (int *)malloc(sizeof(int) * (size_t)nst * (size_t)(D - 1));
+    if (!lab) return OR_ENOMEM;
+    enum_states(D, lmax, lab);
+    const double inv_sqrt_2pi = 1.0 / sqrt(2.0 * M_PI);
+    for (int s = 0; s < nst; s++) {
+        const int *L = lab + (size_t)s * (D - 1);
+        int l1 = L[0];
+        /* e^{i l1 theta_1} = (cos theta_1 + i sin theta_1)^{l1} */
+        double er = 1.0, ei = 0.0;
+        int al = l1 < 0 ? -l1 : l1;
+        for (int k = 0; k < al; k++) {
+            double t = er * c1 - ei * s1;
+            ei = er * s1 + ei * c1;
+            er = t;
+        }
+        if (l1 < 0) ei = -ei;
+        double mag = inv_sqrt_2pi;
+        for (int K = 2; K <= D - 1; K++) mag *= theta_factor(K, L[K - 2], L[K - 1], cK[K], sK[K]);
+        yre[s] = mag * er;
+        yim[s] = mag * ei;
+    }
+    free(lab);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coupling coefficients                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Wigner 3-j symbol by Racah's single-sum formula (DLMF 34.2.4). */
+double oracle_wigner3j(int j1, int j2, int j3, int m1, int m2, int m3)
+{
+    if (m1 + m2 + m3 != 0) return 0.0;
+    if (j3 < abs(j1 - j2) || j3 > j1 + j2) return 0.0;
+    if (abs(m1) > j1 || abs(m2) > j2 || abs(m3) > j3) return 0.0;
+    double ldelta = 0.5 * (lfact(j1 + j2 - j3) + lfact(j1 - j2 + j3) + lfact(-j1 + j2 + j3) - lfact(j1 + j2 + j3 + 1));
+    double lroot = 0.5 * (lfact(j1 + m1) + lfact(j1 - m1) + lfact(j2 + m2) + lfact(j2 - m2) + lfact(j3 + m3) + lfact(j3 - m3));
+    double sum = 0.0;
+    for (int s = 0; s <= j1 + j2 + j3; s++) {
+        int a1 = j1 + j2 - j3 - s, a2 = j1 - m1 - s, a3 = j2 + m2 - s, a4 = j3 - j2 + m1 + s, a5 = j3 - j1 - m2 + s;
+        if (a1 < 0 || a2 < 0 || a3 < 0 || a4 < 0 || a5 < 0) continue;
+        double t = exp(ldelta + lroot - lfact(s) - lfact(a1) - lfact(a2) - lfact(a3) - lfact(a4) - lfact(a5));
+        sum += (s & 1) ? -t : t;
+    }
+    int ph = j1 - j2 - m3;
+    return (ph & 1) ? -sum : sum;
+}
+
+/* Clebsch-Gordan coefficient of eq. CG-examples for D = 3, written with the
+ * paper's index order: state (l1 = m, l2 = l).
+ *   <m1 j1, m2 j2 | M J> = (-1)^{-j1+j2-M} sqrt(2J+1) (j1 j2 J; m1 m2 -M) */
+double oracle_cg3(int j1, int m1, int j2, int m2, int J, int M)
+{
+    double t = sqrt(2.0 * J + 1.0) * oracle_wigner3j(j1, j2, J, m1, m2, -M);
+    int ph = -j1 + j2 - M;
+    return (ph & 1) ? -t : t;
+}
+
+/* dim_D(l): number of states of total angular momentum l (section
+ * "Connection to Angular Momentum Eigenstates"). */
+static double dim_states(int D, int l)
+{
+    if (D == 2) return 1.0;
+    if (D == 3) return 2.0 * l + 1.0;
+    /* binom(l+D-3, D-3) (2l+D-2)/(D-2) */
+    double b = exp(lfact(l + D - 3) - lfact(D - 3) - lfact(l));
+    return b * (2.0 * l + D - 2.0) / (D - 2.0);
+}
+
+double oracle_dim_states(int D, int l) { return dim_states(D, l); }
+
+/* Coupling of two states to vec L = 0 (N = 3). */
+static double couple_pair_to_zero(int D, const int *s1, const int *s2)
+{
+    if (D == 2) return (s1[0] + s2[0] == 0) ? 1.0 : 0.0;
+    if (D == 3) return oracle_cg3(s1[1], s1[0], s2[1], s2[0], 0, 0);
+    /* D >= 4: delta([l'], (-l1, l2, ..)) (-1)^{l_{D-1} - l1} / sqrt(dim) */
+    if (s2[0] != -s1[0]) return 0.0;
+    for (int k = 1; k < D - 1; k++)
+        if (s2[k] != s1[k]) return 0.0;
+    int ph = s1[D - 2] - s1[0];
+    double v = 1.0 / sqrt(dim_states(D, s1[D - 2]));
+    return (ph & 1) ? -v : v;
+}
+
+/* eq. Coupling-C with vec L = 0 and N = 4:
+ *   C = sum_{[l12]} <[l1] [l2] | [l12]> <[l12] [l3] | 0>
+ * D = 2: delta(l1 + l2 + l3, 0).  D = 3: sum over M12 of CG products with
+ * l12 = l3 (the final CG vanishes otherwise). */
+static double couple_three_to_zero(int D, const int *s1, const int *s2, const int *s3, int l12)
+{
+    if (D == 2) return (s1[0] + s2[0] + s3[0] == 0) ? 1.0 : 0.0;
+    if (D == 3) {
+        double c = 0.0;
+        for (int M12 = -l12; M12 <= l12; M12++) {
+            double a = oracle_cg3(s1[1], s1[0], s2[1], s2[0], l12, M12);
+            if (a == 0.0) continue;
+            c += a * oracle_cg3(l12, M12, s3[1], s3[0], 0, 0);
+        }
+        return c;
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Output index sets: Lambda labels and radial tuples                       */
+/* ------------------------------------------------------------------------ */
+
+/* Lambda labels of the isotropic (vec L = 0) basis.
+ *  N = 3, D >= 3: (l)               l = 0..lmax
+ *  N = 3, D = 2 : (l1, l2 = -l1)    l1 = 0..lmax
+ *  N = 4, D = 3 : (l1, l2, l3)      triangle |l1-l2| <= l3 <= l1+l2, all <= lmax
+ *                 (intermediate l12 = l3 is implied)
+ *  N = 4, D = 2 : (l1, l2, l3)      l1 = 0..lmax, l2 = -lmax..lmax, l3 = -l1-l2, |l3| <= lmax
+ * Labels are stored with 3 integers each (unused entries 0). */
+static int enum_lambda(int D, int N, int lmax, int *lab)
+{
+    int cnt = 0;
+    if (N == 3) {
+        for (int l = 0; l <= lmax; l++) {
+            if (lab) { lab[3 * cnt] = l; lab[3 * cnt + 1] = (D == 2) ? -l : 0; lab[3 * cnt + 2] = 0; }
+            cnt++;
+        }
+        return cnt;
+    }
+    if (N == 4 && D == 3) {
+        for (int l1 = 0; l1 <= lmax; l1++)
+            for (int l2 = 0; l2 <= lmax; l2++)
+                for (int l3 = 0; l3 <= lmax; l3++) {
+                    if (l3 < abs(l1 - l2) || l3 > l1 + l2) continue;
+                    if (lab) { lab[3 * cnt] = l1; lab[3 * cnt + 1] = l2; lab[3 * cnt + 2] = l3; }
+                    cnt++;
+                }
+        return cnt;
+    }
+    if (N == 4 && D == 2) {
+        for (int l1 = 0; l1 <= lmax; l1++)
+            for (int l2 = -lmax; l2 <= lmax; l2++) {
+                int l3 = -l1 - l2;
+                if (abs(l3) > lmax) continue;
+                if (lab) { lab[3 * cnt] = l1; lab[3 * cnt + 1] = l2; lab[3 * cnt + 2] = l3; }
+                cnt++;
+            }
+        return cnt;
+    }
+    return -1;
+}
+
+int oracle_num_lambda(int D, int N, int lmax) { return enum_lambda(D, N, lmax, NULL); }
+int oracle_lambda_labels(int D, int N, int lmax, int *lab) { return enum_lambda(D, N, lmax, lab); }
+
+static int enum_btuples(int nb, int N, int mode, int *bt)
+{
+    int cnt = 0;
+    if (N == 3) {
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                if (mode == 0 && !(b1 < b2)) continue;
+                if (bt) { bt[3 * cnt] = b1; bt[3 * cnt + 1] = b2; bt[3 * cnt + 2] = 0; }
+                cnt++;
+            }
+        return cnt;
+    }
+    if (N == 4) {
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++)
+                for (int b3 = 0; b3 < nb; b3++) {
+                    if (mode == 0 && !(b1 < b2 && b2 < b3)) continue;
+                    if (bt) { bt[3 * cnt] = b1; bt[3 * cnt + 1] = b2; bt[3 * cnt + 2] = b3; }
+                    cnt++;
+                }
+        return cnt;
+    }
+    return -1;
+}
+
+int oracle_num_btuples(int nb, int N, int mode) { return enum_btuples(nb, N, mode, NULL); }
+int oracle_btuple_labels(int nb, int N, int mode, int *bt) { return enum_btuples(nb, N, mode, bt); }
+
+/* Surface area of S^{D-1}: 2 pi^{D/2} / Gamma(D/2). */
+static double sphere_area(int D) { return 2.0 * pow(M_PI, 0.5 * D) / tgamma(0.5 * D); }
+
+double oracle_bin_volume(int D, double e0, double e1)
+{
+    return sphere_area(D) * (pow(e1, (double)D) - pow(e0, (double)D)) / (double)D;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coupling terms: for every Lambda, the list of state tuples with C != 0   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int lam;      /* Lambda index */
+    int s[3];     /* state index per leg */
+    double c;     /* coupling coefficient */
+} term_t;
+
+static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
+{
+    int nst = enum_states(D, lmax, NULL);
+    int nlam = enum_lambda(D, N, lmax, NULL);
+    int *slab = (int *)malloc(sizeof(int) * (size_t)nst * (D - 1));
+    int *llab = (int *)malloc(sizeof(int) * 3 * (size_t)nlam);
+    if (!slab || !llab) { free(slab); free(llab); return OR_ENOMEM; }
+    enum_states(D, lmax, slab);
+    enum_lambda(D, N, lmax, llab);
+    int cap = 1024, nt = 0;
+    term_t *t = (term_t *)malloc(sizeof(term_t) * cap);
+    if (!t) { free(slab); free(llab); return OR_ENOMEM; }
+    for (int L = 0; L < nlam; L++) {
+        const int *lam = llab + 3 * L;
+        for (int a = 0; a < nst; a++) {
+            const int *sa = slab + (size_t)a * (D - 1);
+            /* leg 1 must carry total angular momentum lam[0] */
+            if (sa[D - 2] != lam[0]) continue;
+            for (int b = 0; b < nst; b++) {
+                const int *sb = slab + (size_t)b * (D - 1);
+                /* leg 2 carries lam[1]; for N = 3 and D >= 3 the label holds only l */
+                int want2 = (N == 3 && D >= 3) ? lam[0] : lam[1];
+                if (sb[D - 2] != want2) continue;
+                if (N == 3) {
+                    double c = couple_pair_to_zero(D, sa, sb);
+                    if (c == 0.0) continue;
+                    if (nt == cap) { cap *= 2; term_t *nt2 = (term_t *)realloc(t, sizeof(term_t) * cap); if (!nt2) { free(t); free(slab); free(llab); return OR_ENOMEM; } t = nt2; }
+                    t[nt].lam = L; t[nt].s[0] = a; t[nt].s[1] = b; t[nt].s[2] = -1; t[nt].c = c; nt++;
+                    continue;
+                }
+                for (int d = 0; d < nst; d++) {
+                    const int *sd = slab + (size_t)d * (D - 1);
+                    if (sd[D - 2] != lam[2]) continue;
+                    int l12 = (D == 2) ? 0 : lam[2];
+                    double c = couple_three_to_zero(D, sa, sb, sd, l12);
+                    if (c == 0.0) continue;
+                    if (nt == cap) { cap *= 2; term_t *nt2 = (term_t *)realloc(t, sizeof(term_t) * cap); if (!nt2) { free(t); free(slab); free(llab); return OR_ENOMEM; } t = nt2; }
+                    t[nt].lam = L; t[nt].s[0] = a; t[nt].s[1] = b; t[nt].s[2] = d; t[nt].c = c; nt++;
+                }
+            }
+        }
+    }
+    free(slab);
+    free(llab);
+    *out = t;
+    *nterm_out = nt;
+    return OR_OK;
+}
+
+/* Exposes the coupling terms (for tests): fills up to cap entries of
+ * lam[], s[3*i], c[] and returns the total count. */
+int oracle_coupling_terms(int D, int N, int lmax, int cap, int *lam, int *s, double *c)
+{
+    term_t *t = NULL;
+    int nt = 0;
+    int st = build_terms(D, N, lmax, &t, &nt);
+    if (st != OR_OK) return -1;
+    for (int i = 0; i < nt && i < cap; i++) {
+        lam[i] = t[i].lam;
+        s[3 * i] = t[i].s[0]; s[3 * i + 1] = t[i].s[1]; s[3 * i + 2] = t[i].s[2];
+        c[i] = t[i].c;
+    }
+    free(t);
+    return nt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The estimator                                                            */
+/* ------------------------------------------------------------------------ */
+
+static int check_cfg(const oracle_cfg *cfg)
+{
+    if (!cfg || !cfg->edges) return OR_EINVAL;
+    if (cfg->D < 2 || cfg->D > 4 || cfg->N < 3 || cfg->N > 4) return OR_EUNSUP;
+    if (cfg->N == 4 && cfg->D == 4) return OR_EUNSUP;
+    if (cfg->lmax < 0 || cfg->nbins < 1) return OR_EINVAL;
+    if (!(cfg->edges[0] > 0.0)) return OR_EINVAL;
+    for (int b = 0; b < cfg->nbins; b++)
+        if (!(cfg->edges[b + 1] > cfg->edges[b])) return OR_EINVAL;
+    for (int k = 0; k < cfg->D; k++) {
+        if (!(cfg->box[k] > 0.0)) return OR_EINVAL;
+        if (cfg->periodic && !(2.0 * cfg->edges[cfg->nbins] < cfg->box[k])) return OR_EINVAL;
+    }
+    return OR_OK;
+}
+
+/* Harmonic stage for one primary: a[b][s] (complex, interleaved re/im), already
+ * divided by v_b.  Returns the number of in-range ordered pairs. */
+static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
+                           int nst, double *a, double *yre, double *yim)
+{
+    const int D = cfg->D, nb = cfg->nbins;
+    memset(a, 0, sizeof(double) * 2 * (size_t)nb * nst);
+    long pairs = 0;
+    double e2lo = cfg->edges[0] * cfg->edges[0];
+    double e2hi = cfg->edges[nb] * cfg->edges[nb];
+    for (long k = 0; k < n; k++) {
+        double d[4];
+        double r2 = 0.0;
+        for (int ax = 0; ax < D; ax++) {
+            double v = pos[(size_t)ax * n + k] - pos[(size_t)ax * n + j];
+            if (cfg->periodic) v -= cfg->box[ax] * nearbyint(v / cfg->box[ax]);
+            d[ax] = v;
+            r2 += v * v;
+        }
+        if (r2 < e2lo || r2 >= e2hi) continue;
+        int b = 0;
+        while (b + 1 < nb && r2 >= cfg->edges[b + 1] * cfg->edges[b + 1]) b++;
+        pairs++;
+        oracle_harmonics(D, cfg->lmax, d, yre, yim);
+        double *ab = a + 2 * (size_t)b * nst;
+        for (int s = 0; s < nst; s++) {
+            ab[2 * s] += w[k] * yre[s];
+            ab[2 * s + 1] -= w[k] * yim[s];  /* conj(Y) */
+        }
+    }
+    for (int b = 0; b < nb; b++) {
+        double vb = oracle_bin_volume(D, cfg->edges[b], cfg->edges[b + 1]);
+        for (int s = 0; s < 2 * nst; s++) a[2 * (size_t)b * nst + s] /= vb;
+    }
+    return pairs;
+}
+
+/* Coefficients a^b_[l](y_j) of eq. NPCF-estimator-discrete for the listed
+ * primaries: out[p][b][s][2]. */
+int oracle_alm(const oracle_cfg *cfg, const double *pos, const double *w, long n,
+               const long *prim, long nprim, double *out, long *pairs_out)
+{
+    int st = check_cfg(cfg);
+    if (st != OR_OK) return st;
+    int nst = enum_states(cfg->D, cfg->lmax, NULL);
+    long pairs = 0;
+    int fail = 0;
+#pragma omp parallel reduction(+ : pairs)
+    {
+        double *yre = (double *)malloc(sizeof(double) * nst);
+        double *yim = (double *)malloc(sizeof(double) * nst);
+        if (!yre || !yim) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (long p = 0; p < nprim; p++) {
+                double *a = out + 2 * (size_t)p * cfg->nbins * nst;
+                pairs += harmonic_stage(cfg, pos, w, n, prim[p], nst, a, yre, yim);
+            }
+        }
+        free(yre);
+        free(yim);
+    }
+    if (fail) return OR_ENOMEM;
+    if (pairs_out) *pairs_out = pairs;
+    return OR_OK;
+}
+
+/* Full estimator over the listed primaries against all n secondaries.
+ * zeta_out[lambda][btuple][2] (complex, finalised: divided by V_D; the 1/v_b
+ * factors sit inside a).  pairs_out: in-range ordered pairs. */
+int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long n,
+                const long *prim, long nprim, double *zeta_out, long *pairs_out)
+{
+    int st = check_cfg(cfg);
+    if (st != OR_OK) return st;
+    const int D = cfg->D, N = cfg->N, nb = cfg->nbins;
+    int nst = enum_states(D, cfg->lmax, NULL);
+    int nlam = enum_lambda(D, N, cfg->lmax, NULL);
+    int nbt = enum_btuples(nb, N, cfg->btuple_mode, NULL);
+    int *bt = (int *)malloc(sizeof(int) * 3 * (size_t)nbt);
+    term_t *terms = NULL;
+    int nterm = 0;
+    if (!bt) return OR_ENOMEM;
+    enum_btuples(nb, N, cfg->btuple_mode, bt);
+    st = build_terms(D, N, cfg->lmax, &terms, &nterm);
+    if (st != OR_OK) { free(bt); return st; }
+
+    size_t zlen = 2 * (size_t)nlam * nbt;
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    double *part = (double *)calloc((size_t)nthr * zlen, sizeof(double));
+    if (!part) { free(bt); free(terms); return OR_ENOMEM; }
+    long pairs = 0;
+    int fail = 0;
+#pragma omp parallel reduction(+ : pairs)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *z = part + (size_t)tid * zlen;
+        double *a = (double *)malloc(sizeof(double) * 2 * (size_t)nb * nst);
+        double *yre = (double *)malloc(sizeof(double) * nst);
+        double *yim = (double *)malloc(sizeof(double) * nst);
+        if (!a || !yre || !yim) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (long p = 0; p < nprim; p++) {
+                long j = prim[p];
+                pairs += harmonic_stage(cfg, pos, w, n, j, nst, a, yre, yim);
+                /* coupling stage: zeta^{Lambda,b} += w_j sum C prod_i a^{b_i}_{[l^i]} */
+                for (int t = 0; t < nterm; t++) {
+                    const term_t *T = terms + t;
+                    double *zl = z + 2 * (size_t)T->lam * nbt;
+                    for (int q = 0; q < nbt; q++) {
+                        const int *B = bt + 3 * q;
+                        const double *x1 = a + 2 * ((size_t)B[0] * nst + T->s[0]);
+                        const double *x2 = a + 2 * ((size_t)B[1] * nst + T->s[1]);
+                        double pr = x1[0] * x2[0] - x1[1] * x2[1];
+                        double pi = x1[0] * x2[1] + x1[1] * x2[0];
+                        if (N == 4) {
+                            const double *x3 = a + 2 * ((size_t)B[2] * nst + T->s[2]);
+                            double qr = pr * x3[0] - pi * x3[1];
+                            double qi = pr * x3[1] + pi * x3[0];
+                            pr = qr;
+                            pi = qi;
+                        }
+                        zl[2 * q] += w[j] * T->c * pr;
+                        zl[2 * q + 1] += w[j] * T->c * pi;
+                    }
+                }
+            }
+        }
+        free(a);
+        free(yre);
+        free(yim);
+    }
+    if (fail) { free(part); free(bt); free(terms); return OR_ENOMEM; }
+    double VD = 1.0;
+    for (int k = 0; k < D; k++) VD *= cfg->box[k];
+    for (size_t i = 0; i < zlen; i++) {
+        double s = 0.0;
+        for (int t = 0; t < nthr; t++) s += part[(size_t)t * zlen + i];
+        zeta_out[i] = s / VD;
+    }
+    if (pairs_out) *pairs_out = pairs;
+    free(part);
+    free(bt);
+    free(terms);
+    return OR_OK;
+}

@@ -1,0 +1,161 @@
+"""Seeded synthetic catalogues for the NPCF estimator.
+
+This module holds no arithmetic of the estimator itself: it only draws point
+sets and weights.  Both the GPU path and the FP64 CPU oracle consume its
+output.
+
+Every coordinate is placed on the lattice box * q / 2^32 (q an unsigned
+32-bit integer per axis), so that the double-precision positions are exact
+and a fixed-point copy of them loses nothing.
+
+The workloads stand in for the data the paper discusses (galaxy surveys,
+turbulence simulations); none of those data sets is used.  Recipes:
+
+* ``uniform``    -- n points uniform in a periodic box.
+* ``clustered``  -- Poisson-sampled Gaussian blobs: ``n_blob`` points, each
+  picks one of ``n_centres`` uniform centres and is offset by N(0, sigma^2) per
+  axis (wrapped), plus ``n_uniform`` uniform background points.
+* ``vorticity_tracers`` (D = 2) -- points drawn with density proportional to
+  exp(omega) for a random-phase field omega on a grid, whose per-mode
+  amplitude falls as 1/|k| (shell energy spectrum ~ k^-3), normalised to
+  unit variance.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+TWO32 = float(2 ** 32)
+
+
+def to_lattice(x: np.ndarray, box) -> np.ndarray:
+    """Snap coordinates [D][n] onto the box * q / 2^32 lattice (periodic)."""
+    box = np.asarray(box, dtype=np.float64).reshape(-1, 1)
+    q = np.floor(np.mod(x, box) / box * TWO32)
+    q = np.mod(q, TWO32)
+    return q * box / TWO32
+
+
+def uniform(rng: np.random.Generator, n: int, box) -> np.ndarray:
+    box = np.asarray(box, dtype=np.float64)
+    x = rng.uniform(0.0, 1.0, size=(len(box), n)) * box[:, None]
+    return to_lattice(x, box)
+
+
+def clustered(rng: np.random.Generator, n_blob: int, n_uniform: int, n_centres: int, sigma: float, box) -> np.ndarray:
+    box = np.asarray(box, dtype=np.float64)
+    D = len(box)
+    centres = rng.uniform(0.0, 1.0, size=(D, n_centres)) * box[:, None]
+    pick = rng.integers(0, n_centres, size=n_blob)
+    blob = centres[:, pick] + rng.normal(0.0, sigma, size=(D, n_blob))
+    back = rng.uniform(0.0, 1.0, size=(D, n_uniform)) * box[:, None]
+    return to_lattice(np.concatenate([blob, back], axis=1), box)
+
+
+def vorticity_tracers(rng: np.random.Generator, n: int, grid: int, box: float) -> np.ndarray:
+    white = rng.normal(size=(grid, grid))
+    fk = np.fft.rfft2(white)
+    kx = np.fft.fftfreq(grid) * grid
+    ky = np.fft.rfftfreq(grid) * grid
+    kk = np.sqrt(kx[:, None] ** 2 + ky[None, :] ** 2)
+    filt = np.zeros_like(kk)
+    band = (kk >= 1.0) & (kk <= grid // 2)
+    filt[band] = 1.0 / kk[band]
+    omega = np.fft.irfft2(fk * filt, s=(grid, grid))
+    omega = (omega - omega.mean()) / omega.std()
+    dens = np.exp(omega).ravel()
+    cdf = np.cumsum(dens)
+    cdf /= cdf[-1]
+    cell = np.searchsorted(cdf, rng.uniform(0.0, 1.0, size=n), side="right")
+    cell = np.minimum(cell, grid * grid - 1)
+    ix, iy = np.divmod(cell, grid)
+    h = box / grid
+    x = (ix + rng.uniform(0.0, 1.0, size=n)) * h
+    y = (iy + rng.uniform(0.0, 1.0, size=n)) * h
+    return to_lattice(np.stack([x, y]), [box, box])
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    D: int
+    N: int
+    lmax: int
+    edges: np.ndarray
+    box: list
+    pos: np.ndarray          # [D][n] float64 on the lattice
+    w: np.ndarray            # [n] float64
+    n_data: int = 0          # leading points that are data (rest: randoms)
+    note: str = ""
+
+
+def c1_small_3pcf(seed: int = 1001) -> Workload:
+    """D=3, N=3: 2000 uniform points, periodic cube of side 100, w = 1,
+    8 linear bins in [2, 20], lmax = 4."""
+    rng = np.random.default_rng(seed)
+    box = [100.0] * 3
+    pos = uniform(rng, 2000, box)
+    return Workload("D3-N3-uniform-2k", 3, 3, 4, np.linspace(2.0, 20.0, 9), box, pos, np.ones(2000), 2000)
+
+
+def c2_clustered_4pcf(seed: int = 1002, n_data: int = 200_000, n_rand: int = 600_000) -> Workload:
+    """D=3, N=4: 200k clustered data (half in 2000 Gaussian blobs of sigma 5,
+    half uniform), w = +1, plus 600k uniform randoms with w = -1/3, periodic
+    cube of side 1000, 10 linear bins in [20, 160], lmax = 5."""
+    rng = np.random.default_rng(seed)
+    box = [1000.0] * 3
+    data = clustered(rng, n_data // 2, n_data - n_data // 2, 2000, 5.0, box)
+    rand = uniform(rng, n_rand, box)
+    pos = np.concatenate([data, rand], axis=1)
+    w = np.concatenate([np.ones(n_data), np.full(n_rand, -1.0 / 3.0)])
+    return Workload(f"D3-N4-clustered-{n_data // 1000}k+{n_rand // 1000}k-randoms", 3, 4, 5,
+                    np.linspace(20.0, 160.0, 11), box, pos, w, n_data)
+
+
+def c3_vorticity_4pcf(seed: int = 1003, n: int = 500_000, grid: int = 1024) -> Workload:
+    """D=2, N=4: tracers of exp(vorticity) on a periodic square of side 2 pi,
+    w = 1, 12 linear bins in [0.02, 0.5], |l| <= 8."""
+    rng = np.random.default_rng(seed)
+    box = 2.0 * math.pi
+    pos = vorticity_tracers(rng, n, grid, box)
+    return Workload(f"D2-N4-vorticity-{n // 1000}k", 2, 4, 8, np.linspace(0.02, 0.5, 13), [box, box], pos, np.ones(n), n)
+
+
+def c4_batch_sizes(count: int = 64, seed: int = 4000) -> list:
+    """Data sizes of the batched workload: log-uniform in [20k, 300k]."""
+    rng = np.random.default_rng(seed)
+    return [int(round(math.exp(rng.uniform(math.log(20_000), math.log(300_000))))) for _ in range(count)]
+
+
+def c4_catalogue(c: int, n_data: int) -> Workload:
+    """One catalogue of the batched D=3, N=4 workload (seed 4000 + c): the
+    clustered generator of c2 plus 3 n_data uniform randoms at w = -1/3."""
+    return c2_clustered_4pcf(seed=4000 + c, n_data=n_data, n_rand=3 * n_data)
+
+
+def c5_hyper_3pcf(seed: int = 1005, n_blob: int = 1_000_000, n_uniform: int = 1_000_000) -> Workload:
+    """D=4, N=3: 2M points (1M in 2000 Gaussian blobs of sigma 5, 1M uniform)
+    in a periodic hypercube of side 500, w ~ N(1, 0.1^2), 10 linear bins in
+    [5, 50], lmax = 6."""
+    rng = np.random.default_rng(seed)
+    box = [500.0] * 4
+    pos = clustered(rng, n_blob, n_uniform, 2000, 5.0, box)
+    n = pos.shape[1]
+    w = rng.normal(1.0, 0.1, size=n)
+    return Workload(f"D4-N3-clustered-{n // 1000}k", 4, 3, 6, np.linspace(5.0, 50.0, 11), box, pos, w, n)
+
+
+def tiny(D: int, N: int, lmax: int, n: int, seed: int, box_side: float = 10.0, rmax: float = 4.0,
+         nbins: int = 3, weights: str = "mixed") -> Workload:
+    """Small periodic catalogue for brute-force and parity tests."""
+    rng = np.random.default_rng(seed)
+    box = [box_side] * D
+    pos = uniform(rng, n, box)
+    if weights == "ones":
+        w = np.ones(n)
+    else:
+        w = rng.uniform(-0.5, 1.5, size=n)
+    edges = np.linspace(rmax / (nbins + 1), rmax, nbins + 1)
+    return Workload(f"tiny-D{D}-N{N}-{n}", D, N, lmax, edges, box, pos, w, n)

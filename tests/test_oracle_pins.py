@@ -1,0 +1,496 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (mpmath Ferrers functions, SciPy spherical harmonics and Gegenbauer
+polynomials, SymPy Wigner/Clebsch-Gordan symbols), a closed form, an
+invariance, an exact count printed in the paper, or a brute-force O(n^N)
+evaluation of the naive estimator at tiny n (the paper's own check that the
+naive and separable estimators agree, section Applications, Fig. 3 caption).
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy.special import eval_gegenbauer, roots_legendre, sph_harm_y
+from sympy.physics.wigner import clebsch_gordan, wigner_3j
+
+import oracle
+from paper_2106_10278_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def sphere_area(D):
+    return 2.0 * math.pi ** (D / 2) / math.gamma(D / 2)
+
+
+def rand_unit(rng, D):
+    x = rng.normal(size=D)
+    return x / np.linalg.norm(x)
+
+
+def rand_rotation(rng, D):
+    q, r = np.linalg.qr(rng.normal(size=(D, D)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+# --------------------------------------------------------------------------
+# Single-particle basis
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mu", [0, 0.5, 1, 1.5, 2, 2.5, 3, 3.5, 5.5])
+def test_ferrers_matches_mpmath(mu):
+    """Ferrers functions of the first kind (DLMF 14.3) used by eq. hypersph-def."""
+    for n in range(0, 7):
+        for x in [-0.93, -0.4, 0.013, 0.31, 0.88]:
+            # DLMF 14.3.1: P^{-mu}_nu(x) = ((1-x)/(1+x))^{mu/2} F(nu+1, -nu; mu+1; (1-x)/2) / Gamma(mu+1)
+            nu = mu + n
+            ref = float(((1 - mpmath.mpf(x)) / (1 + mpmath.mpf(x))) ** (mpmath.mpf(mu) / 2)
+                        * mpmath.hyp2f1(nu + 1, -nu, mu + 1, (1 - mpmath.mpf(x)) / 2) / mpmath.gamma(mu + 1))
+            got = oracle.ferrers_neg(mu, n, x)
+            assert got == pytest.approx(ref, rel=1e-11, abs=1e-14), (mu, n, x)
+
+
+def test_d3_harmonics_match_scipy():
+    """D = 3 closed form of section Hyperspherical Harmonics: the P^{-l1}_{l2}
+    form equals (-1)^m times SciPy's Condon-Shortley Y_l^m (DLMF 14.9.3)."""
+    rng = np.random.default_rng(0)
+    lab = oracle.state_labels(3, 7)
+    for _ in range(20):
+        x = rng.normal(size=3)
+        r = np.linalg.norm(x)
+        th, ph = np.arccos(x[2] / r), np.arctan2(x[1], x[0])
+        got = oracle.harmonics(3, 7, x)
+        ref = np.array([(-1.0) ** int(m) * sph_harm_y(int(l), int(m), th, ph) for m, l in lab])
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_d2_harmonics_closed_form():
+    """D = 2: Y_l = e^{i l theta_1} / sqrt(2 pi)."""
+    for th in [0.1, 1.3, 2.9, -2.0]:
+        got = oracle.harmonics(2, 6, np.array([3.0 * math.cos(th), 3.0 * math.sin(th)]))
+        lab = oracle.state_labels(2, 6)[:, 0]
+        np.testing.assert_allclose(got, np.exp(1j * lab * th) / math.sqrt(2 * math.pi), atol=1e-14)
+
+
+@pytest.mark.parametrize("D,lmax", [(2, 5), (3, 4), (4, 3)])
+def test_state_count_formula(D, lmax):
+    """Number of states of total angular momentum l: binom(l+D-3, D-3)(2l+D-2)/(D-2)
+    for D >= 3, one for D = 2 (section Connection to Angular Momentum Eigenstates)."""
+    lab = oracle.state_labels(D, lmax)
+    for l in range(lmax + 1):
+        cnt = int(np.sum(lab[:, -1] == l))
+        if D == 2:
+            assert int(np.sum(lab[:, 0] == l)) == 1
+            continue
+        ref = math.comb(l + D - 3, D - 3) * (2 * l + D - 2) // (D - 2)
+        assert cnt == ref
+        if D == 4:
+            assert cnt == (l + 1) ** 2
+
+
+def _sphere_quadrature(D, nq):
+    """Product rule on S^{D-1}: uniform in theta_1, Gauss-Legendre in theta_K
+    with the measure sin^{K-1}(theta_K) d theta_K."""
+    t1 = np.arange(2 * nq) * (2 * math.pi / (2 * nq))
+    w1 = np.full(2 * nq, 2 * math.pi / (2 * nq))
+    grids = [(t1, w1)]
+    g, gw = roots_legendre(nq)
+    th = 0.5 * math.pi * (g + 1.0)
+    for K in range(2, D):
+        grids.append((th, 0.5 * math.pi * gw * np.sin(th) ** (K - 1)))
+    pts = []
+    wts = []
+    for idx in np.ndindex(*[len(gr[0]) for gr in grids]):
+        ang = [grids[k][0][idx[k]] for k in range(D - 1)]
+        wt = np.prod([grids[k][1][idx[k]] for k in range(D - 1)])
+        # x_1 = prod_{K>=2} sin th_K cos th_1, x_2 = prod sin th_K sin th_1,
+        # x_{K+1} = prod_{J>K} sin th_J cos th_K, x_D = cos th_{D-1}
+        x = np.zeros(D)
+        s = 1.0
+        for K in range(D - 1, 1, -1):
+            x[K] = s * math.cos(ang[K - 1])
+            s *= math.sin(ang[K - 1])
+        x[0] = s * math.cos(ang[0])
+        x[1] = s * math.sin(ang[0])
+        pts.append(x)
+        wts.append(wt)
+    return np.array(pts), np.array(wts)
+
+
+@pytest.mark.parametrize("D,lmax,nq", [(2, 6, 16), (3, 5, 32), (4, 3, 24)])
+def test_orthonormality(D, lmax, nq):
+    """Orthonormality of the hyperspherical harmonics on S^{D-1}."""
+    pts, wts = _sphere_quadrature(D, nq)
+    Y = np.array([oracle.harmonics(D, lmax, p) for p in pts])
+    assert wts.sum() == pytest.approx(sphere_area(D), rel=1e-12)
+    G = (Y * wts[:, None]).T @ Y.conj()
+    np.testing.assert_allclose(G, np.eye(Y.shape[1]), atol=1e-11)
+
+
+@pytest.mark.parametrize("D,lmax", [(2, 6), (3, 6), (4, 5)])
+def test_addition_theorem(D, lmax):
+    """sum over states of total l of Y(x) Y*(y) = dim/|S^{D-1}| * C^{(D/2-1)}_l(x.y)/C^{(D/2-1)}_l(1)
+    (Chebyshev T_l for D = 2)."""
+    rng = np.random.default_rng(D)
+    lab = oracle.state_labels(D, lmax)
+    tot = np.abs(lab[:, 0]) if D == 2 else lab[:, -1]
+    for _ in range(6):
+        x, y = rand_unit(rng, D), rand_unit(rng, D)
+        t = float(x @ y)
+        Yx, Yy = oracle.harmonics(D, lmax, x), oracle.harmonics(D, lmax, y)
+        for l in range(lmax + 1):
+            sel = tot == l
+            s = np.sum(Yx[sel] * Yy[sel].conj())
+            dim = int(sel.sum())
+            if D == 2:
+                g = math.cos(l * math.acos(max(-1.0, min(1.0, t))))
+            else:
+                a = D / 2 - 1
+                g = eval_gegenbauer(l, a, t) / eval_gegenbauer(l, a, 1.0)
+            assert s.real == pytest.approx(dim / sphere_area(D) * g, abs=1e-12)
+            assert abs(s.imag) < 1e-12
+
+
+@pytest.mark.parametrize("D,lmax", [(2, 5), (3, 5), (4, 4)])
+def test_conjugation_and_parity(D, lmax):
+    """eq. complex-conj-hypersph: Y* = (-1)^{l1} Y_{(-l1)...} for D >= 3
+    (Y*_l = Y_{-l} in D = 2) and P[Y] = (-1)^{l_{D-1}} Y."""
+    rng = np.random.default_rng(7)
+    lab = [tuple(r) for r in oracle.state_labels(D, lmax)]
+    index = {s: i for i, s in enumerate(lab)}
+    for _ in range(5):
+        x = rng.normal(size=D)
+        Y, Ym = oracle.harmonics(D, lmax, x), oracle.harmonics(D, lmax, -x)
+        for i, s in enumerate(lab):
+            flip = (-s[0],) + s[1:]
+            sign = 1.0 if D == 2 else (-1.0) ** s[0]
+            assert Y[i].conjugate() == pytest.approx(sign * Y[index[flip]], abs=1e-13)
+            assert Ym[i] == pytest.approx((-1.0) ** s[-1] * Y[i], abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Coupling
+# --------------------------------------------------------------------------
+
+def test_wigner3j_matches_sympy():
+    for j1 in range(0, 5):
+        for j2 in range(0, 5):
+            for j3 in range(abs(j1 - j2), j1 + j2 + 1):
+                for m1 in range(-j1, j1 + 1):
+                    for m2 in range(-j2, j2 + 1):
+                        m3 = -m1 - m2
+                        if abs(m3) > j3:
+                            continue
+                        ref = float(wigner_3j(j1, j2, j3, m1, m2, m3))
+                        assert oracle.wigner3j(j1, j2, j3, m1, m2, m3) == pytest.approx(ref, abs=1e-13)
+
+
+def test_cg3_matches_sympy_and_orthogonality():
+    """eq. CG-examples (D = 3) is the standard Clebsch-Gordan coefficient;
+    eq. CG-orthonorm holds."""
+    for j1 in range(0, 4):
+        for j2 in range(0, 4):
+            for J in range(abs(j1 - j2), j1 + j2 + 1):
+                for m1 in range(-j1, j1 + 1):
+                    for m2 in range(-j2, j2 + 1):
+                        M = m1 + m2
+                        if abs(M) > J:
+                            continue
+                        ref = float(clebsch_gordan(j1, j2, J, m1, m2, M))
+                        assert oracle.cg3(j1, m1, j2, m2, J, M) == pytest.approx(ref, abs=1e-13)
+            for J in range(abs(j1 - j2), j1 + j2 + 1):
+                for Jp in range(abs(j1 - j2), j1 + j2 + 1):
+                    for M in range(-min(J, Jp), min(J, Jp) + 1):
+                        s = sum(oracle.cg3(j1, m1, j2, M - m1, J, M) * oracle.cg3(j1, m1, j2, M - m1, Jp, M)
+                                for m1 in range(-j1, j1 + 1) if abs(M - m1) <= j2)
+                        assert s == pytest.approx(1.0 if J == Jp else 0.0, abs=1e-12)
+
+
+def _basis_function(D, N, lmax):
+    """P^0_Lambda(rhat_1..rhat_{N-1}) = sum C prod Y (eq. N-1-particle-basis-wavefunction),
+    assembled from the oracle's harmonics and coupling terms."""
+    lam, s, c = oracle.coupling_terms(D, N, lmax)
+    nlam = len(oracle.lambda_labels(D, N, lmax))
+
+    def P(*dirs):
+        Ys = [oracle.harmonics(D, lmax, d) for d in dirs]
+        out = np.zeros(nlam, dtype=complex)
+        prod = c * Ys[0][s[:, 0]] * Ys[1][s[:, 1]]
+        if N == 4:
+            prod = prod * Ys[2][s[:, 2]]
+        np.add.at(out, lam, prod)
+        return out
+
+    return P
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 4), (3, 3, 5), (4, 3, 4), (2, 4, 4), (2, 3, 4)])
+def test_isotropic_basis_rotation_invariance_and_parity(D, N, lmax):
+    """vec L = 0 states are invariant under SO(D); eq. basis-parity-conj:
+    P* = (-1)^{sum l} P and P(-r) = (-1)^{sum l} P."""
+    rng = np.random.default_rng(11)
+    P = _basis_function(D, N, lmax)
+    labels = oracle.lambda_labels(D, N, lmax)
+    if D == 2:
+        tot = np.zeros(len(labels), dtype=int)  # sum of l1 is zero
+        par = labels[:, 0] + labels[:, 1] + (labels[:, 2] if N == 4 else 0)
+    else:
+        tot = 2 * labels[:, 0] if N == 3 else labels.sum(axis=1)
+        par = tot
+    for _ in range(4):
+        dirs = [rand_unit(rng, D) for _ in range(N - 1)]
+        R = rand_rotation(rng, D)
+        p0 = P(*dirs)
+        p1 = P(*[R @ d for d in dirs])
+        np.testing.assert_allclose(p1, p0, atol=1e-12)
+        pm = P(*[-d for d in dirs])
+        np.testing.assert_allclose(pm, ((-1.0) ** par) * p0, atol=1e-12)
+        if D >= 3:
+            np.testing.assert_allclose(p0.conj(), ((-1.0) ** tot) * p0, atol=1e-12)
+    assert np.max(np.abs(P(*[rand_unit(rng, D) for _ in range(N - 1)]))) > 1e-3
+
+
+def test_d3_n3_coupling_closed_form():
+    """<l m, l -m | 0 0> = (-1)^{l-m}/sqrt(2l+1) (DLMF 34.3.1 with the CG relation)."""
+    lam, s, c = oracle.coupling_terms(3, 3, 5)
+    lab = oracle.state_labels(3, 5)
+    for L, (a, b), cc in zip(lam, s[:, :2], c):
+        m, l = lab[a]
+        assert lab[b][0] == -m and lab[b][1] == l == L
+        assert cc == pytest.approx((-1.0) ** (l - m) / math.sqrt(2 * l + 1), abs=1e-14)
+
+
+def test_paper_component_counts():
+    """Counts printed in section Applications (golden fixture)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_counts.json")))
+    assert len(oracle.lambda_labels(2, 4, 4)) == g["d2_n4_lmax4_angular"]
+    assert len(oracle.btuple_labels(10, 4)) == g["n4_nbins10_radial"]
+    assert math.comb(10, 4) == g["n5_nbins10_radial"]
+
+
+def test_bin_volumes_sum_to_shell():
+    for D in (2, 3, 4):
+        e = np.array([0.7, 1.1, 2.0, 3.5])
+        tot = sum(oracle.bin_volume(D, e[b], e[b + 1]) for b in range(3))
+        ball = lambda r: math.pi ** (D / 2) / math.gamma(D / 2 + 1) * r ** D
+        assert tot == pytest.approx(ball(e[-1]) - ball(e[0]), rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Separable estimator == naive estimator (brute force, tiny n)
+# --------------------------------------------------------------------------
+
+def _neighbours(wl, j):
+    d = wl.pos - wl.pos[:, j:j + 1]
+    box = np.asarray(wl.box)[:, None]
+    d = d - box * np.round(d / box)
+    r2 = np.sum(d * d, axis=0)
+    e2 = wl.edges ** 2
+    ok = (r2 >= e2[0]) & (r2 < e2[-1])
+    idx = np.nonzero(ok)[0]
+    b = np.searchsorted(e2, r2[idx], side="right") - 1
+    return idx, b, d[:, idx].T
+
+
+def _indep_basis(D, N, lmax):
+    """P^0_Lambda from SciPy/SymPy/closed forms, independent of the oracle."""
+    labels = oracle.lambda_labels(D, N, lmax)
+    if D == 2:
+        def P(*dirs):
+            ph = [np.arctan2(d[:, 1], d[:, 0]) for d in dirs]
+            ls = [labels[:, 0], labels[:, 1]] + ([labels[:, 2]] if N == 4 else [])
+            tot = 0.0
+            for k in range(N - 1):
+                shape = [1] * (N - 1)
+                shape[k] = -1
+                tot = tot + ls[k].reshape((-1,) + (1,) * (N - 1)) * ph[k].reshape(shape)[None]
+            return np.exp(1j * tot) / (2 * math.pi) ** ((N - 1) / 2)
+        return P
+    if N == 3:
+        def P(d1, d2):
+            t = np.clip(d1 @ d2.T, -1.0, 1.0)
+            out = []
+            for l in labels[:, 0]:
+                dim = math.comb(l + D - 3, D - 3) * (2 * l + D - 2) / (D - 2)
+                a = D / 2 - 1
+                g = eval_gegenbauer(int(l), a, t) / eval_gegenbauer(int(l), a, 1.0)
+                out.append((-1.0) ** l * math.sqrt(dim) / sphere_area(D) * g)
+            return np.array(out)
+        return P
+    assert D == 3 and N == 4
+
+    def Yall(d):
+        th = np.arccos(np.clip(d[:, 2], -1, 1))
+        ph = np.arctan2(d[:, 1], d[:, 0])
+        return {(l, m): (-1.0) ** m * sph_harm_y(l, m, th, ph) for l in range(lmax + 1) for m in range(-l, l + 1)}
+
+    coup = []
+    for l1, l2, l3 in labels:
+        terms = []
+        for m1 in range(-l1, l1 + 1):
+            for m2 in range(-l2, l2 + 1):
+                m3 = -m1 - m2
+                if abs(m3) > l3:
+                    continue
+                c = sum(float(clebsch_gordan(l1, l2, l3, m1, m2, M)) * float(clebsch_gordan(l3, l3, 0, M, m3, 0))
+                        for M in [m1 + m2] if abs(M) <= l3)
+                if c != 0.0:
+                    terms.append((m1, m2, m3, c))
+        coup.append((l1, l2, l3, terms))
+
+    def P(d1, d2, d3):
+        Y1, Y2, Y3 = Yall(d1), Yall(d2), Yall(d3)
+        out = np.zeros((len(labels), len(d1), len(d2), len(d3)), dtype=complex)
+        for i, (l1, l2, l3, terms) in enumerate(coup):
+            for m1, m2, m3, c in terms:
+                out[i] += c * np.einsum("a,b,c->abc", Y1[(l1, m1)], Y2[(l2, m2)], Y3[(l3, m3)])
+        return out
+
+    return P
+
+
+def _brute_force(wl, btuple_mode):
+    """eq. NPCF-estimator-intro-discrete with B = P^0_Lambda prod Theta^{b_i}/v_{b_i},
+    coefficients extracted with conj(P) (eq. zeta-basis-coeff), sums over all
+    secondaries unrestricted."""
+    D, N = wl.D, wl.N
+    nb = len(wl.edges) - 1
+    vb = np.array([sphere_area(D) * (wl.edges[b + 1] ** D - wl.edges[b] ** D) / D for b in range(nb)])
+    labels = oracle.lambda_labels(D, N, wl.lmax)
+    P = _indep_basis(D, N, wl.lmax)
+    full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
+    for j in range(wl.pos.shape[1]):
+        idx, b, d = _neighbours(wl, j)
+        if len(idx) == 0:
+            continue
+        u = d / np.linalg.norm(d, axis=1, keepdims=True)
+        ww = wl.w[idx] / vb[b]
+        pv = np.conj(P(*([u] * (N - 1))))
+        if N == 3:
+            contrib = pv * ww[None, :, None] * ww[None, None, :]
+            for i1 in range(len(idx)):
+                np.add.at(full, (slice(None), b[i1], b), wl.w[j] * contrib[:, i1, :])
+        else:
+            contrib = pv * ww[None, :, None, None] * ww[None, None, :, None] * ww[None, None, None, :]
+            for i1 in range(len(idx)):
+                for i2 in range(len(idx)):
+                    np.add.at(full, (slice(None), b[i1], b[i2], b), wl.w[j] * contrib[:, i1, i2, :])
+    full /= np.prod(wl.box)
+    bt = oracle.btuple_labels(nb, N, btuple_mode)
+    return np.stack([full[(slice(None),) + tuple(bt[q])] for q in range(len(bt))], axis=1)
+
+
+@pytest.mark.parametrize("D,N,lmax,n,mode", [
+    (3, 4, 2, 30, 0), (3, 4, 2, 24, 1), (3, 3, 4, 40, 1), (4, 3, 3, 40, 1),
+    (2, 4, 3, 30, 1), (2, 3, 4, 40, 1), (2, 4, 3, 30, 0)])
+def test_separable_equals_naive(D, N, lmax, n, mode):
+    """The paper's naive-vs-separable agreement, to rounding."""
+    box = {2: 6.0, 3: 8.0, 4: 6.0}[D]
+    wl = inputs.tiny(D, N, lmax, n, seed=100 + D * 10 + N, box_side=box, rmax=2.8, nbins=3)
+    ref = _brute_force(wl, mode)
+    got, _ = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=mode)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+# --------------------------------------------------------------------------
+# Invariants of the estimator
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 3), (3, 3, 4), (4, 3, 3), (2, 4, 4)])
+def test_l0_is_weighted_count(D, N, lmax):
+    """zeta_{0...0}^b = sum_j w_j prod_i W_{b_i}(j) / (V_D prod v_{b_i} |S^{D-1}|^{(N-1)/2})."""
+    wl = inputs.tiny(D, N, lmax, 60, seed=5, box_side=8.0, rmax=3.0, nbins=3)
+    nb = 3
+    got, _ = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1)
+    labels = oracle.lambda_labels(D, N, lmax)
+    i0 = int(np.nonzero(np.all(labels == 0, axis=1))[0][0])
+    vb = np.array([oracle.bin_volume(D, wl.edges[b], wl.edges[b + 1]) for b in range(nb)])
+    bt = oracle.btuple_labels(nb, N, 1)
+    ref = np.zeros(len(bt))
+    for j in range(wl.pos.shape[1]):
+        idx, b, _ = _neighbours(wl, j)
+        W = np.bincount(b, weights=wl.w[idx], minlength=nb) / vb
+        ref += wl.w[j] * np.prod(W[bt], axis=1)
+    ref /= np.prod(wl.box) * sphere_area(D) ** ((N - 1) / 2)
+    np.testing.assert_allclose(got[i0].real, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    assert np.max(np.abs(got[i0].imag)) < 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 3), (3, 3, 4), (4, 3, 3)])
+def test_parity_real_imaginary(D, N, lmax):
+    """Real field, vec L = 0: even sum l gives a real coefficient, odd an imaginary one."""
+    wl = inputs.tiny(D, N, lmax, 50, seed=9, box_side=8.0, rmax=3.0, nbins=3)
+    z, _ = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w)
+    labels = oracle.lambda_labels(D, N, lmax)
+    tot = 2 * labels[:, 0] if N == 3 else labels.sum(axis=1)
+    scale = np.abs(z).max()
+    for i in range(len(labels)):
+        other = z[i].imag if tot[i] % 2 == 0 else z[i].real
+        assert np.max(np.abs(other)) < 1e-13 * scale
+    if N == 4:
+        assert np.max(np.abs(z[tot % 2 == 1].imag)) > 1e-6 * scale
+
+
+def _apply_cube_symmetry(wl, perm, flips):
+    pos = wl.pos[list(perm)].copy()
+    for ax, f in enumerate(flips):
+        if f:
+            pos[ax] = np.mod(wl.box[ax] - pos[ax], wl.box[ax])
+    return pos
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 3), (2, 4, 3), (4, 3, 2)])
+def test_lattice_symmetries(D, N, lmax):
+    """Exact symmetries of the periodic box: proper ones leave every component
+    unchanged; improper ones flip the odd-parity components (eq. basis-parity-conj)."""
+    wl = inputs.tiny(D, N, lmax, 40, seed=21, box_side=7.0, rmax=3.0, nbins=3)
+    z, _ = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w)
+    labels = oracle.lambda_labels(D, N, lmax)
+    if D == 2:
+        par = labels[:, 0] + labels[:, 1] + labels[:, 2]
+    else:
+        par = 2 * labels[:, 0] if N == 3 else labels.sum(axis=1)
+    rng = np.random.default_rng(3)
+    scale = np.abs(z).max()
+    for _ in range(3):
+        perm = rng.permutation(D)
+        flips = rng.integers(0, 2, size=D)
+        det = np.linalg.det(np.eye(D)[perm]) * np.prod([-1 if f else 1 for f in flips])
+        z2, _ = oracle.npcf(D, N, lmax, wl.edges, wl.box, _apply_cube_symmetry(wl, perm, flips), wl.w)
+        if D == 2:
+            # SO(2) acts on l by a phase e^{i sum(l) alpha} = 1; reflections conjugate (l -> -l)
+            if det > 0:
+                np.testing.assert_allclose(z2, z, atol=1e-12 * scale)
+            continue
+        sign = np.where((par % 2 == 1) & (det < 0), -1.0, 1.0)
+        np.testing.assert_allclose(z2, sign[:, None] * z, atol=1e-12 * scale)
+
+
+def test_translation_and_weight_scaling():
+    wl = inputs.tiny(3, 4, 3, 40, seed=4, box_side=7.0, rmax=3.0, nbins=3)
+    z, p = oracle.npcf(3, 4, 3, wl.edges, wl.box, wl.pos, wl.w)
+    shift = inputs.to_lattice(wl.pos + np.array([[1.75], [-2.5], [3.125]]), wl.box)
+    z2, p2 = oracle.npcf(3, 4, 3, wl.edges, wl.box, shift, wl.w)
+    assert p2 == p
+    np.testing.assert_allclose(z2, z, rtol=0, atol=1e-13 * np.abs(z).max())
+    z3, _ = oracle.npcf(3, 4, 3, wl.edges, wl.box, wl.pos, 2.5 * wl.w)
+    np.testing.assert_allclose(z3, 2.5 ** 4 * z, rtol=1e-12, atol=1e-14 * np.abs(z3).max())
+
+
+def test_primary_additivity():
+    """Eq. NPCF-estimator-discrete sums over primaries: disjoint ranges add up."""
+    wl = inputs.tiny(3, 4, 2, 50, seed=8, box_side=7.0, rmax=3.0, nbins=3)
+    z, p = oracle.npcf(3, 4, 2, wl.edges, wl.box, wl.pos, wl.w)
+    za, pa = oracle.npcf(3, 4, 2, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(0, 17))
+    zb, pb = oracle.npcf(3, 4, 2, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(17, 50))
+    assert pa + pb == p
+    np.testing.assert_allclose(za + zb, z, rtol=1e-13, atol=1e-15 * np.abs(z).max())
