@@ -1,0 +1,196 @@
+/*
+ * npcf.h -- C ABI of the MI355X (gfx950) separable N-point correlation
+ * function estimator.
+ *
+ * The estimator is eq. NPCF-estimator-discrete of Philcox & Slepian,
+ * "Efficient Computation of N-Point Correlation Functions in D Dimensions"
+ * (arXiv:2106.10278), section "Application to Discrete Data":
+ *
+ *   zeta^{Lambda, b} = 1/V_D * sum_j w_j sum_{[l^1]..[l^{N-1}]} C^{Lambda;0} prod_i a^{b_i}_{[l^i]}(y_j)
+ *   a^b_[l](y_j)     = 1/v_b * sum_k w_k Y*_[l](unit(y_k - y_j)) Theta^b(|y_k - y_j|)
+ *
+ * for isotropic (vec L = 0) basis states, N in {3, 4}, D in {2, 3, 4}
+ * (D = 4 with N = 3 only), flat periodic or open boxes.  The harmonic stage
+ * (the O(n^2) sum defining a) and the coupling stage (the per-primary sum
+ * over [l] weighted by the coupling coefficients of eq. Coupling-C) run as
+ * hand-written HIP kernels on the plan's stream.
+ *
+ * Conventions (fixed by the library, documented per call):
+ *  - hyperspherical harmonics of Appendix A (eq. hypersph-def) with azimuth
+ *    factor e^{+i l1 theta1}, theta1 = atan2(x2, x1), cos theta_K =
+ *    x_{K+1}/|x_{1..K+1}|;
+ *  - index sets |l1| <= l2 <= ... <= l_{D-1} <= lmax (eq. selection-rules);
+ *  - coupling to vec L = 0 through the Clebsch-Gordan coefficients of eq.
+ *    CG-examples (D = 2: Kronecker delta; D = 3: Wigner 3-j); for D = 4, N = 3
+ *    the coupling of two states to zero is (-1)^{l3-l1}/sqrt((l3+1)^2);
+ *  - bins: e_b <= r < e_{b+1} on exact lattice distances; v_b the shell
+ *    volume |S^{D-1}| (e_{b+1}^D - e_b^D)/D;
+ *  - output: for D >= 3 the real part of zeta for even sum of the l_{D-1}
+ *    and the imaginary part for odd (eq. basis-parity-conj: the other part
+ *    vanishes for a real field); D = 2 outputs both parts.
+ *
+ * Positions are quantised on the device to the lattice box * q / 2^32
+ * (q = round(x / box * 2^32) mod 2^32 per axis); inputs already on that
+ * lattice are represented exactly.
+ *
+ * Thread safety: a plan is used by one host thread at a time; calls on one
+ * plan are ordered on its stream.  No C++ exception crosses this ABI.
+ */
+#ifndef NPCF_H
+#define NPCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NPCF_OK = 0,
+    NPCF_E_INVALID = 1,      /* bad argument or configuration */
+    NPCF_E_UNSUPPORTED = 2,  /* valid request outside what the library implements */
+    NPCF_E_NOMEM = 3,        /* device or host allocation failed */
+    NPCF_E_DEVICE = 4,       /* a HIP call failed (no GPU, launch failure, ...) */
+    NPCF_E_STATE = 5         /* call out of order (e.g. after a failed accumulate) */
+} npcf_status;
+
+/* Coupling-stage arithmetic.  The harmonic stage always evaluates pair
+ * geometry and harmonics in FP32 with exact integer periodic separations and
+ * FP64 near-edge binning; long reductions are carried in FP64. */
+typedef enum {
+    NPCF_PLAIN_FP32 = 0,    /* coupling products in FP32 (MFMA f32) */
+    NPCF_MIXED_BF16X3 = 1,  /* coupling GEMM in BF16 hi+lo split, 3 MFMA products, FP32 accumulate */
+    NPCF_MIXED_FP16X3 = 2,  /* FP16 hi+lo split of power-of-two scaled operand tiles, 3 MFMA products */
+    NPCF_MIXED_BF16X6 = 3   /* BF16 hi+mid+lo split, 6 MFMA products (FP32-level accuracy) */
+} npcf_precision;
+
+typedef enum {
+    NPCF_NORM_RAW = 0,         /* eq. NPCF-estimator-discrete as written */
+    NPCF_NORM_BY_RANDOMS = 1   /* divide each zeta^{Lambda,b} by the Lambda = 0 component of the
+                                  randoms-only estimator (accumulated with NPCF_ROLE_RANDOMS) */
+} npcf_norm;
+
+typedef enum {
+    NPCF_ROLE_DATA = 0,     /* accumulate into the estimator */
+    NPCF_ROLE_RANDOMS = 1   /* accumulate into the randoms normalisation accumulator */
+} npcf_role;
+
+typedef struct {
+    int D;               /* dimension: 2, 3 or 4 */
+    int N;               /* correlation order: 3 or 4 (N = 4 needs D <= 3) */
+    int lmax;            /* maximum l_{D-1}: D=2 <= 16, D=3 <= 10, D=4 <= 8 */
+    int nbins;           /* radial bins, 1..16 */
+    const double *edges; /* host, nbins+1 strictly increasing values, edges[0] > 0; copied */
+    double box[4];       /* side length per axis (first D used), > 0; V_D = product */
+    int periodic;        /* 1: periodic box (requires 2 * edges[nbins] < every side); 0: open */
+    int btuple_mode;     /* 0: b1 < b2 < ... (default); 1: every tuple (b1..b_{N-1} free) */
+    int precision;       /* npcf_precision */
+    int norm;            /* npcf_norm */
+} npcf_config;
+
+typedef struct npcf_plan_s *npcf_plan_t;
+
+/* Create a plan.  Validates cfg, enumerates the basis (Lambda labels and
+ * radial tuples), builds the coupling tables (eq. Coupling-C) on the host in
+ * FP64 and uploads them, and allocates device workspace for catalogues of up
+ * to max_points points.  `stream` is a hipStream_t (NULL: the default
+ * stream).  The plan owns all device memory it allocates.
+ * Errors: NPCF_E_INVALID (bad cfg, max_points < 1, out == NULL),
+ * NPCF_E_UNSUPPORTED (N, D, lmax or nbins outside the table above),
+ * NPCF_E_NOMEM, NPCF_E_DEVICE. */
+npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, npcf_plan_t *out);
+
+/* Add the contribution of primaries [prim_begin, prim_end) (indices into the
+ * catalogue) against all n secondaries of the same catalogue to the plan's
+ * FP64 accumulator selected by `role` (eq. NPCF-estimator-discrete is a sum
+ * over primaries, so calls over disjoint ranges add up).
+ *  pos: device pointer, SoA double [D][n] (pos[k*n + i] = coordinate k of point i)
+ *  w:   device pointer, double [n] (real weights)
+ * The caller keeps pos and w valid until the plan's stream has passed this
+ * call.  Asynchronous.  Errors: NPCF_E_INVALID (n < 1, n > max_points, empty or
+ * out-of-range primary range, NULL pointers, bad role), NPCF_E_DEVICE.
+ * Non-finite coordinates or weights set a device flag reported by the next
+ * npcf_finalize as NPCF_E_INVALID. */
+npcf_status npcf_accumulate(npcf_plan_t plan, const double *pos, const double *w, int64_t n,
+                            int64_t prim_begin, int64_t prim_end, int role);
+
+/* Synchronise the plan's stream and write the finalised estimator to `out`
+ * (host, double, out_len entries): zeta / (V_D prod_i v_{b_i}), parity part
+ * as described above, optionally divided by the randoms normalisation.
+ * Layout: out[lambda * n_bt + t] (D >= 3) or out[(lambda * n_bt + t) * 2 + {0: Re, 1: Im}]
+ * (D = 2), Lambda and radial tuples in the order of npcf_describe.
+ * Does not reset the accumulators.  Errors: NPCF_E_INVALID (out_len wrong,
+ * out NULL, non-finite input seen, BY_RANDOMS with a zero randoms
+ * normalisation), NPCF_E_DEVICE. */
+npcf_status npcf_finalize(npcf_plan_t plan, double *out, size_t out_len);
+
+/* Describe the output layout.  Any pointer may be NULL.
+ *  n_lambda: number of Lambda labels; lambda_labels: int [n_lambda][3]
+ *    (N=3, D>=3: (l,0,0); N=3, D=2: (l,-l,0); N=4: (l1,l2,l3), l12 = l3 implied for D = 3,
+ *    l3 = -l1-l2 for D = 2), lexicographic;
+ *  n_bt: number of radial tuples; btuples: int [n_bt][3] (unused entries 0), lexicographic;
+ *  out_len: entries npcf_finalize writes. */
+npcf_status npcf_describe(npcf_plan_t plan, int *n_lambda, int *lambda_labels, int *n_bt, int *btuples,
+                          size_t *out_len);
+
+/* Number of ordered in-range pairs (e_0 <= r < e_nbins, i != j) seen by the
+ * harmonic stage since the last reset, for each role (synchronises). */
+npcf_status npcf_pair_count(npcf_plan_t plan, int64_t *pairs_data, int64_t *pairs_randoms);
+
+/* Harmonic stage only (eq. alm-bin-def, discrete form): a^b_[l](y_j) for
+ * primaries j in [prim_begin, prim_end), written to `out` (host, double,
+ * (prim_end-prim_begin) * nbins * n_state * 2 entries,
+ * out[((p * nbins + b) * n_state + s) * 2 + {Re, Im}]), including 1/v_b.
+ * States are the stored half l1 >= 0 in the order: D=2: l = 0..lmax;
+ * D=3: (l, m) l-major, m = 0..l; D=4: (l3, l2, l1) l3-major, l1 = 0..l2.
+ * The others follow from a_{(-l1)..} = (-1)^{l1} conj(a_{l1..}) (D >= 3) or
+ * a_{-l} = conj(a_l) (D = 2).  Synchronises.  Errors as npcf_accumulate,
+ * plus NPCF_E_INVALID when out_len is wrong. */
+npcf_status npcf_alm(npcf_plan_t plan, const double *pos, const double *w, int64_t n,
+                     int64_t prim_begin, int64_t prim_end, double *out, size_t out_len);
+
+/* Batched accumulation of `ncat` independent catalogues in one persistent
+ * launch sequence (captured as a HIP graph on first use for a given shape).
+ * Catalogue c: pos[c] (device, SoA double [D][n[c]]), w[c] (device, double
+ * [n[c]]), n_data[c] leading points are data, the rest randoms (both act as
+ * primaries and secondaries with their weights).  Results go to ncat
+ * separate FP64 accumulators read back with npcf_finalize_batch.  Requires
+ * n[c] <= max_points.  Errors: NPCF_E_INVALID, NPCF_E_NOMEM, NPCF_E_DEVICE. */
+npcf_status npcf_accumulate_batch(npcf_plan_t plan, int ncat, const double *const *pos, const double *const *w,
+                                  const int64_t *n);
+
+/* Finalised output of catalogue `cat` of the last npcf_accumulate_batch, with
+ * the same layout and rules as npcf_finalize; per-catalogue completion time
+ * in milliseconds from the start of the batch (device clock) in *done_ms
+ * (may be NULL). */
+npcf_status npcf_finalize_batch(npcf_plan_t plan, int cat, double *out, size_t out_len, double *done_ms);
+
+/* Zero the accumulators and pair counters (asynchronous). */
+npcf_status npcf_reset(npcf_plan_t plan);
+
+/* Release the plan and its device memory (synchronises first). NULL is a no-op. */
+npcf_status npcf_destroy(npcf_plan_t plan);
+
+/* Tuning knobs (0 keeps the default): cell subdivision s (cells of side
+ * >= r_max / s, 1..4) and primaries per coupling block.  Takes effect on
+ * the next accumulate. */
+npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block);
+
+/* Device time in milliseconds, accumulated since the last reset and measured
+ * with HIP events on the plan's stream, of ms3[0] the harmonic stage,
+ * ms3[1] the coupling stage with its FP64 reduction and ms3[2] the cell-list
+ * build (synchronises). */
+npcf_status npcf_stage_ms(npcf_plan_t plan, double *ms3);
+
+/* Static description of a status code (never NULL). */
+const char *npcf_strerror(npcf_status status);
+
+/* Library version string (never NULL). */
+const char *npcf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPCF_H */

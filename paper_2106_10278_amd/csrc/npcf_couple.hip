@@ -1,0 +1,458 @@
+// Coupling stage of the separable NPCF estimator (eq. NPCF-estimator-discrete,
+// the per-primary sum over [l] weighted by C^{Lambda;0} of eq. Coupling-C),
+// recast as small GEMMs that contract over the primary index on MFMA.
+//
+// N = 4 (D = 3 and D = 2).  For a job (Lambda, part, tile of radial pairs):
+//   S_g[i, (b1,b2)] = w_i sum_terms c * op(a_i[b1][s1]) * op(a_i[b2][s2])      (VALU)
+//   Z[(b1,b2), b3] += sum_g sum_i  part( S_g[i,(b1,b2)] * op(a_i[b3][s3_g]) )  (MFMA, K = primaries x {re,im})
+// where g runs over m3 >= 0 for D = 3 (the -m3 half is folded into c by the
+// symmetry a_{l,-m} = (-1)^m conj(a_{l,m}) of a real field) and over the single
+// term for D = 2.
+//
+// N = 3: per Lambda = l, a Hermitian rank-K update
+//   Z[b1, b2] += sum_i sum_{s in l} f_s w_i (a_i[b1][s] conj(a_i[b2][s]))   (MFMA, K = primaries x states x {re,im})
+//
+// Every MFMA chain covers one K = 32 slice and is folded into FP64 at once,
+// so FP32 rounding never accumulates over more than 32 products; per-block
+// FP64 partials are summed over blocks in a fixed order (deterministic).
+// Precision variants of the slice:
+//   0 plain  FP32 operands, 8 x v_mfma_f32_16x16x4_f32
+//   1 BF16   hi + lo split, 3 x v_mfma_f32_16x16x32_bf16 (hi*hi + hi*lo + lo*hi)
+//   2 FP16   hi + lo split after a power-of-two scaling of each operand tile,
+//            3 x v_mfma_f32_16x16x32_f16
+//   3 BF16   hi + mid + lo split, 6 products (all pairs of total order <= 2)
+#include "npcf_internal.h"
+
+namespace npcf {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int kRowsStep = 16;   // primaries staged in LDS per step
+constexpr int kJobsPerWave = 8;
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Power-of-two scale that brings the wave's largest |x| into [0.5, 1) (1 when
+// every x is zero).  FP16's exponent range is too narrow for products of
+// coefficients spanning many octaves without it.
+__device__ __forceinline__ float wave_pow2_scale(float m)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (!(m > 0.f) || !isfinite(m)) return 1.f;
+    int e;
+    frexpf(m, &e);
+    return ldexpf(1.f, -e);
+}
+
+// One K = 32 slice: lane l holds 8 (A, B) operand pairs; A row = l % 16,
+// B column = l % 16, and the 4 lane quarters together cover 32 K indices
+// (the order of K is immaterial to the sum).  Accumulates into c (from zero)
+// and returns the factor that undoes any operand scaling.
+template <int PREC>
+__device__ __forceinline__ void mfma_k32(const float (&Av)[8], const float (&Bv)[8], v4f &c, double &unscale)
+{
+    unscale = 1.0;
+    if constexpr (PREC == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[i], Bv[i], c, 0, 0, 0);
+    } else if constexpr (PREC == 1) {
+        v8bf ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ah[i] = (__bf16)Av[i];
+            al[i] = (__bf16)(Av[i] - (float)ah[i]);
+            bh[i] = (__bf16)Bv[i];
+            bl[i] = (__bf16)(Bv[i] - (float)bh[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    } else if constexpr (PREC == 2) {
+        float ma = 0.f, mb = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ma = fmaxf(ma, fabsf(Av[i]));
+            mb = fmaxf(mb, fabsf(Bv[i]));
+        }
+        const float sa = wave_pow2_scale(ma), sb = wave_pow2_scale(mb);
+        v8h ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const float x = Av[i] * sa, y = Bv[i] * sb;
+            ah[i] = (_Float16)x;
+            al[i] = (_Float16)(x - (float)ah[i]);
+            bh[i] = (_Float16)y;
+            bl[i] = (_Float16)(y - (float)bh[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
+        unscale = 1.0 / ((double)sa * (double)sb);
+    } else {
+        v8bf ah, am, al, bh, bm, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ah[i] = (__bf16)Av[i];
+            float r = Av[i] - (float)ah[i];
+            am[i] = (__bf16)r;
+            al[i] = (__bf16)(r - (float)am[i]);
+            bh[i] = (__bf16)Bv[i];
+            r = Bv[i] - (float)bh[i];
+            bm[i] = (__bf16)r;
+            bl[i] = (__bf16)(r - (float)bm[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    }
+}
+
+// XCD-aware block -> (rowblock, jobgroup): blocks are dispatched round-robin
+// over the 8 XCDs, so the job groups of one rowblock are given consecutive
+// slots on one XCD and its rows of a are served from that XCD's L2.
+__device__ __forceinline__ bool block_work(int nrb, int njg, int &rb, int &jg)
+{
+    const int b = blockIdx.x;
+    const int x = b % kXcd;
+    const int s = b / kXcd;
+    rb = (s / njg) * kXcd + x;
+    jg = s % njg;
+    return rb < nrb;
+}
+
+// Stage kRowsStep rows of a (and their weights) into LDS, zero-padding rows
+// past the end.
+__device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, float *Ast, float *wst)
+{
+    const int rowlen = a.nb * 2 * a.nstate;
+    const int total = kRowsStep * rowlen;
+    const int r_lim = a.nrows - r0;
+    const float *src = a.A + (size_t)r0 * rowlen;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) Ast[t] = (t < r_lim * rowlen) ? src[t] : 0.f;
+    for (int t = threadIdx.x; t < kRowsStep; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// N = 4
+// ---------------------------------------------------------------------------
+struct Job4 {
+    int lam, part_kind, tile;
+};
+
+__device__ __forceinline__ Job4 decode_job4(const CoupleArgs &a, int job, int nparts)
+{
+    Job4 j;
+    j.tile = job % a.mtiles;
+    const int lp = job / a.mtiles;
+    j.lam = lp / nparts;
+    const int part = lp % nparts;
+    j.part_kind = (nparts == 2) ? part : a.lam_part[j.lam];
+    return j;
+}
+
+// complex S of a group for radial pair bb of primary p (already times w_p)
+__device__ __forceinline__ float2 form_s(const CoupleArgs &a, const CoupleGroup &g, const float *Ast, int rowlen,
+                                         int p, int2 bb, bool rowok, float wp)
+{
+    float sr = 0.f, si = 0.f;
+    if (rowok) {
+        const float *Ap = Ast + p * rowlen;
+        const float *A1 = Ap + bb.x * 2 * a.nstate;
+        const float *A2 = Ap + bb.y * 2 * a.nstate;
+        for (int t = g.term_begin; t < g.term_end; t++) {
+            const CoupleTerm tm = a.terms[t];
+            const float2 x = *reinterpret_cast<const float2 *>(A1 + 2 * tm.s1);
+            const float2 y = *reinterpret_cast<const float2 *>(A2 + 2 * tm.s2);
+            const float xi = tm.conj1 ? -x.y : x.y;
+            const float yi = tm.conj2 ? -y.y : y.y;
+            sr += tm.coef * (x.x * y.x - xi * yi);
+            si += tm.coef * (x.x * yi + xi * y.x);
+        }
+    }
+    return make_float2(sr * wp, si * wp);
+}
+
+// The two K-components of part(S * a3): Re -> Sr a3r + (-Si) a3i; Im -> Sr a3i + Si a3r.
+__device__ __forceinline__ void part_operands(int part_kind, float2 s, float a3r, float a3i, float &A0, float &B0,
+                                              float &A1, float &B1)
+{
+    if (part_kind == 0) {
+        A0 = s.x; B0 = a3r;
+        A1 = -s.y; B1 = a3i;
+    } else {
+        A0 = s.x; B0 = a3i;
+        A1 = s.y; B1 = a3r;
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int nparts)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int rowlen = a.nb * 2 * a.nstate;
+    float *Ast = reinterpret_cast<float *>(smem);
+    float *wst = Ast + kRowsStep * rowlen;
+    const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
+    int rb, jg;
+    if (!block_work(a.n_rowblocks, njg, rb, jg)) return;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
+
+    double acc64[kJobsPerWave][4];
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) acc64[j][v] = 0.0;
+
+    const int r_begin = rb * a.rows_per_block;
+    int r_end = r_begin + a.rows_per_block;
+    if (r_end > a.nrows) r_end = a.nrows;
+    const int n = lane & 15;   // A row within the tile / output column b3
+    const int kq = lane >> 4;  // K quarter
+
+    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+        __syncthreads();
+        stage_rows(a, r0, Ast, wst);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kJobsPerWave; j++) {
+            const int job = job0 + j;
+            if (job >= njobs) break;
+            const Job4 jb = decode_job4(a, job, nparts);
+            const int m = jb.tile * 16 + n;
+            const bool rowok = m < a.mrows;
+            const int2 bb = rowok ? a.row_pairs[m] : make_int2(0, 0);
+            const bool colok = n < a.nb;
+            for (int gi = a.lam_group_begin[jb.lam]; gi < a.lam_group_begin[jb.lam + 1]; gi++) {
+                const CoupleGroup g = a.groups[gi];
+                float Av[8], Bv[8];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int p = 4 * kq + q;
+                    const float2 sv = form_s(a, g, Ast, rowlen, p, bb, rowok, wst[p]);
+                    float a3r = 0.f, a3i = 0.f;
+                    if (colok) {
+                        const float2 v = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * 2 * a.nstate + 2 * g.s3);
+                        a3r = v.x;
+                        a3i = g.conj3 ? -v.y : v.y;
+                    }
+                    part_operands(jb.part_kind, sv, a3r, a3i, Av[2 * q], Bv[2 * q], Av[2 * q + 1], Bv[2 * q + 1]);
+                }
+                v4f c = v4f{0.f, 0.f, 0.f, 0.f};
+                double unscale;
+                mfma_k32<PREC>(Av, Bv, c, unscale);
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc64[j][v] += (double)c[v] * unscale;
+            }
+        }
+    }
+    // per-block partials: partial[rb][job][16][16]; lane holds rows 4 kq + v of column n
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++) {
+        const int job = job0 + j;
+        if (job >= njobs) break;
+        double *dst = a.partial + ((size_t)rb * njobs + job) * 256;
+#pragma unroll
+        for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc64[j][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// N = 3: job = (Lambda, part); part 0: Re, 1: Im (D = 2 only)
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void k_couple3(CoupleArgs a, int njobs, int nparts, const float *sfac)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int rowlen = a.nb * 2 * a.nstate;
+    float *Ast = reinterpret_cast<float *>(smem);
+    float *wst = Ast + kRowsStep * rowlen;
+    const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
+    int rb, jg;
+    if (!block_work(a.n_rowblocks, njg, rb, jg)) return;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
+
+    double acc64[kJobsPerWave][4];
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) acc64[j][v] = 0.0;
+    const int r_begin = rb * a.rows_per_block;
+    int r_end = r_begin + a.rows_per_block;
+    if (r_end > a.nrows) r_end = a.nrows;
+    const int n = lane & 15;   // b1 (A row) and b2 (B column) of this lane
+    const int kq = lane >> 4;
+    const bool bok = n < a.nb;
+
+    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+        __syncthreads();
+        stage_rows(a, r0, Ast, wst);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kJobsPerWave; j++) {
+            const int job = job0 + j;
+            if (job >= njobs) break;
+            const int lam = job / nparts;
+            const int part_kind = (nparts == 2) ? (job % nparts) : 0;
+            const CoupleGroup g = a.groups[a.lam_group_begin[lam]];
+            const int kper = 2 * g.nst;   // K entries per primary: states x {re, im}
+            const int ktot = kRowsStep * kper;
+            for (int k0 = 0; k0 < ktot; k0 += 32) {
+                float Av[8], Bv[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const int k = k0 + 8 * kq + i;
+                    Av[i] = 0.f;
+                    Bv[i] = 0.f;
+                    if (k < ktot && bok) {
+                        const int p = k / kper;
+                        const int rr = k - p * kper;
+                        const int s = g.s3 + (rr >> 1);
+                        const int c = rr & 1;
+                        const float2 x = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * 2 * a.nstate + 2 * s);
+                        Bv[i] = c ? x.y : x.x;
+                        const float wf = wst[p] * g.scale3 * sfac[s];
+                        // Re(a[b1] conj(a[b2])) = ar ar' + ai ai';  Im = ai ar' - ar ai'
+                        Av[i] = (part_kind == 0) ? wf * (c ? x.y : x.x) : wf * (c ? -x.x : x.y);
+                    }
+                }
+                v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                double unscale;
+                mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc64[j][v] += (double)cc[v] * unscale;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++) {
+        const int job = job0 + j;
+        if (job >= njobs) break;
+        double *dst = a.partial + ((size_t)rb * njobs + job) * 256;
+#pragma unroll
+        for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc64[j][v];
+    }
+}
+
+__global__ void k_reduce_partials(const double *partial, int nrb, int64_t len, double *acc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int r = 0; r < nrb; r++) s += partial[(size_t)r * len + i];
+    acc[i] += s;
+}
+
+struct FinArgs {
+    const double *acc;
+    const double *acc_rand;
+    int nlam;
+    int nparts;              // 2 for D = 2, else 1
+    int mtiles;
+    const int *bt_row;       // GEMM row of each radial tuple
+    const int *bt_col;       // GEMM column
+    const double *bt_scale;  // 1 / (V_D prod v_b)
+    int nbt;
+    int norm_by_randoms;
+    int lam0;                // index of Lambda = 0 (randoms normalisation)
+    double *out;
+    int *bad;
+};
+
+__global__ void k_finalize(FinArgs f)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)f.nlam * f.nparts * f.nbt;
+    if (i >= total) return;
+    const int part = (int)(i % f.nparts);
+    const int64_t lt = i / f.nparts;
+    const int t = (int)(lt % f.nbt);
+    const int lam = (int)(lt / f.nbt);
+    const int m = f.bt_row[t], c = f.bt_col[t];
+    const int tile = m / 16;
+    const size_t job = ((size_t)lam * f.nparts + part) * f.mtiles + tile;
+    double v = f.acc[job * 256 + (m % 16) * 16 + c] * f.bt_scale[t];
+    if (f.norm_by_randoms) {
+        const size_t job0 = ((size_t)f.lam0 * f.nparts + 0) * f.mtiles + tile;
+        const double r = f.acc_rand[job0 * 256 + (m % 16) * 16 + c] * f.bt_scale[t];
+        if (r == 0.0 || !isfinite(r)) atomicOr(f.bad, 2);
+        v = v / r;
+    }
+    f.out[i] = v;  // [lambda][t][part]
+}
+
+inline int couple_lds(const CoupleArgs &a) { return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4; }
+
+template <class K, class... Args>
+hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... args)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), lds, s, args...);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam * nparts * mtiles : nlam * nparts; }
+
+int couple_nblocks(int njobs, int nrb)
+{
+    const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
+    const int per_xcd = njg * ((nrb + kXcd - 1) / kXcd);
+    return per_xcd * kXcd;
+}
+
+hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
+                                hipStream_t s)
+{
+    const int lds = couple_lds(a);
+    const int nblk = couple_nblocks(njobs, a.n_rowblocks);
+    if (N == 4) {
+        switch (precision) {
+        case 0: return launch_with_lds(k_couple4<0>, nblk, lds, s, a, njobs, nparts);
+        case 1: return launch_with_lds(k_couple4<1>, nblk, lds, s, a, njobs, nparts);
+        case 2: return launch_with_lds(k_couple4<2>, nblk, lds, s, a, njobs, nparts);
+        case 3: return launch_with_lds(k_couple4<3>, nblk, lds, s, a, njobs, nparts);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (precision) {
+    case 0: return launch_with_lds(k_couple3<0>, nblk, lds, s, a, njobs, nparts, sfac);
+    case 1: return launch_with_lds(k_couple3<1>, nblk, lds, s, a, njobs, nparts, sfac);
+    case 2: return launch_with_lds(k_couple3<2>, nblk, lds, s, a, njobs, nparts, sfac);
+    case 3: return launch_with_lds(k_couple3<3>, nblk, lds, s, a, njobs, nparts, sfac);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_partials(const double *partial, int nrb, int64_t len, double *acc, hipStream_t s)
+{
+    const int64_t g = (len + 255) / 256;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)g), dim3(256), 0, s, partial, nrb, len, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam, int nparts, int mtiles,
+                            const int *bt_row, const int *bt_col, const double *bt_scale, int nbt, int norm_by_randoms,
+                            int lam0, double *out, int *bad, hipStream_t s)
+{
+    FinArgs f{acc, acc_rand, nlam, nparts, mtiles, bt_row, bt_col, bt_scale, nbt, norm_by_randoms, lam0, out, bad};
+    const int64_t total = (int64_t)nlam * nparts * nbt;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+}  // namespace npcf

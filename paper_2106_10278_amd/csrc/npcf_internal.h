@@ -1,0 +1,176 @@
+// Internal declarations shared by the host planner and the HIP kernels of the
+// NPCF library.  Nothing here is part of the public ABI (include/npcf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "npcf.h"
+
+namespace npcf {
+
+constexpr int kMaxD = 4;
+constexpr int kMaxBins = 16;
+constexpr int kWave = 64;
+
+// Number of stored harmonic states (l1 >= 0 half) for dimension D and lmax L.
+//   D = 2: l = 0..L                       -> L + 1
+//   D = 3: (l, m), 0 <= m <= l <= L        -> (L+1)(L+2)/2
+//   D = 4: (l3, l2, l1), 0 <= l1 <= l2 <= l3 <= L -> sum_{l3} (l3+1)(l3+2)/2
+__host__ __device__ constexpr int stored_states(int D, int L)
+{
+    return D == 2 ? L + 1
+         : D == 3 ? (L + 1) * (L + 2) / 2
+                  : (L + 1) * (L + 2) * (L + 3) / 6;
+}
+
+// ---------------------------------------------------------------------------
+// Device workspace of one catalogue after the cell-list build.
+// ---------------------------------------------------------------------------
+struct CellList {
+    uint32_t *q[kMaxD] = {nullptr, nullptr, nullptr, nullptr};  // sorted lattice coordinates (SoA)
+    float *w = nullptr;               // sorted weights (FP32)
+    double *w64 = nullptr;            // sorted weights (FP64)
+    int32_t *orig = nullptr;          // sorted position -> original index
+    uint32_t *cell_start = nullptr;   // [ncell + 1]
+    int ncs[kMaxD] = {1, 1, 1, 1};    // cells per side
+    int64_t ncell = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Harmonic stage arguments.
+// ---------------------------------------------------------------------------
+struct HarmArgs {
+    const uint32_t *q[kMaxD];
+    const float *w;
+    const uint32_t *cell_start;
+    const int32_t *prim;      // sorted positions of this chunk's primaries
+    int nrows;
+    int nb;
+    int ncs[kMaxD];
+    double cell_len[kMaxD];   // cell side, lattice units (2^32 / ncs)
+    double rmax_lat[kMaxD];   // r_max in lattice units per axis
+    double scale64[kMaxD];    // physical length of one lattice unit per axis
+    float scale[kMaxD];
+    float e2lo_f, e2hi_f;     // conservative FP32 range test on r^2 (physical)
+    float bucket_lo, bucket_inv;  // r^2 -> bucket index for the first bin guess
+    int nbucket;
+    const double *e2;         // [nb + 1] squared edges (physical, FP64)
+    const uint8_t *bucket_bin;  // [nbucket] bin at the low end of each r^2 bucket
+    const float *hconst;      // recurrence constants of the harmonics
+    float *A;                 // out: [nrows][nb][2 * nstate]
+    float *wrow;              // out: [nrows] primary weights
+    unsigned long long *pairs;  // in-range pair counter
+    unsigned int *work;       // dynamic row counter (zeroed before launch)
+    int periodic;
+};
+
+// ---------------------------------------------------------------------------
+// Coupling stage arguments.
+// ---------------------------------------------------------------------------
+// One coupling term of a (Lambda, group) GEMM K-slice: S += coef * op1(a[s1]) * op2(a[s2]).
+struct CoupleTerm {
+    int16_t s1, s2;     // stored state indices
+    int8_t conj1, conj2;
+    int16_t pad;
+    float coef;
+};
+
+// A group is one (Lambda, m3) pair for N = 4 (the contraction partner a3 =
+// a[s3], conjugated when conj3) and one Lambda for N = 3.
+struct CoupleGroup {
+    int term_begin, term_end;   // N = 4: into the term table
+    int s3;                     // N = 4: state of leg 3; N = 3: first state of l
+    int nst;                    // N = 3: number of stored states of l
+    int conj3;
+    float scale3;               // N = 3: coefficient (f * sign / sqrt(dim)); N = 4: unused
+};
+
+struct CoupleArgs {
+    const float *A;            // [nrows][nb][2 * nstate]
+    const float *wrow;         // [nrows]
+    int nrows;
+    int nb;
+    int nstate;
+    int rows_per_block;        // primaries per workgroup (multiple of 16)
+    int n_rowblocks;
+    int nlam;
+    int lam_per_block;
+    const CoupleTerm *terms;
+    const CoupleGroup *groups;
+    const int *lam_group_begin;   // [nlam + 1] groups of each Lambda
+    const int *lam_part;          // [nlam] 0: Re, 1: Im, 2: both (D = 2)
+    const int2 *row_pairs;        // [mrows] (b1, b2) of GEMM row m (N = 4); unused for N = 3
+    int mrows;                    // valid GEMM rows (N = 4)
+    int mtiles;                   // ceil(mrows / 16) (N = 4); 1 (N = 3)
+    double *partial;              // out: [n_rowblocks][nlam][2][mtiles*16][16]
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_quantize(int D, int periodic, const double *pos, const double *w, int64_t n, const double *box,
+                           const int *ncs, uint32_t *const qtmp[kMaxD], uint32_t *cell, uint32_t *count, int *bad,
+                           hipStream_t s);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *scratch,
+                                 int64_t scratch_len, hipStream_t s);
+hipError_t launch_scatter_perm(int64_t n, const uint32_t *cell, uint32_t *cursor, int32_t *perm, hipStream_t s);
+hipError_t launch_cellsort(int64_t n, const uint32_t *cell, const uint32_t *cell_start, const int32_t *perm,
+                           int32_t *perm_sorted, hipStream_t s);
+hipError_t launch_gather(int D, int64_t n, const int32_t *perm_sorted, uint32_t *const qtmp[kMaxD],
+                         const double *w, uint32_t *const qs[kMaxD], float *ws, double *w64s, int32_t *orig,
+                         hipStream_t s);
+hipError_t launch_primlist(int64_t n, const int32_t *orig, int64_t p0, int64_t p1, uint32_t *flag,
+                           uint32_t *pos_out, int32_t *prim, uint32_t *scratch, int64_t scratch_len, hipStream_t s);
+hipError_t launch_harmonic_d2(int L, const HarmArgs &a, int grid, hipStream_t s);
+hipError_t launch_harmonic_d3(int L, const HarmArgs &a, int grid, hipStream_t s);
+hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s);
+int harmonic_lds_bytes_d2(int L, int nb);
+int harmonic_lds_bytes_d3(int L, int nb);
+int harmonic_lds_bytes_d4(int L, int nb);
+int couple_njobs(int N, int nlam, int nparts, int mtiles);
+int couple_nblocks(int njobs, int nrb);
+hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
+                                hipStream_t s);
+hipError_t launch_reduce_partials(const double *partial, int nrb, int64_t len, double *acc, hipStream_t s);
+hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam, int nparts, int mtiles,
+                            const int *bt_row, const int *bt_col, const double *bt_scale, int nbt, int norm_by_randoms,
+                            int lam0, double *out, int *bad, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Host planner (npcf_plan.cpp)
+// ---------------------------------------------------------------------------
+struct Tables {
+    int nstate = 0;
+    std::vector<int> state_lab;        // [nstate][3]: (l1, l2, l3) as applicable
+    std::vector<int> lam_lab;          // [nlam][3]
+    std::vector<int> bt_lab;           // [nbt][3]
+    int nlam = 0, nbt = 0, nparts = 1;
+    std::vector<int> lam_part;         // [nlam]
+    std::vector<CoupleTerm> terms;
+    std::vector<CoupleGroup> groups;
+    std::vector<int> lam_group_begin;  // [nlam + 1]
+    std::vector<int2> row_pairs;       // N = 4 GEMM rows
+    int mrows = 0, mtiles = 1;
+    std::vector<int> bt_row, bt_col;
+    std::vector<double> bt_scale;
+    std::vector<float> sfac;           // [nstate] N = 3 state factors
+    std::vector<float> hconst;         // harmonic recurrence constants
+    std::vector<double> e2;            // [nb + 1]
+    std::vector<uint8_t> bucket_bin;
+    float bucket_lo = 0.f, bucket_inv = 0.f;
+    float e2lo_f = 0.f, e2hi_f = 0.f;
+    std::vector<double> vb;            // bin volumes
+    int lam0 = 0;
+};
+
+// Validates cfg and fills the tables; returns NPCF_OK or an error code and a message.
+npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err);
+double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M);
+
+}  // namespace npcf

@@ -1,0 +1,309 @@
+// Host planner of the NPCF library: validation, basis enumeration, coupling
+// tables (eq. Coupling-C with the Clebsch-Gordan coefficients of eq.
+// CG-examples), recurrence constants of the harmonics (Appendix A, eq.
+// hypersph-def, in Gegenbauer form) and binning tables.  All in FP64 on the
+// host; the device receives FP32/FP64 tables.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "npcf_internal.h"
+
+namespace npcf {
+
+namespace {
+
+const int kLmaxD[5] = {0, 0, 16, 10, 8};
+
+long double lfac(int n) { return std::lgamma((long double)n + 1.0L); }
+
+// Normalisation of Gegenbauer polynomials: N(lambda, n)^2 * int_{-1}^{1}
+// (1-x^2)^{lambda-1/2} [C^{(lambda)}_n(x)]^2 dx = 1, with the integral equal to
+// pi 2^{1-2 lambda} Gamma(n+2 lambda) / (n! (n+lambda) Gamma(lambda)^2).
+double gegenbauer_norm(double lambda, int n)
+{
+    long double lg = std::log((long double)M_PI) + (1.0L - 2.0L * lambda) * std::log(2.0L) +
+                     std::lgamma((long double)n + 2.0L * lambda) - lfac(n) - std::log((long double)n + lambda) -
+                     2.0L * std::lgamma((long double)lambda);
+    return (double)std::exp(-0.5L * lg);
+}
+
+// Recurrence constants of c_n = K_n C^{(lambda)}_n:  c_0 = K_0,
+// c_n = alpha_n t c_{n-1} - beta_n s c_{n-2}, with
+// alpha_n = (K_n / K_{n-1}) 2 (n + lambda - 1) / n,  beta_n = (K_n / K_{n-2}) (n + 2 lambda - 2) / n.
+void push_gegenbauer(std::vector<float> &h, double lambda, int nmax, double pref)
+{
+    std::vector<double> K(nmax + 1);
+    for (int n = 0; n <= nmax; n++) K[n] = pref * gegenbauer_norm(lambda, n);
+    h.push_back((float)K[0]);
+    for (int n = 1; n <= nmax; n++) {
+        double al = K[n] / K[n - 1] * 2.0 * (n + lambda - 1.0) / n;
+        double be = (n >= 2) ? K[n] / K[n - 2] * (n + 2.0 * lambda - 2.0) / n : 0.0;
+        h.push_back((float)al);
+        h.push_back((float)be);
+    }
+}
+
+int state_index(int D, int l1, int l2, int l3)
+{
+    if (D == 2) return l1;
+    if (D == 3) return l2 * (l2 + 1) / 2 + l1;
+    return l3 * (l3 + 1) * (l3 + 2) / 6 + l2 * (l2 + 1) / 2 + l1;
+}
+
+double dim_so(int D, int l)
+{
+    if (D == 2) return 1.0;
+    if (D == 3) return 2.0 * l + 1.0;
+    // D = 4: (l+1)^2 states of total angular momentum l
+    return (double)(l + 1) * (l + 1);
+}
+
+}  // namespace
+
+// <j1 m1, j2 m2 | J M> by Racah's closed form for the Clebsch-Gordan
+// coefficient (sum over k with all factorial arguments non-negative).
+double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M)
+{
+    if (M != m1 + m2) return 0.0;
+    if (J < std::abs(j1 - j2) || J > j1 + j2) return 0.0;
+    if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(M) > J) return 0.0;
+    long double pre = 0.5L * (std::log(2.0L * J + 1.0L) + lfac(j1 + j2 - J) + lfac(j1 - j2 + J) + lfac(-j1 + j2 + J) -
+                              lfac(j1 + j2 + J + 1) + lfac(j1 + m1) + lfac(j1 - m1) + lfac(j2 + m2) + lfac(j2 - m2) +
+                              lfac(J + M) + lfac(J - M));
+    long double sum = 0.0L;
+    for (int k = 0; k <= j1 + j2 + J; k++) {
+        int f1 = j1 + j2 - J - k, f2 = j1 - m1 - k, f3 = j2 + m2 - k, f4 = J - j2 + m1 + k, f5 = J - j1 - m2 + k;
+        if (f1 < 0 || f2 < 0 || f3 < 0 || f4 < 0 || f5 < 0) continue;
+        long double term = std::exp(pre - lfac(k) - lfac(f1) - lfac(f2) - lfac(f3) - lfac(f4) - lfac(f5));
+        sum += (k % 2) ? -term : term;
+    }
+    return (double)sum;
+}
+
+npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
+{
+    const int D = cfg.D, N = cfg.N, L = cfg.lmax, nb = cfg.nbins;
+    if (D < 2 || D > 4 || (N != 3 && N != 4)) { err = "D must be 2..4 and N 3 or 4"; return NPCF_E_UNSUPPORTED; }
+    if (N == 4 && D == 4) { err = "N = 4 needs D <= 3 (no SO(4) coupling table)"; return NPCF_E_UNSUPPORTED; }
+    if (L < 0) { err = "lmax must be >= 0"; return NPCF_E_INVALID; }
+    if (L > kLmaxD[D]) { err = "lmax above the supported maximum for this D"; return NPCF_E_UNSUPPORTED; }
+    if (nb < 1) { err = "nbins must be >= 1"; return NPCF_E_INVALID; }
+    if (nb > kMaxBins) { err = "nbins above 16"; return NPCF_E_UNSUPPORTED; }
+    if (!cfg.edges) { err = "edges is NULL"; return NPCF_E_INVALID; }
+    for (int b = 0; b <= nb; b++)
+        if (!std::isfinite(cfg.edges[b])) { err = "edges must be finite"; return NPCF_E_INVALID; }
+    if (!(cfg.edges[0] > 0.0)) { err = "edges[0] must be > 0"; return NPCF_E_INVALID; }
+    for (int b = 0; b < nb; b++)
+        if (!(cfg.edges[b + 1] > cfg.edges[b])) { err = "edges must increase strictly"; return NPCF_E_INVALID; }
+    for (int k = 0; k < D; k++) {
+        if (!(cfg.box[k] > 0.0) || !std::isfinite(cfg.box[k])) { err = "box sides must be positive"; return NPCF_E_INVALID; }
+        if (!(2.0 * cfg.edges[nb] < cfg.box[k])) { err = "need 2 * edges[nbins] < every box side"; return NPCF_E_INVALID; }
+    }
+    if (cfg.btuple_mode != 0 && cfg.btuple_mode != 1) { err = "btuple_mode must be 0 or 1"; return NPCF_E_INVALID; }
+    if (cfg.precision < 0 || cfg.precision > 3) { err = "unknown precision"; return NPCF_E_INVALID; }
+    if (cfg.norm != 0 && cfg.norm != 1) { err = "unknown norm"; return NPCF_E_INVALID; }
+    if (cfg.periodic != 0 && cfg.periodic != 1) { err = "periodic must be 0 or 1"; return NPCF_E_INVALID; }
+
+    // ---- stored states (l1 >= 0 half) --------------------------------------
+    t.nstate = stored_states(D, L);
+    t.state_lab.assign(3 * t.nstate, 0);
+    t.sfac.assign(t.nstate, 1.f);
+    for (int l3 = 0; l3 <= (D == 4 ? L : 0); l3++)
+        for (int l2 = 0; l2 <= (D == 2 ? 0 : (D == 3 ? L : l3)); l2++)
+            for (int l1 = 0; l1 <= (D == 2 ? L : l2); l1++) {
+                int s = state_index(D, l1, l2, l3);
+                t.state_lab[3 * s] = l1;
+                t.state_lab[3 * s + 1] = l2;
+                t.state_lab[3 * s + 2] = l3;
+                t.sfac[s] = (D >= 3 && l1 > 0) ? 2.f : 1.f;
+            }
+
+    // ---- Lambda labels ----------------------------------------------------------
+    t.lam_lab.clear();
+    if (N == 3) {
+        for (int l = 0; l <= L; l++) {
+            t.lam_lab.push_back(l);
+            t.lam_lab.push_back(D == 2 ? -l : 0);
+            t.lam_lab.push_back(0);
+        }
+    } else if (D == 3) {
+        for (int l1 = 0; l1 <= L; l1++)
+            for (int l2 = 0; l2 <= L; l2++)
+                for (int l3 = std::abs(l1 - l2); l3 <= std::min(L, l1 + l2); l3++) {
+                    t.lam_lab.push_back(l1);
+                    t.lam_lab.push_back(l2);
+                    t.lam_lab.push_back(l3);
+                }
+    } else {
+        for (int l1 = 0; l1 <= L; l1++)
+            for (int l2 = -L; l2 <= L; l2++) {
+                int l3 = -l1 - l2;
+                if (std::abs(l3) > L) continue;
+                t.lam_lab.push_back(l1);
+                t.lam_lab.push_back(l2);
+                t.lam_lab.push_back(l3);
+            }
+    }
+    t.nlam = (int)t.lam_lab.size() / 3;
+    t.nparts = (D == 2) ? 2 : 1;
+    t.lam0 = 0;
+    for (int i = 0; i < t.nlam; i++)
+        if (t.lam_lab[3 * i] == 0 && t.lam_lab[3 * i + 1] == 0 && t.lam_lab[3 * i + 2] == 0) {
+            t.lam0 = i;
+            break;
+        }
+
+    // ---- radial tuples and GEMM row/column of each ------------------------------
+    t.bt_lab.clear();
+    t.row_pairs.clear();
+    t.bt_row.clear();
+    t.bt_col.clear();
+    if (N == 3) {
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                if (cfg.btuple_mode == 0 && !(b1 < b2)) continue;
+                t.bt_lab.insert(t.bt_lab.end(), {b1, b2, 0});
+                t.bt_row.push_back(b1);
+                t.bt_col.push_back(b2);
+            }
+        t.mrows = nb;
+        t.mtiles = 1;
+    } else {
+        std::vector<int> rowid(nb * nb, -1);
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++) {
+                if (cfg.btuple_mode == 0 && !(b1 < b2 && b2 < nb - 1)) continue;
+                rowid[b1 * nb + b2] = (int)t.row_pairs.size();
+                t.row_pairs.push_back(make_int2(b1, b2));
+            }
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++)
+                for (int b3 = 0; b3 < nb; b3++) {
+                    if (cfg.btuple_mode == 0 && !(b1 < b2 && b2 < b3)) continue;
+                    t.bt_lab.insert(t.bt_lab.end(), {b1, b2, b3});
+                    t.bt_row.push_back(rowid[b1 * nb + b2]);
+                    t.bt_col.push_back(b3);
+                }
+        t.mrows = (int)t.row_pairs.size();
+        t.mtiles = std::max(1, (t.mrows + 15) / 16);
+        if (t.row_pairs.empty()) t.row_pairs.push_back(make_int2(0, 0));
+    }
+    t.nbt = (int)t.bt_lab.size() / 3;
+
+    // ---- bins ------------------------------------------------------------------
+    const double area = 2.0 * std::pow(M_PI, 0.5 * D) / std::tgamma(0.5 * D);
+    t.e2.resize(nb + 1);
+    t.vb.resize(nb);
+    for (int b = 0; b <= nb; b++) t.e2[b] = cfg.edges[b] * cfg.edges[b];
+    for (int b = 0; b < nb; b++) t.vb[b] = area * (std::pow(cfg.edges[b + 1], D) - std::pow(cfg.edges[b], D)) / D;
+    double VD = 1.0;
+    for (int k = 0; k < D; k++) VD *= cfg.box[k];
+    t.bt_scale.resize(t.nbt);
+    for (int i = 0; i < t.nbt; i++) {
+        double p = VD;
+        for (int k = 0; k < N - 1; k++) p *= t.vb[t.bt_lab[3 * i + k]];
+        t.bt_scale[i] = 1.0 / p;
+    }
+    t.e2lo_f = (float)(t.e2[0] * (1.0 - 1e-5));
+    t.e2hi_f = (float)(t.e2[nb] * (1.0 + 1e-5));
+    const int nbucket = 1024;
+    t.bucket_bin.resize(nbucket);
+    t.bucket_lo = (float)t.e2[0];
+    t.bucket_inv = (float)(nbucket / (t.e2[nb] - t.e2[0]));
+    for (int k = 0; k < nbucket; k++) {
+        double r2 = t.e2[0] + (t.e2[nb] - t.e2[0]) * k / nbucket;
+        int b = 0;
+        while (b + 1 < nb && r2 >= t.e2[b + 1]) b++;
+        t.bucket_bin[k] = (uint8_t)b;
+    }
+
+    // ---- harmonic recurrence constants ---------------------------------------------
+    t.hconst.clear();
+    const double inv_sqrt_2pi = 1.0 / std::sqrt(2.0 * M_PI);
+    if (D == 2) {
+        t.hconst.push_back((float)inv_sqrt_2pi);
+    } else if (D == 3) {
+        for (int m = 0; m <= L; m++) push_gegenbauer(t.hconst, m + 0.5, L - m, inv_sqrt_2pi);
+    } else {
+        for (int l2 = 0; l2 <= L; l2++) push_gegenbauer(t.hconst, l2 + 1.0, L - l2, 1.0);
+        for (int l1 = 0; l1 <= L; l1++) push_gegenbauer(t.hconst, l1 + 0.5, L - l1, inv_sqrt_2pi);
+    }
+
+    // ---- coupling groups and terms ----------------------------------------------------
+    t.terms.clear();
+    t.groups.clear();
+    t.lam_group_begin.assign(1, 0);
+    t.lam_part.assign(t.nlam, 0);
+    for (int lam = 0; lam < t.nlam; lam++) {
+        const int *lb = &t.lam_lab[3 * lam];
+        if (N == 3) {
+            const int l = lb[0];
+            CoupleGroup g{};
+            if (D == 2) {
+                g.s3 = l;
+                g.nst = 1;
+                g.scale3 = 1.f;
+            } else {
+                g.s3 = state_index(D, 0, D == 3 ? l : 0, l);
+                g.nst = (D == 3) ? (l + 1) : (l + 1) * (l + 2) / 2;
+                // C = (-1)^{l - l1} / sqrt(dim) for the pair ([l], (-l1, ...)); with
+                // a_{(-l1)} = (-1)^{l1} conj(a_{l1}) the product is (-1)^l a conj(a) / sqrt(dim)
+                g.scale3 = (float)(((l % 2) ? -1.0 : 1.0) / std::sqrt(dim_so(D, l)));
+            }
+            t.groups.push_back(g);
+            t.lam_part[lam] = 0;
+        } else if (D == 2) {
+            const int l1 = lb[0], l2 = lb[1], l3 = lb[2];
+            CoupleGroup g{};
+            g.term_begin = (int)t.terms.size();
+            CoupleTerm tm{};
+            tm.s1 = (int16_t)l1;
+            tm.conj1 = 0;
+            tm.s2 = (int16_t)std::abs(l2);
+            tm.conj2 = l2 < 0;
+            tm.coef = 1.f;
+            t.terms.push_back(tm);
+            g.term_end = (int)t.terms.size();
+            g.s3 = std::abs(l3);
+            g.conj3 = l3 < 0;
+            t.groups.push_back(g);
+        } else {
+            const int l1 = lb[0], l2 = lb[1], l3 = lb[2];
+            t.lam_part[lam] = (l1 + l2 + l3) % 2;
+            for (int m3 = 0; m3 <= l3; m3++) {
+                CoupleGroup g{};
+                g.term_begin = (int)t.terms.size();
+                g.s3 = state_index(3, m3, l3, 0);
+                g.conj3 = 0;
+                const double fold = (m3 > 0) ? 2.0 : 1.0;
+                for (int m1 = -l1; m1 <= l1; m1++) {
+                    const int m2 = -m1 - m3;
+                    if (std::abs(m2) > l2) continue;
+                    // eq. Coupling-C: sum over M12 of <l1 m1, l2 m2 | l12 M12><l12 M12, l3 m3 | 0 0>, l12 = l3
+                    double c = 0.0;
+                    for (int M12 = -l3; M12 <= l3; M12++)
+                        c += clebsch_gordan(l1, m1, l2, m2, l3, M12) * clebsch_gordan(l3, M12, l3, m3, 0, 0);
+                    if (c == 0.0) continue;
+                    CoupleTerm tm{};
+                    double sgn = 1.0;
+                    tm.s1 = (int16_t)state_index(3, std::abs(m1), l1, 0);
+                    tm.conj1 = m1 < 0;
+                    if (m1 < 0 && (-m1) % 2) sgn = -sgn;
+                    tm.s2 = (int16_t)state_index(3, std::abs(m2), l2, 0);
+                    tm.conj2 = m2 < 0;
+                    if (m2 < 0 && (-m2) % 2) sgn = -sgn;
+                    tm.coef = (float)(fold * sgn * c);
+                    t.terms.push_back(tm);
+                }
+                g.term_end = (int)t.terms.size();
+                if (g.term_end > g.term_begin) t.groups.push_back(g);
+            }
+        }
+        t.lam_group_begin.push_back((int)t.groups.size());
+    }
+    if (t.terms.empty()) t.terms.push_back(CoupleTerm{});
+    return NPCF_OK;
+}
+
+}  // namespace npcf

@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path (called through the C ABI) against the FP64 oracle
+on the same seeded inputs, per multipole.
+
+Tolerances follow the targets of the plain and mixed paths: relative error
+per multipole <= 1e-6 (plain FP32) and <= 1e-5 (split-precision coupling).
+Bin assignment is exact on lattice inputs, so pair counts are compared bit
+for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_10278_amd import inputs
+from npcf_testutil import gpu_run, oracle_reported, per_multipole_error
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"plain": 1e-6, "mixed_bf16": 1e-5, "mixed_fp16": 1e-5}
+
+
+def _case(D, N, lmax, n, seed, box, rmax, nbins, weights="mixed"):
+    return inputs.tiny(D, N, lmax, n, seed, box_side=box, rmax=rmax, nbins=nbins, weights=weights)
+
+
+TINY = {
+    "D3N3": (3, 3, 4, 400, 1, 20.0, 5.0, 4),
+    "D3N4": (3, 4, 3, 300, 2, 16.0, 4.5, 4),
+    "D2N4": (2, 4, 4, 400, 3, 12.0, 3.0, 5),
+    "D2N3": (2, 3, 5, 400, 4, 12.0, 3.0, 5),
+    "D4N3": (4, 3, 3, 500, 5, 10.0, 3.5, 4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TINY))
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16", "mixed_fp16"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tiny_parity(name, precision, mode):
+    wl = _case(*TINY[name])
+    print(f"[case] {name} {precision} mode={mode}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl, btuple_mode=mode)
+    got, pairs, plan = gpu_run(wl, precision=precision, btuple_mode=mode)
+    assert np.array_equal(plan.lambda_labels, oracle.lambda_labels(wl.D, wl.N, wl.lmax))
+    assert np.array_equal(plan.btuples, oracle.btuple_labels(len(wl.edges) - 1, wl.N, mode))
+    assert pairs == pairs_ref
+    err, _ = per_multipole_error(got, ref)
+    print(f"[err] {name} {precision} mode={mode}: {err:.3e}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16"])
+def test_c1_full(precision):
+    """D = 3, N = 3: 2000 uniform points, 8 bins in [2, 20], lmax = 4 (all primaries)."""
+    wl = inputs.c1_small_3pcf()
+    print(f"[case] c1 {precision}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl, precision=precision)
+    assert pairs == pairs_ref
+    err, _ = per_multipole_error(got, ref)
+    print(f"[err] c1 {precision}: {err:.3e} pairs {pairs}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("D,lmax", [(2, 6), (3, 5), (4, 4)])
+def test_alm_matches_oracle(D, lmax):
+    """Harmonic stage alone (npcf_alm) against the oracle's a^b_[l]."""
+    import torch
+    from paper_2106_10278_amd import NPCF, stored_state_labels
+    wl = _case(D, 3, lmax, 500, 11 + D, 12.0, 4.0, 3)
+    print(f"[case] alm D={D}", flush=True)
+    plan = NPCF(D, 3, lmax, wl.edges, wl.box, max_points=wl.pos.shape[1])
+    pos = torch.from_numpy(wl.pos).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    got = plan.alm(pos, w, 10, 70)
+    ref, _ = oracle.alm(D, lmax, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(10, 70))
+    olab = [tuple(r) for r in oracle.state_labels(D, lmax)]
+    idx = []
+    for s in stored_state_labels(D, lmax):
+        key = (int(s[0]),) if D == 2 else ((int(s[0]), int(s[1])) if D == 3 else (int(s[0]), int(s[1]), int(s[2])))
+        idx.append(olab.index(key))
+    ref = ref[:, :, idx]
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 2e-6 * scale
+
+
+def test_additivity_and_pairs():
+    """Disjoint primary ranges add up (eq. NPCF-estimator-discrete sums over primaries)."""
+    wl = _case(3, 4, 3, 400, 21, 16.0, 4.5, 4)
+    print("[case] additivity", flush=True)
+    full, pf, _ = gpu_run(wl)
+    split, ps, _ = gpu_run(wl, ranges=[(0, 123), (123, 250), (250, 400)])
+    assert pf == ps
+    err, _ = per_multipole_error(split, full)
+    assert err <= 1e-6
+
+
+def test_bin_edges_exact():
+    """Separations exactly on a bin edge go to the upper bin, as in the definition
+    e_b <= r < e_{b+1} (box 128: integer coordinates sit on the lattice)."""
+    rng = np.random.default_rng(5)
+    n = 300
+    pos = rng.integers(0, 16, size=(3, n)).astype(np.float64) * 4.0   # many exact integer distances
+    pos = pos + rng.integers(0, 2, size=(3, n)) * 1.0
+    wl = inputs.Workload("edges", 3, 4, 2, np.array([1.0, 2.0, 4.0, 5.0, 8.0]), [128.0] * 3,
+                         inputs.to_lattice(pos, [128.0] * 3), rng.uniform(0.5, 1.5, size=n), n)
+    print("[case] bin edges", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl)
+    assert pairs == pairs_ref
+    err, _ = per_multipole_error(got, ref)
+    assert err <= 1e-6
+
+
+def test_degenerate_inputs():
+    import torch
+    from paper_2106_10278_amd import NPCF, NPCFError
+    wl = _case(3, 3, 2, 50, 31, 20.0, 1.0, 2)
+    plan = NPCF(3, 3, 2, wl.edges, wl.box, max_points=50)
+    pos = torch.from_numpy(wl.pos).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    with pytest.raises(NPCFError):
+        plan.accumulate(pos, w, 5, 5)           # empty range
+    plan2 = NPCF(3, 3, 2, wl.edges, wl.box, max_points=10)
+    with pytest.raises(NPCFError):
+        plan2.accumulate(pos, w)                # n > max_points
+    # a single point has no pairs: all zeros
+    plan3 = NPCF(3, 3, 2, wl.edges, wl.box, max_points=50)
+    plan3.accumulate(pos[:, :1].contiguous(), w[:1].contiguous())
+    assert np.all(plan3.finalize() == 0.0)
+    assert plan3.pair_count()[0] == 0
+    # non-finite input is reported at finalize
+    bad = pos.clone()
+    bad[0, 3] = float("nan")
+    plan4 = NPCF(3, 3, 2, wl.edges, wl.box, max_points=50)
+    plan4.accumulate(bad, w)
+    with pytest.raises(NPCFError):
+        plan4.finalize()
+
+
+TOL["mixed_bf16x6"] = 1e-5
+
+
+@pytest.mark.parametrize("name", ["D3N4", "D3N3", "D2N4"])
+def test_tiny_bf16x6(name):
+    wl = _case(*TINY[name])
+    print(f"[case] {name} bf16x6", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl, precision="mixed_bf16x6")
+    assert pairs == pairs_ref
+    err, _ = per_multipole_error(got, ref)
+    print(f"[err] {name} bf16x6: {err:.3e}", flush=True)
+    assert err <= TOL["mixed_bf16x6"]
+
+
+FULL = {
+    # workload factory, sampled primary ranges (data part, randoms part)
+    "c2": (inputs.c2_clustered_4pcf, [(0, 48), (200_000, 200_048)]),
+    "c3": (inputs.c3_vorticity_4pcf, [(0, 24)]),
+    "c5": (inputs.c5_hyper_3pcf, [(0, 24), (1_500_000, 1_500_024)]),
+}
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5"])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16"])
+def test_full_catalogue_sampled_primaries(name, precision):
+    """Full-size catalogues of the benchmark configurations, in the launch
+    configuration the benchmark uses, on a sample of primaries the oracle can
+    afford (eq. NPCF-estimator-discrete is a sum over primaries)."""
+    factory, ranges = FULL[name]
+    wl = factory()
+    prims = np.concatenate([np.arange(a, b) for a, b in ranges])
+    print(f"[case] {name} {precision} n={wl.pos.shape[1]} primaries={len(prims)}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl, prims=prims)
+    got, pairs, _ = gpu_run(wl, ranges=ranges, precision=precision)
+    err, errs = per_multipole_error(got, ref)
+    print(f"[err] {name} {precision}: {err:.3e} (pairs {pairs} vs {pairs_ref})", flush=True)
+    assert pairs == pairs_ref
+    assert err <= TOL[precision]
+
+
+def test_norm_by_randoms():
+    """NPCF_NORM_BY_RANDOMS divides by the Lambda = 0 component of the randoms-only estimator."""
+    import torch
+    from paper_2106_10278_amd import NPCF
+    data = _case(3, 4, 2, 300, 41, 16.0, 4.5, 3)
+    rand = _case(3, 4, 2, 600, 42, 16.0, 4.5, 3, weights="ones")
+    print("[case] by_randoms", flush=True)
+    plan = NPCF(3, 4, 2, data.edges, data.box, norm="by_randoms", max_points=600)
+    pd, wd = torch.from_numpy(data.pos).cuda(), torch.from_numpy(data.w).cuda()
+    pr, wr = torch.from_numpy(rand.pos).cuda(), torch.from_numpy(rand.w).cuda()
+    plan.accumulate(pd, wd, role="data")
+    plan.accumulate(pr, wr, role="randoms")
+    got = plan.finalize()
+    zd, _, _ = oracle_reported(data)
+    zr, _, _ = oracle_reported(rand)
+    i0 = int(np.nonzero(np.all(oracle.lambda_labels(3, 4, 2) == 0, axis=1))[0][0])
+    ref = zd / zr[i0][None, :]
+    err, _ = per_multipole_error(got, ref)
+    assert err <= 2e-6
