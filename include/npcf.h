@@ -79,7 +79,7 @@ typedef enum {
 typedef struct {
     int D;               /* dimension: 2, 3 or 4 */
     int N;               /* correlation order: 3 or 4 (N = 4 needs D <= 3) */
-    int lmax;            /* maximum l_{D-1}: D=2 <= 16, D=3 <= 10, D=4 <= 8 */
+    int lmax;            /* maximum l_{D-1}: D=2 <= 16, D=3 <= 10, D=4 <= 6 */
     int nbins;           /* radial bins, 1..16 */
     const double *edges; /* host, nbins+1 strictly increasing values, edges[0] > 0; copied */
     double box[4];       /* side length per axis (first D used), > 0; V_D = product */

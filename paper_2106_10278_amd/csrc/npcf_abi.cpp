@@ -61,13 +61,15 @@ struct npcf_plan_s {
     int64_t ncell = 1;
     int64_t rows_cap = 0;
     int njobs = 0;
+    int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
     bool failed = false;
 
     DevAlloc mem;
     DevAlloc cellmem;  // cell arrays (re-allocated when the cell grid changes)
     // catalogue workspace
     uint32_t *qtmp[kMaxD] = {};
-    uint32_t *qs[kMaxD] = {};
+    uint4 *rec = nullptr;
+    int rep_off[kMaxBins] = {}, rep_cnt[kMaxBins] = {};
     uint32_t *cell = nullptr;
     int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *prim = nullptr;
     float *ws = nullptr;
@@ -142,6 +144,61 @@ void compute_grid(npcf_plan_s *p)
     p->ncell = total;
 }
 
+// Replica pools of the harmonic stage's scatter.  D <= 3: pools sized from
+// the expected share of pairs in each bin at uniform density (shell volume),
+// with a margin of two standard deviations of a 64-pair batch, scaled to fit
+// the kernel's pool; D = 4: one or two replicas per bin for its atomic adds.
+bool assign_replicas(npcf_plan_s *p)
+{
+    const int D = p->D, nb = p->nb;
+    const int nrep = D == 2 ? harmonic_nrep_d2(p->L) : (D == 3 ? harmonic_nrep_d3(p->L) : harmonic_nrep_d4(p->L));
+    if (nrep <= 0) return false;
+    for (int b = 0; b < kMaxBins; b++) p->rep_off[b] = p->rep_cnt[b] = 0;
+    if (D == 4) {
+        const int per = nrep / kMaxBins;
+        for (int b = 0; b < nb; b++) {
+            p->rep_off[b] = b * per;
+            p->rep_cnt[b] = per;
+        }
+        return per >= 1;
+    }
+    std::vector<double> vol(nb);
+    double tot = 0.0;
+    for (int b = 0; b < nb; b++) {
+        vol[b] = std::pow(p->edges[b + 1], D) - std::pow(p->edges[b], D);
+        tot += vol[b];
+    }
+    std::vector<int> want(nb);
+    int sum = 0;
+    for (int b = 0; b < nb; b++) {
+        const double mean = 64.0 * vol[b] / tot;
+        int w = (int)std::ceil(mean + 2.0 * std::sqrt(mean) + 1.0);
+        w = std::max(2, std::min(64, w));
+        want[b] = w;
+        sum += w;
+    }
+    if (sum > nrep) {
+        int s2 = 0;
+        for (int b = 0; b < nb; b++) {
+            want[b] = std::max(1, (int)std::floor((double)want[b] * nrep / sum));
+            s2 += want[b];
+        }
+        while (s2 > nrep) {
+            int bi = (int)(std::max_element(want.begin(), want.end()) - want.begin());
+            if (want[bi] <= 1) return false;
+            want[bi]--;
+            s2--;
+        }
+    }
+    int off = 0;
+    for (int b = 0; b < nb; b++) {
+        p->rep_off[b] = off;
+        p->rep_cnt[b] = want[b];
+        off += want[b];
+    }
+    return true;
+}
+
 npcf_status alloc_cells(npcf_plan_s *p)
 {
     p->cellmem.release();
@@ -204,21 +261,26 @@ npcf_status build_cells(npcf_plan_s *p, const double *pos, const double *w, int6
     NPCF_TRY(hipMemcpyAsync(p->cursor, p->cell_start, (p->ncell + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     NPCF_TRY(launch_scatter_perm(n, p->cell, p->cursor, p->perm, s));
     NPCF_TRY(launch_cellsort(n, p->cell, p->cell_start, p->perm, p->perm_sorted, s));
-    NPCF_TRY(launch_gather(p->D, n, p->perm_sorted, p->qtmp, w, p->qs, p->ws, p->w64s, p->orig, s));
+    NPCF_TRY(launch_gather(p->D, n, p->perm_sorted, p->qtmp, w, p->rec, p->ws, p->w64s, p->orig, s));
     return NPCF_OK;
 }
 
 HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned long long *pairs)
 {
     HarmArgs a{};
+    a.rec = p->rec;
     for (int k = 0; k < kMaxD; k++) {
-        a.q[k] = p->qs[k] ? p->qs[k] : p->qs[0];
         a.ncs[k] = p->ncs[k];
         a.cell_len[k] = 4294967296.0 / p->ncs[k];
+        a.inv_cell_len[k] = p->ncs[k] / 4294967296.0;
         double sc = (k < p->D) ? p->cfg.box[k] / 4294967296.0 : 1.0;
         a.scale64[k] = sc;
         a.scale[k] = (float)sc;
         a.rmax_lat[k] = p->edges[p->nb] / sc;
+    }
+    for (int b = 0; b < kMaxBins; b++) {
+        a.rep_off[b] = p->rep_off[b];
+        a.rep_cnt[b] = p->rep_cnt[b];
     }
     a.w = p->ws;
     a.cell_start = p->cell_start;
@@ -290,6 +352,7 @@ npcf_status run_couple(npcf_plan_s *p, int rows, double *acc)
     a.row_pairs = p->d_row_pairs;
     a.mrows = t.mrows;
     a.mtiles = t.mtiles;
+    a.max_block_terms = p->max_block_terms;
     const int64_t len = (int64_t)p->njobs * 256;
     if ((int64_t)a.n_rowblocks * len > p->partial_len) {
         // grow the partial buffer (rare: only with small custom block sizes)
@@ -396,6 +459,17 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->cell_subdiv = (p->D == 4) ? 2 : 3;
     const Tables &t = p->t;
     p->njobs = couple_njobs(p->N, t.nlam, t.nparts, t.mtiles);
+    if (p->N == 4) {
+        // a block's jobs are consecutive and span the Lambdas [lam(first), lam(last)]
+        const int jpb = couple_jobs_per_block();
+        for (int j0 = 0; j0 < p->njobs; j0 += jpb) {
+            const int j1 = std::min(j0 + jpb, p->njobs) - 1;
+            const int l0 = j0 / t.mtiles / t.nparts, l1 = j1 / t.mtiles / t.nparts;
+            const int gb = t.lam_group_begin[l0], ge = t.lam_group_begin[l1 + 1];
+            if (gb < ge)
+                p->max_block_terms = std::max(p->max_block_terms, t.groups[ge - 1].term_end - t.groups[gb].term_begin);
+        }
+    }
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -403,11 +477,13 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         return NPCF_E_DEVICE;
     }
     compute_grid(p);
-    DevAlloc &m = p->mem;
-    for (int k = 0; k < p->D; k++) {
-        p->qtmp[k] = m.get<uint32_t>(max_points);
-        p->qs[k] = m.get<uint32_t>(max_points);
+    if (!assign_replicas(p)) {
+        delete p;
+        return NPCF_E_UNSUPPORTED;
     }
+    DevAlloc &m = p->mem;
+    for (int k = 0; k < p->D; k++) p->qtmp[k] = m.get<uint32_t>(max_points);
+    p->rec = m.get<uint4>(max_points);
     p->cell = m.get<uint32_t>(max_points);
     p->perm = m.get<int32_t>(max_points);
     p->perm_sorted = m.get<int32_t>(max_points);

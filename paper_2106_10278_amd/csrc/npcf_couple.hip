@@ -159,9 +159,10 @@ __device__ __forceinline__ Job4 decode_job4(const CoupleArgs &a, int job, int np
     return j;
 }
 
-// complex S of a group for radial pair bb of primary p (already times w_p)
-__device__ __forceinline__ float2 form_s(const CoupleArgs &a, const CoupleGroup &g, const float *Ast, int rowlen,
-                                         int p, int2 bb, bool rowok, float wp)
+// complex S of a group for radial pair bb of primary p (already times w_p);
+// the group's terms are read from the block's LDS copy `tl` (offset tbase)
+__device__ __forceinline__ float2 form_s(const CoupleArgs &a, const CoupleGroup &g, const CoupleTerm *tl, int tbase,
+                                         const float *Ast, int rowlen, int p, int2 bb, bool rowok, float wp)
 {
     float sr = 0.f, si = 0.f;
     if (rowok) {
@@ -169,7 +170,7 @@ __device__ __forceinline__ float2 form_s(const CoupleArgs &a, const CoupleGroup 
         const float *A1 = Ap + bb.x * 2 * a.nstate;
         const float *A2 = Ap + bb.y * 2 * a.nstate;
         for (int t = g.term_begin; t < g.term_end; t++) {
-            const CoupleTerm tm = a.terms[t];
+            const CoupleTerm tm = tl[t - tbase];
             const float2 x = *reinterpret_cast<const float2 *>(A1 + 2 * tm.s1);
             const float2 y = *reinterpret_cast<const float2 *>(A2 + 2 * tm.s2);
             const float xi = tm.conj1 ? -x.y : x.y;
@@ -208,6 +209,20 @@ __global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int np
     const int wave = threadIdx.x >> 6;
     const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
 
+    // the coupling terms of this block's jobs, copied to LDS once
+    CoupleTerm *tl = reinterpret_cast<CoupleTerm *>(wst + kRowsStep);
+    int tbase, tend;
+    {
+        const int jfirst = jg * 4 * kJobsPerWave;
+        int jlast = jfirst + 4 * kJobsPerWave - 1;
+        if (jlast > njobs - 1) jlast = njobs - 1;
+        const int lam0 = decode_job4(a, jfirst, nparts).lam, lam1 = decode_job4(a, jlast, nparts).lam;
+        const int gb = a.lam_group_begin[lam0], ge = a.lam_group_begin[lam1 + 1];
+        tbase = gb < ge ? a.groups[gb].term_begin : 0;
+        tend = gb < ge ? a.groups[ge - 1].term_end : 0;
+        for (int t = threadIdx.x; t < tend - tbase; t += blockDim.x) tl[t] = a.terms[tbase + t];
+    }
+
     double acc64[kJobsPerWave][4];
 #pragma unroll
     for (int j = 0; j < kJobsPerWave; j++)
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int np
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int p = 4 * kq + q;
-                    const float2 sv = form_s(a, g, Ast, rowlen, p, bb, rowok, wst[p]);
+                    const float2 sv = form_s(a, g, tl, tbase, Ast, rowlen, p, bb, rowok, wst[p]);
                     float a3r = 0.f, a3i = 0.f;
                     if (colok) {
                         const float2 v = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * 2 * a.nstate + 2 * g.s3);
@@ -393,7 +408,10 @@ __global__ void k_finalize(FinArgs f)
     f.out[i] = v;  // [lambda][t][part]
 }
 
-inline int couple_lds(const CoupleArgs &a) { return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4; }
+inline int couple_lds(const CoupleArgs &a)
+{
+    return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4 + a.max_block_terms * (int)sizeof(CoupleTerm);
+}
 
 template <class K, class... Args>
 hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... args)
@@ -407,6 +425,8 @@ hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... a
 }  // namespace
 
 int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam * nparts * mtiles : nlam * nparts; }
+
+int couple_jobs_per_block() { return 4 * kJobsPerWave; }
 
 int couple_nblocks(int njobs, int nrb)
 {

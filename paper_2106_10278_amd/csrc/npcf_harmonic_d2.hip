@@ -27,26 +27,50 @@ hipError_t launch_harmonic_d2(int L, const HarmArgs &a, int grid, hipStream_t s)
     }
 }
 
-int harmonic_lds_bytes_d2(int L, int nb)
+int harmonic_lds_bytes_d2(int L)
 {
     switch (L) {
-    case 0: return harm::lds_bytes<2, 0>(nb);
-    case 1: return harm::lds_bytes<2, 1>(nb);
-    case 2: return harm::lds_bytes<2, 2>(nb);
-    case 3: return harm::lds_bytes<2, 3>(nb);
-    case 4: return harm::lds_bytes<2, 4>(nb);
-    case 5: return harm::lds_bytes<2, 5>(nb);
-    case 6: return harm::lds_bytes<2, 6>(nb);
-    case 7: return harm::lds_bytes<2, 7>(nb);
-    case 8: return harm::lds_bytes<2, 8>(nb);
-    case 9: return harm::lds_bytes<2, 9>(nb);
-    case 10: return harm::lds_bytes<2, 10>(nb);
-    case 11: return harm::lds_bytes<2, 11>(nb);
-    case 12: return harm::lds_bytes<2, 12>(nb);
-    case 13: return harm::lds_bytes<2, 13>(nb);
-    case 14: return harm::lds_bytes<2, 14>(nb);
-    case 15: return harm::lds_bytes<2, 15>(nb);
-    case 16: return harm::lds_bytes<2, 16>(nb);
+    case 0: return harm::lds_bytes<2, 0>();
+    case 1: return harm::lds_bytes<2, 1>();
+    case 2: return harm::lds_bytes<2, 2>();
+    case 3: return harm::lds_bytes<2, 3>();
+    case 4: return harm::lds_bytes<2, 4>();
+    case 5: return harm::lds_bytes<2, 5>();
+    case 6: return harm::lds_bytes<2, 6>();
+    case 7: return harm::lds_bytes<2, 7>();
+    case 8: return harm::lds_bytes<2, 8>();
+    case 9: return harm::lds_bytes<2, 9>();
+    case 10: return harm::lds_bytes<2, 10>();
+    case 11: return harm::lds_bytes<2, 11>();
+    case 12: return harm::lds_bytes<2, 12>();
+    case 13: return harm::lds_bytes<2, 13>();
+    case 14: return harm::lds_bytes<2, 14>();
+    case 15: return harm::lds_bytes<2, 15>();
+    case 16: return harm::lds_bytes<2, 16>();
+    default: return -1;
+    }
+}
+
+int harmonic_nrep_d2(int L)
+{
+    switch (L) {
+    case 0: return harm::nrep<2, 0>();
+    case 1: return harm::nrep<2, 1>();
+    case 2: return harm::nrep<2, 2>();
+    case 3: return harm::nrep<2, 3>();
+    case 4: return harm::nrep<2, 4>();
+    case 5: return harm::nrep<2, 5>();
+    case 6: return harm::nrep<2, 6>();
+    case 7: return harm::nrep<2, 7>();
+    case 8: return harm::nrep<2, 8>();
+    case 9: return harm::nrep<2, 9>();
+    case 10: return harm::nrep<2, 10>();
+    case 11: return harm::nrep<2, 11>();
+    case 12: return harm::nrep<2, 12>();
+    case 13: return harm::nrep<2, 13>();
+    case 14: return harm::nrep<2, 14>();
+    case 15: return harm::nrep<2, 15>();
+    case 16: return harm::nrep<2, 16>();
     default: return -1;
     }
 }

@@ -21,20 +21,38 @@ hipError_t launch_harmonic_d3(int L, const HarmArgs &a, int grid, hipStream_t s)
     }
 }
 
-int harmonic_lds_bytes_d3(int L, int nb)
+int harmonic_lds_bytes_d3(int L)
 {
     switch (L) {
-    case 0: return harm::lds_bytes<3, 0>(nb);
-    case 1: return harm::lds_bytes<3, 1>(nb);
-    case 2: return harm::lds_bytes<3, 2>(nb);
-    case 3: return harm::lds_bytes<3, 3>(nb);
-    case 4: return harm::lds_bytes<3, 4>(nb);
-    case 5: return harm::lds_bytes<3, 5>(nb);
-    case 6: return harm::lds_bytes<3, 6>(nb);
-    case 7: return harm::lds_bytes<3, 7>(nb);
-    case 8: return harm::lds_bytes<3, 8>(nb);
-    case 9: return harm::lds_bytes<3, 9>(nb);
-    case 10: return harm::lds_bytes<3, 10>(nb);
+    case 0: return harm::lds_bytes<3, 0>();
+    case 1: return harm::lds_bytes<3, 1>();
+    case 2: return harm::lds_bytes<3, 2>();
+    case 3: return harm::lds_bytes<3, 3>();
+    case 4: return harm::lds_bytes<3, 4>();
+    case 5: return harm::lds_bytes<3, 5>();
+    case 6: return harm::lds_bytes<3, 6>();
+    case 7: return harm::lds_bytes<3, 7>();
+    case 8: return harm::lds_bytes<3, 8>();
+    case 9: return harm::lds_bytes<3, 9>();
+    case 10: return harm::lds_bytes<3, 10>();
+    default: return -1;
+    }
+}
+
+int harmonic_nrep_d3(int L)
+{
+    switch (L) {
+    case 0: return harm::nrep<3, 0>();
+    case 1: return harm::nrep<3, 1>();
+    case 2: return harm::nrep<3, 2>();
+    case 3: return harm::nrep<3, 3>();
+    case 4: return harm::nrep<3, 4>();
+    case 5: return harm::nrep<3, 5>();
+    case 6: return harm::nrep<3, 6>();
+    case 7: return harm::nrep<3, 7>();
+    case 8: return harm::nrep<3, 8>();
+    case 9: return harm::nrep<3, 9>();
+    case 10: return harm::nrep<3, 10>();
     default: return -1;
     }
 }

@@ -1,4 +1,4 @@
-// Instantiations of the harmonic-stage kernel for D = 4 (lmax 0..8).
+// Instantiations of the harmonic-stage kernel for D = 4 (lmax 0..6).
 #include "npcf_harmonic_impl.h"
 
 namespace npcf {
@@ -13,24 +13,34 @@ hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s)
     case 4: return harm::launch_dl<4, 4>(a, grid, s);
     case 5: return harm::launch_dl<4, 5>(a, grid, s);
     case 6: return harm::launch_dl<4, 6>(a, grid, s);
-    case 7: return harm::launch_dl<4, 7>(a, grid, s);
-    case 8: return harm::launch_dl<4, 8>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-int harmonic_lds_bytes_d4(int L, int nb)
+int harmonic_lds_bytes_d4(int L)
 {
     switch (L) {
-    case 0: return harm::lds_bytes<4, 0>(nb);
-    case 1: return harm::lds_bytes<4, 1>(nb);
-    case 2: return harm::lds_bytes<4, 2>(nb);
-    case 3: return harm::lds_bytes<4, 3>(nb);
-    case 4: return harm::lds_bytes<4, 4>(nb);
-    case 5: return harm::lds_bytes<4, 5>(nb);
-    case 6: return harm::lds_bytes<4, 6>(nb);
-    case 7: return harm::lds_bytes<4, 7>(nb);
-    case 8: return harm::lds_bytes<4, 8>(nb);
+    case 0: return harm::lds_bytes<4, 0>();
+    case 1: return harm::lds_bytes<4, 1>();
+    case 2: return harm::lds_bytes<4, 2>();
+    case 3: return harm::lds_bytes<4, 3>();
+    case 4: return harm::lds_bytes<4, 4>();
+    case 5: return harm::lds_bytes<4, 5>();
+    case 6: return harm::lds_bytes<4, 6>();
+    default: return -1;
+    }
+}
+
+int harmonic_nrep_d4(int L)
+{
+    switch (L) {
+    case 0: return harm::nrep<4, 0>();
+    case 1: return harm::nrep<4, 1>();
+    case 2: return harm::nrep<4, 2>();
+    case 3: return harm::nrep<4, 3>();
+    case 4: return harm::nrep<4, 4>();
+    case 5: return harm::nrep<4, 5>();
+    case 6: return harm::nrep<4, 6>();
     default: return -1;
     }
 }

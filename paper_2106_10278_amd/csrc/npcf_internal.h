@@ -44,14 +44,15 @@ struct CellList {
 // Harmonic stage arguments.
 // ---------------------------------------------------------------------------
 struct HarmArgs {
-    const uint32_t *q[kMaxD];
-    const float *w;
+    const uint4 *rec;         // sorted packed records: D=2 (q0,q1,w,0), D=3 (q0,q1,q2,w), D=4 (q0..q3)
+    const float *w;           // sorted weights (FP32)
     const uint32_t *cell_start;
     const int32_t *prim;      // sorted positions of this chunk's primaries
     int nrows;
     int nb;
     int ncs[kMaxD];
     double cell_len[kMaxD];   // cell side, lattice units (2^32 / ncs)
+    double inv_cell_len[kMaxD];
     double rmax_lat[kMaxD];   // r_max in lattice units per axis
     double scale64[kMaxD];    // physical length of one lattice unit per axis
     float scale[kMaxD];
@@ -61,6 +62,8 @@ struct HarmArgs {
     const double *e2;         // [nb + 1] squared edges (physical, FP64)
     const uint8_t *bucket_bin;  // [nbucket] bin at the low end of each r^2 bucket
     const float *hconst;      // recurrence constants of the harmonics
+    int rep_off[kMaxBins];    // replica pool of each bin: first replica
+    int rep_cnt[kMaxBins];    //   and its size
     float *A;                 // out: [nrows][nb][2 * nstate]
     float *wrow;              // out: [nrows] primary weights
     unsigned long long *pairs;  // in-range pair counter
@@ -106,7 +109,8 @@ struct CoupleArgs {
     const int2 *row_pairs;        // [mrows] (b1, b2) of GEMM row m (N = 4); unused for N = 3
     int mrows;                    // valid GEMM rows (N = 4)
     int mtiles;                   // ceil(mrows / 16) (N = 4); 1 (N = 3)
-    double *partial;              // out: [n_rowblocks][nlam][2][mtiles*16][16]
+    int max_block_terms;          // N = 4: most terms any block's jobs use (LDS copy)
+    double *partial;              // out: [n_rowblocks][njobs][16][16]
 };
 
 // ---------------------------------------------------------------------------
@@ -123,17 +127,20 @@ hipError_t launch_scatter_perm(int64_t n, const uint32_t *cell, uint32_t *cursor
 hipError_t launch_cellsort(int64_t n, const uint32_t *cell, const uint32_t *cell_start, const int32_t *perm,
                            int32_t *perm_sorted, hipStream_t s);
 hipError_t launch_gather(int D, int64_t n, const int32_t *perm_sorted, uint32_t *const qtmp[kMaxD],
-                         const double *w, uint32_t *const qs[kMaxD], float *ws, double *w64s, int32_t *orig,
-                         hipStream_t s);
+                         const double *w, uint4 *rec, float *ws, double *w64s, int32_t *orig, hipStream_t s);
 hipError_t launch_primlist(int64_t n, const int32_t *orig, int64_t p0, int64_t p1, uint32_t *flag,
                            uint32_t *pos_out, int32_t *prim, uint32_t *scratch, int64_t scratch_len, hipStream_t s);
 hipError_t launch_harmonic_d2(int L, const HarmArgs &a, int grid, hipStream_t s);
 hipError_t launch_harmonic_d3(int L, const HarmArgs &a, int grid, hipStream_t s);
 hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s);
-int harmonic_lds_bytes_d2(int L, int nb);
-int harmonic_lds_bytes_d3(int L, int nb);
-int harmonic_lds_bytes_d4(int L, int nb);
+int harmonic_lds_bytes_d2(int L);
+int harmonic_lds_bytes_d3(int L);
+int harmonic_lds_bytes_d4(int L);
+int harmonic_nrep_d2(int L);
+int harmonic_nrep_d3(int L);
+int harmonic_nrep_d4(int L);
 int couple_njobs(int N, int nlam, int nparts, int mtiles);
+int couple_jobs_per_block();
 int couple_nblocks(int njobs, int nrb);
 hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
                                 hipStream_t s);

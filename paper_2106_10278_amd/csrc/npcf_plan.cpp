@@ -13,7 +13,7 @@ namespace npcf {
 
 namespace {
 
-const int kLmaxD[5] = {0, 0, 16, 10, 8};
+const int kLmaxD[5] = {0, 0, 16, 10, 6};
 
 long double lfac(int n) { return std::lgamma((long double)n + 1.0L); }
 

@@ -177,23 +177,39 @@ struct GatherArgs {
     const int32_t *perm;
     const uint32_t *qtmp[kMaxD];
     const double *w;
-    uint32_t *qs[kMaxD];
+    uint4 *rec;
     float *ws;
     double *w64s;
     int32_t *orig;
 };
 
+// Sorted catalogue as 16-byte records (one load per candidate in the
+// harmonic stage): D = 2 (q0, q1, w, 0), D = 3 (q0, q1, q2, w), D = 4 (q0..q3)
+// with w the FP32 weight bits; FP32 and FP64 weights also as arrays.
 template <int D>
 __global__ void k_gather(GatherArgs a)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
     int32_t i = a.perm[j];
-#pragma unroll
-    for (int k = 0; k < D; k++) a.qs[k][j] = a.qtmp[k][i];
     double wi = a.w[i];
     if (!isfinite(wi)) wi = 0.0;
-    a.ws[j] = (float)wi;
+    const float wf = (float)wi;
+    uint4 r;
+    r.x = a.qtmp[0][i];
+    r.y = a.qtmp[1][i];
+    if (D == 2) {
+        r.z = __float_as_uint(wf);
+        r.w = 0u;
+    } else if (D == 3) {
+        r.z = a.qtmp[2][i];
+        r.w = __float_as_uint(wf);
+    } else {
+        r.z = a.qtmp[2][i];
+        r.w = a.qtmp[3][i];
+    }
+    a.rec[j] = r;
+    a.ws[j] = wf;
     a.w64s[j] = wi;
     a.orig[j] = i;
 }
@@ -293,17 +309,14 @@ hipError_t launch_cellsort(int64_t n, const uint32_t *cell, const uint32_t *cell
 }
 
 hipError_t launch_gather(int D, int64_t n, const int32_t *perm_sorted, uint32_t *const qtmp[kMaxD],
-                         const double *w, uint32_t *const qs[kMaxD], float *ws, double *w64s, int32_t *orig,
-                         hipStream_t s)
+                         const double *w, uint4 *rec, float *ws, double *w64s, int32_t *orig, hipStream_t s)
 {
     GatherArgs a{};
     a.n = n;
     a.perm = perm_sorted;
-    for (int k = 0; k < kMaxD; k++) {
-        a.qtmp[k] = qtmp[k];
-        a.qs[k] = qs[k];
-    }
+    for (int k = 0; k < kMaxD; k++) a.qtmp[k] = qtmp[k] ? qtmp[k] : qtmp[0];
     a.w = w;
+    a.rec = rec;
     a.ws = ws;
     a.w64s = w64s;
     a.orig = orig;
