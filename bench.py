@@ -9,10 +9,11 @@ seeded (see paper_2106_10278_amd/inputs.py).
 A step is one pass of the whole path over the catalogue: quantise + cell list,
 harmonic stage, coupling stage, FP64 reduction and finalisation
 (npcf_reset + npcf_accumulate + npcf_finalize), inputs resident in HBM.
-The mixed-precision path (BF16 hi+lo split coupling) is the headline value;
-the plain FP32 path is timed on the same inputs and reported beside it, with
-the per-multipole relative error of both against the FP64 oracle on a
-sample of primaries.
+Every coupling precision is timed on the same inputs: plain FP32, FP16 hi+lo
+(per-tile power-of-two scaling), BF16 hi+mid+lo and BF16 hi+lo.  The headline
+value is the fastest split-precision path whose per-multipole relative error
+against the FP64 oracle (on a sample of primaries) is within 1e-5; the plain
+path and the others are reported beside it with their errors.
 
 Prints one JSON line.
 """
@@ -31,10 +32,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12      # MI355X, FP32 vector (packed) FLOP/s
-HBM_PEAK = 8.0e12
-# algorithmic FLOPs per in-range pair of the harmonic stage (geometry,
-# recurrences and weighted accumulation), by (D, lmax)
-FLOPS_PER_PAIR = {(3, 5): 235.0, (3, 4): 175.0, (2, 8): 100.0, (4, 6): 870.0}
+MIXED = ("mixed_fp16", "mixed_bf16x6", "mixed_bf16")
+DTYPE = {"plain": "f32", "mixed_fp16": "f32 harmonics + fp16 hi+lo coupling",
+         "mixed_bf16x6": "f32 harmonics + bf16 hi+mid+lo coupling", "mixed_bf16": "f32 harmonics + bf16 hi+lo coupling"}
+
+
+def flops_per_pair(D: int, L: int) -> float:
+    """Algorithmic FP32 operations of the harmonic stage per in-range pair.
+
+    Geometry: D converts, D scalings, D multiplies + (D-1) adds for r^2, one
+    reciprocal square root, D scalings to the unit vector.  Harmonics: the
+    azimuthal factor (x + iy)^m by complex multiplication (6 flops per step),
+    each Gegenbauer recurrence step c_n = alpha t c_{n-1} - beta c_{n-2}
+    (4 flops; D = 4 also scales by rho^2, 1 more), one multiply per real
+    output and one add per output to accumulate it (2 flops per real output).
+    """
+    geo = D + D + (2 * D - 1) + 1 + D
+    if D == 2:
+        return geo + 6 * L + 2 * (2 * L + 1)
+    if D == 3:
+        states = (L + 1) * (L + 2) // 2
+        outputs = 2 * states - (L + 1)              # m = 0 states are real
+        rec = sum(L - m for m in range(L + 1))      # steps with n >= 1
+        return geo + 6 * L + 4 * rec + 2 * outputs
+    states = (L + 1) * (L + 2) * (L + 3) // 6
+    outputs = 2 * states - (L + 1) * (L + 2) // 2   # l1 = 0 states are real
+    rec = 2 * sum(L - k for k in range(L + 1))      # c- and g-tables
+    pair_products = states                          # g * c per state
+    return geo + 1 + 6 * L + 5 * rec + pair_products + 2 * outputs
 
 
 def make_workload(name: str):
@@ -116,7 +141,7 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int):
     ref = oracle.reported_part(z, oracle.lambda_labels(wl.D, wl.N, wl.lmax), wl.D, wl.N)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     errs = {}
-    for prec in ("plain", "mixed_bf16"):
+    for prec in ("plain",) + MIXED:
         plan = plan_factory(prec)
         for a, b in ranges:
             plan.accumulate(pos, w, a, b)
@@ -141,7 +166,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=128, help="oracle primaries per role for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--precisions", default="mixed_bf16,plain")
+    ap.add_argument("--precisions", default="mixed_fp16,mixed_bf16x6,plain,mixed_bf16")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -181,27 +206,30 @@ def main():
                          "harmonic_ms_per_launch": stage["harmonic"] / launches}
         plan.close()
 
-    head = "mixed_bf16" if "mixed_bf16" in results else list(results)[0]
-    r = results[head]
-    key = f"D{wl.D}-N{wl.N}-lmax{wl.lmax}-{wl.name}"
-    fpp = FLOPS_PER_PAIR.get((wl.D, wl.lmax))
-    achieved = fpp * r["pairs_per_step"] / (r["harmonic_ms_per_launch"] * 1e-3) if fpp else None
-    roof = {"kernel": "k_harmonic", "bound": "alu", "achieved": achieved / 1e12 if achieved else None,
-            "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": (achieved / FP32_VECTOR_PEAK) if achieved else None,
-            "traffic": load_traffic(key),
-            "flops_per_pair": fpp, "launch_ms": r["harmonic_ms_per_launch"]}
-
     cpu = None
     errs = None
     if not args.no_cpu:
         cpu, errs = cpu_baseline(wl, factory, pos, w, args.cpu_sample)
 
+    # headline: the fastest split-precision path within 1e-5 of the oracle
+    # (without the oracle check: the FP16 hi+lo path, which carries 22 bits)
+    cands = [p for p in MIXED if p in results and (errs is None or errs[p]["max_rel_err"] <= 1e-5)]
+    if errs is None:
+        cands = [p for p in ("mixed_fp16",) if p in results] or cands
+    head = max(cands, key=lambda p: results[p]["pairs_per_s"]) if cands else list(results)[0]
+    r = results[head]
+    key = f"D{wl.D}-N{wl.N}-lmax{wl.lmax}-{wl.name}"
+    fpp = flops_per_pair(wl.D, wl.lmax)
+    achieved = fpp * r["pairs_per_step"] / (r["harmonic_ms_per_launch"] * 1e-3)
+    roof = {"kernel": "k_harmonic", "bound": "alu", "achieved": achieved / 1e12,
+            "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
+            "traffic": load_traffic(key), "flops_per_pair": fpp, "launch_ms": r["harmonic_ms_per_launch"]}
+
     line = {
         "metric": "pairs/s + 4PCF wall time, mixed vs plain on one GPU at rel err <=1e-5",
         "value": r["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 harmonics + bf16x3 coupling" if head == "mixed_bf16" else "f32",
+        "dtype": DTYPE.get(head, head), "headline_path": head,
         "data": "synthetic",
         "config": {"workload": key, "n_points": n, "n_data": wl.n_data, "D": wl.D, "N": wl.N, "lmax": wl.lmax,
                    "nbins": len(wl.edges) - 1, "r_range": [float(wl.edges[0]), float(wl.edges[-1])],

@@ -90,7 +90,6 @@ struct npcf_plan_s {
     // tables
     double *d_e2 = nullptr;
     uint8_t *d_bucket = nullptr;
-    float *d_hconst = nullptr;
     CoupleTerm *d_terms = nullptr;
     CoupleGroup *d_groups = nullptr;
     int *d_lam_group_begin = nullptr, *d_lam_part = nullptr;
@@ -144,59 +143,21 @@ void compute_grid(npcf_plan_s *p)
     p->ncell = total;
 }
 
-// Replica pools of the harmonic stage's scatter.  D <= 3: pools sized from
-// the expected share of pairs in each bin at uniform density (shell volume),
-// with a margin of two standard deviations of a 64-pair batch, scaled to fit
-// the kernel's pool; D = 4: one or two replicas per bin for its atomic adds.
+// Replica pools of the harmonic stage's scatter (D = 4 only: one or two
+// replicas per bin for its atomic adds; D <= 3 stages the batch sorted by bin
+// and needs none).
 bool assign_replicas(npcf_plan_s *p)
 {
     const int D = p->D, nb = p->nb;
-    const int nrep = D == 2 ? harmonic_nrep_d2(p->L) : (D == 3 ? harmonic_nrep_d3(p->L) : harmonic_nrep_d4(p->L));
-    if (nrep <= 0) return false;
     for (int b = 0; b < kMaxBins; b++) p->rep_off[b] = p->rep_cnt[b] = 0;
-    if (D == 4) {
-        const int per = nrep / kMaxBins;
-        for (int b = 0; b < nb; b++) {
-            p->rep_off[b] = b * per;
-            p->rep_cnt[b] = per;
-        }
-        return per >= 1;
-    }
-    std::vector<double> vol(nb);
-    double tot = 0.0;
+    if (D <= 3) return true;
+    const int nrep = harmonic_nrep_d4(p->L);
+    const int per = nrep / kMaxBins;
     for (int b = 0; b < nb; b++) {
-        vol[b] = std::pow(p->edges[b + 1], D) - std::pow(p->edges[b], D);
-        tot += vol[b];
+        p->rep_off[b] = b * per;
+        p->rep_cnt[b] = per;
     }
-    std::vector<int> want(nb);
-    int sum = 0;
-    for (int b = 0; b < nb; b++) {
-        const double mean = 64.0 * vol[b] / tot;
-        int w = (int)std::ceil(mean + 2.0 * std::sqrt(mean) + 1.0);
-        w = std::max(2, std::min(64, w));
-        want[b] = w;
-        sum += w;
-    }
-    if (sum > nrep) {
-        int s2 = 0;
-        for (int b = 0; b < nb; b++) {
-            want[b] = std::max(1, (int)std::floor((double)want[b] * nrep / sum));
-            s2 += want[b];
-        }
-        while (s2 > nrep) {
-            int bi = (int)(std::max_element(want.begin(), want.end()) - want.begin());
-            if (want[bi] <= 1) return false;
-            want[bi]--;
-            s2--;
-        }
-    }
-    int off = 0;
-    for (int b = 0; b < nb; b++) {
-        p->rep_off[b] = off;
-        p->rep_cnt[b] = want[b];
-        off += want[b];
-    }
-    return true;
+    return per >= 1;
 }
 
 npcf_status alloc_cells(npcf_plan_s *p)
@@ -294,7 +255,6 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
     a.nbucket = (int)p->t.bucket_bin.size();
     a.e2 = p->d_e2;
     a.bucket_bin = p->d_bucket;
-    a.hconst = p->d_hconst;
     a.A = p->A;
     a.wrow = p->wrow;
     a.pairs = pairs;
@@ -512,7 +472,6 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->bad = m.get<int>(1);
     p->d_e2 = m.get<double>(t.e2.size());
     p->d_bucket = m.get<uint8_t>(t.bucket_bin.size());
-    p->d_hconst = m.get<float>(t.hconst.size());
     p->d_terms = m.get<CoupleTerm>(t.terms.size());
     p->d_groups = m.get<CoupleGroup>(std::max<size_t>(1, t.groups.size()));
     p->d_lam_group_begin = m.get<int>(t.lam_group_begin.size());
@@ -532,7 +491,6 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(p->d_e2, t.e2, s);
     if (e == hipSuccess) e = upload(p->d_bucket, t.bucket_bin, s);
-    if (e == hipSuccess) e = upload(p->d_hconst, t.hconst, s);
     if (e == hipSuccess) e = upload(p->d_terms, t.terms, s);
     if (e == hipSuccess) e = upload(p->d_groups, t.groups, s);
     if (e == hipSuccess) e = upload(p->d_lam_group_begin, t.lam_group_begin, s);

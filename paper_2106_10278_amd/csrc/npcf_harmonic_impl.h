@@ -37,38 +37,17 @@ constexpr int kQCap = 128;          // pair queue entries per wave
 constexpr int kSegCap = 128;        // candidate segments per row chunk
 constexpr int kMaxBucket = 1024;
 constexpr int kFlushBatches = 16;   // FP32 replica adds between FP64 folds
-constexpr int kTableBytes = (kMaxBins + 1) * 8 + kMaxBucket + 2 * kMaxBins * 4;
-constexpr int kRepBudget = 16384;   // bytes of replica pool per wave
+constexpr int kTableBytes = (kMaxBins + 1) * 8 + (kMaxBins + 1) * 4 + kMaxBucket + 2 * kMaxBins * 4;
+// FP32 binning is exact unless r^2 lies within this relative distance of an edge
+// (bound on the FP32 error of r^2 and of the rounded edge: about 12 ulp); such
+// lanes redo the FP64 binning
+constexpr float kEdgeTol = 2e-6f;
 
 #define NPCF_WAVE_SYNC()                                       \
     do {                                                       \
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); \
         __builtin_amdgcn_wave_barrier();                       \
     } while (0)
-
-template <int D, int L>
-struct Cfg {
-    static constexpr int NST = stored_states(D, L);
-    static constexpr int SLOTS = 2 * NST;
-    static constexpr bool RANK = D <= 3;
-    static constexpr int NREP_RAW = kRepBudget / (SLOTS * 4);
-    static constexpr int NREP = RANK ? (NREP_RAW > 128 ? 128 : NREP_RAW)
-                                     : ((24576 / (SLOTS * 4)) >= 2 * kMaxBins ? 2 * kMaxBins : kMaxBins);
-    static constexpr bool KEEP = SLOTS <= 64;                  // harmonic values fit in registers
-    static constexpr int NK = (kMaxBins * SLOTS + 63) / 64;   // FP64 accumulators per lane
-    static constexpr int QWORDS = (D == 4) ? 5 : 4;            // queue words per pair
-    static constexpr int WAVE_BYTES = kQCap * QWORDS * 4 + kSegCap * 8 + SLOTS * NREP * 4;
-};
-
-__device__ __forceinline__ unsigned lane_id()
-{
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-__device__ __forceinline__ int rank_in_mask(unsigned long long m)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
 
 // Slots the harmonics write: the imaginary slot of a state with l1 = 0 stays zero.
 template <int D, int L>
@@ -90,6 +69,54 @@ __host__ __device__ constexpr bool emitted(int slot)
     return r - l2 * (l2 + 1) / 2 != 0;
 }
 
+// index of an emitted slot among the emitted slots
+template <int D, int L>
+__host__ __device__ constexpr int compact_of(int slot)
+{
+    int c = 0;
+    for (int t = 0; t < slot; t++) c += emitted<D, L>(t) ? 1 : 0;
+    return c;
+}
+
+// compact index of every slot (-1: not emitted), as a table the compiler folds
+template <int D, int L>
+struct CompactTable {
+    static constexpr int N = 2 * stored_states(D, L);
+    int v[N];
+    constexpr CompactTable() : v{}
+    {
+        int c = 0;
+        for (int t = 0; t < N; t++) v[t] = emitted<D, L>(t) ? c++ : -1;
+    }
+};
+
+template <int D, int L>
+struct Cfg {
+    static constexpr int NST = stored_states(D, L);
+    static constexpr int SLOTS = 2 * NST;
+    static constexpr int NE = compact_of<D, L>(SLOTS);             // emitted slots
+    static constexpr bool STAGE = D <= 3;                          // sorted staging, no replicas
+    static constexpr int SSTR = 65;                                // staging row stride (floats)
+    static constexpr int CJ = (NE + 63) / 64;                      // emitted slots per lane
+    static constexpr int NREP = STAGE ? 0 : ((24576 / (SLOTS * 4)) >= 2 * kMaxBins ? 2 * kMaxBins : kMaxBins);
+    static constexpr int NK = STAGE ? CJ * kMaxBins : (kMaxBins * SLOTS + 63) / 64;  // FP64 accumulators per lane
+    static constexpr int QWORDS = (D == 4) ? 5 : 4;                // queue words per pair
+    static constexpr int WAVE_BYTES = kQCap * QWORDS * 4 + kSegCap * 8 + (STAGE ? NE * SSTR * 4 : SLOTS * NREP * 4);
+};
+
+__device__ __forceinline__ unsigned lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// wave-wide ballot of a boolean straight into a 64-bit lane mask
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int rank_in_mask(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 template <int D>
 __device__ __forceinline__ uint32_t rec_coord(const uint4 &r, int k)
 {
@@ -108,10 +135,14 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     const int wave = threadIdx.x >> 6;
 
     double *e2 = reinterpret_cast<double *>(smem);
-    uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 8);
-    int *roff = reinterpret_cast<int *>(smem + (kMaxBins + 1) * 8 + kMaxBucket);
+    float *e2f = reinterpret_cast<float *>(smem + (kMaxBins + 1) * 8);
+    uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 12);
+    int *roff = reinterpret_cast<int *>(smem + (kMaxBins + 1) * 12 + kMaxBucket);
     int *rcnt = roff + kMaxBins;
-    for (int t = threadIdx.x; t <= nb; t += blockDim.x) e2[t] = a.e2[t];
+    for (int t = threadIdx.x; t <= nb; t += blockDim.x) {
+        e2[t] = a.e2[t];
+        e2f[t] = (float)a.e2[t];
+    }
     for (int t = threadIdx.x; t < a.nbucket; t += blockDim.x) btab[t] = a.bucket_bin[t];
     for (int t = threadIdx.x; t < kMaxBins; t += blockDim.x) {
         roff[t] = a.rep_off[t];
@@ -122,12 +153,32 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     int4 *q4 = reinterpret_cast<int4 *>(wb);                                     // [kQCap]
     float *qwx = reinterpret_cast<float *>(wb + kQCap * 16);                     // [kQCap] (D = 4 weight)
     uint2 *segs = reinterpret_cast<uint2 *>(wb + kQCap * C::QWORDS * 4);         // [kSegCap]
-    float *rep = reinterpret_cast<float *>(wb + kQCap * C::QWORDS * 4 + kSegCap * 8);  // [SLOTS][NREP]
-    for (int t = lane; t < SLOTS * NREP; t += 64) rep[t] = 0.f;
+    // D <= 3: staging [NE][SSTR] (column 64 takes the lanes without a pair);
+    // D = 4: replica pools [SLOTS][NREP]
+    float *stage = reinterpret_cast<float *>(wb + kQCap * C::QWORDS * 4 + kSegCap * 8);
+    float *rep = stage;
+    if constexpr (!C::STAGE)
+        for (int t = lane; t < SLOTS * NREP; t += 64) rep[t] = 0.f;
     __syncthreads();
 
+    // D <= 3: this lane reduces emitted slots c = lane + 64 j; fslot[j] is the
+    // slot's place in the row of a (-1: none)
+    int fslot[C::CJ];
+#pragma unroll
+    for (int j = 0; j < C::CJ; j++) {
+        const int c = lane + 64 * j;
+        fslot[j] = -1;
+        for (int t = 0, k = 0; t < SLOTS; t++) {
+            if (!emitted<D, L>(t)) continue;
+            if (k++ == c) {
+                fslot[j] = t;
+                break;
+            }
+        }
+    }
+
     const int nacc = nb * SLOTS;
-    double acc[C::NK];
+    double acc[C::NK];  // D <= 3: acc[j kMaxBins + b] of slot lane + 64 j; D = 4: entry lane + 64 k of [bin][slot]
 #pragma unroll
     for (int k = 0; k < C::NK; k++) acc[k] = 0.0;
 
@@ -154,6 +205,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
         // ---- fold the FP32 replicas into the FP64 accumulators -------------
         auto flush = [&]() {
             NPCF_WAVE_SYNC();
+            if constexpr (C::STAGE) return;  // sums go straight to FP64 per batch
 #pragma unroll
             for (int k = 0; k < C::NK; k++) {
                 const int t = lane + 64 * k;
@@ -191,77 +243,100 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                     wk = __int_as_float(D == 3 ? e.w : e.z);
                 }
             }
-            // FP64 squared distance, summed axis by axis without contraction
-            double r2 = 0.0;
+            // FP32 squared distance and bin; lanes within kEdgeTol of an edge
+            // (rare) redo both in FP64, summed axis by axis without contraction
             float f[D];
             float fr2 = 0.f;
 #pragma unroll
             for (int k = 0; k < D; k++) {
-                const double v = __dmul_rn((double)dq[k], a.scale64[k]);
-                r2 = __dadd_rn(r2, __dmul_rn(v, v));
                 f[k] = (float)dq[k] * a.scale[k];
                 fr2 += f[k] * f[k];
             }
-            const bool valid = live && r2 >= e2lo && r2 < e2hi;
-            int bin = 0;
-            if (valid) {
-                int bk = (int)(((float)r2 - a.bucket_lo) * a.bucket_inv);
+            int bin;
+            {
+                int bk = (int)((fr2 - a.bucket_lo) * a.bucket_inv);
                 bk = bk < 0 ? 0 : (bk >= a.nbucket ? a.nbucket - 1 : bk);
                 bin = btab[bk];
-                while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
-                while (bin > 0 && r2 < e2[bin]) bin--;
+                while (bin + 1 < nb && fr2 >= e2f[bin + 1]) bin++;
+                while (bin > 0 && fr2 < e2f[bin]) bin--;
             }
-            const unsigned long long vm = __ballot(valid);
+            const float tol = kEdgeTol * fr2;
+            const bool near = live && (fr2 - e2f[bin] < tol || e2f[bin + 1] - fr2 < tol);
+            bool valid = live && fr2 >= e2f[0] && fr2 < e2f[nb];
+            if (ballot(near)) {
+                if (near) {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; k++) {
+                        const double v = __dmul_rn((double)dq[k], a.scale64[k]);
+                        r2 = __dadd_rn(r2, __dmul_rn(v, v));
+                    }
+                    valid = r2 >= e2lo && r2 < e2hi;
+                    bin = 0;
+                    while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
+                }
+            }
+            if (!valid) bin = 0;
+            const unsigned long long vm = ballot(valid);
             my_pairs += (unsigned long long)__popcll(vm);
-            const float rinv = valid ? rsqrtf(fr2) : 0.f;
+            const float rinv = valid ? __builtin_amdgcn_rsqf(fr2) : 0.f;  // fr2 >= e2[0] > 0: no denormal path
+            if (!valid) wk = 0.f;  // invalid lanes evaluate harmonics of weight zero
             float u[D];
 #pragma unroll
             for (int k = 0; k < D; k++) u[k] = f[k] * rinv;
 
-            if constexpr (C::RANK) {
-                // rank among the valid lanes of the same bin (bins < 16: 4 bit planes)
-                unsigned long long m = vm & ((1ull << lane) - 1ull);
+            if constexpr (C::STAGE) {
+                // position of this pair in the batch sorted by bin: lanes with a
+                // smaller bin, plus lanes of the same bin below this one (bins
+                // < 16: compare four bit planes, most significant first)
+                unsigned long long Bk[4];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const bool bit = (bin >> k) & 1;
-                    const unsigned long long B = __ballot(valid && bit);
-                    m &= bit ? B : ~B;
+                for (int k = 0; k < 4; k++) Bk[k] = ballot(valid && ((bin >> k) & 1));
+                unsigned long long same = vm, lt = 0ull;
+#pragma unroll
+                for (int k = 3; k >= 0; k--) {
+                    const unsigned long long mk = 0ull - (unsigned long long)((bin >> k) & 1);
+                    lt |= same & ~Bk[k] & mk;
+                    same &= Bk[k] ^ ~mk;
                 }
-                const int rank = __popcll(m);
-                const int R = rcnt[bin];
-                const int ro = roff[bin];
-                if constexpr (C::KEEP) {
-                    // harmonics once, kept in registers; overflow rounds only redo the scatter
-                    float vals[SLOTS];
+                const int pos = valid ? __popcll(lt) + rank_in_mask(same) : 64;
+                constexpr CompactTable<D, L> CT{};
+                harmonics<D, L>(u, wk, [&](int slot, float v) {
+                    if (CT.v[slot] >= 0) stage[CT.v[slot] * C::SSTR + pos] = v;
+                });
+                NPCF_WAVE_SYNC();
+                // lanes over emitted slots: each bin's run of sorted pairs, summed in
+                // FP32 (two interleaved partial sums) and added to the FP64 accumulator
 #pragma unroll
-                    for (int s = 0; s < SLOTS; s++) vals[s] = 0.f;
-                    if (valid) harmonics<D, L>(u, wk, a.hconst, [&](int slot, float v) { vals[slot] = v; });
-                    for (int rd = 0;; rd++) {
-                        const bool act = valid && rank >= rd * R && rank < (rd + 1) * R;
-                        if (__ballot(act) == 0ull) break;
-                        if (act) {
-                            float *base = rep + ro + (rank - rd * R);
+                for (int j = 0; j < C::CJ; j++) {
+                    const int c = lane + 64 * j;
+                    const float *row = stage + (c < C::NE ? c : C::NE - 1) * C::SSTR;
+                    int j0 = 0;
 #pragma unroll
-                            for (int s = 0; s < SLOTS; s++)
-                                if (emitted<D, L>(s)) base[s * NREP] += vals[s];
+                    for (int b = 0; b < kMaxBins; b++) {
+                        if (b < nb) {
+                            unsigned long long mb = vm;
+#pragma unroll
+                            for (int k = 0; k < 4; k++) mb &= ((b >> k) & 1) ? Bk[k] : ~Bk[k];
+                            const int cnt = __popcll(mb);
+                            if (cnt) {
+                                float s0 = 0.f, s1 = 0.f;
+                                int t = j0;
+                                for (; t + 1 < j0 + cnt; t += 2) {
+                                    s0 += row[t];
+                                    s1 += row[t + 1];
+                                }
+                                if (t < j0 + cnt) s0 += row[t];
+                                acc[j * kMaxBins + b] += (double)(s0 + s1);
+                                j0 += cnt;
+                            }
                         }
-                        NPCF_WAVE_SYNC();
-                    }
-                } else {
-                    for (int rd = 0;; rd++) {
-                        const bool act = valid && rank >= rd * R && rank < (rd + 1) * R;
-                        if (__ballot(act) == 0ull) break;
-                        if (act) {
-                            float *base = rep + ro + (rank - rd * R);
-                            harmonics<D, L>(u, wk, a.hconst, [&](int slot, float v) { base[slot * NREP] += v; });
-                        }
-                        NPCF_WAVE_SYNC();
                     }
                 }
             } else {
                 float *base = rep + roff[bin] + (lane & (rcnt[bin] - 1));
                 if (valid) {
-                    harmonics<D, L>(u, wk, a.hconst, [&](int slot, float v) {
+                    harmonics<D, L>(u, wk, [&](int slot, float v) {
                         __hip_atomic_fetch_add(base + slot * NREP, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     });
                 }
@@ -365,7 +440,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                     }
                 }
             }
-            const unsigned long long m0 = __ballot(has0), m1 = __ballot(has1);
+            const unsigned long long m0 = ballot(has0), m1 = ballot(has1);
             const int n0 = __popcll(m0);
             if (has0) segs[rank_in_mask(m0)] = make_uint2(sa0, sb0);
             if (has1) segs[n0 + rank_in_mask(m1)] = make_uint2(sa1, sb1);
@@ -412,7 +487,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                         }
                         inr = fits && r2f >= e2lo_f && r2f < e2hi_f;
                     }
-                    const unsigned long long m = __ballot(inr);
+                    const unsigned long long m = ballot(inr);
                     if (inr) {
                         const int slot = qn + rank_in_mask(m);
                         int4 e;
@@ -440,7 +515,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                             if (D == 4) qwx[lane] = qwx[64 + lane];
                         }
                         qn = rest;
-                        if (++nbatch % kFlushBatches == 0) flush();
+                        if (!C::STAGE && ++nbatch % kFlushBatches == 0) flush();
                         NPCF_WAVE_SYNC();
                     }
                     cur = nxt;
@@ -452,11 +527,26 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
         flush();
         // the primary's row of a (FP32) and its weight; clear the FP64 accumulators
         float *Arow = a.A + (size_t)row * nacc;
+        if constexpr (C::STAGE) {
+            // emitted slots from the accumulators, then zeros in the others
 #pragma unroll
-        for (int k = 0; k < C::NK; k++) {
-            const int t = lane + 64 * k;
-            if (t < nacc) Arow[t] = (float)acc[k];
-            acc[k] = 0.0;
+            for (int j = 0; j < C::CJ; j++) {
+#pragma unroll
+                for (int b = 0; b < kMaxBins; b++) {
+                    if (b < nb && fslot[j] >= 0) Arow[b * SLOTS + fslot[j]] = (float)acc[j * kMaxBins + b];
+                    acc[j * kMaxBins + b] = 0.0;
+                }
+            }
+            constexpr CompactTable<D, L> CT{};
+            for (int t = lane; t < nacc; t += 64)
+                if (CT.v[t % SLOTS] < 0) Arow[t] = 0.f;
+        } else {
+#pragma unroll
+            for (int k = 0; k < C::NK; k++) {
+                const int t = lane + 64 * k;
+                if (t < nacc) Arow[t] = (float)acc[k];
+                acc[k] = 0.0;
+            }
         }
         if (lane == 0) a.wrow[row] = wi;
     }

@@ -9,15 +9,83 @@
 namespace npcf {
 namespace harm {
 
+// ---- recurrence constants, evaluated at compile time ---------------------------------
+// Normalised Gegenbauer values c_n = K_n C^{(lambda)}_n obey c_0 = K_0 and
+//   c_n = alpha_n t c_{n-1} - beta_n s c_{n-2},
+//   alpha_n = (K_n / K_{n-1}) 2 (n + lambda - 1) / n,  beta_n = (K_n / K_{n-2}) (n + 2 lambda - 2) / n,
+// with K_n^2 / K_{n-1}^2 = n (n + lambda) / ((n - 1 + 2 lambda)(n - 1 + lambda)) and
+// K_0^2 = lambda Gamma(lambda) / (sqrt(pi) Gamma(lambda + 1/2)) (the inverse norm of
+// C^{(lambda)}_0 on [-1, 1] with weight (1 - t^2)^{lambda - 1/2}).
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr double ct_sqrt(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    double r = x > 1.0 ? x : 1.0;  // Newton from above: monotone decrease to sqrt(x)
+    for (int i = 0; i < 200; i++) {
+        const double n = 0.5 * (r + x / r);
+        if (!(n < r)) break;
+        r = n;
+    }
+    return r;
+}
+
+// Gamma(lambda) / Gamma(lambda + 1/2) for lambda in {1/2, 1, 3/2, 2, ...}
+constexpr double gamma_ratio(double lambda)
+{
+    double lam = (lambda - (double)(int)lambda) != 0.0 ? 0.5 : 1.0;
+    double g = lam == 0.5 ? ct_sqrt(kPi) : 2.0 / ct_sqrt(kPi);
+    while (lam < lambda) {
+        g *= lam / (lam + 0.5);
+        lam += 1.0;
+    }
+    return g;
+}
+
+// c_0 followed by (alpha_n, beta_n) for n = 1..nmax, each times pref
+constexpr int push_gegenbauer(float *out, int at, double lambda, int nmax, double pref)
+{
+    double k0 = pref * ct_sqrt(lambda * gamma_ratio(lambda) / ct_sqrt(kPi));
+    out[at++] = (float)k0;
+    double r1 = 1.0, r2 = 1.0;  // K_{n-1}/K_{n-2}, K_n/K_{n-1}
+    for (int n = 1; n <= nmax; n++) {
+        r1 = r2;
+        r2 = ct_sqrt(n * (n + lambda) / ((n - 1 + 2.0 * lambda) * (n - 1 + lambda)));
+        out[at++] = (float)(r2 * 2.0 * (n + lambda - 1.0) / n);
+        out[at++] = (float)(n >= 2 ? r2 * r1 * (n + 2.0 * lambda - 2.0) / n : 0.0);
+    }
+    return at;
+}
+
+template <int D, int L>
+struct HarmConst {
+    static constexpr int N = D == 2 ? 1 : (D == 3 ? (L + 1) * (L + 1) : 2 * (L + 1) * (L + 1));
+    float v[N];
+    constexpr HarmConst() : v{}
+    {
+        const double inv_sqrt_2pi = 1.0 / ct_sqrt(2.0 * kPi);
+        int at = 0;
+        if (D == 2) {
+            v[0] = (float)inv_sqrt_2pi;
+        } else if (D == 3) {
+            for (int m = 0; m <= L; m++) at = push_gegenbauer(v, at, m + 0.5, L - m, inv_sqrt_2pi);
+        } else {
+            for (int l2 = 0; l2 <= L; l2++) at = push_gegenbauer(v, at, l2 + 1.0, L - l2, 1.0);
+            for (int l1 = 0; l1 <= L; l1++) at = push_gegenbauer(v, at, l1 + 0.5, L - l1, inv_sqrt_2pi);
+        }
+    }
+};
+
 // The emitted value for stored state s is w * conj(Y_s(u)) split into real
 // (slot 2s) and imaginary (slot 2s+1) parts; m = 0 (l1 = 0) states have no
 // imaginary part and emit only the real slot.
 
 // D = 2: Y_l = e^{i l theta1} / sqrt(2 pi); conj -> (u1 - i u2)^l / sqrt(2 pi).
 template <int L, class F>
-__device__ __forceinline__ void harm_d2(const float *u, float w, const float *__restrict__ hc, F &&emit)
+__device__ __forceinline__ void harm_d2(const float *u, float w, F &&emit)
 {
-    float pr = w * hc[0], pi = 0.f;
+    constexpr HarmConst<2, L> H{};
+    float pr = w * H.v[0], pi = 0.f;
     emit(0, pr);
 #pragma unroll
     for (int l = 1; l <= L; l++) {
@@ -34,8 +102,10 @@ __device__ __forceinline__ void harm_d2(const float *u, float w, const float *__
 // Gegenbauer values obey c_n = alpha_n u3 c_{n-1} - beta_n c_{n-2}; hc holds,
 // for m = 0..L, c_0 followed by (alpha_n, beta_n) for n = 1..L-m.
 template <int L, class F>
-__device__ __forceinline__ void harm_d3(const float *u, float w, const float *__restrict__ hc, F &&emit)
+__device__ __forceinline__ void harm_d3(const float *u, float w, F &&emit)
 {
+    constexpr HarmConst<3, L> H{};
+    const float *hc = H.v;
     float pr = w, pi = 0.f;
     int ci = 0;
 #pragma unroll
@@ -72,8 +142,10 @@ __device__ __forceinline__ void harm_d3(const float *u, float w, const float *__
 // both by three-term recurrences; hc holds the c tables (for l2 = 0..L: c_0,
 // (alpha, beta) for n = 1..L-l2), then the g tables (for l1 = 0..L).
 template <int L, class F>
-__device__ __forceinline__ void harm_d4(const float *u, float w, const float *__restrict__ hc, F &&emit)
+__device__ __forceinline__ void harm_d4(const float *u, float w, F &&emit)
 {
+    constexpr HarmConst<4, L> H{};
+    const float *hc = H.v;
     constexpr int NT = (L + 1) * (L + 2) / 2;
     float ct[NT];  // ct[tri(l2) + (l3 - l2)]
     float gt[NT];  // gt[tri(l1) + (l2 - l1)]
@@ -131,11 +203,11 @@ __device__ __forceinline__ void harm_d4(const float *u, float w, const float *__
 }
 
 template <int D, int L, class F>
-__device__ __forceinline__ void harmonics(const float *u, float w, const float *__restrict__ hc, F &&emit)
+__device__ __forceinline__ void harmonics(const float *u, float w, F &&emit)
 {
-    if constexpr (D == 2) harm_d2<L>(u, w, hc, emit);
-    else if constexpr (D == 3) harm_d3<L>(u, w, hc, emit);
-    else harm_d4<L>(u, w, hc, emit);
+    if constexpr (D == 2) harm_d2<L>(u, w, emit);
+    else if constexpr (D == 3) harm_d3<L>(u, w, emit);
+    else harm_d4<L>(u, w, emit);
 }
 
 }  // namespace harm

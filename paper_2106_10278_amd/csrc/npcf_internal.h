@@ -61,7 +61,6 @@ struct HarmArgs {
     int nbucket;
     const double *e2;         // [nb + 1] squared edges (physical, FP64)
     const uint8_t *bucket_bin;  // [nbucket] bin at the low end of each r^2 bucket
-    const float *hconst;      // recurrence constants of the harmonics
     int rep_off[kMaxBins];    // replica pool of each bin: first replica
     int rep_cnt[kMaxBins];    //   and its size
     float *A;                 // out: [nrows][nb][2 * nstate]
@@ -167,7 +166,6 @@ struct Tables {
     std::vector<int> bt_row, bt_col;
     std::vector<double> bt_scale;
     std::vector<float> sfac;           // [nstate] N = 3 state factors
-    std::vector<float> hconst;         // harmonic recurrence constants
     std::vector<double> e2;            // [nb + 1]
     std::vector<uint8_t> bucket_bin;
     float bucket_lo = 0.f, bucket_inv = 0.f;

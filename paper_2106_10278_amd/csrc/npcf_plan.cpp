@@ -20,30 +20,6 @@ long double lfac(int n) { return std::lgamma((long double)n + 1.0L); }
 // Normalisation of Gegenbauer polynomials: N(lambda, n)^2 * int_{-1}^{1}
 // (1-x^2)^{lambda-1/2} [C^{(lambda)}_n(x)]^2 dx = 1, with the integral equal to
 // pi 2^{1-2 lambda} Gamma(n+2 lambda) / (n! (n+lambda) Gamma(lambda)^2).
-double gegenbauer_norm(double lambda, int n)
-{
-    long double lg = std::log((long double)M_PI) + (1.0L - 2.0L * lambda) * std::log(2.0L) +
-                     std::lgamma((long double)n + 2.0L * lambda) - lfac(n) - std::log((long double)n + lambda) -
-                     2.0L * std::lgamma((long double)lambda);
-    return (double)std::exp(-0.5L * lg);
-}
-
-// Recurrence constants of c_n = K_n C^{(lambda)}_n:  c_0 = K_0,
-// c_n = alpha_n t c_{n-1} - beta_n s c_{n-2}, with
-// alpha_n = (K_n / K_{n-1}) 2 (n + lambda - 1) / n,  beta_n = (K_n / K_{n-2}) (n + 2 lambda - 2) / n.
-void push_gegenbauer(std::vector<float> &h, double lambda, int nmax, double pref)
-{
-    std::vector<double> K(nmax + 1);
-    for (int n = 0; n <= nmax; n++) K[n] = pref * gegenbauer_norm(lambda, n);
-    h.push_back((float)K[0]);
-    for (int n = 1; n <= nmax; n++) {
-        double al = K[n] / K[n - 1] * 2.0 * (n + lambda - 1.0) / n;
-        double be = (n >= 2) ? K[n] / K[n - 2] * (n + 2.0 * lambda - 2.0) / n : 0.0;
-        h.push_back((float)al);
-        h.push_back((float)be);
-    }
-}
-
 int state_index(int D, int l1, int l2, int l3)
 {
     if (D == 2) return l1;
@@ -216,18 +192,6 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
         int b = 0;
         while (b + 1 < nb && r2 >= t.e2[b + 1]) b++;
         t.bucket_bin[k] = (uint8_t)b;
-    }
-
-    // ---- harmonic recurrence constants ---------------------------------------------
-    t.hconst.clear();
-    const double inv_sqrt_2pi = 1.0 / std::sqrt(2.0 * M_PI);
-    if (D == 2) {
-        t.hconst.push_back((float)inv_sqrt_2pi);
-    } else if (D == 3) {
-        for (int m = 0; m <= L; m++) push_gegenbauer(t.hconst, m + 0.5, L - m, inv_sqrt_2pi);
-    } else {
-        for (int l2 = 0; l2 <= L; l2++) push_gegenbauer(t.hconst, l2 + 1.0, L - l2, 1.0);
-        for (int l1 = 0; l1 <= L; l1++) push_gegenbauer(t.hconst, l1 + 0.5, L - l1, inv_sqrt_2pi);
     }
 
     // ---- coupling groups and terms ----------------------------------------------------

@@ -18,6 +18,38 @@ def per_multipole_error(got, ref):
     return float(errs.max()) if errs.size else 0.0, errs
 
 
+def condition_scale(wl, btuple_mode=0, prims=None):
+    """Sum of the magnitudes of every term of the estimator,
+    (1/V) sum_i |w_i| sum_terms |C| prod_k |a_i^{b_k}[s_k]|, per (Lambda, b-tuple),
+    from the oracle's a_lm and coupling coefficients (eq. NPCF-estimator-discrete
+    with every term replaced by its absolute value).  A sum evaluated with unit
+    roundoff u has forward error bounded by about u times this scale, so errors
+    are judged against it where the multipole itself cancels."""
+    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims)
+    lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax)
+    nb = len(wl.edges) - 1
+    bts = oracle.btuple_labels(nb, wl.N, btuple_mode)
+    nlam = len(oracle.lambda_labels(wl.D, wl.N, wl.lmax))
+    w = np.abs(wl.w if prims is None else wl.w[prims])
+    A = np.abs(a)
+    out = np.zeros((nlam, len(bts)))
+    for t in range(len(lam)):
+        if wl.N == 3:
+            m = np.einsum("i,ij,ik->jk", w, A[:, :, s[t, 0]], A[:, :, s[t, 1]])
+            out[lam[t]] += abs(c[t]) * m[bts[:, 0], bts[:, 1]]
+        else:
+            m = np.einsum("i,ij,ik,il->jkl", w, A[:, :, s[t, 0]], A[:, :, s[t, 1]], A[:, :, s[t, 2]])
+            out[lam[t]] += abs(c[t]) * m[bts[:, 0], bts[:, 1], bts[:, 2]]
+    return out / float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
+
+
+def conditioned_error(got, ref, scale):
+    """max over multipoles of max_b |got - ref| / max_b scale."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    errs = np.array([np.max(np.abs(got[i] - ref[i])) / max(np.max(scale[i]), 1e-300) for i in range(ref.shape[0])])
+    return float(errs.max()) if errs.size else 0.0, errs
+
+
 def oracle_reported(wl, prims=None, btuple_mode=0):
     z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims,
                            btuple_mode=btuple_mode)
