@@ -69,7 +69,6 @@ struct npcf_plan_s {
     // catalogue workspace
     uint32_t *qtmp[kMaxD] = {};
     uint4 *rec = nullptr;
-    int rep_off[kMaxBins] = {}, rep_cnt[kMaxBins] = {};
     uint32_t *cell = nullptr;
     int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *prim = nullptr;
     float *ws = nullptr;
@@ -141,23 +140,6 @@ void compute_grid(npcf_plan_s *p)
         s--;
     }
     p->ncell = total;
-}
-
-// Replica pools of the harmonic stage's scatter (D = 4 only: one or two
-// replicas per bin for its atomic adds; D <= 3 stages the batch sorted by bin
-// and needs none).
-bool assign_replicas(npcf_plan_s *p)
-{
-    const int D = p->D, nb = p->nb;
-    for (int b = 0; b < kMaxBins; b++) p->rep_off[b] = p->rep_cnt[b] = 0;
-    if (D <= 3) return true;
-    const int nrep = harmonic_nrep_d4(p->L);
-    const int per = nrep / kMaxBins;
-    for (int b = 0; b < nb; b++) {
-        p->rep_off[b] = b * per;
-        p->rep_cnt[b] = per;
-    }
-    return per >= 1;
 }
 
 npcf_status alloc_cells(npcf_plan_s *p)
@@ -238,10 +220,6 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
         a.scale64[k] = sc;
         a.scale[k] = (float)sc;
         a.rmax_lat[k] = p->edges[p->nb] / sc;
-    }
-    for (int b = 0; b < kMaxBins; b++) {
-        a.rep_off[b] = p->rep_off[b];
-        a.rep_cnt[b] = p->rep_cnt[b];
     }
     a.w = p->ws;
     a.cell_start = p->cell_start;
@@ -437,9 +415,13 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         return NPCF_E_DEVICE;
     }
     compute_grid(p);
-    if (!assign_replicas(p)) {
-        delete p;
-        return NPCF_E_UNSUPPORTED;
+    {
+        const int L = p->L;
+        const int lds = p->D == 2 ? harmonic_lds_bytes_d2(L) : (p->D == 3 ? harmonic_lds_bytes_d3(L) : harmonic_lds_bytes_d4(L));
+        if (lds <= 0 || lds > 160 * 1024) {
+            delete p;
+            return NPCF_E_UNSUPPORTED;
+        }
     }
     DevAlloc &m = p->mem;
     for (int k = 0; k < p->D; k++) p->qtmp[k] = m.get<uint32_t>(max_points);

@@ -51,28 +51,4 @@ int harmonic_lds_bytes_d2(int L)
     }
 }
 
-int harmonic_nrep_d2(int L)
-{
-    switch (L) {
-    case 0: return harm::nrep<2, 0>();
-    case 1: return harm::nrep<2, 1>();
-    case 2: return harm::nrep<2, 2>();
-    case 3: return harm::nrep<2, 3>();
-    case 4: return harm::nrep<2, 4>();
-    case 5: return harm::nrep<2, 5>();
-    case 6: return harm::nrep<2, 6>();
-    case 7: return harm::nrep<2, 7>();
-    case 8: return harm::nrep<2, 8>();
-    case 9: return harm::nrep<2, 9>();
-    case 10: return harm::nrep<2, 10>();
-    case 11: return harm::nrep<2, 11>();
-    case 12: return harm::nrep<2, 12>();
-    case 13: return harm::nrep<2, 13>();
-    case 14: return harm::nrep<2, 14>();
-    case 15: return harm::nrep<2, 15>();
-    case 16: return harm::nrep<2, 16>();
-    default: return -1;
-    }
-}
-
 }  // namespace npcf

@@ -39,22 +39,4 @@ int harmonic_lds_bytes_d3(int L)
     }
 }
 
-int harmonic_nrep_d3(int L)
-{
-    switch (L) {
-    case 0: return harm::nrep<3, 0>();
-    case 1: return harm::nrep<3, 1>();
-    case 2: return harm::nrep<3, 2>();
-    case 3: return harm::nrep<3, 3>();
-    case 4: return harm::nrep<3, 4>();
-    case 5: return harm::nrep<3, 5>();
-    case 6: return harm::nrep<3, 6>();
-    case 7: return harm::nrep<3, 7>();
-    case 8: return harm::nrep<3, 8>();
-    case 9: return harm::nrep<3, 9>();
-    case 10: return harm::nrep<3, 10>();
-    default: return -1;
-    }
-}
-
 }  // namespace npcf

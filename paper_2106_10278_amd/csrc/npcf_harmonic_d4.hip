@@ -31,18 +31,4 @@ int harmonic_lds_bytes_d4(int L)
     }
 }
 
-int harmonic_nrep_d4(int L)
-{
-    switch (L) {
-    case 0: return harm::nrep<4, 0>();
-    case 1: return harm::nrep<4, 1>();
-    case 2: return harm::nrep<4, 2>();
-    case 3: return harm::nrep<4, 3>();
-    case 4: return harm::nrep<4, 4>();
-    case 5: return harm::nrep<4, 5>();
-    case 6: return harm::nrep<4, 6>();
-    default: return -1;
-    }
-}
-
 }  // namespace npcf

@@ -14,19 +14,19 @@
 //    candidate, next batch prefetched);
 //  - phase A (lanes over candidates): exact int32 periodic separation,
 //    conservative FP32 range test, ballot compaction into an LDS pair queue;
-//  - phase B (lanes over 64 queued pairs): FP64 binning that reproduces the
-//    FP64 definition on lattice inputs, FP32 unit vector, harmonics by
-//    Gegenbauer recurrences in registers, then the scatter into per-bin
-//    accumulators:
-//      D <= 3: without atomics.  Each lane takes its rank among the lanes of
-//              the same bin (four bit-plane ballots) and owns replica
-//              roff[bin] + rank of that bin's replica pool for this batch, so a
-//              plain read-add-write never collides; pools are sized from the
-//              shell volumes, and lanes past a pool's size go in another round;
-//      D = 4:  (168 slots) LDS float atomics into two lane-interleaved replicas;
-//  - every kFlushBatches batches the FP32 replicas are folded into FP64
-//    accumulators held in registers (each lane owns a strided set of
-//    (bin, slot) entries), which are written out as the primary's row of a.
+//  - phase B (lanes over 64 queued pairs): bin from FP32 r^2 (FP64, matching
+//    the definition on lattice inputs, for the rare pair near an edge), FP32
+//    unit vector, harmonics by Gegenbauer recurrences in registers;
+//  - scatter without atomics or collisions: each lane takes its position in
+//    the batch sorted by bin (bit-plane ballots) and writes every harmonic it
+//    emits into column `position` of an LDS staging array whose rows follow
+//    the emission order (row stride 65 floats: the writes of one row and the
+//    transposed reads below both touch 64 distinct banks);
+//  - reduction: every E emitted rows (E <= 64) the lanes switch to rows, sum
+//    each bin's contiguous run of columns in FP32 and add it to FP64
+//    accumulators held in registers; the primary's row of a is written once.
+//    The cost per batch is fixed whatever the mix of bins (clustered data put
+//    bursts of one bin into a batch), and the summation order is fixed.
 #pragma once
 #include "npcf_harmonics.h"
 
@@ -36,8 +36,7 @@ namespace harm {
 constexpr int kQCap = 128;          // pair queue entries per wave
 constexpr int kSegCap = 128;        // candidate segments per row chunk
 constexpr int kMaxBucket = 1024;
-constexpr int kFlushBatches = 16;   // FP32 replica adds between FP64 folds
-constexpr int kTableBytes = (kMaxBins + 1) * 8 + (kMaxBins + 1) * 4 + kMaxBucket + 2 * kMaxBins * 4;
+constexpr int kTableBytes = (kMaxBins + 1) * 8 + (kMaxBins + 1) * 4 + kMaxBucket;
 // FP32 binning is exact unless r^2 lies within this relative distance of an edge
 // (bound on the FP32 error of r^2 and of the rounded edge: about 12 ulp); such
 // lanes redo the FP64 binning
@@ -49,44 +48,40 @@ constexpr float kEdgeTol = 2e-6f;
         __builtin_amdgcn_wave_barrier();                       \
     } while (0)
 
-// Slots the harmonics write: the imaginary slot of a state with l1 = 0 stays zero.
+// Emission order of the harmonics functions (npcf_harmonics.h): the slot of
+// every emitted value, in the order emit() is called.  Only emitted slots
+// appear (the imaginary slot of a state with l1 = 0 is never written).
 template <int D, int L>
-__host__ __device__ constexpr bool emitted(int slot)
-{
-    if (slot % 2 == 0) return true;
-    const int s = slot / 2;
-    if (D == 2) return s != 0;
-    if (D == 3) {
-        int l = 0;
-        while ((l + 1) * (l + 2) / 2 <= s) l++;
-        return s - l * (l + 1) / 2 != 0;
-    }
-    int l3 = 0;
-    while ((l3 + 1) * (l3 + 2) * (l3 + 3) / 6 <= s) l3++;
-    int r = s - l3 * (l3 + 1) * (l3 + 2) / 6;
-    int l2 = 0;
-    while ((l2 + 1) * (l2 + 2) / 2 <= r) l2++;
-    return r - l2 * (l2 + 1) / 2 != 0;
-}
-
-// index of an emitted slot among the emitted slots
-template <int D, int L>
-__host__ __device__ constexpr int compact_of(int slot)
-{
-    int c = 0;
-    for (int t = 0; t < slot; t++) c += emitted<D, L>(t) ? 1 : 0;
-    return c;
-}
-
-// compact index of every slot (-1: not emitted), as a table the compiler folds
-template <int D, int L>
-struct CompactTable {
-    static constexpr int N = 2 * stored_states(D, L);
-    int v[N];
-    constexpr CompactTable() : v{}
+struct EmitTable {
+    static constexpr int SLOTS = 2 * stored_states(D, L);
+    static constexpr int NE = D == 2 ? 2 * L + 1
+                              : (D == 3 ? SLOTS - (L + 1) : SLOTS - (L + 1) * (L + 2) / 2);
+    int slot[NE];
+    constexpr EmitTable() : slot{}
     {
-        int c = 0;
-        for (int t = 0; t < N; t++) v[t] = emitted<D, L>(t) ? c++ : -1;
+        int e = 0;
+        if (D == 2) {
+            slot[e++] = 0;
+            for (int l = 1; l <= L; l++) {
+                slot[e++] = 2 * l;
+                slot[e++] = 2 * l + 1;
+            }
+        } else if (D == 3) {
+            for (int m = 0; m <= L; m++)
+                for (int l = m; l <= L; l++) {
+                    const int st = l * (l + 1) / 2 + m;
+                    slot[e++] = 2 * st;
+                    if (m > 0) slot[e++] = 2 * st + 1;
+                }
+        } else {
+            for (int l1 = 0; l1 <= L; l1++)
+                for (int l2 = l1; l2 <= L; l2++)
+                    for (int l3 = l2; l3 <= L; l3++) {
+                        const int st = l3 * (l3 + 1) * (l3 + 2) / 6 + l2 * (l2 + 1) / 2 + l1;
+                        slot[e++] = 2 * st;
+                        if (l1 > 0) slot[e++] = 2 * st + 1;
+                    }
+        }
     }
 };
 
@@ -94,14 +89,13 @@ template <int D, int L>
 struct Cfg {
     static constexpr int NST = stored_states(D, L);
     static constexpr int SLOTS = 2 * NST;
-    static constexpr int NE = compact_of<D, L>(SLOTS);             // emitted slots
-    static constexpr bool STAGE = D <= 3;                          // sorted staging, no replicas
-    static constexpr int SSTR = 65;                                // staging row stride (floats)
-    static constexpr int CJ = (NE + 63) / 64;                      // emitted slots per lane
-    static constexpr int NREP = STAGE ? 0 : ((24576 / (SLOTS * 4)) >= 2 * kMaxBins ? 2 * kMaxBins : kMaxBins);
-    static constexpr int NK = STAGE ? CJ * kMaxBins : (kMaxBins * SLOTS + 63) / 64;  // FP64 accumulators per lane
-    static constexpr int QWORDS = (D == 4) ? 5 : 4;                // queue words per pair
-    static constexpr int WAVE_BYTES = kQCap * QWORDS * 4 + kSegCap * 8 + (STAGE ? NE * SSTR * 4 : SLOTS * NREP * 4);
+    static constexpr int NE = EmitTable<D, L>::NE;             // emitted values per pair
+    static constexpr int NCH = (NE + 63) / 64;                 // staging chunks per pair
+    static constexpr int E = (NE + NCH - 1) / NCH;             // staging rows per chunk
+    static constexpr int SSTR = 65;                            // staging row stride (floats)
+    static constexpr int NK = NCH * kMaxBins;                  // FP64 accumulators per lane
+    static constexpr int QWORDS = (D == 4) ? 5 : 4;            // queue words per pair
+    static constexpr int WAVE_BYTES = kQCap * QWORDS * 4 + kSegCap * 8 + E * SSTR * 4;
 };
 
 __device__ __forceinline__ unsigned lane_id()
@@ -117,6 +111,25 @@ __device__ __forceinline__ int rank_in_mask(unsigned long long m)
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// true if stored state st (index in the library's state order) has l1 > 0,
+// i.e. an imaginary part that the harmonics emit
+template <int D, int L>
+__device__ __forceinline__ bool emitted_im(int st)
+{
+    if (D == 2) return st != 0;
+    if (D == 3) {
+        int l = 0;
+        while ((l + 1) * (l + 2) / 2 <= st) l++;
+        return st - l * (l + 1) / 2 != 0;
+    }
+    int l3 = 0;
+    while ((l3 + 1) * (l3 + 2) * (l3 + 3) / 6 <= st) l3++;
+    int r = st - l3 * (l3 + 1) * (l3 + 2) / 6;
+    int l2 = 0;
+    while ((l2 + 1) * (l2 + 2) / 2 <= r) l2++;
+    return r - l2 * (l2 + 1) / 2 != 0;
+}
+
 template <int D>
 __device__ __forceinline__ uint32_t rec_coord(const uint4 &r, int k)
 {
@@ -128,7 +141,8 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 {
     using C = Cfg<D, L>;
     constexpr int SLOTS = C::SLOTS;
-    constexpr int NREP = C::NREP;
+    constexpr int E = C::E;
+    constexpr int NE = C::NE;
     extern __shared__ __align__(16) char smem[];
     const int nb = a.nb;
     const int lane = (int)lane_id();
@@ -137,48 +151,31 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     double *e2 = reinterpret_cast<double *>(smem);
     float *e2f = reinterpret_cast<float *>(smem + (kMaxBins + 1) * 8);
     uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 12);
-    int *roff = reinterpret_cast<int *>(smem + (kMaxBins + 1) * 12 + kMaxBucket);
-    int *rcnt = roff + kMaxBins;
     for (int t = threadIdx.x; t <= nb; t += blockDim.x) {
         e2[t] = a.e2[t];
         e2f[t] = (float)a.e2[t];
     }
     for (int t = threadIdx.x; t < a.nbucket; t += blockDim.x) btab[t] = a.bucket_bin[t];
-    for (int t = threadIdx.x; t < kMaxBins; t += blockDim.x) {
-        roff[t] = a.rep_off[t];
-        rcnt[t] = a.rep_cnt[t];
-    }
 
     char *wb = smem + kTableBytes + wave * C::WAVE_BYTES;
     int4 *q4 = reinterpret_cast<int4 *>(wb);                                     // [kQCap]
     float *qwx = reinterpret_cast<float *>(wb + kQCap * 16);                     // [kQCap] (D = 4 weight)
     uint2 *segs = reinterpret_cast<uint2 *>(wb + kQCap * C::QWORDS * 4);         // [kSegCap]
-    // D <= 3: staging [NE][SSTR] (column 64 takes the lanes without a pair);
-    // D = 4: replica pools [SLOTS][NREP]
-    float *stage = reinterpret_cast<float *>(wb + kQCap * C::QWORDS * 4 + kSegCap * 8);
-    float *rep = stage;
-    if constexpr (!C::STAGE)
-        for (int t = lane; t < SLOTS * NREP; t += 64) rep[t] = 0.f;
+    float *stage = reinterpret_cast<float *>(wb + kQCap * C::QWORDS * 4 + kSegCap * 8);  // [E][SSTR]
     __syncthreads();
 
-    // D <= 3: this lane reduces emitted slots c = lane + 64 j; fslot[j] is the
-    // slot's place in the row of a (-1: none)
-    int fslot[C::CJ];
+    // this lane reduces staging row `lane` of every chunk k, i.e. emitted value
+    // k E + lane; fslot[k] is its slot in the row of a (-1: none)
+    constexpr EmitTable<D, L> ET{};
+    int fslot[C::NCH];
 #pragma unroll
-    for (int j = 0; j < C::CJ; j++) {
-        const int c = lane + 64 * j;
-        fslot[j] = -1;
-        for (int t = 0, k = 0; t < SLOTS; t++) {
-            if (!emitted<D, L>(t)) continue;
-            if (k++ == c) {
-                fslot[j] = t;
-                break;
-            }
-        }
+    for (int k = 0; k < C::NCH; k++) {
+        const int e = k * E + lane;
+        fslot[k] = (lane < E && e < NE) ? ET.slot[e] : -1;
     }
 
     const int nacc = nb * SLOTS;
-    double acc[C::NK];  // D <= 3: acc[j kMaxBins + b] of slot lane + 64 j; D = 4: entry lane + 64 k of [bin][slot]
+    double acc[C::NK];  // acc[k kMaxBins + b]: chunk k's row `lane`, bin b
 #pragma unroll
     for (int k = 0; k < C::NK; k++) acc[k] = 0.0;
 
@@ -200,30 +197,6 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
         const float wi = (D == 4) ? a.w[ip] : (D == 3 ? __int_as_float((int)ri.w) : __int_as_float((int)ri.z));
 
         int qn = 0;      // queued pairs (wave-uniform)
-        int nbatch = 0;
-
-        // ---- fold the FP32 replicas into the FP64 accumulators -------------
-        auto flush = [&]() {
-            NPCF_WAVE_SYNC();
-            if constexpr (C::STAGE) return;  // sums go straight to FP64 per batch
-#pragma unroll
-            for (int k = 0; k < C::NK; k++) {
-                const int t = lane + 64 * k;
-                if (t < nacc) {
-                    const int b = t / SLOTS;
-                    const int s = t - b * SLOTS;
-                    float *p = rep + s * NREP + roff[b];
-                    const int R = rcnt[b];
-                    double sum = 0.0;
-                    for (int r = 0; r < R; r++) {
-                        sum += (double)p[r];
-                        p[r] = 0.f;
-                    }
-                    acc[k] += sum;
-                }
-            }
-            NPCF_WAVE_SYNC();
-        };
 
         // ---- phase B: queued pairs [0, cnt) ---------------------------------
         auto process = [&](int cnt) {
@@ -280,68 +253,62 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             const unsigned long long vm = ballot(valid);
             my_pairs += (unsigned long long)__popcll(vm);
             const float rinv = valid ? __builtin_amdgcn_rsqf(fr2) : 0.f;  // fr2 >= e2[0] > 0: no denormal path
-            if (!valid) wk = 0.f;  // invalid lanes evaluate harmonics of weight zero
+            if (!valid) wk = 0.f;  // lanes without a pair evaluate harmonics of weight zero
             float u[D];
 #pragma unroll
             for (int k = 0; k < D; k++) u[k] = f[k] * rinv;
 
-            if constexpr (C::STAGE) {
-                // position of this pair in the batch sorted by bin: lanes with a
-                // smaller bin, plus lanes of the same bin below this one (bins
-                // < 16: compare four bit planes, most significant first)
-                unsigned long long Bk[4];
+            // position of this pair in the batch sorted by bin: lanes with a
+            // smaller bin, plus lanes of the same bin below this one (bins < 16:
+            // compare four bit planes, most significant first)
+            unsigned long long Bk[4];
 #pragma unroll
-                for (int k = 0; k < 4; k++) Bk[k] = ballot(valid && ((bin >> k) & 1));
-                unsigned long long same = vm, lt = 0ull;
+            for (int k = 0; k < 4; k++) Bk[k] = ballot(valid && ((bin >> k) & 1));
+            unsigned long long same = vm, lt = 0ull;
 #pragma unroll
-                for (int k = 3; k >= 0; k--) {
-                    const unsigned long long mk = 0ull - (unsigned long long)((bin >> k) & 1);
-                    lt |= same & ~Bk[k] & mk;
-                    same &= Bk[k] ^ ~mk;
-                }
-                const int pos = valid ? __popcll(lt) + rank_in_mask(same) : 64;
-                constexpr CompactTable<D, L> CT{};
-                harmonics<D, L>(u, wk, [&](int slot, float v) {
-                    if (CT.v[slot] >= 0) stage[CT.v[slot] * C::SSTR + pos] = v;
-                });
+            for (int k = 3; k >= 0; k--) {
+                const unsigned long long mk = 0ull - (unsigned long long)((bin >> k) & 1);
+                lt |= same & ~Bk[k] & mk;
+                same &= Bk[k] ^ ~mk;
+            }
+            const int pos = valid ? __popcll(lt) + rank_in_mask(same) : 64;  // column 64: no pair
+
+            // staged rows [0, rows) of chunk k: lanes over rows; each bin's run of
+            // sorted columns summed in FP32 (two interleaved partial sums) and
+            // added to the FP64 accumulator
+            auto reduce = [&](int k, int rows) {
                 NPCF_WAVE_SYNC();
-                // lanes over emitted slots: each bin's run of sorted pairs, summed in
-                // FP32 (two interleaved partial sums) and added to the FP64 accumulator
+                const float *srow = stage + (lane < rows ? lane : rows - 1) * C::SSTR;
+                int j0 = 0;
 #pragma unroll
-                for (int j = 0; j < C::CJ; j++) {
-                    const int c = lane + 64 * j;
-                    const float *row = stage + (c < C::NE ? c : C::NE - 1) * C::SSTR;
-                    int j0 = 0;
+                for (int b = 0; b < kMaxBins; b++) {
+                    if (b < nb) {
+                        unsigned long long mb = vm;
 #pragma unroll
-                    for (int b = 0; b < kMaxBins; b++) {
-                        if (b < nb) {
-                            unsigned long long mb = vm;
-#pragma unroll
-                            for (int k = 0; k < 4; k++) mb &= ((b >> k) & 1) ? Bk[k] : ~Bk[k];
-                            const int cnt = __popcll(mb);
-                            if (cnt) {
-                                float s0 = 0.f, s1 = 0.f;
-                                int t = j0;
-                                for (; t + 1 < j0 + cnt; t += 2) {
-                                    s0 += row[t];
-                                    s1 += row[t + 1];
-                                }
-                                if (t < j0 + cnt) s0 += row[t];
-                                acc[j * kMaxBins + b] += (double)(s0 + s1);
-                                j0 += cnt;
+                        for (int t = 0; t < 4; t++) mb &= ((b >> t) & 1) ? Bk[t] : ~Bk[t];
+                        const int cnt = __popcll(mb);
+                        if (cnt) {
+                            float s0 = 0.f, s1 = 0.f;
+                            int t = j0;
+                            for (; t + 1 < j0 + cnt; t += 2) {
+                                s0 += srow[t];
+                                s1 += srow[t + 1];
                             }
+                            if (t < j0 + cnt) s0 += srow[t];
+                            acc[k * kMaxBins + b] += (double)(s0 + s1);
+                            j0 += cnt;
                         }
                     }
                 }
-            } else {
-                float *base = rep + roff[bin] + (lane & (rcnt[bin] - 1));
-                if (valid) {
-                    harmonics<D, L>(u, wk, [&](int slot, float v) {
-                        __hip_atomic_fetch_add(base + slot * NREP, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    });
-                }
-            }
-            NPCF_WAVE_SYNC();
+                NPCF_WAVE_SYNC();  // the next chunk overwrites the staging rows
+            };
+
+            int e = 0;  // emission counter (a constant at every call once unrolled)
+            harmonics<D, L>(u, wk, [&](int, float v) {
+                stage[(e % E) * C::SSTR + pos] = v;
+                if (e % E == E - 1 || e == NE - 1) reduce(e / E, e % E + 1);
+                e++;
+            });
         };
 
         // ---- stencil: per-axis cell ranges around the primary ----------------
@@ -515,7 +482,6 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                             if (D == 4) qwx[lane] = qwx[64 + lane];
                         }
                         qn = rest;
-                        if (!C::STAGE && ++nbatch % kFlushBatches == 0) flush();
                         NPCF_WAVE_SYNC();
                     }
                     cur = nxt;
@@ -524,29 +490,20 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             }
         }
         if (qn > 0) process(qn);
-        flush();
-        // the primary's row of a (FP32) and its weight; clear the FP64 accumulators
+        // the primary's row of a (FP32): emitted slots from the accumulators,
+        // zeros in the others; clear the accumulators
         float *Arow = a.A + (size_t)row * nacc;
-        if constexpr (C::STAGE) {
-            // emitted slots from the accumulators, then zeros in the others
 #pragma unroll
-            for (int j = 0; j < C::CJ; j++) {
+        for (int k = 0; k < C::NCH; k++) {
 #pragma unroll
-                for (int b = 0; b < kMaxBins; b++) {
-                    if (b < nb && fslot[j] >= 0) Arow[b * SLOTS + fslot[j]] = (float)acc[j * kMaxBins + b];
-                    acc[j * kMaxBins + b] = 0.0;
-                }
+            for (int b = 0; b < kMaxBins; b++) {
+                if (b < nb && fslot[k] >= 0) Arow[b * SLOTS + fslot[k]] = (float)acc[k * kMaxBins + b];
+                acc[k * kMaxBins + b] = 0.0;
             }
-            constexpr CompactTable<D, L> CT{};
-            for (int t = lane; t < nacc; t += 64)
-                if (CT.v[t % SLOTS] < 0) Arow[t] = 0.f;
-        } else {
-#pragma unroll
-            for (int k = 0; k < C::NK; k++) {
-                const int t = lane + 64 * k;
-                if (t < nacc) Arow[t] = (float)acc[k];
-                acc[k] = 0.0;
-            }
+        }
+        for (int t = lane; t < nacc; t += 64) {
+            const int sl = t % SLOTS;
+            if (sl % 2 == 1 && !emitted_im<D, L>(sl / 2)) Arow[t] = 0.f;
         }
         if (lane == 0) a.wrow[row] = wi;
     }
@@ -555,9 +512,6 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 
 template <int D, int L>
 int lds_bytes() { return kTableBytes + 4 * Cfg<D, L>::WAVE_BYTES; }
-
-template <int D, int L>
-int nrep() { return Cfg<D, L>::NREP; }
 
 template <int D, int L>
 hipError_t launch_dl(const HarmArgs &a, int grid, hipStream_t s)

@@ -5,6 +5,7 @@
 // (never emitted for l1 = 0, which is real).
 #pragma once
 #include "npcf_internal.h"
+#include <type_traits>
 
 namespace npcf {
 namespace harm {
@@ -76,6 +77,27 @@ struct HarmConst {
     }
 };
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).  Every
+// index below is a constant, so the emitted slots, table offsets and the
+// caller's emission counter fold at compile time (triangular loops under
+// #pragma unroll are not always unrolled fully).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Offset of (alpha_n, beta_n, ...) tables in HarmConst: c_0 then 2 per step.
+constexpr int geg_table_offset(int first_nmax, int j)
+{
+    int off = 0;
+    for (int t = 0; t < j; t++) off += 1 + 2 * (first_nmax - t);
+    return off;
+}
+
 // The emitted value for stored state s is w * conj(Y_s(u)) split into real
 // (slot 2s) and imaginary (slot 2s+1) parts; m = 0 (l1 = 0) states have no
 // imaginary part and emit only the real slot.
@@ -87,119 +109,109 @@ __device__ __forceinline__ void harm_d2(const float *u, float w, F &&emit)
     constexpr HarmConst<2, L> H{};
     float pr = w * H.v[0], pi = 0.f;
     emit(0, pr);
-#pragma unroll
-    for (int l = 1; l <= L; l++) {
-        float nr = pr * u[0] + pi * u[1];
-        float ni = pi * u[0] - pr * u[1];
+    static_for<1, L + 1>([&](auto lc) {
+        constexpr int l = lc;
+        const float nr = pr * u[0] + pi * u[1];
+        const float ni = pi * u[0] - pr * u[1];
         pr = nr;
         pi = ni;
         emit(2 * l, pr);
         emit(2 * l + 1, pi);
-    }
+    });
 }
 
 // D = 3: Y_{m,l} = K (u1 + i u2)^m C^{(m+1/2)}_{l-m}(u3).  The normalised
-// Gegenbauer values obey c_n = alpha_n u3 c_{n-1} - beta_n c_{n-2}; hc holds,
-// for m = 0..L, c_0 followed by (alpha_n, beta_n) for n = 1..L-m.
+// Gegenbauer values obey c_n = alpha_n u3 c_{n-1} - beta_n c_{n-2}; the table
+// holds, for m = 0..L, c_0 followed by (alpha_n, beta_n) for n = 1..L-m.
 template <int L, class F>
 __device__ __forceinline__ void harm_d3(const float *u, float w, F &&emit)
 {
     constexpr HarmConst<3, L> H{};
-    const float *hc = H.v;
     float pr = w, pi = 0.f;
-    int ci = 0;
-#pragma unroll
-    for (int m = 0; m <= L; m++) {
-        if (m > 0) {
-            float nr = pr * u[0] + pi * u[1];
-            float ni = pi * u[0] - pr * u[1];
+    static_for<0, L + 1>([&](auto mc) {
+        constexpr int m = mc;
+        constexpr int base = geg_table_offset(L, m);
+        if constexpr (m > 0) {
+            const float nr = pr * u[0] + pi * u[1];
+            const float ni = pi * u[0] - pr * u[1];
             pr = nr;
             pi = ni;
         }
-        float c1 = hc[ci++];
-        float c2 = 0.f;
+        float c1 = H.v[base], c2 = 0.f;
         {
-            const int s = m * (m + 1) / 2 + m;
+            constexpr int s = m * (m + 1) / 2 + m;
             emit(2 * s, c1 * pr);
-            if (m > 0) emit(2 * s + 1, c1 * pi);
+            if constexpr (m > 0) emit(2 * s + 1, c1 * pi);
         }
-#pragma unroll
-        for (int l = m + 1; l <= L; l++) {
-            float al = hc[ci++], be = hc[ci++];
-            float c = al * u[2] * c1 - be * c2;
+        static_for<m + 1, L + 1>([&](auto lc) {
+            constexpr int l = lc;
+            constexpr int n = l - m;
+            const float c = H.v[base + 2 * n - 1] * u[2] * c1 - H.v[base + 2 * n] * c2;
             c2 = c1;
             c1 = c;
-            const int s = l * (l + 1) / 2 + m;
+            constexpr int s = l * (l + 1) / 2 + m;
             emit(2 * s, c * pr);
-            if (m > 0) emit(2 * s + 1, c * pi);
-        }
-    }
+            if constexpr (m > 0) emit(2 * s + 1, c * pi);
+        });
+    });
 }
 
 // D = 4: Y_{l1 l2 l3} = (u1 + i u2)^{l1} g_{l1}(l2) c_{l2}(l3) with
 //   c_{l2}(l3) = N3 C^{(l2+1)}_{l3-l2}(u4)
 //   g_{l1}(l2) = (2 pi)^{-1/2} N2 rho^{l2-l1} C^{(l1+1/2)}_{l2-l1}(u3/rho), rho^2 = u1^2+u2^2+u3^2,
-// both by three-term recurrences; hc holds the c tables (for l2 = 0..L: c_0,
-// (alpha, beta) for n = 1..L-l2), then the g tables (for l1 = 0..L).
+// both by three-term recurrences; the table holds the c tables (for
+// l2 = 0..L: c_0, (alpha, beta) for n = 1..L-l2), then the g tables (l1 = 0..L).
 template <int L, class F>
 __device__ __forceinline__ void harm_d4(const float *u, float w, F &&emit)
 {
     constexpr HarmConst<4, L> H{};
-    const float *hc = H.v;
     constexpr int NT = (L + 1) * (L + 2) / 2;
+    constexpr int GBASE = geg_table_offset(L, L + 1);
     float ct[NT];  // ct[tri(l2) + (l3 - l2)]
     float gt[NT];  // gt[tri(l1) + (l2 - l1)]
     const float rho2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    int ci = 0;
-    int ti = 0;
-#pragma unroll
-    for (int l2 = 0; l2 <= L; l2++) {
-        float c1 = hc[ci++], c2 = 0.f;
-        ct[ti++] = c1;
-#pragma unroll
-        for (int n = 1; n <= L - l2; n++) {
-            float al = hc[ci++], be = hc[ci++];
-            float c = al * u[3] * c1 - be * c2;
+    static_for<0, L + 1>([&](auto jc) {
+        constexpr int j = jc;
+        constexpr int cb = geg_table_offset(L, j);
+        constexpr int gb = GBASE + geg_table_offset(L, j);
+        constexpr int ti = (j * (2 * L + 3 - j)) / 2;
+        float c1 = H.v[cb], c2 = 0.f, g1 = H.v[gb], g2 = 0.f;
+        ct[ti] = c1;
+        gt[ti] = g1;
+        static_for<1, L - j + 1>([&](auto nc) {
+            constexpr int n = nc;
+            const float c = H.v[cb + 2 * n - 1] * u[3] * c1 - H.v[cb + 2 * n] * c2;
             c2 = c1;
             c1 = c;
-            ct[ti++] = c;
-        }
-    }
-    ti = 0;
-#pragma unroll
-    for (int l1 = 0; l1 <= L; l1++) {
-        float g1 = hc[ci++], g2 = 0.f;
-        gt[ti++] = g1;
-#pragma unroll
-        for (int n = 1; n <= L - l1; n++) {
-            float al = hc[ci++], be = hc[ci++];
-            float g = al * u[2] * g1 - be * rho2 * g2;
+            ct[ti + n] = c;
+            const float g = H.v[gb + 2 * n - 1] * u[2] * g1 - H.v[gb + 2 * n] * rho2 * g2;
             g2 = g1;
             g1 = g;
-            gt[ti++] = g;
-        }
-    }
+            gt[ti + n] = g;
+        });
+    });
     float pr = w, pi = 0.f;
-#pragma unroll
-    for (int l1 = 0; l1 <= L; l1++) {
-        if (l1 > 0) {
-            float nr = pr * u[0] + pi * u[1];
-            float ni = pi * u[0] - pr * u[1];
+    static_for<0, L + 1>([&](auto l1c) {
+        constexpr int l1 = l1c;
+        if constexpr (l1 > 0) {
+            const float nr = pr * u[0] + pi * u[1];
+            const float ni = pi * u[0] - pr * u[1];
             pr = nr;
             pi = ni;
         }
-#pragma unroll
-        for (int l2 = l1; l2 <= L; l2++) {
+        static_for<l1, L + 1>([&](auto l2c) {
+            constexpr int l2 = l2c;
             const float g = gt[(l1 * (2 * L + 3 - l1)) / 2 + (l2 - l1)];
-#pragma unroll
-            for (int l3 = l2; l3 <= L; l3++) {
-                const float v = g * ct[(l2 * (2 * L + 3 - l2)) / 2 + (l3 - l2)];
-                const int s = l3 * (l3 + 1) * (l3 + 2) / 6 + l2 * (l2 + 1) / 2 + l1;
-                emit(2 * s, v * pr);
-                if (l1 > 0) emit(2 * s + 1, v * pi);
-            }
-        }
-    }
+            const float gr = g * pr, gi = g * pi;
+            static_for<l2, L + 1>([&](auto l3c) {
+                constexpr int l3 = l3c;
+                const float c = ct[(l2 * (2 * L + 3 - l2)) / 2 + (l3 - l2)];
+                constexpr int s = l3 * (l3 + 1) * (l3 + 2) / 6 + l2 * (l2 + 1) / 2 + l1;
+                emit(2 * s, c * gr);
+                if constexpr (l1 > 0) emit(2 * s + 1, c * gi);
+            });
+        });
+    });
 }
 
 template <int D, int L, class F>

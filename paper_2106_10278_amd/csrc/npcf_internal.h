@@ -61,8 +61,6 @@ struct HarmArgs {
     int nbucket;
     const double *e2;         // [nb + 1] squared edges (physical, FP64)
     const uint8_t *bucket_bin;  // [nbucket] bin at the low end of each r^2 bucket
-    int rep_off[kMaxBins];    // replica pool of each bin: first replica
-    int rep_cnt[kMaxBins];    //   and its size
     float *A;                 // out: [nrows][nb][2 * nstate]
     float *wrow;              // out: [nrows] primary weights
     unsigned long long *pairs;  // in-range pair counter
@@ -135,9 +133,6 @@ hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s)
 int harmonic_lds_bytes_d2(int L);
 int harmonic_lds_bytes_d3(int L);
 int harmonic_lds_bytes_d4(int L);
-int harmonic_nrep_d2(int L);
-int harmonic_nrep_d3(int L);
-int harmonic_nrep_d4(int L);
 int couple_njobs(int N, int nlam, int nparts, int mtiles);
 int couple_jobs_per_block();
 int couple_nblocks(int njobs, int nrb);
