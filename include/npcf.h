@@ -150,21 +150,36 @@ npcf_status npcf_pair_count(npcf_plan_t plan, int64_t *pairs_data, int64_t *pair
 npcf_status npcf_alm(npcf_plan_t plan, const double *pos, const double *w, int64_t n,
                      int64_t prim_begin, int64_t prim_end, double *out, size_t out_len);
 
-/* Batched accumulation of `ncat` independent catalogues in one persistent
- * launch sequence (captured as a HIP graph on first use for a given shape).
- * Catalogue c: pos[c] (device, SoA double [D][n[c]]), w[c] (device, double
- * [n[c]]), n_data[c] leading points are data, the rest randoms (both act as
- * primaries and secondaries with their weights).  Results go to ncat
- * separate FP64 accumulators read back with npcf_finalize_batch.  Requires
- * n[c] <= max_points.  Errors: NPCF_E_INVALID, NPCF_E_NOMEM, NPCF_E_DEVICE. */
+/* Batched accumulation of `ncat` independent catalogues (the estimator of
+ * eq. NPCF-estimator-discrete for each, every point a primary; the c4-style
+ * workload of many data-plus-randoms catalogues of uneven sizes).
+ * Catalogue c: pos[c] (device, SoA double [D][n[c]]) and w[c] (device,
+ * double [n[c]]); data and randoms of one catalogue are one point set told
+ * apart only by their weights.  All catalogues share one cell list (keys
+ * catalogue-major) and run as one launch sequence: a persistent harmonic
+ * kernel over rows of every catalogue, coupling blocks cut at catalogue
+ * boundaries, one FP64 accumulator per catalogue.  The sequence is captured
+ * as a HIP graph the first time a shape (ncat, n[], pos[], w[]) is seen and
+ * replayed afterwards; device workspace for the batch is allocated then
+ * (independent of max_points).  Asynchronous: ordered after the plan's stream
+ * and the plan's stream waits for it.  The caller's buffers must stay valid
+ * and unchanged in address while the shape is reused.  Not available with
+ * NPCF_NORM_BY_RANDOMS (NPCF_E_UNSUPPORTED).
+ * Errors: NPCF_E_INVALID (null pointers, ncat < 1, n[c] < 1, more than 2^31
+ * points in total), NPCF_E_UNSUPPORTED (too many cells for 32-bit keys),
+ * NPCF_E_NOMEM, NPCF_E_DEVICE, NPCF_E_STATE. */
 npcf_status npcf_accumulate_batch(npcf_plan_t plan, int ncat, const double *const *pos, const double *const *w,
                                   const int64_t *n);
 
-/* Finalised output of catalogue `cat` of the last npcf_accumulate_batch, with
- * the same layout and rules as npcf_finalize; per-catalogue completion time
- * in milliseconds from the start of the batch (device clock) in *done_ms
- * (may be NULL). */
-npcf_status npcf_finalize_batch(npcf_plan_t plan, int cat, double *out, size_t out_len, double *done_ms);
+/* Finalised output of catalogue `cat` of the last npcf_accumulate_batch,
+ * with the layout and rules of npcf_finalize (synchronises).  *done_ms (may
+ * be NULL): that catalogue's completion time in milliseconds after the start
+ * of the batch, from device-clock timestamps written in the launch sequence;
+ * *pairs (may be NULL): its in-range ordered pair count.
+ * Errors: NPCF_E_INVALID (cat out of range, out_len wrong, non-finite input),
+ * NPCF_E_STATE (no batch run yet). */
+npcf_status npcf_finalize_batch(npcf_plan_t plan, int cat, double *out, size_t out_len, double *done_ms,
+                                int64_t *pairs);
 
 /* Zero the accumulators and pair counters (asynchronous). */
 npcf_status npcf_reset(npcf_plan_t plan);
@@ -172,10 +187,13 @@ npcf_status npcf_reset(npcf_plan_t plan);
 /* Release the plan and its device memory (synchronises first). NULL is a no-op. */
 npcf_status npcf_destroy(npcf_plan_t plan);
 
-/* Tuning knobs (0 keeps the default): cell subdivision s (cells of side
- * >= r_max / s, 1..4) and primaries per coupling block.  Takes effect on
- * the next accumulate. */
-npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block);
+/* Tuning knobs (0 keeps the current value): cell subdivision s (cells of
+ * side >= r_max / s, 1..4), primaries per coupling block (rounded up to a
+ * multiple of 16), and primaries per chunk (rows of a^b held at once; at most
+ * the size chosen at plan time).  Synchronises; takes effect on the next
+ * accumulate (a batch shape is captured again).  Errors: NPCF_E_INVALID
+ * (out of range), NPCF_E_NOMEM. */
+npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block, int64_t chunk_rows);
 
 /* Device time in milliseconds, accumulated since the last reset and measured
  * with HIP events on the plan's stream, of ms3[0] the harmonic stage,
@@ -185,6 +203,11 @@ npcf_status npcf_stage_ms(npcf_plan_t plan, double *ms3);
 
 /* Static description of a status code (never NULL). */
 const char *npcf_strerror(npcf_status status);
+
+/* The last HIP failure behind an NPCF_E_DEVICE or NPCF_E_NOMEM on the
+ * calling thread: the HIP error name and code and the failing call ("" if
+ * none; never NULL; valid until the next failure on this thread). */
+const char *npcf_last_error_detail(void);
 
 /* Library version string (never NULL). */
 const char *npcf_version(void);

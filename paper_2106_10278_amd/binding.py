@@ -30,7 +30,10 @@ class NPCFLibraryMissing(RuntimeError):
 class NPCFError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
-        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        detail = ""
+        if status in (NPCF_E_DEVICE, NPCF_E_NOMEM):
+            detail = load_library().npcf_last_error_detail().decode()
+        super().__init__(f"{what}: {strerror(status)} (status {status})" + (f" [{detail}]" if detail else ""))
 
 
 class _Config(ctypes.Structure):
@@ -54,6 +57,11 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise NPCFLibraryMissing(
             f"{LIB_PATH} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # soname), which must be loaded first so that the library binds to it;
+    # loaded the other way round, torch would bring a second runtime and the
+    # two would contend for the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
     ip = ctypes.POINTER(ctypes.c_int)
@@ -64,14 +72,15 @@ def load_library():
     lib.npcf_pair_count.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.npcf_alm.argtypes = [vp, vp, vp, i64, i64, i64, dp, ctypes.c_size_t]
     lib.npcf_accumulate_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
-    lib.npcf_finalize_batch.argtypes = [vp, ctypes.c_int, dp, ctypes.c_size_t, dp]
+    lib.npcf_finalize_batch.argtypes = [vp, ctypes.c_int, dp, ctypes.c_size_t, dp, ctypes.POINTER(i64)]
     lib.npcf_reset.argtypes = [vp]
     lib.npcf_destroy.argtypes = [vp]
-    lib.npcf_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.npcf_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
     lib.npcf_stage_ms.argtypes = [vp, dp]
     lib.npcf_strerror.argtypes = [ctypes.c_int]
     lib.npcf_strerror.restype = ctypes.c_char_p
     lib.npcf_version.restype = ctypes.c_char_p
+    lib.npcf_last_error_detail.restype = ctypes.c_char_p
     for name in ("npcf_plan", "npcf_accumulate", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
                  "npcf_accumulate_batch", "npcf_finalize_batch", "npcf_reset", "npcf_destroy", "npcf_set_tuning",
                  "npcf_stage_ms"):
@@ -192,19 +201,24 @@ class NPCF:
         _check(load_library().npcf_accumulate_batch(self._h, ncat, P, W, Ns), "npcf_accumulate_batch")
 
     def finalize_batch(self, cat: int):
+        """(zeta of catalogue `cat`, its completion time in ms after the batch
+        start, its in-range pair count)."""
         out = np.zeros(self.out_len)
         done = ctypes.c_double()
+        pairs = ctypes.c_int64()
         _check(load_library().npcf_finalize_batch(self._h, int(cat), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                                  self.out_len, ctypes.byref(done)), "npcf_finalize_batch")
-        return self._shape(out), done.value
+                                                  self.out_len, ctypes.byref(done), ctypes.byref(pairs)),
+               "npcf_finalize_batch")
+        return self._shape(out), done.value, pairs.value
 
     def stage_ms(self):
         ms = (ctypes.c_double * 3)()
         _check(load_library().npcf_stage_ms(self._h, ms), "npcf_stage_ms")
         return {"harmonic": ms[0], "coupling": ms[1], "cells": ms[2]}
 
-    def set_tuning(self, cell_subdiv: int = 0, couple_block: int = 0):
-        _check(load_library().npcf_set_tuning(self._h, int(cell_subdiv), int(couple_block)), "npcf_set_tuning")
+    def set_tuning(self, cell_subdiv: int = 0, couple_block: int = 0, chunk_rows: int = 0):
+        _check(load_library().npcf_set_tuning(self._h, int(cell_subdiv), int(couple_block), int(chunk_rows)),
+               "npcf_set_tuning")
 
     def reset(self):
         _check(load_library().npcf_reset(self._h), "npcf_reset")

@@ -46,6 +46,8 @@ struct StageTimer {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
+struct BatchState;
+
 }  // namespace
 
 struct npcf_plan_s {
@@ -59,7 +61,8 @@ struct npcf_plan_s {
     int couple_rows = 0;  // 0: automatic
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
-    int64_t rows_cap = 0;
+    int64_t rows_cap = 0;      // primaries per chunk (rows of a held at once)
+    int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
     bool failed = false;
@@ -98,20 +101,29 @@ struct npcf_plan_s {
     double *d_bt_scale = nullptr;
     // stage timing (harmonic, coupling, prep) in ms, accumulated since reset
     std::vector<StageTimer> timers[3];
-    // batch state
-    std::vector<double *> batch_acc;
-    std::vector<hipEvent_t> batch_done;
-    hipEvent_t batch_start = nullptr;
+    int ncu = 256;  // compute units of the plan's device
+    // batched accumulation (npcf_accumulate_batch); owned
+    BatchState *batch = nullptr;
 };
 
 namespace {
 
+// The last HIP failure seen on this thread (npcf_last_error_detail).
+thread_local char g_last_error[256] = "";
+
 npcf_status dev_err(hipError_t e) { return e == hipSuccess ? NPCF_OK : (e == hipErrorOutOfMemory ? NPCF_E_NOMEM : NPCF_E_DEVICE); }
 
-#define NPCF_TRY(expr)                                  \
-    do {                                                \
-        hipError_t e__ = (expr);                        \
-        if (e__ != hipSuccess) return dev_err(e__);     \
+npcf_status dev_err_at(hipError_t e, const char *what, int line)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%d) from %s at npcf_abi.cpp:%d", hipGetErrorName(e),
+                  (int)e, what, line);
+    return dev_err(e);
+}
+
+#define NPCF_TRY(expr)                                                      \
+    do {                                                                    \
+        hipError_t e__ = (expr);                                            \
+        if (e__ != hipSuccess) return dev_err_at(e__, #expr, __LINE__);     \
     } while (0)
 
 template <class T>
@@ -241,38 +253,37 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
     return a;
 }
 
+// Persistent harmonic launch over a.nrows rows (rows handed out dynamically
+// through a.work, which is cleared first).
+hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(a.work, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    int grid = p->ncu * 8;
+    const int64_t need = ((int64_t)a.nrows + 3) / 4;
+    if (grid > need) grid = (int)std::max<int64_t>(1, need);
+    switch (p->D) {
+    case 2: return launch_harmonic_d2(p->L, a, grid, s);
+    case 3: return launch_harmonic_d3(p->L, a, grid, s);
+    default: return launch_harmonic_d4(p->L, a, grid, s);
+    }
+}
+
 npcf_status run_harmonic(npcf_plan_s *p, int rows, const int32_t *prim, unsigned long long *pairs)
 {
     hipStream_t s = p->stream;
-    NPCF_TRY(launch_fill_u32(p->work, 0u, 1, s));
     HarmArgs a = harm_args(p, rows, prim, pairs);
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
-    }
-    // persistent grid: a few workgroups per CU, rows handed out dynamically
-    int grid = ncu * 8;
-    int64_t need = ((int64_t)rows + 3) / 4;
-    if (grid > need) grid = (int)std::max<int64_t>(1, need);
     StageTimer t;
     npcf_status st = timer_begin(p, 0, t);
     if (st != NPCF_OK) return st;
-    hipError_t e;
-    switch (p->D) {
-    case 2: e = launch_harmonic_d2(p->L, a, grid, s); break;
-    case 3: e = launch_harmonic_d3(p->L, a, grid, s); break;
-    default: e = launch_harmonic_d4(p->L, a, grid, s); break;
-    }
-    NPCF_TRY(e);
+    NPCF_TRY(launch_harmonic(p, a, s));
     NPCF_TRY(hipEventRecord(t.b, s));
     p->timers[0].push_back(t);
     return NPCF_OK;
 }
 
-npcf_status run_couple(npcf_plan_s *p, int rows, double *acc)
+CoupleArgs couple_args(const npcf_plan_s *p, int rows)
 {
-    hipStream_t s = p->stream;
     const Tables &t = p->t;
     CoupleArgs a{};
     a.A = p->A;
@@ -291,6 +302,14 @@ npcf_status run_couple(npcf_plan_s *p, int rows, double *acc)
     a.mrows = t.mrows;
     a.mtiles = t.mtiles;
     a.max_block_terms = p->max_block_terms;
+    return a;
+}
+
+npcf_status run_couple(npcf_plan_s *p, int rows, double *acc)
+{
+    hipStream_t s = p->stream;
+    const Tables &t = p->t;
+    CoupleArgs a = couple_args(p, rows);
     const int64_t len = (int64_t)p->njobs * 256;
     if ((int64_t)a.n_rowblocks * len > p->partial_len) {
         // grow the partial buffer (rare: only with small custom block sizes)
@@ -351,6 +370,226 @@ npcf_status accumulate_impl(npcf_plan_s *p, const double *pos, const double *w, 
     return NPCF_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batches: ncat independent catalogues in one captured launch sequence.
+//   quantise all catalogues into one array with cell key c * ncell + cell ->
+//   one counting sort (catalogue-major, so catalogue c occupies sorted
+//   positions [off[c], off[c+1]) and cells [c * ncell, (c+1) * ncell)) ->
+//   per chunk of rows: persistent harmonic launch over rows of any catalogue,
+//   coupling with row blocks cut at catalogue boundaries, FP64 reduction of
+//   each catalogue's blocks into its own accumulator, and a device-clock
+//   timestamp for every catalogue whose last row the chunk holds.
+// The sequence is captured once per shape (sizes and input pointers) as a HIP
+// graph on an internal stream and replayed; it is ordered after the plan's
+// stream by events, and the plan's stream waits for it.
+// ---------------------------------------------------------------------------
+struct BatchSeg {
+    int cat, rb0, rb1;  // catalogue and its row blocks [rb0, rb1) in the chunk
+};
+
+struct BatchChunk {
+    int64_t r0 = 0;       // first global row
+    int rows = 0;
+    int rb_off = 0;       // into the row-block tables
+    int nrb = 0;
+    std::vector<BatchSeg> segs;
+    std::vector<int> ends;  // catalogues whose last row is in this chunk
+};
+
+struct BatchState {
+    int ncat = 0;
+    int64_t ntot = 0;
+    std::vector<int64_t> n, off;
+    std::vector<const double *> pos, w;
+    int ncs[kMaxD] = {1, 1, 1, 1};
+    int64_t ncell_cat = 1, ncell_tot = 1;
+    int rpb = 64;
+    std::vector<BatchChunk> chunks;
+    DevAlloc mem;
+    const double **d_pos = nullptr, **d_w = nullptr;
+    int64_t *d_off = nullptr;
+    uint32_t *qtmp[kMaxD] = {};
+    double *wall = nullptr, *w64s = nullptr;
+    uint32_t *cell = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *scan = nullptr;
+    int64_t scan_len = 0;
+    int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *iota = nullptr;
+    uint4 *rec = nullptr;
+    float *ws = nullptr;
+    double *acc = nullptr, *partial = nullptr;
+    unsigned long long *pairs = nullptr, *ts = nullptr;
+    int *rb_begin = nullptr, *rb_end = nullptr;
+    hipStream_t cs = nullptr;           // capture / replay stream (default priority)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double clock_khz = 0.0;
+    bool done = false;                  // a batch has been launched on this shape
+};
+
+void batch_release(npcf_plan_s *p)
+{
+    BatchState *b = p->batch;
+    if (!b) return;
+    if (b->cs) (void)hipStreamSynchronize(b->cs);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->cs) (void)hipStreamDestroy(b->cs);
+    b->mem.release();
+    delete b;
+    p->batch = nullptr;
+}
+
+bool batch_same_shape(const BatchState *b, int ncat, const double *const *pos, const double *const *w,
+                      const int64_t *n, const int *ncs)
+{
+    if (!b || b->ncat != ncat) return false;
+    for (int k = 0; k < kMaxD; k++)
+        if (b->ncs[k] != ncs[k]) return false;
+    for (int c = 0; c < ncat; c++)
+        if (b->n[c] != n[c] || b->pos[c] != pos[c] || b->w[c] != w[c]) return false;
+    return true;
+}
+
+npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, const double *const *w,
+                        const int64_t *n)
+{
+    batch_release(p);
+    BatchState *b = new (std::nothrow) BatchState();
+    if (!b) return NPCF_E_NOMEM;
+    p->batch = b;
+    b->ncat = ncat;
+    b->n.assign(n, n + ncat);
+    b->pos.assign(pos, pos + ncat);
+    b->w.assign(w, w + ncat);
+    b->off.assign(ncat + 1, 0);
+    for (int c = 0; c < ncat; c++) b->off[c + 1] = b->off[c] + n[c];
+    b->ntot = b->off[ncat];
+    if (b->ntot > (int64_t)INT32_MAX) return NPCF_E_INVALID;
+    b->ncell_cat = 1;
+    for (int k = 0; k < kMaxD; k++) b->ncs[k] = p->ncs[k];
+    for (int k = 0; k < p->D; k++) b->ncell_cat *= p->ncs[k];
+    b->ncell_tot = b->ncell_cat * ncat;
+    if (b->ncell_tot + 1 >= (int64_t)UINT32_MAX) return NPCF_E_UNSUPPORTED;  // 32-bit cell keys
+
+    // chunks of rows and their row blocks (never straddling a catalogue)
+    const int64_t cap = p->rows_cap;
+    b->rpb = couple_rows_per_block(p, std::min<int64_t>(cap, b->ntot));
+    std::vector<int> rbb, rbe;
+    for (int64_t r0 = 0; r0 < b->ntot; r0 += cap) {
+        BatchChunk ch;
+        ch.r0 = r0;
+        ch.rows = (int)std::min<int64_t>(cap, b->ntot - r0);
+        ch.rb_off = (int)rbb.size();
+        for (int c = 0; c < ncat; c++) {
+            const int64_t lo = std::max<int64_t>(b->off[c], r0), hi = std::min<int64_t>(b->off[c + 1], r0 + ch.rows);
+            if (lo >= hi) continue;
+            BatchSeg sg{c, (int)rbb.size() - ch.rb_off, 0};
+            for (int64_t r = lo; r < hi; r += b->rpb) {
+                rbb.push_back((int)(r - r0));
+                rbe.push_back((int)(std::min<int64_t>(r + b->rpb, hi) - r0));
+            }
+            sg.rb1 = (int)rbb.size() - ch.rb_off;
+            ch.segs.push_back(sg);
+            if (b->off[c + 1] <= r0 + ch.rows) ch.ends.push_back(c);
+        }
+        ch.nrb = (int)rbb.size() - ch.rb_off;
+        b->chunks.push_back(ch);
+    }
+    int max_nrb = 1;
+    for (auto &ch : b->chunks) max_nrb = std::max(max_nrb, ch.nrb);
+
+    DevAlloc &m = b->mem;
+    const int64_t N = std::max<int64_t>(b->ntot, 1);
+    const int64_t len = (int64_t)p->njobs * 256;
+    b->d_pos = m.get<const double *>(ncat);
+    b->d_w = m.get<const double *>(ncat);
+    b->d_off = m.get<int64_t>(ncat + 1);
+    for (int k = 0; k < p->D; k++) b->qtmp[k] = m.get<uint32_t>(N);
+    b->wall = m.get<double>(N);
+    b->w64s = m.get<double>(N);
+    b->cell = m.get<uint32_t>(N);
+    b->count = m.get<uint32_t>(b->ncell_tot + 1);
+    b->cell_start = m.get<uint32_t>(b->ncell_tot + 1);
+    b->cursor = m.get<uint32_t>(b->ncell_tot + 1);
+    b->scan_len = (std::max<int64_t>(b->ncell_tot + 1, N) + 1023) / 1024 + 1;
+    b->scan = m.get<uint32_t>(b->scan_len);
+    b->perm = m.get<int32_t>(N);
+    b->perm_sorted = m.get<int32_t>(N);
+    b->orig = m.get<int32_t>(N);
+    b->iota = m.get<int32_t>(N);
+    b->rec = m.get<uint4>(N);
+    b->ws = m.get<float>(N);
+    b->acc = m.get<double>((size_t)ncat * len);
+    b->partial = m.get<double>((size_t)max_nrb * len);
+    b->pairs = m.get<unsigned long long>(ncat);
+    b->ts = m.get<unsigned long long>(ncat + 1);
+    b->rb_begin = m.get<int>(std::max<size_t>(1, rbb.size()));
+    b->rb_end = m.get<int>(std::max<size_t>(1, rbe.size()));
+    if (!m.ok) return NPCF_E_NOMEM;
+    NPCF_TRY(hipStreamCreate(&b->cs));
+    NPCF_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    NPCF_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    int dev = 0, khz = 0;
+    NPCF_TRY(hipGetDevice(&dev));
+    NPCF_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    b->clock_khz = khz > 0 ? (double)khz : 100000.0;
+    hipStream_t s = b->cs;
+    NPCF_TRY(hipMemcpyAsync(b->d_pos, pos, ncat * sizeof(double *), hipMemcpyHostToDevice, s));
+    NPCF_TRY(hipMemcpyAsync(b->d_w, w, ncat * sizeof(double *), hipMemcpyHostToDevice, s));
+    NPCF_TRY(hipMemcpyAsync(b->d_off, b->off.data(), (ncat + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (!rbb.empty()) {
+        NPCF_TRY(hipMemcpyAsync(b->rb_begin, rbb.data(), rbb.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        NPCF_TRY(hipMemcpyAsync(b->rb_end, rbe.data(), rbe.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    NPCF_TRY(launch_iota_i32(b->iota, N, s));
+    NPCF_TRY(hipStreamSynchronize(s));
+    return NPCF_OK;
+}
+
+// Every launch of one batch, in order, on stream s (captured into the graph).
+npcf_status batch_record(npcf_plan_s *p, hipStream_t s)
+{
+    BatchState *b = p->batch;
+    const int64_t len = (int64_t)p->njobs * 256;
+    NPCF_TRY(launch_timestamp(b->ts + b->ncat, s));
+    NPCF_TRY(launch_fill_f64(b->acc, 0.0, (int64_t)b->ncat * len, s));
+    NPCF_TRY(launch_fill_u32((uint32_t *)b->pairs, 0u, 2 * (int64_t)b->ncat, s));
+    NPCF_TRY(launch_fill_u32(b->count, 0u, b->ncell_tot + 1, s));
+    // cell list of every catalogue at once
+    NPCF_TRY(launch_quantize_batch(p->D, p->cfg.periodic, b->ncat, b->d_pos, b->d_w, b->d_off, b->ntot, p->cfg.box,
+                                   b->ncs, b->ncell_cat, b->qtmp, b->wall, b->cell, b->count, p->bad, s));
+    NPCF_TRY(launch_exclusive_scan(b->count, b->cell_start, b->ncell_tot + 1, b->scan, b->scan_len, s));
+    NPCF_TRY(launch_copy_u32(b->cursor, b->cell_start, b->ncell_tot + 1, s));
+    NPCF_TRY(launch_scatter_perm(b->ntot, b->cell, b->cursor, b->perm, s));
+    NPCF_TRY(launch_cellsort(b->ntot, b->cell, b->cell_start, b->perm, b->perm_sorted, s));
+    NPCF_TRY(launch_gather(p->D, b->ntot, b->perm_sorted, b->qtmp, b->wall, b->rec, b->ws, b->w64s, b->orig, s));
+    // chunks: harmonic over rows of any catalogue, coupling per catalogue
+    for (const BatchChunk &ch : b->chunks) {
+        HarmArgs ha = harm_args(p, ch.rows, b->iota + ch.r0, b->pairs);
+        ha.rec = b->rec;
+        ha.w = b->ws;
+        ha.cell_start = b->cell_start;
+        ha.cat_begin = b->d_off;
+        ha.ncat = b->ncat;
+        ha.ncell_cat = b->ncell_cat;
+        NPCF_TRY(launch_harmonic(p, ha, s));
+        CoupleArgs ca = couple_args(p, ch.rows);
+        ca.rows_per_block = b->rpb;
+        ca.n_rowblocks = ch.nrb;
+        ca.rb_begin = b->rb_begin + ch.rb_off;
+        ca.rb_end = b->rb_end + ch.rb_off;
+        ca.partial = b->partial;
+        NPCF_TRY(launch_couple_kernel(p->N, p->cfg.precision, ca, p->njobs, p->t.nparts, p->d_sfac, s));
+        for (const BatchSeg &sg : ch.segs)
+            NPCF_TRY(launch_reduce_partials(b->partial + (size_t)sg.rb0 * len, sg.rb1 - sg.rb0, len,
+                                            b->acc + (size_t)sg.cat * len, s));
+        for (int c : ch.ends) NPCF_TRY(launch_timestamp(b->ts + c, s));
+    }
+    return NPCF_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -367,6 +606,8 @@ const char *npcf_strerror(npcf_status status)
     }
     return "unknown status";
 }
+
+const char *npcf_last_error_detail(void) { return g_last_error; }
 
 const char *npcf_version(void) { return "npcf-mi355x 0.1 (gfx950)"; }
 
@@ -410,9 +651,14 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     }
 
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
+    if (const hipError_t eg = hipGetDevice(&dev); eg != hipSuccess) {
         delete p;
-        return NPCF_E_DEVICE;
+        return dev_err_at(eg, "hipGetDevice", __LINE__);
+    }
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            p->ncu = ncu;
     }
     compute_grid(p);
     {
@@ -437,6 +683,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->flagpos = m.get<uint32_t>(max_points);
     const int64_t rowbytes = (int64_t)p->nb * 2 * t.nstate * sizeof(float);
     p->rows_cap = std::min<int64_t>(max_points, std::max<int64_t>(1024, kADefaultBudget / rowbytes));
+    p->rows_cap_max = p->rows_cap;
     p->A = m.get<float>((size_t)p->rows_cap * p->nb * 2 * t.nstate);
     p->wrow = m.get<float>(p->rows_cap);
     // partials for the automatic coupling block size
@@ -487,7 +734,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         p->mem.release();
         p->cellmem.release();
         delete p;
-        return dev_err(e);
+        return dev_err_at(e, "table upload", __LINE__);
     }
     *out = p;
     st = npcf_reset(p);
@@ -518,20 +765,21 @@ npcf_status npcf_destroy(npcf_plan_t p)
     if (!p) return NPCF_OK;
     (void)hipStreamSynchronize(p->stream);
     clear_timers(p);
-    for (auto e : p->batch_done) (void)hipEventDestroy(e);
-    if (p->batch_start) (void)hipEventDestroy(p->batch_start);
-    for (auto a : p->batch_acc) (void)hipFree(a);
+    batch_release(p);
     p->mem.release();
     p->cellmem.release();
     delete p;
     return NPCF_OK;
 }
 
-npcf_status npcf_set_tuning(npcf_plan_t p, int cell_subdiv, int couple_block)
+npcf_status npcf_set_tuning(npcf_plan_t p, int cell_subdiv, int couple_block, int64_t chunk_rows)
 {
     if (!p) return NPCF_E_INVALID;
-    if (cell_subdiv < 0 || cell_subdiv > 4 || couple_block < 0) return NPCF_E_INVALID;
+    if (cell_subdiv < 0 || cell_subdiv > 4 || couple_block < 0 || chunk_rows < 0 || chunk_rows > p->rows_cap_max)
+        return NPCF_E_INVALID;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return NPCF_E_DEVICE;
+    batch_release(p);  // the captured batch depends on every knob
+    if (chunk_rows > 0) p->rows_cap = chunk_rows;
     if (cell_subdiv > 0 && cell_subdiv != p->cell_subdiv) {
         p->cell_subdiv = cell_subdiv;
         compute_grid(p);
@@ -643,21 +891,67 @@ npcf_status npcf_alm(npcf_plan_t p, const double *pos, const double *w, int64_t 
 npcf_status npcf_accumulate_batch(npcf_plan_t p, int ncat, const double *const *pos, const double *const *w,
                                   const int64_t *n)
 {
-    (void)pos;
-    (void)w;
-    (void)n;
-    if (!p || ncat < 1) return NPCF_E_INVALID;
-    return NPCF_E_UNSUPPORTED;
+    if (!p || ncat < 1 || !pos || !w || !n) return NPCF_E_INVALID;
+    if (p->failed) return NPCF_E_STATE;
+    if (p->cfg.norm == NPCF_NORM_BY_RANDOMS) return NPCF_E_UNSUPPORTED;
+    for (int c = 0; c < ncat; c++)
+        if (!pos[c] || !w[c] || n[c] < 1) return NPCF_E_INVALID;
+    npcf_status st = NPCF_OK;
+    if (!batch_same_shape(p->batch, ncat, pos, w, n, p->ncs)) {
+        NPCF_TRY(hipStreamSynchronize(p->stream));
+        st = batch_setup(p, ncat, pos, w, n);
+        if (st != NPCF_OK) {
+            batch_release(p);
+            return st;
+        }
+    }
+    BatchState *b = p->batch;
+    // order after the caller's stream, capture once, replay
+    NPCF_TRY(hipEventRecord(b->ev_in, p->stream));
+    NPCF_TRY(hipStreamWaitEvent(b->cs, b->ev_in, 0));
+    if (!b->exec) {
+        NPCF_TRY(hipStreamBeginCapture(b->cs, hipStreamCaptureModeRelaxed));
+        st = batch_record(p, b->cs);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->cs, &g);
+        if (st != NPCF_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            batch_release(p);
+            return st != NPCF_OK ? st : dev_err_at(ec, "hipStreamEndCapture", __LINE__);
+        }
+        b->graph = g;
+        const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            batch_release(p);
+            return dev_err_at(ei, "hipGraphInstantiate", __LINE__);
+        }
+    }
+    NPCF_TRY(hipGraphLaunch(b->exec, b->cs));
+    NPCF_TRY(hipEventRecord(b->ev_out, b->cs));
+    NPCF_TRY(hipStreamWaitEvent(p->stream, b->ev_out, 0));
+    b->done = true;
+    return NPCF_OK;
 }
 
-npcf_status npcf_finalize_batch(npcf_plan_t p, int cat, double *out, size_t out_len, double *done_ms)
+npcf_status npcf_finalize_batch(npcf_plan_t p, int cat, double *out, size_t out_len, double *done_ms,
+                                int64_t *pairs)
 {
-    (void)cat;
-    (void)out;
-    (void)out_len;
-    (void)done_ms;
     if (!p) return NPCF_E_INVALID;
-    return NPCF_E_UNSUPPORTED;
+    if (p->failed) return NPCF_E_STATE;
+    BatchState *b = p->batch;
+    if (!b || !b->done) return NPCF_E_STATE;
+    if (cat < 0 || cat >= b->ncat) return NPCF_E_INVALID;
+    const int64_t len = (int64_t)p->njobs * 256;
+    npcf_status st = finalize_from(p, b->acc + (size_t)cat * len, nullptr, out, out_len);
+    if (st != NPCF_OK) return st;
+    unsigned long long h[2] = {0, 0}, pc = 0;
+    NPCF_TRY(hipMemcpyAsync(&h[0], b->ts + cat, sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    NPCF_TRY(hipMemcpyAsync(&h[1], b->ts + b->ncat, sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    NPCF_TRY(hipMemcpyAsync(&pc, b->pairs + cat, sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    NPCF_TRY(hipStreamSynchronize(p->stream));
+    if (done_ms) *done_ms = (double)(int64_t)(h[0] - h[1]) / b->clock_khz;
+    if (pairs) *pairs = (int64_t)pc;
+    return NPCF_OK;
 }
 
 // Stage times (ms) accumulated since the last reset: [0] harmonic, [1] coupling + reduce, [2] cell list.

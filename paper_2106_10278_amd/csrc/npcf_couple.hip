@@ -130,12 +130,12 @@ __device__ __forceinline__ bool block_work(int nrb, int njg, int &rb, int &jg)
 }
 
 // Stage kRowsStep rows of a (and their weights) into LDS, zero-padding rows
-// past the end.
-__device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, float *Ast, float *wst)
+// at and past r_end (the end of this block's rows).
+__device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, int r_end, float *Ast, float *wst)
 {
     const int rowlen = a.nb * 2 * a.nstate;
     const int total = kRowsStep * rowlen;
-    const int r_lim = a.nrows - r0;
+    const int r_lim = r_end - r0;
     const float *src = a.A + (size_t)r0 * rowlen;
     for (int t = threadIdx.x; t < total; t += blockDim.x) Ast[t] = (t < r_lim * rowlen) ? src[t] : 0.f;
     for (int t = threadIdx.x; t < kRowsStep; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
@@ -229,15 +229,19 @@ __global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int np
 #pragma unroll
         for (int v = 0; v < 4; v++) acc64[j][v] = 0.0;
 
-    const int r_begin = rb * a.rows_per_block;
+    int r_begin = rb * a.rows_per_block;
     int r_end = r_begin + a.rows_per_block;
+    if (a.rb_begin) {
+        r_begin = a.rb_begin[rb];
+        r_end = a.rb_end[rb];
+    }
     if (r_end > a.nrows) r_end = a.nrows;
     const int n = lane & 15;   // A row within the tile / output column b3
     const int kq = lane >> 4;  // K quarter
 
     for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
         __syncthreads();
-        stage_rows(a, r0, Ast, wst);
+        stage_rows(a, r0, r_end, Ast, wst);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kJobsPerWave; j++) {
@@ -304,8 +308,12 @@ __global__ __launch_bounds__(256) void k_couple3(CoupleArgs a, int njobs, int np
     for (int j = 0; j < kJobsPerWave; j++)
 #pragma unroll
         for (int v = 0; v < 4; v++) acc64[j][v] = 0.0;
-    const int r_begin = rb * a.rows_per_block;
+    int r_begin = rb * a.rows_per_block;
     int r_end = r_begin + a.rows_per_block;
+    if (a.rb_begin) {
+        r_begin = a.rb_begin[rb];
+        r_end = a.rb_end[rb];
+    }
     if (r_end > a.nrows) r_end = a.nrows;
     const int n = lane & 15;   // b1 (A row) and b2 (B column) of this lane
     const int kq = lane >> 4;
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(256) void k_couple3(CoupleArgs a, int njobs, int np
 
     for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
         __syncthreads();
-        stage_rows(a, r0, Ast, wst);
+        stage_rows(a, r0, r_end, Ast, wst);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kJobsPerWave; j++) {

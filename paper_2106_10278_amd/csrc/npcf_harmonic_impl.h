@@ -179,7 +179,6 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 #pragma unroll
     for (int k = 0; k < C::NK; k++) acc[k] = 0.0;
 
-    unsigned long long my_pairs = 0;
     const float e2lo_f = a.e2lo_f, e2hi_f = a.e2hi_f;
     const double e2lo = e2[0], e2hi = e2[nb];
     const double rmax2 = e2hi * (1.0 + 1e-9);
@@ -191,6 +190,19 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
         if (row >= a.nrows) break;
         const int ip = a.prim[row];
         const uint4 ri = a.rec[ip];
+        // the primary's catalogue (batches) and that catalogue's cell table
+        int cat = 0;
+        if (a.cat_begin) {
+            int lo = 0, hi = a.ncat;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (a.cat_begin[mid] <= ip) lo = mid;
+                else hi = mid;
+            }
+            cat = lo;
+        }
+        const uint32_t *cs = a.cell_start + (size_t)cat * (size_t)a.ncell_cat;
+        unsigned long long row_pairs = 0;
         uint32_t qi[D];
 #pragma unroll
         for (int k = 0; k < D; k++) qi[k] = rec_coord<D>(ri, k);
@@ -251,7 +263,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             }
             if (!valid) bin = 0;
             const unsigned long long vm = ballot(valid);
-            my_pairs += (unsigned long long)__popcll(vm);
+            row_pairs += (unsigned long long)__popcll(vm);
             const float rinv = valid ? __builtin_amdgcn_rsqf(fr2) : 0.f;  // fr2 >= e2[0] > 0: no denormal path
             if (!valid) wk = 0.f;  // lanes without a pair evaluate harmonics of weight zero
             float u[D];
@@ -396,13 +408,13 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                         ra1 = 0; rb1 = xb - a.ncs[0];
                     }
                     if (rb0 >= ra0) {
-                        sa0 = a.cell_start[lin + ra0];
-                        sb0 = a.cell_start[lin + rb0 + 1];
+                        sa0 = cs[lin + ra0];
+                        sb0 = cs[lin + rb0 + 1];
                         has0 = sb0 > sa0;
                     }
                     if (rb1 >= ra1) {
-                        sa1 = a.cell_start[lin + ra1];
-                        sb1 = a.cell_start[lin + rb1 + 1];
+                        sa1 = cs[lin + ra1];
+                        sb1 = cs[lin + rb1 + 1];
                         has1 = sb1 > sa1;
                     }
                 }
@@ -505,9 +517,11 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             const int sl = t % SLOTS;
             if (sl % 2 == 1 && !emitted_im<D, L>(sl / 2)) Arow[t] = 0.f;
         }
-        if (lane == 0) a.wrow[row] = wi;
+        if (lane == 0) {
+            a.wrow[row] = wi;
+            if (row_pairs) atomicAdd(a.pairs + cat, row_pairs);
+        }
     }
-    if (lane == 0 && my_pairs) atomicAdd(a.pairs, my_pairs);
 }
 
 template <int D, int L>

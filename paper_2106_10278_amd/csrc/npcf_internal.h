@@ -63,9 +63,15 @@ struct HarmArgs {
     const uint8_t *bucket_bin;  // [nbucket] bin at the low end of each r^2 bucket
     float *A;                 // out: [nrows][nb][2 * nstate]
     float *wrow;              // out: [nrows] primary weights
-    unsigned long long *pairs;  // in-range pair counter
+    unsigned long long *pairs;  // in-range pair counters, one per catalogue
     unsigned int *work;       // dynamic row counter (zeroed before launch)
     int periodic;
+    // batches: several catalogues sorted catalogue-major into one cell list.
+    // cat_begin[c] is catalogue c's first sorted position ([ncat + 1]); its
+    // cells are cell_start[c * ncell_cat ...].  nullptr: a single catalogue.
+    const int64_t *cat_begin;
+    int ncat;
+    int64_t ncell_cat;
 };
 
 // ---------------------------------------------------------------------------
@@ -108,6 +114,10 @@ struct CoupleArgs {
     int mtiles;                   // ceil(mrows / 16) (N = 4); 1 (N = 3)
     int max_block_terms;          // N = 4: most terms any block's jobs use (LDS copy)
     double *partial;              // out: [n_rowblocks][njobs][16][16]
+    // batches: rows [rb_begin[rb], rb_end[rb]) of row block rb (blocks never
+    // straddle two catalogues); nullptr: blocks of rows_per_block rows
+    const int *rb_begin;
+    const int *rb_end;
 };
 
 // ---------------------------------------------------------------------------
@@ -118,6 +128,16 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_quantize(int D, int periodic, const double *pos, const double *w, int64_t n, const double *box,
                            const int *ncs, uint32_t *const qtmp[kMaxD], uint32_t *cell, uint32_t *count, int *bad,
                            hipStream_t s);
+// batches: quantise every catalogue's points into one array (global index g =
+// off[c] + i) with cell key c * ncell_cat + cell, and copy the FP64 weights
+hipError_t launch_quantize_batch(int D, int periodic, int ncat, const double *const *pos, const double *const *w,
+                                 const int64_t *off, int64_t ntot, const double *box, const int *ncs,
+                                 int64_t ncell_cat, uint32_t *const qtmp[kMaxD], double *wall, uint32_t *cell,
+                                 uint32_t *count, int *bad, hipStream_t s);
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
+// device clock (constant-rate wall clock) at this point of the stream into *ts
+hipError_t launch_timestamp(unsigned long long *ts, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *scratch,
                                  int64_t scratch_len, hipStream_t s);
 hipError_t launch_scatter_perm(int64_t n, const uint32_t *cell, uint32_t *cursor, int32_t *perm, hipStream_t s);

@@ -73,6 +73,80 @@ __global__ void k_quantize(QuantArgs a)
     atomicAdd(&a.count[lin], 1u);
 }
 
+struct QuantBatchArgs {
+    const double *const *pos;   // [ncat] device pointers, SoA [D][n_c]
+    const double *const *w;     // [ncat]
+    const int64_t *off;         // [ncat + 1] first global index of each catalogue
+    int ncat;
+    int64_t ntot;
+    double box[kMaxD];
+    int ncs[kMaxD];
+    int64_t ncell_cat;
+    int periodic;
+    uint32_t *q[kMaxD];
+    double *wall;
+    uint32_t *cell;
+    uint32_t *count;
+    int *bad;
+};
+
+template <int D>
+__global__ void k_quantize_batch(QuantBatchArgs a)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.ntot) return;
+    int lo = 0, hi = a.ncat;  // catalogue c with off[c] <= g < off[c + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.off[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const int64_t i = g - a.off[lo];
+    const int64_t n = a.off[lo + 1] - a.off[lo];
+    const double *pos = a.pos[lo];
+    const double wi = a.w[lo][i];
+    bool ok = isfinite(wi);
+    uint64_t lin = 0, mul = 1;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const double x = pos[(int64_t)k * n + i];
+        ok = ok && isfinite(x);
+        if (!a.periodic) ok = ok && x >= 0.0 && x < a.box[k];
+        double t = x / a.box[k];
+        t = t - floor(t);
+        const double qd = rint(t * 4294967296.0);
+        uint64_t qq = (uint64_t)(int64_t)qd;
+        if (!a.periodic && qq > 0xffffffffull) qq = 0xffffffffull;
+        uint32_t q = (uint32_t)(qq & 0xffffffffull);
+        if (!ok) q = 0;
+        a.q[k][g] = q;
+        lin += (((uint64_t)q * (uint64_t)a.ncs[k]) >> 32) * mul;
+        mul *= (uint64_t)a.ncs[k];
+    }
+    if (!ok) atomicOr(a.bad, 1);
+    const uint64_t key = (uint64_t)lo * (uint64_t)a.ncell_cat + lin;
+    a.wall[g] = wi;
+    a.cell[g] = (uint32_t)key;
+    atomicAdd(&a.count[key], 1u);
+}
+
+__global__ void k_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_iota_i32(int32_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = (int32_t)i;
+}
+
+__global__ void k_timestamp(unsigned long long *ts)
+{
+    if (threadIdx.x == 0) *ts = (unsigned long long)wall_clock64();
+}
+
 // ---- exclusive scan (1024 elements per block, 256 threads x 4) -------------
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlk * kScanItems;
@@ -279,6 +353,61 @@ hipError_t launch_quantize(int D, int periodic, const double *pos, const double 
     case 4: hipLaunchKernelGGL(k_quantize<4>, dim3(grid_for(n)), dim3(kBlk), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize_batch(int D, int periodic, int ncat, const double *const *pos, const double *const *w,
+                                 const int64_t *off, int64_t ntot, const double *box, const int *ncs,
+                                 int64_t ncell_cat, uint32_t *const qtmp[kMaxD], double *wall, uint32_t *cell,
+                                 uint32_t *count, int *bad, hipStream_t s)
+{
+    QuantBatchArgs a{};
+    a.pos = pos;
+    a.w = w;
+    a.off = off;
+    a.ncat = ncat;
+    a.ntot = ntot;
+    for (int k = 0; k < kMaxD; k++) {
+        a.box[k] = box[k];
+        a.ncs[k] = ncs[k];
+        a.q[k] = qtmp[k];
+    }
+    a.ncell_cat = ncell_cat;
+    a.periodic = periodic;
+    a.wall = wall;
+    a.cell = cell;
+    a.count = count;
+    a.bad = bad;
+    switch (D) {
+    case 2: hipLaunchKernelGGL(k_quantize_batch<2>, dim3(grid_for(ntot)), dim3(kBlk), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_quantize_batch<3>, dim3(grid_for(ntot)), dim3(kBlk), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_quantize_batch<4>, dim3(grid_for(ntot)), dim3(kBlk), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + kBlk - 1) / kBlk;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)g), dim3(kBlk), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + kBlk - 1) / kBlk;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)g), dim3(kBlk), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestamp(unsigned long long *ts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_timestamp, dim3(1), dim3(64), 0, s, ts);
     return hipGetLastError();
 }
 

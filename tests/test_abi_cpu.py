@@ -2,6 +2,7 @@
 the public header declares, and rejects invalid configurations before any
 device call."""
 import ctypes
+import os
 import subprocess
 
 import numpy as np
@@ -99,3 +100,23 @@ def test_valid_plan_needs_a_device(lib):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _plan(lib) == binding.NPCF_E_DEVICE
+
+
+def test_single_hip_runtime_per_process():
+    """Loading the library first (before any torch import) must not bring a
+    second HIP runtime next to the one PyTorch ships: one libamdhip64 and one
+    libhsa-runtime64 mapped, in a fresh interpreter."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2106_10278_amd import binding\n"
+        "binding.load_library()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+        "print(len([l for l in libs if 'amdhip64' in l]), len([l for l in libs if 'hsa-runtime64' in l]))\n"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[-2:] == ["1", "1"]
