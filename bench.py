@@ -158,6 +158,51 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int):
     return base, errs
 
 
+def run_batch(precisions, steps: int, warmup: int, tune: bool = True):
+    """The batched workload: 64 D = 3, N = 4 catalogues (data sizes
+    log-uniform in [20k, 300k], clustered as c2, plus 3x randoms at w = -1/3)
+    in one npcf_accumulate_batch per step (captured HIP graph, replayed).
+    Reports aggregate pairs/s over the wall time of accumulate_batch +
+    finalize of every catalogue, and percentiles of the per-catalogue
+    completion times taken from device-clock timestamps."""
+    import torch
+    from paper_2106_10278_amd import NPCF, inputs
+    sizes = inputs.c4_batch_sizes()
+    pos, w = [], []
+    ref = None
+    for c, nd in enumerate(sizes):
+        wl = inputs.c4_catalogue(c, nd)
+        ref = ref or wl
+        pos.append(torch.from_numpy(np.ascontiguousarray(wl.pos)).to("cuda:0"))
+        w.append(torch.from_numpy(np.ascontiguousarray(wl.w)).to("cuda:0"))
+    npts = int(sum(int(x.shape[1]) for x in pos))
+    out = {"workload": f"D3-N4-lmax5 batch of {len(sizes)} catalogues (data log-uniform in [20k, 300k], "
+                       f"clustered as c2, + 3x randoms w=-1/3), {npts} points",
+           "catalogues": len(sizes), "points": npts, "paths": {}}
+    for prec in precisions:
+        big = int(np.argmax([int(x.shape[1]) for x in pos]))
+        plan = NPCF(3, 4, 5, ref.edges, ref.box, precision=prec, max_points=int(pos[big].shape[1]))
+        tuning = plan.autotune(pos[big], w[big]) if tune else None   # tile shapes from the largest catalogue
+        walls, lat, pairs = [], [], 0
+        for it in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.accumulate_batch(pos, w)
+            res = [plan.finalize_batch(c) for c in range(len(sizes))]
+            torch.cuda.synchronize()
+            if it >= warmup:
+                walls.append(time.perf_counter() - t0)
+                lat.extend(r[1] for r in res)
+                pairs += sum(r[2] for r in res)
+        plan.close()
+        wall = float(np.sum(walls))
+        out["paths"][prec] = {
+            "pairs_per_s": pairs / wall, "wall_ms_per_batch": 1e3 * wall / steps, "pairs_per_batch": pairs // steps,
+            "latency_ms": {q: float(np.percentile(lat, v)) for q, v in (("p50", 50), ("p90", 90), ("p99", 99))}
+            | {"max": float(np.max(lat))}, "tuning": tuning}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +212,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128, help="oracle primaries per role for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="mixed_fp16,mixed_bf16x6,plain,mixed_bf16")
+    ap.add_argument("--batch-steps", type=int, default=1, help="timed passes of the batched workload (0: skip)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes (no autotuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -195,6 +242,7 @@ def main():
     results = {}
     for prec in args.precisions.split(","):
         plan = factory(prec)
+        tuning = plan.autotune(pos, w) if not args.no_tune else None
         for _ in range(args.warmup):
             plan.reset()
             plan.accumulate(pos, w)
@@ -203,7 +251,7 @@ def main():
         results[prec] = {"pairs_per_s": pairs / wall, "ms_per_step": 1e3 * wall / args.steps,
                          "ms_median": float(np.median(ms)), "pairs_per_step": pairs // args.steps,
                          "stage_ms_per_step": {k: v / args.steps for k, v in stage.items()},
-                         "harmonic_ms_per_launch": stage["harmonic"] / launches}
+                         "harmonic_ms_per_launch": stage["harmonic"] / launches, "tuning": tuning}
         plan.close()
 
     cpu = None
@@ -225,6 +273,10 @@ def main():
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
             "traffic": load_traffic(key), "flops_per_pair": fpp, "launch_ms": r["harmonic_ms_per_launch"]}
 
+    batch = None
+    if args.batch_steps > 0 and args.workload == "c2":
+        batch = run_batch([head, "plain"] if head != "plain" else ["plain"], args.batch_steps, 1, not args.no_tune)
+
     line = {
         "metric": "pairs/s + 4PCF wall time, mixed vs plain on one GPU at rel err <=1e-5",
         "value": r["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -238,6 +290,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_vs_oracle": errs,
+        "batch": batch,
     }
     print(json.dumps(line))
 

@@ -195,6 +195,17 @@ npcf_status npcf_destroy(npcf_plan_t plan);
  * (out of range), NPCF_E_NOMEM. */
 npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block, int64_t chunk_rows);
 
+/* Autotuner: times the harmonic stage with its cell list for every cell
+ * subdivision s = 1..4, then the coupling stage for several primaries per
+ * coupling block (the automatic size and 64..1024), on `sample` primaries of
+ * the given catalogue taken from four ranges spread over it (best of two runs
+ * each, HIP events), and keeps the fastest settings (as npcf_set_tuning).
+ * Resets the accumulators.  Outputs (may be NULL): the chosen subdivision,
+ * block size (0: automatic) and the sampled time in ms.  Errors as
+ * npcf_accumulate. */
+npcf_status npcf_autotune(npcf_plan_t plan, const double *pos, const double *w, int64_t n, int64_t sample,
+                          int *cell_subdiv, int *couple_block, double *best_ms);
+
 /* Device time in milliseconds, accumulated since the last reset and measured
  * with HIP events on the plan's stream, of ms3[0] the harmonic stage,
  * ms3[1] the coupling stage with its FP64 reduction and ms3[2] the cell-list

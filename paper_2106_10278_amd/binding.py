@@ -77,13 +77,14 @@ def load_library():
     lib.npcf_destroy.argtypes = [vp]
     lib.npcf_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
     lib.npcf_stage_ms.argtypes = [vp, dp]
+    lib.npcf_autotune.argtypes = [vp, vp, vp, i64, i64, ip, ip, dp]
     lib.npcf_strerror.argtypes = [ctypes.c_int]
     lib.npcf_strerror.restype = ctypes.c_char_p
     lib.npcf_version.restype = ctypes.c_char_p
     lib.npcf_last_error_detail.restype = ctypes.c_char_p
     for name in ("npcf_plan", "npcf_accumulate", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
                  "npcf_accumulate_batch", "npcf_finalize_batch", "npcf_reset", "npcf_destroy", "npcf_set_tuning",
-                 "npcf_stage_ms"):
+                 "npcf_stage_ms", "npcf_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -219,6 +220,14 @@ class NPCF:
     def set_tuning(self, cell_subdiv: int = 0, couple_block: int = 0, chunk_rows: int = 0):
         _check(load_library().npcf_set_tuning(self._h, int(cell_subdiv), int(couple_block), int(chunk_rows)),
                "npcf_set_tuning")
+
+    def autotune(self, pos, w, sample: int = 8192):
+        """Pick the cell subdivision and coupling block size by timing a
+        sample of primaries (resets the accumulators)."""
+        cs, cb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(load_library().npcf_autotune(self._h, _dptr(pos), _dptr(w), int(w.shape[0]), int(sample),
+                                            ctypes.byref(cs), ctypes.byref(cb), ctypes.byref(ms)), "npcf_autotune")
+        return {"cell_subdiv": cs.value, "couple_block": cb.value, "sample_ms": ms.value}
 
     def reset(self):
         _check(load_library().npcf_reset(self._h), "npcf_reset")

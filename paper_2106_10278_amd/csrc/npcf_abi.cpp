@@ -954,6 +954,80 @@ npcf_status npcf_finalize_batch(npcf_plan_t p, int cat, double *out, size_t out_
     return NPCF_OK;
 }
 
+npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int64_t n, int64_t sample,
+                          int *cell_subdiv, int *couple_block, double *best_ms)
+{
+    npcf_status st = check_inputs(p, pos, w, n, 0, n);
+    if (st != NPCF_OK) return st;
+    if (sample < 4) sample = 4;
+    if (sample > n) sample = n;
+    // four primary ranges spread over the catalogue (data and randoms alike)
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    for (int k = 0; k < 4; k++) {
+        const int64_t a = n * k / 4, b = std::min<int64_t>(n, a + std::max<int64_t>(1, sample / 4));
+        if (a < b) ranges.push_back({a, b});
+    }
+    auto measure = [&](double &harm, double &coup) -> npcf_status {
+        double best_h = 1e300, best_c = 1e300;
+        for (int rep = 0; rep < 2; rep++) {  // best of two
+            npcf_status s2 = npcf_reset(p);
+            if (s2 != NPCF_OK) return s2;
+            for (auto &r : ranges) {
+                s2 = npcf_accumulate(p, pos, w, n, r.first, r.second, NPCF_ROLE_DATA);
+                if (s2 != NPCF_OK) return s2;
+            }
+            double ms3[3];
+            s2 = npcf_stage_ms(p, ms3);
+            if (s2 != NPCF_OK) return s2;
+            best_h = std::min(best_h, ms3[0] + ms3[2]);
+            best_c = std::min(best_c, ms3[1]);
+        }
+        harm = best_h;
+        coup = best_c;
+        return NPCF_OK;
+    };
+    double h = 0.0, c = 0.0;
+    st = measure(h, c);  // first launches (code loading) out of the way
+    if (st != NPCF_OK) return st;
+    // cell subdivision: harmonic stage + cell list
+    int best_s = p->cell_subdiv;
+    double best_h = 1e300;
+    for (int sdv = 1; sdv <= 4; sdv++) {
+        st = npcf_set_tuning(p, sdv, 0, 0);
+        if (st != NPCF_OK) return st;
+        st = measure(h, c);
+        if (st != NPCF_OK) return st;
+        if (h < best_h) {
+            best_h = h;
+            best_s = sdv;
+        }
+    }
+    st = npcf_set_tuning(p, best_s, 0, 0);
+    if (st != NPCF_OK) return st;
+    // primaries per coupling block (0: the automatic size)
+    const int cands[] = {0, 64, 128, 256, 512, 1024};
+    int best_b = 0;
+    double best_c = 1e300;
+    for (int cb : cands) {
+        batch_release(p);
+        p->couple_rows = cb;
+        st = measure(h, c);
+        if (st != NPCF_OK) return st;
+        if (c < best_c) {
+            best_c = c;
+            best_b = cb;
+        }
+    }
+    batch_release(p);
+    p->couple_rows = best_b;
+    st = npcf_reset(p);
+    if (st != NPCF_OK) return st;
+    if (cell_subdiv) *cell_subdiv = best_s;
+    if (couple_block) *couple_block = best_b;
+    if (best_ms) *best_ms = best_h + best_c;
+    return NPCF_OK;
+}
+
 // Stage times (ms) accumulated since the last reset: [0] harmonic, [1] coupling + reduce, [2] cell list.
 npcf_status npcf_stage_ms(npcf_plan_t p, double *ms3)
 {

@@ -14,9 +14,10 @@
 //    candidate, next batch prefetched);
 //  - phase A (lanes over candidates): exact int32 periodic separation,
 //    conservative FP32 range test, ballot compaction into an LDS pair queue;
-//  - phase B (lanes over 64 queued pairs): bin from FP32 r^2 (FP64, matching
-//    the definition on lattice inputs, for the rare pair near an edge), FP32
-//    unit vector, harmonics by Gegenbauer recurrences in registers;
+//  - phase B (lanes over 64 queued pairs): FP64 r^2 with the definition's
+//    arithmetic (exact bins on lattice inputs), unit vector normalised in
+//    FP64 and rounded to FP32, harmonics by Gegenbauer recurrences in FP32
+//    registers;
 //  - scatter without atomics or collisions: each lane takes its position in
 //    the batch sorted by bin (bit-plane ballots) and writes every harmonic it
 //    emits into column `position` of an LDS staging array whose rows follow
@@ -36,11 +37,7 @@ namespace harm {
 constexpr int kQCap = 128;          // pair queue entries per wave
 constexpr int kSegCap = 128;        // candidate segments per row chunk
 constexpr int kMaxBucket = 1024;
-constexpr int kTableBytes = (kMaxBins + 1) * 8 + (kMaxBins + 1) * 4 + kMaxBucket;
-// FP32 binning is exact unless r^2 lies within this relative distance of an edge
-// (bound on the FP32 error of r^2 and of the rounded edge: about 12 ulp); such
-// lanes redo the FP64 binning
-constexpr float kEdgeTol = 2e-6f;
+constexpr int kTableBytes = (kMaxBins + 1) * 8 + kMaxBucket;
 
 #define NPCF_WAVE_SYNC()                                       \
     do {                                                       \
@@ -149,12 +146,8 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     const int wave = threadIdx.x >> 6;
 
     double *e2 = reinterpret_cast<double *>(smem);
-    float *e2f = reinterpret_cast<float *>(smem + (kMaxBins + 1) * 8);
-    uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 12);
-    for (int t = threadIdx.x; t <= nb; t += blockDim.x) {
-        e2[t] = a.e2[t];
-        e2f[t] = (float)a.e2[t];
-    }
+    uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 8);
+    for (int t = threadIdx.x; t <= nb; t += blockDim.x) e2[t] = a.e2[t];
     for (int t = threadIdx.x; t < a.nbucket; t += blockDim.x) btab[t] = a.bucket_bin[t];
 
     char *wb = smem + kTableBytes + wave * C::WAVE_BYTES;
@@ -228,47 +221,37 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                     wk = __int_as_float(D == 3 ? e.w : e.z);
                 }
             }
-            // FP32 squared distance and bin; lanes within kEdgeTol of an edge
-            // (rare) redo both in FP64, summed axis by axis without contraction
-            float f[D];
-            float fr2 = 0.f;
+            // separation in FP64 from the exact integer offsets: r^2 summed axis
+            // by axis without contraction (the definition's arithmetic, so the
+            // bin is decided exactly as there), the unit vector normalised in
+            // FP64 and rounded once to FP32 (its error enters Y_l about l times)
+            double v[D];
+            double r2 = 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
-                f[k] = (float)dq[k] * a.scale[k];
-                fr2 += f[k] * f[k];
+                v[k] = __dmul_rn((double)dq[k], a.scale64[k]);
+                r2 = __dadd_rn(r2, __dmul_rn(v[k], v[k]));
             }
             int bin;
             {
-                int bk = (int)((fr2 - a.bucket_lo) * a.bucket_inv);
+                int bk = (int)(((float)r2 - a.bucket_lo) * a.bucket_inv);
                 bk = bk < 0 ? 0 : (bk >= a.nbucket ? a.nbucket - 1 : bk);
                 bin = btab[bk];
-                while (bin + 1 < nb && fr2 >= e2f[bin + 1]) bin++;
-                while (bin > 0 && fr2 < e2f[bin]) bin--;
+                while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
+                while (bin > 0 && r2 < e2[bin]) bin--;
             }
-            const float tol = kEdgeTol * fr2;
-            const bool near = live && (fr2 - e2f[bin] < tol || e2f[bin + 1] - fr2 < tol);
-            bool valid = live && fr2 >= e2f[0] && fr2 < e2f[nb];
-            if (ballot(near)) {
-                if (near) {
-                    double r2 = 0.0;
-#pragma unroll
-                    for (int k = 0; k < D; k++) {
-                        const double v = __dmul_rn((double)dq[k], a.scale64[k]);
-                        r2 = __dadd_rn(r2, __dmul_rn(v, v));
-                    }
-                    valid = r2 >= e2lo && r2 < e2hi;
-                    bin = 0;
-                    while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
-                }
-            }
+            const bool valid = live && r2 >= e2lo && r2 < e2hi;
             if (!valid) bin = 0;
             const unsigned long long vm = ballot(valid);
             row_pairs += (unsigned long long)__popcll(vm);
-            const float rinv = valid ? __builtin_amdgcn_rsqf(fr2) : 0.f;  // fr2 >= e2[0] > 0: no denormal path
+            // 1/r: hardware FP64 estimate plus one Newton step
+            const double rs = valid ? r2 : 1.0;
+            double rinv = __builtin_amdgcn_rsq(rs);
+            rinv = rinv * (1.5 - 0.5 * rs * rinv * rinv);
             if (!valid) wk = 0.f;  // lanes without a pair evaluate harmonics of weight zero
             float u[D];
 #pragma unroll
-            for (int k = 0; k < D; k++) u[k] = f[k] * rinv;
+            for (int k = 0; k < D; k++) u[k] = valid ? (float)(v[k] * rinv) : 0.f;
 
             // position of this pair in the batch sorted by bin: lanes with a
             // smaller bin, plus lanes of the same bin below this one (bins < 16:

@@ -213,3 +213,21 @@ def test_norm_by_randoms():
     cerr, _ = conditioned_error(got * zr[i0][None, :], zd, condition_scale(data))
     print(f"[err] by_randoms conditioned {cerr:.3e}", flush=True)
     assert cerr <= 2e-6
+
+
+def test_autotune_keeps_results():
+    """The autotuner only changes tile shapes: results after it match the
+    oracle, and the chosen settings are in range."""
+    import torch
+    from paper_2106_10278_amd import NPCF
+    wl = _case(3, 4, 3, 600, 51, 16.0, 4.5, 4)
+    print("[case] autotune", flush=True)
+    plan = NPCF(3, 4, 3, wl.edges, wl.box, max_points=600)
+    pos = torch.from_numpy(wl.pos).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    t = plan.autotune(pos, w, sample=256)
+    assert 1 <= t["cell_subdiv"] <= 4 and t["couple_block"] in (0, 64, 128, 256, 512, 1024) and t["sample_ms"] > 0
+    got, pairs, _ = gpu_run(wl, plan=plan)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl), f"autotuned s={t['cell_subdiv']} b={t['couple_block']}", strict=False)
