@@ -214,6 +214,7 @@ def main():
     ap.add_argument("--precisions", default="mixed_fp16,mixed_bf16x6,plain,mixed_bf16")
     ap.add_argument("--batch-steps", type=int, default=1, help="timed passes of the batched workload (0: skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes (no autotuner)")
+    ap.add_argument("--tuning", default="", help="fixed 'cell_subdiv,couple_block' instead of the autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -242,7 +243,12 @@ def main():
     results = {}
     for prec in args.precisions.split(","):
         plan = factory(prec)
-        tuning = plan.autotune(pos, w) if not args.no_tune else None
+        if args.tuning:
+            sdv, blk = (int(x) for x in args.tuning.split(","))
+            plan.set_tuning(cell_subdiv=sdv, couple_block=blk)
+            tuning = {"cell_subdiv": sdv, "couple_block": blk, "fixed": True}
+        else:
+            tuning = plan.autotune(pos, w) if not args.no_tune else None
         for _ in range(args.warmup):
             plan.reset()
             plan.accumulate(pos, w)
