@@ -65,6 +65,7 @@ struct npcf_plan_s {
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
+    bool term_coupling = false;  // force the term-by-term N = 4 kernel (NPCF_COUPLING=terms)
     bool failed = false;
 
     DevAlloc mem;
@@ -99,6 +100,11 @@ struct npcf_plan_s {
     float *d_sfac = nullptr;
     int *d_bt_row = nullptr, *d_bt_col = nullptr;
     double *d_bt_scale = nullptr;
+    FPair *d_fpairs = nullptr;
+    FGroup *d_fgroups = nullptr;
+    FProd *d_fprods = nullptr;
+    float *d_fcoef = nullptr;
+    int2 *d_ftasks = nullptr;
     // stage timing (harmonic, coupling, prep) in ms, accumulated since reset
     std::vector<StageTimer> timers[3];
     int ncu = 256;  // compute units of the plan's device
@@ -302,6 +308,14 @@ CoupleArgs couple_args(const npcf_plan_s *p, int rows)
     a.mrows = t.mrows;
     a.mtiles = t.mtiles;
     a.max_block_terms = p->max_block_terms;
+    if (p->d_fpairs && !p->term_coupling) {
+        a.fpairs = p->d_fpairs;
+        a.fgroups = p->d_fgroups;
+        a.fprods = p->d_fprods;
+        a.fcoef = p->d_fcoef;
+        a.ftasks = p->d_ftasks;
+        a.nftasks = (int)t.ftasks.size();
+    }
     return a;
 }
 
@@ -662,6 +676,10 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     }
     compute_grid(p);
     {
+        const char *cv = std::getenv("NPCF_COUPLING");
+        p->term_coupling = cv && std::strcmp(cv, "terms") == 0;
+    }
+    {
         const int L = p->L;
         const int lds = p->D == 2 ? harmonic_lds_bytes_d2(L) : (p->D == 3 ? harmonic_lds_bytes_d3(L) : harmonic_lds_bytes_d4(L));
         if (lds <= 0 || lds > 160 * 1024) {
@@ -710,6 +728,13 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->d_bt_row = m.get<int>(t.bt_row.size());
     p->d_bt_col = m.get<int>(t.bt_col.size());
     p->d_bt_scale = m.get<double>(t.bt_scale.size());
+    if (!t.fpairs.empty()) {
+        p->d_fpairs = m.get<FPair>(t.fpairs.size());
+        p->d_fgroups = m.get<FGroup>(t.fgroups.size());
+        p->d_fprods = m.get<FProd>(t.fprods.size());
+        p->d_fcoef = m.get<float>(t.fcoef.size());
+        p->d_ftasks = m.get<int2>(t.ftasks.size());
+    }
     if (!m.ok || alloc_cells(p) != NPCF_OK) {
         p->mem.release();
         p->cellmem.release();
@@ -729,6 +754,13 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     if (e == hipSuccess) e = upload(p->d_bt_row, t.bt_row, s);
     if (e == hipSuccess) e = upload(p->d_bt_col, t.bt_col, s);
     if (e == hipSuccess) e = upload(p->d_bt_scale, t.bt_scale, s);
+    if (!t.fpairs.empty()) {
+        if (e == hipSuccess) e = upload(p->d_fpairs, t.fpairs, s);
+        if (e == hipSuccess) e = upload(p->d_fgroups, t.fgroups, s);
+        if (e == hipSuccess) e = upload(p->d_fprods, t.fprods, s);
+        if (e == hipSuccess) e = upload(p->d_fcoef, t.fcoef, s);
+        if (e == hipSuccess) e = upload(p->d_ftasks, t.ftasks, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         p->mem.release();

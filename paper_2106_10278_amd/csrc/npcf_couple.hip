@@ -287,6 +287,163 @@ __global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int np
 }
 
 // ---------------------------------------------------------------------------
+// N = 4, D = 3, factorised: a job is (pair (l1, l2), tile of radial pairs)
+// and produces every Lambda = (l1, l2, l3) of the pair.  Per group (pair, m3)
+// each product P_{m1} = op(a_{l1}[b1]) op(a_{l2}[b2]) is formed once and added,
+// with its coefficient for each l3, into that slot's S; each slot then takes
+// its MFMA slice against a_{l3 m3}[b3].  Two jobs per wave (paired by cost).
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
+{
+    // read-only tables: the constant address space lets uniform loads go
+    // through the scalar unit
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// a wave-uniform value held in a scalar register (table indices and
+// coefficients, so their loads and uses stay on the scalar path)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int rowlen = a.nb * 2 * a.nstate;
+    float *Ast = reinterpret_cast<float *>(smem);
+    float *wst = Ast + kRowsStep * rowlen;
+    const int ntg = (a.nftasks + 3) / 4;
+    int rb, tg;
+    if (!block_work(a.n_rowblocks, ntg, rb, tg)) return;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int task = tg * 4 + wave;
+    const auto tasks = as_const(a.ftasks);
+    const auto pairs = as_const(a.fpairs);
+    const auto groups = as_const(a.fgroups);
+    const auto prods = as_const(a.fprods);
+    const auto coef = as_const(a.fcoef);
+    int jobs[2] = {-1, -1};
+    if (task < a.nftasks) {
+        jobs[0] = uni(tasks[task].x);
+        jobs[1] = uni(tasks[task].y);
+    }
+
+    double acc[2][kMaxSlots][4];
+#pragma unroll
+    for (int js = 0; js < 2; js++)
+#pragma unroll
+        for (int k = 0; k < kMaxSlots; k++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[js][k][v] = 0.0;
+
+    int r_begin = rb * a.rows_per_block;
+    int r_end = r_begin + a.rows_per_block;
+    if (a.rb_begin) {
+        r_begin = a.rb_begin[rb];
+        r_end = a.rb_end[rb];
+    }
+    if (r_end > a.nrows) r_end = a.nrows;
+    const int n = lane & 15;   // GEMM row within the tile / output column b3
+    const int kq = lane >> 4;  // K quarter: primaries 4 kq .. 4 kq + 3 of the step
+    const int st2 = 2 * a.nstate;
+
+    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+        __syncthreads();
+        stage_rows(a, r0, r_end, Ast, wst);
+        __syncthreads();
+#pragma unroll
+        for (int js = 0; js < 2; js++) {
+            const int job = jobs[js];
+            if (job < 0) continue;
+            const int pp = uni(job / a.mtiles);
+            const int tile = uni(job - pp * a.mtiles);
+            const int m = tile * 16 + n;
+            const bool rowok = m < a.mrows;
+            const int2 bb = rowok ? a.row_pairs[m] : make_int2(0, 0);
+            const bool colok = n < a.nb;
+            const int gb = uni(pairs[pp].grp_begin), ge = uni(pairs[pp].grp_end);
+            for (int g = gb; g < ge; g++) {
+                const int pb = uni(groups[g].prod_begin), np = uni(groups[g].prod_end) - pb;
+                const int cb = uni(groups[g].coef_begin), mask = uni(groups[g].slot_mask);
+                float sr[kMaxSlots][4], si[kMaxSlots][4];
+#pragma unroll
+                for (int k = 0; k < kMaxSlots; k++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) sr[k][q] = si[k][q] = 0.f;
+                for (int t = 0; t < np; t++) {
+                    const int s1 = uni((int)prods[pb + t].s1), s2 = uni((int)prods[pb + t].s2);
+                    const bool conj1 = uni((int)prods[pb + t].conj1) != 0, conj2 = uni((int)prods[pb + t].conj2) != 0;
+                    float c[kMaxSlots];
+#pragma unroll
+                    for (int k = 0; k < kMaxSlots; k++) c[k] = ((mask >> k) & 1) ? uni(coef[cb + k * np + t]) : 0.f;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const float *Ap = Ast + (4 * kq + q) * rowlen;
+                        const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * s1);
+                        const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * s2);
+                        const float xi = conj1 ? -x.y : x.y;
+                        const float yi = conj2 ? -y.y : y.y;
+                        const float pr = x.x * y.x - xi * yi;
+                        const float pi = x.x * yi + xi * y.x;
+#pragma unroll
+                        for (int k = 0; k < kMaxSlots; k++) {
+                            if ((mask >> k) & 1) {
+                                sr[k][q] += c[k] * pr;
+                                si[k][q] += c[k] * pi;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kMaxSlots; k++) {
+                    if (!((mask >> k) & 1)) continue;
+                    const int s3 = uni((int)groups[g].s3[k]);
+                    const int part = uni(pairs[pp].part[k]);
+                    float Av[8], Bv[8];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int p = 4 * kq + q;
+                        const float wp = wst[p];
+                        const float2 sv = rowok ? make_float2(sr[k][q] * wp, si[k][q] * wp) : make_float2(0.f, 0.f);
+                        float a3r = 0.f, a3i = 0.f;
+                        if (colok) {
+                            const float2 v = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * st2 + 2 * s3);
+                            a3r = v.x;
+                            a3i = v.y;
+                        }
+                        part_operands(part, sv, a3r, a3i, Av[2 * q], Bv[2 * q], Av[2 * q + 1], Bv[2 * q + 1]);
+                    }
+                    v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                    double unscale;
+                    mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+                    for (int v = 0; v < 4; v++) acc[js][k][v] += (double)cc[v] * unscale;
+                }
+            }
+        }
+    }
+    // per-block partials in the term-by-term layout: partial[rb][lam * mtiles + tile][16][16]
+#pragma unroll
+    for (int js = 0; js < 2; js++) {
+        const int job = jobs[js];
+        if (job < 0) continue;
+        const int pp = uni(job / a.mtiles);
+        const int tile = uni(job - pp * a.mtiles);
+        const int nslot = uni(pairs[pp].nslot);
+#pragma unroll
+        for (int k = 0; k < kMaxSlots; k++) {
+            if (k >= nslot) break;
+            const int ojob = uni(pairs[pp].lam[k]) * a.mtiles + tile;
+            double *dst = a.partial + ((size_t)rb * njobs + ojob) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc[js][k][v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // N = 3: job = (Lambda, part); part 0: Re, 1: Im (D = 2 only)
 // ---------------------------------------------------------------------------
 template <int PREC>
@@ -436,6 +593,8 @@ int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam
 
 int couple_jobs_per_block() { return 4 * kJobsPerWave; }
 
+int couple_ftask_groups(int nftasks) { return (nftasks + 3) / 4; }
+
 int couple_nblocks(int njobs, int nrb)
 {
     const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
@@ -447,7 +606,19 @@ hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int n
                                 hipStream_t s)
 {
     const int lds = couple_lds(a);
-    const int nblk = couple_nblocks(njobs, a.n_rowblocks);
+    int nblk = couple_nblocks(njobs, a.n_rowblocks);
+    if (N == 4 && a.fpairs) {
+        const int ntg = couple_ftask_groups(a.nftasks);
+        nblk = ntg * ((a.n_rowblocks + kXcd - 1) / kXcd) * kXcd;
+        const int lds_f = (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4;
+        switch (precision) {
+        case 0: return launch_with_lds(k_couple4f<0>, nblk, lds_f, s, a, njobs);
+        case 1: return launch_with_lds(k_couple4f<1>, nblk, lds_f, s, a, njobs);
+        case 2: return launch_with_lds(k_couple4f<2>, nblk, lds_f, s, a, njobs);
+        case 3: return launch_with_lds(k_couple4f<3>, nblk, lds_f, s, a, njobs);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (N == 4) {
         switch (precision) {
         case 0: return launch_with_lds(k_couple4<0>, nblk, lds, s, a, njobs, nparts);

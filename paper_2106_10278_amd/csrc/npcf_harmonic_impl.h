@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             const int pos = valid ? __popcll(lt) + rank_in_mask(same) : 64;  // column 64: no pair
 
             // staged rows [0, rows) of chunk k: lanes over rows; each bin's run of
-            // sorted columns summed in FP32 (two interleaved partial sums) and
+            // sorted columns summed in FP32 (four interleaved partial sums) and
             // added to the FP64 accumulator
             auto reduce = [&](int k, int rows) {
                 NPCF_WAVE_SYNC();
@@ -283,14 +283,26 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                         for (int t = 0; t < 4; t++) mb &= ((b >> t) & 1) ? Bk[t] : ~Bk[t];
                         const int cnt = __popcll(mb);
                         if (cnt) {
-                            float s0 = 0.f, s1 = 0.f;
+                            // eight columns in flight per step (the loads, not the
+                            // adds, set the pace), four partial sums
+                            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
                             int t = j0;
-                            for (; t + 1 < j0 + cnt; t += 2) {
+                            const int te = j0 + cnt;
+                            for (; t + 7 < te; t += 8) {
+                                float x[8];
+#pragma unroll
+                                for (int q = 0; q < 8; q++) x[q] = srow[t + q];
+                                s0 += x[0] + x[4];
+                                s1 += x[1] + x[5];
+                                s2 += x[2] + x[6];
+                                s3 += x[3] + x[7];
+                            }
+                            for (; t + 1 < te; t += 2) {
                                 s0 += srow[t];
                                 s1 += srow[t + 1];
                             }
-                            if (t < j0 + cnt) s0 += srow[t];
-                            acc[k * kMaxBins + b] += (double)(s0 + s1);
+                            if (t < te) s2 += srow[t];
+                            acc[k * kMaxBins + b] += (double)((s0 + s1) + (s2 + s3));
                             j0 += cnt;
                         }
                     }

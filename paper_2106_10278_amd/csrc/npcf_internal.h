@@ -75,6 +75,30 @@ struct HarmArgs {
 };
 
 // ---------------------------------------------------------------------------
+// Factorised N = 4, D = 3 coupling.  For a pair (l1, l2) and m3 >= 0 the
+// products P_{m1} = op(a_{l1 |m1|}[b1]) op(a_{l2 |m2|}[b2]) (m2 = -m1 - m3) are
+// shared by every l3 of the pair; S_{l3} = sum_{m1} coef(l3, m1) P_{m1} for each
+// output slot (one slot per l3 of the pair, in increasing l3).
+constexpr int kMaxSlots = 6;   // l3 values of one (l1, l2) pair at lmax <= 10 is at most 11; 6 covers lmax <= 5
+struct FProd {
+    int16_t s1, s2;      // stored state indices
+    int8_t conj1, conj2;
+    int16_t pad;
+};
+struct FGroup {          // one (pair, m3)
+    int prod_begin, prod_end;
+    int coef_begin;      // coef[coef_begin + slot * nprod + (t - prod_begin)]
+    int slot_mask;       // slots with l3 >= m3
+    int16_t s3[kMaxSlots];  // state of leg 3 for each slot: (l3, m3)
+};
+struct FPair {
+    int grp_begin, grp_end;
+    int nslot;
+    int lam[kMaxSlots];  // Lambda index of each slot
+    int part[kMaxSlots]; // 0: Re, 1: Im
+};
+
+// ---------------------------------------------------------------------------
 // Coupling stage arguments.
 // ---------------------------------------------------------------------------
 // One coupling term of a (Lambda, group) GEMM K-slice: S += coef * op1(a[s1]) * op2(a[s2]).
@@ -118,6 +142,13 @@ struct CoupleArgs {
     // straddle two catalogues); nullptr: blocks of rows_per_block rows
     const int *rb_begin;
     const int *rb_end;
+    // factorised N = 4, D = 3 (nullptr: term-by-term kernel)
+    const FPair *fpairs;
+    const FGroup *fgroups;
+    const FProd *fprods;
+    const float *fcoef;
+    const int2 *ftasks;          // per wave: two jobs (pair * mtiles + tile), -1 for none
+    int nftasks;
 };
 
 // ---------------------------------------------------------------------------
@@ -155,6 +186,7 @@ int harmonic_lds_bytes_d3(int L);
 int harmonic_lds_bytes_d4(int L);
 int couple_njobs(int N, int nlam, int nparts, int mtiles);
 int couple_jobs_per_block();
+int couple_ftask_groups(int nftasks);
 int couple_nblocks(int njobs, int nrb);
 hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
                                 hipStream_t s);
@@ -187,6 +219,12 @@ struct Tables {
     float e2lo_f = 0.f, e2hi_f = 0.f;
     std::vector<double> vb;            // bin volumes
     int lam0 = 0;
+    // factorised N = 4, D = 3 coupling (empty otherwise)
+    std::vector<FPair> fpairs;
+    std::vector<FGroup> fgroups;
+    std::vector<FProd> fprods;
+    std::vector<float> fcoef;
+    std::vector<int2> ftasks;
 };
 
 // Validates cfg and fills the tables; returns NPCF_OK or an error code and a message.

@@ -51,6 +51,7 @@ def _case(D, N, lmax, n, seed, box, rmax, nbins, weights="mixed"):
 TINY = {
     "D3N3": (3, 3, 4, 400, 1, 20.0, 5.0, 4),
     "D3N4": (3, 4, 3, 300, 2, 16.0, 4.5, 4),
+    "D3N4L6": (3, 4, 6, 200, 6, 16.0, 4.5, 3),   # lmax > 5: the term-by-term coupling kernel
     "D2N4": (2, 4, 4, 400, 3, 12.0, 3.0, 5),
     "D2N3": (2, 3, 5, 400, 4, 12.0, 3.0, 5),
     "D4N3": (4, 3, 3, 500, 5, 10.0, 3.5, 4),
@@ -231,3 +232,22 @@ def test_autotune_keeps_results():
     ref, pairs_ref, _ = oracle_reported(wl)
     assert pairs == pairs_ref
     _check(got, ref, "plain", condition_scale(wl), f"autotuned s={t['cell_subdiv']} b={t['couple_block']}", strict=False)
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6"])
+def test_factorised_coupling_matches_terms(precision, monkeypatch):
+    """D = 3, N = 4: the factorised coupling kernel (products shared by every l3
+    of a pair) and the term-by-term kernel (NPCF_COUPLING=terms) agree with each
+    other and with the oracle."""
+    wl = _case(3, 4, 5, 300, 61, 16.0, 4.5, 4)
+    print(f"[case] factorised vs terms {precision}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    scale = condition_scale(wl)
+    fac, pf, _ = gpu_run(wl, precision=precision)
+    monkeypatch.setenv("NPCF_COUPLING", "terms")
+    trm, pt, _ = gpu_run(wl, precision=precision)
+    assert pf == pt == pairs_ref
+    _check(fac, ref, precision, scale, "factorised", strict=False)
+    _check(trm, ref, precision, scale, "terms", strict=False)
+    cerr, _ = conditioned_error(fac, trm, scale)
+    assert cerr <= 2 * TOL[precision]
