@@ -37,7 +37,9 @@ namespace harm {
 constexpr int kQCap = 128;          // pair queue entries per wave
 constexpr int kSegCap = 128;        // candidate segments per row chunk
 constexpr int kMaxBucket = 1024;
-constexpr int kTableBytes = (kMaxBins + 1) * 8 + kMaxBucket;
+// LDS regions start on 16-byte boundaries: the pair queue is read and
+// written as 16-byte records (misaligned, each access stalls)
+constexpr int kTableBytes = ((kMaxBins + 1) * 8 + kMaxBucket + 15) / 16 * 16;
 
 #define NPCF_WAVE_SYNC()                                       \
     do {                                                       \
@@ -92,7 +94,7 @@ struct Cfg {
     static constexpr int SSTR = 65;                            // staging row stride (floats)
     static constexpr int NK = NCH * kMaxBins;                  // FP64 accumulators per lane
     static constexpr int QWORDS = (D == 4) ? 5 : 4;            // queue words per pair
-    static constexpr int WAVE_BYTES = kQCap * QWORDS * 4 + kSegCap * 8 + E * SSTR * 4;
+    static constexpr int WAVE_BYTES = (kQCap * QWORDS * 4 + kSegCap * 8 + E * SSTR * 4 + 15) / 16 * 16;
 };
 
 __device__ __forceinline__ unsigned lane_id()
