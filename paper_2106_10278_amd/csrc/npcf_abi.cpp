@@ -66,6 +66,7 @@ struct npcf_plan_s {
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
     bool term_coupling = false;  // force the term-by-term N = 4 kernel (NPCF_COUPLING=terms)
+    bool bin_queues = false;     // harmonic kernel: per-bin queues or bin-sorted staging (NPCF_HARMONIC=queue|stage)
     bool failed = false;
 
     DevAlloc mem;
@@ -256,6 +257,7 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
     a.pairs = pairs;
     a.work = p->work;
     a.periodic = p->cfg.periodic;
+    a.bin_queues = p->bin_queues ? 1 : 0;
     return a;
 }
 
@@ -265,8 +267,11 @@ hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t 
 {
     hipError_t e = launch_fill_u32(a.work, 0u, 1, s);
     if (e != hipSuccess) return e;
-    int grid = p->ncu * 8;
-    const int64_t need = ((int64_t)a.nrows + 3) / 4;
+    // persistent grid: 8 blocks of 4 waves (staging kernel) or 16 blocks of 2
+    // waves (bin-queue kernel) per CU, rows handed out dynamically
+    const int wpb = a.bin_queues ? 2 : 4;
+    int grid = p->ncu * 32 / wpb;
+    const int64_t need = ((int64_t)a.nrows + wpb - 1) / wpb;
     if (grid > need) grid = (int)std::max<int64_t>(1, need);
     switch (p->D) {
     case 2: return launch_harmonic_d2(p->L, a, grid, s);
@@ -678,6 +683,9 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     {
         const char *cv = std::getenv("NPCF_COUPLING");
         p->term_coupling = cv && std::strcmp(cv, "terms") == 0;
+        const char *hv = std::getenv("NPCF_HARMONIC");
+        if (hv && std::strcmp(hv, "stage") == 0) p->bin_queues = false;
+        if (hv && std::strcmp(hv, "queue") == 0) p->bin_queues = true;
     }
     {
         const int L = p->L;

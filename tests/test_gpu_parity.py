@@ -251,3 +251,23 @@ def test_factorised_coupling_matches_terms(precision, monkeypatch):
     _check(trm, ref, precision, scale, "terms", strict=False)
     cerr, _ = conditioned_error(fac, trm, scale)
     assert cerr <= 2 * TOL[precision]
+
+
+@pytest.mark.parametrize("name", ["D3N4", "D2N4", "D4N3", "D3N4L6"])
+def test_harmonic_kernels_agree(name, monkeypatch):
+    """The two harmonic-stage kernels (bin-sorted staging, NPCF_HARMONIC=stage;
+    per-bin queues, NPCF_HARMONIC=queue) give the same pair counts and agree
+    with each other and with the oracle."""
+    wl = _case(*TINY[name])
+    print(f"[case] harmonic kernels {name}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    scale = condition_scale(wl)
+    monkeypatch.setenv("NPCF_HARMONIC", "stage")
+    st, ps, _ = gpu_run(wl)
+    monkeypatch.setenv("NPCF_HARMONIC", "queue")
+    qu, pq, _ = gpu_run(wl)
+    assert ps == pq == pairs_ref
+    _check(st, ref, "plain", scale, f"{name} staging", strict=False)
+    _check(qu, ref, "plain", scale, f"{name} queues", strict=False)
+    cerr, _ = conditioned_error(st, qu, scale)
+    assert cerr <= 2e-6
