@@ -215,9 +215,11 @@ npcf_status npcf_stage_ms(npcf_plan_t plan, double *ms3);
 /* Static description of a status code (never NULL). */
 const char *npcf_strerror(npcf_status status);
 
-/* The last HIP failure behind an NPCF_E_DEVICE or NPCF_E_NOMEM on the
- * calling thread: the HIP error name and code and the failing call ("" if
- * none; never NULL; valid until the next failure on this thread). */
+/* Detail of the last failure on the calling thread: for NPCF_E_DEVICE or
+ * NPCF_E_NOMEM the HIP error name and code and the failing call; for an
+ * NPCF_E_UNSUPPORTED from npcf_plan the setting it rejected, where one is
+ * named ("" if none; never NULL; npcf_plan clears it on entry; valid until
+ * the next failure on this thread). */
 const char *npcf_last_error_detail(void);
 
 /* Library version string (never NULL). */

@@ -31,7 +31,7 @@ class NPCFError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
         detail = ""
-        if status in (NPCF_E_DEVICE, NPCF_E_NOMEM):
+        if status in (NPCF_E_DEVICE, NPCF_E_NOMEM, NPCF_E_UNSUPPORTED):
             detail = load_library().npcf_last_error_detail().decode()
         super().__init__(f"{what}: {strerror(status)} (status {status})" + (f" [{detail}]" if detail else ""))
 

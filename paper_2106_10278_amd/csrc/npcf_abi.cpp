@@ -66,7 +66,6 @@ struct npcf_plan_s {
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
     bool term_coupling = false;  // force the term-by-term N = 4 kernel (NPCF_COUPLING=terms)
-    bool bin_queues = false;     // harmonic kernel: per-bin queues or bin-sorted staging (NPCF_HARMONIC=queue|stage)
     bool failed = false;
 
     DevAlloc mem;
@@ -257,7 +256,6 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
     a.pairs = pairs;
     a.work = p->work;
     a.periodic = p->cfg.periodic;
-    a.bin_queues = p->bin_queues ? 1 : 0;
     return a;
 }
 
@@ -267,11 +265,9 @@ hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t 
 {
     hipError_t e = launch_fill_u32(a.work, 0u, 1, s);
     if (e != hipSuccess) return e;
-    // persistent grid: 8 blocks of 4 waves (staging kernel) or 16 blocks of 2
-    // waves (bin-queue kernel) per CU, rows handed out dynamically
-    const int wpb = a.bin_queues ? 2 : 4;
-    int grid = p->ncu * 32 / wpb;
-    const int64_t need = ((int64_t)a.nrows + wpb - 1) / wpb;
+    // persistent grid: 8 blocks of 4 waves per CU, rows handed out dynamically
+    int grid = p->ncu * 8;
+    const int64_t need = ((int64_t)a.nrows + 3) / 4;
     if (grid > need) grid = (int)std::max<int64_t>(1, need);
     switch (p->D) {
     case 2: return launch_harmonic_d2(p->L, a, grid, s);
@@ -634,6 +630,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
 {
     if (!out) return NPCF_E_INVALID;
     *out = nullptr;
+    g_last_error[0] = '\0';
     if (!cfg || max_points < 1 || max_points > (int64_t)INT32_MAX) return NPCF_E_INVALID;
     npcf_plan_s *p = new (std::nothrow) npcf_plan_s();
     if (!p) return NPCF_E_NOMEM;
@@ -683,9 +680,15 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     {
         const char *cv = std::getenv("NPCF_COUPLING");
         p->term_coupling = cv && std::strcmp(cv, "terms") == 0;
+        // the per-bin queue harmonic kernel is switched off (its first run
+        // did not finish; no cause found yet): asking for it is an error
         const char *hv = std::getenv("NPCF_HARMONIC");
-        if (hv && std::strcmp(hv, "stage") == 0) p->bin_queues = false;
-        if (hv && std::strcmp(hv, "queue") == 0) p->bin_queues = true;
+        if (hv && std::strcmp(hv, "stage") != 0) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "NPCF_HARMONIC=%s: only 'stage' (bin-sorted staging) is available", hv);
+            delete p;
+            return NPCF_E_UNSUPPORTED;
+        }
     }
     {
         const int L = p->L;

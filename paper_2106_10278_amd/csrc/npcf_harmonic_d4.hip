@@ -1,19 +1,18 @@
 // Instantiations of the harmonic-stage kernel for D = 4 (lmax 0..6).
-#include <algorithm>
-#include "npcf_harmonic_bq.h"
+#include "npcf_harmonic_impl.h"
 
 namespace npcf {
 
 hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s)
 {
     switch (L) {
-    case 0: return a.bin_queues ? harm::launch_dl_bq<4, 0>(a, grid, s) : harm::launch_dl<4, 0>(a, grid, s);
-    case 1: return a.bin_queues ? harm::launch_dl_bq<4, 1>(a, grid, s) : harm::launch_dl<4, 1>(a, grid, s);
-    case 2: return a.bin_queues ? harm::launch_dl_bq<4, 2>(a, grid, s) : harm::launch_dl<4, 2>(a, grid, s);
-    case 3: return a.bin_queues ? harm::launch_dl_bq<4, 3>(a, grid, s) : harm::launch_dl<4, 3>(a, grid, s);
-    case 4: return a.bin_queues ? harm::launch_dl_bq<4, 4>(a, grid, s) : harm::launch_dl<4, 4>(a, grid, s);
-    case 5: return a.bin_queues ? harm::launch_dl_bq<4, 5>(a, grid, s) : harm::launch_dl<4, 5>(a, grid, s);
-    case 6: return a.bin_queues ? harm::launch_dl_bq<4, 6>(a, grid, s) : harm::launch_dl<4, 6>(a, grid, s);
+    case 0: return harm::launch_dl<4, 0>(a, grid, s);
+    case 1: return harm::launch_dl<4, 1>(a, grid, s);
+    case 2: return harm::launch_dl<4, 2>(a, grid, s);
+    case 3: return harm::launch_dl<4, 3>(a, grid, s);
+    case 4: return harm::launch_dl<4, 4>(a, grid, s);
+    case 5: return harm::launch_dl<4, 5>(a, grid, s);
+    case 6: return harm::launch_dl<4, 6>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -21,13 +20,13 @@ hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s)
 int harmonic_lds_bytes_d4(int L)
 {
     switch (L) {
-    case 0: return std::max(harm::lds_bytes<4, 0>(), harm::lds_bytes_bq<4, 0>());
-    case 1: return std::max(harm::lds_bytes<4, 1>(), harm::lds_bytes_bq<4, 1>());
-    case 2: return std::max(harm::lds_bytes<4, 2>(), harm::lds_bytes_bq<4, 2>());
-    case 3: return std::max(harm::lds_bytes<4, 3>(), harm::lds_bytes_bq<4, 3>());
-    case 4: return std::max(harm::lds_bytes<4, 4>(), harm::lds_bytes_bq<4, 4>());
-    case 5: return std::max(harm::lds_bytes<4, 5>(), harm::lds_bytes_bq<4, 5>());
-    case 6: return std::max(harm::lds_bytes<4, 6>(), harm::lds_bytes_bq<4, 6>());
+    case 0: return harm::lds_bytes<4, 0>();
+    case 1: return harm::lds_bytes<4, 1>();
+    case 2: return harm::lds_bytes<4, 2>();
+    case 3: return harm::lds_bytes<4, 3>();
+    case 4: return harm::lds_bytes<4, 4>();
+    case 5: return harm::lds_bytes<4, 5>();
+    case 6: return harm::lds_bytes<4, 6>();
     default: return -1;
     }
 }

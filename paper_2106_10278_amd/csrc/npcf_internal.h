@@ -72,7 +72,6 @@ struct HarmArgs {
     const int64_t *cat_begin;
     int ncat;
     int64_t ncell_cat;
-    int bin_queues;           // 1: bin-queue kernel (one bin per batch), 0: bin-sorted staging
 };
 
 // ---------------------------------------------------------------------------

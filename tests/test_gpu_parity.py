@@ -253,6 +253,9 @@ def test_factorised_coupling_matches_terms(precision, monkeypatch):
     assert cerr <= 2 * TOL[precision]
 
 
+@pytest.mark.skip(reason="the per-bin queue harmonic kernel is switched off: its first GPU run "
+                         "did not finish on the 300-point D=3 N=4 case and no cause has been "
+                         "found by reading its code; NPCF_HARMONIC=queue is rejected")
 @pytest.mark.parametrize("name", ["D3N4", "D2N4", "D4N3", "D3N4L6"])
 def test_harmonic_kernels_agree(name, monkeypatch):
     """The two harmonic-stage kernels (bin-sorted staging, NPCF_HARMONIC=stage;
@@ -271,3 +274,13 @@ def test_harmonic_kernels_agree(name, monkeypatch):
     _check(qu, ref, "plain", scale, f"{name} queues", strict=False)
     cerr, _ = conditioned_error(st, qu, scale)
     assert cerr <= 2e-6
+
+
+def test_harmonic_queue_kernel_rejected(monkeypatch):
+    """NPCF_HARMONIC names a kernel that is switched off: plan creation fails
+    with NPCF_E_UNSUPPORTED before anything is launched."""
+    from paper_2106_10278_amd import NPCF, NPCFError
+    wl = _case(*TINY["D3N4"])
+    monkeypatch.setenv("NPCF_HARMONIC", "queue")
+    with pytest.raises(NPCFError, match="NPCF_HARMONIC"):
+        NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, max_points=wl.pos.shape[1])
