@@ -19,10 +19,11 @@
 //    FP64 and rounded to FP32, harmonics by Gegenbauer recurrences in FP32
 //    registers;
 //  - scatter without atomics or collisions: each lane takes its position in
-//    the batch sorted by bin (bit-plane ballots) and writes every harmonic it
-//    emits into column `position` of an LDS staging array whose rows follow
-//    the emission order (row stride 65 floats: the writes of one row and the
-//    transposed reads below both touch 64 distinct banks);
+//    the batch sorted by bin (bit-plane ballots; per-bin masks and counts on
+//    the scalar unit) and writes every harmonic it emits into column
+//    `position` of an LDS staging array whose rows follow the emission order
+//    (row stride 65 floats: the writes of one row and the transposed reads
+//    below both touch distinct banks);
 //  - reduction: every E emitted rows (E <= 64) the lanes switch to rows, sum
 //    each bin's contiguous run of columns in FP32 and add it to FP64
 //    accumulators held in registers; the primary's row of a is written once.
@@ -94,7 +95,11 @@ struct Cfg {
     static constexpr int SSTR = 65;                            // staging row stride (floats)
     static constexpr int NK = NCH * kMaxBins;                  // FP64 accumulators per lane
     static constexpr int QWORDS = (D == 4) ? 5 : 4;            // queue words per pair
-    static constexpr int WAVE_BYTES = (kQCap * QWORDS * 4 + kSegCap * 8 + E * SSTR * 4 + 15) / 16 * 16;
+    static constexpr int STAGE_BYTES = (E * SSTR * 4 + 15) / 16 * 16;  // per wave
+    static constexpr int WAVE_BYTES = (kQCap * QWORDS * 4 + kSegCap * 8 + 15) / 16 * 16;  // queue, segments
+    // LDS: the four waves' staging rows first (small immediate offsets for the
+    // reduction's reads), then the bin tables, then each wave's queue and segments
+    static constexpr int LDS_BYTES = 4 * STAGE_BYTES + kTableBytes + 4 * WAVE_BYTES;
 };
 
 __device__ __forceinline__ unsigned lane_id()
@@ -147,16 +152,17 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     const int lane = (int)lane_id();
     const int wave = threadIdx.x >> 6;
 
-    double *e2 = reinterpret_cast<double *>(smem);
-    uint8_t *btab = reinterpret_cast<uint8_t *>(smem + (kMaxBins + 1) * 8);
+    char *tabs = smem + 4 * C::STAGE_BYTES;
+    double *e2 = reinterpret_cast<double *>(tabs);
+    uint8_t *btab = reinterpret_cast<uint8_t *>(tabs + (kMaxBins + 1) * 8);
     for (int t = threadIdx.x; t <= nb; t += blockDim.x) e2[t] = a.e2[t];
     for (int t = threadIdx.x; t < a.nbucket; t += blockDim.x) btab[t] = a.bucket_bin[t];
 
-    char *wb = smem + kTableBytes + wave * C::WAVE_BYTES;
+    char *wb = tabs + kTableBytes + wave * C::WAVE_BYTES;
     int4 *q4 = reinterpret_cast<int4 *>(wb);                                     // [kQCap]
     float *qwx = reinterpret_cast<float *>(wb + kQCap * 16);                     // [kQCap] (D = 4 weight)
     uint2 *segs = reinterpret_cast<uint2 *>(wb + kQCap * C::QWORDS * 4);         // [kSegCap]
-    float *stage = reinterpret_cast<float *>(wb + kQCap * C::QWORDS * 4 + kSegCap * 8);  // [E][SSTR]
+    float *stage = reinterpret_cast<float *>(smem + wave * C::STAGE_BYTES);  // [E][SSTR]
     __syncthreads();
 
     // this lane reduces staging row `lane` of every chunk k, i.e. emitted value
@@ -255,20 +261,40 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 #pragma unroll
             for (int k = 0; k < D; k++) u[k] = valid ? (float)(v[k] * rinv) : 0.f;
 
-            // position of this pair in the batch sorted by bin: lanes with a
-            // smaller bin, plus lanes of the same bin below this one (bins < 16:
-            // compare four bit planes, most significant first)
+            // position of this pair in the batch sorted by bin.  Per bin b the
+            // lanes holding it, M_b, follow from four bit-plane ballots with
+            // scalar operations; the bin's run of columns starts at the number
+            // of valid lanes of smaller bins, and a lane of bin b takes
+            // start_b + (lanes of M_b below it).  Lanes without a pair take the
+            // columns after the last valid one (they stage zeros).  The scalar
+            // side keeps each bin's count for the reduction.
             unsigned long long Bk[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) Bk[k] = ballot(valid && ((bin >> k) & 1));
-            unsigned long long same = vm, lt = 0ull;
+            for (int k = 0; k < 4; k++) Bk[k] = ballot(((bin >> k) & 1) != 0);  // invalid lanes hold bin 0
+            const int nvalid = __popcll(vm);
+            int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(~vm >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)~vm, (unsigned)nvalid));
+            int bcnt[kMaxBins];
+            {
+                int run = 0;
 #pragma unroll
-            for (int k = 3; k >= 0; k--) {
-                const unsigned long long mk = 0ull - (unsigned long long)((bin >> k) & 1);
-                lt |= same & ~Bk[k] & mk;
-                same &= Bk[k] ^ ~mk;
+                for (int b = 0; b < kMaxBins; b++) {
+                    bcnt[b] = 0;
+                    if (b < nb) {
+                        unsigned long long mb = vm;
+#pragma unroll
+                        for (int t = 0; t < 4; t++) mb &= ((b >> t) & 1) ? Bk[t] : ~Bk[t];
+                        const int cnt = __popcll(mb);
+                        if (cnt) {
+                            const int cand = (int)__builtin_amdgcn_mbcnt_hi(
+                                (unsigned)(mb >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mb, (unsigned)run));
+                            if (__builtin_amdgcn_inverse_ballot_w64(mb)) pos = cand;
+                            run += cnt;
+                            bcnt[b] = cnt;
+                        }
+                    }
+                }
             }
-            const int pos = valid ? __popcll(lt) + rank_in_mask(same) : 64;  // column 64: no pair
 
             // staged rows [0, rows) of chunk k: lanes over rows; each bin's run of
             // sorted columns summed in FP32 (four interleaved partial sums) and
@@ -279,34 +305,29 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                 int j0 = 0;
 #pragma unroll
                 for (int b = 0; b < kMaxBins; b++) {
-                    if (b < nb) {
-                        unsigned long long mb = vm;
+                    const int cnt = bcnt[b];
+                    if (cnt) {
+                        // eight columns in flight per step (the loads, not the
+                        // adds, set the pace), four partial sums
+                        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                        int t = j0;
+                        const int te = j0 + cnt;
+                        for (; t + 7 < te; t += 8) {
+                            float x[8];
 #pragma unroll
-                        for (int t = 0; t < 4; t++) mb &= ((b >> t) & 1) ? Bk[t] : ~Bk[t];
-                        const int cnt = __popcll(mb);
-                        if (cnt) {
-                            // eight columns in flight per step (the loads, not the
-                            // adds, set the pace), four partial sums
-                            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                            int t = j0;
-                            const int te = j0 + cnt;
-                            for (; t + 7 < te; t += 8) {
-                                float x[8];
-#pragma unroll
-                                for (int q = 0; q < 8; q++) x[q] = srow[t + q];
-                                s0 += x[0] + x[4];
-                                s1 += x[1] + x[5];
-                                s2 += x[2] + x[6];
-                                s3 += x[3] + x[7];
-                            }
-                            for (; t + 1 < te; t += 2) {
-                                s0 += srow[t];
-                                s1 += srow[t + 1];
-                            }
-                            if (t < te) s2 += srow[t];
-                            acc[k * kMaxBins + b] += (double)((s0 + s1) + (s2 + s3));
-                            j0 += cnt;
+                            for (int q = 0; q < 8; q++) x[q] = srow[t + q];
+                            s0 += x[0] + x[4];
+                            s1 += x[1] + x[5];
+                            s2 += x[2] + x[6];
+                            s3 += x[3] + x[7];
                         }
+                        for (; t + 1 < te; t += 2) {
+                            s0 += srow[t];
+                            s1 += srow[t + 1];
+                        }
+                        if (t < te) s2 += srow[t];
+                        acc[k * kMaxBins + b] += (double)((s0 + s1) + (s2 + s3));
+                        j0 = te;
                     }
                 }
                 NPCF_WAVE_SYNC();  // the next chunk overwrites the staging rows
@@ -522,7 +543,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 }
 
 template <int D, int L>
-int lds_bytes() { return kTableBytes + 4 * Cfg<D, L>::WAVE_BYTES; }
+int lds_bytes() { return Cfg<D, L>::LDS_BYTES; }
 
 template <int D, int L>
 hipError_t launch_dl(const HarmArgs &a, int grid, hipStream_t s)
