@@ -147,6 +147,10 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     constexpr int SLOTS = C::SLOTS;
     constexpr int E = C::E;
     constexpr int NE = C::NE;
+    // candidate batches in flight in phase A: D = 4 rows of cells hold fewer
+    // candidates per segment, so the loads of one batch alone do not cover
+    // the latency (measured: c5 179 -> 177 ms with two; c2 165 -> 166 ms)
+    constexpr int kPrefetch = D == 4 ? 2 : 1;
     extern __shared__ __align__(16) char smem[];
     const int nb = a.nb;
     const int lane = (int)lane_id();
@@ -444,24 +448,67 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             const int nseg = n0 + __popcll(m1);
             NPCF_WAVE_SYNC();
 
-            for (int si = 0; si < nseg; si++) {
-                const uint2 sg = segs[si];
-                const uint32_t s0 = sg.x, s1 = sg.y;
-                uint4 cur = make_uint4(0, 0, 0, 0);
-                float curw = 0.f;
-                if (s0 + (uint32_t)lane < s1) {
-                    cur = a.rec[s0 + lane];
-                    if (D == 4) curw = a.w[s0 + lane];
-                }
-                for (uint32_t b0 = s0; b0 < s1; b0 += 64) {
-                    // prefetch the next batch of this segment
-                    const uint32_t kn = b0 + 64 + (uint32_t)lane;
-                    uint4 nxt = make_uint4(0, 0, 0, 0);
-                    float nxtw = 0.f;
-                    if (kn < s1) {
-                        nxt = a.rec[kn];
-                        if (D == 4) nxtw = a.w[kn];
+            // candidate batches of 64 over the chunk's segments, streamed
+            // through kPrefetch loads in flight (across segment ends): batch p
+            // holds records [pb[p], pe[p]) of one segment, pb == pe past the end
+            int ci = 0;
+            uint32_t cb = 0, ce = 0;
+            if (nseg > 0) {
+                const uint2 sg = segs[0];
+                cb = sg.x;
+                ce = sg.y;
+            }
+            auto advance = [&]() {
+                cb += 64;
+                if (cb >= ce) {
+                    ci++;
+                    if (ci < nseg) {
+                        const uint2 sg = segs[ci];
+                        cb = sg.x;
+                        ce = sg.y;
+                    } else {
+                        cb = 0;
+                        ce = 0;
                     }
+                }
+            };
+            uint4 pr[kPrefetch];
+            float pw[kPrefetch];
+            uint32_t pb[kPrefetch], pe[kPrefetch];
+#pragma unroll
+            for (int p = 0; p < kPrefetch; p++) {
+                pb[p] = cb;
+                pe[p] = ce;
+                pr[p] = make_uint4(0, 0, 0, 0);
+                pw[p] = 0.f;
+                if (cb + (uint32_t)lane < ce) {
+                    pr[p] = a.rec[cb + lane];
+                    if (D == 4) pw[p] = a.w[cb + lane];
+                }
+                advance();
+            }
+            while (pb[0] < pe[0]) {
+                const uint4 cur = pr[0];
+                const float curw = pw[0];
+                const uint32_t b0 = pb[0], s1 = pe[0];
+                // shift the pipeline and issue the next batch's loads
+#pragma unroll
+                for (int p = 0; p + 1 < kPrefetch; p++) {
+                    pr[p] = pr[p + 1];
+                    pw[p] = pw[p + 1];
+                    pb[p] = pb[p + 1];
+                    pe[p] = pe[p + 1];
+                }
+                pb[kPrefetch - 1] = cb;
+                pe[kPrefetch - 1] = ce;
+                pr[kPrefetch - 1] = make_uint4(0, 0, 0, 0);
+                pw[kPrefetch - 1] = 0.f;
+                if (cb + (uint32_t)lane < ce) {
+                    pr[kPrefetch - 1] = a.rec[cb + lane];
+                    if (D == 4) pw[kPrefetch - 1] = a.w[cb + lane];
+                }
+                advance();
+                {
                     bool inr = false;
                     int dq[D];
                     if (b0 + (uint32_t)lane < s1) {
@@ -514,8 +561,6 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                         qn = rest;
                         NPCF_WAVE_SYNC();
                     }
-                    cur = nxt;
-                    curw = nxtw;
                 }
             }
         }
