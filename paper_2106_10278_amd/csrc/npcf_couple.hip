@@ -306,6 +306,73 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(c
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
 
+// One group (pair, m3) of a job with its NA active slots (the first NA):
+// S of every slot for this lane's 16-row tile row and its four primaries of
+// the step, then one MFMA slice per slot, folded into the FP64 accumulators.
+template <int PREC, int NA>
+__device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int g, const float *Ast, const float *wst,
+                                               int rowlen, int st2, int kq, int n, int2 bb, bool rowok, bool colok,
+                                               double (&acc)[kMaxSlots][4])
+{
+    const auto pairs = as_const(a.fpairs);
+    const auto groups = as_const(a.fgroups);
+    const auto prods = as_const(a.fprods);
+    const auto coef = as_const(a.fcoef);
+    const int pb = uni(groups[g].prod_begin), np = uni(groups[g].prod_end) - pb;
+    const int cb = uni(groups[g].coef_begin);
+    float sr[NA][4], si[NA][4];
+#pragma unroll
+    for (int k = 0; k < NA; k++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) sr[k][q] = si[k][q] = 0.f;
+    for (int t = 0; t < np; t++) {
+        const int s1 = uni((int)prods[pb + t].s1), s2 = uni((int)prods[pb + t].s2);
+        const bool conj1 = uni((int)prods[pb + t].conj1) != 0, conj2 = uni((int)prods[pb + t].conj2) != 0;
+        float c[NA];
+#pragma unroll
+        for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + k * np + t]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const float *Ap = Ast + (4 * kq + q) * rowlen;
+            const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * s1);
+            const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * s2);
+            const float xi = conj1 ? -x.y : x.y;
+            const float yi = conj2 ? -y.y : y.y;
+            const float pr = x.x * y.x - xi * yi;
+            const float pi = x.x * yi + xi * y.x;
+#pragma unroll
+            for (int k = 0; k < NA; k++) {
+                sr[k][q] += c[k] * pr;
+                si[k][q] += c[k] * pi;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; k++) {
+        const int s3 = uni((int)groups[g].s3[k]);
+        const int part = uni(pairs[pp].part[k]);
+        float Av[8], Bv[8];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int p = 4 * kq + q;
+            const float wp = wst[p];
+            const float2 sv = rowok ? make_float2(sr[k][q] * wp, si[k][q] * wp) : make_float2(0.f, 0.f);
+            float a3r = 0.f, a3i = 0.f;
+            if (colok) {
+                const float2 v = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * st2 + 2 * s3);
+                a3r = v.x;
+                a3i = v.y;
+            }
+            part_operands(part, sv, a3r, a3i, Av[2 * q], Bv[2 * q], Av[2 * q + 1], Bv[2 * q + 1]);
+        }
+        v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+        double unscale;
+        mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+        for (int v = 0; v < 4; v++) acc[k][v] += (double)cc[v] * unscale;
+    }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
 {
@@ -322,21 +389,17 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
     const auto tasks = as_const(a.ftasks);
     const auto pairs = as_const(a.fpairs);
     const auto groups = as_const(a.fgroups);
-    const auto prods = as_const(a.fprods);
-    const auto coef = as_const(a.fcoef);
     int jobs[2] = {-1, -1};
     if (task < a.nftasks) {
         jobs[0] = uni(tasks[task].x);
         jobs[1] = uni(tasks[task].y);
     }
 
-    double acc[2][kMaxSlots][4];
+    double acc0[kMaxSlots][4], acc1[kMaxSlots][4];
 #pragma unroll
-    for (int js = 0; js < 2; js++)
+    for (int k = 0; k < kMaxSlots; k++)
 #pragma unroll
-        for (int k = 0; k < kMaxSlots; k++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) acc[js][k][v] = 0.0;
+        for (int v = 0; v < 4; v++) acc0[k][v] = acc1[k][v] = 0.0;
 
     int r_begin = rb * a.rows_per_block;
     int r_end = r_begin + a.rows_per_block;
@@ -353,10 +416,9 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
         __syncthreads();
         stage_rows(a, r0, r_end, Ast, wst);
         __syncthreads();
-#pragma unroll
-        for (int js = 0; js < 2; js++) {
-            const int job = jobs[js];
-            if (job < 0) continue;
+        // the wave's two jobs, each into its own accumulators
+        auto run_job = [&](int job, double (&acc)[kMaxSlots][4]) {
+            if (job < 0) return;
             const int pp = uni(job / a.mtiles);
             const int tile = uni(job - pp * a.mtiles);
             const int m = tile * 16 + n;
@@ -365,70 +427,22 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
             const bool colok = n < a.nb;
             const int gb = uni(pairs[pp].grp_begin), ge = uni(pairs[pp].grp_end);
             for (int g = gb; g < ge; g++) {
-                const int pb = uni(groups[g].prod_begin), np = uni(groups[g].prod_end) - pb;
-                const int cb = uni(groups[g].coef_begin), mask = uni(groups[g].slot_mask);
-                float sr[kMaxSlots][4], si[kMaxSlots][4];
-#pragma unroll
-                for (int k = 0; k < kMaxSlots; k++)
-#pragma unroll
-                    for (int q = 0; q < 4; q++) sr[k][q] = si[k][q] = 0.f;
-                for (int t = 0; t < np; t++) {
-                    const int s1 = uni((int)prods[pb + t].s1), s2 = uni((int)prods[pb + t].s2);
-                    const bool conj1 = uni((int)prods[pb + t].conj1) != 0, conj2 = uni((int)prods[pb + t].conj2) != 0;
-                    float c[kMaxSlots];
-#pragma unroll
-                    for (int k = 0; k < kMaxSlots; k++) c[k] = ((mask >> k) & 1) ? uni(coef[cb + k * np + t]) : 0.f;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const float *Ap = Ast + (4 * kq + q) * rowlen;
-                        const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * s1);
-                        const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * s2);
-                        const float xi = conj1 ? -x.y : x.y;
-                        const float yi = conj2 ? -y.y : y.y;
-                        const float pr = x.x * y.x - xi * yi;
-                        const float pi = x.x * yi + xi * y.x;
-#pragma unroll
-                        for (int k = 0; k < kMaxSlots; k++) {
-                            if ((mask >> k) & 1) {
-                                sr[k][q] += c[k] * pr;
-                                si[k][q] += c[k] * pi;
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < kMaxSlots; k++) {
-                    if (!((mask >> k) & 1)) continue;
-                    const int s3 = uni((int)groups[g].s3[k]);
-                    const int part = uni(pairs[pp].part[k]);
-                    float Av[8], Bv[8];
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const int p = 4 * kq + q;
-                        const float wp = wst[p];
-                        const float2 sv = rowok ? make_float2(sr[k][q] * wp, si[k][q] * wp) : make_float2(0.f, 0.f);
-                        float a3r = 0.f, a3i = 0.f;
-                        if (colok) {
-                            const float2 v = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * st2 + 2 * s3);
-                            a3r = v.x;
-                            a3i = v.y;
-                        }
-                        part_operands(part, sv, a3r, a3i, Av[2 * q], Bv[2 * q], Av[2 * q + 1], Bv[2 * q + 1]);
-                    }
-                    v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
-                    double unscale;
-                    mfma_k32<PREC>(Av, Bv, cc, unscale);
-#pragma unroll
-                    for (int v = 0; v < 4; v++) acc[js][k][v] += (double)cc[v] * unscale;
+                switch (uni(groups[g].nact)) {
+                case 1: couple4f_group<PREC, 1>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                case 2: couple4f_group<PREC, 2>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                case 3: couple4f_group<PREC, 3>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                case 4: couple4f_group<PREC, 4>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                case 5: couple4f_group<PREC, 5>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                default: couple4f_group<PREC, kMaxSlots>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
                 }
             }
-        }
+        };
+        run_job(jobs[0], acc0);
+        run_job(jobs[1], acc1);
     }
     // per-block partials in the term-by-term layout: partial[rb][lam * mtiles + tile][16][16]
-#pragma unroll
-    for (int js = 0; js < 2; js++) {
-        const int job = jobs[js];
-        if (job < 0) continue;
+    auto write_job = [&](int job, const double (&acc)[kMaxSlots][4]) {
+        if (job < 0) return;
         const int pp = uni(job / a.mtiles);
         const int tile = uni(job - pp * a.mtiles);
         const int nslot = uni(pairs[pp].nslot);
@@ -438,9 +452,11 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
             const int ojob = uni(pairs[pp].lam[k]) * a.mtiles + tile;
             double *dst = a.partial + ((size_t)rb * njobs + ojob) * 256;
 #pragma unroll
-            for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc[js][k][v];
+            for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc[k][v];
         }
-    }
+    };
+    write_job(jobs[0], acc0);
+    write_job(jobs[1], acc1);
 }
 
 // ---------------------------------------------------------------------------

@@ -88,7 +88,8 @@ struct FProd {
 struct FGroup {          // one (pair, m3)
     int prod_begin, prod_end;
     int coef_begin;      // coef[coef_begin + slot * nprod + (t - prod_begin)]
-    int slot_mask;       // slots with l3 >= m3
+    int slot_mask;       // slots with l3 >= m3: slots [0, nact) (a pair's slots run by falling l3)
+    int nact;            // number of active slots
     int16_t s3[kMaxSlots];  // state of leg 3 for each slot: (l3, m3)
 };
 struct FPair {

@@ -54,6 +54,21 @@ void build_factorised(Tables &t, int L)
                 }
             }
             if (pr.nslot == 0) continue;
+            // slots by falling l3 (stable): the slots a group m3 reaches,
+            // l3 >= m3, are then the first ones
+            {
+                int order[kMaxSlots];
+                for (int k = 0; k < pr.nslot; k++) order[k] = k;
+                std::stable_sort(order, order + pr.nslot, [&](int x, int y) {
+                    return t.lam_lab[3 * pr.lam[x] + 2] > t.lam_lab[3 * pr.lam[y] + 2];
+                });
+                FPair sorted = pr;
+                for (int k = 0; k < pr.nslot; k++) {
+                    sorted.lam[k] = pr.lam[order[k]];
+                    sorted.part[k] = pr.part[order[k]];
+                }
+                pr = sorted;
+            }
             pr.grp_begin = (int)t.fgroups.size();
             double c_pair = 0.0;
             int l3max = 0;
@@ -84,6 +99,7 @@ void build_factorised(Tables &t, int L)
                     g.s3[k] = (int16_t)(l3 >= m3 ? state_index(3, m3, l3, 0) : 0);
                     if (l3 < m3) continue;
                     g.slot_mask |= 1 << k;
+                    g.nact = k + 1;
                     for (int j = 0; j < np; j++) {
                         const int m1 = m1s[j], m2 = -m1 - m3;
                         // eq. Coupling-C: sum over M12 of <l1 m1, l2 m2 | l12 M12><l12 M12, l3 m3 | 0 0>, l12 = l3
@@ -98,6 +114,13 @@ void build_factorised(Tables &t, int L)
                     c_pair += 2.0 * np + 8.0;  // FMAs into this slot's S and its MFMA slice
                 }
                 c_pair += 6.0 * np;            // products
+                if (g.slot_mask != (1 << g.nact) - 1) {  // the kernel takes the active slots as a prefix
+                    t.fpairs.clear();
+                    t.fgroups.clear();
+                    t.fprods.clear();
+                    t.fcoef.clear();
+                    return;
+                }
                 t.fgroups.push_back(g);
             }
             pr.grp_end = (int)t.fgroups.size();
