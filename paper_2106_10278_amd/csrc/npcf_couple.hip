@@ -374,7 +374,7 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple4f(CoupleArgs a, int njobs)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
             }
         };
         run_job(jobs[0], acc0);
-        run_job(jobs[1], acc1);
+        if (kFJobsPerWave > 1) run_job(jobs[1], acc1);
     }
     // per-block partials in the term-by-term layout: partial[rb][lam * mtiles + tile][16][16]
     auto write_job = [&](int job, const double (&acc)[kMaxSlots][4]) {
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_couple4f(CoupleArgs a, int njobs)
         }
     };
     write_job(jobs[0], acc0);
-    write_job(jobs[1], acc1);
+    if (kFJobsPerWave > 1) write_job(jobs[1], acc1);
 }
 
 // ---------------------------------------------------------------------------

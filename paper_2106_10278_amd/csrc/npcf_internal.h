@@ -85,6 +85,9 @@ struct FProd {
     int8_t conj1, conj2;
     int16_t pad;
 };
+// jobs (pair, tile) per wave of the factorised N = 4 coupling kernel
+constexpr int kFJobsPerWave = 1;
+
 struct FGroup {          // one (pair, m3)
     int prod_begin, prod_end;
     int coef_begin;      // coef[coef_begin + slot * nprod + (t - prod_begin)]

@@ -127,18 +127,24 @@ void build_factorised(Tables &t, int L)
             t.fpairs.push_back(pr);
             cost.push_back(c_pair);
         }
-    // jobs (pair, tile), two per wave: heaviest with lightest
+    // jobs (pair, tile) by falling cost.  One per wave: consecutive tasks share
+    // a block (and its row steps), so a block holds jobs of similar cost.  Two
+    // per wave: heaviest with lightest.
     std::vector<int> jobs;
     for (int pp = 0; pp < (int)t.fpairs.size(); pp++)
         for (int tile = 0; tile < t.mtiles; tile++) jobs.push_back(pp * t.mtiles + tile);
-    std::sort(jobs.begin(), jobs.end(),
-              [&](int x, int y) { return cost[x / t.mtiles] > cost[y / t.mtiles]; });
-    size_t lo = 0, hi = jobs.size();
-    while (lo < hi) {
-        int2 tk;
-        tk.x = jobs[lo++];
-        tk.y = (lo < hi) ? jobs[--hi] : -1;
-        t.ftasks.push_back(tk);
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [&](int x, int y) { return cost[x / t.mtiles] > cost[y / t.mtiles]; });
+    if (kFJobsPerWave == 1) {
+        for (int j : jobs) t.ftasks.push_back(make_int2(j, -1));
+    } else {
+        size_t lo = 0, hi = jobs.size();
+        while (lo < hi) {
+            int2 tk;
+            tk.x = jobs[lo++];
+            tk.y = (lo < hi) ? jobs[--hi] : -1;
+            t.ftasks.push_back(tk);
+        }
     }
 }
 
