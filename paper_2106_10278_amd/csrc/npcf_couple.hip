@@ -32,7 +32,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kRowsStep = 16;   // primaries staged in LDS per step
-constexpr int kJobsPerWave = 8;
+constexpr int kJobsPerWave = 4;
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -196,7 +196,7 @@ __device__ __forceinline__ void part_operands(int part_kind, float2 s, float a3r
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_couple4(CoupleArgs a, int njobs, int nparts)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple4(CoupleArgs a, int njobs, int nparts)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // N = 3: job = (Lambda, part); part 0: Re, 1: Im (D = 2 only)
 // ---------------------------------------------------------------------------
 template <int PREC>
-__global__ __launch_bounds__(256) void k_couple3(CoupleArgs a, int njobs, int nparts, const float *sfac)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3(CoupleArgs a, int njobs, int nparts, const float *sfac)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
