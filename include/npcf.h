@@ -196,13 +196,13 @@ npcf_status npcf_destroy(npcf_plan_t plan);
 npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block, int64_t chunk_rows);
 
 /* Autotuner: times the harmonic stage with its cell list for every cell
- * subdivision s = 1..4, then the coupling stage for several primaries per
- * coupling block (the automatic size and 64..1024), on `sample` primaries of
- * the given catalogue taken from four ranges spread over it (best of two runs
- * each, HIP events), and keeps the fastest settings (as npcf_set_tuning).
- * Resets the accumulators.  Outputs (may be NULL): the chosen subdivision,
- * block size (0: automatic) and the sampled time in ms.  Errors as
- * npcf_accumulate. */
+ * subdivision s = 1..4 on `sample` primaries of the given catalogue, taken
+ * from four ranges spread over it (best of two runs each, HIP events), and
+ * keeps the fastest (as npcf_set_tuning).  The coupling block size is left
+ * automatic: a sample leaves large blocks short of work where the full
+ * catalogue does not, so it cannot rank them.  Resets the accumulators.
+ * Outputs (may be NULL): the chosen subdivision, block size (always 0:
+ * automatic) and the sampled time in ms.  Errors as npcf_accumulate. */
 npcf_status npcf_autotune(npcf_plan_t plan, const double *pos, const double *w, int64_t n, int64_t sample,
                           int *cell_subdiv, int *couple_block, double *best_ms);
 

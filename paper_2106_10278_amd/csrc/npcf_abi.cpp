@@ -176,6 +176,16 @@ npcf_status alloc_cells(npcf_plan_s *p)
 int couple_rows_per_block(const npcf_plan_s *p, int64_t nrows)
 {
     if (p->couple_rows > 0) return ((p->couple_rows + 15) / 16) * 16;
+    if (p->N == 4) {
+        // about 32k blocks in all, 256 to 1024 primaries each (measured at
+        // full size: c2 and c3 are fastest at 512-1024, slower at 64 and 2048)
+        const int jpb = couple_jobs_per_block();
+        const int bpr = (!p->t.fpairs.empty() && !p->term_coupling) ? couple_ftask_groups((int)p->t.ftasks.size())
+                                                                     : (p->njobs + jpb - 1) / jpb;
+        int64_t rpb = nrows * bpr / 32768;
+        rpb = ((rpb + 15) / 16) * 16;
+        return (int)std::min<int64_t>(1024, std::max<int64_t>(256, rpb));
+    }
     const int njg = (p->njobs + 31) / 32;
     int64_t want_rb = std::max<int64_t>(8, (2048 + njg - 1) / njg);
     int64_t rpb = (nrows + want_rb - 1) / want_rb;
@@ -1047,21 +1057,16 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
     }
     st = npcf_set_tuning(p, best_s, 0, 0);
     if (st != NPCF_OK) return st;
-    // primaries per coupling block (0: the automatic size)
-    const int cands[] = {0, 64, 128, 256, 512, 1024};
-    int best_b = 0;
-    double best_c = 1e300;
-    for (int cb : cands) {
-        batch_release(p);
-        p->couple_rows = cb;
-        st = measure(h, c);
-        if (st != NPCF_OK) return st;
-        if (c < best_c) {
-            best_c = c;
-            best_b = cb;
-        }
-    }
+    // primaries per coupling block: the automatic size.  Timed on a sample,
+    // large blocks leave the machine partly idle where a full catalogue does
+    // not, so a sample cannot rank block sizes; the rule was measured at full
+    // size instead.
+    const int best_b = 0;
     batch_release(p);
+    p->couple_rows = best_b;
+    st = measure(h, c);
+    if (st != NPCF_OK) return st;
+    const double best_c = c;
     p->couple_rows = best_b;
     st = npcf_reset(p);
     if (st != NPCF_OK) return st;
