@@ -188,7 +188,7 @@ npcf_status npcf_reset(npcf_plan_t plan);
 npcf_status npcf_destroy(npcf_plan_t plan);
 
 /* Tuning knobs (0 keeps the current value): cell subdivision s (cells of
- * side >= r_max / s, 1..4), primaries per coupling block (rounded up to a
+ * side >= r_max / s, 1..8), primaries per coupling block (rounded up to a
  * multiple of 16), and primaries per chunk (rows of a^b held at once; at most
  * the size chosen at plan time).  Synchronises; takes effect on the next
  * accumulate (a batch shape is captured again).  Errors: NPCF_E_INVALID
@@ -196,7 +196,7 @@ npcf_status npcf_destroy(npcf_plan_t plan);
 npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block, int64_t chunk_rows);
 
 /* Autotuner: times the harmonic stage with its cell list for every cell
- * subdivision s = 1..4 on `sample` primaries of the given catalogue, taken
+ * subdivision s = 1..6 on `sample` primaries of the given catalogue, taken
  * from four ranges spread over it (best of two runs each, HIP events), and
  * keeps the fastest (as npcf_set_tuning).  The coupling block size is left
  * automatic: a sample leaves large blocks short of work where the full

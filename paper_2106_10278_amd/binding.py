@@ -222,8 +222,8 @@ class NPCF:
                "npcf_set_tuning")
 
     def autotune(self, pos, w, sample: int = 8192):
-        """Pick the cell subdivision and coupling block size by timing a
-        sample of primaries (resets the accumulators)."""
+        """Pick the cell subdivision by timing a sample of primaries; the
+        coupling block size stays automatic (resets the accumulators)."""
         cs, cb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(load_library().npcf_autotune(self._h, _dptr(pos), _dptr(w), int(w.shape[0]), int(sample),
                                             ctypes.byref(cs), ctypes.byref(cb), ctypes.byref(ms)), "npcf_autotune")

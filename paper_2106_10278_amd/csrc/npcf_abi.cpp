@@ -828,7 +828,7 @@ npcf_status npcf_destroy(npcf_plan_t p)
 npcf_status npcf_set_tuning(npcf_plan_t p, int cell_subdiv, int couple_block, int64_t chunk_rows)
 {
     if (!p) return NPCF_E_INVALID;
-    if (cell_subdiv < 0 || cell_subdiv > 4 || couple_block < 0 || chunk_rows < 0 || chunk_rows > p->rows_cap_max)
+    if (cell_subdiv < 0 || cell_subdiv > 8 || couple_block < 0 || chunk_rows < 0 || chunk_rows > p->rows_cap_max)
         return NPCF_E_INVALID;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return NPCF_E_DEVICE;
     batch_release(p);  // the captured batch depends on every knob
@@ -1045,7 +1045,7 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
     // cell subdivision: harmonic stage + cell list
     int best_s = p->cell_subdiv;
     double best_h = 1e300;
-    for (int sdv = 1; sdv <= 4; sdv++) {
+    for (int sdv = 1; sdv <= 6; sdv++) {
         st = npcf_set_tuning(p, sdv, 0, 0);
         if (st != NPCF_OK) return st;
         st = measure(h, c);

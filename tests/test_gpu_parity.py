@@ -227,7 +227,7 @@ def test_autotune_keeps_results():
     pos = torch.from_numpy(wl.pos).cuda()
     w = torch.from_numpy(wl.w).cuda()
     t = plan.autotune(pos, w, sample=256)
-    assert 1 <= t["cell_subdiv"] <= 4 and t["couple_block"] in (0, 64, 128, 256, 512, 1024) and t["sample_ms"] > 0
+    assert 1 <= t["cell_subdiv"] <= 6 and t["couple_block"] in (0, 64, 128, 256, 512, 1024) and t["sample_ms"] > 0
     got, pairs, _ = gpu_run(wl, plan=plan)
     ref, pairs_ref, _ = oracle_reported(wl)
     assert pairs == pairs_ref
@@ -284,3 +284,19 @@ def test_harmonic_queue_kernel_rejected(monkeypatch):
     monkeypatch.setenv("NPCF_HARMONIC", "queue")
     with pytest.raises(NPCFError, match="NPCF_HARMONIC"):
         NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, max_points=wl.pos.shape[1])
+
+
+@pytest.mark.parametrize("sdv", [1, 3, 6, 8])
+def test_cell_subdivision_keeps_results(sdv):
+    """Finer or coarser cell lists change only which candidates phase A sees:
+    pair counts stay exact and the multipoles match the oracle."""
+    import torch
+    from paper_2106_10278_amd import NPCF
+    wl = _case(3, 4, 3, 500, 71, 20.0, 4.5, 4)
+    print(f"[case] cell subdivision {sdv}", flush=True)
+    plan = NPCF(3, 4, 3, wl.edges, wl.box, max_points=wl.pos.shape[1])
+    plan.set_tuning(cell_subdiv=sdv)
+    got, pairs, _ = gpu_run(wl, plan=plan)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl), f"subdivision {sdv}", strict=False)
