@@ -127,6 +127,35 @@ def load_traffic(key: str):
     return d.get("bytes_per_launch")
 
 
+def coupling_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("npcf_couple.hip", "npcf_plan.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2106_10278_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def coupling_roofline(key: str, path: str, coupling_ms: float):
+    """MFMA flops per coupling launch from a committed rocprofv3 counter run
+    (taken on the current coupling source), over the live coupling-stage time
+    of this run (which also holds the 0.5 ms FP64 reduction of partials)."""
+    fpath = os.path.join(ROOT, "profiles", "coupling_mfma.json")
+    if not os.path.exists(fpath):
+        return None
+    try:
+        d = json.load(open(fpath))
+    except Exception:
+        return None
+    if d.get("coupling_source_sha256_16") != coupling_source_hash() or d.get("workload") != key:
+        return None
+    e = d.get("paths", {}).get(path)
+    if not e:
+        return None
+    achieved = e["mfma_flops"] / (coupling_ms * 1e-3)
+    return {"kernel": "k_couple4f", "bound": "mfma", "dtype": e["mfma_dtype"], "achieved": achieved / 1e12,
+            "peak": e["peak"] / 1e12, "unit": "TFLOP/s", "frac": achieved / e["peak"], "mfma_flops": e["mfma_flops"],
+            "stage_ms": coupling_ms, "source": d.get("source")}
+
+
 def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int):
     """Time the FP64 oracle on a bounded sample of primaries (both roles)."""
     import oracle
@@ -294,6 +323,7 @@ def main():
                    "box": float(wl.box[0]), "parallelism": "single GPU"},
         "paths": results,
         "roofline": roof,
+        "coupling_roofline": coupling_roofline(key, head, r["stage_ms_per_step"]["coupling"]),
         "cpu_baseline": cpu,
         "parity_vs_oracle": errs,
         "batch": batch,
