@@ -83,7 +83,8 @@ typedef struct {
     int nbins;           /* radial bins, 1..16 */
     const double *edges; /* host, nbins+1 strictly increasing values, edges[0] > 0; copied */
     double box[4];       /* side length per axis (first D used), > 0; V_D = product */
-    int periodic;        /* 1: periodic box (requires 2 * edges[nbins] < every side); 0: open */
+    int periodic;        /* 1: periodic box, 0: open; either way 2 * edges[nbins] < every side
+                            (separations are held as 32-bit lattice offsets) */
     int btuple_mode;     /* 0: b1 < b2 < ... (default); 1: every tuple (b1..b_{N-1} free) */
     int precision;       /* npcf_precision */
     int norm;            /* npcf_norm */

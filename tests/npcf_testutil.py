@@ -18,14 +18,14 @@ def per_multipole_error(got, ref):
     return float(errs.max()) if errs.size else 0.0, errs
 
 
-def condition_scale(wl, btuple_mode=0, prims=None):
+def condition_scale(wl, btuple_mode=0, prims=None, periodic=True):
     """Sum of the magnitudes of every term of the estimator,
     (1/V) sum_i |w_i| sum_terms |C| prod_k |a_i^{b_k}[s_k]|, per (Lambda, b-tuple),
     from the oracle's a_lm and coupling coefficients (eq. NPCF-estimator-discrete
     with every term replaced by its absolute value).  A sum evaluated with unit
     roundoff u has forward error bounded by about u times this scale, so errors
     are judged against it where the multipole itself cancels."""
-    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims)
+    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic)
     lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax)
     nb = len(wl.edges) - 1
     bts = oracle.btuple_labels(nb, wl.N, btuple_mode)

@@ -300,3 +300,27 @@ def test_cell_subdivision_keeps_results(sdv):
     ref, pairs_ref, _ = oracle_reported(wl)
     assert pairs == pairs_ref
     _check(got, ref, "plain", condition_scale(wl), f"subdivision {sdv}", strict=False)
+
+
+@pytest.mark.parametrize("D,N,lmax,n,box,rmax", [(3, 4, 3, 400, 10.0, 4.0), (2, 4, 4, 400, 8.0, 3.0),
+                                                  (4, 3, 3, 500, 8.0, 3.5), (3, 3, 4, 400, 10.0, 4.0)])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6"])
+def test_open_box_parity(D, N, lmax, n, box, rmax, precision):
+    """Open (non-periodic) box: separations without wrap-around, cell ranges
+    clipped at the walls (the kernels' non-periodic instantiations)."""
+    import torch
+    from paper_2106_10278_amd import NPCF
+    wl = _case(D, N, lmax, n, 80 + D + N, box, rmax, 4)
+    print(f"[case] open box D={D} N={N} {precision}", flush=True)
+    plan = NPCF(D, N, lmax, wl.edges, wl.box, periodic=False, precision=precision, max_points=n)
+    plan.accumulate(torch.from_numpy(wl.pos).cuda(), torch.from_numpy(wl.w).cuda())
+    got = plan.finalize()
+    z, pairs_ref = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, periodic=False)
+    ref = oracle.reported_part(z, oracle.lambda_labels(D, N, lmax), D, N)
+    assert plan.pair_count()[0] == pairs_ref
+    # the periodic box would have more pairs: the open path is really taken
+    _, pairs_per = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, periodic=True)
+    assert pairs_per > pairs_ref
+    scale = condition_scale(wl, periodic=False)
+    _check(got, ref, precision, scale, f"open D={D} N={N}", strict=False)
+

@@ -287,10 +287,11 @@ def test_bin_volumes_sum_to_shell():
 # Separable estimator == naive estimator (brute force, tiny n)
 # --------------------------------------------------------------------------
 
-def _neighbours(wl, j):
+def _neighbours(wl, j, periodic=True):
     d = wl.pos - wl.pos[:, j:j + 1]
     box = np.asarray(wl.box)[:, None]
-    d = d - box * np.round(d / box)
+    if periodic:
+        d = d - box * np.round(d / box)
     r2 = np.sum(d * d, axis=0)
     e2 = wl.edges ** 2
     ok = (r2 >= e2[0]) & (r2 < e2[-1])
@@ -356,7 +357,7 @@ def _indep_basis(D, N, lmax):
     return P
 
 
-def _brute_force(wl, btuple_mode):
+def _brute_force(wl, btuple_mode, periodic=True):
     """eq. NPCF-estimator-intro-discrete with B = P^0_Lambda prod Theta^{b_i}/v_{b_i},
     coefficients extracted with conj(P) (eq. zeta-basis-coeff), sums over all
     secondaries unrestricted."""
@@ -367,7 +368,7 @@ def _brute_force(wl, btuple_mode):
     P = _indep_basis(D, N, wl.lmax)
     full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
     for j in range(wl.pos.shape[1]):
-        idx, b, d = _neighbours(wl, j)
+        idx, b, d = _neighbours(wl, j, periodic)
         if len(idx) == 0:
             continue
         u = d / np.linalg.norm(d, axis=1, keepdims=True)
@@ -399,6 +400,39 @@ def test_separable_equals_naive(D, N, lmax, n, mode):
     scale = np.max(np.abs(ref))
     assert scale > 0
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("D,N,lmax,n", [(3, 4, 2, 30), (3, 3, 3, 40), (4, 3, 2, 40), (2, 4, 3, 30)])
+def test_separable_equals_naive_open_box(D, N, lmax, n):
+    """Open box (no wrap-around): the separable estimator equals the naive one
+    computed with plain Euclidean separations; the box is small enough that
+    many pairs would wrap if it were periodic, so the two boxes differ."""
+    box = {2: 4.0, 3: 5.0, 4: 4.5}[D]
+    wl = inputs.tiny(D, N, lmax, n, seed=300 + D * 10 + N, box_side=box, rmax=2.2, nbins=3)
+    ref = _brute_force(wl, 1, periodic=False)
+    got, pairs = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1, periodic=False)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+    # pair count: ordered pairs with e_0 <= r < e_nb, no wrap
+    cnt = sum(len(_neighbours(wl, j, periodic=False)[0]) for j in range(n))
+    assert pairs == cnt
+    cnt_per = sum(len(_neighbours(wl, j)[0]) for j in range(n))
+    assert cnt_per != cnt
+
+
+def test_open_box_equals_periodic_away_from_walls():
+    """Points at least r_max from every wall have no wrapped pairs: the open
+    and the periodic estimators agree exactly."""
+    rng = np.random.default_rng(17)
+    D, N, lmax, n, L, rmax = 3, 4, 3, 60, 20.0, 3.0
+    pos = rng.uniform(rmax, L - rmax, size=(D, n))
+    wl = inputs.Workload("inner", D, N, lmax, np.linspace(0.75, rmax, 4), [L] * D,
+                         inputs.to_lattice(pos, [L] * D), rng.uniform(-0.5, 1.5, size=n), n)
+    a, pa = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, periodic=True)
+    b, pb = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, periodic=False)
+    assert pa == pb and pa > 0
+    np.testing.assert_array_equal(a, b)
 
 
 # --------------------------------------------------------------------------
