@@ -324,3 +324,18 @@ def test_open_box_parity(D, N, lmax, n, box, rmax, precision):
     scale = condition_scale(wl, periodic=False)
     _check(got, ref, precision, scale, f"open D={D} N={N}", strict=False)
 
+
+
+@pytest.mark.parametrize("D,N,lmax,nbins", [(3, 3, 10, 3), (2, 3, 16, 3), (4, 3, 6, 3), (2, 4, 16, 3), (3, 4, 8, 3)])
+def test_largest_lmax(D, N, lmax, nbins):
+    """The largest harmonic orders the library takes (D = 2: 16, D = 3: 10,
+    D = 4: 6; for D = 3, N = 4 a high order with the term-by-term coupling):
+    the instantiations with the most emitted values per pair and the most
+    staging chunks."""
+    box, rmax = {2: (10.0, 3.0), 3: (12.0, 4.0), 4: (9.0, 3.5)}[D]
+    wl = _case(D, N, lmax, 250, 90 + D + lmax, box, rmax, nbins)
+    print(f"[case] largest lmax D={D} N={N} lmax={lmax}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl), f"D={D} N={N} lmax={lmax}", strict=False)
