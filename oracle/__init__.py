@@ -45,6 +45,7 @@ class _Cfg(ctypes.Structure):
         ("edges", ctypes.POINTER(ctypes.c_double)),
         ("box", ctypes.c_double * 4),
         ("periodic", ctypes.c_int), ("btuple_mode", ctypes.c_int),
+        ("basis", ctypes.c_int), ("Lmax", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,9 @@ def _load():
     lib.oracle_bin_volume.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.oracle_bin_volume.restype = ctypes.c_double
     lib.oracle_coupling_terms.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, dp]
+    lib.oracle_num_lambda_los.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.oracle_lambda_labels_los.argtypes = [ctypes.c_int, ctypes.c_int, ip]
+    lib.oracle_coupling_terms_los.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, dp]
     lib.oracle_alm.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_long, lp, ctypes.c_long, dp, lp]
     lib.oracle_npcf.argtypes = [ctypes.POINTER(_Cfg), dp, dp, ctypes.c_long, lp, ctypes.c_long, dp, lp]
     _lib = lib
@@ -134,8 +138,17 @@ def dim_states(D: int, l: int) -> float:
     return _load().oracle_dim_states(D, l)
 
 
-def lambda_labels(D: int, N: int, lmax: int) -> np.ndarray:
+def lambda_labels(D: int, N: int, lmax: int, Lmax=None) -> np.ndarray:
+    """Lambda labels; with Lmax given (D = 3, N = 3), the line-of-sight basis
+    labels (l1, l2, L) with L <= Lmax."""
     lib = _load()
+    if Lmax is not None:
+        if (D, N) != (3, 3):
+            raise ValueError("the line-of-sight basis needs D = 3, N = 3")
+        n = lib.oracle_num_lambda_los(lmax, Lmax)
+        lab = np.zeros((n, 3), dtype=np.int32)
+        lib.oracle_lambda_labels_los(lmax, Lmax, _ip(lab))
+        return lab
     n = lib.oracle_num_lambda(D, N, lmax)
     if n < 0:
         raise ValueError("unsupported (D, N)")
@@ -156,9 +169,17 @@ def bin_volume(D: int, e0: float, e1: float) -> float:
     return _load().oracle_bin_volume(D, e0, e1)
 
 
-def coupling_terms(D: int, N: int, lmax: int):
-    """(lambda index, state-index tuple, C) for every non-zero coupling term."""
+def coupling_terms(D: int, N: int, lmax: int, Lmax=None):
+    """(lambda index, state-index tuple, C) for every non-zero coupling term
+    (with Lmax: the line-of-sight basis, D = 3, N = 3)."""
     lib = _load()
+    if Lmax is not None:
+        cnt = lib.oracle_coupling_terms_los(lmax, Lmax, 0, None, None, None)
+        lam = np.zeros(cnt, dtype=np.int32)
+        s = np.zeros((cnt, 3), dtype=np.int32)
+        c = np.zeros(cnt)
+        lib.oracle_coupling_terms_los(lmax, Lmax, cnt, _ip(lam), _ip(s), _dp(c))
+        return lam, s, c
     cnt = lib.oracle_coupling_terms(D, N, lmax, 0, None, None, None)
     lam = np.zeros(cnt, dtype=np.int32)
     s = np.zeros((cnt, 3), dtype=np.int32)
@@ -167,7 +188,7 @@ def coupling_terms(D: int, N: int, lmax: int):
     return lam, s, c
 
 
-def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0):
+def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None):
     edges = np.ascontiguousarray(edges, dtype=np.float64)
     cfg = _Cfg()
     cfg.D, cfg.N, cfg.lmax, cfg.nbins = D, N, lmax, len(edges) - 1
@@ -177,6 +198,8 @@ def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0):
         cfg.box[k] = float(b[k])
     cfg.periodic = 1 if periodic else 0
     cfg.btuple_mode = btuple_mode
+    cfg.basis = 0 if Lmax is None else 1
+    cfg.Lmax = 0 if Lmax is None else int(Lmax)
     return cfg, edges
 
 
@@ -204,13 +227,14 @@ def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True):
     return out[..., 0] + 1j * out[..., 1], int(pairs.value)
 
 
-def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0):
+def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0, Lmax=None):
     """Complex zeta^{Lambda,b} [nlambda][nbtuple] over the listed primaries
-    (default: all) against all secondaries, plus the in-range pair count."""
+    (default: all) against all secondaries, plus the in-range pair count.
+    With Lmax (D = 3, N = 3): the line-of-sight basis P^{0L}, L <= Lmax."""
     lib = _load()
-    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode)
+    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode, Lmax)
     pos, w, n, prims = _prep(pos, w, prims)
-    nlam = lib.oracle_num_lambda(D, N, lmax)
+    nlam = len(lambda_labels(D, N, lmax, Lmax)) if Lmax is not None else lib.oracle_num_lambda(D, N, lmax)
     nbt = lib.oracle_num_btuples(len(edges) - 1, N, btuple_mode)
     if nlam < 0 or nbt < 0:
         raise ValueError("unsupported (D, N)")
@@ -222,12 +246,13 @@ def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=
     return out[..., 0] + 1j * out[..., 1], int(pairs.value)
 
 
-def reported_part(zeta: np.ndarray, labels: np.ndarray, D: int, N: int) -> np.ndarray:
+def reported_part(zeta: np.ndarray, labels: np.ndarray, D: int, N: int, los: bool = False) -> np.ndarray:
     """Apply the paper's parity rule: for D >= 3 report Re for even sum of the
-    total angular momenta and Im for odd; D = 2 stays complex."""
+    total angular momenta and Im for odd; D = 2 stays complex.  For the
+    line-of-sight basis the sum is l1 + l2 + L (P^{0L}* = (-1)^{l1+l2+L} P^{0L})."""
     if D == 2:
         return zeta
-    if N == 3:
+    if N == 3 and not los:
         tot = 2 * labels[:, 0]
     else:
         tot = labels[:, 0] + labels[:, 1] + labels[:, 2]

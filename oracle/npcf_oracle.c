@@ -31,7 +31,14 @@
  *    a convention: parity unpinned by the paper for that sign);
  *  - top-hat bins Theta^b(r) = 1 iff e_b <= r < e_{b+1}, compared on squared
  *    distances; v_b = |S^{D-1}| (e_{b+1}^D - e_b^D) / D;
- *  - periodic minimum-image separations when cfg->periodic is set.
+ *  - periodic minimum-image separations when cfg->periodic is set;
+ *  - with cfg->basis = 1 (D = 3, N = 3 only), the line-of-sight basis of
+ *    section "Large-Scale Structure" (L_1 = 0, L = L_2 up to cfg->Lmax, line of
+ *    sight along axis 3):
+ *      P^{0L}_{l1 l2} = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0) Y_{l1 m} Y_{l2,-m},
+ *    whose coefficients follow from the same a^b_[l] with C_m the factor in
+ *    front of Y_{l1 m} Y_{l2,-m} (coefficient extraction with the conjugate
+ *    basis, as for the isotropic case).
  *
  * The unrestricted sum over secondaries k runs over all n points for every
  * primary (brute force, no cell grid); the self pair is excluded because
@@ -50,6 +57,8 @@ typedef struct {
     double box[4];        /* box side per axis (also V_D = product of sides) */
     int periodic;         /* 1: minimum-image separations */
     int btuple_mode;      /* 0: b1 < b2 < ... ; 1: every tuple */
+    int basis;            /* 0: isotropic (vec L = 0); 1: line-of-sight P^{0L} (D = 3, N = 3) */
+    int Lmax;             /* basis 1: largest L */
 } oracle_cfg;
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
@@ -284,9 +293,20 @@ static double couple_three_to_zero(int D, const int *s1, const int *s2, const in
  *                 (intermediate l12 = l3 is implied)
  *  N = 4, D = 2 : (l1, l2, l3)      l1 = 0..lmax, l2 = -lmax..lmax, l3 = -l1-l2, |l3| <= lmax
  * Labels are stored with 3 integers each (unused entries 0). */
-static int enum_lambda(int D, int N, int lmax, int *lab)
+static int enum_lambda_b(int D, int N, int lmax, int basis, int Lmax, int *lab)
 {
     int cnt = 0;
+    if (basis == 1) {
+        /* (l1, l2, L): l1, l2 = 0..lmax, |l1 - l2| <= L <= min(l1 + l2, Lmax) */
+        if (D != 3 || N != 3) return -1;
+        for (int l1 = 0; l1 <= lmax; l1++)
+            for (int l2 = 0; l2 <= lmax; l2++)
+                for (int L = abs(l1 - l2); L <= l1 + l2 && L <= Lmax; L++) {
+                    if (lab) { lab[3 * cnt] = l1; lab[3 * cnt + 1] = l2; lab[3 * cnt + 2] = L; }
+                    cnt++;
+                }
+        return cnt;
+    }
     if (N == 3) {
         for (int l = 0; l <= lmax; l++) {
             if (lab) { lab[3 * cnt] = l; lab[3 * cnt + 1] = (D == 2) ? -l : 0; lab[3 * cnt + 2] = 0; }
@@ -317,8 +337,12 @@ static int enum_lambda(int D, int N, int lmax, int *lab)
     return -1;
 }
 
+static int enum_lambda(int D, int N, int lmax, int *lab) { return enum_lambda_b(D, N, lmax, 0, 0, lab); }
+
 int oracle_num_lambda(int D, int N, int lmax) { return enum_lambda(D, N, lmax, NULL); }
 int oracle_lambda_labels(int D, int N, int lmax, int *lab) { return enum_lambda(D, N, lmax, lab); }
+int oracle_num_lambda_los(int lmax, int Lmax) { return enum_lambda_b(3, 3, lmax, 1, Lmax, NULL); }
+int oracle_lambda_labels_los(int lmax, int Lmax, int *lab) { return enum_lambda_b(3, 3, lmax, 1, Lmax, lab); }
 
 static int enum_btuples(int nb, int N, int mode, int *bt)
 {
@@ -366,15 +390,16 @@ typedef struct {
     double c;     /* coupling coefficient */
 } term_t;
 
-static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
+static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **out, int *nterm_out)
 {
     int nst = enum_states(D, lmax, NULL);
-    int nlam = enum_lambda(D, N, lmax, NULL);
+    int nlam = enum_lambda_b(D, N, lmax, basis, Lmax, NULL);
+    if (nlam < 0) return OR_EUNSUP;
     int *slab = (int *)malloc(sizeof(int) * (size_t)nst * (D - 1));
     int *llab = (int *)malloc(sizeof(int) * 3 * (size_t)nlam);
     if (!slab || !llab) { free(slab); free(llab); return OR_ENOMEM; }
     enum_states(D, lmax, slab);
-    enum_lambda(D, N, lmax, llab);
+    enum_lambda_b(D, N, lmax, basis, Lmax, llab);
     int cap = 1024, nt = 0;
     term_t *t = (term_t *)malloc(sizeof(term_t) * cap);
     if (!t) { free(slab); free(llab); return OR_ENOMEM; }
@@ -386,11 +411,21 @@ static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
             if (sa[D - 2] != lam[0]) continue;
             for (int b = 0; b < nst; b++) {
                 const int *sb = slab + (size_t)b * (D - 1);
-                /* leg 2 carries lam[1]; for N = 3 and D >= 3 the label holds only l */
-                int want2 = (N == 3 && D >= 3) ? lam[0] : lam[1];
+                /* leg 2 carries lam[1]; for the isotropic N = 3, D >= 3 basis the
+                 * label holds only l */
+                int want2 = (N == 3 && D >= 3 && basis == 0) ? lam[0] : lam[1];
                 if (sb[D - 2] != want2) continue;
                 if (N == 3) {
-                    double c = couple_pair_to_zero(D, sa, sb);
+                    double c;
+                    if (basis == 1) {
+                        /* P^{0L}_{l1 l2}: (-1)^{l2-l1} sqrt(2L+1) (l1 l2 L; m -m 0) for
+                         * leg states (m, l1) and (-m, l2) */
+                        if (sb[0] != -sa[0]) continue;
+                        c = oracle_wigner3j(lam[0], lam[1], lam[2], sa[0], sb[0], 0) * sqrt(2.0 * lam[2] + 1.0);
+                        if ((lam[1] - lam[0]) & 1) c = -c;
+                    } else {
+                        c = couple_pair_to_zero(D, sa, sb);
+                    }
                     if (c == 0.0) continue;
                     if (nt == cap) { cap *= 2; term_t *nt2 = (term_t *)realloc(t, sizeof(term_t) * cap); if (!nt2) { free(t); free(slab); free(llab); return OR_ENOMEM; } t = nt2; }
                     t[nt].lam = L; t[nt].s[0] = a; t[nt].s[1] = b; t[nt].s[2] = -1; t[nt].c = c; nt++;
@@ -415,6 +450,11 @@ static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
     return OR_OK;
 }
 
+static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
+{
+    return build_terms_b(D, N, lmax, 0, 0, out, nterm_out);
+}
+
 /* Exposes the coupling terms (for tests): fills up to cap entries of
  * lam[], s[3*i], c[] and returns the total count. */
 int oracle_coupling_terms(int D, int N, int lmax, int cap, int *lam, int *s, double *c)
@@ -422,6 +462,22 @@ int oracle_coupling_terms(int D, int N, int lmax, int cap, int *lam, int *s, dou
     term_t *t = NULL;
     int nt = 0;
     int st = build_terms(D, N, lmax, &t, &nt);
+    if (st != OR_OK) return -1;
+    for (int i = 0; i < nt && i < cap; i++) {
+        lam[i] = t[i].lam;
+        s[3 * i] = t[i].s[0]; s[3 * i + 1] = t[i].s[1]; s[3 * i + 2] = t[i].s[2];
+        c[i] = t[i].c;
+    }
+    free(t);
+    return nt;
+}
+
+/* The same for the line-of-sight basis (D = 3, N = 3, L <= Lmax). */
+int oracle_coupling_terms_los(int lmax, int Lmax, int cap, int *lam, int *s, double *c)
+{
+    term_t *t = NULL;
+    int nt = 0;
+    int st = build_terms_b(3, 3, lmax, 1, Lmax, &t, &nt);
     if (st != OR_OK) return -1;
     for (int i = 0; i < nt && i < cap; i++) {
         lam[i] = t[i].lam;
@@ -441,6 +497,9 @@ static int check_cfg(const oracle_cfg *cfg)
     if (!cfg || !cfg->edges) return OR_EINVAL;
     if (cfg->D < 2 || cfg->D > 4 || cfg->N < 3 || cfg->N > 4) return OR_EUNSUP;
     if (cfg->N == 4 && cfg->D == 4) return OR_EUNSUP;
+    if (cfg->basis != 0 && cfg->basis != 1) return OR_EINVAL;
+    if (cfg->basis == 1 && (cfg->D != 3 || cfg->N != 3)) return OR_EUNSUP;
+    if (cfg->basis == 1 && cfg->Lmax < 0) return OR_EINVAL;
     if (cfg->lmax < 0 || cfg->nbins < 1) return OR_EINVAL;
     if (!(cfg->edges[0] > 0.0)) return OR_EINVAL;
     for (int b = 0; b < cfg->nbins; b++)
@@ -531,14 +590,14 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
     if (st != OR_OK) return st;
     const int D = cfg->D, N = cfg->N, nb = cfg->nbins;
     int nst = enum_states(D, cfg->lmax, NULL);
-    int nlam = enum_lambda(D, N, cfg->lmax, NULL);
+    int nlam = enum_lambda_b(D, N, cfg->lmax, cfg->basis, cfg->Lmax, NULL);
     int nbt = enum_btuples(nb, N, cfg->btuple_mode, NULL);
     int *bt = (int *)malloc(sizeof(int) * 3 * (size_t)nbt);
     term_t *terms = NULL;
     int nterm = 0;
     if (!bt) return OR_ENOMEM;
     enum_btuples(nb, N, cfg->btuple_mode, bt);
-    st = build_terms(D, N, cfg->lmax, &terms, &nterm);
+    st = build_terms_b(D, N, cfg->lmax, cfg->basis, cfg->Lmax, &terms, &nterm);
     if (st != OR_OK) { free(bt); return st; }
 
     size_t zlen = 2 * (size_t)nlam * nbt;

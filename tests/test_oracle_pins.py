@@ -528,3 +528,100 @@ def test_primary_additivity():
     zb, pb = oracle.npcf(3, 4, 2, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(17, 50))
     assert pa + pb == p
     np.testing.assert_allclose(za + zb, z, rtol=1e-13, atol=1e-15 * np.abs(z).max())
+
+
+# --------------------------------------------------------------------------
+# Line-of-sight basis P^{0L}_{l1 l2} (section "Large-Scale Structure")
+# --------------------------------------------------------------------------
+
+def _los_basis(lmax, Lmax):
+    """P^{0L}_{l1 l2}(d1, d2) = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0)
+    Y_{l1 m}(d1) Y_{l2,-m}(d2), from SciPy harmonics and SymPy 3j symbols."""
+    labels = oracle.lambda_labels(3, 3, lmax, Lmax)
+
+    def Yall(d):
+        th = np.arccos(np.clip(d[:, 2], -1, 1))
+        ph = np.arctan2(d[:, 1], d[:, 0])
+        return {(l, m): (-1.0) ** m * sph_harm_y(l, m, th, ph) for l in range(lmax + 1) for m in range(-l, l + 1)}
+
+    def P(d1, d2):
+        Y1, Y2 = Yall(d1), Yall(d2)
+        out = np.zeros((len(labels), len(d1), len(d2)), dtype=complex)
+        for i, (l1, l2, L) in enumerate(labels):
+            pre = (-1.0) ** (l2 - l1) * math.sqrt(2 * L + 1)
+            for m in range(-min(l1, l2), min(l1, l2) + 1):
+                c = float(wigner_3j(int(l1), int(l2), int(L), m, -m, 0))
+                if c != 0.0:
+                    out[i] += pre * c * np.outer(Y1[(int(l1), m)], Y2[(int(l2), -m)])
+        return out
+
+    return labels, P
+
+
+def test_los_basis_l0_is_isotropic():
+    """L = 0 forces l1 = l2 = l: the line-of-sight components equal the
+    isotropic 3PCF ones (eq. for P^{0L} with the 3j value at L = 0)."""
+    wl = inputs.tiny(3, 3, 4, 80, seed=41, box_side=8.0, rmax=3.0, nbins=3)
+    iso, _ = oracle.npcf(3, 3, 4, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1)
+    los, _ = oracle.npcf(3, 3, 4, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1, Lmax=0)
+    lab = oracle.lambda_labels(3, 3, 4, 0)
+    assert np.all(lab[:, 0] == lab[:, 1]) and np.all(lab[:, 2] == 0)
+    np.testing.assert_allclose(los, iso[lab[:, 0]], rtol=0, atol=1e-13 * np.max(np.abs(iso)))
+
+
+@pytest.mark.parametrize("lmax,Lmax,mode", [(2, 4, 1), (3, 2, 0), (2, 1, 1)])
+def test_los_separable_equals_naive(lmax, Lmax, mode):
+    """Separable line-of-sight estimator equals the naive pair sum with an
+    independently built basis (coefficients extracted with conj(P))."""
+    wl = inputs.tiny(3, 3, lmax, 40, seed=55 + lmax, box_side=8.0, rmax=2.8, nbins=3)
+    labels, P = _los_basis(lmax, Lmax)
+    nb = 3
+    vb = np.array([oracle.bin_volume(3, wl.edges[b], wl.edges[b + 1]) for b in range(nb)])
+    full = np.zeros((len(labels), nb, nb), dtype=complex)
+    for j in range(wl.pos.shape[1]):
+        idx, b, d = _neighbours(wl, j)
+        if len(idx) == 0:
+            continue
+        u = d / np.linalg.norm(d, axis=1, keepdims=True)
+        ww = wl.w[idx] / vb[b]
+        pv = np.conj(P(u, u)) * ww[None, :, None] * ww[None, None, :]
+        for i1 in range(len(idx)):
+            np.add.at(full, (slice(None), b[i1], b), wl.w[j] * pv[:, i1, :])
+    full /= np.prod(wl.box)
+    bt = oracle.btuple_labels(nb, 3, mode)
+    ref = full[:, bt[:, 0], bt[:, 1]]
+    got, _ = oracle.npcf(3, 3, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=mode, Lmax=Lmax)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+def test_los_rotation_and_parity():
+    """A quarter turn about the line of sight (axis 3) maps the periodic cube
+    onto itself and leaves every P^{0L} component unchanged; a quarter turn
+    about axis 1 leaves the L = 0 (isotropic) components unchanged but not the
+    L > 0 ones.  The part the parity rule drops (Im for even l1+l2+L, Re for
+    odd) vanishes for real weights."""
+    L_box = 8.0
+    wl = inputs.tiny(3, 3, 3, 120, seed=77, box_side=L_box, rmax=3.0, nbins=3)
+    # anisotropic input: stretch the catalogue along the line of sight
+    pos = wl.pos.copy()
+    pos[2] = np.mod(pos[2] * 1.0, L_box)
+    rng = np.random.default_rng(3)
+    pos[2] = np.mod(pos[2] + 0.25 * rng.standard_normal(pos.shape[1]) * (pos[0] > L_box / 2), L_box)
+    pos = inputs.to_lattice(pos, wl.box)
+    args = (3, 3, 3, wl.edges, wl.box)
+    z0, _ = oracle.npcf(*args, pos, wl.w, btuple_mode=1, Lmax=4)
+    rz = np.stack([np.mod(-pos[1], L_box), pos[0], pos[2]])
+    rx = np.stack([pos[0], np.mod(-pos[2], L_box), pos[1]])
+    zz, _ = oracle.npcf(*args, rz, wl.w, btuple_mode=1, Lmax=4)
+    zx, _ = oracle.npcf(*args, rx, wl.w, btuple_mode=1, Lmax=4)
+    lab = oracle.lambda_labels(3, 3, 3, 4)
+    sc = np.max(np.abs(z0))
+    np.testing.assert_allclose(zz, z0, rtol=0, atol=1e-12 * sc)
+    iso = lab[:, 2] == 0
+    np.testing.assert_allclose(zx[iso], z0[iso], rtol=0, atol=1e-12 * sc)
+    assert np.max(np.abs(zx[~iso] - z0[~iso])) > 1e-6 * sc
+    odd = (lab.sum(axis=1) % 2) == 1
+    dropped = np.where(odd[:, None], z0.real, z0.imag)
+    assert np.max(np.abs(dropped)) <= 1e-12 * sc
