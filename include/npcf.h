@@ -76,6 +76,12 @@ typedef enum {
     NPCF_ROLE_RANDOMS = 1   /* accumulate into the randoms normalisation accumulator */
 } npcf_role;
 
+typedef enum {
+    NPCF_BASIS_ISOTROPIC = 0,     /* vec L = 0: the isotropic basis (eq. Coupling-C) */
+    NPCF_BASIS_LINE_OF_SIGHT = 1  /* D = 3, N = 3: P^{0L}_{l1 l2} (section "Large-Scale Structure"),
+                                     line of sight along axis 3, labels (l1, l2, L), L <= Lmax */
+} npcf_basis;
+
 typedef struct {
     int D;               /* dimension: 2, 3 or 4 */
     int N;               /* correlation order: 3 or 4 (N = 4 needs D <= 3) */
@@ -88,6 +94,8 @@ typedef struct {
     int btuple_mode;     /* 0: b1 < b2 < ... (default); 1: every tuple (b1..b_{N-1} free) */
     int precision;       /* npcf_precision */
     int norm;            /* npcf_norm */
+    int basis;           /* npcf_basis (0 for a zero-initialised config) */
+    int Lmax;            /* NPCF_BASIS_LINE_OF_SIGHT: largest L, 0..2 lmax (ignored otherwise) */
 } npcf_config;
 
 typedef struct npcf_plan_s *npcf_plan_t;
@@ -129,7 +137,8 @@ npcf_status npcf_finalize(npcf_plan_t plan, double *out, size_t out_len);
 /* Describe the output layout.  Any pointer may be NULL.
  *  n_lambda: number of Lambda labels; lambda_labels: int [n_lambda][3]
  *    (N=3, D>=3: (l,0,0); N=3, D=2: (l,-l,0); N=4: (l1,l2,l3), l12 = l3 implied for D = 3,
- *    l3 = -l1-l2 for D = 2), lexicographic;
+ *    l3 = -l1-l2 for D = 2; line-of-sight basis: (l1,l2,L), |l1-l2| <= L <= min(l1+l2, Lmax),
+ *    Re part reported for even l1+l2+L, Im for odd), lexicographic;
  *  n_bt: number of radial tuples; btuples: int [n_bt][3] (unused entries 0), lexicographic;
  *  out_len: entries npcf_finalize writes. */
 npcf_status npcf_describe(npcf_plan_t plan, int *n_lambda, int *lambda_labels, int *n_bt, int *btuples,

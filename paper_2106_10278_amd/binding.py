@@ -43,6 +43,7 @@ class _Config(ctypes.Structure):
         ("box", ctypes.c_double * 4),
         ("periodic", ctypes.c_int), ("btuple_mode", ctypes.c_int),
         ("precision", ctypes.c_int), ("norm", ctypes.c_int),
+        ("basis", ctypes.c_int), ("Lmax", ctypes.c_int),
     ]
 
 
@@ -125,7 +126,8 @@ class NPCF:
     """One estimator plan (npcf_plan ... npcf_destroy)."""
 
     def __init__(self, D: int, N: int, lmax: int, edges, box, periodic: bool = True, btuple_mode: int = 0,
-                 precision: str = "plain", norm: str = "raw", max_points: int = 1 << 20, stream=None):
+                 precision: str = "plain", norm: str = "raw", max_points: int = 1 << 20, stream=None,
+                 Lmax=None):
         lib = load_library()
         self.D, self.N, self.lmax = int(D), int(N), int(lmax)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -139,6 +141,9 @@ class NPCF:
         cfg.btuple_mode = int(btuple_mode)
         cfg.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
         cfg.norm = NORM[norm] if isinstance(norm, str) else int(norm)
+        # Lmax given: the line-of-sight basis P^{0L}_{l1 l2} (D = 3, N = 3)
+        cfg.basis = 0 if Lmax is None else 1
+        cfg.Lmax = 0 if Lmax is None else int(Lmax)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

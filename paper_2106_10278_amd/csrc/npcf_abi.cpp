@@ -319,6 +319,7 @@ CoupleArgs couple_args(const npcf_plan_s *p, int rows)
     a.mrows = t.mrows;
     a.mtiles = t.mtiles;
     a.max_block_terms = p->max_block_terms;
+    a.n3_terms = t.n3_terms ? 1 : 0;
     if (p->d_fpairs && !p->term_coupling) {
         a.fpairs = p->d_fpairs;
         a.fgroups = p->d_fgroups;

@@ -542,6 +542,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
+// N = 3 from a term list (line-of-sight basis): job = Lambda,
+//   Z[b1, b2] += sum_i w_i sum_t c_t op1(a_i[b1][s1_t]) op2(a_i[b2][s2_t])
+// (op: conjugation per leg), its Re or Im part (lam_part) on MFMA with
+// K = primaries x terms x {two real products of the complex product}.
+template <int PREC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3t(CoupleArgs a, int njobs)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int rowlen = a.nb * 2 * a.nstate;
+    float *Ast = reinterpret_cast<float *>(smem);
+    float *wst = Ast + kRowsStep * rowlen;
+    const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
+    int rb, jg;
+    if (!block_work(a.n_rowblocks, njg, rb, jg)) return;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
+
+    double acc64[kJobsPerWave][4];
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) acc64[j][v] = 0.0;
+    int r_begin = rb * a.rows_per_block;
+    int r_end = r_begin + a.rows_per_block;
+    if (a.rb_begin) {
+        r_begin = a.rb_begin[rb];
+        r_end = a.rb_end[rb];
+    }
+    if (r_end > a.nrows) r_end = a.nrows;
+    const int n = lane & 15;   // b1 (A row) and b2 (B column) of this lane
+    const int kq = lane >> 4;
+    const bool bok = n < a.nb;
+
+    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+        __syncthreads();
+        stage_rows(a, r0, r_end, Ast, wst);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kJobsPerWave; j++) {
+            const int lam = job0 + j;
+            if (lam >= njobs) break;
+            const int im = a.lam_part[lam];
+            const CoupleGroup g = a.groups[a.lam_group_begin[lam]];
+            const int nt = g.term_end - g.term_begin;
+            const int kper = 2 * nt;   // K entries per primary: terms x {two real products}
+            const int ktot = kRowsStep * kper;
+            for (int k0 = 0; k0 < ktot; k0 += 32) {
+                float Av[8], Bv[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    const int k = k0 + 8 * kq + i;
+                    Av[i] = 0.f;
+                    Bv[i] = 0.f;
+                    if (k < ktot && bok) {
+                        const int p = k / kper;
+                        const int rr = k - p * kper;
+                        const CoupleTerm tm = a.terms[g.term_begin + (rr >> 1)];
+                        const int c = rr & 1;
+                        const float *Ap = Ast + p * rowlen + n * 2 * a.nstate;
+                        const float2 x = *reinterpret_cast<const float2 *>(Ap + 2 * tm.s1);
+                        const float2 y = *reinterpret_cast<const float2 *>(Ap + 2 * tm.s2);
+                        const float xi = tm.conj1 ? -x.y : x.y;
+                        const float yi = tm.conj2 ? -y.y : y.y;
+                        const float wf = wst[p] * tm.coef;
+                        // Re(x y) = xr yr + (-xi) yi;  Im(x y) = xr yi + xi yr
+                        if (!im) {
+                            Av[i] = c ? -wf * xi : wf * x.x;
+                            Bv[i] = c ? yi : y.x;
+                        } else {
+                            Av[i] = c ? wf * xi : wf * x.x;
+                            Bv[i] = c ? y.x : yi;
+                        }
+                    }
+                }
+                v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                double unscale;
+                mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc64[j][v] += (double)cc[v] * unscale;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kJobsPerWave; j++) {
+        const int job = job0 + j;
+        if (job >= njobs) break;
+        double *dst = a.partial + ((size_t)rb * njobs + job) * 256;
+#pragma unroll
+        for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc64[j][v];
+    }
+}
+
 __global__ void k_reduce_partials(const double *partial, int nrb, int64_t len, double *acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -641,6 +734,15 @@ hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int n
         case 1: return launch_with_lds(k_couple4<1>, nblk, lds, s, a, njobs, nparts);
         case 2: return launch_with_lds(k_couple4<2>, nblk, lds, s, a, njobs, nparts);
         case 3: return launch_with_lds(k_couple4<3>, nblk, lds, s, a, njobs, nparts);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.n3_terms) {
+        switch (precision) {
+        case 0: return launch_with_lds(k_couple3t<0>, nblk, lds, s, a, njobs);
+        case 1: return launch_with_lds(k_couple3t<1>, nblk, lds, s, a, njobs);
+        case 2: return launch_with_lds(k_couple3t<2>, nblk, lds, s, a, njobs);
+        case 3: return launch_with_lds(k_couple3t<3>, nblk, lds, s, a, njobs);
         default: return hipErrorInvalidValue;
         }
     }

@@ -153,6 +153,9 @@ struct CoupleArgs {
     const float *fcoef;
     const int2 *ftasks;          // per wave: two jobs (pair * mtiles + tile), -1 for none
     int nftasks;
+    // N = 3 with a term list per Lambda (line-of-sight basis): one group per
+    // Lambda, terms (s1, conj1, s2, conj2, coef) pairing a[b1] with a[b2]
+    int n3_terms;
 };
 
 // ---------------------------------------------------------------------------
@@ -229,6 +232,7 @@ struct Tables {
     std::vector<FProd> fprods;
     std::vector<float> fcoef;
     std::vector<int2> ftasks;
+    bool n3_terms = false;             // N = 3 coupling from a term list (line-of-sight basis)
 };
 
 // Validates cfg and fills the tables; returns NPCF_OK or an error code and a message.

@@ -208,6 +208,11 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     if (cfg.precision < 0 || cfg.precision > 3) { err = "unknown precision"; return NPCF_E_INVALID; }
     if (cfg.norm != 0 && cfg.norm != 1) { err = "unknown norm"; return NPCF_E_INVALID; }
     if (cfg.periodic != 0 && cfg.periodic != 1) { err = "periodic must be 0 or 1"; return NPCF_E_INVALID; }
+    if (cfg.basis != NPCF_BASIS_ISOTROPIC && cfg.basis != NPCF_BASIS_LINE_OF_SIGHT) { err = "unknown basis"; return NPCF_E_INVALID; }
+    const bool los = cfg.basis == NPCF_BASIS_LINE_OF_SIGHT;
+    if (los && (D != 3 || N != 3)) { err = "the line-of-sight basis needs D = 3, N = 3"; return NPCF_E_UNSUPPORTED; }
+    if (los && (cfg.Lmax < 0 || cfg.Lmax > 2 * L)) { err = "Lmax must be 0..2 lmax"; return NPCF_E_INVALID; }
+    t.n3_terms = los;
 
     // ---- stored states (l1 >= 0 half) --------------------------------------
     t.nstate = stored_states(D, L);
@@ -225,7 +230,16 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
 
     // ---- Lambda labels ----------------------------------------------------------
     t.lam_lab.clear();
-    if (N == 3) {
+    if (los) {
+        // (l1, l2, L): |l1 - l2| <= L <= min(l1 + l2, Lmax)
+        for (int l1 = 0; l1 <= L; l1++)
+            for (int l2 = 0; l2 <= L; l2++)
+                for (int LL = std::abs(l1 - l2); LL <= std::min(l1 + l2, cfg.Lmax); LL++) {
+                    t.lam_lab.push_back(l1);
+                    t.lam_lab.push_back(l2);
+                    t.lam_lab.push_back(LL);
+                }
+    } else if (N == 3) {
         for (int l = 0; l <= L; l++) {
             t.lam_lab.push_back(l);
             t.lam_lab.push_back(D == 2 ? -l : 0);
@@ -329,7 +343,29 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     t.lam_part.assign(t.nlam, 0);
     for (int lam = 0; lam < t.nlam; lam++) {
         const int *lb = &t.lam_lab[3 * lam];
-        if (N == 3) {
+        if (los) {
+            // P^{0L}_{l1 l2} = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0) Y_{l1 m} Y_{l2,-m}
+            // (section "Large-Scale Structure"); the prefactor times the 3j symbol is
+            // the Clebsch-Gordan coefficient <l1 m, l2 -m | L 0>.  Legs from the stored
+            // m >= 0 half: a_{l,-m} = (-1)^m conj(a_{l,m}).
+            const int l1 = lb[0], l2 = lb[1], LL = lb[2];
+            t.lam_part[lam] = (l1 + l2 + LL) % 2;
+            CoupleGroup g{};
+            g.term_begin = (int)t.terms.size();
+            for (int m = -std::min(l1, l2); m <= std::min(l1, l2); m++) {
+                const double c = clebsch_gordan(l1, m, l2, -m, LL, 0);
+                if (c == 0.0) continue;
+                CoupleTerm tm{};
+                tm.s1 = (int16_t)state_index(3, std::abs(m), l1, 0);
+                tm.conj1 = m < 0;
+                tm.s2 = (int16_t)state_index(3, std::abs(m), l2, 0);
+                tm.conj2 = m > 0;
+                tm.coef = (float)(((m % 2) != 0 ? -1.0 : 1.0) * c);
+                t.terms.push_back(tm);
+            }
+            g.term_end = (int)t.terms.size();
+            t.groups.push_back(g);
+        } else if (N == 3) {
             const int l = lb[0];
             CoupleGroup g{};
             if (D == 2) {

@@ -18,7 +18,7 @@ def per_multipole_error(got, ref):
     return float(errs.max()) if errs.size else 0.0, errs
 
 
-def condition_scale(wl, btuple_mode=0, prims=None, periodic=True):
+def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
     """Sum of the magnitudes of every term of the estimator,
     (1/V) sum_i |w_i| sum_terms |C| prod_k |a_i^{b_k}[s_k]|, per (Lambda, b-tuple),
     from the oracle's a_lm and coupling coefficients (eq. NPCF-estimator-discrete
@@ -26,10 +26,10 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True):
     roundoff u has forward error bounded by about u times this scale, so errors
     are judged against it where the multipole itself cancels."""
     a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic)
-    lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax)
+    lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax, Lmax)
     nb = len(wl.edges) - 1
     bts = oracle.btuple_labels(nb, wl.N, btuple_mode)
-    nlam = len(oracle.lambda_labels(wl.D, wl.N, wl.lmax))
+    nlam = len(oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax))
     w = np.abs(wl.w if prims is None else wl.w[prims])
     A = np.abs(a)
     out = np.zeros((nlam, len(bts)))
@@ -50,14 +50,14 @@ def conditioned_error(got, ref, scale):
     return float(errs.max()) if errs.size else 0.0, errs
 
 
-def oracle_reported(wl, prims=None, btuple_mode=0):
+def oracle_reported(wl, prims=None, btuple_mode=0, Lmax=None):
     z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims,
-                           btuple_mode=btuple_mode)
-    labels = oracle.lambda_labels(wl.D, wl.N, wl.lmax)
-    return oracle.reported_part(z, labels, wl.D, wl.N), pairs, z
+                           btuple_mode=btuple_mode, Lmax=Lmax)
+    labels = oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)
+    return oracle.reported_part(z, labels, wl.D, wl.N, los=Lmax is not None), pairs, z
 
 
-def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", plan=None):
+def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", plan=None, Lmax=None):
     import torch
     from paper_2106_10278_amd import NPCF
     pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).to(device)
@@ -65,7 +65,7 @@ def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", 
     n = wl.pos.shape[1]
     if plan is None:
         plan = NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, btuple_mode=btuple_mode, precision=precision,
-                    max_points=n)
+                    max_points=n, Lmax=Lmax)
     if ranges is None:
         ranges = [(0, n)]
     for a, b in ranges:
