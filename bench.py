@@ -72,6 +72,8 @@ def make_workload(name: str):
         return inputs.c3_vorticity_4pcf()
     if name == "c5":
         return inputs.c5_hyper_3pcf()
+    if name == "c6":
+        return inputs.c6_los_3pcf()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -165,9 +167,10 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int):
         ranges.append((nd, nd + sample_per_role))
     prims = np.concatenate([np.arange(a, b) for a, b in ranges])
     t0 = time.perf_counter()
-    z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims)
+    Lmax = wl.Lmax
+    z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax)
     dt = time.perf_counter() - t0
-    ref = oracle.reported_part(z, oracle.lambda_labels(wl.D, wl.N, wl.lmax), wl.D, wl.N)
+    ref = oracle.reported_part(z, oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax), wl.D, wl.N, los=Lmax is not None)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     errs = {}
     for prec in ("plain",) + MIXED:
@@ -177,7 +180,7 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int):
         got = plan.finalize()
         gp = plan.pair_count()[0]
         e, worst = rel_err(got, ref)
-        errs[prec] = {"max_rel_err": e, "worst_lambda": [int(x) for x in oracle.lambda_labels(wl.D, wl.N, wl.lmax)[worst]],
+        errs[prec] = {"max_rel_err": e, "worst_lambda": [int(x) for x in oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)[worst]],
                       "pairs_match": bool(gp == pairs)}
         plan.close()
     base = {"value": pairs / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
@@ -267,7 +270,8 @@ def main():
     w = torch.from_numpy(np.ascontiguousarray(wl.w)).to("cuda:0")
 
     def factory(prec):
-        return NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, precision=prec, max_points=n)
+        return NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, precision=prec, max_points=n,
+                    Lmax=wl.Lmax)
 
     results = {}
     for prec in args.precisions.split(","):

@@ -89,6 +89,7 @@ class Workload:
     w: np.ndarray            # [n] float64
     n_data: int = 0          # leading points that are data (rest: randoms)
     note: str = ""
+    Lmax: object = None      # line-of-sight basis (D = 3, N = 3): largest L; None: isotropic
 
 
 def c1_small_3pcf(seed: int = 1001) -> Workload:
@@ -112,6 +113,27 @@ def c2_clustered_4pcf(seed: int = 1002, n_data: int = 200_000, n_rand: int = 600
     w = np.concatenate([np.ones(n_data), np.full(n_rand, -1.0 / 3.0)])
     return Workload(f"D3-N4-clustered-{n_data // 1000}k+{n_rand // 1000}k-randoms", 3, 4, 5,
                     np.linspace(20.0, 160.0, 11), box, pos, w, n_data)
+
+
+def c6_los_3pcf(seed: int = 1006, n_data: int = 200_000, n_rand: int = 600_000) -> Workload:
+    """D=3, N=3, line-of-sight basis (L <= 6): the c2 catalogue shape with
+    redshift-space-like anisotropy -- blob offsets along axis 3 four times
+    wider (sigma 20 against 5 across) -- 200k data (half in 2000 blobs, half
+    uniform), w = +1, plus 600k uniform randoms with w = -1/3, periodic cube of
+    side 1000, 10 linear bins in [20, 160], lmax = 5."""
+    rng = np.random.default_rng(seed)
+    box = np.array([1000.0] * 3)
+    nb = n_data // 2
+    centres = rng.uniform(0.0, 1.0, size=(3, 2000)) * box[:, None]
+    pick = rng.integers(0, 2000, size=nb)
+    sig = np.array([5.0, 5.0, 20.0])[:, None]
+    blob = centres[:, pick] + rng.normal(0.0, 1.0, size=(3, nb)) * sig
+    back = rng.uniform(0.0, 1.0, size=(3, n_data - nb)) * box[:, None]
+    rand = rng.uniform(0.0, 1.0, size=(3, n_rand)) * box[:, None]
+    pos = to_lattice(np.concatenate([blob, back, rand], axis=1), box)
+    w = np.concatenate([np.ones(n_data), np.full(n_rand, -1.0 / 3.0)])
+    return Workload(f"D3-N3-los-Lmax6-rsd-{n_data // 1000}k+{n_rand // 1000}k-randoms", 3, 3, 5,
+                    np.linspace(20.0, 160.0, 11), list(box), pos, w, n_data, Lmax=6)
 
 
 def c3_vorticity_4pcf(seed: int = 1003, n: int = 500_000, grid: int = 1024) -> Workload:

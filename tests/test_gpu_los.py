@@ -66,3 +66,27 @@ def test_los_rejects_other_dimensions():
         NPCF(3, 4, 2, wl.edges, wl.box, max_points=50, Lmax=2)
     with pytest.raises(NPCFError):
         NPCF(3, 3, 2, wl.edges, wl.box, max_points=50, Lmax=5)   # Lmax > 2 lmax
+
+
+_C6 = {}
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed_fp16", "mixed_bf16x6"])
+def test_c6_full_catalogue_sampled(precision):
+    """The line-of-sight workload at full size (800k points, L <= 6): 48 data
+    and 48 random primaries against every secondary, in the benchmark's launch
+    configuration, against the oracle on the same primaries."""
+    if "wl" not in _C6:
+        wl = inputs.c6_los_3pcf()
+        prims = np.concatenate([np.arange(0, 48), np.arange(wl.n_data, wl.n_data + 48)])
+        ref, pairs_ref, _ = oracle_reported(wl, prims=prims, Lmax=wl.Lmax)
+        scale = condition_scale(wl, prims=prims, Lmax=wl.Lmax)
+        _C6.update(wl=wl, ref=ref, pairs=pairs_ref, scale=scale)
+    wl, ref = _C6["wl"], _C6["ref"]
+    print(f"[case] c6 sampled {precision}", flush=True)
+    got, pairs, _ = gpu_run(wl, ranges=[(0, 48), (wl.n_data, wl.n_data + 48)], precision=precision, Lmax=wl.Lmax)
+    assert pairs == _C6["pairs"]
+    err, _ = per_multipole_error(got, ref)
+    cerr, _ = conditioned_error(got, ref, _C6["scale"])
+    print(f"[err] c6 {precision}: strict {err:.3e} conditioned {cerr:.3e}", flush=True)
+    assert cerr <= TOL[precision]
