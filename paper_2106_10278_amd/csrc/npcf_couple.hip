@@ -543,9 +543,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 // N = 3 from a term list (line-of-sight basis): job = Lambda,
-//   Z[b1, b2] += sum_i w_i sum_t c_t op1(a_i[b1][s1_t]) op2(a_i[b2][s2_t])
-// (op: conjugation per leg), its Re or Im part (lam_part) on MFMA with
-// K = primaries x terms x {two real products of the complex product}.
+//   Z[b1, b2] += sum_i w_i sum_t c_t part(a_i[b1][s1_t] conj(a_i[b2][s2_t]))
+// with part = Re (lam_part 0) or Im (1), the +-m terms of the basis folded
+// into c_t on the host, on MFMA with K = primaries x terms x {two real
+// products}.
 template <int PREC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3t(CoupleArgs a, int njobs)
 {
@@ -604,16 +605,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                         const float *Ap = Ast + p * rowlen + n * 2 * a.nstate;
                         const float2 x = *reinterpret_cast<const float2 *>(Ap + 2 * tm.s1);
                         const float2 y = *reinterpret_cast<const float2 *>(Ap + 2 * tm.s2);
-                        const float xi = tm.conj1 ? -x.y : x.y;
-                        const float yi = tm.conj2 ? -y.y : y.y;
                         const float wf = wst[p] * tm.coef;
-                        // Re(x y) = xr yr + (-xi) yi;  Im(x y) = xr yi + xi yr
+                        // Re(x conj(y)) = xr yr + xi yi;  Im(x conj(y)) = xi yr + (-xr) yi
                         if (!im) {
-                            Av[i] = c ? -wf * xi : wf * x.x;
-                            Bv[i] = c ? yi : y.x;
+                            Av[i] = c ? wf * x.y : wf * x.x;
+                            Bv[i] = c ? y.y : y.x;
                         } else {
-                            Av[i] = c ? wf * xi : wf * x.x;
-                            Bv[i] = c ? y.x : yi;
+                            Av[i] = c ? -wf * x.x : wf * x.y;
+                            Bv[i] = c ? y.y : y.x;
                         }
                     }
                 }

@@ -346,21 +346,22 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
         if (los) {
             // P^{0L}_{l1 l2} = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0) Y_{l1 m} Y_{l2,-m}
             // (section "Large-Scale Structure"); the prefactor times the 3j symbol is
-            // the Clebsch-Gordan coefficient <l1 m, l2 -m | L 0>.  Legs from the stored
-            // m >= 0 half: a_{l,-m} = (-1)^m conj(a_{l,m}).
+            // the Clebsch-Gordan coefficient c_m = <l1 m, l2 -m | L 0>.  With
+            // a_{l,-m} = (-1)^m conj(a_{l,m}) and c_{-m} = (-1)^{l1+l2+L} c_m, the terms
+            // m and -m (m > 0) add to 2 (-1)^m c_m Re(a1 conj(a2)) (l1+l2+L even) or
+            // i 2 (-1)^m c_m Im(a1 conj(a2)) (odd); m = 0 gives c_0 a1 a2 (real
+            // states).  Terms: m = 0..min(l1, l2), legs (l1, m) and (l2, m).
             const int l1 = lb[0], l2 = lb[1], LL = lb[2];
             t.lam_part[lam] = (l1 + l2 + LL) % 2;
             CoupleGroup g{};
             g.term_begin = (int)t.terms.size();
-            for (int m = -std::min(l1, l2); m <= std::min(l1, l2); m++) {
+            for (int m = 0; m <= std::min(l1, l2); m++) {
                 const double c = clebsch_gordan(l1, m, l2, -m, LL, 0);
                 if (c == 0.0) continue;
                 CoupleTerm tm{};
-                tm.s1 = (int16_t)state_index(3, std::abs(m), l1, 0);
-                tm.conj1 = m < 0;
-                tm.s2 = (int16_t)state_index(3, std::abs(m), l2, 0);
-                tm.conj2 = m > 0;
-                tm.coef = (float)(((m % 2) != 0 ? -1.0 : 1.0) * c);
+                tm.s1 = (int16_t)state_index(3, m, l1, 0);
+                tm.s2 = (int16_t)state_index(3, m, l2, 0);
+                tm.coef = (float)((m > 0 ? 2.0 : 1.0) * ((m % 2) ? -1.0 : 1.0) * c);
                 t.terms.push_back(tm);
             }
             g.term_end = (int)t.terms.size();
