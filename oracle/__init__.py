@@ -12,6 +12,9 @@ conventions of the paper:
   a real field and vec L = 0, even sum of l_{D-1} gives a purely real
   coefficient, odd gives a purely imaginary one, so for D >= 3 the reported
   value is Re (even) or Im (odd); D = 2 coefficients are reported complex.
+* N = 5 (D = 3, section "Hydrodynamic Turbulence"): labels are
+  (l1, l2, l12, l3, l4) and radial tuples (b1, b2, b3, b4); the parity sum is
+  l1 + l2 + l3 + l4.
 """
 from __future__ import annotations
 
@@ -152,7 +155,7 @@ def lambda_labels(D: int, N: int, lmax: int, Lmax=None) -> np.ndarray:
     n = lib.oracle_num_lambda(D, N, lmax)
     if n < 0:
         raise ValueError("unsupported (D, N)")
-    lab = np.zeros((n, 3), dtype=np.int32)
+    lab = np.zeros((n, 5 if N == 5 else 3), dtype=np.int32)
     lib.oracle_lambda_labels(D, N, lmax, _ip(lab))
     return lab
 
@@ -160,7 +163,7 @@ def lambda_labels(D: int, N: int, lmax: int, Lmax=None) -> np.ndarray:
 def btuple_labels(nbins: int, N: int, mode: int = 0) -> np.ndarray:
     lib = _load()
     n = lib.oracle_num_btuples(nbins, N, mode)
-    bt = np.zeros((n, 3), dtype=np.int32)
+    bt = np.zeros((n, 4 if N == 5 else 3), dtype=np.int32)
     lib.oracle_btuple_labels(nbins, N, mode, _ip(bt))
     return bt[:, : N - 1].copy()
 
@@ -181,8 +184,10 @@ def coupling_terms(D: int, N: int, lmax: int, Lmax=None):
         lib.oracle_coupling_terms_los(lmax, Lmax, cnt, _ip(lam), _ip(s), _dp(c))
         return lam, s, c
     cnt = lib.oracle_coupling_terms(D, N, lmax, 0, None, None, None)
+    if cnt < 0:
+        raise ValueError("unsupported (D, N)")
     lam = np.zeros(cnt, dtype=np.int32)
-    s = np.zeros((cnt, 3), dtype=np.int32)
+    s = np.zeros((cnt, 4 if N == 5 else 3), dtype=np.int32)
     c = np.zeros(cnt)
     lib.oracle_coupling_terms(D, N, lmax, cnt, _ip(lam), _ip(s), _dp(c))
     return lam, s, c
@@ -254,6 +259,8 @@ def reported_part(zeta: np.ndarray, labels: np.ndarray, D: int, N: int, los: boo
         return zeta
     if N == 3 and not los:
         tot = 2 * labels[:, 0]
+    elif N == 5:
+        tot = labels[:, 0] + labels[:, 1] + labels[:, 3] + labels[:, 4]
     else:
         tot = labels[:, 0] + labels[:, 1] + labels[:, 2]
     odd = (tot % 2) == 1

@@ -38,7 +38,15 @@
  *      P^{0L}_{l1 l2} = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0) Y_{l1 m} Y_{l2,-m},
  *    whose coefficients follow from the same a^b_[l] with C_m the factor in
  *    front of Y_{l1 m} Y_{l2,-m} (coefficient extraction with the conjugate
- *    basis, as for the isotropic case).
+ *    basis, as for the isotropic case);
+ *  - N = 5 (D = 3 only): the isotropic 5PCF of section "Hydrodynamic
+ *    Turbulence", labels (l1, l2, l12, l3, l4) with the intermediate l12 of the
+ *    first two legs, C the three-CG chain of eq. Coupling-C
+ *      C = sum <l1 m1, l2 m2 | l12 M12> <l12 M12, l3 m3 | l4 M123> <l4 M123, l4 m4 | 0 0>,
+ *    which equals that section's explicit 3-j form with the prefactor
+ *    sqrt(2 l12 + 1) (the printed sqrt(2 l12 - 1) is read as a typo, since the
+ *    CG chain fixes it).  Labels are stored 5 integers each and radial tuples 4
+ *    each for N = 5 (3 each otherwise).
  *
  * The unrestricted sum over secondaries k runs over all n points for every
  * primary (brute force, no cell grid); the self pair is excluded because
@@ -62,6 +70,11 @@ typedef struct {
 } oracle_cfg;
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
+
+/* Integers per Lambda label, per radial tuple and per coupling term. */
+static int lab_width(int N) { return N == 5 ? 5 : 3; }
+static int bt_width(int N) { return N == 5 ? 4 : 3; }
+static int legs(int N) { return N - 1; }
 
 /* ------------------------------------------------------------------------ */
 /* Index sets                                                               */
@@ -282,6 +295,25 @@ static double couple_three_to_zero(int D, const int *s1, const int *s2, const in
     return 0.0;
 }
 
+/* eq. Coupling-C with vec L = 0 and N = 5 (D = 3): the CG chain over the
+ * intermediate M12 and M123, with l123 = l4 (the last CG couples l123 and l4
+ * to zero, which needs l123 = l4). */
+static double couple_four_to_zero(const int *s1, const int *s2, const int *s3, const int *s4, int l12)
+{
+    const int l4 = s4[1];
+    double c = 0.0;
+    for (int M12 = -l12; M12 <= l12; M12++) {
+        double a = oracle_cg3(s1[1], s1[0], s2[1], s2[0], l12, M12);
+        if (a == 0.0) continue;
+        for (int M123 = -l4; M123 <= l4; M123++) {
+            double b = oracle_cg3(l12, M12, s3[1], s3[0], l4, M123);
+            if (b == 0.0) continue;
+            c += a * b * oracle_cg3(l4, M123, l4, s4[0], 0, 0);
+        }
+    }
+    return c;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Output index sets: Lambda labels and radial tuples                       */
 /* ------------------------------------------------------------------------ */
@@ -292,7 +324,10 @@ static double couple_three_to_zero(int D, const int *s1, const int *s2, const in
  *  N = 4, D = 3 : (l1, l2, l3)      triangle |l1-l2| <= l3 <= l1+l2, all <= lmax
  *                 (intermediate l12 = l3 is implied)
  *  N = 4, D = 2 : (l1, l2, l3)      l1 = 0..lmax, l2 = -lmax..lmax, l3 = -l1-l2, |l3| <= lmax
- * Labels are stored with 3 integers each (unused entries 0). */
+ *  N = 5, D = 3 : (l1, l2, l12, l3, l4)  l1, l2, l3, l4 <= lmax, |l1-l2| <= l12 <= l1+l2
+ *                 (l12 bounded by the triangle rule only), |l12-l3| <= l4 <= l12+l3;
+ *                 both parities (odd sums of l give imaginary coefficients)
+ * Labels are stored with 3 integers each (unused entries 0), 5 for N = 5. */
 static int enum_lambda_b(int D, int N, int lmax, int basis, int Lmax, int *lab)
 {
     int cnt = 0;
@@ -322,6 +357,21 @@ static int enum_lambda_b(int D, int N, int lmax, int basis, int Lmax, int *lab)
                     if (lab) { lab[3 * cnt] = l1; lab[3 * cnt + 1] = l2; lab[3 * cnt + 2] = l3; }
                     cnt++;
                 }
+        return cnt;
+    }
+    if (N == 5 && D == 3) {
+        for (int l1 = 0; l1 <= lmax; l1++)
+            for (int l2 = 0; l2 <= lmax; l2++)
+                for (int l12 = abs(l1 - l2); l12 <= l1 + l2; l12++)
+                    for (int l3 = 0; l3 <= lmax; l3++)
+                        for (int l4 = 0; l4 <= lmax; l4++) {
+                            if (l4 < abs(l12 - l3) || l4 > l12 + l3) continue;
+                            if (lab) {
+                                int *o = lab + 5 * cnt;
+                                o[0] = l1; o[1] = l2; o[2] = l12; o[3] = l3; o[4] = l4;
+                            }
+                            cnt++;
+                        }
         return cnt;
     }
     if (N == 4 && D == 2) {
@@ -366,6 +416,17 @@ static int enum_btuples(int nb, int N, int mode, int *bt)
                 }
         return cnt;
     }
+    if (N == 5) {
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++)
+                for (int b3 = 0; b3 < nb; b3++)
+                    for (int b4 = 0; b4 < nb; b4++) {
+                        if (mode == 0 && !(b1 < b2 && b2 < b3 && b3 < b4)) continue;
+                        if (bt) { int *o = bt + 4 * cnt; o[0] = b1; o[1] = b2; o[2] = b3; o[3] = b4; }
+                        cnt++;
+                    }
+        return cnt;
+    }
     return -1;
 }
 
@@ -386,9 +447,25 @@ double oracle_bin_volume(int D, double e0, double e1)
 
 typedef struct {
     int lam;      /* Lambda index */
-    int s[3];     /* state index per leg */
+    int s[4];     /* state index per leg (unused legs -1) */
     double c;     /* coupling coefficient */
 } term_t;
+
+static int push_term(term_t **t, int *cap, int *nt, int lam, const int *s, double c)
+{
+    if (*nt == *cap) {
+        term_t *t2 = (term_t *)realloc(*t, sizeof(term_t) * 2 * (size_t)*cap);
+        if (!t2) return OR_ENOMEM;
+        *t = t2;
+        *cap *= 2;
+    }
+    term_t *o = *t + *nt;
+    o->lam = lam;
+    for (int k = 0; k < 4; k++) o->s[k] = s[k];
+    o->c = c;
+    (*nt)++;
+    return OR_OK;
+}
 
 static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **out, int *nterm_out)
 {
@@ -396,7 +473,8 @@ static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **o
     int nlam = enum_lambda_b(D, N, lmax, basis, Lmax, NULL);
     if (nlam < 0) return OR_EUNSUP;
     int *slab = (int *)malloc(sizeof(int) * (size_t)nst * (D - 1));
-    int *llab = (int *)malloc(sizeof(int) * 3 * (size_t)nlam);
+    const int LW = lab_width(N);
+    int *llab = (int *)malloc(sizeof(int) * LW * (size_t)nlam);
     if (!slab || !llab) { free(slab); free(llab); return OR_ENOMEM; }
     enum_states(D, lmax, slab);
     enum_lambda_b(D, N, lmax, basis, Lmax, llab);
@@ -404,7 +482,32 @@ static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **o
     term_t *t = (term_t *)malloc(sizeof(term_t) * cap);
     if (!t) { free(slab); free(llab); return OR_ENOMEM; }
     for (int L = 0; L < nlam; L++) {
-        const int *lam = llab + 3 * L;
+        const int *lam = llab + (size_t)LW * L;
+        if (N == 5) {
+            /* legs (l1, m1), (l2, m2), (l3, m3), (l4, m4) with m1+m2+m3+m4 = 0
+             * (outside it every CG chain vanishes) */
+            for (int a = 0; a < nst; a++) {
+                const int *sa = slab + (size_t)a * 2;
+                if (sa[1] != lam[0]) continue;
+                for (int b = 0; b < nst; b++) {
+                    const int *sb = slab + (size_t)b * 2;
+                    if (sb[1] != lam[1]) continue;
+                    for (int d = 0; d < nst; d++) {
+                        const int *sd = slab + (size_t)d * 2;
+                        if (sd[1] != lam[3]) continue;
+                        for (int e = 0; e < nst; e++) {
+                            const int *se = slab + (size_t)e * 2;
+                            if (se[1] != lam[4] || sa[0] + sb[0] + sd[0] + se[0] != 0) continue;
+                            double c = couple_four_to_zero(sa, sb, sd, se, lam[2]);
+                            if (c == 0.0) continue;
+                            const int ss[4] = {a, b, d, e};
+                            if (push_term(&t, &cap, &nt, L, ss, c) != OR_OK) { free(t); free(slab); free(llab); return OR_ENOMEM; }
+                        }
+                    }
+                }
+            }
+            continue;
+        }
         for (int a = 0; a < nst; a++) {
             const int *sa = slab + (size_t)a * (D - 1);
             /* leg 1 must carry total angular momentum lam[0] */
@@ -427,8 +530,8 @@ static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **o
                         c = couple_pair_to_zero(D, sa, sb);
                     }
                     if (c == 0.0) continue;
-                    if (nt == cap) { cap *= 2; term_t *nt2 = (term_t *)realloc(t, sizeof(term_t) * cap); if (!nt2) { free(t); free(slab); free(llab); return OR_ENOMEM; } t = nt2; }
-                    t[nt].lam = L; t[nt].s[0] = a; t[nt].s[1] = b; t[nt].s[2] = -1; t[nt].c = c; nt++;
+                    const int ss[4] = {a, b, -1, -1};
+                    if (push_term(&t, &cap, &nt, L, ss, c) != OR_OK) { free(t); free(slab); free(llab); return OR_ENOMEM; }
                     continue;
                 }
                 for (int d = 0; d < nst; d++) {
@@ -437,8 +540,8 @@ static int build_terms_b(int D, int N, int lmax, int basis, int Lmax, term_t **o
                     int l12 = (D == 2) ? 0 : lam[2];
                     double c = couple_three_to_zero(D, sa, sb, sd, l12);
                     if (c == 0.0) continue;
-                    if (nt == cap) { cap *= 2; term_t *nt2 = (term_t *)realloc(t, sizeof(term_t) * cap); if (!nt2) { free(t); free(slab); free(llab); return OR_ENOMEM; } t = nt2; }
-                    t[nt].lam = L; t[nt].s[0] = a; t[nt].s[1] = b; t[nt].s[2] = d; t[nt].c = c; nt++;
+                    const int ss[4] = {a, b, d, -1};
+                    if (push_term(&t, &cap, &nt, L, ss, c) != OR_OK) { free(t); free(slab); free(llab); return OR_ENOMEM; }
                 }
             }
         }
@@ -456,16 +559,17 @@ static int build_terms(int D, int N, int lmax, term_t **out, int *nterm_out)
 }
 
 /* Exposes the coupling terms (for tests): fills up to cap entries of
- * lam[], s[3*i], c[] and returns the total count. */
+ * lam[], s[W*i + k] (W = 4 for N = 5, else 3), c[] and returns the total count. */
 int oracle_coupling_terms(int D, int N, int lmax, int cap, int *lam, int *s, double *c)
 {
     term_t *t = NULL;
     int nt = 0;
     int st = build_terms(D, N, lmax, &t, &nt);
     if (st != OR_OK) return -1;
+    const int W = N == 5 ? 4 : 3;
     for (int i = 0; i < nt && i < cap; i++) {
         lam[i] = t[i].lam;
-        s[3 * i] = t[i].s[0]; s[3 * i + 1] = t[i].s[1]; s[3 * i + 2] = t[i].s[2];
+        for (int k = 0; k < W; k++) s[W * i + k] = t[i].s[k];
         c[i] = t[i].c;
     }
     free(t);
@@ -495,8 +599,10 @@ int oracle_coupling_terms_los(int lmax, int Lmax, int cap, int *lam, int *s, dou
 static int check_cfg(const oracle_cfg *cfg)
 {
     if (!cfg || !cfg->edges) return OR_EINVAL;
-    if (cfg->D < 2 || cfg->D > 4 || cfg->N < 3 || cfg->N > 4) return OR_EUNSUP;
+    if (cfg->D < 2 || cfg->D > 4 || cfg->N < 3 || cfg->N > 5) return OR_EUNSUP;
     if (cfg->N == 4 && cfg->D == 4) return OR_EUNSUP;
+    if (cfg->N == 5 && cfg->D != 3) return OR_EUNSUP;
+    if (cfg->N == 5 && cfg->basis != 0) return OR_EUNSUP;
     if (cfg->basis != 0 && cfg->basis != 1) return OR_EINVAL;
     if (cfg->basis == 1 && (cfg->D != 3 || cfg->N != 3)) return OR_EUNSUP;
     if (cfg->basis == 1 && cfg->Lmax < 0) return OR_EINVAL;
@@ -592,7 +698,8 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
     int nst = enum_states(D, cfg->lmax, NULL);
     int nlam = enum_lambda_b(D, N, cfg->lmax, cfg->basis, cfg->Lmax, NULL);
     int nbt = enum_btuples(nb, N, cfg->btuple_mode, NULL);
-    int *bt = (int *)malloc(sizeof(int) * 3 * (size_t)nbt);
+    const int BW = bt_width(N), NL = legs(N);
+    int *bt = (int *)malloc(sizeof(int) * BW * (size_t)nbt);
     term_t *terms = NULL;
     int nterm = 0;
     if (!bt) return OR_ENOMEM;
@@ -632,15 +739,13 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
                     const term_t *T = terms + t;
                     double *zl = z + 2 * (size_t)T->lam * nbt;
                     for (int q = 0; q < nbt; q++) {
-                        const int *B = bt + 3 * q;
-                        const double *x1 = a + 2 * ((size_t)B[0] * nst + T->s[0]);
-                        const double *x2 = a + 2 * ((size_t)B[1] * nst + T->s[1]);
-                        double pr = x1[0] * x2[0] - x1[1] * x2[1];
-                        double pi = x1[0] * x2[1] + x1[1] * x2[0];
-                        if (N == 4) {
-                            const double *x3 = a + 2 * ((size_t)B[2] * nst + T->s[2]);
-                            double qr = pr * x3[0] - pi * x3[1];
-                            double qi = pr * x3[1] + pi * x3[0];
+                        const int *B = bt + BW * q;
+                        /* product of the legs' a^{b_i}_{[l^i]} */
+                        double pr = 1.0, pi = 0.0;
+                        for (int k = 0; k < NL; k++) {
+                            const double *x = a + 2 * ((size_t)B[k] * nst + T->s[k]);
+                            double qr = pr * x[0] - pi * x[1];
+                            double qi = pr * x[1] + pi * x[0];
                             pr = qr;
                             pi = qi;
                         }

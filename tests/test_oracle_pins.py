@@ -273,6 +273,10 @@ def test_paper_component_counts():
     assert len(oracle.lambda_labels(2, 4, 4)) == g["d2_n4_lmax4_angular"]
     assert len(oracle.btuple_labels(10, 4)) == g["n4_nbins10_radial"]
     assert math.comb(10, 4) == g["n5_nbins10_radial"]
+    assert len(oracle.btuple_labels(10, 5)) == g["n5_nbins10_radial"]
+    lab5 = oracle.lambda_labels(3, 5, 4)
+    even = (lab5[:, 0] + lab5[:, 1] + lab5[:, 3] + lab5[:, 4]) % 2 == 0
+    assert int(even.sum()) == g["n5_lmax4_angular_even"]
 
 
 def test_bin_volumes_sum_to_shell():
@@ -625,3 +629,180 @@ def test_los_rotation_and_parity():
     odd = (lab.sum(axis=1) % 2) == 1
     dropped = np.where(odd[:, None], z0.real, z0.imag)
     assert np.max(np.abs(dropped)) <= 1e-12 * sc
+
+
+# --------------------------------------------------------------------------
+# Isotropic 5PCF (D = 3, N = 5; section "Hydrodynamic Turbulence")
+# --------------------------------------------------------------------------
+
+def _parity_sum5(labels):
+    return labels[:, 0] + labels[:, 1] + labels[:, 3] + labels[:, 4]
+
+
+_W3J = {}
+
+
+def _w3j(*a):
+    if a not in _W3J:
+        _W3J[a] = float(wigner_3j(*a))
+    return _W3J[a]
+
+
+def _explicit_c5(l1, l2, l12, l3, l4, m1, m2, m3, m4):
+    """The section's explicit 5PCF coefficient with the prefactor sqrt(2 l12 + 1):
+    (-1)^{l1+l2+l3+l4} (-1)^{l12-m12} sqrt(2 l12+1) (l1 l2 l12; m1 m2 -m12)(l12 l3 l4; m12 m3 m4)."""
+    m12 = m1 + m2
+    if m12 + m3 + m4 != 0 or abs(m12) > l12:
+        return 0.0
+    return ((-1.0) ** (l1 + l2 + l3 + l4 + l12 - m12) * math.sqrt(2 * l12 + 1)
+            * _w3j(l1, l2, l12, m1, m2, -m12) * _w3j(l12, l3, l4, m12, m3, m4))
+
+
+@pytest.mark.parametrize("lmax", [2, 3])
+def test_5pcf_coupling_is_the_explicit_3j_form(lmax):
+    """The oracle builds C from the CG chain of eq. Coupling-C; it must equal
+    the explicit two-3j form (SymPy) term by term, and list every non-zero
+    term of it."""
+    labels = oracle.lambda_labels(3, 5, lmax)
+    st = oracle.state_labels(3, lmax)
+    lam, s, c = oracle.coupling_terms(3, 5, lmax)
+    got = {}
+    for L, ss, cc in zip(lam, s, c):
+        ms = tuple(int(st[k][0]) for k in ss)
+        assert tuple(int(st[k][1]) for k in ss) == tuple(int(v) for v in labels[L][[0, 1, 3, 4]])
+        got[(int(L),) + ms] = cc
+    nz = 0
+    for L, (l1, l2, l12, l3, l4) in enumerate(labels):
+        l1, l2, l12, l3, l4 = map(int, (l1, l2, l12, l3, l4))
+        for m1 in range(-l1, l1 + 1):
+            for m2 in range(-l2, l2 + 1):
+                for m3 in range(-l3, l3 + 1):
+                    m4 = -m1 - m2 - m3
+                    if abs(m4) > l4:
+                        continue
+                    ref = _explicit_c5(l1, l2, l12, l3, l4, m1, m2, m3, m4)
+                    key = (L, m1, m2, m3, m4)
+                    if abs(ref) < 1e-15:
+                        assert abs(got.get(key, 0.0)) < 1e-13
+                        continue
+                    nz += 1
+                    assert got[key] == pytest.approx(ref, rel=1e-12, abs=1e-14)
+    # terms whose exact value is zero by cancellation appear in the oracle as
+    # rounding noise (checked above to stay below 1e-13); the rest match one to one
+    assert nz == sum(1 for v in got.values() if abs(v) >= 1e-13)
+
+
+def test_5pcf_basis_rotation_invariance_and_parity():
+    """P^0_Lambda of the 5PCF is SO(3)-invariant; P(-r) = P* = (-1)^{l1+l2+l3+l4} P."""
+    lmax = 2
+    lam, s, c = oracle.coupling_terms(3, 5, lmax)
+    labels = oracle.lambda_labels(3, 5, lmax)
+    par = _parity_sum5(labels)
+
+    def P(*dirs):
+        Ys = [oracle.harmonics(3, lmax, d) for d in dirs]
+        out = np.zeros(len(labels), dtype=complex)
+        np.add.at(out, lam, c * Ys[0][s[:, 0]] * Ys[1][s[:, 1]] * Ys[2][s[:, 2]] * Ys[3][s[:, 3]])
+        return out
+
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        dirs = [rand_unit(rng, 3) for _ in range(4)]
+        R = rand_rotation(rng, 3)
+        p0 = P(*dirs)
+        np.testing.assert_allclose(P(*[R @ d for d in dirs]), p0, atol=1e-12)
+        np.testing.assert_allclose(P(*[-d for d in dirs]), ((-1.0) ** par) * p0, atol=1e-12)
+        np.testing.assert_allclose(p0.conj(), ((-1.0) ** par) * p0, atol=1e-12)
+    assert np.max(np.abs(p0[par % 2 == 1])) > 1e-3
+
+
+def _brute_force5(wl, btuple_mode):
+    """Naive 5PCF: unrestricted sum over 4-tuples of secondaries of
+    prod_i w Theta^{b_i}/v_{b_i} conj(P_Lambda), P from SciPy harmonics and the
+    explicit 3j form (independent of the oracle)."""
+    lmax = wl.lmax
+    nb = len(wl.edges) - 1
+    vb = np.array([sphere_area(3) * (wl.edges[b + 1] ** 3 - wl.edges[b] ** 3) / 3 for b in range(nb)])
+    labels = oracle.lambda_labels(3, 5, lmax)
+    coup = []
+    for l1, l2, l12, l3, l4 in labels:
+        l1, l2, l12, l3, l4 = map(int, (l1, l2, l12, l3, l4))
+        terms = []
+        for m1 in range(-l1, l1 + 1):
+            for m2 in range(-l2, l2 + 1):
+                for m3 in range(-l3, l3 + 1):
+                    m4 = -m1 - m2 - m3
+                    if abs(m4) <= l4:
+                        v = _explicit_c5(l1, l2, l12, l3, l4, m1, m2, m3, m4)
+                        if v != 0.0:
+                            terms.append(((l1, m1), (l2, m2), (l3, m3), (l4, m4), v))
+        coup.append(terms)
+    full = np.zeros((len(labels),) + (nb,) * 4, dtype=complex)
+    for j in range(wl.pos.shape[1]):
+        idx, b, d = _neighbours(wl, j)
+        if len(idx) == 0:
+            continue
+        u = d / np.linalg.norm(d, axis=1, keepdims=True)
+        th = np.arccos(np.clip(u[:, 2], -1, 1))
+        ph = np.arctan2(u[:, 1], u[:, 0])
+        Y = {(l, m): (-1.0) ** m * sph_harm_y(l, m, th, ph) for l in range(lmax + 1) for m in range(-l, l + 1)}
+        Bm = np.zeros((len(idx), nb))
+        Bm[np.arange(len(idx)), b] = wl.w[idx] / vb[b]
+        for i, terms in enumerate(coup):
+            pv = np.zeros((len(idx),) * 4, dtype=complex)
+            for k1, k2, k3, k4, v in terms:
+                pv += v * np.multiply.outer(np.multiply.outer(Y[k1], Y[k2]), np.multiply.outer(Y[k3], Y[k4]))
+            full[i] += wl.w[j] * np.einsum("pqrs,pa,qb,rc,sd->abcd", np.conj(pv), Bm, Bm, Bm, Bm, optimize=True)
+    full /= np.prod(wl.box)
+    bt = oracle.btuple_labels(nb, 5, btuple_mode)
+    return full[:, bt[:, 0], bt[:, 1], bt[:, 2], bt[:, 3]]
+
+
+@pytest.mark.parametrize("lmax,n,nbins,mode", [(2, 40, 3, 1), (1, 50, 5, 0)])
+def test_5pcf_separable_equals_naive(lmax, n, nbins, mode):
+    """The paper's naive-vs-separable check for its isotropic 5PCF, to rounding."""
+    wl = inputs.tiny(3, 5, lmax, n, seed=500 + lmax, box_side=8.0, rmax=2.8, nbins=nbins)
+    ref = _brute_force5(wl, mode)
+    got, _ = oracle.npcf(3, 5, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=mode)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+def test_5pcf_l0_is_weighted_count_and_parity():
+    """zeta_{00000}^b = sum_j w_j prod_i W_{b_i}(j) / (V prod v_{b_i} (4 pi)^2);
+    even l1+l2+l3+l4 gives real coefficients, odd imaginary ones."""
+    lmax, nb = 2, 3
+    wl = inputs.tiny(3, 5, lmax, 60, seed=6, box_side=8.0, rmax=3.0, nbins=nb)
+    z, _ = oracle.npcf(3, 5, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1)
+    labels = oracle.lambda_labels(3, 5, lmax)
+    i0 = int(np.nonzero(np.all(labels == 0, axis=1))[0][0])
+    vb = np.array([oracle.bin_volume(3, wl.edges[b], wl.edges[b + 1]) for b in range(nb)])
+    bt = oracle.btuple_labels(nb, 5, 1)
+    ref = np.zeros(len(bt))
+    for j in range(wl.pos.shape[1]):
+        idx, b, _ = _neighbours(wl, j)
+        W = np.bincount(b, weights=wl.w[idx], minlength=nb) / vb
+        ref += wl.w[j] * np.prod(W[bt], axis=1)
+    ref /= np.prod(wl.box) * (4 * math.pi) ** 2
+    np.testing.assert_allclose(z[i0].real, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    par = _parity_sum5(labels)
+    scale = np.abs(z).max()
+    dropped = np.where((par % 2 == 1)[:, None], z.real, z.imag)
+    assert np.max(np.abs(dropped)) < 1e-13 * scale
+    assert np.max(np.abs(z[par % 2 == 1].imag)) > 1e-6 * scale
+
+
+def test_5pcf_lattice_symmetries():
+    """Proper symmetries of the periodic cube leave every 5PCF component
+    unchanged; improper ones flip the odd-parity ones."""
+    lmax = 2
+    wl = inputs.tiny(3, 5, lmax, 40, seed=22, box_side=7.0, rmax=3.0, nbins=3)
+    z, _ = oracle.npcf(3, 5, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1)
+    par = _parity_sum5(oracle.lambda_labels(3, 5, lmax))
+    scale = np.abs(z).max()
+    for perm, flips in [((1, 2, 0), (0, 0, 0)), ((0, 1, 2), (1, 0, 0)), ((2, 0, 1), (1, 1, 0))]:
+        det = np.linalg.det(np.eye(3)[list(perm)]) * np.prod([-1 if f else 1 for f in flips])
+        z2, _ = oracle.npcf(3, 5, lmax, wl.edges, wl.box, _apply_cube_symmetry(wl, perm, flips), wl.w, btuple_mode=1)
+        sign = np.where((par % 2 == 1) & (det < 0), -1.0, 1.0)
+        np.testing.assert_allclose(z2, sign[:, None] * z, atol=1e-12 * scale)
