@@ -9,8 +9,8 @@
  *   zeta^{Lambda, b} = 1/V_D * sum_j w_j sum_{[l^1]..[l^{N-1}]} C^{Lambda;0} prod_i a^{b_i}_{[l^i]}(y_j)
  *   a^b_[l](y_j)     = 1/v_b * sum_k w_k Y*_[l](unit(y_k - y_j)) Theta^b(|y_k - y_j|)
  *
- * for isotropic (vec L = 0) basis states, N in {3, 4}, D in {2, 3, 4}
- * (D = 4 with N = 3 only), flat periodic or open boxes.  The harmonic stage
+ * for isotropic (vec L = 0) basis states, N in {3, 4, 5}, D in {2, 3, 4}
+ * (D = 4 with N = 3 only, N = 5 with D = 3 only), flat periodic or open boxes.  The harmonic stage
  * (the O(n^2) sum defining a) and the coupling stage (the per-primary sum
  * over [l] weighted by the coupling coefficients of eq. Coupling-C) run as
  * hand-written HIP kernels on the plan's stream.
@@ -22,7 +22,10 @@
  *  - index sets |l1| <= l2 <= ... <= l_{D-1} <= lmax (eq. selection-rules);
  *  - coupling to vec L = 0 through the Clebsch-Gordan coefficients of eq.
  *    CG-examples (D = 2: Kronecker delta; D = 3: Wigner 3-j); for D = 4, N = 3
- *    the coupling of two states to zero is (-1)^{l3-l1}/sqrt((l3+1)^2);
+ *    the coupling of two states to zero is (-1)^{l3-l1}/sqrt((l3+1)^2); for
+ *    N = 5 (section "Hydrodynamic Turbulence") the three-CG chain of eq.
+ *    Coupling-C through the intermediate l12, i.e. that section's two-3j
+ *    form with the prefactor sqrt(2 l12 + 1);
  *  - bins: e_b <= r < e_{b+1} on exact lattice distances; v_b the shell
  *    volume |S^{D-1}| (e_{b+1}^D - e_b^D)/D;
  *  - output: for D >= 3 the real part of zeta for even sum of the l_{D-1}
@@ -84,8 +87,8 @@ typedef enum {
 
 typedef struct {
     int D;               /* dimension: 2, 3 or 4 */
-    int N;               /* correlation order: 3 or 4 (N = 4 needs D <= 3) */
-    int lmax;            /* maximum l_{D-1}: D=2 <= 16, D=3 <= 10, D=4 <= 6 */
+    int N;               /* correlation order: 3, 4 or 5 (N = 4 needs D <= 3, N = 5 D = 3) */
+    int lmax;            /* maximum l_{D-1}: D=2 <= 16, D=3 <= 10 (<= 5 for N = 5), D=4 <= 6 */
     int nbins;           /* radial bins, 1..16 */
     const double *edges; /* host, nbins+1 strictly increasing values, edges[0] > 0; copied */
     double box[4];       /* side length per axis (first D used), > 0; V_D = product */
@@ -135,11 +138,14 @@ npcf_status npcf_accumulate(npcf_plan_t plan, const double *pos, const double *w
 npcf_status npcf_finalize(npcf_plan_t plan, double *out, size_t out_len);
 
 /* Describe the output layout.  Any pointer may be NULL.
- *  n_lambda: number of Lambda labels; lambda_labels: int [n_lambda][3]
+ *  n_lambda: number of Lambda labels; lambda_labels: int [n_lambda][3], [n_lambda][5] for N = 5
  *    (N=3, D>=3: (l,0,0); N=3, D=2: (l,-l,0); N=4: (l1,l2,l3), l12 = l3 implied for D = 3,
  *    l3 = -l1-l2 for D = 2; line-of-sight basis: (l1,l2,L), |l1-l2| <= L <= min(l1+l2, Lmax),
- *    Re part reported for even l1+l2+L, Im for odd), lexicographic;
- *  n_bt: number of radial tuples; btuples: int [n_bt][3] (unused entries 0), lexicographic;
+ *    Re part reported for even l1+l2+L, Im for odd; N = 5: (l1,l2,l12,l3,l4) with
+ *    |l1-l2| <= l12 <= l1+l2 (not capped at lmax), |l12-l3| <= l4 <= min(l12+l3, lmax), Re
+ *    reported for even l1+l2+l3+l4, Im for odd), lexicographic;
+ *  n_bt: number of radial tuples; btuples: int [n_bt][3] (unused entries 0), [n_bt][4] for
+ *    N = 5, lexicographic;
  *  out_len: entries npcf_finalize writes. */
 npcf_status npcf_describe(npcf_plan_t plan, int *n_lambda, int *lambda_labels, int *n_bt, int *btuples,
                           size_t *out_len);

@@ -154,8 +154,9 @@ class NPCF:
         nl, nb_ = ctypes.c_int(), ctypes.c_int()
         olen = ctypes.c_size_t()
         _check(lib.npcf_describe(h, ctypes.byref(nl), None, ctypes.byref(nb_), None, ctypes.byref(olen)), "npcf_describe")
-        lab = np.zeros((nl.value, 3), dtype=np.int32)
-        bt = np.zeros((nb_.value, 3), dtype=np.int32)
+        # N = 5: labels (l1, l2, l12, l3, l4) and radial tuples of 4; else 3 each
+        lab = np.zeros((nl.value, 5 if self.N == 5 else 3), dtype=np.int32)
+        bt = np.zeros((nb_.value, 4 if self.N == 5 else 3), dtype=np.int32)
         _check(lib.npcf_describe(h, None, lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), None,
                                  bt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), None), "npcf_describe")
         self.lambda_labels = lab

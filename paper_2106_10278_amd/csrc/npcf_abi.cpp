@@ -105,6 +105,13 @@ struct npcf_plan_s {
     FProd *d_fprods = nullptr;
     float *d_fcoef = nullptr;
     int2 *d_ftasks = nullptr;
+    C5Job *d_c5jobs = nullptr;
+    C5Label *d_c5labels = nullptr;
+    int *d_c5mterm = nullptr;
+    CoupleTerm *d_c5terms = nullptr;
+    int2 *d_c5pairs = nullptr;
+    int *d_c5idx = nullptr;
+    double *d_c5sign = nullptr;
     // stage timing (harmonic, coupling, prep) in ms, accumulated since reset
     std::vector<StageTimer> timers[3];
     int ncu = 256;  // compute units of the plan's device
@@ -176,6 +183,13 @@ npcf_status alloc_cells(npcf_plan_s *p)
 int couple_rows_per_block(const npcf_plan_s *p, int64_t nrows)
 {
     if (p->couple_rows > 0) return ((p->couple_rows + 15) / 16) * 16;
+    if (p->N == 5) {
+        // about 4096 blocks in all, 256 to 4096 primaries each (the partials
+        // hold one accumulator set per row block)
+        int64_t rpb = nrows * (int64_t)p->t.c5jobs.size() / 4096;
+        rpb = ((rpb + 15) / 16) * 16;
+        return (int)std::min<int64_t>(4096, std::max<int64_t>(256, rpb));
+    }
     if (p->N == 4) {
         // about 32k blocks in all, 256 to 1024 primaries each (measured at
         // full size: c2 and c3 are fastest at 512-1024, slower at 64 and 2048)
@@ -320,6 +334,14 @@ CoupleArgs couple_args(const npcf_plan_s *p, int rows)
     a.mtiles = t.mtiles;
     a.max_block_terms = p->max_block_terms;
     a.n3_terms = t.n3_terms ? 1 : 0;
+    if (p->N == 5) {
+        a.c5jobs = p->d_c5jobs;
+        a.nc5jobs = (int)t.c5jobs.size();
+        a.c5labels = p->d_c5labels;
+        a.c5mterm = p->d_c5mterm;
+        a.c5terms = p->d_c5terms;
+        a.c5pairs = p->d_c5pairs;
+    }
     if (p->d_fpairs && !p->term_coupling) {
         a.fpairs = p->d_fpairs;
         a.fgroups = p->d_fgroups;
@@ -664,7 +686,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->nb = cfg->nbins;
     p->cell_subdiv = (p->D == 4) ? 2 : 3;
     const Tables &t = p->t;
-    p->njobs = couple_njobs(p->N, t.nlam, t.nparts, t.mtiles);
+    p->njobs = p->N == 5 ? t.c5tiles : couple_njobs(p->N, t.nlam, t.nparts, t.mtiles);
     if (p->N == 4) {
         // a block's jobs are consecutive and span the Lambdas [lam(first), lam(last)]
         const int jpb = couple_jobs_per_block();
@@ -704,7 +726,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     {
         const int L = p->L;
         const int lds = p->D == 2 ? harmonic_lds_bytes_d2(L) : (p->D == 3 ? harmonic_lds_bytes_d3(L) : harmonic_lds_bytes_d4(L));
-        if (lds <= 0 || lds > 160 * 1024) {
+        if (lds <= 0 || lds > 160 * 1024 || (p->N == 5 && couple5_lds_bytes(p->nb, t.nstate) > 160 * 1024)) {
             delete p;
             return NPCF_E_UNSUPPORTED;
         }
@@ -757,6 +779,15 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         p->d_fcoef = m.get<float>(t.fcoef.size());
         p->d_ftasks = m.get<int2>(t.ftasks.size());
     }
+    if (p->N == 5) {
+        p->d_c5jobs = m.get<C5Job>(t.c5jobs.size());
+        p->d_c5labels = m.get<C5Label>(t.c5labels.size());
+        p->d_c5mterm = m.get<int>(t.c5mterm.size());
+        p->d_c5terms = m.get<CoupleTerm>(t.c5terms.size());
+        p->d_c5pairs = m.get<int2>(t.c5pairs.size());
+        p->d_c5idx = m.get<int>(t.c5idx.size());
+        p->d_c5sign = m.get<double>(t.c5sign.size());
+    }
     if (!m.ok || alloc_cells(p) != NPCF_OK) {
         p->mem.release();
         p->cellmem.release();
@@ -782,6 +813,15 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         if (e == hipSuccess) e = upload(p->d_fprods, t.fprods, s);
         if (e == hipSuccess) e = upload(p->d_fcoef, t.fcoef, s);
         if (e == hipSuccess) e = upload(p->d_ftasks, t.ftasks, s);
+    }
+    if (p->N == 5) {
+        if (e == hipSuccess) e = upload(p->d_c5jobs, t.c5jobs, s);
+        if (e == hipSuccess) e = upload(p->d_c5labels, t.c5labels, s);
+        if (e == hipSuccess) e = upload(p->d_c5mterm, t.c5mterm, s);
+        if (e == hipSuccess) e = upload(p->d_c5terms, t.c5terms, s);
+        if (e == hipSuccess) e = upload(p->d_c5pairs, t.c5pairs, s);
+        if (e == hipSuccess) e = upload(p->d_c5idx, t.c5idx, s);
+        if (e == hipSuccess) e = upload(p->d_c5sign, t.c5sign, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -875,8 +915,12 @@ static npcf_status finalize_from(npcf_plan_t p, const double *acc, const double 
     const Tables &t = p->t;
     if (!out || out_len != (size_t)t.nlam * t.nbt * t.nparts) return NPCF_E_INVALID;
     hipStream_t s = p->stream;
-    NPCF_TRY(launch_finalize2(acc, acc_rand, t.nlam, t.nparts, t.mtiles, p->d_bt_row, p->d_bt_col, p->d_bt_scale, t.nbt,
-                              p->cfg.norm == NPCF_NORM_BY_RANDOMS, t.lam0, p->out_dev, p->bad, s));
+    if (p->N == 5)
+        NPCF_TRY(launch_finalize_idx(acc, acc_rand, p->d_c5idx, p->d_c5sign, p->d_bt_scale, t.nlam, t.nbt,
+                                     p->cfg.norm == NPCF_NORM_BY_RANDOMS, t.lam0, p->out_dev, p->bad, s));
+    else
+        NPCF_TRY(launch_finalize2(acc, acc_rand, t.nlam, t.nparts, t.mtiles, p->d_bt_row, p->d_bt_col, p->d_bt_scale,
+                                  t.nbt, p->cfg.norm == NPCF_NORM_BY_RANDOMS, t.lam0, p->out_dev, p->bad, s));
     NPCF_TRY(hipMemcpyAsync(out, p->out_dev, out_len * sizeof(double), hipMemcpyDeviceToHost, s));
     int bad = 0;
     NPCF_TRY(hipMemcpyAsync(&bad, p->bad, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -634,6 +634,165 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
+// ---------------------------------------------------------------------------
+// N = 5, D = 3 (isotropic 5PCF): job = (l12, beta = b2, S-label group, column
+// group).  Per staged step of 16 primaries and per M = 0..l12 the block forms
+//   S~_M for its rows (S label, b1) with b2 = beta   (VALU, into LDS)
+//   T~_M for its columns (T label, (b3, b4))          (VALU, into LDS)
+// and each wave runs its 16-column tile against every row tile on MFMA with
+// K = 16 primaries x {re, im}: A = (S~r, -S~i), B = (T~r, T~i), so the tile
+// accumulates Re(S~ T~).  Every computed entry is an output of the b-tuple
+// order (b1 < b2 = beta < b3 < b4, or every tuple in the full-tensor mode).
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int rowlen = a.nb * 2 * a.nstate;
+    const int st2 = 2 * a.nstate;
+    float *Ast = reinterpret_cast<float *>(smem);
+    float *wst = Ast + kRowsStep * rowlen;
+    float *Sst = wst + kRowsStep;               // [kC5Rows][kC5Stride]
+    float *Tst = Sst + kC5Rows * kC5Stride;     // [kC5Cols][kC5Stride]
+    int rb, jb;
+    if (!block_work(a.n_rowblocks, a.nc5jobs, rb, jb)) return;
+    const auto jobs = as_const(a.c5jobs);
+    const int l12 = uni(jobs[jb].l12), beta = uni(jobs[jb].beta), nb1 = uni(jobs[jb].nb1);
+    const int s_begin = uni(jobs[jb].s_begin), ns = uni(jobs[jb].ns), t_begin = uni(jobs[jb].t_begin);
+    const int col_begin = uni(jobs[jb].col_begin), ncol = uni(jobs[jb].ncol);
+    const int pair_begin = uni(jobs[jb].pair_begin), npair = uni(jobs[jb].npair);
+    const int nrt = uni(jobs[jb].nrt), tile_begin = uni(jobs[jb].tile_begin);
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int n = lane & 15;   // A row / B column within a tile
+    const int kq = lane >> 4;  // K quarter: primaries 4 kq .. 4 kq + 3
+    const bool has_cols = wave * 16 < ncol;
+
+    // rows and columns no item writes stay zero
+    for (int t = threadIdx.x; t < (kC5Rows + kC5Cols) * kC5Stride; t += blockDim.x) Sst[t] = 0.f;
+
+    double acc[8][4];
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) acc[r][v] = 0.0;
+
+    int r_begin = rb * a.rows_per_block;
+    int r_end = r_begin + a.rows_per_block;
+    if (a.rb_begin) {
+        r_begin = a.rb_begin[rb];
+        r_end = a.rb_end[rb];
+    }
+    if (r_end > a.nrows) r_end = a.nrows;
+
+    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+        __syncthreads();
+        stage_rows(a, r0, r_end, Ast, wst);
+        for (int M = 0; M <= l12; M++) {
+            __syncthreads();
+            // S~ rows: item (S label, primary), every b1 at once
+            for (int it = threadIdx.x; it < ns * kRowsStep; it += blockDim.x) {
+                const int sl = it >> 4, p = it & 15;
+                const C5Label lab = a.c5labels[s_begin + sl];
+                const int tb = a.c5mterm[lab.mt + M], te = a.c5mterm[lab.mt + M + 1];
+                const float *Ap = Ast + p * rowlen;
+                float sr[kMaxBins], si[kMaxBins];
+#pragma unroll
+                for (int b = 0; b < kMaxBins; b++) sr[b] = si[b] = 0.f;
+                for (int t = tb; t < te; t++) {
+                    const CoupleTerm tm = a.c5terms[t];
+                    const float2 y = *reinterpret_cast<const float2 *>(Ap + beta * st2 + 2 * tm.s2);
+                    const float cyr = tm.coef * y.x, cyi = tm.coef * (tm.conj2 ? -y.y : y.y);
+#pragma unroll
+                    for (int b = 0; b < kMaxBins; b++) {
+                        if (b < nb1) {
+                            const float2 x = *reinterpret_cast<const float2 *>(Ap + b * st2 + 2 * tm.s1);
+                            const float xi = tm.conj1 ? -x.y : x.y;
+                            sr[b] += x.x * cyr - xi * cyi;
+                            si[b] += x.x * cyi + xi * cyr;
+                        }
+                    }
+                }
+                const float wp = wst[p];
+#pragma unroll
+                for (int b = 0; b < kMaxBins; b++) {
+                    if (b < nb1) {
+                        float re = sr[b] * wp, im = si[b] * wp;
+                        if (lab.rot) {  // times -i
+                            const float t0 = re;
+                            re = im;
+                            im = -t0;
+                        }
+                        float *dst = Sst + (sl * nb1 + b) * kC5Stride + 2 * p;
+                        dst[0] = re;
+                        dst[1] = -im;
+                    }
+                }
+            }
+            // T~ columns: item (column, primary)
+            for (int it = threadIdx.x; it < ncol * kRowsStep; it += blockDim.x) {
+                const int cl = it >> 4, p = it & 15;
+                const int col = col_begin + cl;
+                const int tl = col / npair;
+                const int2 bb = a.c5pairs[pair_begin + (col - tl * npair)];
+                const C5Label lab = a.c5labels[t_begin + tl];
+                const int tb = a.c5mterm[lab.mt + M], te = a.c5mterm[lab.mt + M + 1];
+                const float *Ap = Ast + p * rowlen;
+                float tr = 0.f, ti = 0.f;
+                for (int t = tb; t < te; t++) {
+                    const CoupleTerm tm = a.c5terms[t];
+                    const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * tm.s1);
+                    const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * tm.s2);
+                    const float xi = tm.conj1 ? -x.y : x.y;
+                    const float yi = tm.conj2 ? -y.y : y.y;
+                    tr += tm.coef * (x.x * y.x - xi * yi);
+                    ti += tm.coef * (x.x * yi + xi * y.x);
+                }
+                if (lab.rot) {
+                    const float t0 = tr;
+                    tr = ti;
+                    ti = -t0;
+                }
+                float *dst = Tst + cl * kC5Stride + 2 * p;
+                dst[0] = tr;
+                dst[1] = ti;
+            }
+            __syncthreads();
+            if (has_cols) {
+                float Bv[8];
+                const float *bp = Tst + (wave * 16 + n) * kC5Stride + 8 * kq;
+#pragma unroll
+                for (int i = 0; i < 8; i++) Bv[i] = bp[i];
+#pragma unroll
+                for (int rt = 0; rt < 8; rt++) {
+                    if (rt < nrt) {
+                        float Av[8];
+                        const float *ap = Sst + (rt * 16 + n) * kC5Stride + 8 * kq;
+#pragma unroll
+                        for (int i = 0; i < 8; i++) Av[i] = ap[i];
+                        v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                        double unscale;
+                        mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+                        for (int v = 0; v < 4; v++) acc[rt][v] += (double)cc[v] * unscale;
+                    }
+                }
+            }
+        }
+    }
+    // per-block partials: partial[rb][tile][16][16]; lane holds rows 4 kq + v of column n
+    if (has_cols) {
+#pragma unroll
+        for (int rt = 0; rt < 8; rt++) {
+            if (rt < nrt) {
+                double *dst = a.partial + ((size_t)rb * ntiles + tile_begin + rt * 4 + wave) * 256;
+#pragma unroll
+                for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc[rt][v];
+            }
+        }
+    }
+}
+
 __global__ void k_reduce_partials(const double *partial, int nrb, int64_t len, double *acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -658,6 +817,22 @@ struct FinArgs {
     double *out;
     int *bad;
 };
+
+__global__ void k_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
+                               const double *bt_scale, int nlam, int nbt, int norm_by_randoms, int lam0, double *out,
+                               int *bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nlam * nbt) return;
+    const int lam = (int)(i / nbt), t = (int)(i % nbt);
+    double v = acc[idx[i]] * sign[lam] * bt_scale[t];
+    if (norm_by_randoms) {
+        const double r = acc_rand[idx[(int64_t)lam0 * nbt + t]] * sign[lam0] * bt_scale[t];
+        if (r == 0.0 || !isfinite(r)) atomicOr(bad, 2);
+        v = v / r;
+    }
+    out[i] = v;
+}
 
 __global__ void k_finalize(FinArgs f)
 {
@@ -699,6 +874,11 @@ hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... a
 
 int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam * nparts * mtiles : nlam * nparts; }
 
+int couple5_lds_bytes(int nb, int nstate)
+{
+    return (kRowsStep * nb * 2 * nstate + kRowsStep + (kC5Rows + kC5Cols) * kC5Stride) * 4;
+}
+
 int couple_jobs_per_block() { return 4 * kJobsPerWave; }
 
 int couple_ftask_groups(int nftasks) { return (nftasks + 3) / 4; }
@@ -713,6 +893,18 @@ int couple_nblocks(int njobs, int nrb)
 hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
                                 hipStream_t s)
 {
+    if (N == 5) {
+        // njobs: the output tiles of the partial layout
+        const int nblk5 = ((a.n_rowblocks + kXcd - 1) / kXcd) * kXcd * a.nc5jobs;
+        const int lds5 = couple5_lds_bytes(a.nb, a.nstate);
+        switch (precision) {
+        case 0: return launch_with_lds(k_couple5<0>, nblk5, lds5, s, a, njobs);
+        case 1: return launch_with_lds(k_couple5<1>, nblk5, lds5, s, a, njobs);
+        case 2: return launch_with_lds(k_couple5<2>, nblk5, lds5, s, a, njobs);
+        case 3: return launch_with_lds(k_couple5<3>, nblk5, lds5, s, a, njobs);
+        default: return hipErrorInvalidValue;
+        }
+    }
     const int lds = couple_lds(a);
     int nblk = couple_nblocks(njobs, a.n_rowblocks);
     if (N == 4 && a.fpairs) {
@@ -758,6 +950,16 @@ hipError_t launch_reduce_partials(const double *partial, int nrb, int64_t len, d
 {
     const int64_t g = (len + 255) / 256;
     hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)g), dim3(256), 0, s, partial, nrb, len, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
+                               const double *bt_scale, int nlam, int nbt, int norm_by_randoms, int lam0, double *out,
+                               int *bad, hipStream_t s)
+{
+    const int64_t total = (int64_t)nlam * nbt;
+    hipLaunchKernelGGL(k_finalize_idx, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, acc, acc_rand, idx, sign,
+                       bt_scale, nlam, nbt, norm_by_randoms, lam0, out, bad);
     return hipGetLastError();
 }
 

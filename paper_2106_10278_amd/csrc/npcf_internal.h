@@ -103,6 +103,34 @@ struct FPair {
 };
 
 // ---------------------------------------------------------------------------
+// Isotropic 5PCF (D = 3, N = 5).  With M = m1 + m2 (folded to M >= 0):
+//   zeta = sgn * sum_i w_i sum_{M >= 0} Re( S~_M[i](b1, b2) T~_M[i](b3, b4) )
+//   S~_M = (-i)^{rot} h_M sum_{m1} (l1 l2 l12; m1, M-m1, -M) a_{l1 m1}[b1] a_{l2, M-m1}[b2]
+//   T~_M = (-i)^{rot} (-1)^{l3+l4} sum_{m3} (l12 l3 l4; M, m3, -M-m3) a_{l3 m3}[b3] a_{l4, -M-m3}[b4]
+// A job is (l12, beta = b2, group of S labels, group of <= kC5Cols columns):
+// GEMM rows (S label, b1), columns (T label, (b3, b4)), K = primaries x {re, im}
+// per M, every computed entry an output of the b-tuple order.
+// ---------------------------------------------------------------------------
+constexpr int kC5Rows = 128;   // GEMM rows of one job (8 tiles)
+constexpr int kC5Cols = 64;    // GEMM columns of one job (one 16-column tile per wave)
+constexpr int kC5Stride = 36;  // floats per staged row/column of S~ / T~ (32 K values + pad)
+constexpr int kLmax5 = 5;
+struct C5Label {   // one S label (l1, l2 | l12) or T label (l3, l4 | l12)
+    int mt;        // terms of M: c5terms[c5mterm[mt + M] .. c5mterm[mt + M + 1]), M = 0..l12
+    int rot;       // 1: multiply by -i (odd l1 + l2, resp. l3 + l4)
+};
+struct C5Job {
+    int l12, beta;
+    int nb1;                 // b1 values of each S label (b1 < nb1)
+    int s_begin, ns;         // S labels [s_begin, s_begin + ns)
+    int t_begin;             // first T label of this l12
+    int col_begin, ncol;     // columns [col_begin, col_begin + ncol): T label col / npair, pair col % npair
+    int pair_begin, npair;   // (b3, b4) pairs of this beta: c5pairs[pair_begin ..)
+    int nrt;                 // row tiles: ceil(ns * nb1 / 16) <= 8
+    int tile_begin;          // output tiles tile_begin + rt * 4 + ct
+};
+
+// ---------------------------------------------------------------------------
 // Coupling stage arguments.
 // ---------------------------------------------------------------------------
 // One coupling term of a (Lambda, group) GEMM K-slice: S += coef * op1(a[s1]) * op2(a[s2]).
@@ -156,6 +184,13 @@ struct CoupleArgs {
     // N = 3 with a term list per Lambda (line-of-sight basis): one group per
     // Lambda, terms (s1, conj1, s2, conj2, coef) pairing a[b1] with a[b2]
     int n3_terms;
+    // N = 5 (see C5Job); the output tiles are the "jobs" of the partial layout
+    const C5Job *c5jobs;
+    int nc5jobs;
+    const C5Label *c5labels;
+    const int *c5mterm;
+    const CoupleTerm *c5terms;
+    const int2 *c5pairs;
 };
 
 // ---------------------------------------------------------------------------
@@ -201,6 +236,12 @@ hipError_t launch_reduce_partials(const double *partial, int nrb, int64_t len, d
 hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam, int nparts, int mtiles,
                             const int *bt_row, const int *bt_col, const double *bt_scale, int nbt, int norm_by_randoms,
                             int lam0, double *out, int *bad, hipStream_t s);
+// finalize from an accumulator index per output (N = 5): out[lam * nbt + t] =
+// acc[idx[lam * nbt + t]] * sign[lam] * bt_scale[t] (optionally over the randoms' Lambda = 0)
+hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
+                               const double *bt_scale, int nlam, int nbt, int norm_by_randoms, int lam0, double *out,
+                               int *bad, hipStream_t s);
+int couple5_lds_bytes(int nb, int nstate);
 
 // ---------------------------------------------------------------------------
 // Host planner (npcf_plan.cpp)
@@ -208,8 +249,9 @@ hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam,
 struct Tables {
     int nstate = 0;
     std::vector<int> state_lab;        // [nstate][3]: (l1, l2, l3) as applicable
-    std::vector<int> lam_lab;          // [nlam][3]
-    std::vector<int> bt_lab;           // [nbt][3]
+    std::vector<int> lam_lab;          // [nlam][lab_w]
+    std::vector<int> bt_lab;           // [nbt][bt_w]
+    int lab_w = 3, bt_w = 3;           // 5 and 4 for N = 5
     int nlam = 0, nbt = 0, nparts = 1;
     std::vector<int> lam_part;         // [nlam]
     std::vector<CoupleTerm> terms;
@@ -233,10 +275,20 @@ struct Tables {
     std::vector<float> fcoef;
     std::vector<int2> ftasks;
     bool n3_terms = false;             // N = 3 coupling from a term list (line-of-sight basis)
+    // N = 5 (empty otherwise)
+    std::vector<C5Label> c5labels;
+    std::vector<int> c5mterm;
+    std::vector<CoupleTerm> c5terms;
+    std::vector<int2> c5pairs;
+    std::vector<C5Job> c5jobs;
+    int c5tiles = 0;                   // output tiles (accumulator = c5tiles x 256 doubles)
+    std::vector<int> c5idx;            // [nlam][nbt] accumulator index of each output
+    std::vector<double> c5sign;        // [nlam]
 };
 
 // Validates cfg and fills the tables; returns NPCF_OK or an error code and a message.
 npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err);
 double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M);
+double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
 
 }  // namespace npcf

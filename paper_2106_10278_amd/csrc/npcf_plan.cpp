@@ -163,7 +163,148 @@ double dim_so(int D, int l)
     return (double)(l + 1) * (l + 1);
 }
 
+// Isotropic 5PCF tables (see C5Job): per l12 the S labels (l1, l2) and T
+// labels (l3, l4) that couple to it, their per-M term lists, the jobs, and the
+// accumulator index and sign of every output (Lambda, b-tuple).
+bool build_c5(Tables &t, int L, int nb, int mode)
+{
+    const int L12 = 2 * L;
+    std::vector<std::vector<int2>> pl(L12 + 1);
+    for (int l12 = 0; l12 <= L12; l12++)
+        for (int la = 0; la <= L; la++)
+            for (int lb = 0; lb <= L; lb++)
+                if (std::abs(la - lb) <= l12 && l12 <= la + lb) pl[l12].push_back(make_int2(la, lb));
+    // a leg a_{l m} from the stored m >= 0 half: a_{l,-m} = (-1)^m conj(a_{l m})
+    auto push_term = [&](int ma, int la, int mb, int lb, double c) {
+        CoupleTerm tm{};
+        double sg = 1.0;
+        tm.s1 = (int16_t)state_index(3, std::abs(ma), la, 0);
+        tm.conj1 = ma < 0;
+        if (ma < 0 && (-ma) % 2) sg = -sg;
+        tm.s2 = (int16_t)state_index(3, std::abs(mb), lb, 0);
+        tm.conj2 = mb < 0;
+        if (mb < 0 && (-mb) % 2) sg = -sg;
+        tm.coef = (float)(sg * c);
+        t.c5terms.push_back(tm);
+    };
+    std::vector<int> s_first(L12 + 1), t_first(L12 + 1);
+    for (int l12 = 0; l12 <= L12; l12++)
+        for (int side = 0; side < 2; side++) {
+            (side == 0 ? s_first : t_first)[l12] = (int)t.c5labels.size();
+            for (const int2 pr : pl[l12]) {
+                const int la = pr.x, lb = pr.y;
+                const double par = ((la + lb) % 2) ? -1.0 : 1.0;
+                C5Label lab{};
+                lab.mt = (int)t.c5mterm.size();
+                lab.rot = (la + lb) % 2;
+                for (int M = 0; M <= l12; M++) {
+                    t.c5mterm.push_back((int)t.c5terms.size());
+                    if (side == 0) {
+                        // S_M: the first 3-j of the section's 5PCF form with m12 = M, times
+                        // (-1)^{l1+l2} sqrt(2 l12 + 1) (-1)^{l12-M} and the +-M fold (2 for M > 0)
+                        const double h = par * std::sqrt(2.0 * l12 + 1.0) * (((l12 - M) % 2) ? -1.0 : 1.0) * (M > 0 ? 2.0 : 1.0);
+                        for (int m1 = -la; m1 <= la; m1++) {
+                            const int m2 = M - m1;
+                            if (std::abs(m2) > lb) continue;
+                            const double c = wigner3j(la, lb, l12, m1, m2, -M);
+                            if (c != 0.0) push_term(m1, la, m2, lb, h * c);
+                        }
+                    } else {
+                        // T_M: the second 3-j with m12 = M, times (-1)^{l3+l4}
+                        for (int m3 = -la; m3 <= la; m3++) {
+                            const int m4 = -M - m3;
+                            if (std::abs(m4) > lb) continue;
+                            const double c = wigner3j(l12, la, lb, M, m3, m4);
+                            if (c != 0.0) push_term(m3, la, m4, lb, par * c);
+                        }
+                    }
+                }
+                t.c5mterm.push_back((int)t.c5terms.size());
+                t.c5labels.push_back(lab);
+            }
+        }
+    // radial pairs (b3, b4) of each beta, and the jobs of each (l12, beta)
+    std::vector<int> pair_begin(nb), npair(nb), pidx(nb * nb * nb, -1);
+    for (int beta = 0; beta < nb; beta++) {
+        pair_begin[beta] = (int)t.c5pairs.size();
+        for (int b3 = 0; b3 < nb; b3++)
+            for (int b4 = 0; b4 < nb; b4++) {
+                if (mode == 0 && !(beta < b3 && b3 < b4)) continue;
+                pidx[(beta * nb + b3) * nb + b4] = (int)t.c5pairs.size() - pair_begin[beta];
+                t.c5pairs.push_back(make_int2(b3, b4));
+            }
+        npair[beta] = (int)t.c5pairs.size() - pair_begin[beta];
+    }
+    if (t.c5pairs.empty()) t.c5pairs.push_back(make_int2(0, 0));
+    std::vector<int> first_job((L12 + 1) * nb, -1), spg_of((L12 + 1) * nb, 1), ncg_of((L12 + 1) * nb, 1);
+    t.c5tiles = 0;
+    for (int l12 = 0; l12 <= L12; l12++)
+        for (int beta = 0; beta < nb; beta++) {
+            const int nb1 = mode == 0 ? beta : nb;
+            const int ns_all = (int)pl[l12].size();
+            if (nb1 == 0 || npair[beta] == 0 || ns_all == 0) continue;
+            const int spg = std::max(1, kC5Rows / nb1);
+            const int ncol_all = ns_all * npair[beta];
+            const int ncg = (ncol_all + kC5Cols - 1) / kC5Cols;
+            first_job[l12 * nb + beta] = (int)t.c5jobs.size();
+            spg_of[l12 * nb + beta] = spg;
+            ncg_of[l12 * nb + beta] = ncg;
+            for (int s0 = 0; s0 < ns_all; s0 += spg)
+                for (int cg = 0; cg < ncg; cg++) {
+                    C5Job j{};
+                    j.l12 = l12;
+                    j.beta = beta;
+                    j.nb1 = nb1;
+                    j.s_begin = s_first[l12] + s0;
+                    j.ns = std::min(spg, ns_all - s0);
+                    j.t_begin = t_first[l12];
+                    j.col_begin = cg * kC5Cols;
+                    j.ncol = std::min(kC5Cols, ncol_all - j.col_begin);
+                    j.pair_begin = pair_begin[beta];
+                    j.npair = npair[beta];
+                    j.nrt = (j.ns * nb1 + 15) / 16;
+                    j.tile_begin = t.c5tiles;
+                    t.c5tiles += j.nrt * 4;
+                    t.c5jobs.push_back(j);
+                }
+        }
+    if ((int64_t)t.c5tiles * 256 > (int64_t)INT32_MAX || (int64_t)t.nlam * t.nbt > (1LL << 28)) return false;
+    // accumulator index and sign of every output
+    t.c5sign.assign(t.nlam, 1.0);
+    t.c5idx.assign((size_t)t.nlam * t.nbt, 0);
+    for (int lam = 0; lam < t.nlam; lam++) {
+        const int *lb = &t.lam_lab[5 * lam];
+        const int l12 = lb[2];
+        int s = -1, tt = -1;
+        for (int k = 0; k < (int)pl[l12].size(); k++) {
+            if (pl[l12][k].x == lb[0] && pl[l12][k].y == lb[1]) s = k;
+            if (pl[l12][k].x == lb[3] && pl[l12][k].y == lb[4]) tt = k;
+        }
+        // Re(S~ T~) is -Re(S T) when both phases are -i (even parity, odd l1 + l2)
+        if (((lb[0] + lb[1]) % 2) && ((lb[3] + lb[4]) % 2)) t.c5sign[lam] = -1.0;
+        for (int q = 0; q < t.nbt; q++) {
+            const int *B = &t.bt_lab[4 * q];
+            const int beta = B[1], key = l12 * nb + beta;
+            const int nb1 = mode == 0 ? beta : nb;
+            const int col = tt * npair[beta] + pidx[(beta * nb + B[2]) * nb + B[3]];
+            const int sg = s / spg_of[key], cg = col / kC5Cols;
+            const C5Job &j = t.c5jobs[first_job[key] + sg * ncg_of[key] + cg];
+            const int row = (s - (j.s_begin - s_first[l12])) * nb1 + B[0];
+            const int cl = col - j.col_begin;
+            t.c5idx[(size_t)lam * t.nbt + q] = (j.tile_begin + (row / 16) * 4 + cl / 16) * 256 + (row % 16) * 16 + cl % 16;
+        }
+    }
+    return true;
+}
+
 }  // namespace
+
+double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3)
+{
+    // (j1 j2 j3; m1 m2 m3) = (-1)^{j1-j2-m3} <j1 m1, j2 m2 | j3, -m3> / sqrt(2 j3 + 1)
+    const double cg = clebsch_gordan(j1, m1, j2, m2, j3, -m3);
+    return (((j1 - j2 - m3) % 2) ? -cg : cg) / std::sqrt(2.0 * j3 + 1.0);
+}
 
 // <j1 m1, j2 m2 | J M> by Racah's closed form for the Clebsch-Gordan
 // coefficient (sum over k with all factorial arguments non-negative).
@@ -188,10 +329,12 @@ double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M)
 npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
 {
     const int D = cfg.D, N = cfg.N, L = cfg.lmax, nb = cfg.nbins;
-    if (D < 2 || D > 4 || (N != 3 && N != 4)) { err = "D must be 2..4 and N 3 or 4"; return NPCF_E_UNSUPPORTED; }
+    if (D < 2 || D > 4 || N < 3 || N > 5) { err = "D must be 2..4 and N 3, 4 or 5"; return NPCF_E_UNSUPPORTED; }
     if (N == 4 && D == 4) { err = "N = 4 needs D <= 3 (no SO(4) coupling table)"; return NPCF_E_UNSUPPORTED; }
+    if (N == 5 && D != 3) { err = "N = 5 needs D = 3"; return NPCF_E_UNSUPPORTED; }
     if (L < 0) { err = "lmax must be >= 0"; return NPCF_E_INVALID; }
     if (L > kLmaxD[D]) { err = "lmax above the supported maximum for this D"; return NPCF_E_UNSUPPORTED; }
+    if (N == 5 && L > kLmax5) { err = "lmax above 5 for N = 5"; return NPCF_E_UNSUPPORTED; }
     if (nb < 1) { err = "nbins must be >= 1"; return NPCF_E_INVALID; }
     if (nb > kMaxBins) { err = "nbins above 16"; return NPCF_E_UNSUPPORTED; }
     if (!cfg.edges) { err = "edges is NULL"; return NPCF_E_INVALID; }
@@ -211,6 +354,8 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     if (cfg.basis != NPCF_BASIS_ISOTROPIC && cfg.basis != NPCF_BASIS_LINE_OF_SIGHT) { err = "unknown basis"; return NPCF_E_INVALID; }
     const bool los = cfg.basis == NPCF_BASIS_LINE_OF_SIGHT;
     if (los && (D != 3 || N != 3)) { err = "the line-of-sight basis needs D = 3, N = 3"; return NPCF_E_UNSUPPORTED; }
+    t.lab_w = N == 5 ? 5 : 3;
+    t.bt_w = N == 5 ? 4 : 3;
     if (los && (cfg.Lmax < 0 || cfg.Lmax > 2 * L)) { err = "Lmax must be 0..2 lmax"; return NPCF_E_INVALID; }
     t.n3_terms = los;
 
@@ -239,6 +384,14 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
                     t.lam_lab.push_back(l2);
                     t.lam_lab.push_back(LL);
                 }
+    } else if (N == 5) {
+        // (l1, l2, l12, l3, l4): l12 by the triangle rule only, l4 <= lmax
+        for (int l1 = 0; l1 <= L; l1++)
+            for (int l2 = 0; l2 <= L; l2++)
+                for (int l12 = std::abs(l1 - l2); l12 <= l1 + l2; l12++)
+                    for (int l3 = 0; l3 <= L; l3++)
+                        for (int l4 = std::abs(l12 - l3); l4 <= std::min(L, l12 + l3); l4++)
+                            t.lam_lab.insert(t.lam_lab.end(), {l1, l2, l12, l3, l4});
     } else if (N == 3) {
         for (int l = 0; l <= L; l++) {
             t.lam_lab.push_back(l);
@@ -263,11 +416,11 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
                 t.lam_lab.push_back(l3);
             }
     }
-    t.nlam = (int)t.lam_lab.size() / 3;
+    t.nlam = (int)t.lam_lab.size() / t.lab_w;
     t.nparts = (D == 2) ? 2 : 1;
     t.lam0 = 0;
     for (int i = 0; i < t.nlam; i++)
-        if (t.lam_lab[3 * i] == 0 && t.lam_lab[3 * i + 1] == 0 && t.lam_lab[3 * i + 2] == 0) {
+        if (std::all_of(&t.lam_lab[t.lab_w * i], &t.lam_lab[t.lab_w * (i + 1)], [](int v) { return v == 0; })) {
             t.lam0 = i;
             break;
         }
@@ -277,7 +430,16 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     t.row_pairs.clear();
     t.bt_row.clear();
     t.bt_col.clear();
-    if (N == 3) {
+    if (N == 5) {
+        for (int b1 = 0; b1 < nb; b1++)
+            for (int b2 = 0; b2 < nb; b2++)
+                for (int b3 = 0; b3 < nb; b3++)
+                    for (int b4 = 0; b4 < nb; b4++) {
+                        if (cfg.btuple_mode == 0 && !(b1 < b2 && b2 < b3 && b3 < b4)) continue;
+                        t.bt_lab.insert(t.bt_lab.end(), {b1, b2, b3, b4});
+                    }
+        t.row_pairs.push_back(make_int2(0, 0));
+    } else if (N == 3) {
         for (int b1 = 0; b1 < nb; b1++)
             for (int b2 = 0; b2 < nb; b2++) {
                 if (cfg.btuple_mode == 0 && !(b1 < b2)) continue;
@@ -307,7 +469,7 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
         t.mtiles = std::max(1, (t.mrows + 15) / 16);
         if (t.row_pairs.empty()) t.row_pairs.push_back(make_int2(0, 0));
     }
-    t.nbt = (int)t.bt_lab.size() / 3;
+    t.nbt = (int)t.bt_lab.size() / t.bt_w;
 
     // ---- bins ------------------------------------------------------------------
     const double area = 2.0 * std::pow(M_PI, 0.5 * D) / std::tgamma(0.5 * D);
@@ -320,7 +482,7 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     t.bt_scale.resize(t.nbt);
     for (int i = 0; i < t.nbt; i++) {
         double p = VD;
-        for (int k = 0; k < N - 1; k++) p *= t.vb[t.bt_lab[3 * i + k]];
+        for (int k = 0; k < N - 1; k++) p *= t.vb[t.bt_lab[t.bt_w * i + k]];
         t.bt_scale[i] = 1.0 / p;
     }
     t.e2lo_f = (float)(t.e2[0] * (1.0 - 1e-5));
@@ -341,6 +503,17 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     t.groups.clear();
     t.lam_group_begin.assign(1, 0);
     t.lam_part.assign(t.nlam, 0);
+    if (N == 5) {
+        for (int lam = 0; lam < t.nlam; lam++) {
+            const int *lb = &t.lam_lab[5 * lam];
+            t.lam_part[lam] = (lb[0] + lb[1] + lb[3] + lb[4]) % 2;
+        }
+        t.terms.push_back(CoupleTerm{});
+        t.groups.push_back(CoupleGroup{});
+        t.lam_group_begin.push_back(1);
+        if (!build_c5(t, L, nb, cfg.btuple_mode)) { err = "too many outputs for N = 5"; return NPCF_E_UNSUPPORTED; }
+        return NPCF_OK;
+    }
     for (int lam = 0; lam < t.nlam; lam++) {
         const int *lb = &t.lam_lab[3 * lam];
         if (los) {

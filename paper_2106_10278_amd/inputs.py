@@ -15,6 +15,8 @@ turbulence simulations); none of those data sets is used.  Recipes:
 * ``clustered``  -- Poisson-sampled Gaussian blobs: ``n_blob`` points, each
   picks one of ``n_centres`` uniform centres and is offset by N(0, sigma^2) per
   axis (wrapped), plus ``n_uniform`` uniform background points.
+* the isotropic 5PCF workload uses ``uniform`` in a unit cube, as the
+  paper's 5PCF timing test does.
 * ``vorticity_tracers`` (D = 2) -- points drawn with density proportional to
   exp(omega) for a random-phase field omega on a grid, whose per-mode
   amplitude falls as 1/|k| (shell energy spectrum ~ k^-3), normalised to
@@ -134,6 +136,16 @@ def c6_los_3pcf(seed: int = 1006, n_data: int = 200_000, n_rand: int = 600_000) 
     w = np.concatenate([np.ones(n_data), np.full(n_rand, -1.0 / 3.0)])
     return Workload(f"D3-N3-los-Lmax6-rsd-{n_data // 1000}k+{n_rand // 1000}k-randoms", 3, 3, 5,
                     np.linspace(20.0, 160.0, 11), list(box), pos, w, n_data, Lmax=6)
+
+
+def c7_uniform_5pcf(seed: int = 1007, n: int = 100_000) -> Workload:
+    """D=3, N=5 (isotropic 5PCF): n uniform points in a periodic unit cube,
+    w = 1, 10 linear bins in [0.1, 0.4], lmax = 4 -- the setting of the paper's
+    5PCF timing test (section "Hydrodynamic Turbulence"), at a fixed n."""
+    rng = np.random.default_rng(seed)
+    box = [1.0] * 3
+    pos = uniform(rng, n, box)
+    return Workload(f"D3-N5-uniform-{n // 1000}k", 3, 5, 4, np.linspace(0.1, 0.4, 11), box, pos, np.ones(n), n)
 
 
 def c3_vorticity_4pcf(seed: int = 1003, n: int = 500_000, grid: int = 1024) -> Workload:

@@ -33,6 +33,15 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
     w = np.abs(wl.w if prims is None else wl.w[prims])
     A = np.abs(a)
     out = np.zeros((nlam, len(bts)))
+    if wl.N == 5:
+        # four legs: gather the b-tuples' legs per chunk of terms
+        for t0 in range(0, len(lam), 4096):
+            sl = slice(t0, t0 + 4096)
+            X = w[:, None, None] * A[:, bts[:, 0]][:, :, s[sl, 0]]
+            for k in range(1, 4):
+                X = X * A[:, bts[:, k]][:, :, s[sl, k]]
+            np.add.at(out, lam[sl], np.abs(c[sl])[:, None] * X.sum(axis=0).T)
+        return out / float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
     for t in range(len(lam)):
         if wl.N == 3:
             m = np.einsum("i,ij,ik->jk", w, A[:, :, s[t, 0]], A[:, :, s[t, 1]])

@@ -1,0 +1,93 @@
+"""GPU parity of the isotropic 5PCF (D = 3, N = 5; section "Hydrodynamic
+Turbulence"): the N = 5 coupling kernel (S~ and T~ formed per M in LDS, one
+MFMA GEMM per (l12, b2) block) against the FP64 oracle on the same seeded
+inputs, per multipole, with the conditioned measure and the tolerances of
+the other parity tests."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_10278_amd import inputs
+from npcf_testutil import condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"plain": 1e-6, "mixed_fp16": 1e-5, "mixed_bf16x6": 1e-5, "mixed_bf16": 5e-5}
+
+
+@pytest.mark.parametrize("lmax,nbins,mode,n", [(2, 5, 0, 300), (3, 6, 0, 300), (2, 3, 1, 200), (4, 5, 0, 250),
+                                               (1, 16, 0, 400)])
+@pytest.mark.parametrize("precision", ["plain", "mixed_fp16", "mixed_bf16x6", "mixed_bf16"])
+def test_5pcf_parity(lmax, nbins, mode, n, precision):
+    wl = inputs.tiny(3, 5, lmax, n, seed=70 + lmax + nbins, box_side=10.0, rmax=4.0, nbins=nbins)
+    print(f"[case] 5pcf lmax={lmax} nbins={nbins} mode={mode} n={n} {precision}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl, btuple_mode=mode)
+    got, pairs, plan = gpu_run(wl, precision=precision, btuple_mode=mode)
+    assert np.array_equal(plan.lambda_labels, oracle.lambda_labels(3, 5, lmax))
+    assert np.array_equal(plan.btuples, oracle.btuple_labels(nbins, 5, mode))
+    assert pairs == pairs_ref
+    scale = condition_scale(wl, mode)
+    cerr, _ = conditioned_error(got, ref, scale)
+    err, _ = per_multipole_error(got, ref)
+    print(f"[err] 5pcf lmax={lmax} nbins={nbins} mode={mode} {precision}: strict {err:.3e} conditioned {cerr:.3e}",
+          flush=True)
+    assert cerr <= TOL[precision]
+
+
+def test_5pcf_chunked_primaries_and_randoms_norm():
+    """Disjoint primary ranges add up (eq. NPCF-estimator-discrete sums over
+    primaries), and the randoms normalisation divides by the randoms' Lambda = 0."""
+    wl = inputs.tiny(3, 5, 2, 300, seed=81, box_side=10.0, rmax=4.0, nbins=5)
+    print("[case] 5pcf chunked + randoms norm", flush=True)
+    whole, _, _ = gpu_run(wl)
+    parts, _, _ = gpu_run(wl, ranges=[(0, 97), (97, 211), (211, 300)])
+    scale = condition_scale(wl)
+    cerr, _ = conditioned_error(parts, whole, scale)
+    assert cerr <= 1e-6
+    import torch
+    from paper_2106_10278_amd import NPCF
+    plan = NPCF(3, 5, 2, wl.edges, wl.box, norm="by_randoms", max_points=300)
+    pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).to("cuda:0")
+    w = torch.from_numpy(np.ascontiguousarray(wl.w)).to("cuda:0")
+    plan.accumulate(pos, w, role="data")
+    ones = torch.ones_like(w)
+    plan.accumulate(pos, ones, role="randoms")
+    got = plan.finalize()
+    rr, _, _ = gpu_run(inputs.Workload(wl.name, 3, 5, 2, wl.edges, wl.box, wl.pos, np.ones(300), 300))
+    ref = whole / rr[0][None, :]
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=0)
+
+
+def test_5pcf_rejects():
+    from paper_2106_10278_amd import NPCF, NPCFError
+    e = np.linspace(1.0, 4.0, 6)
+    with pytest.raises(NPCFError):
+        NPCF(2, 5, 2, e, [10.0, 10.0], max_points=50)   # N = 5 needs D = 3
+    with pytest.raises(NPCFError):
+        NPCF(3, 5, 6, e, [10.0] * 3, max_points=50)     # lmax above 5
+    with pytest.raises(NPCFError):
+        NPCF(3, 5, 2, e, [10.0] * 3, max_points=50, Lmax=2)
+
+
+_C7 = {}
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed_fp16", "mixed_bf16x6"])
+def test_c7_full_catalogue_sampled(precision):
+    """The 5PCF workload at full size (100k uniform points, lmax 4, 10 bins):
+    32 primaries against every secondary, in the benchmark's launch
+    configuration, against the oracle on the same primaries."""
+    if "wl" not in _C7:
+        wl = inputs.c7_uniform_5pcf()
+        prims = np.arange(0, 32)
+        ref, pairs_ref, _ = oracle_reported(wl, prims=prims)
+        scale = condition_scale(wl, prims=prims)
+        _C7.update(wl=wl, ref=ref, pairs=pairs_ref, scale=scale)
+    wl, ref = _C7["wl"], _C7["ref"]
+    print(f"[case] c7 sampled {precision}", flush=True)
+    got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)
+    assert pairs == _C7["pairs"]
+    err, _ = per_multipole_error(got, ref)
+    cerr, _ = conditioned_error(got, ref, _C7["scale"])
+    print(f"[err] c7 {precision}: strict {err:.3e} conditioned {cerr:.3e}", flush=True)
+    assert cerr <= TOL[precision]
