@@ -64,7 +64,9 @@ def _plan(lib, **kw):
 @pytest.mark.parametrize("kw,expect", [
     (dict(D=5), binding.NPCF_E_UNSUPPORTED),
     (dict(D=1), binding.NPCF_E_UNSUPPORTED),
-    (dict(N=5), binding.NPCF_E_UNSUPPORTED),
+    (dict(N=6), binding.NPCF_E_UNSUPPORTED),
+    (dict(D=2, N=5), binding.NPCF_E_UNSUPPORTED),        # N = 5 needs D = 3
+    (dict(N=5, lmax=6), binding.NPCF_E_UNSUPPORTED),     # lmax above 5 for N = 5
     (dict(D=4, N=4), binding.NPCF_E_UNSUPPORTED),
     (dict(lmax=-1), binding.NPCF_E_INVALID),
     (dict(D=3, lmax=11), binding.NPCF_E_UNSUPPORTED),
