@@ -74,6 +74,8 @@ def make_workload(name: str):
         return inputs.c5_hyper_3pcf()
     if name == "c6":
         return inputs.c6_los_3pcf()
+    if name == "c7":
+        return inputs.c7_uniform_5pcf()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -303,7 +305,8 @@ def main():
     cands = [p for p in MIXED if p in results and (errs is None or errs[p]["max_rel_err"] <= 1e-5)]
     if errs is None:
         cands = [p for p in ("mixed_fp16",) if p in results] or cands
-    head = max(cands, key=lambda p: results[p]["pairs_per_s"]) if cands else list(results)[0]
+    head = (max(cands, key=lambda p: results[p]["pairs_per_s"]) if cands
+            else ("plain" if "plain" in results else list(results)[0]))
     r = results[head]
     key = f"D{wl.D}-N{wl.N}-lmax{wl.lmax}-{wl.name}"
     fpp = flops_per_pair(wl.D, wl.lmax)

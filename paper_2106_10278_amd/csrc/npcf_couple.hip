@@ -634,6 +634,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
+// FP16 hi + lo slice with a power-of-two scale per A row and per B column
+// (lanes n, n+16, n+32, n+48 hold one row / column): used where a tile mixes
+// rows of very different size, which one scale per tile would push into
+// FP16's subnormal range.  c[v] (row 4 kq + v, column n) is returned unscaled
+// in FP64 in out[v].
+__device__ __forceinline__ float pow2_scale(float m)
+{
+    if (!(m > 0.f) || !isfinite(m)) return 1.f;
+    int e;
+    frexpf(m, &e);
+    return ldexpf(1.f, -e);
+}
+
+__device__ __forceinline__ void mfma_k32_f16_rowscaled(const float (&Av)[8], const float (&Bv)[8], int kq, double (&out)[4])
+{
+    float ma = 0.f, mb = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        ma = fmaxf(ma, fabsf(Av[i]));
+        mb = fmaxf(mb, fabsf(Bv[i]));
+    }
+    ma = fmaxf(ma, __shfl_xor(ma, 16));
+    ma = fmaxf(ma, __shfl_xor(ma, 32));
+    mb = fmaxf(mb, __shfl_xor(mb, 16));
+    mb = fmaxf(mb, __shfl_xor(mb, 32));
+    const float sa = pow2_scale(ma), sb = pow2_scale(mb);
+    v8h ah, al, bh, bl;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const float x = Av[i] * sa, y = Bv[i] * sb;
+        ah[i] = (_Float16)x;
+        al[i] = (_Float16)(x - (float)ah[i]);
+        bh[i] = (_Float16)y;
+        bl[i] = (_Float16)(y - (float)bh[i]);
+    }
+    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const float sr = __shfl(sa, 4 * kq + v);   // lane 4 kq + v holds row 4 kq + v's scale
+        out[v] = (double)c[v] / ((double)sr * (double)sb);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // N = 5, D = 3 (isotropic 5PCF): job = (l12, beta = b2, S-label group, column
 // group).  Per staged step of 16 primaries and per M = 0..l12 the block forms
@@ -770,11 +816,19 @@ __global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
                         const float *ap = Sst + (rt * 16 + n) * kC5Stride + 8 * kq;
 #pragma unroll
                         for (int i = 0; i < 8; i++) Av[i] = ap[i];
-                        v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
-                        double unscale;
-                        mfma_k32<PREC>(Av, Bv, cc, unscale);
+                        if constexpr (PREC == 2) {
+                            // rows of one tile belong to different S labels
+                            double o[4];
+                            mfma_k32_f16_rowscaled(Av, Bv, kq, o);
 #pragma unroll
-                        for (int v = 0; v < 4; v++) acc[rt][v] += (double)cc[v] * unscale;
+                            for (int v = 0; v < 4; v++) acc[rt][v] += o[v];
+                        } else {
+                            v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
+                            double unscale;
+                            mfma_k32<PREC>(Av, Bv, cc, unscale);
+#pragma unroll
+                            for (int v = 0; v < 4; v++) acc[rt][v] += (double)cc[v] * unscale;
+                        }
                     }
                 }
             }
