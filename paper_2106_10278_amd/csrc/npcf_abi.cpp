@@ -108,7 +108,7 @@ struct npcf_plan_s {
     C5Job *d_c5jobs = nullptr;
     C5Label *d_c5labels = nullptr;
     int *d_c5mterm = nullptr;
-    CoupleTerm *d_c5terms = nullptr;
+    uint2 *d_c5terms = nullptr;
     int2 *d_c5pairs = nullptr;
     int *d_c5idx = nullptr;
     double *d_c5sign = nullptr;
@@ -184,11 +184,15 @@ int couple_rows_per_block(const npcf_plan_s *p, int64_t nrows)
 {
     if (p->couple_rows > 0) return ((p->couple_rows + 15) / 16) * 16;
     if (p->N == 5) {
-        // about 4096 blocks in all, 256 to 4096 primaries each (the partials
-        // hold one accumulator set per row block)
-        int64_t rpb = nrows * (int64_t)p->t.c5jobs.size() / 4096;
-        rpb = ((rpb + 15) / 16) * 16;
-        return (int)std::min<int64_t>(4096, std::max<int64_t>(256, rpb));
+        // about 32k blocks in all, at least 256 primaries each (measured on the
+        // 5PCF workload: 256-512 beat 1024-4096, whose long blocks leave the
+        // chip idle in the tail), and no more row blocks than keep the per-block
+        // partials (one accumulator set each) within 1 GiB
+        int64_t rpb = nrows * (int64_t)p->t.c5jobs.size() / 32768;
+        rpb = std::max<int64_t>(256, ((rpb + 15) / 16) * 16);
+        const int64_t max_nrb = std::max<int64_t>(8, (1LL << 30) / ((int64_t)p->t.c5tiles * 256 * 8));
+        if ((nrows + rpb - 1) / rpb > max_nrb) rpb = ((nrows + max_nrb - 1) / max_nrb + 15) / 16 * 16;
+        return (int)rpb;
     }
     if (p->N == 4) {
         // about 32k blocks in all, 256 to 1024 primaries each (measured at
@@ -341,6 +345,7 @@ CoupleArgs couple_args(const npcf_plan_s *p, int rows)
         a.c5mterm = p->d_c5mterm;
         a.c5terms = p->d_c5terms;
         a.c5pairs = p->d_c5pairs;
+        a.c5_lds_extra = t.c5_lds_extra;
     }
     if (p->d_fpairs && !p->term_coupling) {
         a.fpairs = p->d_fpairs;
@@ -726,7 +731,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     {
         const int L = p->L;
         const int lds = p->D == 2 ? harmonic_lds_bytes_d2(L) : (p->D == 3 ? harmonic_lds_bytes_d3(L) : harmonic_lds_bytes_d4(L));
-        if (lds <= 0 || lds > 160 * 1024 || (p->N == 5 && couple5_lds_bytes(p->nb, t.nstate) > 160 * 1024)) {
+        if (lds <= 0 || lds > 160 * 1024 || (p->N == 5 && couple5_lds_bytes(p->nb, t.nstate, t.c5_lds_extra) > 160 * 1024)) {
             delete p;
             return NPCF_E_UNSUPPORTED;
         }
@@ -783,7 +788,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         p->d_c5jobs = m.get<C5Job>(t.c5jobs.size());
         p->d_c5labels = m.get<C5Label>(t.c5labels.size());
         p->d_c5mterm = m.get<int>(t.c5mterm.size());
-        p->d_c5terms = m.get<CoupleTerm>(t.c5terms.size());
+        p->d_c5terms = m.get<uint2>(t.c5packed.size());
         p->d_c5pairs = m.get<int2>(t.c5pairs.size());
         p->d_c5idx = m.get<int>(t.c5idx.size());
         p->d_c5sign = m.get<double>(t.c5sign.size());
@@ -818,7 +823,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         if (e == hipSuccess) e = upload(p->d_c5jobs, t.c5jobs, s);
         if (e == hipSuccess) e = upload(p->d_c5labels, t.c5labels, s);
         if (e == hipSuccess) e = upload(p->d_c5mterm, t.c5mterm, s);
-        if (e == hipSuccess) e = upload(p->d_c5terms, t.c5terms, s);
+        if (e == hipSuccess) e = upload(p->d_c5terms, t.c5packed, s);
         if (e == hipSuccess) e = upload(p->d_c5pairs, t.c5pairs, s);
         if (e == hipSuccess) e = upload(p->d_c5idx, t.c5idx, s);
         if (e == hipSuccess) e = upload(p->d_c5sign, t.c5sign, s);

@@ -690,6 +690,16 @@ __device__ __forceinline__ void mfma_k32_f16_rowscaled(const float (&Av)[8], con
 // accumulates Re(S~ T~).  Every computed entry is an output of the b-tuple
 // order (b1 < b2 = beta < b3 < b4, or every tuple in the full-tensor mode).
 // ---------------------------------------------------------------------------
+// one packed term (see C5Label): a_{s1} a_{s2} with conjugation flags, times coef
+__device__ __forceinline__ void c5_term(uint2 v, int &s1, int &s2, bool &c1, bool &c2, float &coef)
+{
+    s1 = (int)(v.x & 0xff);
+    s2 = (int)((v.x >> 8) & 0xff);
+    c1 = (v.x >> 16) & 1;
+    c2 = (v.x >> 17) & 1;
+    coef = __uint_as_float(v.y);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
 {
@@ -700,6 +710,7 @@ __global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
     float *wst = Ast + kRowsStep * rowlen;
     float *Sst = wst + kRowsStep;               // [kC5Rows][kC5Stride]
     float *Tst = Sst + kC5Rows * kC5Stride;     // [kC5Cols][kC5Stride]
+    int *tab = reinterpret_cast<int *>(Tst + kC5Cols * kC5Stride);
     int rb, jb;
     if (!block_work(a.n_rowblocks, a.nc5jobs, rb, jb)) return;
     const auto jobs = as_const(a.c5jobs);
@@ -713,6 +724,48 @@ __global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
     const int n = lane & 15;   // A row / B column within a tile
     const int kq = lane >> 4;  // K quarter: primaries 4 kq .. 4 kq + 3
     const bool has_cols = wave * 16 < ncol;
+
+    // the job's term tables, copied to LDS once: per label its l12 + 2 range
+    // entries (relative to its side's first term) and phase flag, then the terms
+    const int nmt = l12 + 2;
+    const int t0 = col_begin / npair, ntl = (col_begin + ncol - 1) / npair - t0 + 1;
+    const auto labels = as_const(a.c5labels);
+    const int smt0 = uni(labels[s_begin].mt), tmt0 = uni(labels[t_begin + t0].mt);
+    const int sbase = uni(a.c5mterm[smt0]), tbase = uni(a.c5mterm[tmt0]);
+    const int sterms = uni(a.c5mterm[smt0 + ns * nmt - 1]) - sbase;
+    const int tterms = uni(a.c5mterm[tmt0 + ntl * nmt - 1]) - tbase;
+    int *Smt = tab;                      // [ns * nmt]
+    int *Tmt = Smt + ns * nmt;           // [ntl * nmt]
+    int *Srot = Tmt + ntl * nmt;         // [ns]
+    int *Trot = Srot + ns;               // [ntl]
+    int *Srow = Trot + ntl;              // [kC5Rows]: S label | b1 << 16 of GEMM row r
+    uint2 *Sterm = reinterpret_cast<uint2 *>(tab + (((ns + ntl) * (nmt + 1) + kC5Rows + 1) & ~1));   // 8-byte aligned
+    uint2 *Tterm = Sterm + sterms;
+    for (int i = threadIdx.x; i < ns * nmt; i += blockDim.x) Smt[i] = a.c5mterm[smt0 + i] - sbase;
+    for (int i = threadIdx.x; i < ntl * nmt; i += blockDim.x) Tmt[i] = a.c5mterm[tmt0 + i] - tbase;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) Srot[i] = a.c5labels[s_begin + i].rot;
+    for (int i = threadIdx.x; i < ntl; i += blockDim.x) Trot[i] = a.c5labels[t_begin + t0 + i].rot;
+    for (int i = threadIdx.x; i < kC5Rows; i += blockDim.x) Srow[i] = (i / nb1) | ((i % nb1) << 16);
+    const int nrows_s = ns * nb1;
+    for (int i = threadIdx.x; i < sterms; i += blockDim.x) Sterm[i] = a.c5terms[sbase + i];
+    for (int i = threadIdx.x; i < tterms; i += blockDim.x) Tterm[i] = a.c5terms[tbase + i];
+
+    // this thread's column items (column cl = threadIdx / 16 + 16 k, primary p = threadIdx % 16)
+    const int p_item = threadIdx.x & 15;
+    int tl_item[4];
+    int2 bb_item[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int cl = (threadIdx.x >> 4) + 16 * k;
+        tl_item[k] = 0;
+        bb_item[k] = make_int2(0, 0);
+        if (cl < ncol) {
+            const int col = col_begin + cl;
+            const int tl = col / npair;
+            tl_item[k] = tl - t0;
+            bb_item[k] = a.c5pairs[pair_begin + (col - tl * npair)];
+        }
+    }
 
     // rows and columns no item writes stay zero
     for (int t = threadIdx.x; t < (kC5Rows + kC5Cols) * kC5Stride; t += blockDim.x) Sst[t] = 0.f;
@@ -736,72 +789,71 @@ __global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
         stage_rows(a, r0, r_end, Ast, wst);
         for (int M = 0; M <= l12; M++) {
             __syncthreads();
-            // S~ rows: item (S label, primary), every b1 at once
-            for (int it = threadIdx.x; it < ns * kRowsStep; it += blockDim.x) {
-                const int sl = it >> 4, p = it & 15;
-                const C5Label lab = a.c5labels[s_begin + sl];
-                const int tb = a.c5mterm[lab.mt + M], te = a.c5mterm[lab.mt + M + 1];
-                const float *Ap = Ast + p * rowlen;
-                float sr[kMaxBins], si[kMaxBins];
-#pragma unroll
-                for (int b = 0; b < kMaxBins; b++) sr[b] = si[b] = 0.f;
-                for (int t = tb; t < te; t++) {
-                    const CoupleTerm tm = a.c5terms[t];
-                    const float2 y = *reinterpret_cast<const float2 *>(Ap + beta * st2 + 2 * tm.s2);
-                    const float cyr = tm.coef * y.x, cyi = tm.coef * (tm.conj2 ? -y.y : y.y);
-#pragma unroll
-                    for (int b = 0; b < kMaxBins; b++) {
-                        if (b < nb1) {
-                            const float2 x = *reinterpret_cast<const float2 *>(Ap + b * st2 + 2 * tm.s1);
-                            const float xi = tm.conj1 ? -x.y : x.y;
-                            sr[b] += x.x * cyr - xi * cyi;
-                            si[b] += x.x * cyi + xi * cyr;
-                        }
+            // S~ rows: this thread's items (row = threadIdx / 16 + 16 k, primary p_item)
+            {
+                const float *Ap = Ast + p_item * rowlen;
+                const float wp = wst[p_item];
+                for (int row = threadIdx.x >> 4; row < nrows_s; row += 16) {
+                    const int info = Srow[row];
+                    const int sl = info & 0xffff, b1 = info >> 16;
+                    const int tb = Smt[sl * nmt + M], te = Smt[sl * nmt + M + 1];
+                    float sr = 0.f, si = 0.f;
+                    for (int t = tb; t < te; t++) {
+                        int s1, s2;
+                        bool c1, c2;
+                        float coef;
+                        c5_term(Sterm[t], s1, s2, c1, c2, coef);
+                        const float2 x = *reinterpret_cast<const float2 *>(Ap + b1 * st2 + 2 * s1);
+                        const float2 y = *reinterpret_cast<const float2 *>(Ap + beta * st2 + 2 * s2);
+                        const float xi = c1 ? -x.y : x.y;
+                        const float yi = c2 ? -y.y : y.y;
+                        sr += coef * (x.x * y.x - xi * yi);
+                        si += coef * (x.x * yi + xi * y.x);
                     }
-                }
-                const float wp = wst[p];
-#pragma unroll
-                for (int b = 0; b < kMaxBins; b++) {
-                    if (b < nb1) {
-                        float re = sr[b] * wp, im = si[b] * wp;
-                        if (lab.rot) {  // times -i
-                            const float t0 = re;
-                            re = im;
-                            im = -t0;
-                        }
-                        float *dst = Sst + (sl * nb1 + b) * kC5Stride + 2 * p;
-                        dst[0] = re;
-                        dst[1] = -im;
+                    float re = sr * wp, im = si * wp;
+                    if (Srot[sl]) {  // times -i
+                        const float t1 = re;
+                        re = im;
+                        im = -t1;
                     }
+                    float *dst = Sst + row * kC5Stride + 2 * p_item;
+                    dst[0] = re;
+                    dst[1] = -im;
                 }
             }
-            // T~ columns: item (column, primary)
-            for (int it = threadIdx.x; it < ncol * kRowsStep; it += blockDim.x) {
-                const int cl = it >> 4, p = it & 15;
-                const int col = col_begin + cl;
-                const int tl = col / npair;
-                const int2 bb = a.c5pairs[pair_begin + (col - tl * npair)];
-                const C5Label lab = a.c5labels[t_begin + tl];
-                const int tb = a.c5mterm[lab.mt + M], te = a.c5mterm[lab.mt + M + 1];
-                const float *Ap = Ast + p * rowlen;
-                float tr = 0.f, ti = 0.f;
-                for (int t = tb; t < te; t++) {
-                    const CoupleTerm tm = a.c5terms[t];
-                    const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * tm.s1);
-                    const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * tm.s2);
-                    const float xi = tm.conj1 ? -x.y : x.y;
-                    const float yi = tm.conj2 ? -y.y : y.y;
-                    tr += tm.coef * (x.x * y.x - xi * yi);
-                    ti += tm.coef * (x.x * yi + xi * y.x);
+            // T~ columns: this thread's items
+            {
+                const float *Ap = Ast + p_item * rowlen;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int cl = (threadIdx.x >> 4) + 16 * k;
+                    if (cl < ncol) {
+                        const int tl = tl_item[k];
+                        const int2 bb = bb_item[k];
+                        const int tb = Tmt[tl * nmt + M], te = Tmt[tl * nmt + M + 1];
+                        float tr = 0.f, ti = 0.f;
+                        for (int t = tb; t < te; t++) {
+                            int s1, s2;
+                            bool c1, c2;
+                            float coef;
+                            c5_term(Tterm[t], s1, s2, c1, c2, coef);
+                            const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * s1);
+                            const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * s2);
+                            const float xi = c1 ? -x.y : x.y;
+                            const float yi = c2 ? -y.y : y.y;
+                            tr += coef * (x.x * y.x - xi * yi);
+                            ti += coef * (x.x * yi + xi * y.x);
+                        }
+                        if (Trot[tl]) {
+                            const float t1 = tr;
+                            tr = ti;
+                            ti = -t1;
+                        }
+                        float *dst = Tst + cl * kC5Stride + 2 * p_item;
+                        dst[0] = tr;
+                        dst[1] = ti;
+                    }
                 }
-                if (lab.rot) {
-                    const float t0 = tr;
-                    tr = ti;
-                    ti = -t0;
-                }
-                float *dst = Tst + cl * kC5Stride + 2 * p;
-                dst[0] = tr;
-                dst[1] = ti;
             }
             __syncthreads();
             if (has_cols) {
@@ -928,9 +980,9 @@ hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... a
 
 int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam * nparts * mtiles : nlam * nparts; }
 
-int couple5_lds_bytes(int nb, int nstate)
+int couple5_lds_bytes(int nb, int nstate, int extra)
 {
-    return (kRowsStep * nb * 2 * nstate + kRowsStep + (kC5Rows + kC5Cols) * kC5Stride) * 4;
+    return (kRowsStep * nb * 2 * nstate + kRowsStep + (kC5Rows + kC5Cols) * kC5Stride) * 4 + extra;
 }
 
 int couple_jobs_per_block() { return 4 * kJobsPerWave; }
@@ -950,7 +1002,7 @@ hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int n
     if (N == 5) {
         // njobs: the output tiles of the partial layout
         const int nblk5 = ((a.n_rowblocks + kXcd - 1) / kXcd) * kXcd * a.nc5jobs;
-        const int lds5 = couple5_lds_bytes(a.nb, a.nstate);
+        const int lds5 = couple5_lds_bytes(a.nb, a.nstate, a.c5_lds_extra);
         switch (precision) {
         case 0: return launch_with_lds(k_couple5<0>, nblk5, lds5, s, a, njobs);
         case 1: return launch_with_lds(k_couple5<1>, nblk5, lds5, s, a, njobs);

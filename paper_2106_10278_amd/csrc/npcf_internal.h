@@ -119,6 +119,9 @@ struct C5Label {   // one S label (l1, l2 | l12) or T label (l3, l4 | l12)
     int mt;        // terms of M: c5terms[c5mterm[mt + M] .. c5mterm[mt + M + 1]), M = 0..l12
     int rot;       // 1: multiply by -i (odd l1 + l2, resp. l3 + l4)
 };
+// A term in 8 bytes: x = s1 | s2 << 8 | conj1 << 16 | conj2 << 17, y = coef (FP32 bits).
+// The labels of one l12 are consecutive and each holds l12 + 2 entries of
+// c5mterm, so a job's labels own one contiguous run of c5mterm and of c5terms.
 struct C5Job {
     int l12, beta;
     int nb1;                 // b1 values of each S label (b1 < nb1)
@@ -189,8 +192,9 @@ struct CoupleArgs {
     int nc5jobs;
     const C5Label *c5labels;
     const int *c5mterm;
-    const CoupleTerm *c5terms;
+    const uint2 *c5terms;
     const int2 *c5pairs;
+    int c5_lds_extra;            // bytes of the largest job's term tables in LDS
 };
 
 // ---------------------------------------------------------------------------
@@ -241,7 +245,7 @@ hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam,
 hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
                                const double *bt_scale, int nlam, int nbt, int norm_by_randoms, int lam0, double *out,
                                int *bad, hipStream_t s);
-int couple5_lds_bytes(int nb, int nstate);
+int couple5_lds_bytes(int nb, int nstate, int extra);
 
 // ---------------------------------------------------------------------------
 // Host planner (npcf_plan.cpp)
@@ -279,6 +283,8 @@ struct Tables {
     std::vector<C5Label> c5labels;
     std::vector<int> c5mterm;
     std::vector<CoupleTerm> c5terms;
+    std::vector<uint2> c5packed;       // c5terms in the 8-byte device form
+    int c5_lds_extra = 0;
     std::vector<int2> c5pairs;
     std::vector<C5Job> c5jobs;
     int c5tiles = 0;                   // output tiles (accumulator = c5tiles x 256 doubles)

@@ -269,6 +269,27 @@ bool build_c5(Tables &t, int L, int nb, int mode)
                 }
         }
     if ((int64_t)t.c5tiles * 256 > (int64_t)INT32_MAX || (int64_t)t.nlam * t.nbt > (1LL << 28)) return false;
+    // device form of the terms, and the LDS a job's tables take: per label
+    // l12 + 2 range entries and a phase flag, 8 bytes per term
+    t.c5packed.clear();
+    for (const CoupleTerm &tm : t.c5terms) {
+        uint2 v;
+        v.x = (uint32_t)(uint16_t)tm.s1 | ((uint32_t)(uint16_t)tm.s2 << 8) | ((uint32_t)(tm.conj1 != 0) << 16) |
+              ((uint32_t)(tm.conj2 != 0) << 17);
+        std::memcpy(&v.y, &tm.coef, 4);
+        t.c5packed.push_back(v);
+    }
+    t.c5_lds_extra = 0;
+    for (const C5Job &j : t.c5jobs) {
+        const int nmt = j.l12 + 2;
+        const int t0 = j.col_begin / j.npair, t1 = (j.col_begin + j.ncol - 1) / j.npair;
+        const int ntl = t1 - t0 + 1;
+        const C5Label &sf = t.c5labels[j.s_begin], &tf = t.c5labels[j.t_begin + t0];
+        const int sterms = t.c5mterm[sf.mt + j.ns * nmt - 1] - t.c5mterm[sf.mt];
+        const int tterms = t.c5mterm[tf.mt + ntl * nmt - 1] - t.c5mterm[tf.mt];
+        const int bytes = 4 * (((j.ns + ntl) * (nmt + 1) + kC5Rows + 1) & ~1) + 8 * (sterms + tterms);
+        t.c5_lds_extra = std::max(t.c5_lds_extra, (bytes + 15) / 16 * 16);
+    }
     // accumulator index and sign of every output
     t.c5sign.assign(t.nlam, 1.0);
     t.c5idx.assign((size_t)t.nlam * t.nbt, 0);
