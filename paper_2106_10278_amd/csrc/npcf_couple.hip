@@ -21,125 +21,13 @@
 //   2 FP16   hi + lo split after a power-of-two scaling of each operand tile,
 //            3 x v_mfma_f32_16x16x32_f16
 //   3 BF16   hi + mid + lo split, 6 products (all pairs of total order <= 2)
-#include "npcf_internal.h"
+#include "npcf_couple_common.h"
 
 namespace npcf {
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-
-constexpr int kRowsStep = 16;   // primaries staged in LDS per step
 constexpr int kJobsPerWave = 4;
-constexpr int kXcd = 8;
-
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-
-// Power-of-two scale that brings the wave's largest |x| into [0.5, 1) (1 when
-// every x is zero).  FP16's exponent range is too narrow for products of
-// coefficients spanning many octaves without it.
-__device__ __forceinline__ float wave_pow2_scale(float m)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if (!(m > 0.f) || !isfinite(m)) return 1.f;
-    int e;
-    frexpf(m, &e);
-    return ldexpf(1.f, -e);
-}
-
-// One K = 32 slice: lane l holds 8 (A, B) operand pairs; A row = l % 16,
-// B column = l % 16, and the 4 lane quarters together cover 32 K indices
-// (the order of K is immaterial to the sum).  Accumulates into c (from zero)
-// and returns the factor that undoes any operand scaling.
-template <int PREC>
-__device__ __forceinline__ void mfma_k32(const float (&Av)[8], const float (&Bv)[8], v4f &c, double &unscale)
-{
-    unscale = 1.0;
-    if constexpr (PREC == 0) {
-#pragma unroll
-        for (int i = 0; i < 8; i++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[i], Bv[i], c, 0, 0, 0);
-    } else if constexpr (PREC == 1) {
-        v8bf ah, al, bh, bl;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            ah[i] = (__bf16)Av[i];
-            al[i] = (__bf16)(Av[i] - (float)ah[i]);
-            bh[i] = (__bf16)Bv[i];
-            bl[i] = (__bf16)(Bv[i] - (float)bh[i]);
-        }
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-    } else if constexpr (PREC == 2) {
-        float ma = 0.f, mb = 0.f;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            ma = fmaxf(ma, fabsf(Av[i]));
-            mb = fmaxf(mb, fabsf(Bv[i]));
-        }
-        const float sa = wave_pow2_scale(ma), sb = wave_pow2_scale(mb);
-        v8h ah, al, bh, bl;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const float x = Av[i] * sa, y = Bv[i] * sb;
-            ah[i] = (_Float16)x;
-            al[i] = (_Float16)(x - (float)ah[i]);
-            bh[i] = (_Float16)y;
-            bl[i] = (_Float16)(y - (float)bh[i]);
-        }
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
-        unscale = 1.0 / ((double)sa * (double)sb);
-    } else {
-        v8bf ah, am, al, bh, bm, bl;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            ah[i] = (__bf16)Av[i];
-            float r = Av[i] - (float)ah[i];
-            am[i] = (__bf16)r;
-            al[i] = (__bf16)(r - (float)am[i]);
-            bh[i] = (__bf16)Bv[i];
-            r = Bv[i] - (float)bh[i];
-            bm[i] = (__bf16)r;
-            bl[i] = (__bf16)(r - (float)bm[i]);
-        }
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-    }
-}
-
-// XCD-aware block -> (rowblock, jobgroup): blocks are dispatched round-robin
-// over the 8 XCDs, so the job groups of one rowblock are given consecutive
-// slots on one XCD and its rows of a are served from that XCD's L2.
-__device__ __forceinline__ bool block_work(int nrb, int njg, int &rb, int &jg)
-{
-    const int b = blockIdx.x;
-    const int x = b % kXcd;
-    const int s = b / kXcd;
-    rb = (s / njg) * kXcd + x;
-    jg = s % njg;
-    return rb < nrb;
-}
-
-// Stage kRowsStep rows of a (and their weights) into LDS, zero-padding rows
-// at and past r_end (the end of this block's rows).
-__device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, int r_end, float *Ast, float *wst)
-{
-    const int rowlen = a.nb * 2 * a.nstate;
-    const int total = kRowsStep * rowlen;
-    const int r_lim = r_end - r0;
-    const float *src = a.A + (size_t)r0 * rowlen;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) Ast[t] = (t < r_lim * rowlen) ? src[t] : 0.f;
-    for (int t = threadIdx.x; t < kRowsStep; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
-}
 
 // ---------------------------------------------------------------------------
 // N = 4
@@ -293,19 +181,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // with its coefficient for each l3, into that slot's S; each slot then takes
 // its MFMA slice against a_{l3 m3}[b3].  Two jobs per wave (paired by cost).
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
-{
-    // read-only tables: the constant address space lets uniform loads go
-    // through the scalar unit
-    return (const __attribute__((address_space(4))) T *)p;
-}
-
-// a wave-uniform value held in a scalar register (table indices and
-// coefficients, so their loads and uses stay on the scalar path)
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
-
 // One group (pair, m3) of a job with its NA active slots (the first NA):
 // S of every slot for this lane's 16-row tile row and its four primaries of
 // the step, then one MFMA slice per slot, folded into the FP64 accumulators.
@@ -634,271 +509,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
-// FP16 hi + lo slice with a power-of-two scale per A row and per B column
-// (lanes n, n+16, n+32, n+48 hold one row / column): used where a tile mixes
-// rows of very different size, which one scale per tile would push into
-// FP16's subnormal range.  c[v] (row 4 kq + v, column n) is returned unscaled
-// in FP64 in out[v].
-__device__ __forceinline__ float pow2_scale(float m)
-{
-    if (!(m > 0.f) || !isfinite(m)) return 1.f;
-    int e;
-    frexpf(m, &e);
-    return ldexpf(1.f, -e);
-}
-
-__device__ __forceinline__ void mfma_k32_f16_rowscaled(const float (&Av)[8], const float (&Bv)[8], int kq, double (&out)[4])
-{
-    float ma = 0.f, mb = 0.f;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        ma = fmaxf(ma, fabsf(Av[i]));
-        mb = fmaxf(mb, fabsf(Bv[i]));
-    }
-    ma = fmaxf(ma, __shfl_xor(ma, 16));
-    ma = fmaxf(ma, __shfl_xor(ma, 32));
-    mb = fmaxf(mb, __shfl_xor(mb, 16));
-    mb = fmaxf(mb, __shfl_xor(mb, 32));
-    const float sa = pow2_scale(ma), sb = pow2_scale(mb);
-    v8h ah, al, bh, bl;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const float x = Av[i] * sa, y = Bv[i] * sb;
-        ah[i] = (_Float16)x;
-        al[i] = (_Float16)(x - (float)ah[i]);
-        bh[i] = (_Float16)y;
-        bl[i] = (_Float16)(y - (float)bh[i]);
-    }
-    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-        const float sr = __shfl(sa, 4 * kq + v);   // lane 4 kq + v holds row 4 kq + v's scale
-        out[v] = (double)c[v] / ((double)sr * (double)sb);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// N = 5, D = 3 (isotropic 5PCF): job = (l12, beta = b2, S-label group, column
-// group).  Per staged step of 16 primaries and per M = 0..l12 the block forms
-//   S~_M for its rows (S label, b1) with b2 = beta   (VALU, into LDS)
-//   T~_M for its columns (T label, (b3, b4))          (VALU, into LDS)
-// and each wave runs its 16-column tile against every row tile on MFMA with
-// K = 16 primaries x {re, im}: A = (S~r, -S~i), B = (T~r, T~i), so the tile
-// accumulates Re(S~ T~).  Every computed entry is an output of the b-tuple
-// order (b1 < b2 = beta < b3 < b4, or every tuple in the full-tensor mode).
-// ---------------------------------------------------------------------------
-// one packed term (see C5Label): a_{s1} a_{s2} with conjugation flags, times coef
-__device__ __forceinline__ void c5_term(uint2 v, int &s1, int &s2, bool &c1, bool &c2, float &coef)
-{
-    s1 = (int)(v.x & 0xff);
-    s2 = (int)((v.x >> 8) & 0xff);
-    c1 = (v.x >> 16) & 1;
-    c2 = (v.x >> 17) & 1;
-    coef = __uint_as_float(v.y);
-}
-
-template <int PREC>
-__global__ __launch_bounds__(256) void k_couple5(CoupleArgs a, int ntiles)
-{
-    extern __shared__ __align__(16) char smem[];
-    const int rowlen = a.nb * 2 * a.nstate;
-    const int st2 = 2 * a.nstate;
-    float *Ast = reinterpret_cast<float *>(smem);
-    float *wst = Ast + kRowsStep * rowlen;
-    float *Sst = wst + kRowsStep;               // [kC5Rows][kC5Stride]
-    float *Tst = Sst + kC5Rows * kC5Stride;     // [kC5Cols][kC5Stride]
-    int *tab = reinterpret_cast<int *>(Tst + kC5Cols * kC5Stride);
-    int rb, jb;
-    if (!block_work(a.n_rowblocks, a.nc5jobs, rb, jb)) return;
-    const auto jobs = as_const(a.c5jobs);
-    const int l12 = uni(jobs[jb].l12), beta = uni(jobs[jb].beta), nb1 = uni(jobs[jb].nb1);
-    const int s_begin = uni(jobs[jb].s_begin), ns = uni(jobs[jb].ns), t_begin = uni(jobs[jb].t_begin);
-    const int col_begin = uni(jobs[jb].col_begin), ncol = uni(jobs[jb].ncol);
-    const int pair_begin = uni(jobs[jb].pair_begin), npair = uni(jobs[jb].npair);
-    const int nrt = uni(jobs[jb].nrt), tile_begin = uni(jobs[jb].tile_begin);
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int n = lane & 15;   // A row / B column within a tile
-    const int kq = lane >> 4;  // K quarter: primaries 4 kq .. 4 kq + 3
-    const bool has_cols = wave * 16 < ncol;
-
-    // the job's term tables, copied to LDS once: per label its l12 + 2 range
-    // entries (relative to its side's first term) and phase flag, then the terms
-    const int nmt = l12 + 2;
-    const int t0 = col_begin / npair, ntl = (col_begin + ncol - 1) / npair - t0 + 1;
-    const auto labels = as_const(a.c5labels);
-    const int smt0 = uni(labels[s_begin].mt), tmt0 = uni(labels[t_begin + t0].mt);
-    const int sbase = uni(a.c5mterm[smt0]), tbase = uni(a.c5mterm[tmt0]);
-    const int sterms = uni(a.c5mterm[smt0 + ns * nmt - 1]) - sbase;
-    const int tterms = uni(a.c5mterm[tmt0 + ntl * nmt - 1]) - tbase;
-    int *Smt = tab;                      // [ns * nmt]
-    int *Tmt = Smt + ns * nmt;           // [ntl * nmt]
-    int *Srot = Tmt + ntl * nmt;         // [ns]
-    int *Trot = Srot + ns;               // [ntl]
-    int *Srow = Trot + ntl;              // [kC5Rows]: S label | b1 << 16 of GEMM row r
-    uint2 *Sterm = reinterpret_cast<uint2 *>(tab + (((ns + ntl) * (nmt + 1) + kC5Rows + 1) & ~1));   // 8-byte aligned
-    uint2 *Tterm = Sterm + sterms;
-    for (int i = threadIdx.x; i < ns * nmt; i += blockDim.x) Smt[i] = a.c5mterm[smt0 + i] - sbase;
-    for (int i = threadIdx.x; i < ntl * nmt; i += blockDim.x) Tmt[i] = a.c5mterm[tmt0 + i] - tbase;
-    for (int i = threadIdx.x; i < ns; i += blockDim.x) Srot[i] = a.c5labels[s_begin + i].rot;
-    for (int i = threadIdx.x; i < ntl; i += blockDim.x) Trot[i] = a.c5labels[t_begin + t0 + i].rot;
-    for (int i = threadIdx.x; i < kC5Rows; i += blockDim.x) Srow[i] = (i / nb1) | ((i % nb1) << 16);
-    const int nrows_s = ns * nb1;
-    for (int i = threadIdx.x; i < sterms; i += blockDim.x) Sterm[i] = a.c5terms[sbase + i];
-    for (int i = threadIdx.x; i < tterms; i += blockDim.x) Tterm[i] = a.c5terms[tbase + i];
-
-    // this thread's column items (column cl = threadIdx / 16 + 16 k, primary p = threadIdx % 16)
-    const int p_item = threadIdx.x & 15;
-    int tl_item[4];
-    int2 bb_item[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const int cl = (threadIdx.x >> 4) + 16 * k;
-        tl_item[k] = 0;
-        bb_item[k] = make_int2(0, 0);
-        if (cl < ncol) {
-            const int col = col_begin + cl;
-            const int tl = col / npair;
-            tl_item[k] = tl - t0;
-            bb_item[k] = a.c5pairs[pair_begin + (col - tl * npair)];
-        }
-    }
-
-    // rows and columns no item writes stay zero
-    for (int t = threadIdx.x; t < (kC5Rows + kC5Cols) * kC5Stride; t += blockDim.x) Sst[t] = 0.f;
-
-    double acc[8][4];
-#pragma unroll
-    for (int r = 0; r < 8; r++)
-#pragma unroll
-        for (int v = 0; v < 4; v++) acc[r][v] = 0.0;
-
-    int r_begin = rb * a.rows_per_block;
-    int r_end = r_begin + a.rows_per_block;
-    if (a.rb_begin) {
-        r_begin = a.rb_begin[rb];
-        r_end = a.rb_end[rb];
-    }
-    if (r_end > a.nrows) r_end = a.nrows;
-
-    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
-        __syncthreads();
-        stage_rows(a, r0, r_end, Ast, wst);
-        for (int M = 0; M <= l12; M++) {
-            __syncthreads();
-            // S~ rows: this thread's items (row = threadIdx / 16 + 16 k, primary p_item)
-            {
-                const float *Ap = Ast + p_item * rowlen;
-                const float wp = wst[p_item];
-                for (int row = threadIdx.x >> 4; row < nrows_s; row += 16) {
-                    const int info = Srow[row];
-                    const int sl = info & 0xffff, b1 = info >> 16;
-                    const int tb = Smt[sl * nmt + M], te = Smt[sl * nmt + M + 1];
-                    float sr = 0.f, si = 0.f;
-                    for (int t = tb; t < te; t++) {
-                        int s1, s2;
-                        bool c1, c2;
-                        float coef;
-                        c5_term(Sterm[t], s1, s2, c1, c2, coef);
-                        const float2 x = *reinterpret_cast<const float2 *>(Ap + b1 * st2 + 2 * s1);
-                        const float2 y = *reinterpret_cast<const float2 *>(Ap + beta * st2 + 2 * s2);
-                        const float xi = c1 ? -x.y : x.y;
-                        const float yi = c2 ? -y.y : y.y;
-                        sr += coef * (x.x * y.x - xi * yi);
-                        si += coef * (x.x * yi + xi * y.x);
-                    }
-                    float re = sr * wp, im = si * wp;
-                    if (Srot[sl]) {  // times -i
-                        const float t1 = re;
-                        re = im;
-                        im = -t1;
-                    }
-                    float *dst = Sst + row * kC5Stride + 2 * p_item;
-                    dst[0] = re;
-                    dst[1] = -im;
-                }
-            }
-            // T~ columns: this thread's items
-            {
-                const float *Ap = Ast + p_item * rowlen;
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int cl = (threadIdx.x >> 4) + 16 * k;
-                    if (cl < ncol) {
-                        const int tl = tl_item[k];
-                        const int2 bb = bb_item[k];
-                        const int tb = Tmt[tl * nmt + M], te = Tmt[tl * nmt + M + 1];
-                        float tr = 0.f, ti = 0.f;
-                        for (int t = tb; t < te; t++) {
-                            int s1, s2;
-                            bool c1, c2;
-                            float coef;
-                            c5_term(Tterm[t], s1, s2, c1, c2, coef);
-                            const float2 x = *reinterpret_cast<const float2 *>(Ap + bb.x * st2 + 2 * s1);
-                            const float2 y = *reinterpret_cast<const float2 *>(Ap + bb.y * st2 + 2 * s2);
-                            const float xi = c1 ? -x.y : x.y;
-                            const float yi = c2 ? -y.y : y.y;
-                            tr += coef * (x.x * y.x - xi * yi);
-                            ti += coef * (x.x * yi + xi * y.x);
-                        }
-                        if (Trot[tl]) {
-                            const float t1 = tr;
-                            tr = ti;
-                            ti = -t1;
-                        }
-                        float *dst = Tst + cl * kC5Stride + 2 * p_item;
-                        dst[0] = tr;
-                        dst[1] = ti;
-                    }
-                }
-            }
-            __syncthreads();
-            if (has_cols) {
-                float Bv[8];
-                const float *bp = Tst + (wave * 16 + n) * kC5Stride + 8 * kq;
-#pragma unroll
-                for (int i = 0; i < 8; i++) Bv[i] = bp[i];
-#pragma unroll
-                for (int rt = 0; rt < 8; rt++) {
-                    if (rt < nrt) {
-                        float Av[8];
-                        const float *ap = Sst + (rt * 16 + n) * kC5Stride + 8 * kq;
-#pragma unroll
-                        for (int i = 0; i < 8; i++) Av[i] = ap[i];
-                        if constexpr (PREC == 2) {
-                            // rows of one tile belong to different S labels
-                            double o[4];
-                            mfma_k32_f16_rowscaled(Av, Bv, kq, o);
-#pragma unroll
-                            for (int v = 0; v < 4; v++) acc[rt][v] += o[v];
-                        } else {
-                            v4f cc = v4f{0.f, 0.f, 0.f, 0.f};
-                            double unscale;
-                            mfma_k32<PREC>(Av, Bv, cc, unscale);
-#pragma unroll
-                            for (int v = 0; v < 4; v++) acc[rt][v] += (double)cc[v] * unscale;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    // per-block partials: partial[rb][tile][16][16]; lane holds rows 4 kq + v of column n
-    if (has_cols) {
-#pragma unroll
-        for (int rt = 0; rt < 8; rt++) {
-            if (rt < nrt) {
-                double *dst = a.partial + ((size_t)rb * ntiles + tile_begin + rt * 4 + wave) * 256;
-#pragma unroll
-                for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc[rt][v];
-            }
-        }
-    }
-}
-
 __global__ void k_reduce_partials(const double *partial, int nrb, int64_t len, double *acc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -967,23 +577,9 @@ inline int couple_lds(const CoupleArgs &a)
     return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4 + a.max_block_terms * (int)sizeof(CoupleTerm);
 }
 
-template <class K, class... Args>
-hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... args)
-{
-    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), lds, s, args...);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 int couple_njobs(int N, int nlam, int nparts, int mtiles) { return N == 4 ? nlam * nparts * mtiles : nlam * nparts; }
-
-int couple5_lds_bytes(int nb, int nstate, int extra)
-{
-    return (kRowsStep * nb * 2 * nstate + kRowsStep + (kC5Rows + kC5Cols) * kC5Stride) * 4 + extra;
-}
 
 int couple_jobs_per_block() { return 4 * kJobsPerWave; }
 
@@ -999,18 +595,7 @@ int couple_nblocks(int njobs, int nrb)
 hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int njobs, int nparts, const float *sfac,
                                 hipStream_t s)
 {
-    if (N == 5) {
-        // njobs: the output tiles of the partial layout
-        const int nblk5 = ((a.n_rowblocks + kXcd - 1) / kXcd) * kXcd * a.nc5jobs;
-        const int lds5 = couple5_lds_bytes(a.nb, a.nstate, a.c5_lds_extra);
-        switch (precision) {
-        case 0: return launch_with_lds(k_couple5<0>, nblk5, lds5, s, a, njobs);
-        case 1: return launch_with_lds(k_couple5<1>, nblk5, lds5, s, a, njobs);
-        case 2: return launch_with_lds(k_couple5<2>, nblk5, lds5, s, a, njobs);
-        case 3: return launch_with_lds(k_couple5<3>, nblk5, lds5, s, a, njobs);
-        default: return hipErrorInvalidValue;
-        }
-    }
+    if (N == 5) return launch_couple5(precision, a, njobs, s);  // njobs: output tiles
     const int lds = couple_lds(a);
     int nblk = couple_nblocks(njobs, a.n_rowblocks);
     if (N == 4 && a.fpairs) {

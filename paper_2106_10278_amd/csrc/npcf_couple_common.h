@@ -1,0 +1,149 @@
+// Device helpers shared by the coupling kernels (npcf_couple.hip: N = 3, 4;
+// npcf_couple5.hip: N = 5): MFMA K = 32 slices in the four precisions, the
+// XCD-aware block mapping, staging of rows of a, scalar-path helpers.
+#pragma once
+
+#include "npcf_internal.h"
+
+namespace npcf {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int kRowsStep = 16;   // primaries staged in LDS per step
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Power-of-two scale that brings the wave's largest |x| into [0.5, 1) (1 when
+// every x is zero).  FP16's exponent range is too narrow for products of
+// coefficients spanning many octaves without it.
+__device__ __forceinline__ float wave_pow2_scale(float m)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (!(m > 0.f) || !isfinite(m)) return 1.f;
+    int e;
+    frexpf(m, &e);
+    return ldexpf(1.f, -e);
+}
+
+// One K = 32 slice: lane l holds 8 (A, B) operand pairs; A row = l % 16,
+// B column = l % 16, and the 4 lane quarters together cover 32 K indices
+// (the order of K is immaterial to the sum).  Accumulates into c (from zero)
+// and returns the factor that undoes any operand scaling.
+template <int PREC>
+__device__ __forceinline__ void mfma_k32(const float (&Av)[8], const float (&Bv)[8], v4f &c, double &unscale)
+{
+    unscale = 1.0;
+    if constexpr (PREC == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[i], Bv[i], c, 0, 0, 0);
+    } else if constexpr (PREC == 1) {
+        v8bf ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ah[i] = (__bf16)Av[i];
+            al[i] = (__bf16)(Av[i] - (float)ah[i]);
+            bh[i] = (__bf16)Bv[i];
+            bl[i] = (__bf16)(Bv[i] - (float)bh[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    } else if constexpr (PREC == 2) {
+        float ma = 0.f, mb = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ma = fmaxf(ma, fabsf(Av[i]));
+            mb = fmaxf(mb, fabsf(Bv[i]));
+        }
+        const float sa = wave_pow2_scale(ma), sb = wave_pow2_scale(mb);
+        v8h ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const float x = Av[i] * sa, y = Bv[i] * sb;
+            ah[i] = (_Float16)x;
+            al[i] = (_Float16)(x - (float)ah[i]);
+            bh[i] = (_Float16)y;
+            bl[i] = (_Float16)(y - (float)bh[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
+        unscale = 1.0 / ((double)sa * (double)sb);
+    } else {
+        v8bf ah, am, al, bh, bm, bl;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            ah[i] = (__bf16)Av[i];
+            float r = Av[i] - (float)ah[i];
+            am[i] = (__bf16)r;
+            al[i] = (__bf16)(r - (float)am[i]);
+            bh[i] = (__bf16)Bv[i];
+            r = Bv[i] - (float)bh[i];
+            bm[i] = (__bf16)r;
+            bl[i] = (__bf16)(r - (float)bm[i]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    }
+}
+
+// XCD-aware block -> (rowblock, jobgroup): blocks are dispatched round-robin
+// over the 8 XCDs, so the job groups of one rowblock are given consecutive
+// slots on one XCD and its rows of a are served from that XCD's L2.
+__device__ __forceinline__ bool block_work(int nrb, int njg, int &rb, int &jg)
+{
+    const int b = blockIdx.x;
+    const int x = b % kXcd;
+    const int s = b / kXcd;
+    rb = (s / njg) * kXcd + x;
+    jg = s % njg;
+    return rb < nrb;
+}
+
+// Stage kRowsStep rows of a (and their weights) into LDS, zero-padding rows
+// at and past r_end (the end of this block's rows).
+__device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, int r_end, float *Ast, float *wst)
+{
+    const int rowlen = a.nb * 2 * a.nstate;
+    const int total = kRowsStep * rowlen;
+    const int r_lim = r_end - r0;
+    const float *src = a.A + (size_t)r0 * rowlen;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) Ast[t] = (t < r_lim * rowlen) ? src[t] : 0.f;
+    for (int t = threadIdx.x; t < kRowsStep; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
+}
+
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
+{
+    // read-only tables: the constant address space lets uniform loads go
+    // through the scalar unit
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
+// a wave-uniform value held in a scalar register (table indices and
+// coefficients, so their loads and uses stay on the scalar path)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+template <class K, class... Args>
+hipError_t launch_with_lds(K kernel, int nblk, int lds, hipStream_t s, Args... args)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(nblk), dim3(256), lds, s, args...);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace npcf

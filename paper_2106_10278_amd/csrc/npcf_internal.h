@@ -246,6 +246,7 @@ hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const 
                                const double *bt_scale, int nlam, int nbt, int norm_by_randoms, int lam0, double *out,
                                int *bad, hipStream_t s);
 int couple5_lds_bytes(int nb, int nstate, int extra);
+hipError_t launch_couple5(int precision, const CoupleArgs &a, int ntiles, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Host planner (npcf_plan.cpp)
@@ -296,5 +297,9 @@ struct Tables {
 npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err);
 double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M);
 double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
+// stored state index: D = 2: l; D = 3: (l = l2, m = l1); D = 4: (l3, l2, l1)
+int state_index(int D, int l1, int l2, int l3);
+// N = 5 tables (npcf_plan5.cpp); false when the outputs exceed the index range
+bool build_c5(Tables &t, int L, int nb, int mode);
 
 }  // namespace npcf
