@@ -127,6 +127,29 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
 npcf_status npcf_accumulate(npcf_plan_t plan, const double *pos, const double *w, int64_t n,
                             int64_t prim_begin, int64_t prim_end, int role);
 
+/* Gridded data (section "Application to Gridded Data"): the field X sampled
+ * on a periodic grid of dims[0] x ... x dims[D-1] nodes covering the box
+ * (node (i_0, ..) at x_k = i_k box_k / dims_k) is the catalogue of its nodes
+ * with weights w = X dV (dV = prod box_k / dims_k), and a^b_[l] of every node
+ * is computed for all nodes at once as the correlation of w with
+ * conj(Y_[l]) Theta^b / v_b, by FFTs on the device (complex FP64, one pass per
+ * axis).  The nodes [prim_begin, prim_end) (row-major node index, last axis
+ * fastest) are then the primaries of the coupling stage, as in
+ * npcf_accumulate; the result equals npcf_accumulate on the node catalogue up
+ * to rounding.  The plan keeps the FFTs of the kernels for the last grid shape
+ * (nbins x states x prod dims complex doubles, twice that while accumulating);
+ * a new shape rebuilds them.
+ *  field: device pointer, double [prod dims], row-major
+ *  dims:  host pointer, int [D], each a power of two in 2..2048
+ * The primary count per call is limited only by memory (chunks of up to
+ * max_points rows).  Asynchronous after the first call on a shape.
+ * Errors: NPCF_E_INVALID (NULL pointers, dims not powers of two, empty or
+ * out-of-range node range, open box, bad role), NPCF_E_UNSUPPORTED (D = 4),
+ * NPCF_E_NOMEM, NPCF_E_DEVICE.  Non-finite field values are reported by the
+ * next npcf_finalize as NPCF_E_INVALID. */
+npcf_status npcf_accumulate_grid(npcf_plan_t plan, const double *field, const int *dims, int64_t prim_begin,
+                                 int64_t prim_end, int role);
+
 /* Synchronise the plan's stream and write the finalised estimator to `out`
  * (host, double, out_len entries): zeta / (V_D prod_i v_{b_i}), parity part
  * as described above, optionally divided by the randoms normalisation.

@@ -48,6 +48,23 @@ struct StageTimer {
 
 struct BatchState;
 
+// Gridded data (npcf_accumulate_grid): the kernel spectra of one grid shape
+// and the per-call buffers.
+struct GridState {
+    int dims[3] = {0, 0, 0};
+    int64_t ng = 0;
+    int nbs = 0;                          // bins x stored states
+    DevAlloc mem;
+    double2 *khat = nullptr;              // [nbs][ng] FFT of K'_{b,s}
+    double2 *work = nullptr;              // [nbs][ng] a_{b,s} on the grid
+    double2 *xhat = nullptr;              // [ng] FFT of the weights
+    double *w64 = nullptr;
+    float *w32 = nullptr;
+    uint8_t *sreal = nullptr;             // [nstate] states with l1 = 0 (real a)
+    double2 *tw[3] = {nullptr, nullptr, nullptr};   // twiddles e^{-2 pi i j / n} per axis
+    unsigned long long offsets_in_range = 0;        // grid offsets with e_0 <= r < e_nb
+};
+
 }  // namespace
 
 struct npcf_plan_s {
@@ -117,6 +134,8 @@ struct npcf_plan_s {
     int ncu = 256;  // compute units of the plan's device
     // batched accumulation (npcf_accumulate_batch); owned
     BatchState *batch = nullptr;
+    // gridded accumulation (npcf_accumulate_grid); owned
+    GridState *grid = nullptr;
 };
 
 namespace {
@@ -643,6 +662,130 @@ npcf_status batch_record(npcf_plan_s *p, hipStream_t s)
     }
     return NPCF_OK;
 }
+void grid_release(npcf_plan_s *p)
+{
+    if (!p->grid) return;
+    (void)hipStreamSynchronize(p->stream);
+    p->grid->mem.release();
+    delete p->grid;
+    p->grid = nullptr;
+}
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// Kernel spectra for a grid shape: K'_{b,s} on the grid, then its FFT.
+npcf_status grid_setup(npcf_plan_s *p, const int *dims)
+{
+    grid_release(p);
+    GridState *g = new (std::nothrow) GridState();
+    if (!g) return NPCF_E_NOMEM;
+    p->grid = g;
+    const int D = p->D;
+    g->ng = 1;
+    for (int k = 0; k < D; k++) {
+        g->dims[k] = dims[k];
+        g->ng *= dims[k];
+    }
+    g->nbs = p->nb * p->t.nstate;
+    DevAlloc &m = g->mem;
+    g->khat = m.get<double2>((size_t)g->nbs * g->ng);
+    g->work = m.get<double2>((size_t)g->nbs * g->ng);
+    g->xhat = m.get<double2>(g->ng);
+    g->w64 = m.get<double>(g->ng);
+    g->w32 = m.get<float>(g->ng);
+    g->sreal = m.get<uint8_t>(p->t.nstate);
+    for (int k = 0; k < D; k++) g->tw[k] = m.get<double2>(dims[k] / 2);
+    if (!m.ok) return NPCF_E_NOMEM;
+    hipStream_t s = p->stream;
+    std::vector<uint8_t> sreal(p->t.nstate);
+    for (int st = 0; st < p->t.nstate; st++) sreal[st] = p->t.state_lab[3 * st] == 0;
+    NPCF_TRY(hipMemcpyAsync(g->sreal, sreal.data(), sreal.size(), hipMemcpyHostToDevice, s));
+    std::vector<std::vector<double2>> tws(D);
+    for (int k = 0; k < D; k++) {
+        const int n = dims[k];
+        tws[k].resize(n / 2);
+        for (int j = 0; j < n / 2; j++) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * j / n;
+            tws[k][j] = make_double2((double)cosl(a), (double)-sinl(a));
+        }
+        NPCF_TRY(hipMemcpyAsync(g->tw[k], tws[k].data(), tws[k].size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    }
+    GridArgs ga{};
+    ga.ng = g->ng;
+    for (int k = 0; k < 3; k++) {
+        ga.dims[k] = k < D ? dims[k] : 1;
+        ga.h[k] = k < D ? p->cfg.box[k] / dims[k] : 1.0;
+    }
+    ga.e2 = p->d_e2;
+    ga.nb = p->nb;
+    for (int b = 0; b < p->nb; b++) ga.inv_vb[b] = 1.0 / p->t.vb[b];
+    NPCF_TRY(launch_grid_kernel(D, p->L, ga, g->khat, (int64_t)g->nbs * g->ng, s));
+    int64_t stride = g->ng;
+    for (int k = 0; k < D; k++) {
+        stride /= dims[k];
+        NPCF_TRY(launch_fft(g->khat, g->khat, g->tw[k], dims[k], stride, (int64_t)g->nbs * g->ng, 0, nullptr, g->ng, s));
+    }
+    // in-range offsets (the same FP64 arithmetic as the kernel grid)
+    const double *e2 = p->t.e2.data();
+    int R[3] = {0, 0, 0};
+    for (int k = 0; k < D; k++) R[k] = (int)std::ceil(p->edges[p->nb] / ga.h[k]) + 1;
+    unsigned long long cnt = 0;
+    for (int a0 = -R[0]; a0 <= R[0]; a0++)
+        for (int a1 = -R[1]; a1 <= R[1]; a1++)
+            for (int a2 = (D == 3 ? -R[2] : 0); a2 <= (D == 3 ? R[2] : 0); a2++) {
+                const int mm[3] = {a0, a1, a2};
+                double r2 = 0.0;
+                for (int k = 0; k < D; k++) {
+                    const double d = (double)mm[k] * ga.h[k];
+                    r2 += d * d;
+                }
+                if (r2 >= e2[0] && r2 < e2[p->nb]) cnt++;
+            }
+    g->offsets_in_range = cnt;
+    NPCF_TRY(hipStreamSynchronize(s));
+    return NPCF_OK;
+}
+
+npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int64_t p1, int role)
+{
+    GridState *g = p->grid;
+    hipStream_t s = p->stream;
+    const int D = p->D;
+    double dV = 1.0;
+    for (int k = 0; k < D; k++) dV *= p->cfg.box[k] / g->dims[k];
+    StageTimer th;
+    npcf_status st = timer_begin(p, 0, th);
+    if (st != NPCF_OK) return st;
+    NPCF_TRY(launch_grid_weights(field, g->ng, dV, g->w64, g->w32, g->xhat, p->bad, s));
+    int64_t stride = g->ng;
+    for (int k = 0; k < D; k++) {
+        stride /= g->dims[k];
+        NPCF_TRY(launch_fft(g->xhat, g->xhat, g->tw[k], g->dims[k], stride, g->ng, 0, nullptr, g->ng, s));
+    }
+    // a = FFT^-1[FFT(w) FFT(K')]: the product is taken as the first inverse pass loads
+    stride = g->ng;
+    for (int k = 0; k < D; k++) {
+        stride /= g->dims[k];
+        NPCF_TRY(launch_fft(k == 0 ? g->khat : g->work, g->work, g->tw[k], g->dims[k], stride,
+                            (int64_t)g->nbs * g->ng, 1, k == 0 ? g->xhat : nullptr, g->ng, s));
+    }
+    NPCF_TRY(launch_add_u64(p->pairs + role, (unsigned long long)(p1 - p0) * g->offsets_in_range, s));
+    NPCF_TRY(hipEventRecord(th.b, s));
+    p->timers[0].push_back(th);
+    for (int64_t c0 = p0; c0 < p1; c0 += p->rows_cap) {
+        const int rows = (int)std::min<int64_t>(p->rows_cap, p1 - c0);
+        StageTimer tr;
+        st = timer_begin(p, 0, tr);
+        if (st != NPCF_OK) return st;
+        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, p->t.nstate, g->sreal, g->w32, c0, rows, p->A, p->wrow, s));
+        NPCF_TRY(hipEventRecord(tr.b, s));
+        p->timers[0].push_back(tr);
+        st = run_couple(p, rows, p->acc[role]);
+        if (st != NPCF_OK) return st;
+    }
+    return NPCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -865,6 +1008,7 @@ npcf_status npcf_destroy(npcf_plan_t p)
     (void)hipStreamSynchronize(p->stream);
     clear_timers(p);
     batch_release(p);
+    grid_release(p);
     p->mem.release();
     p->cellmem.release();
     delete p;
@@ -899,6 +1043,38 @@ npcf_status npcf_accumulate(npcf_plan_t p, const double *pos, const double *w, i
     if (st != NPCF_OK) return st;
     if (role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
     st = accumulate_impl(p, pos, w, n, prim_begin, prim_end, p->acc[role], p->pairs + role);
+    if (st != NPCF_OK) p->failed = true;
+    return st;
+}
+
+npcf_status npcf_accumulate_grid(npcf_plan_t p, const double *field, const int *dims, int64_t prim_begin,
+                                 int64_t prim_end, int role)
+{
+    if (!p || !field || !dims) return NPCF_E_INVALID;
+    if (p->failed) return NPCF_E_STATE;
+    if (role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
+    if (p->D > 3) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "gridded data needs D = 2 or 3");
+        return NPCF_E_UNSUPPORTED;
+    }
+    if (!p->cfg.periodic) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "gridded data needs a periodic box");
+        return NPCF_E_INVALID;
+    }
+    int64_t ng = 1;
+    for (int k = 0; k < p->D; k++) {
+        if (!pow2_in(dims[k], 2, 2048)) {
+            std::snprintf(g_last_error, sizeof(g_last_error), "grid dims must be powers of two in 2..2048");
+            return NPCF_E_INVALID;
+        }
+        ng *= dims[k];
+    }
+    if (ng > (int64_t)INT32_MAX || prim_begin < 0 || prim_end > ng || prim_begin >= prim_end) return NPCF_E_INVALID;
+    bool same = p->grid != nullptr;
+    for (int k = 0; k < p->D && same; k++) same = p->grid->dims[k] == dims[k];
+    npcf_status st = NPCF_OK;
+    if (!same) st = grid_setup(p, dims);
+    if (st == NPCF_OK) st = grid_accumulate(p, field, prim_begin, prim_end, role);
     if (st != NPCF_OK) p->failed = true;
     return st;
 }

@@ -198,6 +198,18 @@ struct CoupleArgs {
 };
 
 // ---------------------------------------------------------------------------
+// Gridded-data estimator (npcf_grid.hip).
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    int dims[3];
+    int64_t ng;
+    double h[3];            // grid spacing per axis
+    const double *e2;       // [nb + 1] squared edges (device)
+    int nb;
+    double inv_vb[kMaxBins];
+};
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -240,6 +252,18 @@ hipError_t launch_reduce_partials(const double *partial, int nrb, int64_t len, d
 hipError_t launch_finalize2(const double *acc, const double *acc_rand, int nlam, int nparts, int mtiles,
                             const int *bt_row, const int *bt_col, const double *bt_scale, int nbt, int norm_by_randoms,
                             int lam0, double *out, int *bad, hipStream_t s);
+// gridded data: kernel grids K'_{b,s} (zero-filled first), one FFT axis pass,
+// node weights, node rows of a, a device counter increment
+hipError_t launch_grid_kernel(int D, int L, const GridArgs &g, double2 *kern, int64_t nkern, hipStream_t s);
+int fft_lines_per_block(int n);
+int fft_lds_bytes(int n);
+hipError_t launch_fft(const double2 *src, double2 *dst, const double2 *tw, int n, int64_t stride, int64_t total,
+                      int inverse, const double2 *premul, int64_t ng, hipStream_t s);
+hipError_t launch_grid_weights(const double *field, int64_t ng, double dV, double *w64, float *w32, double2 *xin,
+                               int *bad, hipStream_t s);
+hipError_t launch_grid_rows(const double2 *a, int64_t ng, int nbs, int nst, const uint8_t *sreal, const float *w32,
+                            int64_t r0, int rows, float *A, float *wrow, hipStream_t s);
+hipError_t launch_add_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 // finalize from an accumulator index per output (N = 5): out[lam * nbt + t] =
 // acc[idx[lam * nbt + t]] * sign[lam] * bt_scale[t] (optionally over the randoms' Lambda = 0)
 hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,

@@ -17,6 +17,11 @@ turbulence simulations); none of those data sets is used.  Recipes:
   axis (wrapped), plus ``n_uniform`` uniform background points.
 * the isotropic 5PCF workload uses ``uniform`` in a unit cube, as the
   paper's 5PCF timing test does.
+* ``lognormal_grid`` -- a field on a periodic grid (the gridded-data
+  estimator's input): a Gaussian random field with power spectrum
+  P(k) ~ k^slope (random phases, unit variance), mapped to a log-normal
+  contrast X = exp(sigma g - sigma^2 / 2) - 1, as a stand-in for the density
+  of a turbulence simulation.
 * ``vorticity_tracers`` (D = 2) -- points drawn with density proportional to
   exp(omega) for a random-phase field omega on a grid, whose per-mode
   amplitude falls as 1/|k| (shell energy spectrum ~ k^-3), normalised to
@@ -79,6 +84,27 @@ def vorticity_tracers(rng: np.random.Generator, n: int, grid: int, box: float) -
     return to_lattice(np.stack([x, y]), [box, box])
 
 
+def lognormal_grid(rng: np.random.Generator, dims, slope: float = -11.0 / 3.0, sigma: float = 1.0) -> np.ndarray:
+    dims = tuple(int(d) for d in dims)
+    white = rng.normal(size=dims)
+    fk = np.fft.rfftn(white)
+    ks = np.meshgrid(*[np.fft.fftfreq(d) * d for d in dims[:-1]], np.fft.rfftfreq(dims[-1]) * dims[-1], indexing="ij")
+    kk = np.sqrt(sum(k * k for k in ks))
+    amp = np.zeros_like(kk)
+    amp[kk > 0] = kk[kk > 0] ** (slope / 2.0)
+    g = np.fft.irfftn(fk * amp, s=dims)
+    g = (g - g.mean()) / g.std()
+    return np.exp(sigma * g - 0.5 * sigma * sigma) - 1.0
+
+
+def grid_nodes(dims, box) -> np.ndarray:
+    """Node coordinates [D][prod dims] of a periodic grid (row-major, last axis
+    fastest), node (i_0, ..) at x_k = i_k box_k / dims_k."""
+    axes = [np.arange(d) * (b / d) for d, b in zip(dims, box)]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return to_lattice(np.stack([m.ravel() for m in mesh]), box)
+
+
 @dataclasses.dataclass
 class Workload:
     name: str
@@ -92,6 +118,7 @@ class Workload:
     n_data: int = 0          # leading points that are data (rest: randoms)
     note: str = ""
     Lmax: object = None      # line-of-sight basis (D = 3, N = 3): largest L; None: isotropic
+    field: object = None     # gridded data: the field on the grid (pos and w are then its nodes)
 
 
 def c1_small_3pcf(seed: int = 1001) -> Workload:
@@ -146,6 +173,26 @@ def c7_uniform_5pcf(seed: int = 1007, n: int = 100_000) -> Workload:
     box = [1.0] * 3
     pos = uniform(rng, n, box)
     return Workload(f"D3-N5-uniform-{n // 1000}k", 3, 5, 4, np.linspace(0.1, 0.4, 11), box, pos, np.ones(n), n)
+
+
+def grid_workload(name: str, D: int, N: int, lmax: int, dims, box, edges, seed: int, sigma: float = 1.0) -> Workload:
+    """A gridded-data workload: the log-normal field on the grid, and its node
+    catalogue (positions, weights X dV) for the pair path and the oracle."""
+    rng = np.random.default_rng(seed)
+    field = lognormal_grid(rng, dims, sigma=sigma)
+    pos = grid_nodes(dims, box)
+    dV = float(np.prod([b / d for d, b in zip(dims, box)]))
+    n = pos.shape[1]
+    return Workload(name, D, N, lmax, np.asarray(edges, dtype=np.float64), list(box), pos, field.ravel() * dV, n,
+                    field=field)
+
+
+def c8_grid_4pcf(seed: int = 1008, g: int = 128) -> Workload:
+    """D=3, N=4 on gridded data: a log-normal field (spectrum k^-11/3, sigma 1)
+    on a periodic 128^3 grid of unit spacing, 10 linear bins in [2, 12],
+    lmax = 4 (section "Application to Gridded Data")."""
+    return grid_workload(f"D3-N4-grid-{g}^3-lognormal", 3, 4, 4, (g, g, g), [float(g)] * 3, np.linspace(2.0, 12.0, 11),
+                         seed)
 
 
 def c3_vorticity_4pcf(seed: int = 1003, n: int = 500_000, grid: int = 1024) -> Workload:
