@@ -150,6 +150,15 @@ npcf_status npcf_accumulate(npcf_plan_t plan, const double *pos, const double *w
 npcf_status npcf_accumulate_grid(npcf_plan_t plan, const double *field, const int *dims, int64_t prim_begin,
                                  int64_t prim_end, int role);
 
+/* Harmonic stage of the gridded path alone: a^b_[l] (eq. alm-bin-def,
+ * including 1/v_b) of the nodes [prim_begin, prim_end), from the same FFTs as
+ * npcf_accumulate_grid, written to `out` (host, double, (prim_end -
+ * prim_begin) * nbins * n_state * 2 entries, layout as npcf_alm).  The node
+ * pairs are counted as data pairs.  Synchronises.  Errors as
+ * npcf_accumulate_grid, plus NPCF_E_INVALID when out_len is wrong. */
+npcf_status npcf_alm_grid(npcf_plan_t plan, const double *field, const int *dims, int64_t prim_begin,
+                          int64_t prim_end, double *out, size_t out_len);
+
 /* Synchronise the plan's stream and write the finalised estimator to `out`
  * (host, double, out_len entries): zeta / (V_D prod_i v_{b_i}), parity part
  * as described above, optionally divided by the randoms normalisation.

@@ -71,6 +71,7 @@ def load_library():
     lib.npcf_finalize.argtypes = [vp, dp, ctypes.c_size_t]
     lib.npcf_describe.argtypes = [vp, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_size_t)]
     lib.npcf_accumulate_grid.argtypes = [vp, vp, ip, i64, i64, ctypes.c_int]
+    lib.npcf_alm_grid.argtypes = [vp, vp, ip, i64, i64, dp, ctypes.c_size_t]
     lib.npcf_pair_count.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.npcf_alm.argtypes = [vp, vp, vp, i64, i64, i64, dp, ctypes.c_size_t]
     lib.npcf_accumulate_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
@@ -86,7 +87,7 @@ def load_library():
     lib.npcf_last_error_detail.restype = ctypes.c_char_p
     for name in ("npcf_plan", "npcf_accumulate", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
                  "npcf_accumulate_batch", "npcf_finalize_batch", "npcf_reset", "npcf_destroy", "npcf_set_tuning",
-                 "npcf_stage_ms", "npcf_autotune", "npcf_accumulate_grid"):
+                 "npcf_stage_ms", "npcf_autotune", "npcf_accumulate_grid", "npcf_alm_grid"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -184,6 +185,21 @@ class NPCF:
             prim_end = ng
         _check(load_library().npcf_accumulate_grid(self._h, _dptr(field), dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                                    int(prim_begin), int(prim_end), ROLE[role]), "npcf_accumulate_grid")
+
+    def alm_grid(self, field, prim_begin: int = 0, prim_end: int | None = None) -> np.ndarray:
+        """a^b_[l] of the grid nodes [prim_begin, prim_end) from the FFT path."""
+        dims = np.ascontiguousarray(list(field.shape), dtype=np.int32)
+        ng = int(np.prod(dims))
+        if prim_end is None:
+            prim_end = ng
+        nb = len(self.edges) - 1
+        nst = stored_states(self.D, self.lmax)
+        out = np.zeros((prim_end - prim_begin, nb, nst, 2))
+        _check(load_library().npcf_alm_grid(self._h, _dptr(field), dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                            int(prim_begin), int(prim_end),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+               "npcf_alm_grid")
+        return out[..., 0] + 1j * out[..., 1]
 
     def finalize(self) -> np.ndarray:
         out = np.zeros(self.out_len)

@@ -718,7 +718,6 @@ npcf_status grid_setup(npcf_plan_s *p, const int *dims)
     }
     ga.e2 = p->d_e2;
     ga.nb = p->nb;
-    for (int b = 0; b < p->nb; b++) ga.inv_vb[b] = 1.0 / p->t.vb[b];
     NPCF_TRY(launch_grid_kernel(D, p->L, ga, g->khat, (int64_t)g->nbs * g->ng, s));
     int64_t stride = g->ng;
     for (int k = 0; k < D; k++) {
@@ -746,7 +745,9 @@ npcf_status grid_setup(npcf_plan_s *p, const int *dims)
     return NPCF_OK;
 }
 
-npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int64_t p1, int role)
+// a on every node of the grid (g->work), counting the primaries' pairs into
+// the role's pair counter
+npcf_status grid_harmonics(npcf_plan_s *p, const double *field, int64_t p0, int64_t p1, int role)
 {
     GridState *g = p->grid;
     hipStream_t s = p->stream;
@@ -772,6 +773,15 @@ npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int
     NPCF_TRY(launch_add_u64(p->pairs + role, (unsigned long long)(p1 - p0) * g->offsets_in_range, s));
     NPCF_TRY(hipEventRecord(th.b, s));
     p->timers[0].push_back(th);
+    return NPCF_OK;
+}
+
+npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int64_t p1, int role)
+{
+    GridState *g = p->grid;
+    hipStream_t s = p->stream;
+    npcf_status st = grid_harmonics(p, field, p0, p1, role);
+    if (st != NPCF_OK) return st;
     for (int64_t c0 = p0; c0 < p1; c0 += p->rows_cap) {
         const int rows = (int)std::min<int64_t>(p->rows_cap, p1 - c0);
         StageTimer tr;
@@ -1047,12 +1057,11 @@ npcf_status npcf_accumulate(npcf_plan_t p, const double *pos, const double *w, i
     return st;
 }
 
-npcf_status npcf_accumulate_grid(npcf_plan_t p, const double *field, const int *dims, int64_t prim_begin,
-                                 int64_t prim_end, int role)
+static npcf_status grid_check(npcf_plan_t p, const double *field, const int *dims, int64_t prim_begin,
+                              int64_t prim_end)
 {
     if (!p || !field || !dims) return NPCF_E_INVALID;
     if (p->failed) return NPCF_E_STATE;
-    if (role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
     if (p->D > 3) {
         std::snprintf(g_last_error, sizeof(g_last_error), "gridded data needs D = 2 or 3");
         return NPCF_E_UNSUPPORTED;
@@ -1074,9 +1083,51 @@ npcf_status npcf_accumulate_grid(npcf_plan_t p, const double *field, const int *
     for (int k = 0; k < p->D && same; k++) same = p->grid->dims[k] == dims[k];
     npcf_status st = NPCF_OK;
     if (!same) st = grid_setup(p, dims);
-    if (st == NPCF_OK) st = grid_accumulate(p, field, prim_begin, prim_end, role);
     if (st != NPCF_OK) p->failed = true;
     return st;
+}
+
+npcf_status npcf_accumulate_grid(npcf_plan_t p, const double *field, const int *dims, int64_t prim_begin,
+                                 int64_t prim_end, int role)
+{
+    if (p && role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
+    npcf_status st = grid_check(p, field, dims, prim_begin, prim_end);
+    if (st != NPCF_OK) return st;
+    st = grid_accumulate(p, field, prim_begin, prim_end, role);
+    if (st != NPCF_OK) p->failed = true;
+    return st;
+}
+
+npcf_status npcf_alm_grid(npcf_plan_t p, const double *field, const int *dims, int64_t prim_begin, int64_t prim_end,
+                          double *out, size_t out_len)
+{
+    npcf_status st = grid_check(p, field, dims, prim_begin, prim_end);
+    if (st != NPCF_OK) return st;
+    const Tables &t = p->t;
+    const int64_t nprim = prim_end - prim_begin;
+    const int64_t per = (int64_t)p->nb * t.nstate * 2;
+    if (!out || out_len != (size_t)(nprim * per)) return NPCF_E_INVALID;
+    st = grid_harmonics(p, field, prim_begin, prim_end, NPCF_ROLE_DATA);
+    if (st != NPCF_OK) {
+        p->failed = true;
+        return st;
+    }
+    GridState *g = p->grid;
+    std::vector<float> Ah;
+    for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->rows_cap) {
+        const int rows = (int)std::min<int64_t>(p->rows_cap, prim_end - c0);
+        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, t.nstate, g->sreal, g->w32, c0, rows, p->A, p->wrow,
+                                  p->stream));
+        Ah.resize((size_t)rows * per);
+        NPCF_TRY(hipMemcpyAsync(Ah.data(), p->A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+        NPCF_TRY(hipStreamSynchronize(p->stream));
+        for (int r = 0; r < rows; r++)
+            for (int b = 0; b < p->nb; b++)
+                for (int64_t k = 0; k < 2 * t.nstate; k++)
+                    out[(c0 - prim_begin + r) * per + b * 2 * t.nstate + k] =
+                        (double)Ah[(size_t)r * per + b * 2 * t.nstate + k] / t.vb[b];
+    }
+    return NPCF_OK;
 }
 
 npcf_status npcf_describe(npcf_plan_t p, int *n_lambda, int *lambda_labels, int *n_bt, int *btuples, size_t *out_len)

@@ -1,8 +1,9 @@
 // Gridded-data estimator (section "Application to Gridded Data"): for a field
 // X on a periodic grid the harmonic coefficients of every node come from one
 // correlation per (bin, state),
-//   a^b_s(x) = 1/v_b sum_r w(x + r) conj(Y_s(rhat)) Theta^b(|r|),   w = X dV,
-// evaluated as the convolution w * K' with K'(r) = conj(Y_s(-rhat)) Theta^b(|r|) / v_b:
+//   a^b_s(x) = sum_r w(x + r) conj(Y_s(rhat)) Theta^b(|r|),   w = X dV
+// (the 1/v_b of eq. alm-bin-def is applied at finalize, as on the pair path),
+// evaluated as the convolution w * K' with K'(r) = conj(Y_s(-rhat)) Theta^b(|r|):
 //   a^b_s = FFT^-1[ FFT(w) FFT(K') ]
 // (the kernel with its sign flip stands for the (-1)^l of the paper's form).
 // The node rows of a then go through the same coupling kernels as the pair
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double2 *src, double2 *d
 
 // K'_{b,s} at every grid offset: node index -> minimum-image integer offset m,
 // r = m h, bin of r^2 (FP64, the definition's arithmetic), and for an
-// in-range r the harmonics of u = -rhat times 1 / (v_b ng) (the inverse FFT
-// is unnormalised).  kern is zero-filled before; states l1 = 0 get no
+// in-range r the harmonics of u = -rhat times 1 / ng (the inverse FFT is
+// unnormalised).  kern is zero-filled before; states l1 = 0 get no
 // imaginary part.
 template <int D, int L>
 __global__ __launch_bounds__(256) void k_grid_kernel(GridArgs g, double2 *kern)
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_grid_kernel(GridArgs g, double2 *kern)
     for (int k = 0; k < D; k++) u[k] = (float)(-d[k] * inv);
     constexpr int nst = stored_states(D, L);
     double2 *out = kern + (int64_t)b * nst * g.ng + node;
-    const float wk = (float)(g.inv_vb[b] / (double)g.ng);
+    const float wk = (float)(1.0 / (double)g.ng);
     harm::harmonics<D, L>(u, wk, [&](int slot, float v) {
         double2 *p = out + (int64_t)(slot >> 1) * g.ng;
         if (slot & 1)

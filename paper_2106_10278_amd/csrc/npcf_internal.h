@@ -206,7 +206,6 @@ struct GridArgs {
     double h[3];            // grid spacing per axis
     const double *e2;       // [nb + 1] squared edges (device)
     int nb;
-    double inv_vb[kMaxBins];
 };
 
 // ---------------------------------------------------------------------------

@@ -65,6 +65,31 @@ def test_grid_parity(case, precision):
     assert cerr <= TOL[precision]
 
 
+@pytest.mark.parametrize("D,lmax,dims,box,edges", [
+    (3, 4, (16, 16, 16), [16.0] * 3, np.linspace(1.5, 6.0, 5)),
+    (3, 2, (8, 16, 32), [8.0, 16.0, 32.0], np.linspace(1.0, 3.9, 4)),
+    (2, 8, (32, 64), [32.0, 64.0], np.linspace(1.0, 12.0, 6)),
+])
+def test_grid_alm_matches_oracle(D, lmax, dims, box, edges):
+    """Harmonic stage of the gridded path alone (FFT correlation, npcf_alm_grid)
+    against the oracle's a^b_[l] of the same nodes."""
+    import torch
+    from paper_2106_10278_amd import NPCF, stored_state_labels
+    wl = inputs.grid_workload("alm", D, 3, lmax, dims, box, edges, seed=11 + D)
+    print(f"[case] grid alm D={D} dims={dims}", flush=True)
+    plan = NPCF(D, 3, lmax, wl.edges, wl.box, max_points=wl.pos.shape[1])
+    field = torch.from_numpy(np.ascontiguousarray(wl.field)).to("cuda:0")
+    got = plan.alm_grid(field, 100, 300)
+    plan.close()
+    ref, _ = oracle.alm(D, lmax, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(100, 300))
+    olab = [tuple(r) for r in oracle.state_labels(D, lmax)]
+    idx = [olab.index((int(st[0]),) if D == 2 else (int(st[0]), int(st[1]))) for st in stored_state_labels(D, lmax)]
+    ref = ref[:, :, idx]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"[err] grid alm D={D}: {err:.3e}", flush=True)
+    assert err <= 2e-6
+
+
 def test_grid_matches_pair_path_and_ranges():
     """The FFT path equals the pair path on the node catalogue (two GPU
     paths), and node ranges add up."""
