@@ -92,7 +92,7 @@ def lognormal_grid(rng: np.random.Generator, dims, slope: float = -11.0 / 3.0, s
     kk = np.sqrt(sum(k * k for k in ks))
     amp = np.zeros_like(kk)
     amp[kk > 0] = kk[kk > 0] ** (slope / 2.0)
-    g = np.fft.irfftn(fk * amp, s=dims)
+    g = np.fft.irfftn(fk * amp, s=dims, axes=tuple(range(len(dims))))
     g = (g - g.mean()) / g.std()
     return np.exp(sigma * g - 0.5 * sigma * sigma) - 1.0
 

@@ -105,7 +105,7 @@ def test_grid_matches_pair_path_and_ranges():
     assert cerr <= 1e-6
     parts, _ = _grid_run(wl, ranges=[(0, 1000), (1000, 2500), (2500, 4096)])
     cerr2, _ = conditioned_error(parts, grid, scale)
-    assert cerr2 <= 1e-9
+    assert cerr2 <= 1e-6   # other row blocks: another FP32 summation order
 
 
 def test_grid_rejects():
