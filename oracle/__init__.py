@@ -49,6 +49,7 @@ class _Cfg(ctypes.Structure):
         ("box", ctypes.c_double * 4),
         ("periodic", ctypes.c_int), ("btuple_mode", ctypes.c_int),
         ("basis", ctypes.c_int), ("Lmax", ctypes.c_int),
+        ("geometry", ctypes.c_int),
     ]
 
 
@@ -193,7 +194,7 @@ def coupling_terms(D: int, N: int, lmax: int, Lmax=None):
     return lam, s, c
 
 
-def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None):
+def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None, sphere=False):
     edges = np.ascontiguousarray(edges, dtype=np.float64)
     cfg = _Cfg()
     cfg.D, cfg.N, cfg.lmax, cfg.nbins = D, N, lmax, len(edges) - 1
@@ -205,6 +206,7 @@ def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None):
     cfg.btuple_mode = btuple_mode
     cfg.basis = 0 if Lmax is None else 1
     cfg.Lmax = 0 if Lmax is None else int(Lmax)
+    cfg.geometry = 1 if sphere else 0
     return cfg, edges
 
 
@@ -218,10 +220,12 @@ def _prep(pos, w, prims):
     return pos, w, n, prims
 
 
-def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True):
-    """a^b_[l](y_j) for the listed primaries: complex [nprim][nbins][nstates]."""
+def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True, sphere=False):
+    """a^b_[l](y_j) for the listed primaries: complex [nprim][nbins][nstates].
+    sphere: points on the unit 2-sphere (D = 2, pos [3][n] unit vectors, edges
+    in radians of great-circle angle)."""
     lib = _load()
-    cfg, edges = _cfg(D, 3, lmax, edges, box, periodic)
+    cfg, edges = _cfg(D, 3, lmax, edges, box, periodic, sphere=sphere)
     pos, w, n, prims = _prep(pos, w, prims)
     nst = lib.oracle_num_states(D, lmax)
     out = np.zeros((len(prims), len(edges) - 1, nst, 2))
@@ -232,12 +236,12 @@ def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True):
     return out[..., 0] + 1j * out[..., 1], int(pairs.value)
 
 
-def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0, Lmax=None):
+def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0, Lmax=None, sphere=False):
     """Complex zeta^{Lambda,b} [nlambda][nbtuple] over the listed primaries
     (default: all) against all secondaries, plus the in-range pair count.
     With Lmax (D = 3, N = 3): the line-of-sight basis P^{0L}, L <= Lmax."""
     lib = _load()
-    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode, Lmax)
+    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode, Lmax, sphere)
     pos, w, n, prims = _prep(pos, w, prims)
     nlam = len(lambda_labels(D, N, lmax, Lmax)) if Lmax is not None else lib.oracle_num_lambda(D, N, lmax)
     nbt = lib.oracle_num_btuples(len(edges) - 1, N, btuple_mode)

@@ -48,6 +48,17 @@
  *    CG chain fixes it).  Labels are stored 5 integers each and radial tuples 4
  *    each for N = 5 (3 each otherwise).
  *
+ *  - with cfg->geometry = 1 (D = 2 only), points on the unit 2-sphere
+ *    (section "Cosmic Microwave Background"): positions are unit vectors in
+ *    R^3 (pos[3][n]); the radial coordinate is the great-circle angle theta
+ *    between primary p and secondary q, binned e_b <= theta < e_{b+1}, i.e.
+ *    cos(e_{b+1}) < p.q <= cos(e_b) on the FP64 dot product; the direction is
+ *    the angle phi of q in a right-handed orthonormal tangent frame (e1, e2)
+ *    at p, e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1, so
+ *    that cos phi, sin phi are q.e1, q.e2 over their norm; Y_l = e^{i l phi} /
+ *    sqrt(2 pi); v_b = 2 pi (cos e_b - cos e_{b+1}) (the annulus' area) and
+ *    V = 4 pi.  Isotropic components do not depend on the frame.
+ *
  * The unrestricted sum over secondaries k runs over all n points for every
  * primary (brute force, no cell grid); the self pair is excluded because
  * edges[0] > 0.
@@ -67,6 +78,7 @@ typedef struct {
     int btuple_mode;      /* 0: b1 < b2 < ... ; 1: every tuple */
     int basis;            /* 0: isotropic (vec L = 0); 1: line-of-sight P^{0L} (D = 3, N = 3) */
     int Lmax;             /* basis 1: largest L */
+    int geometry;         /* 0: flat box; 1: unit 2-sphere (D = 2) */
 } oracle_cfg;
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
@@ -599,6 +611,14 @@ int oracle_coupling_terms_los(int lmax, int Lmax, int cap, int *lam, int *s, dou
 static int check_cfg(const oracle_cfg *cfg)
 {
     if (!cfg || !cfg->edges) return OR_EINVAL;
+    if (cfg->geometry != 0 && cfg->geometry != 1) return OR_EINVAL;
+    if (cfg->geometry == 1) {
+        if (cfg->D != 2 || cfg->basis != 0 || cfg->N > 4) return OR_EUNSUP;
+        if (cfg->lmax < 0 || cfg->nbins < 1 || !(cfg->edges[0] > 0.0) || cfg->edges[cfg->nbins] > M_PI) return OR_EINVAL;
+        for (int b = 0; b < cfg->nbins; b++)
+            if (!(cfg->edges[b + 1] > cfg->edges[b])) return OR_EINVAL;
+        return OR_OK;
+    }
     if (cfg->D < 2 || cfg->D > 4 || cfg->N < 3 || cfg->N > 5) return OR_EUNSUP;
     if (cfg->N == 4 && cfg->D == 4) return OR_EUNSUP;
     if (cfg->N == 5 && cfg->D != 3) return OR_EUNSUP;
@@ -619,12 +639,57 @@ static int check_cfg(const oracle_cfg *cfg)
 
 /* Harmonic stage for one primary: a[b][s] (complex, interleaved re/im), already
  * divided by v_b.  Returns the number of in-range ordered pairs. */
+/* Unit 2-sphere (cfg->geometry = 1): see the header.  a[b][s] divided by the
+ * annulus area v_b. */
+static double sphere_bin_area(double e0, double e1) { return 2.0 * M_PI * (cos(e0) - cos(e1)); }
+
+static long harmonic_stage_sphere(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
+                                  int nst, double *a, double *yre, double *yim)
+{
+    const int nb = cfg->nbins;
+    const double p[3] = {pos[j], pos[n + j], pos[2 * n + j]};
+    /* tangent frame at p */
+    double ax[3] = {0.0, 0.0, 1.0};
+    if (fabs(p[2]) > 0.9) { ax[0] = 1.0; ax[2] = 0.0; }
+    double e1[3] = {ax[1] * p[2] - ax[2] * p[1], ax[2] * p[0] - ax[0] * p[2], ax[0] * p[1] - ax[1] * p[0]};
+    double nn = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int k = 0; k < 3; k++) e1[k] /= nn;
+    const double e2[3] = {p[1] * e1[2] - p[2] * e1[1], p[2] * e1[0] - p[0] * e1[2], p[0] * e1[1] - p[1] * e1[0]};
+    long pairs = 0;
+    for (long k = 0; k < n; k++) {
+        const double q[3] = {pos[k], pos[n + k], pos[2 * n + k]};
+        const double c = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+        /* e_b <= theta < e_{b+1}  <=>  cos(e_{b+1}) < c <= cos(e_b) */
+        if (!(c <= cos(cfg->edges[0]) && c > cos(cfg->edges[nb]))) continue;
+        int b = 0;
+        while (b + 1 < nb && c <= cos(cfg->edges[b + 1])) b++;
+        const double t1 = q[0] * e1[0] + q[1] * e1[1] + q[2] * e1[2];
+        const double t2 = q[0] * e2[0] + q[1] * e2[1] + q[2] * e2[2];
+        const double tn = sqrt(t1 * t1 + t2 * t2);
+        if (!(tn > 0.0)) continue;
+        const double u[2] = {t1 / tn, t2 / tn};
+        pairs++;
+        oracle_harmonics(2, cfg->lmax, u, yre, yim);
+        double *ab = a + 2 * (size_t)b * nst;
+        for (int s = 0; s < nst; s++) {
+            ab[2 * s] += w[k] * yre[s];
+            ab[2 * s + 1] -= w[k] * yim[s];  /* conj(Y) */
+        }
+    }
+    for (int b = 0; b < nb; b++) {
+        const double vb = sphere_bin_area(cfg->edges[b], cfg->edges[b + 1]);
+        for (int s = 0; s < 2 * nst; s++) a[2 * (size_t)b * nst + s] /= vb;
+    }
+    return pairs;
+}
+
 static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
                            int nst, double *a, double *yre, double *yim)
 {
     const int D = cfg->D, nb = cfg->nbins;
     memset(a, 0, sizeof(double) * 2 * (size_t)nb * nst);
     long pairs = 0;
+    if (cfg->geometry == 1) return harmonic_stage_sphere(cfg, pos, w, n, j, nst, a, yre, yim);
     double e2lo = cfg->edges[0] * cfg->edges[0];
     double e2hi = cfg->edges[nb] * cfg->edges[nb];
     for (long k = 0; k < n; k++) {
@@ -762,6 +827,7 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
     if (fail) { free(part); free(bt); free(terms); return OR_ENOMEM; }
     double VD = 1.0;
     for (int k = 0; k < D; k++) VD *= cfg->box[k];
+    if (cfg->geometry == 1) VD = 4.0 * M_PI;   /* area of the unit 2-sphere */
     for (size_t i = 0; i < zlen; i++) {
         double s = 0.0;
         for (int t = 0; t < nthr; t++) s += part[(size_t)t * zlen + i];

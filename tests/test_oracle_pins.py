@@ -806,3 +806,127 @@ def test_5pcf_lattice_symmetries():
         z2, _ = oracle.npcf(3, 5, lmax, wl.edges, wl.box, _apply_cube_symmetry(wl, perm, flips), wl.w, btuple_mode=1)
         sign = np.where((par % 2 == 1) & (det < 0), -1.0, 1.0)
         np.testing.assert_allclose(z2, sign[:, None] * z, atol=1e-12 * scale)
+
+
+# --------------------------------------------------------------------------
+# Points on the unit 2-sphere (D = 2 harmonics; section "Cosmic Microwave Background")
+# --------------------------------------------------------------------------
+
+def _sphere_points(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(3, n))
+    return x / np.linalg.norm(x, axis=0), rng.uniform(-0.5, 1.5, size=n)
+
+
+def _sphere_area_quad(e0, e1):
+    from scipy.integrate import quad
+    return 2 * math.pi * quad(math.sin, e0, e1, epsabs=1e-14, epsrel=1e-14)[0]
+
+
+def _sphere_brute(pos, w, edges, N, lmax, btuple_mode):
+    """Naive estimator on S^2: for each primary p, unrestricted (N-1)-tuples of
+    secondaries in the angular bins, basis (2 pi)^{-(N-1)/2} e^{i sum l_k phi_k}
+    with phi measured from the spherical-coordinate direction e_theta of p (a
+    frame other than the oracle's), coefficients through conj(P), over 4 pi."""
+    labels = oracle.lambda_labels(2, N, lmax)
+    nb = len(edges) - 1
+    vb = np.array([_sphere_area_quad(edges[b], edges[b + 1]) for b in range(nb)])
+    n = pos.shape[1]
+    full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
+    for j in range(n):
+        p = pos[:, j]
+        th = math.acos(np.clip(p[2], -1, 1))
+        ph = math.atan2(p[1], p[0])
+        et = np.array([math.cos(th) * math.cos(ph), math.cos(th) * math.sin(ph), -math.sin(th)])
+        ep = np.array([-math.sin(ph), math.cos(ph), 0.0])
+        ang = np.arccos(np.clip(pos.T @ p, -1, 1))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        idx = np.nonzero(ok)[0]
+        if len(idx) == 0:
+            continue
+        b = np.searchsorted(edges, ang[idx], side="right") - 1
+        phi = np.arctan2(pos[:, idx].T @ ep, pos[:, idx].T @ et)
+        Bm = np.zeros((len(idx), nb))
+        Bm[np.arange(len(idx)), b] = w[idx] / vb[b]
+        ls = [labels[:, k] for k in range(N - 1)]
+        if N == 3:
+            P = np.exp(1j * (ls[0][:, None, None] * phi[None, :, None] + ls[1][:, None, None] * phi[None, None, :]))
+            full += w[j] * np.einsum("lpq,pa,qb->lab", np.conj(P), Bm, Bm) / (2 * math.pi)
+        else:
+            P = np.exp(1j * (ls[0][:, None, None, None] * phi[None, :, None, None]
+                             + ls[1][:, None, None, None] * phi[None, None, :, None]
+                             + ls[2][:, None, None, None] * phi[None, None, None, :]))
+            full += w[j] * np.einsum("lpqr,pa,qb,rc->labc", np.conj(P), Bm, Bm, Bm, optimize=True) / (2 * math.pi) ** 1.5
+    full /= 4 * math.pi
+    bt = oracle.btuple_labels(nb, N, btuple_mode)
+    return full[(slice(None),) + tuple(bt[:, k] for k in range(N - 1))]
+
+
+@pytest.mark.parametrize("N,lmax,mode", [(4, 3, 1), (3, 5, 1), (4, 2, 0)])
+def test_sphere_separable_equals_naive(N, lmax, mode):
+    edges = np.array([0.35, 0.6, 0.9, 1.3, 1.9]) if mode == 0 else np.array([0.3, 0.7, 1.2, 1.7])
+    pos, w = _sphere_points(60, 40 + N + lmax)
+    ref = _sphere_brute(pos, w, edges, N, lmax, mode)
+    got, _ = oracle.npcf(2, N, lmax, edges, [1.0, 1.0], pos, w, btuple_mode=mode, sphere=True)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+def test_sphere_rotation_invariance_and_l0():
+    """Any rotation of the sphere leaves every isotropic component unchanged;
+    zeta_{000}^b = sum_p w_p prod_i W_{b_i}(p) / (4 pi prod v_{b_i} (2 pi)^{(N-1)/2})
+    with the bin areas from quadrature."""
+    N, lmax = 4, 3
+    edges = np.array([0.3, 0.7, 1.2, 1.7])
+    pos, w = _sphere_points(200, 9)
+    z, pairs = oracle.npcf(2, N, lmax, edges, [1.0, 1.0], pos, w, btuple_mode=1, sphere=True)
+    R = rand_rotation(np.random.default_rng(5), 3)
+    z2, pairs2 = oracle.npcf(2, N, lmax, edges, [1.0, 1.0], R @ pos, w, btuple_mode=1, sphere=True)
+    assert pairs2 == pairs
+    np.testing.assert_allclose(z2, z, rtol=0, atol=1e-12 * np.abs(z).max())
+    nb = len(edges) - 1
+    vb = np.array([_sphere_area_quad(edges[b], edges[b + 1]) for b in range(nb)])
+    labels = oracle.lambda_labels(2, N, lmax)
+    i0 = int(np.nonzero(np.all(labels == 0, axis=1))[0][0])
+    bt = oracle.btuple_labels(nb, N, 1)
+    ref = np.zeros(len(bt))
+    for j in range(pos.shape[1]):
+        ang = np.arccos(np.clip(pos.T @ pos[:, j], -1, 1))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        b = np.searchsorted(edges, ang[ok], side="right") - 1
+        W = np.bincount(b, weights=w[ok], minlength=nb) / vb
+        ref += w[j] * np.prod(W[bt], axis=1)
+    ref /= 4 * math.pi * (2 * math.pi) ** ((N - 1) / 2)
+    np.testing.assert_allclose(z[i0].real, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+def test_sphere_alm_frame_phase():
+    """a_l of the oracle in its tangent frame equals, up to the phase e^{-i l alpha}
+    of the frame's rotation alpha, the sum in the spherical-coordinate frame."""
+    pos, w = _sphere_points(80, 3)
+    edges = np.array([0.4, 1.0, 1.6])
+    lmax = 4
+    a, _ = oracle.alm(2, lmax, edges, [1.0, 1.0], pos, w, sphere=True)
+    lab = oracle.state_labels(2, lmax)[:, 0]
+    vb = np.array([_sphere_area_quad(edges[b], edges[b + 1]) for b in range(2)])
+    for j in (0, 17, 55):
+        p = pos[:, j]
+        th, ph = math.acos(p[2]), math.atan2(p[1], p[0])
+        et = np.array([math.cos(th) * math.cos(ph), math.cos(th) * math.sin(ph), -math.sin(th)])
+        ep = np.array([-math.sin(ph), math.cos(ph), 0.0])
+        ang = np.arccos(np.clip(pos.T @ p, -1, 1))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        idx = np.nonzero(ok)[0]
+        b = np.searchsorted(edges, ang[idx], side="right") - 1
+        phi = np.arctan2(pos[:, idx].T @ ep, pos[:, idx].T @ et)
+        ref = np.zeros((2, len(lab)), dtype=complex)
+        for k in range(len(idx)):
+            ref[b[k]] += w[idx[k]] * np.exp(-1j * lab * phi[k]) / math.sqrt(2 * math.pi) / vb[b[k]]
+        # the two frames differ by one rotation angle per primary: a = ref * e^{i l alpha}
+        l1 = int(np.nonzero(lab == 1)[0][0])
+        alpha = np.angle(a[j, :, l1].sum() / ref[:, l1].sum())
+        np.testing.assert_allclose(a[j], ref * np.exp(1j * lab * alpha)[None, :], rtol=0, atol=1e-12 * np.abs(ref).max())
