@@ -85,6 +85,19 @@ typedef enum {
                                      line of sight along axis 3, labels (l1, l2, L), L <= Lmax */
 } npcf_basis;
 
+typedef enum {
+    NPCF_GEOMETRY_FLAT = 0,      /* flat box (periodic or open) */
+    NPCF_GEOMETRY_SPHERE = 1     /* points on the unit 2-sphere (section "Cosmic Microwave Background"):
+                                    D = 2, N = 3 or 4, isotropic basis, lmax <= 5; positions are unit
+                                    vectors in R^3 (pos [3][n]); edges are great-circle angles in
+                                    radians, 0 < edges[0], edges[nbins] <= pi, bins e_b <= theta <
+                                    e_{b+1} decided on the FP64 dot product; the direction of a
+                                    secondary is its angle in the tangent frame e1 = unit(z x p)
+                                    (unit(x x p) when |p_z| > 0.9), e2 = p x e1 at the primary p;
+                                    v_b = 2 pi (cos e_b - cos e_{b+1}), V = 4 pi; box and periodic
+                                    are ignored; every secondary is visited (no cell list) */
+} npcf_geometry;
+
 typedef struct {
     int D;               /* dimension: 2, 3 or 4 */
     int N;               /* correlation order: 3, 4 or 5 (N = 4 needs D <= 3, N = 5 D = 3) */
@@ -99,6 +112,7 @@ typedef struct {
     int norm;            /* npcf_norm */
     int basis;           /* npcf_basis (0 for a zero-initialised config) */
     int Lmax;            /* NPCF_BASIS_LINE_OF_SIGHT: largest L, 0..2 lmax (ignored otherwise) */
+    int geometry;        /* npcf_geometry (0, flat, for a zero-initialised config) */
 } npcf_config;
 
 typedef struct npcf_plan_s *npcf_plan_t;

@@ -44,6 +44,7 @@ class _Config(ctypes.Structure):
         ("periodic", ctypes.c_int), ("btuple_mode", ctypes.c_int),
         ("precision", ctypes.c_int), ("norm", ctypes.c_int),
         ("basis", ctypes.c_int), ("Lmax", ctypes.c_int),
+        ("geometry", ctypes.c_int),
     ]
 
 
@@ -129,7 +130,7 @@ class NPCF:
 
     def __init__(self, D: int, N: int, lmax: int, edges, box, periodic: bool = True, btuple_mode: int = 0,
                  precision: str = "plain", norm: str = "raw", max_points: int = 1 << 20, stream=None,
-                 Lmax=None):
+                 Lmax=None, sphere: bool = False):
         lib = load_library()
         self.D, self.N, self.lmax = int(D), int(N), int(lmax)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -146,6 +147,8 @@ class NPCF:
         # Lmax given: the line-of-sight basis P^{0L}_{l1 l2} (D = 3, N = 3)
         cfg.basis = 0 if Lmax is None else 1
         cfg.Lmax = 0 if Lmax is None else int(Lmax)
+        # points on the unit 2-sphere (D = 2): pos [3][n] unit vectors, edges in radians
+        cfg.geometry = 1 if sphere else 0
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

@@ -426,9 +426,44 @@ npcf_status prepare(npcf_plan_s *p, const double *pos, const double *w, int64_t 
     return NPCF_OK;
 }
 
+// Sphere harmonic stage for rows [0, rows) = primaries p0 + [0, rows): every
+// secondary, no cell list.
+npcf_status run_sphere(npcf_plan_s *p, const double *pos, const double *w, int64_t n, int64_t p0, int rows,
+                       unsigned long long *pairs)
+{
+    SphereArgs a{};
+    a.pos = pos;
+    a.w = w;
+    a.n = n;
+    a.p0 = p0;
+    a.rows = rows;
+    a.nb = p->nb;
+    for (int b = 0; b <= p->nb; b++) a.cedge[b] = p->t.cedge[b];
+    a.A = p->A;
+    a.wrow = p->wrow;
+    a.pairs = pairs;
+    StageTimer t;
+    npcf_status st = timer_begin(p, 0, t);
+    if (st != NPCF_OK) return st;
+    NPCF_TRY(launch_sphere(p->L, a, p->stream));
+    NPCF_TRY(hipEventRecord(t.b, p->stream));
+    p->timers[0].push_back(t);
+    return NPCF_OK;
+}
+
 npcf_status accumulate_impl(npcf_plan_s *p, const double *pos, const double *w, int64_t n, int64_t p0, int64_t p1,
                             double *acc, unsigned long long *pairs)
 {
+    if (p->t.sphere) {
+        for (int64_t c0 = p0; c0 < p1; c0 += p->rows_cap) {
+            const int rows = (int)std::min<int64_t>(p->rows_cap, p1 - c0);
+            npcf_status st = run_sphere(p, pos, w, n, c0, rows, pairs);
+            if (st != NPCF_OK) return st;
+            st = run_couple(p, rows, acc);
+            if (st != NPCF_OK) return st;
+        }
+        return NPCF_OK;
+    }
     npcf_status st = prepare(p, pos, w, n, p0, p1);
     if (st != NPCF_OK) return st;
     const int64_t nprim = p1 - p0;
@@ -1062,6 +1097,10 @@ static npcf_status grid_check(npcf_plan_t p, const double *field, const int *dim
 {
     if (!p || !field || !dims) return NPCF_E_INVALID;
     if (p->failed) return NPCF_E_STATE;
+    if (p->t.sphere) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "gridded data needs flat geometry");
+        return NPCF_E_UNSUPPORTED;
+    }
     if (p->D > 3) {
         std::snprintf(g_last_error, sizeof(g_last_error), "gridded data needs D = 2 or 3");
         return NPCF_E_UNSUPPORTED;
@@ -1188,6 +1227,26 @@ npcf_status npcf_alm(npcf_plan_t p, const double *pos, const double *w, int64_t 
     const int64_t nprim = prim_end - prim_begin;
     const int64_t per = (int64_t)p->nb * t.nstate * 2;
     if (!out || out_len != (size_t)(nprim * per)) return NPCF_E_INVALID;
+    if (t.sphere) {
+        std::vector<float> Ah;
+        for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->rows_cap) {
+            const int rows = (int)std::min<int64_t>(p->rows_cap, prim_end - c0);
+            st = run_sphere(p, pos, w, n, c0, rows, p->pairs);
+            if (st != NPCF_OK) {
+                p->failed = true;
+                return st;
+            }
+            Ah.resize((size_t)rows * per);
+            NPCF_TRY(hipMemcpyAsync(Ah.data(), p->A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+            NPCF_TRY(hipStreamSynchronize(p->stream));
+            for (int r = 0; r < rows; r++)
+                for (int b = 0; b < p->nb; b++)
+                    for (int64_t k = 0; k < 2 * t.nstate; k++)
+                        out[(c0 - prim_begin + r) * per + b * 2 * t.nstate + k] =
+                            (double)Ah[(size_t)r * per + b * 2 * t.nstate + k] / t.vb[b];
+        }
+        return NPCF_OK;
+    }
     st = prepare(p, pos, w, n, prim_begin, prim_end);
     if (st != NPCF_OK) {
         p->failed = true;
@@ -1221,6 +1280,10 @@ npcf_status npcf_alm(npcf_plan_t p, const double *pos, const double *w, int64_t 
 npcf_status npcf_accumulate_batch(npcf_plan_t p, int ncat, const double *const *pos, const double *const *w,
                                   const int64_t *n)
 {
+    if (p && p->t.sphere) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "batches are for flat geometry");
+        return NPCF_E_UNSUPPORTED;
+    }
     if (!p || ncat < 1 || !pos || !w || !n) return NPCF_E_INVALID;
     if (p->failed) return NPCF_E_STATE;
     if (p->cfg.norm == NPCF_NORM_BY_RANDOMS) return NPCF_E_UNSUPPORTED;
@@ -1289,6 +1352,13 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
 {
     npcf_status st = check_inputs(p, pos, w, n, 0, n);
     if (st != NPCF_OK) return st;
+    if (p->t.sphere) {
+        // no cell grid on the sphere: keep the automatic coupling block
+        if (cell_subdiv) *cell_subdiv = p->cell_subdiv;
+        if (couple_block) *couple_block = 0;
+        if (best_ms) *best_ms = 0.0;
+        return NPCF_OK;
+    }
     if (sample < 4) sample = 4;
     if (sample > n) sample = n;
     // four primary ranges spread over the catalogue (data and randoms alike)

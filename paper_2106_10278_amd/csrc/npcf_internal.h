@@ -209,6 +209,23 @@ struct GridArgs {
 };
 
 // ---------------------------------------------------------------------------
+// Points on the unit 2-sphere (npcf_sphere.hip).
+// ---------------------------------------------------------------------------
+constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
+struct SphereArgs {
+    const double *pos;          // [3][n] unit vectors
+    const double *w;            // [n]
+    int64_t n;
+    int64_t p0;                 // primary of row 0
+    int rows;
+    int nb;
+    double cedge[kMaxBins + 1]; // cos of the edges (decreasing)
+    float *A;                   // out: [rows][nb][2 (L + 1)]
+    float *wrow;                // out: [rows]
+    unsigned long long *pairs;  // in-range pair counter
+};
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -263,6 +280,7 @@ hipError_t launch_grid_weights(const double *field, int64_t ng, double dV, doubl
 hipError_t launch_grid_rows(const double2 *a, int64_t ng, int nbs, int nst, const uint8_t *sreal, const float *w32,
                             int64_t r0, int rows, float *A, float *wrow, hipStream_t s);
 hipError_t launch_add_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
+hipError_t launch_sphere(int L, const SphereArgs &a, hipStream_t s);
 // finalize from an accumulator index per output (N = 5): out[lam * nbt + t] =
 // acc[idx[lam * nbt + t]] * sign[lam] * bt_scale[t] (optionally over the randoms' Lambda = 0)
 hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
@@ -294,7 +312,9 @@ struct Tables {
     std::vector<uint8_t> bucket_bin;
     float bucket_lo = 0.f, bucket_inv = 0.f;
     float e2lo_f = 0.f, e2hi_f = 0.f;
-    std::vector<double> vb;            // bin volumes
+    std::vector<double> vb;            // bin volumes (sphere: annulus areas)
+    bool sphere = false;               // points on the unit 2-sphere
+    std::vector<double> cedge;         // sphere: cos of the edges
     int lam0 = 0;
     // factorised N = 4, D = 3 coupling (empty otherwise)
     std::vector<FPair> fpairs;

@@ -209,9 +209,17 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     if (!(cfg.edges[0] > 0.0)) { err = "edges[0] must be > 0"; return NPCF_E_INVALID; }
     for (int b = 0; b < nb; b++)
         if (!(cfg.edges[b + 1] > cfg.edges[b])) { err = "edges must increase strictly"; return NPCF_E_INVALID; }
-    for (int k = 0; k < D; k++) {
-        if (!(cfg.box[k] > 0.0) || !std::isfinite(cfg.box[k])) { err = "box sides must be positive"; return NPCF_E_INVALID; }
-        if (!(2.0 * cfg.edges[nb] < cfg.box[k])) { err = "need 2 * edges[nbins] < every box side"; return NPCF_E_INVALID; }
+    if (cfg.geometry != NPCF_GEOMETRY_FLAT && cfg.geometry != NPCF_GEOMETRY_SPHERE) { err = "unknown geometry"; return NPCF_E_INVALID; }
+    t.sphere = cfg.geometry == NPCF_GEOMETRY_SPHERE;
+    if (t.sphere) {
+        if (D != 2 || N > 4 || cfg.basis != NPCF_BASIS_ISOTROPIC) { err = "the sphere needs D = 2, N = 3 or 4 and the isotropic basis"; return NPCF_E_UNSUPPORTED; }
+        if (L > kLmaxSphere) { err = "lmax above 5 on the sphere"; return NPCF_E_UNSUPPORTED; }
+        if (!(cfg.edges[nb] <= M_PI)) { err = "sphere edges must not exceed pi"; return NPCF_E_INVALID; }
+    } else {
+        for (int k = 0; k < D; k++) {
+            if (!(cfg.box[k] > 0.0) || !std::isfinite(cfg.box[k])) { err = "box sides must be positive"; return NPCF_E_INVALID; }
+            if (!(2.0 * cfg.edges[nb] < cfg.box[k])) { err = "need 2 * edges[nbins] < every box side"; return NPCF_E_INVALID; }
+        }
     }
     if (cfg.btuple_mode != 0 && cfg.btuple_mode != 1) { err = "btuple_mode must be 0 or 1"; return NPCF_E_INVALID; }
     if (cfg.precision < 0 || cfg.precision > 3) { err = "unknown precision"; return NPCF_E_INVALID; }
@@ -345,6 +353,13 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     for (int b = 0; b < nb; b++) t.vb[b] = area * (std::pow(cfg.edges[b + 1], D) - std::pow(cfg.edges[b], D)) / D;
     double VD = 1.0;
     for (int k = 0; k < D; k++) VD *= cfg.box[k];
+    if (t.sphere) {
+        // annulus areas on the unit sphere, and its area as the volume
+        t.cedge.resize(nb + 1);
+        for (int b = 0; b <= nb; b++) t.cedge[b] = std::cos(cfg.edges[b]);
+        for (int b = 0; b < nb; b++) t.vb[b] = 2.0 * M_PI * (t.cedge[b] - t.cedge[b + 1]);
+        VD = 4.0 * M_PI;
+    }
     t.bt_scale.resize(t.nbt);
     for (int i = 0; i < t.nbt; i++) {
         double p = VD;

@@ -119,6 +119,7 @@ class Workload:
     note: str = ""
     Lmax: object = None      # line-of-sight basis (D = 3, N = 3): largest L; None: isotropic
     field: object = None     # gridded data: the field on the grid (pos and w are then its nodes)
+    sphere: bool = False     # points on the unit 2-sphere: pos [3][n] unit vectors, edges in radians
 
 
 def c1_small_3pcf(seed: int = 1001) -> Workload:
@@ -240,3 +241,21 @@ def tiny(D: int, N: int, lmax: int, n: int, seed: int, box_side: float = 10.0, r
         w = rng.uniform(-0.5, 1.5, size=n)
     edges = np.linspace(rmax / (nbins + 1), rmax, nbins + 1)
     return Workload(f"tiny-D{D}-N{N}-{n}", D, N, lmax, edges, box, pos, w, n)
+
+
+def sphere_points(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n points uniform on the unit 2-sphere: unit vectors [3][n] (normalised
+    Gaussian triples)."""
+    x = rng.normal(size=(3, n))
+    return x / np.linalg.norm(x, axis=0)
+
+
+def c9_sphere_4pcf(seed: int = 1009, n: int = 100_000) -> Workload:
+    """D=2, N=4 on the unit 2-sphere: n uniform points, w = 1, 10 bins equal
+    in cos(theta) over [-0.5, 0.5) (great-circle angles 60 to 120 degrees),
+    lmax = 4 -- the paper's CMB timing test (35 angular, 120 radial
+    components), at a fixed n."""
+    rng = np.random.default_rng(seed)
+    pos = sphere_points(rng, n)
+    edges = np.arccos(np.linspace(0.5, -0.5, 11))
+    return Workload(f"S2-N4-uniform-{n // 1000}k", 2, 4, 4, edges, [1.0, 1.0], pos, np.ones(n), n, sphere=True)

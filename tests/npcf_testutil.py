@@ -25,7 +25,9 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
     with every term replaced by its absolute value).  A sum evaluated with unit
     roundoff u has forward error bounded by about u times this scale, so errors
     are judged against it where the multipole itself cancels."""
-    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic)
+    sphere = getattr(wl, "sphere", False)
+    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic, sphere=sphere)
+    V = 4 * np.pi if sphere else float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
     lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax, Lmax)
     nb = len(wl.edges) - 1
     bts = oracle.btuple_labels(nb, wl.N, btuple_mode)
@@ -41,7 +43,7 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
             for k in range(1, 4):
                 X = X * A[:, bts[:, k]][:, :, s[sl, k]]
             np.add.at(out, lam[sl], np.abs(c[sl])[:, None] * X.sum(axis=0).T)
-        return out / float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
+        return out / V
     for t in range(len(lam)):
         if wl.N == 3:
             m = np.einsum("i,ij,ik->jk", w, A[:, :, s[t, 0]], A[:, :, s[t, 1]])
@@ -49,7 +51,7 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
         else:
             m = np.einsum("i,ij,ik,il->jkl", w, A[:, :, s[t, 0]], A[:, :, s[t, 1]], A[:, :, s[t, 2]])
             out[lam[t]] += abs(c[t]) * m[bts[:, 0], bts[:, 1], bts[:, 2]]
-    return out / float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
+    return out / V
 
 
 def conditioned_error(got, ref, scale):
@@ -61,7 +63,7 @@ def conditioned_error(got, ref, scale):
 
 def oracle_reported(wl, prims=None, btuple_mode=0, Lmax=None):
     z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims,
-                           btuple_mode=btuple_mode, Lmax=Lmax)
+                           btuple_mode=btuple_mode, Lmax=Lmax, sphere=getattr(wl, "sphere", False))
     labels = oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)
     return oracle.reported_part(z, labels, wl.D, wl.N, los=Lmax is not None), pairs, z
 
@@ -74,7 +76,7 @@ def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", 
     n = wl.pos.shape[1]
     if plan is None:
         plan = NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, btuple_mode=btuple_mode, precision=precision,
-                    max_points=n, Lmax=Lmax)
+                    max_points=n, Lmax=Lmax, sphere=getattr(wl, "sphere", False))
     if ranges is None:
         ranges = [(0, n)]
     for a, b in ranges:
