@@ -78,6 +78,8 @@ def make_workload(name: str):
         return inputs.c7_uniform_5pcf()
     if name == "c8":
         return inputs.c8_grid_4pcf()
+    if name == "c9":
+        return inputs.c9_sphere_4pcf()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -165,6 +167,16 @@ def coupling_roofline(key: str, path: str, coupling_ms: float):
             "stage_ms": coupling_ms, "source": d.get("source")}
 
 
+def sphere_flops(L: int, visited: float, pairs: float) -> float:
+    """FP32-equivalent operations of the sphere harmonic stage (FP64 counted
+    twice, the FP64 vector peak being half the FP32 one): every visited pair
+    takes an FP64 dot product (5) for its bin; an in-range pair adds two FP64
+    tangent projections (10), the squared norm (3) and its reciprocal square
+    root, then the D = 2 harmonics and their accumulation (6 per azimuthal
+    step, 2 per real output)."""
+    return 10.0 * visited + (2 * (10 + 3) + 1 + 6 * L + 2 * (2 * L + 1)) * pairs
+
+
 def grid_stage_bytes(wl) -> float:
     """Algorithmic HBM bytes of one pass of the gridded harmonic stage: the
     weights (read X, write w64, w32 and the complex FFT input), the forward
@@ -189,7 +201,8 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None):
     prims = np.concatenate([np.arange(a, b) for a, b in ranges])
     t0 = time.perf_counter()
     Lmax = wl.Lmax
-    z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax)
+    z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax,
+                           sphere=wl.sphere)
     dt = time.perf_counter() - t0
     ref = oracle.reported_part(z, oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax), wl.D, wl.N, los=Lmax is not None)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -297,7 +310,7 @@ def main():
 
     def factory(prec):
         return NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, precision=prec, max_points=n,
-                    Lmax=wl.Lmax)
+                    Lmax=wl.Lmax, sphere=wl.sphere)
 
     results = {}
     for prec in args.precisions.split(","):
@@ -343,6 +356,13 @@ def main():
     roof = {"kernel": "k_harmonic", "bound": "alu", "achieved": achieved / 1e12,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
             "traffic": load_traffic(key), "flops_per_pair": fpp, "launch_ms": r["harmonic_ms_per_launch"]}
+    if wl.sphere:
+        # every pair is visited (no cell list): count the bin test of all of them
+        fl = sphere_flops(wl.lmax, float(n) * n, r["pairs_per_step"])
+        ach = fl / (r["harmonic_ms_per_launch"] * 1e-3)
+        roof = {"kernel": "k_sphere", "bound": "alu", "achieved": ach / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK, "traffic": None,
+                "flops_per_pass": fl, "launch_ms": r["harmonic_ms_per_launch"]}
     if field is not None:
         # the gridded harmonic stage is FFT passes over HBM, not pair arithmetic
         gb = grid_stage_bytes(wl)
@@ -363,7 +383,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": key, "n_points": n, "n_data": wl.n_data, "D": wl.D, "N": wl.N, "lmax": wl.lmax,
                    "nbins": len(wl.edges) - 1, "r_range": [float(wl.edges[0]), float(wl.edges[-1])],
-                   "box": float(wl.box[0]), "parallelism": "single GPU"},
+                   "box": float(wl.box[0]), "geometry": "unit 2-sphere" if wl.sphere else "flat",
+                   "parallelism": "single GPU"},
         "paths": results,
         "roofline": roof,
         "coupling_roofline": coupling_roofline(key, head, r["stage_ms_per_step"]["coupling"]),
