@@ -9,10 +9,13 @@
 //    plain FP64 evaluation bit for bit);
 //  - frame: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
 //    (cos phi, sin phi) = (q.e1, q.e2) / |(q.e1, q.e2)|.
-// A block is 8 waves, one primary each; secondaries come through LDS in
-// tiles (FP64 x, y, z, w); bins are taken 4 per pass, each wave's lanes sum
-// the harmonics of their tile points in FP32 and fold into FP64 after every
-// tile, then the wave reduces its lanes.
+// A block is 8 waves, one primary each; secondaries come through LDS in FP32
+// tiles.  The FP32 cosine decides the bin unless it lies within 1e-6 of an
+// edge (its error is below 4e-7), where the FP64 dot product decides, so the
+// decisions equal the FP64 ones.  As many bins as fit about 100 registers
+// are taken per pass; each lane sums harmonics in FP32 (a 0/1 mask per bin)
+// and every few tiles the wave reduces its lanes into FP64 values held one or
+// two per lane.
 #include "npcf_internal.h"
 #include "npcf_harmonics.h"
 
@@ -22,7 +25,14 @@ namespace {
 
 constexpr int kSphTile = 512;
 constexpr int kSphWaves = 8;
-constexpr int kSphGroup = 4;   // bins per pass
+constexpr int kSphFold = 4;         // tiles between folds of the lanes' FP32 sums
+constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64
+
+// bins per pass: as many as keep the lanes' FP32 sums within about 100 registers
+__host__ __device__ constexpr int sph_group(int L)
+{
+    return (100 / (2 * (L + 1))) < 16 ? (100 / (2 * (L + 1))) : 16;
+}
 
 __device__ __forceinline__ double dot3_rn(double ax, double ay, double az, double bx, double by, double bz)
 {
@@ -32,8 +42,10 @@ __device__ __forceinline__ double dot3_rn(double ax, double ay, double az, doubl
 template <int L>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
-    __shared__ double4 tile[kSphTile];
+    __shared__ float4 tile[kSphTile];
     constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
+    constexpr int G = sph_group(L);
+    constexpr int NG = G * NV;        // values per pass, <= 100: lane j keeps values j and j + 64 in FP64
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * kSphWaves + wave;
     const bool active = row < a.rows;
@@ -51,75 +63,96 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     e1y *= inn;
     e1z *= inn;
     const double e2x = py * e1z - pz * e1y, e2y = pz * e1x - px * e1z, e2z = px * e1y - py * e1x;
+    const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
+    const float e1xf = (float)e1x, e1yf = (float)e1y, e1zf = (float)e1z;
+    const float e2xf = (float)e2x, e2yf = (float)e2y, e2zf = (float)e2z;
 
     unsigned long long cnt = 0;
-    for (int b0 = 0; b0 < a.nb; b0 += kSphGroup) {
-        const int ng = min(kSphGroup, a.nb - b0);
+    for (int b0 = 0; b0 < a.nb; b0 += G) {
+        const int ng = min(G, a.nb - b0);
         const double chi = a.cedge[b0], clo = a.cedge[b0 + ng];
-        double acc[kSphGroup][NV];
+        const float chif = (float)chi, clof = (float)clo;
+        double acc0 = 0.0, acc1 = 0.0;   // FP64 sums of values lane and lane + 64
+        float fs[G][NV];
 #pragma unroll
-        for (int g = 0; g < kSphGroup; g++)
+        for (int g = 0; g < G; g++)
 #pragma unroll
-            for (int v = 0; v < NV; v++) acc[g][v] = 0.0;
+            for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
+        int tiles = 0;
         for (int64_t t0 = 0; t0 < a.n; t0 += kSphTile) {
             const int cnt_t = (int)(a.n - t0 < kSphTile ? a.n - t0 : kSphTile);
             __syncthreads();
             for (int i = threadIdx.x; i < cnt_t; i += blockDim.x) {
                 const int64_t k = t0 + i;
-                tile[i] = make_double4(a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k], a.w[k]);
+                tile[i] = make_float4((float)a.pos[k], (float)a.pos[a.n + k], (float)a.pos[2 * a.n + k], (float)a.w[k]);
             }
             __syncthreads();
-            if (!active) continue;
-            float fs[kSphGroup][NV];
+            if (active) {
+                for (int i = lane; i < cnt_t; i += 64) {
+                    const float4 q = tile[i];
+                    const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
+                    if (c32 > chif + kSphGuard || c32 <= clof - kSphGuard) continue;
+                    // bin from the FP32 cosine; within the guard band of an edge, from the FP64 dot product
+                    bool near = fabsf(c32 - chif) <= kSphGuard || fabsf(c32 - clof) <= kSphGuard;
+                    int bl = 0;
 #pragma unroll
-            for (int g = 0; g < kSphGroup; g++)
+                    for (int g = 1; g < G; g++)
+                        if (g < ng) {
+                            const float ce = (float)a.cedge[b0 + g];
+                            near = near || fabsf(c32 - ce) <= kSphGuard;
+                            bl += c32 <= ce;
+                        }
+                    if (near) {
+                        const int64_t k = t0 + i;
+                        const double c = dot3_rn(px, py, pz, a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k]);
+                        if (!(c <= chi && c > clo)) continue;
+                        bl = 0;
+                        while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
+                    }
+                    const float t1 = q.x * e1xf + q.y * e1yf + q.z * e1zf;
+                    const float t2 = q.x * e2xf + q.y * e2yf + q.z * e2zf;
+                    const float tn2 = t1 * t1 + t2 * t2;
+                    if (!(tn2 > 0.f)) continue;
+                    const float itn = rsqrtf(tn2);
+                    const float u[2] = {t1 * itn, t2 * itn};
+                    cnt++;
+                    float hv[NV];
+                    hv[1] = 0.f;   // l = 0 is real
+                    harm::harmonics<2, L>(u, q.w, [&](int slot, float v) { hv[slot] = v; });
 #pragma unroll
-                for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
-            for (int i = lane; i < cnt_t; i += 64) {
-                const double4 q = tile[i];
-                const double c = dot3_rn(px, py, pz, q.x, q.y, q.z);
-                if (!(c <= chi && c > clo)) continue;
-                int bl = 0;
-                while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
-                const double t1 = q.x * e1x + q.y * e1y + q.z * e1z;
-                const double t2 = q.x * e2x + q.y * e2y + q.z * e2z;
-                const double tn2 = t1 * t1 + t2 * t2;
-                if (!(tn2 > 0.0)) continue;
-                const double itn = 1.0 / sqrt(tn2);
-                const float u[2] = {(float)(t1 * itn), (float)(t2 * itn)};
-                cnt++;
-                float hv[NV];
-                hv[1] = 0.f;   // l = 0 is real
-                harm::harmonics<2, L>(u, (float)q.w, [&](int slot, float v) { hv[slot] = v; });
+                    for (int g = 0; g < G; g++) {
+                        const float m = g == bl ? 1.f : 0.f;
 #pragma unroll
-                for (int g = 0; g < kSphGroup; g++) {
-                    const bool on = g == bl;
-#pragma unroll
-                    for (int v = 0; v < NV; v++) fs[g][v] += on ? hv[v] : 0.f;
+                        for (int v = 0; v < NV; v++) fs[g][v] = fmaf(m, hv[v], fs[g][v]);
+                    }
                 }
             }
+            // every kSphFold tiles and at the end: lanes' FP32 sums into the FP64 values
+            if (++tiles == kSphFold || t0 + kSphTile >= a.n) {
+                tiles = 0;
 #pragma unroll
-            for (int g = 0; g < kSphGroup; g++)
+                for (int g = 0; g < G; g++)
 #pragma unroll
-                for (int v = 0; v < NV; v++) acc[g][v] += (double)fs[g][v];
+                    for (int v = 0; v < NV; v++) {
+                        float x = fs[g][v];
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+                        const int j = g * NV + v;
+                        if (j == lane) acc0 += (double)x;
+                        if (j == lane + 64) acc1 += (double)x;
+                        fs[g][v] = 0.f;
+                    }
+            }
         }
-        // the wave's sums, written by lane 0
+        if (active) {
 #pragma unroll
-        for (int g = 0; g < kSphGroup; g++)
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                double x = acc[g][v];
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-                acc[g][v] = x;
-            }
-        if (active && lane == 0) {
-#pragma unroll
-            for (int g = 0; g < kSphGroup; g++)
-                if (g < ng) {
-#pragma unroll
-                    for (int v = 0; v < NV; v++) a.A[((int64_t)row * a.nb + b0 + g) * NV + v] = (float)acc[g][v];
+            for (int h = 0; h < 2; h++) {
+                const int j = lane + 64 * h;
+                if (j < NG) {
+                    const int g = j / NV, v = j - g * NV;
+                    if (g < ng) a.A[((int64_t)row * a.nb + b0 + g) * NV + v] = (float)(h ? acc1 : acc0);
                 }
+            }
         }
     }
     if (active) {
