@@ -140,7 +140,7 @@ def load_traffic(key: str):
 
 def coupling_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("npcf_couple.hip", "npcf_couple_common.h", "npcf_plan.cpp"):
+    for f in ("npcf_couple.hip", "npcf_couple_common.h", "npcf_plan4.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2106_10278_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

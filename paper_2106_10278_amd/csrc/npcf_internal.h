@@ -342,6 +342,8 @@ double clebsch_gordan(int j1, int m1, int j2, int m2, int J, int M);
 double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
 // stored state index: D = 2: l; D = 3: (l = l2, m = l1); D = 4: (l3, l2, l1)
 int state_index(int D, int l1, int l2, int l3);
+// factorised D = 3, N = 4 coupling tables (npcf_plan4.cpp); left empty when a pair's l3 values exceed the slots
+void build_factorised(Tables &t, int L);
 // N = 5 tables (npcf_plan5.cpp); false when the outputs exceed the index range
 bool build_c5(Tables &t, int L, int nb, int mode);
 
