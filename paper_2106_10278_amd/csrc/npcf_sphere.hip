@@ -39,10 +39,19 @@ __device__ __forceinline__ double dot3_rn(double ax, double ay, double az, doubl
     return __dadd_rn(__dadd_rn(__dmul_rn(ax, bx), __dmul_rn(ay, by)), __dmul_rn(az, bz));
 }
 
+#define NPCF_SPH_WAVE_SYNC()                                   \
+    do {                                                       \
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                       \
+    } while (0)
+
 template <int L>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
     __shared__ float4 tile[kSphTile];
+    // per wave: in-range pairs waiting for the harmonics (point, bin)
+    __shared__ float4 qpt[kSphWaves][128];
+    __shared__ int qbin[kSphWaves][128];
     constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
     constexpr int G = sph_group(L);
     constexpr int NG = G * NV;        // values per pass, <= 100: lane j keeps values j and j + 64 in FP64
@@ -67,7 +76,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     const float e1xf = (float)e1x, e1yf = (float)e1y, e1zf = (float)e1z;
     const float e2xf = (float)e2x, e2yf = (float)e2y, e2zf = (float)e2z;
 
-    unsigned long long cnt = 0;
+    unsigned long long cnt_pairs = 0;   // wave-uniform
     for (int b0 = 0; b0 < a.nb; b0 += G) {
         const int ng = min(G, a.nb - b0);
         const double chi = a.cedge[b0], clo = a.cedge[b0 + ng];
@@ -78,7 +87,33 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         for (int g = 0; g < G; g++)
 #pragma unroll
             for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
+        float cef[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) cef[g] = g < ng ? (float)a.cedge[b0 + g] : 0.f;
         int tiles = 0;
+        int qn = 0;   // queued pairs (wave-uniform)
+        // harmonics of the first cnt queued pairs, one per lane, into the bin sums
+        auto process = [&](int cnt) {
+            const bool live = lane < cnt;
+            const float4 q = live ? qpt[wave][lane] : make_float4(0.f, 0.f, 1.f, 0.f);
+            const int bl = live ? qbin[wave][lane] : 0;
+            const float t1 = q.x * e1xf + q.y * e1yf + q.z * e1zf;
+            const float t2 = q.x * e2xf + q.y * e2yf + q.z * e2zf;
+            const float tn2 = t1 * t1 + t2 * t2;
+            const bool ok = live && tn2 > 0.f;
+            const float itn = ok ? rsqrtf(tn2) : 0.f;
+            const float u[2] = {t1 * itn, t2 * itn};
+            cnt_pairs += __popcll(__builtin_amdgcn_ballot_w64(ok));
+            float hv[NV];
+            hv[1] = 0.f;   // l = 0 is real
+            harm::harmonics<2, L>(u, ok ? q.w : 0.f, [&](int slot, float v) { hv[slot] = v; });
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const float m = (ok && g == bl) ? 1.f : 0.f;
+#pragma unroll
+                for (int v = 0; v < NV; v++) fs[g][v] = fmaf(m, hv[v], fs[g][v]);
+            }
+        };
         for (int64_t t0 = 0; t0 < a.n; t0 += kSphTile) {
             const int cnt_t = (int)(a.n - t0 < kSphTile ? a.n - t0 : kSphTile);
             __syncthreads();
@@ -88,47 +123,71 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             }
             __syncthreads();
             if (active) {
-                for (int i = lane; i < cnt_t; i += 64) {
-                    const float4 q = tile[i];
-                    const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
-                    if (c32 > chif + kSphGuard || c32 <= clof - kSphGuard) continue;
-                    // bin from the FP32 cosine; within the guard band of an edge, from the FP64 dot product
-                    bool near = fabsf(c32 - chif) <= kSphGuard || fabsf(c32 - clof) <= kSphGuard;
+                // scan: bin of every point; in-range pairs go to the wave's queue
+                for (int i0 = 0; i0 < cnt_t; i0 += 64) {
+                    const int i = i0 + lane;
+                    bool valid = false;
                     int bl = 0;
+                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < cnt_t) {
+                        q = tile[i];
+                        const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
+                        if (c32 <= chif + kSphGuard && c32 > clof - kSphGuard) {
+                            // bin from the FP32 cosine; within the guard band of an edge, from the FP64 dot product
+                            bool near = fabsf(c32 - chif) <= kSphGuard || fabsf(c32 - clof) <= kSphGuard;
 #pragma unroll
-                    for (int g = 1; g < G; g++)
-                        if (g < ng) {
-                            const float ce = (float)a.cedge[b0 + g];
-                            near = near || fabsf(c32 - ce) <= kSphGuard;
-                            bl += c32 <= ce;
+                            for (int g = 1; g < G; g++)
+                                if (g < ng) {
+                                    const float ce = cef[g];
+                                    near = near || fabsf(c32 - ce) <= kSphGuard;
+                                    bl += c32 <= ce;
+                                }
+                            valid = true;
+                            if (near) {
+                                const int64_t k = t0 + i;
+                                const double c = dot3_rn(px, py, pz, a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k]);
+                                valid = c <= chi && c > clo;
+                                bl = 0;
+                                while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
+                            }
                         }
-                    if (near) {
-                        const int64_t k = t0 + i;
-                        const double c = dot3_rn(px, py, pz, a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k]);
-                        if (!(c <= chi && c > clo)) continue;
-                        bl = 0;
-                        while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
                     }
-                    const float t1 = q.x * e1xf + q.y * e1yf + q.z * e1zf;
-                    const float t2 = q.x * e2xf + q.y * e2yf + q.z * e2zf;
-                    const float tn2 = t1 * t1 + t2 * t2;
-                    if (!(tn2 > 0.f)) continue;
-                    const float itn = rsqrtf(tn2);
-                    const float u[2] = {t1 * itn, t2 * itn};
-                    cnt++;
-                    float hv[NV];
-                    hv[1] = 0.f;   // l = 0 is real
-                    harm::harmonics<2, L>(u, q.w, [&](int slot, float v) { hv[slot] = v; });
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        const float m = g == bl ? 1.f : 0.f;
-#pragma unroll
-                        for (int v = 0; v < NV; v++) fs[g][v] = fmaf(m, hv[v], fs[g][v]);
+                    const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
+                    const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
+                    if (valid) {
+                        qpt[wave][slot] = q;
+                        qbin[wave][slot] = bl;
+                    }
+                    qn += __popcll(vm);
+                    if (qn >= 64) {
+                        NPCF_SPH_WAVE_SYNC();
+                        process(64);
+                        // move the rest (< 64) to the front
+                        const int rest = qn - 64;
+                        float4 mq = make_float4(0.f, 0.f, 0.f, 0.f);
+                        int mb = 0;
+                        if (lane < rest) {
+                            mq = qpt[wave][64 + lane];
+                            mb = qbin[wave][64 + lane];
+                        }
+                        NPCF_SPH_WAVE_SYNC();
+                        if (lane < rest) {
+                            qpt[wave][lane] = mq;
+                            qbin[wave][lane] = mb;
+                        }
+                        qn = rest;
                     }
                 }
             }
             // every kSphFold tiles and at the end: lanes' FP32 sums into the FP64 values
-            if (++tiles == kSphFold || t0 + kSphTile >= a.n) {
+            const bool last = t0 + kSphTile >= a.n;
+            if (last && active && qn > 0) {
+                NPCF_SPH_WAVE_SYNC();
+                process(qn);
+                qn = 0;
+            }
+            if (++tiles == kSphFold || last) {
                 tiles = 0;
 #pragma unroll
                 for (int g = 0; g < G; g++)
@@ -155,13 +214,9 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             }
         }
     }
-    if (active) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0) {
-            atomicAdd(a.pairs, cnt);
-            a.wrow[row] = (float)a.w[pi];
-        }
+    if (active && lane == 0) {
+        atomicAdd(a.pairs, cnt_pairs);
+        a.wrow[row] = (float)a.w[pi];
     }
 }
 
