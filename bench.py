@@ -220,7 +220,15 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None):
         errs[prec] = {"max_rel_err": e, "worst_lambda": [int(x) for x in oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)[worst]],
                       "pairs_match": bool(gp == pairs)}
         plan.close()
-    base = {"value": pairs / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    base = {"value": pairs / dt, "unit": "pairs/s", "cores": cores, "cpu_model": cpu_model, "kind": "oracle",
             "sample": f"{len(prims)} primaries ({'+'.join(f'[{a},{b})' for a, b in ranges)}) against all "
                       f"{wl.pos.shape[1]} secondaries, {pairs} in-range pairs, {dt:.1f} s",
             "seconds": dt}
