@@ -52,6 +52,11 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     // per wave: in-range pairs waiting for the harmonics (point, bin)
     __shared__ float4 qpt[kSphWaves][128];
     __shared__ int qbin[kSphWaves][128];
+    // the pass's edge cosines (FP32) and a bucket table over its cosine range:
+    // bucket k holds the bin at its upper end, a guess corrected by the edges
+    constexpr int kBuckets = 1024;
+    __shared__ float sce[kMaxBins + 1];
+    __shared__ unsigned char sbk[kBuckets];
     constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
     constexpr int G = sph_group(L);
     constexpr int NG = G * NV;        // values per pass, <= 100: lane j keeps values j and j + 64 in FP64
@@ -87,9 +92,16 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         for (int g = 0; g < G; g++)
 #pragma unroll
             for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
-        float cef[G];
-#pragma unroll
-        for (int g = 0; g < G; g++) cef[g] = g < ng ? (float)a.cedge[b0 + g] : 0.f;
+        const float bw = (chif - clof) / kBuckets, ibw = bw > 0.f ? 1.f / bw : 0.f;
+        __syncthreads();
+        for (int g = threadIdx.x; g <= ng; g += blockDim.x) sce[g] = (float)a.cedge[b0 + g];
+        for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) {
+            const float ck = clof + (k + 1) * bw;   // upper end of bucket k
+            int b = 0;
+            for (int g = 1; g < ng; g++) b += ck <= (float)a.cedge[b0 + g];
+            sbk[k] = (unsigned char)b;
+        }
+        __syncthreads();
         int tiles = 0;
         int qn = 0;   // queued pairs (wave-uniform)
         // harmonics of the first cnt queued pairs, one per lane, into the bin sums
@@ -133,15 +145,14 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         q = tile[i];
                         const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
                         if (c32 <= chif + kSphGuard && c32 > clof - kSphGuard) {
-                            // bin from the FP32 cosine; within the guard band of an edge, from the FP64 dot product
-                            bool near = fabsf(c32 - chif) <= kSphGuard || fabsf(c32 - clof) <= kSphGuard;
-#pragma unroll
-                            for (int g = 1; g < G; g++)
-                                if (g < ng) {
-                                    const float ce = cef[g];
-                                    near = near || fabsf(c32 - ce) <= kSphGuard;
-                                    bl += c32 <= ce;
-                                }
+                            // bin from the FP32 cosine (bucket guess, corrected against the edges);
+                            // within the guard band of an edge, from the FP64 dot product
+                            int kb = (int)((c32 - clof) * ibw);
+                            kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
+                            bl = sbk[kb];
+                            while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
+                            while (bl > 0 && c32 > sce[bl]) bl--;
+                            const bool near = fabsf(c32 - sce[bl]) <= kSphGuard || fabsf(c32 - sce[bl + 1]) <= kSphGuard;
                             valid = true;
                             if (near) {
                                 const int64_t k = t0 + i;
