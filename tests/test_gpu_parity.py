@@ -160,6 +160,39 @@ def test_degenerate_inputs():
         plan4.finalize()
 
 
+def test_coincident_points():
+    """Every point taken twice: pairs at zero separation lie outside every bin
+    (the first edge is positive).  The doubled catalogue matches the oracle
+    on it, and 2^N times the single catalogue's result (4x the pairs)."""
+    base = _case(3, 4, 3, 150, 23, 16.0, 4.5, 4)
+    wl = inputs.Workload("twins", 3, 4, 3, base.edges, base.box, np.concatenate([base.pos, base.pos], axis=1),
+                         np.concatenate([base.w, base.w]), 300)
+    print("[case] coincident points", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl)
+    got1, pairs1, _ = gpu_run(base)
+    assert pairs == pairs_ref == 4 * pairs1
+    scale = condition_scale(wl)
+    _check(got, ref, "plain", scale, "twins", strict=False)
+    cerr, _ = conditioned_error(got, 16.0 * got1, scale)
+    print(f"[err] twins vs 16 x single conditioned {cerr:.3e}", flush=True)
+    assert cerr <= 2e-6
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 3, 4), (3, 4, 3), (2, 4, 4), (4, 3, 2)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_max_bins(D, N, lmax, mode):
+    """The largest bin count the library takes (16): every bit plane of the
+    in-batch bin sort and every bin row of the accumulators is used."""
+    box, rmax = {2: (12.0, 3.0), 3: (14.0, 4.0), 4: (9.0, 3.0)}[D]
+    wl = _case(D, N, lmax, 300, 70 + D + N, box, rmax, 16)
+    print(f"[case] max bins D={D} N={N} lmax={lmax} mode={mode}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl, btuple_mode=mode)
+    got, pairs, _ = gpu_run(wl, btuple_mode=mode)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl, mode), f"max bins D={D} N={N}", strict=False)
+
+
 FULL = {
     # workload factory, sampled primary ranges (data part, randoms part)
     "c2": (inputs.c2_clustered_4pcf, [(0, 48), (200_000, 200_048)]),

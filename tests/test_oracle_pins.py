@@ -524,6 +524,28 @@ def test_translation_and_weight_scaling():
     np.testing.assert_allclose(z3, 2.5 ** 4 * z, rtol=1e-12, atol=1e-14 * np.abs(z3).max())
 
 
+def _twins(wl):
+    """The catalogue with every point taken twice."""
+    return inputs.Workload(wl.name + "-twins", wl.D, wl.N, wl.lmax, wl.edges, wl.box,
+                           np.concatenate([wl.pos, wl.pos], axis=1), np.concatenate([wl.w, wl.w]),
+                           2 * wl.pos.shape[1])
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 3), (2, 3, 4), (4, 3, 2)])
+def test_coincident_twins_scale(D, N, lmax):
+    """Every point taken twice: a primary's twin lies at zero separation, outside
+    every bin (the first edge is positive), and every other neighbour counts
+    twice, so each of the twice as many primaries has twice the a^b_l:
+    zeta scales by 2^N and the pair count by 4."""
+    wl = inputs.tiny(D, N, lmax, 70, seed=41, box_side=8.0, rmax=3.0, nbins=3)
+    tw = _twins(wl)
+    z1, p1 = oracle.npcf(D, N, lmax, wl.edges, wl.box, wl.pos, wl.w, btuple_mode=1)
+    z2, p2 = oracle.npcf(D, N, lmax, tw.edges, tw.box, tw.pos, tw.w, btuple_mode=1)
+    assert p2 == 4 * p1
+    scale = np.abs(z1).max()
+    assert np.max(np.abs(z2 - 2.0 ** N * z1)) <= 1e-12 * 2.0 ** N * scale
+
+
 def test_primary_additivity():
     """Eq. NPCF-estimator-discrete sums over primaries: disjoint ranges add up."""
     wl = inputs.tiny(3, 4, 2, 50, seed=8, box_side=7.0, rmax=3.0, nbins=3)
