@@ -213,8 +213,8 @@ npcf_status npcf_alm(npcf_plan_t plan, const double *pos, const double *w, int64
                      int64_t prim_begin, int64_t prim_end, double *out, size_t out_len);
 
 /* Batched accumulation of `ncat` independent catalogues (the estimator of
- * eq. NPCF-estimator-discrete for each, every point a primary; the c4-style
- * workload of many data-plus-randoms catalogues of uneven sizes).
+ * eq. NPCF-estimator-discrete for each, every point a primary; e.g. many
+ * data-plus-randoms catalogues of uneven sizes).
  * Catalogue c: pos[c] (device, SoA double [D][n[c]]) and w[c] (device,
  * double [n[c]]); data and randoms of one catalogue are one point set told
  * apart only by their weights.  All catalogues share one cell list (keys

@@ -215,7 +215,8 @@ int couple_rows_per_block(const npcf_plan_s *p, int64_t nrows)
     }
     if (p->N == 4) {
         // about 32k blocks in all, 256 to 1024 primaries each (measured at
-        // full size: c2 and c3 are fastest at 512-1024, slower at 64 and 2048)
+        // full size on 800k clustered D = 3 and 500k D = 2 points: fastest at
+        // 512-1024, slower at 64 and 2048)
         const int jpb = couple_jobs_per_block();
         const int bpr = (!p->t.fpairs.empty() && !p->term_coupling) ? couple_ftask_groups((int)p->t.ftasks.size())
                                                                      : (p->njobs + jpb - 1) / jpb;

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
     constexpr int NE = C::NE;
     // candidate batches in flight in phase A: D = 4 rows of cells hold fewer
     // candidates per segment, so the loads of one batch alone do not cover
-    // the latency (measured: c5 179 -> 177 ms with two; c2 165 -> 166 ms)
+    // the latency (measured: 2M clustered D = 4 points 179 -> 177 ms with two; 800k
+    // clustered D = 3 points 165 -> 166 ms)
     constexpr int kPrefetch = D == 4 ? 2 : 1;
     extern __shared__ __align__(16) char smem[];
     const int nb = a.nb;

@@ -146,11 +146,12 @@ def c2_clustered_4pcf(seed: int = 1002, n_data: int = 200_000, n_rand: int = 600
 
 
 def c6_los_3pcf(seed: int = 1006, n_data: int = 200_000, n_rand: int = 600_000) -> Workload:
-    """D=3, N=3, line-of-sight basis (L <= 6): the c2 catalogue shape with
-    redshift-space-like anisotropy -- blob offsets along axis 3 four times
-    wider (sigma 20 against 5 across) -- 200k data (half in 2000 blobs, half
-    uniform), w = +1, plus 600k uniform randoms with w = -1/3, periodic cube of
-    side 1000, 10 linear bins in [20, 160], lmax = 5."""
+    """D=3, N=3, line-of-sight basis (L <= 6): the shape of the clustered
+    800k-point catalogue (c2_clustered_4pcf) with redshift-space-like
+    anisotropy -- blob offsets along axis 3 four times wider (sigma 20 against
+    5 across) -- 200k data (half in 2000 blobs, half uniform), w = +1, plus
+    600k uniform randoms with w = -1/3, periodic cube of side 1000, 10 linear
+    bins in [20, 160], lmax = 5."""
     rng = np.random.default_rng(seed)
     box = np.array([1000.0] * 3)
     nb = n_data // 2
@@ -213,7 +214,7 @@ def c4_batch_sizes(count: int = 64, seed: int = 4000) -> list:
 
 def c4_catalogue(c: int, n_data: int) -> Workload:
     """One catalogue of the batched D=3, N=4 workload (seed 4000 + c): the
-    clustered generator of c2 plus 3 n_data uniform randoms at w = -1/3."""
+    clustered generator (c2_clustered_4pcf) plus 3 n_data uniform randoms at w = -1/3."""
     return c2_clustered_4pcf(seed=4000 + c, n_data=n_data, n_rand=3 * n_data)
 
 
