@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -116,11 +117,23 @@ def rel_err(got, ref):
     return float(np.max(errs)), int(np.argmax(errs))
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """C++/HIP source without its comments and blank lines, so that the hashes
+    below follow the code and not the wording of its comments."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
+def _sources_hash(files) -> str:
     h = hashlib.sha256()
-    for f in ("npcf_harmonic_impl.h",):
-        h.update(open(os.path.join(ROOT, "paper_2106_10278_amd", "csrc", f), "rb").read())
+    for f in files:
+        h.update(_code_only(open(os.path.join(ROOT, "paper_2106_10278_amd", "csrc", f)).read()).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash() -> str:
+    return _sources_hash(("npcf_harmonic_impl.h",))
 
 
 def load_traffic(key: str):
@@ -139,10 +152,7 @@ def load_traffic(key: str):
 
 
 def coupling_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("npcf_couple.hip", "npcf_couple_common.h", "npcf_plan4.cpp"):
-        h.update(open(os.path.join(ROOT, "paper_2106_10278_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    return _sources_hash(("npcf_couple.hip", "npcf_couple_common.h", "npcf_plan4.cpp"))
 
 
 def coupling_roofline(key: str, path: str, coupling_ms: float):
