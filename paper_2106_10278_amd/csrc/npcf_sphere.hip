@@ -52,9 +52,14 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     // per wave: in-range pairs waiting for the harmonics (point, bin)
     __shared__ float4 qpt[kSphWaves][128];
     __shared__ int qbin[kSphWaves][128];
-    // the pass's edge cosines (FP32) and a bucket table over its cosine range:
-    // bucket k holds the bin at its upper end, a guess corrected by the edges
-    constexpr int kBuckets = 1024;
+    // the pass's edge cosines (FP32) and a bucket table over its cosine range.
+    // Entry k is the bin of every cosine in bucket k when no edge, widened by
+    // twice the guard, lies in buckets k - 1 .. k + 1 (the FP32 bucket index
+    // of a cosine is off by at most one); such a cosine is then more than the
+    // guard from every edge and the entry decides.  Otherwise the entry is
+    // 0x80 | the bin at the bucket's upper end, a guess that the search
+    // against the edge cosines corrects, followed by the guard test.
+    constexpr int kBuckets = 8192;
     __shared__ float sce[kMaxBins + 1];
     __shared__ unsigned char sbk[kBuckets];
     constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
@@ -96,10 +101,21 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         __syncthreads();
         for (int g = threadIdx.x; g <= ng; g += blockDim.x) sce[g] = (float)a.cedge[b0 + g];
         for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) {
+            const double lo = (double)clof + (k - 1) * (double)bw - 2.0 * kSphGuard;
+            const double hi = (double)clof + (k + 2) * (double)bw + 2.0 * kSphGuard;
+            const double mid = (double)clof + (k + 0.5) * (double)bw;
             const float ck = clof + (k + 1) * bw;   // upper end of bucket k
-            int b = 0;
-            for (int g = 1; g < ng; g++) b += ck <= (float)a.cedge[b0 + g];
-            sbk[k] = (unsigned char)b;
+            bool edge = false;
+            int b = 0, bg = 0;
+            for (int g = 0; g <= ng; g++) {
+                const double e = a.cedge[b0 + g];
+                edge = edge || (e >= lo && e <= hi);
+                if (g >= 1 && g < ng) {
+                    b += mid <= e;
+                    bg += ck <= (float)e;
+                }
+            }
+            sbk[k] = (unsigned char)(edge ? (0x80 | bg) : b);
         }
         __syncthreads();
         int tiles = 0;
@@ -145,15 +161,20 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         q = tile[i];
                         const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
                         if (c32 <= chif + kSphGuard && c32 > clof - kSphGuard) {
-                            // bin from the FP32 cosine (bucket guess, corrected against the edges);
-                            // within the guard band of an edge, from the FP64 dot product
+                            // bin from the bucket table; near an edge, from the FP32
+                            // cosine against the edges, and within the guard band of
+                            // an edge from the FP64 dot product
                             int kb = (int)((c32 - clof) * ibw);
                             kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
-                            bl = sbk[kb];
-                            while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
-                            while (bl > 0 && c32 > sce[bl]) bl--;
-                            const bool near = fabsf(c32 - sce[bl]) <= kSphGuard || fabsf(c32 - sce[bl + 1]) <= kSphGuard;
+                            const int ent = sbk[kb];
+                            bl = ent & 0x7F;
                             valid = true;
+                            bool near = false;
+                            if (ent & 0x80) {
+                                while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
+                                while (bl > 0 && c32 > sce[bl]) bl--;
+                                near = fabsf(c32 - sce[bl]) <= kSphGuard || fabsf(c32 - sce[bl + 1]) <= kSphGuard;
+                            }
                             if (near) {
                                 const int64_t k = t0 + i;
                                 const double c = dot3_rn(px, py, pz, a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k]);
