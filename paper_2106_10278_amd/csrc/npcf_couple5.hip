@@ -29,10 +29,8 @@ __device__ __forceinline__ void mfma_k32_f16_rowscaled(const float (&Av)[8], con
         ma = fmaxf(ma, fabsf(Av[i]));
         mb = fmaxf(mb, fabsf(Bv[i]));
     }
-    ma = fmaxf(ma, __shfl_xor(ma, 16));
-    ma = fmaxf(ma, __shfl_xor(ma, 32));
-    mb = fmaxf(mb, __shfl_xor(mb, 16));
-    mb = fmaxf(mb, __shfl_xor(mb, 32));
+    ma = max_over_lane_bits45(ma);
+    mb = max_over_lane_bits45(mb);
     const float sa = pow2_scale(ma), sb = pow2_scale(mb);
     v8h ah, al, bh, bl;
 #pragma unroll

@@ -18,13 +18,42 @@ constexpr int kXcd = 8;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// x of the partner lane under a DPP lane pattern (within rows of 16 lanes)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Largest m over the lanes l, l ^ 16, l ^ 32, l ^ 48, in every lane: each
+// permlane swap of a register with itself hands a lane the value of lane
+// l ^ 16 (l ^ 32) in one of the two results.  No LDS traffic.
+__device__ __forceinline__ float max_over_lane_bits45(float m)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+    m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    r = __builtin_amdgcn_permlane32_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+    return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
+// Largest m over the wave, in every lane: DPP steps pair lanes l ^ 1, l ^ 2
+// (quad permutations), l ^ 7 (mirror within 8) and l ^ 8 (rotation by 8
+// within 16), then the permlane swaps cover lane bits 4 and 5.
+__device__ __forceinline__ float wave_max(float m)
+{
+    m = fmaxf(m, dpp_f<0xB1>(m));
+    m = fmaxf(m, dpp_f<0x4E>(m));
+    m = fmaxf(m, dpp_f<0x141>(m));
+    m = fmaxf(m, dpp_f<0x128>(m));
+    return max_over_lane_bits45(m);
+}
+
 // Power-of-two scale that brings the wave's largest |x| into [0.5, 1) (1 when
 // every x is zero).  FP16's exponent range is too narrow for products of
 // coefficients spanning many octaves without it.
 __device__ __forceinline__ float wave_pow2_scale(float m)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    m = wave_max(m);
     if (!(m > 0.f) || !isfinite(m)) return 1.f;
     int e;
     frexpf(m, &e);
