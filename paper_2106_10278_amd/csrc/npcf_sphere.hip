@@ -12,10 +12,11 @@
 // A block is 8 waves, one primary each; secondaries come through LDS in FP32
 // tiles.  The FP32 cosine decides the bin unless it lies within 1e-6 of an
 // edge (its error is below 4e-7), where the FP64 dot product decides, so the
-// decisions equal the FP64 ones.  As many bins as fit about 100 registers
-// are taken per pass; each lane sums harmonics in FP32 (a 0/1 mask per bin)
-// and every few tiles the wave reduces its lanes into FP64 values held one or
-// two per lane.
+// decisions equal the FP64 ones.  As many bins as fit about 50 registers
+// are taken per pass (more passes rescan the points, but fewer registers let
+// four waves share a SIMD and each queued pair feeds fewer masked sums); each
+// lane sums harmonics in FP32 (a 0/1 mask per bin) and every few tiles the
+// wave reduces its lanes into FP64 values held one or two per lane.
 #include "npcf_internal.h"
 #include "npcf_harmonics.h"
 
@@ -28,10 +29,11 @@ constexpr int kSphWaves = 8;
 constexpr int kSphFold = 4;         // tiles between folds of the lanes' FP32 sums
 constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64
 
-// bins per pass: as many as keep the lanes' FP32 sums within about 100 registers
+// bins per pass: as many as keep the lanes' FP32 sums within kSphRegBudget registers
+constexpr int kSphRegBudget = 50;
 __host__ __device__ constexpr int sph_group(int L)
 {
-    return (100 / (2 * (L + 1))) < 16 ? (100 / (2 * (L + 1))) : 16;
+    return (kSphRegBudget / (2 * (L + 1))) < 16 ? (kSphRegBudget / (2 * (L + 1))) : 16;
 }
 
 __device__ __forceinline__ double dot3_rn(double ax, double ay, double az, double bx, double by, double bz)
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     __shared__ unsigned char sbk[kBuckets];
     constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
     constexpr int G = sph_group(L);
-    constexpr int NG = G * NV;        // values per pass, <= 100: lane j keeps values j and j + 64 in FP64
+    constexpr int NG = G * NV;        // values per pass, <= 50 (L <= 5): lane j keeps value j in FP64
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * kSphWaves + wave;
     const bool active = row < a.rows;
