@@ -220,7 +220,12 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                     if (i < cnt_t) {
                         q = tile[i];
                         const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
-                        if (c32 <= chif + kSphGuard && c32 > clof - kSphGuard) {
+                        // range prefilter on the same FP32 differences as the guard
+                        // test below, so that a cosine admitted beyond an outer edge
+                        // is always within the guard of it and decided in FP64
+                        // (chif + guard rounded in FP32 would admit cosines up to
+                        // one rounding beyond the guard)
+                        if (c32 - chif <= kSphGuard && clof - c32 < kSphGuard) {
                             // bin from the bucket table; near an edge, from the FP32
                             // cosine against the edges, and within the guard band of
                             // an edge from the FP64 dot product

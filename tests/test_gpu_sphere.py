@@ -47,6 +47,72 @@ def test_sphere_parity(case, precision):
     assert cerr <= TOL[precision]
 
 
+def _window_points(cos_edges, rng):
+    """Points whose FP32 cosine to (0, 0, 1) is the FP32 rounding of
+    cos(edge) + 1e-6 where that lies beyond the guard of the edge (true cosine
+    just beyond the edge), and mirror points just inside it."""
+    g = np.float32(1e-6)
+    zs = []
+    for c in cos_edges:
+        cf = np.float32(c)
+        hi = np.float32(cf + g)
+        if float(hi) - float(cf) > float(g):
+            zs += [float(hi) - 1e-9, float(hi) - 5e-9]
+        lo = np.float32(cf - g)
+        if float(cf) - float(lo) > float(g):
+            zs += [float(lo) + 1e-9, float(lo) + 5e-9]
+        zs += [c + 1.0e-6, c - 1.0e-6, c + 3e-7, c - 3e-7]
+    pts = []
+    for z in zs:
+        for phi in rng.uniform(0.0, 2 * np.pi, 3):
+            r = np.sqrt(1.0 - z * z)
+            pts.append((r * np.cos(phi), r * np.sin(phi), z))
+    return np.array(pts).T
+
+
+def test_sphere_edge_rounding_windows():
+    """Cosines beyond an outer edge of a pass by more than the guard but no
+    more than one FP32 rounding of (edge + guard): the FP32 range prefilter
+    must not admit them without the FP64 decision (regression: such pairs
+    were counted, twice at a boundary between passes).  11 bins at lmax 4
+    take three passes of 5, 5 and 1 bins."""
+    rng = np.random.default_rng(77)
+    ce = np.array([0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2, 0.1, 0.0, -0.2, -0.4, -0.5])
+    edges = np.arccos(ce)
+    planted = _window_points(np.cos(edges), rng)
+    pos = np.concatenate([np.array([[0.0], [0.0], [1.0]]), planted, inputs.sphere_points(rng, 150)], axis=1)
+    n = pos.shape[1]
+    wl = inputs.Workload("s2-windows", 2, 4, 4, edges, [1.0, 1.0], pos, rng.uniform(0.5, 1.5, size=n), n, sphere=True)
+    print(f"[case] sphere edge windows n={n}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl)
+    assert pairs == pairs_ref
+    cerr, _ = conditioned_error(got, ref, condition_scale(wl))
+    print(f"[err] sphere edge windows plain: conditioned {cerr:.3e}", flush=True)
+    assert cerr <= TOL["plain"]
+
+
+@pytest.mark.parametrize("lmax", [1, 4, 5])
+def test_c9_full_pair_count(lmax):
+    """Every ordered pair of the 100k-point catalogue (1e10 visited): the
+    number in the bins equals the FP64 oracle's count, stored in
+    tests/golden/c9_sphere_pairs.json by make_c9_sphere_pairs.py, exactly.
+    lmax 1, 4 and 5 take the 10 bins in one, two and three passes."""
+    import json
+    import os
+    import torch
+    from paper_2106_10278_amd import NPCF
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c9_sphere_pairs.json")))
+    wl = inputs.c9_sphere_4pcf()
+    assert gold["workload"] == wl.name and gold["n"] == wl.pos.shape[1]
+    print(f"[case] c9 full pair count lmax={lmax}", flush=True)
+    pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).cuda()
+    w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()
+    plan = NPCF(2, 4, lmax, wl.edges, wl.box, max_points=wl.pos.shape[1], sphere=True)
+    plan.accumulate(pos, w)
+    assert plan.pair_count()[0] == gold["pairs"]
+
+
 def test_sphere_alm_and_ranges():
     """The harmonic stage alone (npcf_alm on the sphere) against the oracle's
     a_l in the same tangent frame; primary ranges add up."""
