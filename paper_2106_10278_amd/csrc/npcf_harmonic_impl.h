@@ -247,11 +247,16 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             }
             int bin;
             {
+                // guess from the bucket table, accepted when the two edges
+                // around it (read together) bracket r^2; otherwise a walk
                 int bk = (int)(((float)r2 - a.bucket_lo) * a.bucket_inv);
                 bk = bk < 0 ? 0 : (bk >= a.nbucket ? a.nbucket - 1 : bk);
                 bin = btab[bk];
-                while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
-                while (bin > 0 && r2 < e2[bin]) bin--;
+                const double elo = e2[bin], ehi = e2[bin + 1];
+                if ((r2 < elo) | (r2 >= ehi)) {   // both edges needed: one LDS round trip
+                    while (bin + 1 < nb && r2 >= e2[bin + 1]) bin++;
+                    while (bin > 0 && r2 < e2[bin]) bin--;
+                }
             }
             const bool valid = live && r2 >= e2lo && r2 < e2hi;
             if (!valid) bin = 0;
