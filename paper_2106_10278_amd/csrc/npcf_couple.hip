@@ -200,9 +200,15 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
     for (int k = 0; k < NA; k++)
 #pragma unroll
         for (int q = 0; q < 4; q++) sr[k][q] = si[k][q] = 0.f;
+    // the 8-byte product descriptors as one 64-bit word each: a wave-uniform
+    // address, so a scalar load (the 16- and 8-bit fields alone became
+    // vector loads, one memory round trip per product)
+    const auto pd2 = (const __attribute__((address_space(4))) unsigned long long *)(prods + pb);
     for (int t = 0; t < np; t++) {
-        const int s1 = uni((int)prods[pb + t].s1), s2 = uni((int)prods[pb + t].s2);
-        const bool conj1 = uni((int)prods[pb + t].conj1) != 0, conj2 = uni((int)prods[pb + t].conj2) != 0;
+        const unsigned long long d = pd2[t];
+        const uint32_t dx = (uint32_t)d, dy = (uint32_t)(d >> 32);
+        const int s1 = uni((int)(int16_t)(dx & 0xFFFFu)), s2 = uni((int)(int16_t)(dx >> 16));
+        const bool conj1 = (dy & 0xFFu) != 0, conj2 = (dy & 0xFF00u) != 0;
         float c[NA];
 #pragma unroll
         for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + k * np + t]);
@@ -224,7 +230,9 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
     }
 #pragma unroll
     for (int k = 0; k < NA; k++) {
-        const int s3 = uni((int)groups[g].s3[k]);
+        // s3[] read as dwords (scalar loads), as the product descriptors
+        const uint32_t s3w = ((const __attribute__((address_space(4))) uint32_t *)&groups[g].s3[0])[k >> 1];
+        const int s3 = uni((int)(int16_t)(s3w >> (16 * (k & 1))));
         const int part = uni(pairs[pp].part[k]);
         float Av[8], Bv[8];
 #pragma unroll

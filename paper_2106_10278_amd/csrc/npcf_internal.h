@@ -1,6 +1,7 @@
 // Internal declarations shared by the host planner and the HIP kernels of the
 // NPCF library.  Nothing here is part of the public ABI (include/npcf.h).
 #pragma once
+#include <cstddef>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -95,6 +96,9 @@ struct FGroup {          // one (pair, m3)
     int nact;            // number of active slots
     int16_t s3[kMaxSlots];  // state of leg 3 for each slot: (l3, m3)
 };
+// the coupling kernel reads FProd as one uint2 and FGroup::s3 as dwords
+static_assert(sizeof(FProd) == 8, "FProd is read as one uint2");
+static_assert(offsetof(FGroup, s3) % 4 == 0 && sizeof(FGroup) % 4 == 0, "FGroup::s3 is read as dwords");
 struct FPair {
     int grp_begin, grp_end;
     int nslot;
