@@ -352,9 +352,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int rowlen = a.nb * 2 * a.nstate;
     float *Ast = reinterpret_cast<float *>(smem);
     float *wst = Ast + kRowsStep * rowlen;
+    float *sfs = wst + kRowsStep;   // per-state factors, copied once (read per operand element)
     const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
     int rb, jg;
     if (!block_work(a.n_rowblocks, njg, rb, jg)) return;
+    for (int t = threadIdx.x; t < a.nstate; t += blockDim.x) sfs[t] = sfac[t];   // the row loop's first barrier orders it
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                         const int c = rr & 1;
                         const float2 x = *reinterpret_cast<const float2 *>(Ast + p * rowlen + n * 2 * a.nstate + 2 * s);
                         Bv[i] = c ? x.y : x.x;
-                        const float wf = wst[p] * g.scale3 * sfac[s];
+                        const float wf = wst[p] * g.scale3 * sfs[s];
                         // Re(a[b1] conj(a[b2])) = ar ar' + ai ai';  Im = ai ar' - ar ai'
                         Av[i] = (part_kind == 0) ? wf * (c ? x.y : x.x) : wf * (c ? -x.x : x.y);
                     }
@@ -582,7 +584,11 @@ __global__ void k_finalize(FinArgs f)
 
 inline int couple_lds(const CoupleArgs &a)
 {
-    return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4 + a.max_block_terms * (int)sizeof(CoupleTerm);
+    // rows of a, weights, then the term list (N = 4, line of sight) or the
+    // per-state factors (isotropic N = 3)
+    const int tail = a.max_block_terms * (int)sizeof(CoupleTerm) > a.nstate * 4 ? a.max_block_terms * (int)sizeof(CoupleTerm)
+                                                                                : a.nstate * 4;
+    return (kRowsStep * a.nb * 2 * a.nstate + kRowsStep) * 4 + tail;
 }
 
 }  // namespace
