@@ -3,6 +3,7 @@
 //   quantise -> cell list -> primary list -> [harmonic -> coupling -> FP64 reduce] per chunk
 // on the plan's stream.  No exception crosses the ABI.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -890,6 +891,19 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
             const int gb = t.lam_group_begin[l0], ge = t.lam_group_begin[l1 + 1];
             if (gb < ge)
                 p->max_block_terms = std::max(p->max_block_terms, t.groups[ge - 1].term_end - t.groups[gb].term_begin);
+        }
+    } else if (p->N == 3 && t.n3_terms) {
+        // line-of-sight basis: a block's jobs are up to jpb consecutive Lambdas,
+        // one group each; the block copies the span of their term ranges
+        const int jpb = couple_jobs_per_block();
+        for (int j0 = 0; j0 < p->njobs; j0 += jpb) {
+            int tb = INT_MAX, te = 0;
+            for (int j = j0; j < std::min(j0 + jpb, p->njobs); j++) {
+                const CoupleGroup &g = t.groups[t.lam_group_begin[j]];
+                tb = std::min(tb, g.term_begin);
+                te = std::max(te, g.term_end);
+            }
+            if (te > tb) p->max_block_terms = std::max(p->max_block_terms, te - tb);
         }
     }
 

@@ -446,6 +446,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int wave = threadIdx.x >> 6;
     const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
 
+    // the span of term ranges of this block's Lambdas (one group each),
+    // copied to LDS once: each lane reads its operand's term per element
+    // (at most max_block_terms, the host's bound over all blocks)
+    CoupleTerm *tl = reinterpret_cast<CoupleTerm *>(wst + kRowsStep);
+    int tbase = 0;
+    {
+        int tb = 0x7fffffff, te = 0;
+        for (int lam = jg * 4 * kJobsPerWave; lam < njobs && lam < (jg + 1) * 4 * kJobsPerWave; lam++) {
+            const CoupleGroup gg = a.groups[a.lam_group_begin[lam]];
+            tb = min(tb, gg.term_begin);
+            te = max(te, gg.term_end);
+        }
+        if (te > tb) {
+            tbase = tb;
+            for (int t = threadIdx.x; t < te - tb; t += blockDim.x) tl[t] = a.terms[tb + t];   // ordered by the row loop's first barrier
+        }
+    }
+
     double acc64[kJobsPerWave][4];
 #pragma unroll
     for (int j = 0; j < kJobsPerWave; j++)
@@ -485,7 +503,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     if (k < ktot && bok) {
                         const int p = k / kper;
                         const int rr = k - p * kper;
-                        const CoupleTerm tm = a.terms[g.term_begin + (rr >> 1)];
+                        const CoupleTerm tm = tl[g.term_begin - tbase + (rr >> 1)];
                         const int c = rr & 1;
                         const float *Ap = Ast + p * rowlen + n * 2 * a.nstate;
                         const float2 x = *reinterpret_cast<const float2 *>(Ap + 2 * tm.s1);
