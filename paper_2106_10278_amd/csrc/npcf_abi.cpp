@@ -436,6 +436,7 @@ npcf_status run_sphere(npcf_plan_s *p, const double *pos, const double *w, int64
     SphereArgs a{};
     a.pos = pos;
     a.w = w;
+    a.pf = reinterpret_cast<float4 *>(p->rec);   // the flat path's record buffer (max_points x 16 B), unused here
     a.n = n;
     a.p0 = p0;
     a.rows = rows;

@@ -219,6 +219,7 @@ constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
 struct SphereArgs {
     const double *pos;          // [3][n] unit vectors
     const double *w;            // [n]
+    float4 *pf;                 // scratch [n]: (x, y, z, w) in FP32, written by launch_sphere
     int64_t n;
     int64_t p0;                 // primary of row 0
     int rows;

@@ -205,10 +205,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         for (int64_t t0 = 0; t0 < a.n; t0 += kSphTile) {
             const int cnt_t = (int)(a.n - t0 < kSphTile ? a.n - t0 : kSphTile);
             __syncthreads();
-            for (int i = threadIdx.x; i < cnt_t; i += blockDim.x) {
-                const int64_t k = t0 + i;
-                tile[i] = make_float4((float)a.pos[k], (float)a.pos[a.n + k], (float)a.pos[2 * a.n + k], (float)a.w[k]);
-            }
+            for (int i = threadIdx.x; i < cnt_t; i += blockDim.x) tile[i] = a.pf[t0 + i];
             __syncthreads();
             if (active) {
                 // scan: bin of every point; in-range pairs go to the wave's queue
@@ -313,9 +310,18 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     }
 }
 
+// the points in FP32 (x, y, z, w), once per launch: every block streams
+// them all in every pass
+__global__ __launch_bounds__(256) void k_sphere_pack(const double *pos, const double *w, int64_t n, float4 *pf)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pf[i] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i], (float)w[i]);
+}
+
 template <int L>
 hipError_t launch_l(const SphereArgs &a, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_sphere_pack, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n, a.pf);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
     hipLaunchKernelGGL(k_sphere<L>, dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
     return hipGetLastError();
