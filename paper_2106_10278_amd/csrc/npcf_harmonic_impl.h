@@ -331,11 +331,23 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                             s2 += x[2] + x[6];
                             s3 += x[3] + x[7];
                         }
-                        for (; t + 1 < te; t += 2) {
+                        // the rest (< 8 columns) by its bits: at most three
+                        // blocks of 4, 2 and 1 reads
+                        const int rem = te - t;
+                        if (rem & 4) {
+                            const float x0 = srow[t], x1 = srow[t + 1], x2 = srow[t + 2], x3 = srow[t + 3];
+                            s0 += x0;
+                            s1 += x1;
+                            s2 += x2;
+                            s3 += x3;
+                            t += 4;
+                        }
+                        if (rem & 2) {
                             s0 += srow[t];
                             s1 += srow[t + 1];
+                            t += 2;
                         }
-                        if (t < te) s2 += srow[t];
+                        if (rem & 1) s2 += srow[t];
                         acc[k * kMaxBins + b] += (double)((s0 + s1) + (s2 + s3));
                         j0 = te;
                     }
