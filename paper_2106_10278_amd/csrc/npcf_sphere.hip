@@ -10,9 +10,11 @@
 //  - frame: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
 //    (cos phi, sin phi) = (q.e1, q.e2) / |(q.e1, q.e2)|.
 // A block is 8 waves, one primary each; secondaries come through LDS in FP32
-// tiles.  The FP32 cosine decides the bin unless it lies within 1e-6 of an
-// edge (its error is below 4e-7), where the FP64 dot product decides, so the
-// decisions equal the FP64 ones.  As many bins as fit about 50 registers
+// tiles (the points are packed to FP32 once per launch).  The FP32 cosine
+// decides the bin (through a bucket table where no edge is near, else against
+// the edge cosines) unless it lies within 1e-6 of an edge (its error is below
+// 4e-7), where the FP64 dot product decides, so the decisions equal the FP64
+// ones.  As many bins as fit about 50 registers
 // are taken per pass (more passes rescan the points, but fewer registers let
 // four waves share a SIMD and each queued pair feeds fewer masked sums); each
 // lane sums harmonics in FP32 (a 0/1 mask per bin) and every few tiles the
