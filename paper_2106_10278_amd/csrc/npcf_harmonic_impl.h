@@ -317,12 +317,21 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                 for (int b = 0; b < kMaxBins; b++) {
                     const int cnt = bcnt[b];
                     if (cnt) {
-                        // eight columns in flight per step (the loads, not the
-                        // adds, set the pace), four partial sums
+                        // sixteen, then eight columns in flight per step (the
+                        // loads, not the adds, set the pace), four partial sums
                         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
                         int t = j0;
                         const int te = j0 + cnt;
-                        for (; t + 7 < te; t += 8) {
+                        for (; t + 15 < te; t += 16) {
+                            float x[16];
+#pragma unroll
+                            for (int q = 0; q < 16; q++) x[q] = srow[t + q];
+                            s0 += (x[0] + x[4]) + (x[8] + x[12]);
+                            s1 += (x[1] + x[5]) + (x[9] + x[13]);
+                            s2 += (x[2] + x[6]) + (x[10] + x[14]);
+                            s3 += (x[3] + x[7]) + (x[11] + x[15]);
+                        }
+                        if (t + 7 < te) {
                             float x[8];
 #pragma unroll
                             for (int q = 0; q < 8; q++) x[q] = srow[t + q];
@@ -330,6 +339,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                             s1 += x[1] + x[5];
                             s2 += x[2] + x[6];
                             s3 += x[3] + x[7];
+                            t += 8;
                         }
                         // the rest (< 8 columns) by its bits: at most three
                         // blocks of 4, 2 and 1 reads
