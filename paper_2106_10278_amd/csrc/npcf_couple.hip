@@ -211,7 +211,7 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
         const bool conj1 = (dy & 0xFFu) != 0, conj2 = (dy & 0xFF00u) != 0;
         float c[NA];
 #pragma unroll
-        for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + k * np + t]);
+        for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + t * kFCoefStride + k]);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const float *Ap = Ast + (4 * kq + q) * rowlen;

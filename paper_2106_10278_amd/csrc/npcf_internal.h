@@ -86,12 +86,16 @@ struct FProd {
     int8_t conj1, conj2;
     int16_t pad;
 };
+// coefficients per product in the factorised table: the slots of one product
+// are adjacent and 32-byte aligned (one wide scalar load)
+constexpr int kFCoefStride = 8;
+static_assert(kFCoefStride >= kMaxSlots, "a product holds every slot coefficient");
 // jobs (pair, tile) per wave of the factorised N = 4 coupling kernel
 constexpr int kFJobsPerWave = 1;
 
 struct FGroup {          // one (pair, m3)
     int prod_begin, prod_end;
-    int coef_begin;      // coef[coef_begin + slot * nprod + (t - prod_begin)]
+    int coef_begin;      // coef[coef_begin + (t - prod_begin) * kFCoefStride + slot]
     int slot_mask;       // slots with l3 >= m3: slots [0, nact) (a pair's slots run by falling l3)
     int nact;            // number of active slots
     int16_t s3[kMaxSlots];  // state of leg 3 for each slot: (l3, m3)

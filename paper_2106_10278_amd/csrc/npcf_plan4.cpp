@@ -80,7 +80,7 @@ void build_factorised(Tables &t, int L)
                 const int np = g.prod_end - g.prod_begin;
                 if (np == 0) continue;
                 g.coef_begin = (int)t.fcoef.size();
-                t.fcoef.resize(t.fcoef.size() + (size_t)kMaxSlots * np, 0.f);
+                t.fcoef.resize(t.fcoef.size() + (size_t)kFCoefStride * np, 0.f);
                 const double fold = (m3 > 0) ? 2.0 : 1.0;
                 for (int k = 0; k < pr.nslot; k++) {
                     const int l3 = t.lam_lab[3 * pr.lam[k] + 2];
@@ -97,7 +97,7 @@ void build_factorised(Tables &t, int L)
                         double sgn = 1.0;
                         if (m1 < 0 && (-m1) % 2) sgn = -sgn;
                         if (m2 < 0 && (-m2) % 2) sgn = -sgn;
-                        t.fcoef[g.coef_begin + k * np + j] = (float)(fold * sgn * c);
+                        t.fcoef[g.coef_begin + j * kFCoefStride + k] = (float)(fold * sgn * c);
                     }
                     c_pair += 2.0 * np + 8.0;  // FMAs into this slot's S and its MFMA slice
                 }
