@@ -243,7 +243,7 @@ def test_norm_by_randoms():
     i0 = int(np.nonzero(np.all(oracle.lambda_labels(3, 4, 2) == 0, axis=1))[0][0])
     # the quotient's error is the data estimate's plus the (well conditioned,
     # positive-weight) randoms' Lambda = 0 term's: undo the division by the
-    # oracle's denominator and judge the numerator on the conditioned measure
+    # oracle's denominator and assess the numerator on the conditioned measure
     cerr, _ = conditioned_error(got * zr[i0][None, :], zd, condition_scale(data))
     print(f"[err] by_randoms conditioned {cerr:.3e}", flush=True)
     assert cerr <= 2e-6
