@@ -17,6 +17,7 @@ import pytest
 from scipy.special import eval_gegenbauer, roots_legendre, sph_harm_y
 from sympy.physics.wigner import clebsch_gordan, wigner_3j
 
+import labels_indep
 import oracle
 from paper_2106_10278_amd import inputs
 
@@ -305,8 +306,9 @@ def _neighbours(wl, j, periodic=True):
 
 
 def _indep_basis(D, N, lmax):
-    """P^0_Lambda from SciPy/SymPy/closed forms, independent of the oracle."""
-    labels = oracle.lambda_labels(D, N, lmax)
+    """P^0_Lambda from SciPy/SymPy/closed forms, independent of the oracle
+    (labels too: enumerated from SymPy coefficients, not from the oracle)."""
+    labels = labels_indep.labels(D, N, lmax)
     if D == 2:
         def P(*dirs):
             ph = [np.arctan2(d[:, 1], d[:, 0]) for d in dirs]
@@ -368,7 +370,7 @@ def _brute_force(wl, btuple_mode, periodic=True):
     D, N = wl.D, wl.N
     nb = len(wl.edges) - 1
     vb = np.array([sphere_area(D) * (wl.edges[b + 1] ** D - wl.edges[b] ** D) / D for b in range(nb)])
-    labels = oracle.lambda_labels(D, N, wl.lmax)
+    labels = labels_indep.labels(D, N, wl.lmax)
     P = _indep_basis(D, N, wl.lmax)
     full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
     for j in range(wl.pos.shape[1]):
@@ -563,7 +565,7 @@ def test_primary_additivity():
 def _los_basis(lmax, Lmax):
     """P^{0L}_{l1 l2}(d1, d2) = (-1)^{l2-l1} sqrt(2L+1) sum_m (l1 l2 L; m -m 0)
     Y_{l1 m}(d1) Y_{l2,-m}(d2), from SciPy harmonics and SymPy 3j symbols."""
-    labels = oracle.lambda_labels(3, 3, lmax, Lmax)
+    labels = labels_indep.line_of_sight(lmax, Lmax)
 
     def Yall(d):
         th = np.arccos(np.clip(d[:, 2], -1, 1))
@@ -745,7 +747,7 @@ def _brute_force5(wl, btuple_mode):
     lmax = wl.lmax
     nb = len(wl.edges) - 1
     vb = np.array([sphere_area(3) * (wl.edges[b + 1] ** 3 - wl.edges[b] ** 3) / 3 for b in range(nb)])
-    labels = oracle.lambda_labels(3, 5, lmax)
+    labels = labels_indep.d3_n5(lmax)
     coup = []
     for l1, l2, l12, l3, l4 in labels:
         l1, l2, l12, l3, l4 = map(int, (l1, l2, l12, l3, l4))
@@ -850,7 +852,7 @@ def _sphere_brute(pos, w, edges, N, lmax, btuple_mode):
     secondaries in the angular bins, basis (2 pi)^{-(N-1)/2} e^{i sum l_k phi_k}
     with phi measured from the spherical-coordinate direction e_theta of p (a
     frame other than the oracle's), coefficients through conj(P), over 4 pi."""
-    labels = oracle.lambda_labels(2, N, lmax)
+    labels = labels_indep.d2(N, lmax)
     nb = len(edges) - 1
     vb = np.array([_sphere_area_quad(edges[b], edges[b + 1]) for b in range(nb)])
     n = pos.shape[1]
