@@ -122,7 +122,8 @@ typedef struct npcf_plan_s *npcf_plan_t;
  * FP64 and uploads them, and allocates device workspace for catalogues of up
  * to max_points points.  `stream` is a hipStream_t (NULL: the default
  * stream).  The plan owns all device memory it allocates.
- * Errors: NPCF_E_INVALID (bad cfg, max_points < 1, out == NULL),
+ * Errors: NPCF_E_INVALID (bad cfg, max_points < 1, out == NULL, or no
+ * radial tuple: btuple_mode 0 with fewer than N - 1 bins),
  * NPCF_E_UNSUPPORTED (N, D, lmax or nbins outside the table above),
  * NPCF_E_NOMEM, NPCF_E_DEVICE. */
 npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, npcf_plan_t *out);

@@ -871,6 +871,14 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         delete p;
         return st;
     }
+    if (p->t.nbt == 0) {
+        // b1 < b2 < ... < b_{N-1} needs at least N - 1 bins: nothing to estimate
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "no radial tuple: %d bins with b1 < ... < b%d (btuple_mode 0) needs at least %d bins", cfg->nbins,
+                      cfg->N - 1, cfg->N - 1);
+        delete p;
+        return NPCF_E_INVALID;
+    }
     p->edges.assign(cfg->edges, cfg->edges + cfg->nbins + 1);
     p->cfg.edges = p->edges.data();
     for (int k = cfg->D; k < 4; k++) p->cfg.box[k] = 1.0;

@@ -82,6 +82,10 @@ def _plan(lib, **kw):
     (dict(norm=3), binding.NPCF_E_INVALID),
     (dict(max_points=0), binding.NPCF_E_INVALID),
     (dict(edges_ok=False), binding.NPCF_E_INVALID),
+    # no radial tuple b1 < ... < b_{N-1}: fewer than N - 1 bins in the default mode
+    (dict(N=5, lmax=2, edges=[1.0, 1.5, 2.0, 3.0]), binding.NPCF_E_INVALID),
+    (dict(N=4, edges=[1.0, 2.0, 3.0]), binding.NPCF_E_INVALID),
+    (dict(N=3, edges=[1.0, 2.0]), binding.NPCF_E_INVALID),
 ])
 def test_plan_validation(lib, kw, expect):
     assert _plan(lib, **kw) == expect

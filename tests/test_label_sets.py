@@ -68,7 +68,7 @@ def test_paper_counts_from_independent_sets():
 def test_plan_labels_equal_independent_sets(D, N, lmax, Lmax):
     """The GPU planner's labels (npcf_describe) are the independently enumerated set."""
     from paper_2106_10278_amd import NPCF
-    edges = np.linspace(1.0, 3.0, 4)
+    edges = np.linspace(1.0, 3.0, 6)
     plan = NPCF(D, N, lmax, edges, [10.0] * D, max_points=64, Lmax=Lmax)
     ref = li.labels(D, N, lmax, Lmax)
     got = plan.lambda_labels[:, : ref.shape[1]]
