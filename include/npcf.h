@@ -244,6 +244,28 @@ npcf_status npcf_accumulate_batch(npcf_plan_t plan, int ncat, const double *cons
 npcf_status npcf_finalize_batch(npcf_plan_t plan, int cat, double *out, size_t out_len, double *done_ms,
                                 int64_t *pairs);
 
+/* npcf_accumulate for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, hosts that forbid allocation):
+ * the same computation, arguments, accumulators and errors as
+ * npcf_accumulate, but every per-call device buffer (quantised positions,
+ * cell list, rows of a, coupling partials, work counter) is cut from one
+ * static device workspace of 64 MiB that the library holds on each device it
+ * runs on until the process ends; the call makes no device or host memory
+ * allocation and records no timing events (npcf_stage_ms does not see it).
+ * The workspace used is that of the device that was current when the plan
+ * was made (npcf_plan looks up its address).  Primaries are processed in chunks that fit the
+ * workspace, so results agree with npcf_accumulate up to rounding order.
+ * Every call on a device shares that device's workspace and leaves its
+ * contents behind (each call rewrites what it reads): calls that overlap in
+ * time on one device, from any plans or streams, race and give wrong results.
+ * Flat geometry only.  Errors: as npcf_accumulate; NPCF_E_INVALID also when
+ * the catalogue does not fit the workspace (about 17 MB per 256k points in
+ * D = 3 besides the cell grid and one 16-row chunk; the detail names the bytes
+ * needed), NPCF_E_UNSUPPORTED for the sphere geometry, NPCF_E_DEVICE when the
+ * workspace could not be found on the device. */
+npcf_status npcf_accumulate_static(npcf_plan_t plan, const double *pos, const double *w, int64_t n,
+                                   int64_t prim_begin, int64_t prim_end, int role);
+
 /* Zero the accumulators and pair counters (asynchronous). */
 npcf_status npcf_reset(npcf_plan_t plan);
 

@@ -69,6 +69,7 @@ def load_library():
     ip = ctypes.POINTER(ctypes.c_int)
     lib.npcf_plan.argtypes = [ctypes.POINTER(_Config), vp, i64, ctypes.POINTER(vp)]
     lib.npcf_accumulate.argtypes = [vp, vp, vp, i64, i64, i64, ctypes.c_int]
+    lib.npcf_accumulate_static.argtypes = [vp, vp, vp, i64, i64, i64, ctypes.c_int]
     lib.npcf_finalize.argtypes = [vp, dp, ctypes.c_size_t]
     lib.npcf_describe.argtypes = [vp, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_size_t)]
     lib.npcf_accumulate_grid.argtypes = [vp, vp, ip, i64, i64, ctypes.c_int]
@@ -86,7 +87,7 @@ def load_library():
     lib.npcf_strerror.restype = ctypes.c_char_p
     lib.npcf_version.restype = ctypes.c_char_p
     lib.npcf_last_error_detail.restype = ctypes.c_char_p
-    for name in ("npcf_plan", "npcf_accumulate", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
+    for name in ("npcf_plan", "npcf_accumulate", "npcf_accumulate_static", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
                  "npcf_accumulate_batch", "npcf_finalize_batch", "npcf_reset", "npcf_destroy", "npcf_set_tuning",
                  "npcf_stage_ms", "npcf_autotune", "npcf_accumulate_grid", "npcf_alm_grid"):
         getattr(lib, name).restype = ctypes.c_int
@@ -175,6 +176,15 @@ class NPCF:
             prim_end = n
         _check(load_library().npcf_accumulate(self._h, _dptr(pos), _dptr(w), n, int(prim_begin), int(prim_end),
                                               ROLE[role]), "npcf_accumulate")
+
+    def accumulate_static(self, pos, w, prim_begin: int = 0, prim_end: int | None = None, role: str = "data"):
+        """npcf_accumulate with every per-call device buffer in the library's
+        static workspace (no device allocation; calls overlapping on one device race)."""
+        n = int(w.shape[0])
+        if prim_end is None:
+            prim_end = n
+        _check(load_library().npcf_accumulate_static(self._h, _dptr(pos), _dptr(w), n, int(prim_begin),
+                                                     int(prim_end), ROLE[role]), "npcf_accumulate_static")
 
     def accumulate_grid(self, field, prim_begin: int = 0, prim_end: int | None = None, role: str = "data"):
         """Gridded data: `field` is a contiguous float64 CUDA tensor of shape

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,30 @@ struct StageTimer {
 
 struct BatchState;
 
+// Device buffers of one flat-catalogue accumulation: the catalogue's cell
+// list, the rows of a of one chunk of primaries and the coupling partials.
+// The plan owns one set (allocated at plan time); npcf_accumulate_static
+// carves another from the static workspace for each call.
+struct Workspace {
+    uint32_t *qtmp[kMaxD] = {};
+    uint4 *rec = nullptr;
+    uint32_t *cell = nullptr;
+    int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *prim = nullptr;
+    float *ws = nullptr;
+    double *w64s = nullptr;
+    uint32_t *flag = nullptr, *flagpos = nullptr;
+    uint32_t *count = nullptr, *cell_start = nullptr, *cursor = nullptr;
+    uint32_t *scan_scratch = nullptr;
+    int64_t scan_scratch_len = 0;
+    float *A = nullptr, *wrow = nullptr;
+    double *partial = nullptr;
+    int64_t partial_len = 0;
+    unsigned int *work = nullptr;
+    int64_t rows_cap = 0;    // primaries per chunk (rows of a held at once)
+    bool growable = true;    // the partial buffer may be re-allocated (plan-owned set only)
+    bool timed = true;       // record stage events (the static path creates none)
+};
+
 // Gridded data (npcf_accumulate_grid): the kernel spectra of one grid shape
 // and the per-call buffers.
 struct GridState {
@@ -79,7 +104,6 @@ struct npcf_plan_s {
     int couple_rows = 0;  // 0: automatic
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
-    int64_t rows_cap = 0;      // primaries per chunk (rows of a held at once)
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
@@ -88,25 +112,11 @@ struct npcf_plan_s {
 
     DevAlloc mem;
     DevAlloc cellmem;  // cell arrays (re-allocated when the cell grid changes)
-    // catalogue workspace
-    uint32_t *qtmp[kMaxD] = {};
-    uint4 *rec = nullptr;
-    uint32_t *cell = nullptr;
-    int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *prim = nullptr;
-    float *ws = nullptr;
-    double *w64s = nullptr;
-    uint32_t *flag = nullptr, *flagpos = nullptr;
-    uint32_t *count = nullptr, *cell_start = nullptr, *cursor = nullptr;
-    uint32_t *scan_scratch = nullptr;
-    int64_t scan_scratch_len = 0;
-    // stage buffers
-    float *A = nullptr, *wrow = nullptr;
-    double *partial = nullptr;
-    int64_t partial_len = 0;
+    Workspace wk;      // the plan's own catalogue workspace and stage buffers
+    void *static_ws = nullptr;  // this device's static workspace (npcf_accumulate_static)
     double *acc[2] = {nullptr, nullptr};
     double *out_dev = nullptr;
     unsigned long long *pairs = nullptr;  // [2]
-    unsigned int *work = nullptr;
     int *bad = nullptr;
     // tables
     double *d_e2 = nullptr;
@@ -191,12 +201,12 @@ npcf_status alloc_cells(npcf_plan_s *p)
 {
     p->cellmem.release();
     p->cellmem.ok = true;
-    p->count = p->cellmem.get<uint32_t>(p->ncell + 1);
-    p->cell_start = p->cellmem.get<uint32_t>(p->ncell + 1);
-    p->cursor = p->cellmem.get<uint32_t>(p->ncell + 1);
+    p->wk.count = p->cellmem.get<uint32_t>(p->ncell + 1);
+    p->wk.cell_start = p->cellmem.get<uint32_t>(p->ncell + 1);
+    p->wk.cursor = p->cellmem.get<uint32_t>(p->ncell + 1);
     int64_t m = std::max<int64_t>(p->ncell + 1, p->max_points);
-    p->scan_scratch_len = (m + 1023) / 1024 + 1;
-    p->scan_scratch = p->cellmem.get<uint32_t>(p->scan_scratch_len);
+    p->wk.scan_scratch_len = (m + 1023) / 1024 + 1;
+    p->wk.scan_scratch = p->cellmem.get<uint32_t>(p->wk.scan_scratch_len);
     return p->cellmem.ok ? NPCF_OK : NPCF_E_NOMEM;
 }
 
@@ -262,23 +272,23 @@ void clear_timers(npcf_plan_s *p)
 }
 
 // Build the cell list of a catalogue: sorted SoA lattice coordinates and weights.
-npcf_status build_cells(npcf_plan_s *p, const double *pos, const double *w, int64_t n)
+npcf_status build_cells(npcf_plan_s *p, Workspace &W, const double *pos, const double *w, int64_t n)
 {
     hipStream_t s = p->stream;
-    NPCF_TRY(launch_fill_u32(p->count, 0u, p->ncell + 1, s));
-    NPCF_TRY(launch_quantize(p->D, p->cfg.periodic, pos, w, n, p->cfg.box, p->ncs, p->qtmp, p->cell, p->count, p->bad, s));
-    NPCF_TRY(launch_exclusive_scan(p->count, p->cell_start, p->ncell + 1, p->scan_scratch, p->scan_scratch_len, s));
-    NPCF_TRY(hipMemcpyAsync(p->cursor, p->cell_start, (p->ncell + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    NPCF_TRY(launch_scatter_perm(n, p->cell, p->cursor, p->perm, s));
-    NPCF_TRY(launch_cellsort(n, p->cell, p->cell_start, p->perm, p->perm_sorted, s));
-    NPCF_TRY(launch_gather(p->D, n, p->perm_sorted, p->qtmp, w, p->rec, p->ws, p->w64s, p->orig, s));
+    NPCF_TRY(launch_fill_u32(W.count, 0u, p->ncell + 1, s));
+    NPCF_TRY(launch_quantize(p->D, p->cfg.periodic, pos, w, n, p->cfg.box, p->ncs, W.qtmp, W.cell, W.count, p->bad, s));
+    NPCF_TRY(launch_exclusive_scan(W.count, W.cell_start, p->ncell + 1, W.scan_scratch, W.scan_scratch_len, s));
+    NPCF_TRY(launch_copy_u32(W.cursor, W.cell_start, p->ncell + 1, s));
+    NPCF_TRY(launch_scatter_perm(n, W.cell, W.cursor, W.perm, s));
+    NPCF_TRY(launch_cellsort(n, W.cell, W.cell_start, W.perm, W.perm_sorted, s));
+    NPCF_TRY(launch_gather(p->D, n, W.perm_sorted, W.qtmp, w, W.rec, W.ws, W.w64s, W.orig, s));
     return NPCF_OK;
 }
 
-HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned long long *pairs)
+HarmArgs harm_args(const npcf_plan_s *p, const Workspace &W, int rows, const int32_t *prim, unsigned long long *pairs)
 {
     HarmArgs a{};
-    a.rec = p->rec;
+    a.rec = W.rec;
     for (int k = 0; k < kMaxD; k++) {
         a.ncs[k] = p->ncs[k];
         a.cell_len[k] = 4294967296.0 / p->ncs[k];
@@ -288,8 +298,8 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
         a.scale[k] = (float)sc;
         a.rmax_lat[k] = p->edges[p->nb] / sc;
     }
-    a.w = p->ws;
-    a.cell_start = p->cell_start;
+    a.w = W.ws;
+    a.cell_start = W.cell_start;
     a.prim = prim;
     a.nrows = rows;
     a.nb = p->nb;
@@ -300,10 +310,10 @@ HarmArgs harm_args(const npcf_plan_s *p, int rows, const int32_t *prim, unsigned
     a.nbucket = (int)p->t.bucket_bin.size();
     a.e2 = p->d_e2;
     a.bucket_bin = p->d_bucket;
-    a.A = p->A;
-    a.wrow = p->wrow;
+    a.A = W.A;
+    a.wrow = W.wrow;
     a.pairs = pairs;
-    a.work = p->work;
+    a.work = W.work;
     a.periodic = p->cfg.periodic;
     return a;
 }
@@ -325,25 +335,29 @@ hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t 
     }
 }
 
-npcf_status run_harmonic(npcf_plan_s *p, int rows, const int32_t *prim, unsigned long long *pairs)
+npcf_status run_harmonic(npcf_plan_s *p, Workspace &W, int rows, const int32_t *prim, unsigned long long *pairs)
 {
     hipStream_t s = p->stream;
-    HarmArgs a = harm_args(p, rows, prim, pairs);
+    HarmArgs a = harm_args(p, W, rows, prim, pairs);
     StageTimer t;
-    npcf_status st = timer_begin(p, 0, t);
-    if (st != NPCF_OK) return st;
+    if (W.timed) {
+        npcf_status st = timer_begin(p, 0, t);
+        if (st != NPCF_OK) return st;
+    }
     NPCF_TRY(launch_harmonic(p, a, s));
-    NPCF_TRY(hipEventRecord(t.b, s));
-    p->timers[0].push_back(t);
+    if (W.timed) {
+        NPCF_TRY(hipEventRecord(t.b, s));
+        p->timers[0].push_back(t);
+    }
     return NPCF_OK;
 }
 
-CoupleArgs couple_args(const npcf_plan_s *p, int rows)
+CoupleArgs couple_args(const npcf_plan_s *p, const Workspace &W, int rows)
 {
     const Tables &t = p->t;
     CoupleArgs a{};
-    a.A = p->A;
-    a.wrow = p->wrow;
+    a.A = W.A;
+    a.wrow = W.wrow;
     a.nrows = rows;
     a.nb = p->nb;
     a.nstate = t.nstate;
@@ -379,29 +393,35 @@ CoupleArgs couple_args(const npcf_plan_s *p, int rows)
     return a;
 }
 
-npcf_status run_couple(npcf_plan_s *p, int rows, double *acc)
+npcf_status run_couple(npcf_plan_s *p, Workspace &W, int rows, double *acc)
 {
     hipStream_t s = p->stream;
     const Tables &t = p->t;
-    CoupleArgs a = couple_args(p, rows);
+    CoupleArgs a = couple_args(p, W, rows);
     const int64_t len = (int64_t)p->njobs * 256;
-    if ((int64_t)a.n_rowblocks * len > p->partial_len) {
+    if ((int64_t)a.n_rowblocks * len > W.partial_len) {
+        // the static workspace was carved for this call's block count
+        if (!W.growable) return NPCF_E_INVALID;
         // grow the partial buffer (rare: only with small custom block sizes)
         void *np = nullptr;
         NPCF_TRY(hipStreamSynchronize(s));
         NPCF_TRY(hipMalloc(&np, (size_t)a.n_rowblocks * len * sizeof(double)));
         p->mem.ptrs.push_back(np);
-        p->partial = (double *)np;
-        p->partial_len = (int64_t)a.n_rowblocks * len;
+        W.partial = (double *)np;
+        W.partial_len = (int64_t)a.n_rowblocks * len;
     }
-    a.partial = p->partial;
+    a.partial = W.partial;
     StageTimer tm;
-    npcf_status st = timer_begin(p, 1, tm);
-    if (st != NPCF_OK) return st;
+    if (W.timed) {
+        npcf_status st = timer_begin(p, 1, tm);
+        if (st != NPCF_OK) return st;
+    }
     NPCF_TRY(launch_couple_kernel(p->N, p->cfg.precision, a, p->njobs, t.nparts, p->d_sfac, s));
-    NPCF_TRY(launch_reduce_partials(p->partial, a.n_rowblocks, len, acc, s));
-    NPCF_TRY(hipEventRecord(tm.b, s));
-    p->timers[1].push_back(tm);
+    NPCF_TRY(launch_reduce_partials(W.partial, a.n_rowblocks, len, acc, s));
+    if (W.timed) {
+        NPCF_TRY(hipEventRecord(tm.b, s));
+        p->timers[1].push_back(tm);
+    }
     return NPCF_OK;
 }
 
@@ -414,67 +434,75 @@ npcf_status check_inputs(npcf_plan_s *p, const double *pos, const double *w, int
     return NPCF_OK;
 }
 
-npcf_status prepare(npcf_plan_s *p, const double *pos, const double *w, int64_t n, int64_t p0, int64_t p1)
+npcf_status prepare(npcf_plan_s *p, Workspace &W, const double *pos, const double *w, int64_t n, int64_t p0, int64_t p1)
 {
     StageTimer t;
-    npcf_status st = timer_begin(p, 2, t);
+    if (W.timed) {
+        npcf_status st = timer_begin(p, 2, t);
+        if (st != NPCF_OK) return st;
+    }
+    npcf_status st = build_cells(p, W, pos, w, n);
     if (st != NPCF_OK) return st;
-    st = build_cells(p, pos, w, n);
-    if (st != NPCF_OK) return st;
-    NPCF_TRY(launch_primlist(n, p->orig, p0, p1, p->flag, p->flagpos, p->prim, p->scan_scratch, p->scan_scratch_len,
+    NPCF_TRY(launch_primlist(n, W.orig, p0, p1, W.flag, W.flagpos, W.prim, W.scan_scratch, W.scan_scratch_len,
                              p->stream));
-    NPCF_TRY(hipEventRecord(t.b, p->stream));
-    p->timers[2].push_back(t);
+    if (W.timed) {
+        NPCF_TRY(hipEventRecord(t.b, p->stream));
+        p->timers[2].push_back(t);
+    }
     return NPCF_OK;
 }
 
 // Sphere harmonic stage for rows [0, rows) = primaries p0 + [0, rows): every
 // secondary, no cell list.
-npcf_status run_sphere(npcf_plan_s *p, const double *pos, const double *w, int64_t n, int64_t p0, int rows,
+npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const double *w, int64_t n, int64_t p0, int rows,
                        unsigned long long *pairs)
 {
     SphereArgs a{};
     a.pos = pos;
     a.w = w;
-    a.pf = reinterpret_cast<float4 *>(p->rec);   // the flat path's record buffer (max_points x 16 B), unused here
+    a.pf = reinterpret_cast<float4 *>(W.rec);   // the flat path's record buffer (max_points x 16 B), unused here
     a.n = n;
     a.p0 = p0;
     a.rows = rows;
     a.nb = p->nb;
     for (int b = 0; b <= p->nb; b++) a.cedge[b] = p->t.cedge[b];
-    a.A = p->A;
-    a.wrow = p->wrow;
+    a.A = W.A;
+    a.wrow = W.wrow;
     a.pairs = pairs;
     StageTimer t;
-    npcf_status st = timer_begin(p, 0, t);
-    if (st != NPCF_OK) return st;
+    if (W.timed) {
+        npcf_status st = timer_begin(p, 0, t);
+        if (st != NPCF_OK) return st;
+    }
     NPCF_TRY(launch_sphere(p->L, a, p->stream));
-    NPCF_TRY(hipEventRecord(t.b, p->stream));
-    p->timers[0].push_back(t);
+    if (W.timed) {
+        NPCF_TRY(hipEventRecord(t.b, p->stream));
+        p->timers[0].push_back(t);
+    }
     return NPCF_OK;
 }
 
-npcf_status accumulate_impl(npcf_plan_s *p, const double *pos, const double *w, int64_t n, int64_t p0, int64_t p1,
-                            double *acc, unsigned long long *pairs)
+npcf_status accumulate_impl(npcf_plan_s *p, Workspace &W, const double *pos, const double *w, int64_t n, int64_t p0,
+                            int64_t p1, double *acc, unsigned long long *pairs)
 {
     if (p->t.sphere) {
-        for (int64_t c0 = p0; c0 < p1; c0 += p->rows_cap) {
-            const int rows = (int)std::min<int64_t>(p->rows_cap, p1 - c0);
-            npcf_status st = run_sphere(p, pos, w, n, c0, rows, pairs);
+        for (int64_t c0 = p0; c0 < p1; c0 += W.rows_cap) {
+            const int rows = (int)std::min<int64_t>(W.rows_cap, p1 - c0);
+            npcf_status st = run_sphere(p, W, pos, w, n, c0, rows, pairs);
             if (st != NPCF_OK) return st;
-            st = run_couple(p, rows, acc);
+            st = run_couple(p, W, rows, acc);
             if (st != NPCF_OK) return st;
         }
         return NPCF_OK;
     }
-    npcf_status st = prepare(p, pos, w, n, p0, p1);
+    npcf_status st = prepare(p, W, pos, w, n, p0, p1);
     if (st != NPCF_OK) return st;
     const int64_t nprim = p1 - p0;
-    for (int64_t c0 = 0; c0 < nprim; c0 += p->rows_cap) {
-        const int rows = (int)std::min<int64_t>(p->rows_cap, nprim - c0);
-        st = run_harmonic(p, rows, p->prim + c0, pairs);
+    for (int64_t c0 = 0; c0 < nprim; c0 += W.rows_cap) {
+        const int rows = (int)std::min<int64_t>(W.rows_cap, nprim - c0);
+        st = run_harmonic(p, W, rows, W.prim + c0, pairs);
         if (st != NPCF_OK) return st;
-        st = run_couple(p, rows, acc);
+        st = run_couple(p, W, rows, acc);
         if (st != NPCF_OK) return st;
     }
     return NPCF_OK;
@@ -585,7 +613,7 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
     if (b->ncell_tot + 1 >= (int64_t)UINT32_MAX) return NPCF_E_UNSUPPORTED;  // 32-bit cell keys
 
     // chunks of rows and their row blocks (never straddling a catalogue)
-    const int64_t cap = p->rows_cap;
+    const int64_t cap = p->wk.rows_cap;
     b->rpb = couple_rows_per_block(p, std::min<int64_t>(cap, b->ntot));
     std::vector<int> rbb, rbe;
     for (int64_t r0 = 0; r0 < b->ntot; r0 += cap) {
@@ -678,7 +706,7 @@ npcf_status batch_record(npcf_plan_s *p, hipStream_t s)
     NPCF_TRY(launch_gather(p->D, b->ntot, b->perm_sorted, b->qtmp, b->wall, b->rec, b->ws, b->w64s, b->orig, s));
     // chunks: harmonic over rows of any catalogue, coupling per catalogue
     for (const BatchChunk &ch : b->chunks) {
-        HarmArgs ha = harm_args(p, ch.rows, b->iota + ch.r0, b->pairs);
+        HarmArgs ha = harm_args(p, p->wk, ch.rows, b->iota + ch.r0, b->pairs);
         ha.rec = b->rec;
         ha.w = b->ws;
         ha.cell_start = b->cell_start;
@@ -686,7 +714,7 @@ npcf_status batch_record(npcf_plan_s *p, hipStream_t s)
         ha.ncat = b->ncat;
         ha.ncell_cat = b->ncell_cat;
         NPCF_TRY(launch_harmonic(p, ha, s));
-        CoupleArgs ca = couple_args(p, ch.rows);
+        CoupleArgs ca = couple_args(p, p->wk, ch.rows);
         ca.rows_per_block = b->rpb;
         ca.n_rowblocks = ch.nrb;
         ca.rb_begin = b->rb_begin + ch.rb_off;
@@ -820,18 +848,131 @@ npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int
     hipStream_t s = p->stream;
     npcf_status st = grid_harmonics(p, field, p0, p1, role);
     if (st != NPCF_OK) return st;
-    for (int64_t c0 = p0; c0 < p1; c0 += p->rows_cap) {
-        const int rows = (int)std::min<int64_t>(p->rows_cap, p1 - c0);
+    for (int64_t c0 = p0; c0 < p1; c0 += p->wk.rows_cap) {
+        const int rows = (int)std::min<int64_t>(p->wk.rows_cap, p1 - c0);
         StageTimer tr;
         st = timer_begin(p, 0, tr);
         if (st != NPCF_OK) return st;
-        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, p->t.nstate, g->sreal, g->w32, c0, rows, p->A, p->wrow, s));
+        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, p->t.nstate, g->sreal, g->w32, c0, rows, p->wk.A, p->wk.wrow, s));
         NPCF_TRY(hipEventRecord(tr.b, s));
         p->timers[0].push_back(tr);
-        st = run_couple(p, rows, p->acc[role]);
+        st = run_couple(p, p->wk, rows, p->acc[role]);
         if (st != NPCF_OK) return st;
     }
     return NPCF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static workspace (npcf_accumulate_static).  Callers that cannot allocate
+// device memory (code under stream capture, serving loops) get their per-call
+// buffers from one file-scope device array.  The loader gives every device
+// the library runs on its own copy at its own address, held until the process
+// ends; host code never passes the array's name to a kernel (in host code it
+// is a stand-in, not a device address): npcf_plan looks up this device's
+// address once with hipGetSymbolAddress and every call uses that pointer.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// This device's address of the static workspace (the device must be current).
+npcf_status static_workspace(int dev, void **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return NPCF_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return dev_err_at(e, "hipGetSymbolAddress(scratch)", __LINE__);
+        if (!ptr) return NPCF_E_DEVICE;
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return NPCF_OK;
+}
+
+// Coupling row blocks of a chunk of `rows` primaries.
+int64_t couple_row_blocks(const npcf_plan_s *p, int64_t rows)
+{
+    const int64_t rpb = couple_rows_per_block(p, rows);
+    return (rows + rpb - 1) / rpb;
+}
+
+// Cut the static workspace into the buffers of one flat accumulation of a
+// catalogue of n points with nprim primaries: per-point arrays, the cell
+// arrays of the plan's cell grid, the harmonic work counter, then the rows of
+// a, row weights and coupling partials of the largest chunk of primaries that
+// fits (at most the plan's chunk size).  *need receives the bytes the
+// smallest layout (16-row chunks) would take.  False when even that does not fit.
+bool carve_static(const npcf_plan_s *p, unsigned char *base, int64_t n, int64_t nprim, Workspace &W, size_t *need)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        return o;
+    };
+    const int D = p->D;
+    size_t o_q[kMaxD] = {};
+    for (int k = 0; k < D; k++) o_q[k] = take((size_t)n * 4);
+    const size_t o_rec = take((size_t)n * 16), o_cell = take((size_t)n * 4);
+    const size_t o_perm = take((size_t)n * 4), o_ps = take((size_t)n * 4), o_orig = take((size_t)n * 4),
+                 o_prim = take((size_t)n * 4);
+    const size_t o_ws = take((size_t)n * 4), o_w64 = take((size_t)n * 8);
+    const size_t o_flag = take((size_t)n * 4), o_flagpos = take((size_t)n * 4);
+    const int64_t nc = p->ncell + 1;
+    const size_t o_count = take((size_t)nc * 4), o_cs = take((size_t)nc * 4), o_cur = take((size_t)nc * 4);
+    const int64_t scan_len = (std::max<int64_t>(nc, n) + 1023) / 1024 + 1;
+    const size_t o_scan = take((size_t)scan_len * 4);
+    const size_t o_work = take(4);
+    const size_t fixed = off;
+    const int64_t rowbytes = (int64_t)p->nb * 2 * p->t.nstate * 4;
+    const int64_t len = (int64_t)p->njobs * 256;
+    auto chunk_bytes = [&](int64_t R) {
+        // the largest block count over the full chunks and the last one
+        int64_t nrb = couple_row_blocks(p, std::min(R, nprim));
+        if (nprim % R) nrb = std::max(nrb, couple_row_blocks(p, nprim % R));
+        return ((size_t)(R * rowbytes) + 255) / 256 * 256 + ((size_t)R * 4 + 255) / 256 * 256 +
+               (size_t)nrb * len * 8;
+    };
+    int64_t R = std::min<int64_t>(p->wk.rows_cap, nprim);
+    while (R > 16 && fixed + chunk_bytes(R) > kStaticBytes) R = std::max<int64_t>(16, (R / 2 + 15) / 16 * 16);
+    *need = fixed + chunk_bytes(std::min<int64_t>(16, nprim));
+    if (fixed + chunk_bytes(R) > kStaticBytes) return false;
+    const size_t o_A = take((size_t)R * rowbytes), o_wrow = take((size_t)R * 4);
+    int64_t nrb = couple_row_blocks(p, R);
+    if (nprim % R) nrb = std::max(nrb, couple_row_blocks(p, nprim % R));
+    const size_t o_part = take((size_t)nrb * len * 8);
+    if (off > kStaticBytes) return false;
+    for (int k = 0; k < D; k++) W.qtmp[k] = reinterpret_cast<uint32_t *>(base + o_q[k]);
+    W.rec = reinterpret_cast<uint4 *>(base + o_rec);
+    W.cell = reinterpret_cast<uint32_t *>(base + o_cell);
+    W.perm = reinterpret_cast<int32_t *>(base + o_perm);
+    W.perm_sorted = reinterpret_cast<int32_t *>(base + o_ps);
+    W.orig = reinterpret_cast<int32_t *>(base + o_orig);
+    W.prim = reinterpret_cast<int32_t *>(base + o_prim);
+    W.ws = reinterpret_cast<float *>(base + o_ws);
+    W.w64s = reinterpret_cast<double *>(base + o_w64);
+    W.flag = reinterpret_cast<uint32_t *>(base + o_flag);
+    W.flagpos = reinterpret_cast<uint32_t *>(base + o_flagpos);
+    W.count = reinterpret_cast<uint32_t *>(base + o_count);
+    W.cell_start = reinterpret_cast<uint32_t *>(base + o_cs);
+    W.cursor = reinterpret_cast<uint32_t *>(base + o_cur);
+    W.scan_scratch = reinterpret_cast<uint32_t *>(base + o_scan);
+    W.scan_scratch_len = scan_len;
+    W.work = reinterpret_cast<unsigned int *>(base + o_work);
+    W.A = reinterpret_cast<float *>(base + o_A);
+    W.wrow = reinterpret_cast<float *>(base + o_wrow);
+    W.partial = reinterpret_cast<double *>(base + o_part);
+    W.partial_len = nrb * len;
+    W.rows_cap = R;
+    W.growable = false;
+    W.timed = false;
+    return true;
 }
 
 }  // namespace
@@ -926,6 +1067,12 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
             p->ncu = ncu;
     }
+    // set-up of npcf_accumulate_static: this device's static workspace (a
+    // failed lookup only disables that entry point, which then reports it)
+    if (static_workspace(dev, &p->static_ws) != NPCF_OK) {
+        p->static_ws = nullptr;
+        g_last_error[0] = '\0';
+    }
     compute_grid(p);
     {
         const char *cv = std::getenv("NPCF_COUPLING");
@@ -949,34 +1096,34 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         }
     }
     DevAlloc &m = p->mem;
-    for (int k = 0; k < p->D; k++) p->qtmp[k] = m.get<uint32_t>(max_points);
-    p->rec = m.get<uint4>(max_points);
-    p->cell = m.get<uint32_t>(max_points);
-    p->perm = m.get<int32_t>(max_points);
-    p->perm_sorted = m.get<int32_t>(max_points);
-    p->orig = m.get<int32_t>(max_points);
-    p->prim = m.get<int32_t>(max_points);
-    p->ws = m.get<float>(max_points);
-    p->w64s = m.get<double>(max_points);
-    p->flag = m.get<uint32_t>(max_points);
-    p->flagpos = m.get<uint32_t>(max_points);
+    for (int k = 0; k < p->D; k++) p->wk.qtmp[k] = m.get<uint32_t>(max_points);
+    p->wk.rec = m.get<uint4>(max_points);
+    p->wk.cell = m.get<uint32_t>(max_points);
+    p->wk.perm = m.get<int32_t>(max_points);
+    p->wk.perm_sorted = m.get<int32_t>(max_points);
+    p->wk.orig = m.get<int32_t>(max_points);
+    p->wk.prim = m.get<int32_t>(max_points);
+    p->wk.ws = m.get<float>(max_points);
+    p->wk.w64s = m.get<double>(max_points);
+    p->wk.flag = m.get<uint32_t>(max_points);
+    p->wk.flagpos = m.get<uint32_t>(max_points);
     const int64_t rowbytes = (int64_t)p->nb * 2 * t.nstate * sizeof(float);
-    p->rows_cap = std::min<int64_t>(max_points, std::max<int64_t>(1024, kADefaultBudget / rowbytes));
-    p->rows_cap_max = p->rows_cap;
-    p->A = m.get<float>((size_t)p->rows_cap * p->nb * 2 * t.nstate);
-    p->wrow = m.get<float>(p->rows_cap);
+    p->wk.rows_cap = std::min<int64_t>(max_points, std::max<int64_t>(1024, kADefaultBudget / rowbytes));
+    p->rows_cap_max = p->wk.rows_cap;
+    p->wk.A = m.get<float>((size_t)p->wk.rows_cap * p->nb * 2 * t.nstate);
+    p->wk.wrow = m.get<float>(p->wk.rows_cap);
     // partials for the automatic coupling block size
     {
-        int rpb = couple_rows_per_block(p, p->rows_cap);
-        int64_t nrb = (p->rows_cap + rpb - 1) / rpb;
-        p->partial_len = nrb * (int64_t)p->njobs * 256;
-        p->partial = m.get<double>(p->partial_len);
+        int rpb = couple_rows_per_block(p, p->wk.rows_cap);
+        int64_t nrb = (p->wk.rows_cap + rpb - 1) / rpb;
+        p->wk.partial_len = nrb * (int64_t)p->njobs * 256;
+        p->wk.partial = m.get<double>(p->wk.partial_len);
     }
     p->acc[0] = m.get<double>((size_t)p->njobs * 256);
     p->acc[1] = m.get<double>((size_t)p->njobs * 256);
     p->out_dev = m.get<double>((size_t)t.nlam * t.nparts * t.nbt);
     p->pairs = m.get<unsigned long long>(2);
-    p->work = m.get<unsigned int>(1);
+    p->wk.work = m.get<unsigned int>(1);
     p->bad = m.get<int>(1);
     p->d_e2 = m.get<double>(t.e2.size());
     p->d_bucket = m.get<uint8_t>(t.bucket_bin.size());
@@ -1091,7 +1238,7 @@ npcf_status npcf_set_tuning(npcf_plan_t p, int cell_subdiv, int couple_block, in
         return NPCF_E_INVALID;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return NPCF_E_DEVICE;
     batch_release(p);  // the captured batch depends on every knob
-    if (chunk_rows > 0) p->rows_cap = chunk_rows;
+    if (chunk_rows > 0) p->wk.rows_cap = chunk_rows;
     if (cell_subdiv > 0 && cell_subdiv != p->cell_subdiv) {
         p->cell_subdiv = cell_subdiv;
         compute_grid(p);
@@ -1111,7 +1258,7 @@ npcf_status npcf_accumulate(npcf_plan_t p, const double *pos, const double *w, i
     npcf_status st = check_inputs(p, pos, w, n, prim_begin, prim_end);
     if (st != NPCF_OK) return st;
     if (role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
-    st = accumulate_impl(p, pos, w, n, prim_begin, prim_end, p->acc[role], p->pairs + role);
+    st = accumulate_impl(p, p->wk, pos, w, n, prim_begin, prim_end, p->acc[role], p->pairs + role);
     if (st != NPCF_OK) p->failed = true;
     return st;
 }
@@ -1177,12 +1324,12 @@ npcf_status npcf_alm_grid(npcf_plan_t p, const double *field, const int *dims, i
     }
     GridState *g = p->grid;
     std::vector<float> Ah;
-    for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->rows_cap) {
-        const int rows = (int)std::min<int64_t>(p->rows_cap, prim_end - c0);
-        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, t.nstate, g->sreal, g->w32, c0, rows, p->A, p->wrow,
+    for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->wk.rows_cap) {
+        const int rows = (int)std::min<int64_t>(p->wk.rows_cap, prim_end - c0);
+        NPCF_TRY(launch_grid_rows(g->work, g->ng, g->nbs, t.nstate, g->sreal, g->w32, c0, rows, p->wk.A, p->wk.wrow,
                                   p->stream));
         Ah.resize((size_t)rows * per);
-        NPCF_TRY(hipMemcpyAsync(Ah.data(), p->A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+        NPCF_TRY(hipMemcpyAsync(Ah.data(), p->wk.A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
         NPCF_TRY(hipStreamSynchronize(p->stream));
         for (int r = 0; r < rows; r++)
             for (int b = 0; b < p->nb; b++)
@@ -1253,15 +1400,15 @@ npcf_status npcf_alm(npcf_plan_t p, const double *pos, const double *w, int64_t 
     if (!out || out_len != (size_t)(nprim * per)) return NPCF_E_INVALID;
     if (t.sphere) {
         std::vector<float> Ah;
-        for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->rows_cap) {
-            const int rows = (int)std::min<int64_t>(p->rows_cap, prim_end - c0);
-            st = run_sphere(p, pos, w, n, c0, rows, p->pairs);
+        for (int64_t c0 = prim_begin; c0 < prim_end; c0 += p->wk.rows_cap) {
+            const int rows = (int)std::min<int64_t>(p->wk.rows_cap, prim_end - c0);
+            st = run_sphere(p, p->wk, pos, w, n, c0, rows, p->pairs);
             if (st != NPCF_OK) {
                 p->failed = true;
                 return st;
             }
             Ah.resize((size_t)rows * per);
-            NPCF_TRY(hipMemcpyAsync(Ah.data(), p->A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+            NPCF_TRY(hipMemcpyAsync(Ah.data(), p->wk.A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
             NPCF_TRY(hipStreamSynchronize(p->stream));
             for (int r = 0; r < rows; r++)
                 for (int b = 0; b < p->nb; b++)
@@ -1271,25 +1418,25 @@ npcf_status npcf_alm(npcf_plan_t p, const double *pos, const double *w, int64_t 
         }
         return NPCF_OK;
     }
-    st = prepare(p, pos, w, n, prim_begin, prim_end);
+    st = prepare(p, p->wk, pos, w, n, prim_begin, prim_end);
     if (st != NPCF_OK) {
         p->failed = true;
         return st;
     }
     std::vector<int32_t> prim(nprim), orig(n);
-    NPCF_TRY(hipMemcpyAsync(prim.data(), p->prim, nprim * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
-    NPCF_TRY(hipMemcpyAsync(orig.data(), p->orig, n * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+    NPCF_TRY(hipMemcpyAsync(prim.data(), p->wk.prim, nprim * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+    NPCF_TRY(hipMemcpyAsync(orig.data(), p->wk.orig, n * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
     std::vector<float> Ah;
     unsigned long long *scratch_pairs = p->pairs;  // counted as data pairs
-    for (int64_t c0 = 0; c0 < nprim; c0 += p->rows_cap) {
-        const int rows = (int)std::min<int64_t>(p->rows_cap, nprim - c0);
-        st = run_harmonic(p, rows, p->prim + c0, scratch_pairs);
+    for (int64_t c0 = 0; c0 < nprim; c0 += p->wk.rows_cap) {
+        const int rows = (int)std::min<int64_t>(p->wk.rows_cap, nprim - c0);
+        st = run_harmonic(p, p->wk, rows, p->wk.prim + c0, scratch_pairs);
         if (st != NPCF_OK) {
             p->failed = true;
             return st;
         }
         Ah.resize((size_t)rows * per);
-        NPCF_TRY(hipMemcpyAsync(Ah.data(), p->A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+        NPCF_TRY(hipMemcpyAsync(Ah.data(), p->wk.A, (size_t)rows * per * sizeof(float), hipMemcpyDeviceToHost, p->stream));
         NPCF_TRY(hipStreamSynchronize(p->stream));
         for (int r = 0; r < rows; r++) {
             const int64_t o = orig[prim[c0 + r]] - prim_begin;
@@ -1448,6 +1595,33 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
 }
 
 // Stage times (ms) accumulated since the last reset: [0] harmonic, [1] coupling + reduce, [2] cell list.
+npcf_status npcf_accumulate_static(npcf_plan_t p, const double *pos, const double *w, int64_t n, int64_t prim_begin,
+                                   int64_t prim_end, int role)
+{
+    npcf_status st = check_inputs(p, pos, w, n, prim_begin, prim_end);
+    if (st != NPCF_OK) return st;
+    if (role != NPCF_ROLE_DATA && role != NPCF_ROLE_RANDOMS) return NPCF_E_INVALID;
+    if (p->t.sphere) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "npcf_accumulate_static: flat geometry only");
+        return NPCF_E_UNSUPPORTED;
+    }
+    if (!p->static_ws) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "npcf_accumulate_static: no static workspace on this device");
+        return NPCF_E_DEVICE;
+    }
+    Workspace W;
+    size_t need = 0;
+    if (!carve_static(p, static_cast<unsigned char *>(p->static_ws), n, prim_end - prim_begin, W, &need)) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "npcf_accumulate_static: %lld points need %zu bytes of workspace, the static limit is %zu",
+                      (long long)n, need, kStaticBytes);
+        return NPCF_E_INVALID;
+    }
+    st = accumulate_impl(p, W, pos, w, n, prim_begin, prim_end, p->acc[role], p->pairs + role);
+    if (st != NPCF_OK) p->failed = true;
+    return st;
+}
+
 npcf_status npcf_stage_ms(npcf_plan_t p, double *ms3)
 {
     if (!p || !ms3) return NPCF_E_INVALID;
