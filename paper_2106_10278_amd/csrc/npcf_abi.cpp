@@ -324,14 +324,10 @@ hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t 
 {
     hipError_t e = launch_fill_u32(a.work, 0u, 1, s);
     if (e != hipSuccess) return e;
-    // persistent grid: 8 blocks of 4 waves per CU, rows handed out dynamically
-    int grid = p->ncu * 8;
-    const int64_t need = ((int64_t)a.nrows + 3) / 4;
-    if (grid > need) grid = (int)std::max<int64_t>(1, need);
     switch (p->D) {
-    case 2: return launch_harmonic_d2(p->L, a, grid, s);
-    case 3: return launch_harmonic_d3(p->L, a, grid, s);
-    default: return launch_harmonic_d4(p->L, a, grid, s);
+    case 2: return launch_harmonic_d2(p->L, a, p->ncu, s);
+    case 3: return launch_harmonic_d3(p->L, a, p->ncu, s);
+    default: return launch_harmonic_d4(p->L, a, p->ncu, s);
     }
 }
 

@@ -30,23 +30,10 @@
 //    The cost per batch is fixed whatever the mix of bins (clustered data put
 //    bursts of one bin into a batch), and the summation order is fixed.
 #pragma once
-#include "npcf_harmonics.h"
+#include "npcf_harmonic_scan.h"
 
 namespace npcf {
 namespace harm {
-
-constexpr int kQCap = 128;          // pair queue entries per wave
-constexpr int kSegCap = 128;        // candidate segments per row chunk
-constexpr int kMaxBucket = 1024;
-// LDS regions start on 16-byte boundaries: the pair queue is read and
-// written as 16-byte records (misaligned, each access stalls)
-constexpr int kTableBytes = ((kMaxBins + 1) * 8 + kMaxBucket + 15) / 16 * 16;
-
-#define NPCF_WAVE_SYNC()                                       \
-    do {                                                       \
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); \
-        __builtin_amdgcn_wave_barrier();                       \
-    } while (0)
 
 // Emission order of the harmonics functions (npcf_harmonics.h): the slot of
 // every emitted value, in the order emit() is called.  Only emitted slots
@@ -102,19 +89,6 @@ struct Cfg {
     static constexpr int LDS_BYTES = 4 * STAGE_BYTES + kTableBytes + 4 * WAVE_BYTES;
 };
 
-__device__ __forceinline__ unsigned lane_id()
-{
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-
-// wave-wide ballot of a boolean straight into a 64-bit lane mask
-__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ int rank_in_mask(unsigned long long m)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
 // true if stored state st (index in the library's state order) has l1 > 0,
 // i.e. an imaginary part that the harmonics emit
 template <int D, int L>
@@ -132,12 +106,6 @@ __device__ __forceinline__ bool emitted_im(int st)
     int l2 = 0;
     while ((l2 + 1) * (l2 + 2) / 2 <= r) l2++;
     return r - l2 * (l2 + 1) / 2 != 0;
-}
-
-template <int D>
-__device__ __forceinline__ uint32_t rec_coord(const uint4 &r, int k)
-{
-    return k == 0 ? r.x : (k == 1 ? r.y : (k == 2 ? r.z : r.w));
 }
 
 template <int D, int L, bool PER>
@@ -185,14 +153,11 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
 #pragma unroll
     for (int k = 0; k < C::NK; k++) acc[k] = 0.0;
 
-    const float e2lo_f = a.e2lo_f, e2hi_f = a.e2hi_f;
     const double e2lo = e2[0], e2hi = e2[nb];
     const double rmax2 = e2hi * (1.0 + 1e-9);
 
     for (;;) {
-        int row = 0;
-        if (lane == 0) row = (int)atomicAdd(a.work, 1u);
-        row = __shfl(row, 0);
+        const int row = next_row(a.work, lane);
         if (row >= a.nrows) break;
         const int ip = a.prim[row];
         const uint4 ri = a.rec[ip];
@@ -217,7 +182,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
         int qn = 0;      // queued pairs (wave-uniform)
 
         // ---- phase B: queued pairs [0, cnt) ---------------------------------
-        auto process = [&](int cnt) {
+        auto process = [&](int cnt) __attribute__((always_inline)) {
             NPCF_WAVE_SYNC();
             const bool live = lane < cnt;
             int dq[D];
@@ -309,7 +274,7 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             // staged rows [0, rows) of chunk k: lanes over rows; each bin's run of
             // sorted columns summed in FP32 (four interleaved partial sums) and
             // added to the FP64 accumulator
-            auto reduce = [&](int k, int rows) {
+            auto reduce = [&](int k, int rows) __attribute__((always_inline)) {
                 NPCF_WAVE_SYNC();
                 const float *srow = stage + (lane < rows ? lane : rows - 1) * C::SSTR;
                 int j0 = 0;
@@ -373,225 +338,21 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             });
         };
 
-        // ---- stencil: per-axis cell ranges around the primary ----------------
-        int lo[D], span[D];
-        bool full[D];
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            const double qk = (double)qi[k];
-            long long l0 = (long long)floor((qk - a.rmax_lat[k] - 4.0) * a.inv_cell_len[k]);
-            long long h0 = (long long)floor((qk + a.rmax_lat[k] + 4.0) * a.inv_cell_len[k]);
-            full[k] = false;
-            if (PER) {
-                if (h0 - l0 + 1 >= a.ncs[k]) {
-                    l0 = 0;
-                    h0 = a.ncs[k] - 1;
-                    full[k] = true;
+        // ---- phase A: candidates into the pair queue -------------------------
+        scan_candidates<D, PER, kPrefetch>(a, cs, qi, segs, lane, rmax2,
+                                           [&](bool inr, const int (&dq)[D], const uint4 &cur, float curw) __attribute__((always_inline)) {
+            queue_append<D>(inr, dq, cur, curw, q4, qwx, qn);
+            if (qn >= 64) {
+                process(64);
+                const int rest = qn - 64;
+                if (lane < rest) {
+                    q4[lane] = q4[64 + lane];
+                    if (D == 4) qwx[lane] = qwx[64 + lane];
                 }
-            } else {
-                if (l0 < 0) l0 = 0;
-                if (h0 > a.ncs[k] - 1) h0 = a.ncs[k] - 1;
+                qn = rest;
+                NPCF_WAVE_SYNC();
             }
-            lo[k] = (int)l0;
-            span[k] = (int)(h0 - l0 + 1);
-        }
-        int nrow = 1;
-#pragma unroll
-        for (int k = 1; k < D; k++) nrow *= span[k];
-
-        for (int rbase = 0; rbase < nrow; rbase += 64) {
-            // each lane trims one row of cells to the sphere: up to two segments
-            uint32_t sa0 = 0, sb0 = 0, sa1 = 0, sb1 = 0;
-            bool has0 = false, has1 = false;
-            const int rix = rbase + lane;
-            if (rix < nrow) {
-                int t = rix;
-                double d2 = 0.0;
-                long long lin = 0, mul = a.ncs[0];
-#pragma unroll
-                for (int k = 1; k < D; k++) {
-                    const int c = lo[k] + t % span[k];
-                    t /= span[k];
-                    double dist = 0.0;
-                    if (!full[k]) {
-                        const double slo = (double)c * a.cell_len[k];
-                        const double qk = (double)qi[k];
-                        if (qk < slo) dist = slo - qk;
-                        else if (qk >= slo + a.cell_len[k]) dist = qk - (slo + a.cell_len[k]);
-                        dist = dist > 4.0 ? dist - 4.0 : 0.0;
-                    }
-                    const double dp = dist * a.scale64[k];
-                    d2 += dp * dp;
-                    int cw = c % a.ncs[k];
-                    if (cw < 0) cw += a.ncs[k];
-                    lin += (long long)cw * mul;
-                    mul *= a.ncs[k];
-                }
-                if (d2 < rmax2) {
-                    int xa, xb;
-                    if (full[0]) {
-                        xa = 0;
-                        xb = a.ncs[0] - 1;
-                    } else {
-                        const double h = sqrt(rmax2 - d2) / a.scale64[0] + 4.0;
-                        const double qx = (double)qi[0];
-                        long long x0 = (long long)floor((qx - h) * a.inv_cell_len[0]);
-                        long long x1 = (long long)floor((qx + h) * a.inv_cell_len[0]);
-                        if (PER) {
-                            if (x1 - x0 + 1 >= a.ncs[0]) {
-                                x0 = 0;
-                                x1 = a.ncs[0] - 1;
-                            }
-                        } else {
-                            if (x0 < 0) x0 = 0;
-                            if (x1 > a.ncs[0] - 1) x1 = a.ncs[0] - 1;
-                        }
-                        xa = (int)x0;
-                        xb = (int)x1;
-                    }
-                    int ra0 = xa, rb0 = xb, ra1 = 0, rb1 = -1;
-                    if (xa < 0) {
-                        ra0 = xa + a.ncs[0]; rb0 = a.ncs[0] - 1;
-                        ra1 = 0; rb1 = xb;
-                    } else if (xb >= a.ncs[0]) {
-                        ra0 = xa; rb0 = a.ncs[0] - 1;
-                        ra1 = 0; rb1 = xb - a.ncs[0];
-                    }
-                    if (rb0 >= ra0) {
-                        sa0 = cs[lin + ra0];
-                        sb0 = cs[lin + rb0 + 1];
-                        has0 = sb0 > sa0;
-                    }
-                    if (rb1 >= ra1) {
-                        sa1 = cs[lin + ra1];
-                        sb1 = cs[lin + rb1 + 1];
-                        has1 = sb1 > sa1;
-                    }
-                }
-            }
-            const unsigned long long m0 = ballot(has0), m1 = ballot(has1);
-            const int n0 = __popcll(m0);
-            if (has0) segs[rank_in_mask(m0)] = make_uint2(sa0, sb0);
-            if (has1) segs[n0 + rank_in_mask(m1)] = make_uint2(sa1, sb1);
-            const int nseg = n0 + __popcll(m1);
-            NPCF_WAVE_SYNC();
-
-            // candidate batches of 64 over the chunk's segments, streamed
-            // through kPrefetch loads in flight (across segment ends): batch p
-            // holds records [pb[p], pe[p]) of one segment, pb == pe past the end
-            int ci = 0;
-            uint32_t cb = 0, ce = 0;
-            if (nseg > 0) {
-                const uint2 sg = segs[0];
-                cb = sg.x;
-                ce = sg.y;
-            }
-            auto advance = [&]() {
-                cb += 64;
-                if (cb >= ce) {
-                    ci++;
-                    if (ci < nseg) {
-                        const uint2 sg = segs[ci];
-                        cb = sg.x;
-                        ce = sg.y;
-                    } else {
-                        cb = 0;
-                        ce = 0;
-                    }
-                }
-            };
-            uint4 pr[kPrefetch];
-            float pw[kPrefetch];
-            uint32_t pb[kPrefetch], pe[kPrefetch];
-#pragma unroll
-            for (int p = 0; p < kPrefetch; p++) {
-                pb[p] = cb;
-                pe[p] = ce;
-                pr[p] = make_uint4(0, 0, 0, 0);
-                pw[p] = 0.f;
-                if (cb + (uint32_t)lane < ce) {
-                    pr[p] = a.rec[cb + lane];
-                    if (D == 4) pw[p] = a.w[cb + lane];
-                }
-                advance();
-            }
-            while (pb[0] < pe[0]) {
-                const uint4 cur = pr[0];
-                const float curw = pw[0];
-                const uint32_t b0 = pb[0], s1 = pe[0];
-                // shift the pipeline and issue the next batch's loads
-#pragma unroll
-                for (int p = 0; p + 1 < kPrefetch; p++) {
-                    pr[p] = pr[p + 1];
-                    pw[p] = pw[p + 1];
-                    pb[p] = pb[p + 1];
-                    pe[p] = pe[p + 1];
-                }
-                pb[kPrefetch - 1] = cb;
-                pe[kPrefetch - 1] = ce;
-                pr[kPrefetch - 1] = make_uint4(0, 0, 0, 0);
-                pw[kPrefetch - 1] = 0.f;
-                if (cb + (uint32_t)lane < ce) {
-                    pr[kPrefetch - 1] = a.rec[cb + lane];
-                    if (D == 4) pw[kPrefetch - 1] = a.w[cb + lane];
-                }
-                advance();
-                {
-                    bool inr = false;
-                    int dq[D];
-                    if (b0 + (uint32_t)lane < s1) {
-                        float r2f = 0.f;
-                        bool fits = true;
-#pragma unroll
-                        for (int k = 0; k < D; k++) {
-                            const uint32_t qk = rec_coord<D>(cur, k);
-                            int d;
-                            if (PER) {
-                                d = (int)(qk - qi[k]);  // two's-complement wrap = minimum image
-                            } else {
-                                const long long dl = (long long)qk - (long long)qi[k];
-                                d = (int)dl;
-                                fits = fits && (long long)d == dl;
-                            }
-                            dq[k] = d;
-                            const float fv = (float)d * a.scale[k];
-                            r2f += fv * fv;
-                        }
-                        inr = fits && r2f >= e2lo_f && r2f < e2hi_f;
-                    }
-                    const unsigned long long m = ballot(inr);
-                    if (inr) {
-                        const int slot = qn + rank_in_mask(m);
-                        int4 e;
-                        e.x = dq[0];
-                        e.y = dq[1];
-                        if (D == 2) {
-                            e.z = (int)cur.z;  // weight bits
-                            e.w = 0;
-                        } else if (D == 3) {
-                            e.z = dq[2];
-                            e.w = (int)cur.w;  // weight bits
-                        } else {
-                            e.z = dq[2];
-                            e.w = dq[3];
-                            qwx[slot] = curw;
-                        }
-                        q4[slot] = e;
-                    }
-                    qn += __popcll(m);
-                    if (qn >= 64) {
-                        process(64);
-                        const int rest = qn - 64;
-                        if (lane < rest) {
-                            q4[lane] = q4[64 + lane];
-                            if (D == 4) qwx[lane] = qwx[64 + lane];
-                        }
-                        qn = rest;
-                        NPCF_WAVE_SYNC();
-                    }
-                }
-            }
-        }
+        });
         if (qn > 0) process(qn);
         // the primary's row of a (FP32): emitted slots from the accumulators,
         // zeros in the others; clear the accumulators
@@ -604,14 +365,12 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
                 acc[k * kMaxBins + b] = 0.0;
             }
         }
-        for (int t = lane; t < nacc; t += 64) {
+        for (int t0 = 0; t0 < nacc; t0 += 64) {
+            const int t = t0 + lane;
             const int sl = t % SLOTS;
-            if (sl % 2 == 1 && !emitted_im<D, L>(sl / 2)) Arow[t] = 0.f;
+            if (t < nacc && sl % 2 == 1 && !emitted_im<D, L>(sl / 2)) Arow[t] = 0.f;
         }
-        if (lane == 0) {
-            a.wrow[row] = wi;
-            if (row_pairs) atomicAdd(a.pairs + cat, row_pairs);
-        }
+        finish_row(a.wrow, row, wi, a.pairs + cat, row_pairs, lane);
     }
 }
 

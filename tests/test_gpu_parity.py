@@ -309,6 +309,29 @@ def test_harmonic_kernels_agree(name, monkeypatch):
     assert cerr <= 2e-6
 
 
+MANY_PAIRS = {
+    # about 900-1200 pairs per primary: many 64-pair batches per primary with
+    # bursts of one bin, up to 16 bins
+    "D3N4dense": (3, 4, 3, 4000, 12, 16.0, 6.0, 7),
+    "D3N3dense16": (3, 3, 4, 4000, 13, 16.0, 6.0, 16),
+    "D2N4dense": (2, 4, 5, 6000, 14, 12.0, 3.0, 11),
+    "D3N3L7": (3, 3, 7, 300, 8, 16.0, 4.5, 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MANY_PAIRS))
+def test_dense_catalogues(name):
+    """Catalogues with hundreds of pairs per primary (many batches per row of
+    a, the persistent loop over rows run to its end by every wave): pair
+    counts exact and the multipoles within the bar of the conditioned measure."""
+    wl = _case(*MANY_PAIRS[name])
+    print(f"[case] dense {name}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    got, pairs, _ = gpu_run(wl)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl), f"{name} dense", strict=False)
+
+
 def test_harmonic_queue_kernel_rejected(monkeypatch):
     """NPCF_HARMONIC names a kernel that is switched off: plan creation fails
     with NPCF_E_UNSUPPORTED before anything is launched."""
