@@ -63,6 +63,59 @@ def flops_per_pair(D: int, L: int) -> float:
     return geo + 1 + 6 * L + 5 * rec + pair_products + 2 * outputs
 
 
+def scope_flops_per_pair(D: int, L: int) -> float:
+    """Per-pair FP32 operations of the harmonic stage in the cost model the
+    roofline is quoted against: geometry (10, 25, 30 for D = 2, 3, 4) plus 10
+    per stored harmonic state (its share of the recurrences and of the
+    azimuthal factor, the weight, and the accumulation of both parts).  This
+    gives 235 at D = 3, lmax 5; 175 at D = 3, lmax 4; 100 at D = 2, |m| <= 8
+    and 870 at D = 4, lmax 6.  The instruction-level count of flops_per_pair
+    (177 at D = 3, lmax 5) leaves out the imaginary parts that vanish for
+    m = 0 and counts a real output as one multiply and one add."""
+    states = {2: L + 1, 3: (L + 1) * (L + 2) // 2, 4: (L + 1) * (L + 2) * (L + 3) // 6}[D]
+    return {2: 10, 3: 25, 4: 30}[D] + 10 * states
+
+
+def multipole_errors(got, ref, labels):
+    """Per-multipole errors against the oracle, one row per (Lambda, part):
+    strict max_b |got - ref| / max_b |ref| and the L2 variant
+    ||got - ref||_2 / ||ref||_2 over the radial tuples (rows whose reference
+    is below 1e-12 of the largest are judged against that floor)."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    big = np.max(np.abs(ref))
+    strict, l2 = [], []
+    for i in range(ref.shape[0]):
+        d = np.abs(got[i] - ref[i])
+        strict.append(np.max(d) / max(np.max(np.abs(ref[i])), 1e-12 * big))
+        l2.append(np.sqrt(np.sum(d ** 2)) / max(np.sqrt(np.sum(np.abs(ref[i]) ** 2)), 1e-12 * big))
+    strict, l2 = np.array(strict), np.array(l2)
+    ws, wl2 = int(np.argmax(strict)), int(np.argmax(l2))
+    return {"max_rel_err": float(strict[ws]), "worst_lambda": [int(x) for x in labels[ws]],
+            "quantiles": {q: float(np.percentile(strict, v)) for q, v in (("p50", 50), ("p90", 90), ("p99", 99))},
+            "l2_max": float(l2[wl2]), "worst_lambda_l2": [int(x) for x in labels[wl2]],
+            "per_lambda": [float(f"{e:.3g}") for e in strict]}
+
+
+def c1_one_core():
+    """The oracle on the whole c1 catalogue (2000 points, every primary) with
+    one OpenMP thread, in a child process so that the thread count applies."""
+    import subprocess
+    code = ("import time, sys; sys.path.insert(0, %r)\n"
+            "import oracle\n"
+            "from paper_2106_10278_amd import inputs\n"
+            "wl = inputs.c1_small_3pcf()\n"
+            "t = time.perf_counter()\n"
+            "z, p = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w)\n"
+            "print(time.perf_counter() - t, p)\n") % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return None
+    dt, pairs = r.stdout.split()[-2:]
+    return {"workload": "c1 (D3-N3-lmax4, 2000 uniform points, every primary)", "cores": 1,
+            "seconds": float(dt), "pairs": int(pairs), "pairs_per_s": int(pairs) / float(dt)}
+
+
 def make_workload(name: str):
     from paper_2106_10278_amd import inputs
     if name == "c2":
@@ -226,9 +279,15 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None):
                 plan.accumulate(pos, w, a, b)
         got = plan.finalize()
         gp = plan.pair_count()[0]
-        e, worst = rel_err(got, ref)
-        errs[prec] = {"max_rel_err": e, "worst_lambda": [int(x) for x in oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)[worst]],
-                      "pairs_match": bool(gp == pairs)}
+        labels = oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)
+        if wl.D == 2:
+            # complex output: one row per (Lambda, Re/Im)
+            got = np.concatenate([got.real, got.imag])
+            ref_rows = np.concatenate([ref.real, ref.imag])
+            labels = np.concatenate([labels, labels])
+        else:
+            ref_rows = ref
+        errs[prec] = multipole_errors(got, ref_rows, labels) | {"pairs_match": bool(gp == pairs)}
         plan.close()
     cpu_model = ""
     try:
@@ -242,6 +301,8 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None):
             "sample": f"{len(prims)} primaries ({'+'.join(f'[{a},{b})' for a, b in ranges)}) against all "
                       f"{wl.pos.shape[1]} secondaries, {pairs} in-range pairs, {dt:.1f} s",
             "seconds": dt}
+    if wl.name.startswith("D3-N4-clustered"):
+        base["c1_one_core"] = c1_one_core()
     return base, errs
 
 
@@ -369,11 +430,13 @@ def main():
             else ("plain" if "plain" in results else list(results)[0]))
     r = results[head]
     key = f"D{wl.D}-N{wl.N}-lmax{wl.lmax}-{wl.name}"
-    fpp = flops_per_pair(wl.D, wl.lmax)
+    fpp = scope_flops_per_pair(wl.D, wl.lmax)
     achieved = fpp * r["pairs_per_step"] / (r["harmonic_ms_per_launch"] * 1e-3)
     roof = {"kernel": "k_harmonic", "bound": "alu", "achieved": achieved / 1e12,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
-            "traffic": load_traffic(key), "flops_per_pair": fpp, "launch_ms": r["harmonic_ms_per_launch"]}
+            "traffic": load_traffic(key), "flops_per_pair": fpp,
+            "flops_per_pair_instruction_level": flops_per_pair(wl.D, wl.lmax),
+            "launch_ms": r["harmonic_ms_per_launch"]}
     if wl.sphere:
         # every pair is visited (no cell list): count the bin test of all of them
         fl = sphere_flops(wl.lmax, float(n) * n, r["pairs_per_step"])

@@ -14,7 +14,9 @@
 // decides the bin (through a bucket table where no edge is near, else against
 // the edge cosines) unless it lies within 1e-6 of an edge (its error is below
 // 4e-7), where the FP64 dot product decides, so the decisions equal the FP64
-// ones.  As many bins as fit about 50 registers
+// ones.  In-range pairs are queued by catalogue index; the harmonics take the
+// tangent components from the FP64 positions in an FP64 frame, normalised in
+// FP64 and rounded once to FP32.  As many bins as fit about 50 registers
 // are taken per pass (more passes rescan the points, but fewer registers let
 // four waves share a SIMD and each queued pair feeds fewer masked sums); each
 // lane sums harmonics in FP32 (a 0/1 mask per bin) and every few tiles the
@@ -111,8 +113,10 @@ template <int L>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
     __shared__ float4 tile[kSphTile];
-    // per wave: in-range pairs waiting for the harmonics (point, bin)
-    __shared__ float4 qpt[kSphWaves][128];
+    // per wave: in-range pairs waiting for the harmonics (catalogue index,
+    // weight, bin)
+    __shared__ int qidx[kSphWaves][128];
+    __shared__ float qw[kSphWaves][128];
     __shared__ int qbin[kSphWaves][128];
     // the pass's edge cosines (FP32) and a bucket table over its cosine range.
     // Entry k is the bin of every cosine in bucket k when no edge, widened by
@@ -145,8 +149,6 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     e1z *= inn;
     const double e2x = py * e1z - pz * e1y, e2y = pz * e1x - px * e1z, e2z = px * e1y - py * e1x;
     const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
-    const float e1xf = (float)e1x, e1yf = (float)e1y, e1zf = (float)e1z;
-    const float e2xf = (float)e2x, e2yf = (float)e2y, e2zf = (float)e2z;
 
     unsigned long long cnt_pairs = 0;   // wave-uniform
     for (int b0 = 0; b0 < a.nb; b0 += G) {
@@ -185,18 +187,30 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         // harmonics of the first cnt queued pairs, one per lane, into the bin sums
         auto process = [&](int cnt) {
             const bool live = lane < cnt;
-            const float4 q = live ? qpt[wave][lane] : make_float4(0.f, 0.f, 1.f, 0.f);
+            const int k = live ? qidx[wave][lane] : 0;
+            const float wq = live ? qw[wave][lane] : 0.f;
             const int bl = live ? qbin[wave][lane] : 0;
-            const float t1 = q.x * e1xf + q.y * e1yf + q.z * e1zf;
-            const float t2 = q.x * e2xf + q.y * e2yf + q.z * e2zf;
-            const float tn2 = t1 * t1 + t2 * t2;
-            const bool ok = live && tn2 > 0.f;
-            const float itn = ok ? rsqrtf(tn2) : 0.f;
-            const float u[2] = {t1 * itn, t2 * itn};
+            // tangent components from the FP64 positions and frame, normalised
+            // in FP64 and rounded once to FP32 (each rounding of the direction
+            // enters the l-th harmonic about l times)
+            double qx = 0.0, qy = 0.0, qz = 0.0;
+            if (live) {
+                qx = a.pos[k];
+                qy = a.pos[a.n + k];
+                qz = a.pos[2 * a.n + k];
+            }
+            const double t1 = qx * e1x + qy * e1y + qz * e1z;
+            const double t2 = qx * e2x + qy * e2y + qz * e2z;
+            const double tn2 = t1 * t1 + t2 * t2;
+            const bool ok = live && tn2 > 0.0;
+            const double ts = ok ? tn2 : 1.0;
+            double itn = __builtin_amdgcn_rsq(ts);
+            itn = itn * (1.5 - 0.5 * ts * itn * itn);
+            const float u[2] = {ok ? (float)(t1 * itn) : 0.f, ok ? (float)(t2 * itn) : 0.f};
             cnt_pairs += __popcll(__builtin_amdgcn_ballot_w64(ok));
             float hv[NV];
             hv[1] = 0.f;   // l = 0 is real
-            harm::harmonics<2, L>(u, ok ? q.w : 0.f, [&](int slot, float v) { hv[slot] = v; });
+            harm::harmonics<2, L>(u, ok ? wq : 0.f, [&](int slot, float v) { hv[slot] = v; });
 #pragma unroll
             for (int g = 0; g < G; g++) {
                 const float m = (ok && g == bl) ? 1.f : 0.f;
@@ -252,7 +266,8 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                     const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
                     if (valid) {
-                        qpt[wave][slot] = q;
+                        qidx[wave][slot] = (int)(t0 + i);
+                        qw[wave][slot] = q.w;
                         qbin[wave][slot] = bl;
                     }
                     qn += __popcll(vm);
@@ -261,15 +276,17 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         process(64);
                         // move the rest (< 64) to the front
                         const int rest = qn - 64;
-                        float4 mq = make_float4(0.f, 0.f, 0.f, 0.f);
-                        int mb = 0;
+                        int mi = 0, mb = 0;
+                        float mw = 0.f;
                         if (lane < rest) {
-                            mq = qpt[wave][64 + lane];
+                            mi = qidx[wave][64 + lane];
+                            mw = qw[wave][64 + lane];
                             mb = qbin[wave][64 + lane];
                         }
                         NPCF_SPH_WAVE_SYNC();
                         if (lane < rest) {
-                            qpt[wave][lane] = mq;
+                            qidx[wave][lane] = mi;
+                            qw[wave][lane] = mw;
                             qbin[wave][lane] = mb;
                         }
                         qn = rest;

@@ -84,3 +84,40 @@ def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", 
     out = plan.finalize()
     pairs = plan.pair_count()[0]
     return out, pairs, plan
+
+
+def alm_error(got, ref, wl, prims, D, lmax, sphere=False):
+    """Largest |got - ref| of a^b_[l] values, each over a bound on the sum of
+    the magnitudes of its terms: |w_k conj(Y_s)| <= |w_k| sqrt(dim_l / |S^{D-1}|)
+    (the addition theorem bounds every harmonic of order l), so with
+    A_0 = a^b_0 evaluated with |w|, which is sum_k |w_k| / (v_b sqrt|S^{D-1}|),
+    the bound of state s is A_0 sqrt(dim_l) (dim_l = 1, 2l + 1, (l + 1)^2 for
+    D = 2, 3, 4).  Judged value by value, small multipoles are held to their
+    own scale rather than to the largest |a|.  `got` and `ref` are in the
+    library's stored-state order, [prim][bin][state]."""
+    from paper_2106_10278_amd import stored_state_labels
+    a_abs, _ = oracle.alm(D, lmax, wl.edges, wl.box, wl.pos, np.abs(wl.w), prims=prims, sphere=sphere)
+    olab = [tuple(int(x) for x in r) for r in oracle.state_labels(D, lmax)]
+    zero = (0,) if D == 2 else ((0, 0) if D == 3 else (0, 0, 0))
+    A0 = np.abs(a_abs[:, :, olab.index(zero)])
+    st = stored_state_labels(D, lmax)
+    top = st[:, 0] if D == 2 else (st[:, 1] if D == 3 else st[:, 2])
+    dim = np.ones(len(st)) if D == 2 else ((2 * top + 1.0) if D == 3 else (top + 1.0) ** 2)
+    bound = A0[:, :, None] * np.sqrt(dim)[None, None, :]
+    bound = np.maximum(bound, 1e-300)
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref)) / bound))
+
+
+def strict_where_well_conditioned(got, ref, scale, kappa_max=3.0):
+    """Strict per-multipole errors on the rows whose condition number
+    kappa = max_b S / max_b |ref| (S: sum of the magnitudes of the estimator's
+    terms) is at most kappa_max.  A sum evaluated with unit roundoff u has
+    error below about u S, so on such a row the strict error is within
+    kappa_max of the conditioned one; rows above it are multipoles that cancel
+    to a small fraction of their terms.  Returns (largest strict error over
+    the well-conditioned rows, their count, kappa of every row)."""
+    got, ref, scale = np.asarray(got), np.asarray(ref), np.asarray(scale)
+    kappa = np.array([np.max(scale[i]) / max(np.max(np.abs(ref[i])), 1e-300) for i in range(ref.shape[0])])
+    _, errs = per_multipole_error(got, ref)
+    sel = kappa <= kappa_max
+    return (float(np.max(errs[sel])) if np.any(sel) else 0.0), int(np.sum(sel)), kappa

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2106_10278_amd import inputs
-from npcf_testutil import condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
+from npcf_testutil import strict_where_well_conditioned, condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +76,12 @@ _C7 = {}
 def test_c7_full_catalogue_sampled(precision):
     """The 5PCF workload at full size (100k uniform points, lmax 4, 10 bins):
     32 primaries against every secondary, in the benchmark's launch
-    configuration, against the oracle on the same primaries."""
+    configuration, against the oracle on the same primaries.  Every multipole
+    within the conditioned bar; the strict bar on the rows whose condition
+    number S/|zeta| is at most 3.  With unit weights on uniform points most
+    5PCF multipoles are cancellation noise (S/|zeta| median about 19, up to
+    61): there the FP32 harmonics alone (about l u per value) put the strict
+    error above 1e-6."""
     if "wl" not in _C7:
         wl = inputs.c7_uniform_5pcf()
         prims = np.arange(0, 32)
@@ -89,5 +94,8 @@ def test_c7_full_catalogue_sampled(precision):
     assert pairs == _C7["pairs"]
     err, _ = per_multipole_error(got, ref)
     cerr, _ = conditioned_error(got, ref, _C7["scale"])
-    print(f"[err] c7 {precision}: strict {err:.3e} conditioned {cerr:.3e}", flush=True)
+    serr, nrows, kappa = strict_where_well_conditioned(got, ref, _C7["scale"])
+    print(f"[err] c7 {precision}: strict {err:.3e} conditioned {cerr:.3e}; strict {serr:.3e} on the {nrows} "
+          f"rows with kappa <= 3 (kappa median {np.median(kappa):.1f}, max {kappa.max():.1f})", flush=True)
     assert cerr <= TOL[precision]
+    assert nrows >= 1 and serr <= TOL[precision]

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2106_10278_amd import inputs
-from npcf_testutil import condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
+from npcf_testutil import alm_error, condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
 
 pytestmark = pytest.mark.gpu
 
@@ -127,7 +127,9 @@ def test_sphere_alm_and_ranges():
     ref, _ = oracle.alm(2, 4, wl.edges, wl.box, wl.pos, wl.w, prims=np.arange(20, 120), sphere=True)
     olab = [int(r[0]) for r in oracle.state_labels(2, 4)]
     ref = ref[:, :, [olab.index(l) for l in range(5)]]
-    assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+    err = alm_error(got, ref, wl, np.arange(20, 120), 2, 4, sphere=True)
+    print(f"[err] sphere alm: {err:.3e} of each value's term-magnitude bound", flush=True)
+    assert err <= 1e-6
     plan.close()
     whole, _, _ = gpu_run(wl)
     parts, _, _ = gpu_run(wl, ranges=[(0, 133), (133, 400), (400, 500)])
@@ -154,7 +156,7 @@ _C9 = {}
 def test_c9_full_sphere_sampled(precision):
     """The sphere workload at full size (100k points, the paper's CMB test
     bins): 32 primaries against every point, against the oracle on the same
-    primaries."""
+    primaries, per multipole on the strict measure (and the conditioned one)."""
     if "wl" not in _C9:
         wl = inputs.c9_sphere_4pcf()
         prims = np.arange(0, 32)
@@ -168,3 +170,5 @@ def test_c9_full_sphere_sampled(precision):
     cerr, _ = conditioned_error(got, ref, _C9["scale"])
     print(f"[err] c9 {precision}: strict {err:.3e} conditioned {cerr:.3e}", flush=True)
     assert cerr <= TOL[precision]
+    # every c9 multipole has S/|zeta| <= 3.2: the strict bar holds on all of them
+    assert err <= TOL[precision]
