@@ -60,6 +60,33 @@ __device__ __forceinline__ float wave_pow2_scale(float m)
     return ldexpf(1.f, -e);
 }
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// x = hi + mid + lo in BF16 (each rounded to nearest), two values per packed
+// conversion; a BF16 value widens to FP32 exactly by placing its 16 bits on
+// top of a zero half, so each residual is one subtraction.
+__device__ __forceinline__ void split3_bf16(const float (&x)[8], v8bf &hi, v8bf &mid, v8bf &lo)
+{
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        const v2f v = {x[i], x[i + 1]};
+        const v2bf h = __builtin_convertvector(v, v2bf);
+        const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+        const v2f r = {v[0] - __uint_as_float(hb << 16), v[1] - __uint_as_float(hb & 0xFFFF0000u)};
+        const v2bf m = __builtin_convertvector(r, v2bf);
+        const uint32_t mb = __builtin_bit_cast(uint32_t, m);
+        const v2f t = {r[0] - __uint_as_float(mb << 16), r[1] - __uint_as_float(mb & 0xFFFF0000u)};
+        const v2bf l = __builtin_convertvector(t, v2bf);
+        hi[i] = h[0];
+        hi[i + 1] = h[1];
+        mid[i] = m[0];
+        mid[i + 1] = m[1];
+        lo[i] = l[0];
+        lo[i + 1] = l[1];
+    }
+}
+
 // One K = 32 slice: lane l holds 8 (A, B) operand pairs; A row = l % 16,
 // B column = l % 16, and the 4 lane quarters together cover 32 K indices
 // (the order of K is immaterial to the sum).  Accumulates into c (from zero)
@@ -106,17 +133,8 @@ __device__ __forceinline__ void mfma_k32(const float (&Av)[8], const float (&Bv)
         unscale = 1.0 / ((double)sa * (double)sb);
     } else {
         v8bf ah, am, al, bh, bm, bl;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            ah[i] = (__bf16)Av[i];
-            float r = Av[i] - (float)ah[i];
-            am[i] = (__bf16)r;
-            al[i] = (__bf16)(r - (float)am[i]);
-            bh[i] = (__bf16)Bv[i];
-            r = Bv[i] - (float)bh[i];
-            bm[i] = (__bf16)r;
-            bl[i] = (__bf16)(r - (float)bm[i]);
-        }
+        split3_bf16(Av, ah, am, al);
+        split3_bf16(Bv, bh, bm, bl);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
