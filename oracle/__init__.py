@@ -206,7 +206,8 @@ def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None, sphere
     cfg.btuple_mode = btuple_mode
     cfg.basis = 0 if Lmax is None else 1
     cfg.Lmax = 0 if Lmax is None else int(Lmax)
-    cfg.geometry = 1 if sphere else 0
+    # sphere: points on the unit D-sphere (D = 2: S^2 in R^3; D = 3: S^3 in R^4)
+    cfg.geometry = (D - 1) if sphere else 0
     return cfg, edges
 
 
@@ -222,8 +223,8 @@ def _prep(pos, w, prims):
 
 def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True, sphere=False):
     """a^b_[l](y_j) for the listed primaries: complex [nprim][nbins][nstates].
-    sphere: points on the unit 2-sphere (D = 2, pos [3][n] unit vectors, edges
-    in radians of great-circle angle)."""
+    sphere: points on the unit D-sphere (D = 2: pos [3][n], D = 3: pos [4][n]
+    unit vectors; edges in radians of geodesic angle)."""
     lib = _load()
     cfg, edges = _cfg(D, 3, lmax, edges, box, periodic, sphere=sphere)
     pos, w, n, prims = _prep(pos, w, prims)

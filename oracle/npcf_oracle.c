@@ -59,6 +59,22 @@
  *    sqrt(2 pi); v_b = 2 pi (cos e_b - cos e_{b+1}) (the annulus' area) and
  *    V = 4 pi.  Isotropic components do not depend on the frame.
  *
+ *  - with cfg->geometry = 2 (D = 3), points on the unit 3-sphere, the
+ *    constant-curvature space of section "Constant-Curvature Metric" with
+ *    k = 1, chi(r) = sin r (eq. metric): positions are unit vectors in R^4
+ *    (pos[4][n]); the radial coordinate is the geodesic angle theta between
+ *    primary p and secondary q, binned e_b <= theta < e_{b+1}, i.e.
+ *    cos(e_{b+1}) < p.q <= cos(e_b) on the FP64 dot product; the direction is
+ *    that of q - (p.q) p in the tangent space at p, in the orthonormal frame
+ *    e1 = p i, e2 = p j, e3 = p k (quaternion products, p = a + b i + c j + d k:
+ *    e1 = (-b, a, d, -c), e2 = (-c, -d, a, b), e3 = (-d, c, -b, a), with
+ *    det[p, e1, e2, e3] = +1 everywhere), so u = (q.e1, q.e2, q.e3) / norm and
+ *    the harmonics are the D = 3 ones of u; v_b = |S^2| int chi^{D-1} dr over
+ *    the bin = 2 pi [(e_{b+1} - e_b) - (sin 2e_{b+1} - sin 2e_b) / 2] and
+ *    V = 2 pi^2 (the 3-sphere's volume).  Isotropic components do not depend
+ *    on the frame (a rotation of it rotates every direction at p alike); odd
+ *    ones change sign with its orientation.
+ *
  * The unrestricted sum over secondaries k runs over all n points for every
  * primary (brute force, no cell grid); the self pair is excluded because
  * edges[0] > 0.
@@ -78,7 +94,7 @@ typedef struct {
     int btuple_mode;      /* 0: b1 < b2 < ... ; 1: every tuple */
     int basis;            /* 0: isotropic (vec L = 0); 1: line-of-sight P^{0L} (D = 3, N = 3) */
     int Lmax;             /* basis 1: largest L */
-    int geometry;         /* 0: flat box; 1: unit 2-sphere (D = 2) */
+    int geometry;         /* 0: flat box; 1: unit 2-sphere (D = 2); 2: unit 3-sphere (D = 3) */
 } oracle_cfg;
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
@@ -611,10 +627,14 @@ int oracle_coupling_terms_los(int lmax, int Lmax, int cap, int *lam, int *s, dou
 static int check_cfg(const oracle_cfg *cfg)
 {
     if (!cfg || !cfg->edges) return OR_EINVAL;
-    if (cfg->geometry != 0 && cfg->geometry != 1) return OR_EINVAL;
-    if (cfg->geometry == 1) {
-        if (cfg->D != 2 || cfg->basis != 0 || cfg->N > 4) return OR_EUNSUP;
-        if (cfg->lmax < 0 || cfg->nbins < 1 || !(cfg->edges[0] > 0.0) || cfg->edges[cfg->nbins] > M_PI) return OR_EINVAL;
+    if (cfg->geometry < 0 || cfg->geometry > 2) return OR_EINVAL;
+    if (cfg->geometry != 0) {
+        if (cfg->D != cfg->geometry + 1 || cfg->basis != 0 || cfg->N > 4) return OR_EUNSUP;
+        /* bins are decided on cosines: cos(e_0) must stay below 1, so that the
+         * self pair (p.p = 1 up to rounding) is outside every bin */
+        if (cfg->lmax < 0 || cfg->nbins < 1 || !(cfg->edges[0] > 0.0) || !(cos(cfg->edges[0]) < 1.0 - 1e-12) ||
+            cfg->edges[cfg->nbins] > M_PI)
+            return OR_EINVAL;
         for (int b = 0; b < cfg->nbins; b++)
             if (!(cfg->edges[b + 1] > cfg->edges[b])) return OR_EINVAL;
         return OR_OK;
@@ -683,6 +703,53 @@ static long harmonic_stage_sphere(const oracle_cfg *cfg, const double *pos, cons
     return pairs;
 }
 
+/* Unit 3-sphere (cfg->geometry = 2): see the header.  a[b][s] divided by the
+ * bin volume |S^2| int_{e_b}^{e_{b+1}} sin^2 r dr. */
+static double s3_bin_volume(double e0, double e1)
+{
+    return 2.0 * M_PI * ((e1 - e0) - 0.5 * (sin(2.0 * e1) - sin(2.0 * e0)));
+}
+
+static long harmonic_stage_s3(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
+                              int nst, double *a, double *yre, double *yim)
+{
+    const int nb = cfg->nbins;
+    const double pa = pos[j], pb = pos[n + j], pc = pos[2 * n + j], pd = pos[3 * n + j];
+    /* tangent frame at p: p i, p j, p k */
+    const double e1[4] = {-pb, pa, pd, -pc};
+    const double e2[4] = {-pc, -pd, pa, pb};
+    const double e3[4] = {-pd, pc, -pb, pa};
+    long pairs = 0;
+    for (long k = 0; k < n; k++) {
+        const double q[4] = {pos[k], pos[n + k], pos[2 * n + k], pos[3 * n + k]};
+        const double c = pa * q[0] + pb * q[1] + pc * q[2] + pd * q[3];
+        if (!(c <= cos(cfg->edges[0]) && c > cos(cfg->edges[nb]))) continue;
+        int b = 0;
+        while (b + 1 < nb && c <= cos(cfg->edges[b + 1])) b++;
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int x = 0; x < 4; x++) {
+            t[0] += q[x] * e1[x];
+            t[1] += q[x] * e2[x];
+            t[2] += q[x] * e3[x];
+        }
+        const double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        if (!(tn > 0.0)) continue;
+        const double u[3] = {t[0] / tn, t[1] / tn, t[2] / tn};
+        pairs++;
+        oracle_harmonics(3, cfg->lmax, u, yre, yim);
+        double *ab = a + 2 * (size_t)b * nst;
+        for (int s = 0; s < nst; s++) {
+            ab[2 * s] += w[k] * yre[s];
+            ab[2 * s + 1] -= w[k] * yim[s];  /* conj(Y) */
+        }
+    }
+    for (int b = 0; b < nb; b++) {
+        const double vb = s3_bin_volume(cfg->edges[b], cfg->edges[b + 1]);
+        for (int s = 0; s < 2 * nst; s++) a[2 * (size_t)b * nst + s] /= vb;
+    }
+    return pairs;
+}
+
 static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
                            int nst, double *a, double *yre, double *yim)
 {
@@ -690,6 +757,7 @@ static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const doubl
     memset(a, 0, sizeof(double) * 2 * (size_t)nb * nst);
     long pairs = 0;
     if (cfg->geometry == 1) return harmonic_stage_sphere(cfg, pos, w, n, j, nst, a, yre, yim);
+    if (cfg->geometry == 2) return harmonic_stage_s3(cfg, pos, w, n, j, nst, a, yre, yim);
     double e2lo = cfg->edges[0] * cfg->edges[0];
     double e2hi = cfg->edges[nb] * cfg->edges[nb];
     for (long k = 0; k < n; k++) {
@@ -828,6 +896,7 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
     double VD = 1.0;
     for (int k = 0; k < D; k++) VD *= cfg->box[k];
     if (cfg->geometry == 1) VD = 4.0 * M_PI;   /* area of the unit 2-sphere */
+    if (cfg->geometry == 2) VD = 2.0 * M_PI * M_PI;   /* volume of the unit 3-sphere */
     for (size_t i = 0; i < zlen; i++) {
         double s = 0.0;
         for (int t = 0; t < nthr; t++) s += part[(size_t)t * zlen + i];

@@ -954,3 +954,138 @@ def test_sphere_alm_frame_phase():
         l1 = int(np.nonzero(lab == 1)[0][0])
         alpha = np.angle(a[j, :, l1].sum() / ref[:, l1].sum())
         np.testing.assert_allclose(a[j], ref * np.exp(1j * lab * alpha)[None, :], rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
+# Unit 3-sphere (section "Constant-Curvature Metric", k = 1: chi(r) = sin r)
+# --------------------------------------------------------------------------
+
+def _s3_points(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(4, n))
+    return x / np.linalg.norm(x, axis=0), rng.uniform(-0.5, 1.5, size=n)
+
+
+def _s3_volume_quad(e0, e1):
+    """|S^2| int sin^2 r dr over the bin, by quadrature (eq. metric's volume element)."""
+    from scipy.integrate import quad
+    return 4 * math.pi * quad(lambda r: math.sin(r) ** 2, e0, e1, epsabs=1e-14, epsrel=1e-14)[0]
+
+
+def _second_frame(p):
+    """An orthonormal, positively oriented frame of the tangent space at p
+    (Gram-Schmidt of the coordinate axes), unlike the oracle's quaternion one."""
+    q, _ = np.linalg.qr(np.column_stack([p, np.eye(4)]))
+    f = q[:, 1:4] * np.sign(q[:, 0] @ p)
+    if np.linalg.det(np.column_stack([p, f])) < 0:
+        f[:, 2] = -f[:, 2]
+    return f
+
+
+def _s3_brute(pos, w, edges, N, lmax, btuple_mode):
+    """Naive estimator on S^3: unrestricted (N-1)-tuples of secondaries in the
+    geodesic bins, directions in the second frame, basis from SciPy harmonics
+    and SymPy Clebsch-Gordan coefficients, coefficients through conj(P), bin
+    volumes by quadrature, divided by the 3-sphere's volume 2 pi^2."""
+    nb = len(edges) - 1
+    vb = np.array([_s3_volume_quad(edges[b], edges[b + 1]) for b in range(nb)])
+    labels = labels_indep.labels(3, N, lmax)
+    P = _indep_basis(3, N, lmax)
+    full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
+    for j in range(pos.shape[1]):
+        p = pos[:, j]
+        ang = np.arccos(np.clip(pos.T @ p, -1.0, 1.0))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        idx = np.nonzero(ok)[0]
+        if len(idx) == 0:
+            continue
+        b = np.searchsorted(edges, ang[idx], side="right") - 1
+        t = pos[:, idx].T @ _second_frame(p)
+        u = t / np.linalg.norm(t, axis=1, keepdims=True)
+        ww = w[idx] / vb[b]
+        pv = np.conj(P(*([u] * (N - 1))))
+        if N == 3:
+            contrib = pv * ww[None, :, None] * ww[None, None, :]
+            for i1 in range(len(idx)):
+                np.add.at(full, (slice(None), b[i1], b), w[j] * contrib[:, i1, :])
+        else:
+            contrib = pv * ww[None, :, None, None] * ww[None, None, :, None] * ww[None, None, None, :]
+            for i1 in range(len(idx)):
+                for i2 in range(len(idx)):
+                    np.add.at(full, (slice(None), b[i1], b[i2], b), w[j] * contrib[:, i1, i2, :])
+    full /= 2 * math.pi ** 2
+    bt = oracle.btuple_labels(nb, N, btuple_mode)
+    return full[(slice(None),) + tuple(bt[:, k] for k in range(N - 1))]
+
+
+@pytest.mark.parametrize("N,lmax,mode,n", [(3, 4, 1, 50), (4, 3, 1, 28), (4, 2, 0, 34)])
+def test_s3_separable_equals_naive(N, lmax, mode, n):
+    """The separable estimator on S^3 equals the naive tuple sum built in
+    another tangent frame with an independent basis (isotropic components do
+    not depend on the frame)."""
+    edges = np.array([0.3, 0.7, 1.2, 1.7]) if mode == 1 else np.array([0.35, 0.6, 0.9, 1.3, 1.9])
+    pos, w = _s3_points(n, 60 + N + lmax)
+    ref = _s3_brute(pos, w, edges, N, lmax, mode)
+    got, _ = oracle.npcf(3, N, lmax, edges, [1.0] * 3, pos, w, btuple_mode=mode, sphere=True)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+
+
+def test_s3_rotation_invariance_parity_and_l0():
+    """A random SO(4) rotation leaves every isotropic component unchanged; a
+    reflection keeps the even-parity ones and flips the odd ones (the frame's
+    orientation is reversed); the l = 0 row equals the weighted triplet count
+    sum_j w_j W_b1(j) W_b2(j) W_b3(j) / (2 pi^2 prod v_b (4 pi)^{3/2}) with
+    bin volumes by quadrature."""
+    rng = np.random.default_rng(7)
+    pos, w = _s3_points(80, 8)
+    edges = np.array([0.4, 0.8, 1.3, 1.9])
+    args = (3, 4, 3, edges, [1.0] * 3)
+    z0, p0 = oracle.npcf(*args, pos, w, btuple_mode=1, sphere=True)
+    R, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+    if np.linalg.det(R) < 0:
+        R[:, 0] = -R[:, 0]
+    zr, pr = oracle.npcf(*args, R @ pos, w, btuple_mode=1, sphere=True)
+    sc = np.max(np.abs(z0))
+    assert pr == p0
+    np.testing.assert_allclose(zr, z0, rtol=0, atol=1e-11 * sc)
+    F = np.diag([1.0, 1.0, 1.0, -1.0])
+    zf, _ = oracle.npcf(*args, F @ pos, w, btuple_mode=1, sphere=True)
+    lab = oracle.lambda_labels(3, 4, 3)
+    odd = lab.sum(axis=1) % 2 == 1
+    np.testing.assert_allclose(zf[~odd], z0[~odd], rtol=0, atol=1e-11 * sc)
+    np.testing.assert_allclose(zf[odd], -z0[odd], rtol=0, atol=1e-11 * sc)
+    assert np.max(np.abs(z0[odd])) > 1e-6 * sc
+    # l = 0: weighted counts
+    nb = 3
+    vb = np.array([_s3_volume_quad(edges[b], edges[b + 1]) for b in range(nb)])
+    Wb = np.zeros((pos.shape[1], nb))
+    for j in range(pos.shape[1]):
+        ang = np.arccos(np.clip(pos.T @ pos[:, j], -1, 1))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        b = np.searchsorted(edges, ang[ok], side="right") - 1
+        np.add.at(Wb[j], b, w[ok])
+    bt = oracle.btuple_labels(nb, 4, 1)
+    ref = np.array([np.sum(w * Wb[:, t[0]] * Wb[:, t[1]] * Wb[:, t[2]]) / (vb[t[0]] * vb[t[1]] * vb[t[2]])
+                    for t in bt]) / (2 * math.pi ** 2 * (4 * math.pi) ** 1.5)
+    i0 = int(np.nonzero((lab == 0).all(axis=1))[0][0])
+    np.testing.assert_allclose(z0[i0].real, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
+
+
+def test_s3_bin_volumes_fill_the_sphere():
+    """Bins covering [1e-5, pi) hold the 3-sphere's volume 2 pi^2 up to the
+    first bin's 1e-15 (each bin's volume against quadrature of the metric's
+    volume element), and every pair is in range: the pair count is n (n - 1).
+    An innermost edge whose cosine rounds to 1 is rejected (the self pair
+    could not be told apart from a pair at that distance)."""
+    edges = np.array([1e-5, 0.5, 1.0, 2.0, math.pi])
+    pos, w = _s3_points(30, 3)
+    tot = sum(_s3_volume_quad(edges[b], edges[b + 1]) for b in range(4))
+    assert tot == pytest.approx(2 * math.pi ** 2, rel=1e-9)
+    _, pairs = oracle.npcf(3, 3, 1, edges, [1.0] * 3, pos, w, sphere=True)
+    assert pairs == 30 * 29
+    with pytest.raises(ValueError):
+        oracle.npcf(3, 3, 1, np.array([1e-9, 1.0]), [1.0] * 3, pos, w, sphere=True)
