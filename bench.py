@@ -397,7 +397,7 @@ def main():
         if args.tuning:
             sdv, blk = (int(x) for x in args.tuning.split(","))
             plan.set_tuning(cell_subdiv=sdv, couple_block=blk)
-            tuning = {"cell_subdiv": sdv, "couple_block": blk, "fixed": True}
+            tuning = plan.tuning() | {"fixed": True}
         elif field is None:
             tuning = plan.autotune(pos, w) if not args.no_tune else None
         else:

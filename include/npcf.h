@@ -280,14 +280,43 @@ npcf_status npcf_destroy(npcf_plan_t plan);
  * (out of range), NPCF_E_NOMEM. */
 npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block, int64_t chunk_rows);
 
-/* Autotuner: times the harmonic stage with its cell list for every cell
- * subdivision s = 1..6 on `sample` primaries of the given catalogue, taken
- * from four ranges spread over it (best of two runs each, HIP events), and
- * keeps the fastest (as npcf_set_tuning).  The coupling block size is left
- * automatic: a sample leaves large blocks short of work where the full
- * catalogue does not, so it cannot rank them.  Resets the accumulators.
- * Outputs (may be NULL): the chosen subdivision, block size (always 0:
- * automatic) and the sampled time in ms.  Errors as npcf_accumulate. */
+/* Tile shapes and launch sizes of a plan (npcf_get_tuning, npcf_apply_tuning). */
+typedef struct {
+    int cell_subdiv;             /* cells of side >= r_max / s, 1..8 */
+    int couple_block;            /* primaries per coupling block (multiple of 16; 0: the automatic rule) */
+    int64_t chunk_rows;          /* primaries per chunk (rows of a held at once) */
+    int harmonic_blocks_per_cu;  /* persistent harmonic grid: blocks of four waves per compute unit, 1..32 */
+} npcf_tuning;
+
+/* The plan's current tuning (the automatic values where nothing was set).
+ * Errors: NPCF_E_INVALID (NULL arguments). */
+npcf_status npcf_get_tuning(npcf_plan_t plan, npcf_tuning *out);
+
+/* Set every knob of `t` that is non-zero (as npcf_set_tuning, plus the
+ * harmonic grid).  Synchronises.  Errors: NPCF_E_INVALID (out of range),
+ * NPCF_E_NOMEM. */
+npcf_status npcf_apply_tuning(npcf_plan_t plan, const npcf_tuning *t);
+
+/* Autotuner for the given catalogue (positions and weights as npcf_accumulate):
+ *  - the cell subdivision s = 1..6 (1..4 for D = 4) and then the harmonic
+ *    grid's blocks per CU (2, 3, 4, 6, 8), timing the harmonic stage with its
+ *    cell list on `sample` primaries taken from four ranges spread over the
+ *    catalogue;
+ *  - the primaries per coupling block (the automatic rule, 256, 512, 1024,
+ *    2048) and the chunk rows (the plan's largest, or n / 32), timing the
+ *    coupling and the whole pass on a quarter of the catalogue in four spread
+ *    ranges, so that the row blocks have their full size and fill the GPU as
+ *    the whole catalogue does (a small sample would leave large blocks idle);
+ *  each by the best of two runs (HIP events); a setting other than the
+ *  default must win by 2%.  The choice is applied to the plan (read it with
+ *  npcf_get_tuning).  With the environment variable NPCF_TUNE_CACHE naming a
+ *  file, a tuning stored there for the same problem (D, N, lmax, bins, r_max,
+ *  n, box, precision, b-tuple mode, basis, periodicity, CU count) is applied
+ *  without timing, and a new one is written to it (JSON).  Resets the
+ *  accumulators.  Outputs (may be NULL): the chosen subdivision, block size
+ *  (0: the automatic rule) and the timed ms of harmonic + coupling.  On the
+ *  sphere geometry (no cell grid) nothing is tuned.  Errors as
+ *  npcf_accumulate. */
 npcf_status npcf_autotune(npcf_plan_t plan, const double *pos, const double *w, int64_t n, int64_t sample,
                           int *cell_subdiv, int *couple_block, double *best_ms);
 

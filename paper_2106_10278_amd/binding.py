@@ -48,6 +48,11 @@ class _Config(ctypes.Structure):
     ]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("cell_subdiv", ctypes.c_int), ("couple_block", ctypes.c_int), ("chunk_rows", ctypes.c_int64),
+                ("harmonic_blocks_per_cu", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -83,13 +88,16 @@ def load_library():
     lib.npcf_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64]
     lib.npcf_stage_ms.argtypes = [vp, dp]
     lib.npcf_autotune.argtypes = [vp, vp, vp, i64, i64, ip, ip, dp]
+    lib.npcf_get_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    lib.npcf_apply_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
     lib.npcf_strerror.argtypes = [ctypes.c_int]
     lib.npcf_strerror.restype = ctypes.c_char_p
     lib.npcf_version.restype = ctypes.c_char_p
     lib.npcf_last_error_detail.restype = ctypes.c_char_p
     for name in ("npcf_plan", "npcf_accumulate", "npcf_accumulate_static", "npcf_finalize", "npcf_describe", "npcf_pair_count", "npcf_alm",
                  "npcf_accumulate_batch", "npcf_finalize_batch", "npcf_reset", "npcf_destroy", "npcf_set_tuning",
-                 "npcf_stage_ms", "npcf_autotune", "npcf_accumulate_grid", "npcf_alm_grid"):
+                 "npcf_stage_ms", "npcf_autotune", "npcf_accumulate_grid", "npcf_alm_grid", "npcf_get_tuning",
+                 "npcf_apply_tuning"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -271,12 +279,24 @@ class NPCF:
                "npcf_set_tuning")
 
     def autotune(self, pos, w, sample: int = 8192):
-        """Pick the cell subdivision by timing a sample of primaries; the
-        coupling block size stays automatic (resets the accumulators)."""
+        """Tune the cell subdivision, the harmonic grid, the coupling block
+        size and the chunk rows on this catalogue (npcf_autotune; resets the
+        accumulators).  Returns every knob of the resulting tuning and the
+        timed ms."""
         cs, cb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(load_library().npcf_autotune(self._h, _dptr(pos), _dptr(w), int(w.shape[0]), int(sample),
                                             ctypes.byref(cs), ctypes.byref(cb), ctypes.byref(ms)), "npcf_autotune")
-        return {"cell_subdiv": cs.value, "couple_block": cb.value, "sample_ms": ms.value}
+        return self.tuning() | {"sample_ms": ms.value}
+
+    def tuning(self):
+        t = _Tuning()
+        _check(load_library().npcf_get_tuning(self._h, ctypes.byref(t)), "npcf_get_tuning")
+        return {"cell_subdiv": t.cell_subdiv, "couple_block": t.couple_block, "chunk_rows": t.chunk_rows,
+                "harmonic_blocks_per_cu": t.harmonic_blocks_per_cu}
+
+    def apply_tuning(self, cell_subdiv=0, couple_block=0, chunk_rows=0, harmonic_blocks_per_cu=0):
+        t = _Tuning(int(cell_subdiv), int(couple_block), int(chunk_rows), int(harmonic_blocks_per_cu))
+        _check(load_library().npcf_apply_tuning(self._h, ctypes.byref(t)), "npcf_apply_tuning")
 
     def reset(self):
         _check(load_library().npcf_reset(self._h), "npcf_reset")

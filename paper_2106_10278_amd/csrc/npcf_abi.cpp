@@ -102,6 +102,7 @@ struct npcf_plan_s {
     int D = 0, N = 0, L = 0, nb = 0;
     int cell_subdiv = 3;
     int couple_rows = 0;  // 0: automatic
+    int harm_bpc = 0;     // persistent harmonic grid: blocks per compute unit (0: automatic, 8)
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
@@ -324,10 +325,15 @@ hipError_t launch_harmonic(const npcf_plan_s *p, const HarmArgs &a, hipStream_t 
 {
     hipError_t e = launch_fill_u32(a.work, 0u, 1, s);
     if (e != hipSuccess) return e;
+    // persistent grid: blocks of 4 waves per CU (tuned, default 8), no more
+    // blocks than rows / 4; rows are handed out dynamically
+    int grid = p->ncu * (p->harm_bpc > 0 ? p->harm_bpc : 8);
+    const int64_t need = ((int64_t)a.nrows + 3) / 4;
+    if (grid > need) grid = (int)std::max<int64_t>(1, need);
     switch (p->D) {
-    case 2: return launch_harmonic_d2(p->L, a, p->ncu, s);
-    case 3: return launch_harmonic_d3(p->L, a, p->ncu, s);
-    default: return launch_harmonic_d4(p->L, a, p->ncu, s);
+    case 2: return launch_harmonic_d2(p->L, a, grid, s);
+    case 3: return launch_harmonic_d3(p->L, a, grid, s);
+    default: return launch_harmonic_d4(p->L, a, grid, s);
     }
 }
 
@@ -856,6 +862,113 @@ npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int
         if (st != NPCF_OK) return st;
     }
     return NPCF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner cache: a JSON file of tuned knobs keyed by the problem's shape
+//   {"npcf_tuning": 1, "entries": {"<key>": {"cell_subdiv": s, "couple_block": b,
+//    "chunk_rows": r, "harmonic_blocks_per_cu": g, "ms": t}, ...}}
+// ---------------------------------------------------------------------------
+std::string tune_key(const npcf_plan_s *p, int64_t n)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "D%d-N%d-L%d-nb%d-n%lld-box%.9g", p->D, p->N, p->L, p->nb, (long long)n,
+                  p->cfg.box[0]);
+    std::string k(buf);
+    for (int d = 1; d < p->D; d++) {
+        std::snprintf(buf, sizeof(buf), "x%.9g", p->cfg.box[d]);
+        k += buf;
+    }
+    std::snprintf(buf, sizeof(buf), "-rmax%.9g-prec%d-mode%d-basis%d-per%d-cu%d", p->edges[p->nb], p->cfg.precision,
+                  p->cfg.btuple_mode, p->cfg.basis, p->cfg.periodic, p->ncu);
+    return k + buf;
+}
+
+std::string read_file(const char *path)
+{
+    std::string out;
+    if (FILE *f = std::fopen(path, "rb")) {
+        char buf[4096];
+        size_t k;
+        while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) out.append(buf, k);
+        std::fclose(f);
+    }
+    return out;
+}
+
+// The entries of a cache file as (key, object text) pairs; malformed text gives none.
+std::vector<std::pair<std::string, std::string>> tune_cache_entries(const std::string &text)
+{
+    std::vector<std::pair<std::string, std::string>> out;
+    size_t at = text.find("\"entries\"");
+    if (at == std::string::npos) return out;
+    at = text.find('{', at);
+    if (at == std::string::npos) return out;
+    at++;
+    for (;;) {
+        const size_t k0 = text.find('"', at);
+        const size_t close = text.find('}', at);
+        if (k0 == std::string::npos || (close != std::string::npos && close < k0)) break;
+        const size_t k1 = text.find('"', k0 + 1);
+        const size_t o0 = text.find('{', k1);
+        const size_t o1 = text.find('}', o0);
+        if (k1 == std::string::npos || o0 == std::string::npos || o1 == std::string::npos) break;
+        out.push_back({text.substr(k0 + 1, k1 - k0 - 1), text.substr(o0, o1 - o0 + 1)});
+        at = o1 + 1;
+    }
+    return out;
+}
+
+double json_number(const std::string &obj, const char *field, double dflt)
+{
+    const std::string f = std::string("\"") + field + "\"";
+    size_t at = obj.find(f);
+    if (at == std::string::npos) return dflt;
+    at = obj.find(':', at);
+    if (at == std::string::npos) return dflt;
+    return std::strtod(obj.c_str() + at + 1, nullptr);
+}
+
+bool tune_cache_lookup(const char *path, const std::string &key, npcf_tuning &t, double &ms)
+{
+    for (const auto &e : tune_cache_entries(read_file(path))) {
+        if (e.first != key) continue;
+        t.cell_subdiv = (int)json_number(e.second, "cell_subdiv", 0);
+        t.couple_block = (int)json_number(e.second, "couple_block", 0);
+        t.chunk_rows = (int64_t)json_number(e.second, "chunk_rows", 0);
+        t.harmonic_blocks_per_cu = (int)json_number(e.second, "harmonic_blocks_per_cu", 0);
+        ms = json_number(e.second, "ms", 0.0);
+        return t.cell_subdiv > 0;
+    }
+    return false;
+}
+
+void tune_cache_store(const char *path, const std::string &key, const npcf_tuning &t, double ms)
+{
+    auto entries = tune_cache_entries(read_file(path));
+    char obj[256];
+    std::snprintf(obj, sizeof(obj),
+                  "{\"cell_subdiv\": %d, \"couple_block\": %d, \"chunk_rows\": %lld, \"harmonic_blocks_per_cu\": %d, "
+                  "\"ms\": %.6g}",
+                  t.cell_subdiv, t.couple_block, (long long)t.chunk_rows, t.harmonic_blocks_per_cu, ms);
+    bool found = false;
+    for (auto &e : entries) {
+        if (e.first == key) {
+            e.second = obj;
+            found = true;
+        }
+    }
+    if (!found) entries.push_back({key, obj});
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    std::fprintf(f, "{\"npcf_tuning\": 1, \"entries\": {\n");
+    for (size_t i = 0; i < entries.size(); i++)
+        std::fprintf(f, "  \"%s\": %s%s\n", entries[i].first.c_str(), entries[i].second.c_str(),
+                     i + 1 < entries.size() ? "," : "");
+    std::fprintf(f, "}}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
 }
 
 // ---------------------------------------------------------------------------
@@ -1514,6 +1627,26 @@ npcf_status npcf_finalize_batch(npcf_plan_t p, int cat, double *out, size_t out_
     return NPCF_OK;
 }
 
+npcf_status npcf_get_tuning(npcf_plan_t p, npcf_tuning *out)
+{
+    if (!p || !out) return NPCF_E_INVALID;
+    out->cell_subdiv = p->cell_subdiv;
+    out->couple_block = p->couple_rows;
+    out->chunk_rows = p->wk.rows_cap;
+    out->harmonic_blocks_per_cu = p->harm_bpc > 0 ? p->harm_bpc : 8;
+    return NPCF_OK;
+}
+
+npcf_status npcf_apply_tuning(npcf_plan_t p, const npcf_tuning *t)
+{
+    if (!p || !t) return NPCF_E_INVALID;
+    if (t->harmonic_blocks_per_cu < 0 || t->harmonic_blocks_per_cu > 32) return NPCF_E_INVALID;
+    npcf_status st = npcf_set_tuning(p, t->cell_subdiv, t->couple_block, t->chunk_rows);
+    if (st != NPCF_OK) return st;
+    if (t->harmonic_blocks_per_cu > 0) p->harm_bpc = t->harmonic_blocks_per_cu;
+    return NPCF_OK;
+}
+
 npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int64_t n, int64_t sample,
                           int *cell_subdiv, int *couple_block, double *best_ms)
 {
@@ -1526,17 +1659,33 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
         if (best_ms) *best_ms = 0.0;
         return NPCF_OK;
     }
+    const std::string key = tune_key(p, n);
+    const char *cache = std::getenv("NPCF_TUNE_CACHE");
+    npcf_tuning cached{};
+    double cached_ms = 0.0;
+    if (cache && *cache && tune_cache_lookup(cache, key, cached, cached_ms)) {
+        st = npcf_apply_tuning(p, &cached);
+        if (st != NPCF_OK) return st;
+        if (cell_subdiv) *cell_subdiv = p->cell_subdiv;
+        if (couple_block) *couple_block = p->couple_rows;
+        if (best_ms) *best_ms = cached_ms;
+        return npcf_reset(p);
+    }
     if (sample < 4) sample = 4;
     if (sample > n) sample = n;
-    // four primary ranges spread over the catalogue (data and randoms alike)
-    std::vector<std::pair<int64_t, int64_t>> ranges;
-    for (int k = 0; k < 4; k++) {
-        const int64_t a = n * k / 4, b = std::min<int64_t>(n, a + std::max<int64_t>(1, sample / 4));
-        if (a < b) ranges.push_back({a, b});
-    }
-    auto measure = [&](double &harm, double &coup) -> npcf_status {
-        double best_h = 1e300, best_c = 1e300;
-        for (int rep = 0; rep < 2; rep++) {  // best of two
+    // time the stages over primary ranges spread over the catalogue (data and
+    // randoms alike), best of two
+    auto spread = [&](int64_t per_range) {
+        std::vector<std::pair<int64_t, int64_t>> r;
+        for (int k = 0; k < 4; k++) {
+            const int64_t a = n * k / 4, b = std::min<int64_t>(n, a + std::max<int64_t>(1, per_range));
+            if (a < b) r.push_back({a, b});
+        }
+        return r;
+    };
+    auto measure = [&](const std::vector<std::pair<int64_t, int64_t>> &ranges, double &harm, double &coup) -> npcf_status {
+        double bh = 1e300, bc = 1e300;
+        for (int rep = 0; rep < 2; rep++) {
             npcf_status s2 = npcf_reset(p);
             if (s2 != NPCF_OK) return s2;
             for (auto &r : ranges) {
@@ -1546,23 +1695,26 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
             double ms3[3];
             s2 = npcf_stage_ms(p, ms3);
             if (s2 != NPCF_OK) return s2;
-            best_h = std::min(best_h, ms3[0] + ms3[2]);
-            best_c = std::min(best_c, ms3[1]);
+            bh = std::min(bh, ms3[0] + ms3[2]);
+            bc = std::min(bc, ms3[1]);
         }
-        harm = best_h;
-        coup = best_c;
+        harm = bh;
+        coup = bc;
         return NPCF_OK;
     };
+    const auto small = spread(sample / 4);
     double h = 0.0, c = 0.0;
-    st = measure(h, c);  // first launches (code loading) out of the way
+    st = measure(small, h, c);  // first launches (code loading) out of the way
     if (st != NPCF_OK) return st;
-    // cell subdivision: harmonic stage + cell list
+    // harmonic stage with its cell list, on the primary sample: the cell
+    // subdivision, then the persistent grid's blocks per CU
     int best_s = p->cell_subdiv;
     double best_h = 1e300;
-    for (int sdv = 1; sdv <= 6; sdv++) {
+    const int smax = p->D == 4 ? 4 : 6;
+    for (int sdv = 1; sdv <= smax; sdv++) {
         st = npcf_set_tuning(p, sdv, 0, 0);
         if (st != NPCF_OK) return st;
-        st = measure(h, c);
+        st = measure(small, h, c);
         if (st != NPCF_OK) return st;
         if (h < best_h) {
             best_h = h;
@@ -1571,26 +1723,63 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
     }
     st = npcf_set_tuning(p, best_s, 0, 0);
     if (st != NPCF_OK) return st;
-    // primaries per coupling block: the automatic size.  Timed on a sample,
-    // large blocks leave the machine partly idle where a full catalogue does
-    // not, so a sample cannot rank block sizes; the rule was measured at full
-    // size instead.
-    const int best_b = 0;
-    batch_release(p);
+    int best_g = 8;
+    for (int g : {2, 3, 4, 6, 8}) {
+        p->harm_bpc = g;
+        st = measure(small, h, c);
+        if (st != NPCF_OK) return st;
+        if (h < best_h * (g == 8 ? 1.0 : 0.98)) {   // a different grid must win by 2%
+            best_h = h;
+            best_g = g;
+        }
+    }
+    p->harm_bpc = best_g;
+    // coupling block size and chunk rows, on a quarter of the catalogue in four
+    // spread ranges: full-size row blocks, as many blocks as fill the GPU the
+    // way the whole catalogue does (a primary sample leaves large blocks idle)
+    const auto quarter = spread(std::max<int64_t>(sample / 4, n / 16));
+    int best_b = 0;
+    double best_c = 1e300, best_q = 1e300;
+    for (int b : {0, 256, 512, 1024, 2048}) {
+        batch_release(p);
+        p->couple_rows = b;
+        st = measure(quarter, h, c);
+        if (st != NPCF_OK) return st;
+        if (c < best_c * (b == 0 ? 1.0 : 0.98)) {   // the automatic rule unless 2% slower
+            best_c = c;
+            best_b = b;
+            best_q = h + c;
+        }
+    }
     p->couple_rows = best_b;
-    st = measure(h, c);
+    const int64_t full_rows = p->rows_cap_max;
+    int64_t best_r = full_rows;
+    for (int64_t r : {full_rows, std::max<int64_t>(1024, n / 32)}) {
+        if (r > full_rows || r == best_r) continue;
+        st = npcf_set_tuning(p, 0, 0, r);
+        if (st != NPCF_OK) return st;
+        st = measure(quarter, h, c);
+        if (st != NPCF_OK) return st;
+        if (h + c < 0.98 * best_q) {
+            best_q = h + c;
+            best_r = r;
+        }
+    }
+    st = npcf_set_tuning(p, 0, 0, best_r);
     if (st != NPCF_OK) return st;
-    const double best_c = c;
-    p->couple_rows = best_b;
     st = npcf_reset(p);
     if (st != NPCF_OK) return st;
+    if (cache && *cache) {
+        npcf_tuning t{};
+        (void)npcf_get_tuning(p, &t);
+        tune_cache_store(cache, key, t, best_h + best_c);
+    }
     if (cell_subdiv) *cell_subdiv = best_s;
     if (couple_block) *couple_block = best_b;
     if (best_ms) *best_ms = best_h + best_c;
     return NPCF_OK;
 }
 
-// Stage times (ms) accumulated since the last reset: [0] harmonic, [1] coupling + reduce, [2] cell list.
 npcf_status npcf_accumulate_static(npcf_plan_t p, const double *pos, const double *w, int64_t n, int64_t prim_begin,
                                    int64_t prim_end, int role)
 {
@@ -1618,6 +1807,7 @@ npcf_status npcf_accumulate_static(npcf_plan_t p, const double *pos, const doubl
     return st;
 }
 
+// Stage times (ms) accumulated since the last reset: [0] harmonic, [1] coupling + reduce, [2] cell list.
 npcf_status npcf_stage_ms(npcf_plan_t p, double *ms3)
 {
     if (!p || !ms3) return NPCF_E_INVALID;

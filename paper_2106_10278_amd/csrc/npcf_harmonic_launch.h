@@ -6,21 +6,11 @@
 namespace npcf {
 namespace harm {
 
-// persistent grid of the staging kernel: 8 blocks of 4 waves per CU, no more
-// blocks than rows / 4
-inline int stage_grid(int ncu, int nrows)
-{
-    int grid = ncu * 8;
-    const int64_t need = ((int64_t)nrows + 3) / 4;
-    if (grid > need) grid = (int)(need > 1 ? need : 1);
-    return grid;
-}
-
 template <int D, int L, int LMAX>
-hipError_t launch_l(int l, const HarmArgs &a, int ncu, hipStream_t s)
+hipError_t launch_l(int l, const HarmArgs &a, int grid, hipStream_t s)
 {
-    if (l == L) return launch_dl<D, L>(a, stage_grid(ncu, a.nrows), s);
-    if constexpr (L < LMAX) return launch_l<D, L + 1, LMAX>(l, a, ncu, s);
+    if (l == L) return launch_dl<D, L>(a, grid, s);
+    if constexpr (L < LMAX) return launch_l<D, L + 1, LMAX>(l, a, grid, s);
     return hipErrorInvalidValue;
 }
 

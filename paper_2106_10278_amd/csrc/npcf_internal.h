@@ -261,9 +261,9 @@ hipError_t launch_gather(int D, int64_t n, const int32_t *perm_sorted, uint32_t 
                          const double *w, uint4 *rec, float *ws, double *w64s, int32_t *orig, hipStream_t s);
 hipError_t launch_primlist(int64_t n, const int32_t *orig, int64_t p0, int64_t p1, uint32_t *flag,
                            uint32_t *pos_out, int32_t *prim, uint32_t *scratch, int64_t scratch_len, hipStream_t s);
-hipError_t launch_harmonic_d2(int L, const HarmArgs &a, int ncu, hipStream_t s);
-hipError_t launch_harmonic_d3(int L, const HarmArgs &a, int ncu, hipStream_t s);
-hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int ncu, hipStream_t s);
+hipError_t launch_harmonic_d2(int L, const HarmArgs &a, int grid, hipStream_t s);
+hipError_t launch_harmonic_d3(int L, const HarmArgs &a, int grid, hipStream_t s);
+hipError_t launch_harmonic_d4(int L, const HarmArgs &a, int grid, hipStream_t s);
 int harmonic_lds_bytes_d2(int L);
 int harmonic_lds_bytes_d3(int L);
 int harmonic_lds_bytes_d4(int L);

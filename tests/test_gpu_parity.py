@@ -261,11 +261,48 @@ def test_autotune_keeps_results():
     pos = torch.from_numpy(wl.pos).cuda()
     w = torch.from_numpy(wl.w).cuda()
     t = plan.autotune(pos, w, sample=256)
-    assert 1 <= t["cell_subdiv"] <= 6 and t["couple_block"] in (0, 64, 128, 256, 512, 1024) and t["sample_ms"] > 0
+    assert 1 <= t["cell_subdiv"] <= 6 and t["couple_block"] in (0, 256, 512, 1024, 2048) and t["sample_ms"] > 0
+    assert t["harmonic_blocks_per_cu"] in (2, 3, 4, 6, 8) and 1 <= t["chunk_rows"] <= 600
     got, pairs, _ = gpu_run(wl, plan=plan)
     ref, pairs_ref, _ = oracle_reported(wl)
     assert pairs == pairs_ref
-    _check(got, ref, "plain", condition_scale(wl), f"autotuned s={t['cell_subdiv']} b={t['couple_block']}", strict=False)
+    _check(got, ref, "plain", condition_scale(wl), f"autotuned {t}", strict=False)
+
+
+def test_autotune_cache(tmp_path, monkeypatch):
+    """NPCF_TUNE_CACHE: the first tuning is written to the JSON file under the
+    problem's key; a second plan for the same problem applies it without
+    timing; a different problem gets an entry of its own; results unchanged."""
+    import json
+    import torch
+    from paper_2106_10278_amd import NPCF
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("NPCF_TUNE_CACHE", str(cache))
+    wl = _case(3, 4, 3, 600, 52, 16.0, 4.5, 4)
+    print("[case] autotune cache", flush=True)
+    pos = torch.from_numpy(wl.pos).cuda()
+    w = torch.from_numpy(wl.w).cuda()
+    first = NPCF(3, 4, 3, wl.edges, wl.box, max_points=600)
+    t1 = first.autotune(pos, w, sample=256)
+    entries = json.load(open(cache))["entries"]
+    assert len(entries) == 1
+    (key, ent), = entries.items()
+    assert "D3-N4-L3-nb4-n600" in key
+    assert {k: ent[k] for k in ("cell_subdiv", "couple_block", "chunk_rows", "harmonic_blocks_per_cu")} == \
+        {k: t1[k] for k in ("cell_subdiv", "couple_block", "chunk_rows", "harmonic_blocks_per_cu")}
+    # a planted entry is what a second plan applies (proof that no timing ran)
+    ent.update(cell_subdiv=2, couple_block=512, harmonic_blocks_per_cu=3)
+    json.dump({"npcf_tuning": 1, "entries": {key: ent}}, open(cache, "w"))
+    second = NPCF(3, 4, 3, wl.edges, wl.box, max_points=600)
+    t2 = second.autotune(pos, w, sample=256)
+    assert (t2["cell_subdiv"], t2["couple_block"], t2["harmonic_blocks_per_cu"]) == (2, 512, 3)
+    got, pairs, _ = gpu_run(wl, plan=second)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    assert pairs == pairs_ref
+    _check(got, ref, "plain", condition_scale(wl), "cached tuning", strict=False)
+    other = NPCF(3, 4, 3, wl.edges, wl.box, precision="mixed_bf16x6", max_points=600)
+    other.autotune(pos, w, sample=256)
+    assert len(json.load(open(cache))["entries"]) == 2
 
 
 @pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6"])
