@@ -134,6 +134,8 @@ def make_workload(name: str):
         return inputs.c8_grid_4pcf()
     if name == "c9":
         return inputs.c9_sphere_4pcf()
+    if name == "c10":
+        return inputs.c10_s3_4pcf()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -186,7 +188,7 @@ def _sources_hash(files) -> str:
 
 
 def kernel_source_hash() -> str:
-    return _sources_hash(("npcf_harmonic_impl.h",))
+    return _sources_hash(("npcf_harmonic_impl.h", "npcf_harmonic_scan.h", "npcf_harmonics.h"))
 
 
 def load_traffic(key: str):
@@ -208,7 +210,26 @@ def coupling_source_hash() -> str:
     return _sources_hash(("npcf_couple.hip", "npcf_couple_common.h", "npcf_plan4.cpp"))
 
 
-def coupling_roofline(key: str, path: str, coupling_ms: float):
+def coupling_useful_flops(wl, labels) -> float | None:
+    """Algorithmic minimum of the factorised D = 3, N = 4 coupling per pass:
+    per primary, every term (l1, l2, l3, m1, m2) of every Lambda formed for
+    each radial pair b1 < b2 (a complex multiply-add, 8 flops), and every
+    (Lambda, m3) group contracted against a_{l3 m3}[b3] for each radial
+    triple (8 flops).  About 2.02e6 flops per primary at lmax 5 with 10 bins,
+    1.6e12 for the 800k primaries of the 4PCF workload."""
+    if wl.D != 3 or wl.N != 4 or wl.Lmax is not None:
+        return None
+    nb = len(wl.edges) - 1
+    terms = groups = 0
+    for l1, l2, l3 in (tuple(int(x) for x in r[:3]) for r in labels):
+        groups += 2 * l3 + 1
+        terms += sum(1 for m1 in range(-l1, l1 + 1) for m2 in range(-l2, l2 + 1) if abs(m1 + m2) <= l3)
+    pairs = nb * (nb - 1) // 2
+    triples = nb * (nb - 1) * (nb - 2) // 6
+    return 8.0 * (terms * pairs + groups * triples) * wl.pos.shape[1]
+
+
+def coupling_roofline(key: str, path: str, coupling_ms: float, useful=None):
     """MFMA flops per coupling launch from a committed rocprofv3 counter run
     (taken on the current coupling source), over the live coupling-stage time
     of this run (which also holds the 0.5 ms FP64 reduction of partials)."""
@@ -225,19 +246,29 @@ def coupling_roofline(key: str, path: str, coupling_ms: float):
     if not e:
         return None
     achieved = e["mfma_flops"] / (coupling_ms * 1e-3)
-    return {"kernel": "k_couple4f", "bound": "mfma", "dtype": e["mfma_dtype"], "achieved": achieved / 1e12,
-            "peak": e["peak"] / 1e12, "unit": "TFLOP/s", "frac": achieved / e["peak"], "mfma_flops": e["mfma_flops"],
-            "stage_ms": coupling_ms, "source": d.get("source")}
+    out = {"kernel": "k_couple4f", "bound": "mfma", "dtype": e["mfma_dtype"], "achieved": achieved / 1e12,
+           "peak": e["peak"] / 1e12, "unit": "TFLOP/s", "frac": achieved / e["peak"], "mfma_flops": e["mfma_flops"],
+           "stage_ms": coupling_ms, "source": d.get("source")}
+    if useful:
+        # the algorithmic minimum over the same time: against the path's MFMA
+        # peak and against the FP32 vector peak (S formation runs there)
+        u = useful / (coupling_ms * 1e-3)
+        out.update(useful_flops=useful, useful_achieved=u / 1e12, useful_frac=u / e["peak"],
+                   useful_frac_fp32_vector=u / FP32_VECTOR_PEAK)
+    return out
 
 
-def sphere_flops(L: int, visited: float, pairs: float) -> float:
+def sphere_flops(D: int, L: int, visited: float, pairs: float) -> float:
     """FP32-equivalent operations of the sphere harmonic stage (FP64 counted
     twice, the FP64 vector peak being half the FP32 one): every visited pair
-    takes an FP64 dot product (5) for its bin; an in-range pair adds two FP64
-    tangent projections (10), the squared norm (3) and its reciprocal square
-    root, then the D = 2 harmonics and their accumulation (6 per azimuthal
-    step, 2 per real output)."""
-    return 10.0 * visited + (2 * (10 + 3) + 1 + 6 * L + 2 * (2 * L + 1)) * pairs
+    takes an FP64 dot product of the D + 1 coordinates (2D + 1 operations) for
+    its bin; an in-range pair adds D FP64 tangent projections (2D + 1 each),
+    the squared norm (2D - 1) and its reciprocal square root, then the
+    harmonics and their accumulation as flops_per_pair counts them past the
+    geometry (D = 2: 6 per azimuthal step, 2 per real output)."""
+    geo_flat = D + D + (2 * D - 1) + 1 + D
+    harm = flops_per_pair(D, L) - geo_flat
+    return 2.0 * (2 * D + 1) * visited + (2 * (D * (2 * D + 1) + (2 * D - 1)) + 1 + harm) * pairs
 
 
 def grid_stage_bytes(wl) -> float:
@@ -392,8 +423,10 @@ def main():
                     Lmax=wl.Lmax, sphere=wl.sphere)
 
     results = {}
+    plan_labels = None
     for prec in args.precisions.split(","):
         plan = factory(prec)
+        plan_labels = plan.lambda_labels
         if args.tuning:
             sdv, blk = (int(x) for x in args.tuning.split(","))
             plan.set_tuning(cell_subdiv=sdv, couple_block=blk)
@@ -439,7 +472,7 @@ def main():
             "launch_ms": r["harmonic_ms_per_launch"]}
     if wl.sphere:
         # every pair is visited (no cell list): count the bin test of all of them
-        fl = sphere_flops(wl.lmax, float(n) * n, r["pairs_per_step"])
+        fl = sphere_flops(wl.D, wl.lmax, float(n) * n, r["pairs_per_step"])
         ach = fl / (r["harmonic_ms_per_launch"] * 1e-3)
         roof = {"kernel": "k_sphere", "bound": "alu", "achieved": ach / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK, "traffic": None,
@@ -464,11 +497,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": key, "n_points": n, "n_data": wl.n_data, "D": wl.D, "N": wl.N, "lmax": wl.lmax,
                    "nbins": len(wl.edges) - 1, "r_range": [float(wl.edges[0]), float(wl.edges[-1])],
-                   "box": float(wl.box[0]), "geometry": "unit 2-sphere" if wl.sphere else "flat",
+                   "box": float(wl.box[0]), "geometry": f"unit {wl.D}-sphere" if wl.sphere else "flat",
                    "parallelism": "single GPU"},
         "paths": results,
         "roofline": roof,
-        "coupling_roofline": coupling_roofline(key, head, r["stage_ms_per_step"]["coupling"]),
+        "coupling_roofline": coupling_roofline(key, head, r["stage_ms_per_step"]["coupling"],
+                                               coupling_useful_flops(wl, plan_labels)),
         "cpu_baseline": cpu,
         "parity_vs_oracle": errs,
         "batch": batch,

@@ -87,15 +87,23 @@ typedef enum {
 
 typedef enum {
     NPCF_GEOMETRY_FLAT = 0,      /* flat box (periodic or open) */
-    NPCF_GEOMETRY_SPHERE = 1     /* points on the unit 2-sphere (section "Cosmic Microwave Background"):
-                                    D = 2, N = 3 or 4, isotropic basis, lmax <= 5; positions are unit
-                                    vectors in R^3 (pos [3][n]); edges are great-circle angles in
-                                    radians, 0 < edges[0], edges[nbins] <= pi, bins e_b <= theta <
-                                    e_{b+1} decided on the FP64 dot product; the direction of a
-                                    secondary is its angle in the tangent frame e1 = unit(z x p)
-                                    (unit(x x p) when |p_z| > 0.9), e2 = p x e1 at the primary p;
-                                    v_b = 2 pi (cos e_b - cos e_{b+1}), V = 4 pi; box and periodic
-                                    are ignored; every secondary is visited (no cell list) */
+    NPCF_GEOMETRY_SPHERE = 1     /* points on the unit D-sphere, the constant-curvature space of section
+                                    "Constant-Curvature Metric" with k = 1, chi(r) = sin r (eq. metric):
+                                    D = 2 (the sky of section "Cosmic Microwave Background") or D = 3,
+                                    N = 3 or 4, isotropic basis, lmax <= 5; positions are unit vectors
+                                    in R^{D+1} (pos [D+1][n]); edges are geodesic angles in radians,
+                                    0 < edges[0] with cos(edges[0]) < 1 - 1e-12 (so the self pair is
+                                    in no bin), edges[nbins] <= pi; bins e_b <= theta < e_{b+1}
+                                    decided on the FP64 dot product; the direction of a secondary is
+                                    its tangent component at the primary p in the frame
+                                    D = 2: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
+                                    D = 3: e1, e2, e3 = p i, p j, p k for p = a + b i + c j + d k, i.e.
+                                    (-b, a, d, -c), (-c, -d, a, b), (-d, c, -b, a);
+                                    v_b = |S^{D-1}| int_{e_b}^{e_{b+1}} sin^{D-1} r dr:
+                                    D = 2: 2 pi (cos e_b - cos e_{b+1}), V = 4 pi;
+                                    D = 3: 2 pi (d - cos(e_b + e_{b+1}) sin d), d = e_{b+1} - e_b,
+                                    V = 2 pi^2; box and periodic are ignored; every secondary is
+                                    visited (no cell list) */
 } npcf_geometry;
 
 typedef struct {

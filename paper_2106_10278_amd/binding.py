@@ -156,7 +156,7 @@ class NPCF:
         # Lmax given: the line-of-sight basis P^{0L}_{l1 l2} (D = 3, N = 3)
         cfg.basis = 0 if Lmax is None else 1
         cfg.Lmax = 0 if Lmax is None else int(Lmax)
-        # points on the unit 2-sphere (D = 2): pos [3][n] unit vectors, edges in radians
+        # points on the unit D-sphere (D = 2 or 3): pos [D + 1][n] unit vectors, edges in radians
         cfg.geometry = 1 if sphere else 0
         if stream is None:
             import torch

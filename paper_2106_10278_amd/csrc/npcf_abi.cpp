@@ -476,7 +476,7 @@ npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const do
         npcf_status st = timer_begin(p, 0, t);
         if (st != NPCF_OK) return st;
     }
-    NPCF_TRY(launch_sphere(p->L, a, p->stream));
+    NPCF_TRY(launch_sphere(p->D, p->L, a, p->stream));
     if (W.timed) {
         NPCF_TRY(hipEventRecord(t.b, p->stream));
         p->timers[0].push_back(t);

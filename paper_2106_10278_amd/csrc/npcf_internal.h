@@ -221,15 +221,15 @@ struct GridArgs {
 // ---------------------------------------------------------------------------
 constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
 struct SphereArgs {
-    const double *pos;          // [3][n] unit vectors
+    const double *pos;          // [D + 1][n] unit vectors
     const double *w;            // [n]
-    float4 *pf;                 // scratch [n]: (x, y, z, w) in FP32, written by launch_sphere
+    float4 *pf;                 // scratch [n]: S^2 (x, y, z, w), S^3 the coordinates, in FP32, written by launch_sphere
     int64_t n;
     int64_t p0;                 // primary of row 0
     int rows;
     int nb;
     double cedge[kMaxBins + 1]; // cos of the edges (decreasing)
-    float *A;                   // out: [rows][nb][2 (L + 1)]
+    float *A;                   // out: [rows][nb][2 nstate]
     float *wrow;                // out: [rows]
     unsigned long long *pairs;  // in-range pair counter
 };
@@ -289,7 +289,7 @@ hipError_t launch_grid_weights(const double *field, int64_t ng, double dV, doubl
 hipError_t launch_grid_rows(const double2 *a, int64_t ng, int nbs, int nst, const uint8_t *sreal, const float *w32,
                             int64_t r0, int rows, float *A, float *wrow, hipStream_t s);
 hipError_t launch_add_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
-hipError_t launch_sphere(int L, const SphereArgs &a, hipStream_t s);
+hipError_t launch_sphere(int D, int L, const SphereArgs &a, hipStream_t s);
 // finalize from an accumulator index per output (N = 5): out[lam * nbt + t] =
 // acc[idx[lam * nbt + t]] * sign[lam] * bt_scale[t] (optionally over the randoms' Lambda = 0)
 hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,

@@ -85,9 +85,12 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     if (cfg.geometry != NPCF_GEOMETRY_FLAT && cfg.geometry != NPCF_GEOMETRY_SPHERE) { err = "unknown geometry"; return NPCF_E_INVALID; }
     t.sphere = cfg.geometry == NPCF_GEOMETRY_SPHERE;
     if (t.sphere) {
-        if (D != 2 || N > 4 || cfg.basis != NPCF_BASIS_ISOTROPIC) { err = "the sphere needs D = 2, N = 3 or 4 and the isotropic basis"; return NPCF_E_UNSUPPORTED; }
+        if ((D != 2 && D != 3) || N > 4 || cfg.basis != NPCF_BASIS_ISOTROPIC) { err = "the sphere needs D = 2 or 3, N = 3 or 4 and the isotropic basis"; return NPCF_E_UNSUPPORTED; }
         if (L > kLmaxSphere) { err = "lmax above 5 on the sphere"; return NPCF_E_UNSUPPORTED; }
         if (!(cfg.edges[nb] <= M_PI)) { err = "sphere edges must not exceed pi"; return NPCF_E_INVALID; }
+        // bins are decided on cosines: the self pair (p.p = 1 up to rounding)
+        // must lie outside the innermost edge
+        if (!(std::cos(cfg.edges[0]) < 1.0 - 1e-12)) { err = "sphere edges[0] too small: cos(edges[0]) must be below 1 - 1e-12"; return NPCF_E_INVALID; }
     } else {
         for (int k = 0; k < D; k++) {
             if (!(cfg.box[k] > 0.0) || !std::isfinite(cfg.box[k])) { err = "box sides must be positive"; return NPCF_E_INVALID; }
@@ -227,11 +230,20 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     double VD = 1.0;
     for (int k = 0; k < D; k++) VD *= cfg.box[k];
     if (t.sphere) {
-        // annulus areas on the unit sphere, and its area as the volume
+        // bin volumes |S^{D-1}| int sin^{D-1} r dr and the sphere's volume
         t.cedge.resize(nb + 1);
         for (int b = 0; b <= nb; b++) t.cedge[b] = std::cos(cfg.edges[b]);
-        for (int b = 0; b < nb; b++) t.vb[b] = 2.0 * M_PI * (t.cedge[b] - t.cedge[b + 1]);
-        VD = 4.0 * M_PI;
+        for (int b = 0; b < nb; b++) {
+            if (D == 2) {
+                t.vb[b] = 2.0 * M_PI * (t.cedge[b] - t.cedge[b + 1]);
+            } else {
+                // 4 pi int sin^2 = 2 pi (d - (sin 2 e1 - sin 2 e0) / 2), with the
+                // difference of sines as 2 cos(e0 + e1) sin d
+                const double d = cfg.edges[b + 1] - cfg.edges[b];
+                t.vb[b] = 2.0 * M_PI * (d - std::cos(cfg.edges[b] + cfg.edges[b + 1]) * std::sin(d));
+            }
+        }
+        VD = D == 2 ? 4.0 * M_PI : 2.0 * M_PI * M_PI;
     }
     t.bt_scale.resize(t.nbt);
     for (int i = 0; i < t.nbt; i++) {

@@ -1,26 +1,33 @@
-// Harmonic stage for points on the unit 2-sphere (section "Cosmic Microwave
-// Background"): D = 2 harmonics of the direction of each secondary in a
-// tangent frame at the primary, binned in great-circle angle,
-//   a^b_l(p) = sum_q w_q conj(Y_l(phi_pq)) Theta^b(theta_pq)
+// Harmonic stage for points on the unit D-sphere, the constant-curvature
+// space of section "Constant-Curvature Metric" with k = 1 and chi(r) = sin r
+// (eq. metric): D = 2 is the unit 2-sphere of section "Cosmic Microwave
+// Background", D = 3 the unit 3-sphere.  The radial coordinate of a pair is
+// the geodesic angle theta_pq, the direction that of q in an orthonormal
+// tangent frame at p, and
+//   a^b_[l](p) = sum_q w_q conj(Y_[l](u_pq)) Theta^b(theta_pq)
 // (1/v_b at finalize, as on the flat path), for every secondary q: the bins of
 // the paper's CMB test reach 120 degrees, so a cell list would prune little.
 //  - theta: e_b <= theta < e_{b+1}  <=>  cos e_{b+1} < p.q <= cos e_b, on an
 //    FP64 dot product evaluated without contraction (the comparison matches a
 //    plain FP64 evaluation bit for bit);
-//  - frame: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
-//    (cos phi, sin phi) = (q.e1, q.e2) / |(q.e1, q.e2)|.
+//  - frame, D = 2: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
+//    D = 3, p = a + b i + c j + d k a unit quaternion: e1, e2, e3 = p i, p j,
+//    p k, i.e. (-b, a, d, -c), (-c, -d, a, b), (-d, c, -b, a), orthonormal,
+//    orthogonal to p and positively oriented everywhere;
+//    u = (q.e1, .., q.eD) / |(q.e1, .., q.eD)|.
 // A block is 8 waves, one primary each; secondaries come through LDS in FP32
 // tiles (the points are packed to FP32 once per launch).  The FP32 cosine
 // decides the bin (through a bucket table where no edge is near, else against
 // the edge cosines) unless it lies within 1e-6 of an edge (its error is below
-// 4e-7), where the FP64 dot product decides, so the decisions equal the FP64
-// ones.  In-range pairs are queued by catalogue index; the harmonics take the
-// tangent components from the FP64 positions in an FP64 frame, normalised in
-// FP64 and rounded once to FP32.  As many bins as fit about 50 registers
-// are taken per pass (more passes rescan the points, but fewer registers let
-// four waves share a SIMD and each queued pair feeds fewer masked sums); each
-// lane sums harmonics in FP32 (a 0/1 mask per bin) and every few tiles the
-// wave reduces its lanes into FP64 values held one or two per lane.
+// (D + 3) 2^-24 < 4e-7 for unit vectors), where the FP64 dot product decides, so the decisions
+// equal the FP64 ones.  In-range pairs are queued by catalogue index; the
+// harmonics take the tangent components from the FP64 positions in an FP64
+// frame, normalised in FP64 and rounded once to FP32.  As many bins as fit a
+// register budget are taken per pass (more passes rescan the points, but
+// fewer registers let more waves share a SIMD and each queued pair feeds
+// fewer masked sums); each lane sums harmonics in FP32 (a 0/1 mask per bin)
+// and every few tiles the wave reduces its lanes into FP64 values held one or
+// two per lane.
 #include "npcf_internal.h"
 #include "npcf_harmonics.h"
 
@@ -33,16 +40,60 @@ constexpr int kSphWaves = 8;
 constexpr int kSphFold = 4;         // tiles between folds of the lanes' FP32 sums
 constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64
 
-// bins per pass: as many as keep the lanes' FP32 sums within kSphRegBudget registers
-constexpr int kSphRegBudget = 50;
-__host__ __device__ constexpr int sph_group(int L)
+// real slots per bin: 2 per stored state (the imaginary slots of real states stay 0)
+__host__ __device__ constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * (L + 2); }
+
+// bins per pass: as many as keep the lanes' FP32 sums within the register
+// budget (50 on S^2; 128 on S^3, whose 42 slots per bin at lmax 5 would
+// otherwise take one bin per pass: three bins per pass there ran faster at
+// two waves per SIMD than one or two bins at three or four), at least 1, at
+// most 16, and at most 128 values in all (two per lane after the fold)
+__host__ __device__ constexpr int sph_group(int D, int L)
 {
-    return (kSphRegBudget / (2 * (L + 1))) < 16 ? (kSphRegBudget / (2 * (L + 1))) : 16;
+    const int budget = D == 2 ? 50 : 128;
+    const int g = budget / sph_slots(D, L);
+    const int g1 = g < 1 ? 1 : (g > 16 ? 16 : g);
+    return g1 * sph_slots(D, L) <= 128 ? g1 : 128 / sph_slots(D, L);
 }
 
-__device__ __forceinline__ double dot3_rn(double ax, double ay, double az, double bx, double by, double bz)
+// p.q in FP64, left to right with every product and sum rounded (no contraction)
+template <int D>
+__device__ __forceinline__ double dot_rn(const double (&p)[D + 1], const double *pos, int64_t n, int64_t k)
 {
-    return __dadd_rn(__dadd_rn(__dmul_rn(ax, bx), __dmul_rn(ay, by)), __dmul_rn(az, bz));
+    double c = __dmul_rn(p[0], pos[k]);
+#pragma unroll
+    for (int x = 1; x <= D; x++) c = __dadd_rn(c, __dmul_rn(p[x], pos[x * n + k]));
+    return c;
+}
+
+// Orthonormal tangent frame at the unit vector p (rows e[0..D-1]), see the header.
+template <int D>
+__device__ __forceinline__ void tangent_frame(const double (&p)[D + 1], double (&e)[D][D + 1])
+{
+    if constexpr (D == 2) {
+        double ax = 0.0, ay = 0.0, az = 1.0;
+        if (fabs(p[2]) > 0.9) {
+            ax = 1.0;
+            az = 0.0;
+        }
+        double e1x = ay * p[2] - az * p[1], e1y = az * p[0] - ax * p[2], e1z = ax * p[1] - ay * p[0];
+        const double inn = 1.0 / sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+        e1x *= inn;
+        e1y *= inn;
+        e1z *= inn;
+        e[0][0] = e1x;
+        e[0][1] = e1y;
+        e[0][2] = e1z;
+        e[1][0] = p[1] * e1z - p[2] * e1y;
+        e[1][1] = p[2] * e1x - p[0] * e1z;
+        e[1][2] = p[0] * e1y - p[1] * e1x;
+    } else {
+        // right products of p = (a, b, c, d) with the quaternion units i, j, k
+        const double qa = p[0], qb = p[1], qc = p[2], qd = p[3];
+        e[0][0] = -qb; e[0][1] = qa;  e[0][2] = qd;  e[0][3] = -qc;
+        e[1][0] = -qc; e[1][1] = -qd; e[1][2] = qa;  e[1][3] = qb;
+        e[2][0] = -qd; e[2][1] = qc;  e[2][2] = -qb; e[2][3] = qa;
+    }
 }
 
 #define NPCF_SPH_WAVE_SYNC()                                   \
@@ -109,14 +160,14 @@ __device__ __forceinline__ void fold_lanes(const float *x, int lane, float &y0, 
     y1 = x0[1];
 }
 
-template <int L>
+template <int D, int L>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
     __shared__ float4 tile[kSphTile];
     // per wave: in-range pairs waiting for the harmonics (catalogue index,
-    // weight, bin)
+    // weight (S^2; the FP64 weight is read at the harmonics on S^3), bin)
     __shared__ int qidx[kSphWaves][128];
-    __shared__ float qw[kSphWaves][128];
+    __shared__ float qw[kSphWaves][D == 2 ? 128 : 1];
     __shared__ int qbin[kSphWaves][128];
     // the pass's edge cosines (FP32) and a bucket table over its cosine range.
     // Entry k is the bin of every cosine in bucket k when no edge, widened by
@@ -128,27 +179,19 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     constexpr int kBuckets = 8192;
     __shared__ float sce[kMaxBins + 1];
     __shared__ unsigned char sbk[kBuckets];
-    constexpr int NV = 2 * (L + 1);   // real slots per bin (slot 1, the l = 0 imaginary part, stays 0)
-    constexpr int G = sph_group(L);
-    constexpr int NG = G * NV;        // values per pass, <= 50 (L <= 5): lane j keeps value j in FP64
+    constexpr int NV = sph_slots(D, L);
+    constexpr int G = sph_group(D, L);
+    constexpr int NG = G * NV;        // values per pass, <= 128: lane j keeps values j and j + 64 in FP64
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * kSphWaves + wave;
     const bool active = row < a.rows;
     const int64_t pi = a.p0 + (active ? row : 0);
-    const double px = a.pos[pi], py = a.pos[a.n + pi], pz = a.pos[2 * a.n + pi];
-    // tangent frame at p
-    double ax = 0.0, ay = 0.0, az = 1.0;
-    if (fabs(pz) > 0.9) {
-        ax = 1.0;
-        az = 0.0;
-    }
-    double e1x = ay * pz - az * py, e1y = az * px - ax * pz, e1z = ax * py - ay * px;
-    const double inn = 1.0 / sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
-    e1x *= inn;
-    e1y *= inn;
-    e1z *= inn;
-    const double e2x = py * e1z - pz * e1y, e2y = pz * e1x - px * e1z, e2z = px * e1y - py * e1x;
-    const float pxf = (float)px, pyf = (float)py, pzf = (float)pz;
+    double p[D + 1];
+#pragma unroll
+    for (int x = 0; x <= D; x++) p[x] = a.pos[x * a.n + pi];
+    double e[D][D + 1];
+    tangent_frame<D>(p, e);
+    float pf32[4] = {(float)p[0], (float)p[1], (float)p[2], D == 3 ? (float)p[D] : 0.f};
 
     unsigned long long cnt_pairs = 0;   // wave-uniform
     for (int b0 = 0; b0 < a.nb; b0 += G) {
@@ -172,11 +215,11 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             bool edge = false;
             int b = 0, bg = 0;
             for (int g = 0; g <= ng; g++) {
-                const double e = a.cedge[b0 + g];
-                edge = edge || (e >= lo && e <= hi);
+                const double ec = a.cedge[b0 + g];
+                edge = edge || (ec >= lo && ec <= hi);
                 if (g >= 1 && g < ng) {
-                    b += mid <= e;
-                    bg += ck <= (float)e;
+                    b += mid <= ec;
+                    bg += ck <= (float)ec;
                 }
             }
             sbk[k] = (unsigned char)(edge ? (0x80 | bg) : b);
@@ -188,35 +231,43 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         auto process = [&](int cnt) {
             const bool live = lane < cnt;
             const int k = live ? qidx[wave][lane] : 0;
-            const float wq = live ? qw[wave][lane] : 0.f;
             const int bl = live ? qbin[wave][lane] : 0;
             // tangent components from the FP64 positions and frame, normalised
             // in FP64 and rounded once to FP32 (each rounding of the direction
             // enters the l-th harmonic about l times)
-            double qx = 0.0, qy = 0.0, qz = 0.0;
-            if (live) {
-                qx = a.pos[k];
-                qy = a.pos[a.n + k];
-                qz = a.pos[2 * a.n + k];
+            double q[D + 1];
+#pragma unroll
+            for (int x = 0; x <= D; x++) q[x] = live ? a.pos[x * a.n + k] : 0.0;
+            float wq = 0.f;
+            if constexpr (D == 2) wq = live ? qw[wave][lane] : 0.f;
+            else wq = live ? (float)a.w[k] : 0.f;
+            double t[D];
+            double tn2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                double tc = q[0] * e[c][0];
+#pragma unroll
+                for (int x = 1; x <= D; x++) tc += q[x] * e[c][x];
+                t[c] = tc;
+                tn2 += tc * tc;
             }
-            const double t1 = qx * e1x + qy * e1y + qz * e1z;
-            const double t2 = qx * e2x + qy * e2y + qz * e2z;
-            const double tn2 = t1 * t1 + t2 * t2;
             const bool ok = live && tn2 > 0.0;
             const double ts = ok ? tn2 : 1.0;
             double itn = __builtin_amdgcn_rsq(ts);
             itn = itn * (1.5 - 0.5 * ts * itn * itn);
-            const float u[2] = {ok ? (float)(t1 * itn) : 0.f, ok ? (float)(t2 * itn) : 0.f};
+            float u[D];
+#pragma unroll
+            for (int c = 0; c < D; c++) u[c] = ok ? (float)(t[c] * itn) : 0.f;
             cnt_pairs += __popcll(__builtin_amdgcn_ballot_w64(ok));
-            float hv[NV];
-            hv[1] = 0.f;   // l = 0 is real
-            harm::harmonics<2, L>(u, ok ? wq : 0.f, [&](int slot, float v) { hv[slot] = v; });
+            // every emitted value straight into the masked bin sums (slots never
+            // emitted, the imaginary parts of real states, keep their zeros)
+            float m[G];
 #pragma unroll
-            for (int g = 0; g < G; g++) {
-                const float m = (ok && g == bl) ? 1.f : 0.f;
+            for (int g = 0; g < G; g++) m[g] = (ok && g == bl) ? 1.f : 0.f;
+            harm::harmonics<D, L>(u, ok ? wq : 0.f, [&](int slot, float v) {
 #pragma unroll
-                for (int v = 0; v < NV; v++) fs[g][v] = fmaf(m, hv[v], fs[g][v]);
-            }
+                for (int g = 0; g < G; g++) fs[g][slot] = fmaf(m[g], v, fs[g][slot]);
+            });
         };
         for (int64_t t0 = 0; t0 < a.n; t0 += kSphTile) {
             const int cnt_t = (int)(a.n - t0 < kSphTile ? a.n - t0 : kSphTile);
@@ -232,7 +283,8 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (i < cnt_t) {
                         q = tile[i];
-                        const float c32 = pxf * q.x + pyf * q.y + pzf * q.z;
+                        float c32 = pf32[0] * q.x + pf32[1] * q.y + pf32[2] * q.z;
+                        if constexpr (D == 3) c32 += pf32[3] * q.w;
                         // range prefilter on the same FP32 differences as the guard
                         // test below, so that a cosine admitted beyond an outer edge
                         // is always within the guard of it and decided in FP64
@@ -254,8 +306,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                                 near = fabsf(c32 - sce[bl]) <= kSphGuard || fabsf(c32 - sce[bl + 1]) <= kSphGuard;
                             }
                             if (near) {
-                                const int64_t k = t0 + i;
-                                const double c = dot3_rn(px, py, pz, a.pos[k], a.pos[a.n + k], a.pos[2 * a.n + k]);
+                                const double c = dot_rn<D>(p, a.pos, a.n, t0 + i);
                                 valid = c <= chi && c > clo;
                                 bl = 0;
                                 while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
@@ -267,7 +318,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
                     if (valid) {
                         qidx[wave][slot] = (int)(t0 + i);
-                        qw[wave][slot] = q.w;
+                        if constexpr (D == 2) qw[wave][slot] = q.w;
                         qbin[wave][slot] = bl;
                     }
                     qn += __popcll(vm);
@@ -280,13 +331,13 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         float mw = 0.f;
                         if (lane < rest) {
                             mi = qidx[wave][64 + lane];
-                            mw = qw[wave][64 + lane];
+                            if constexpr (D == 2) mw = qw[wave][64 + lane];
                             mb = qbin[wave][64 + lane];
                         }
                         NPCF_SPH_WAVE_SYNC();
                         if (lane < rest) {
                             qidx[wave][lane] = mi;
-                            qw[wave][lane] = mw;
+                            if constexpr (D == 2) qw[wave][lane] = mw;
                             qbin[wave][lane] = mb;
                         }
                         qn = rest;
@@ -329,36 +380,48 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     }
 }
 
-// the points in FP32 (x, y, z, w), once per launch: every block streams
-// them all in every pass
+// the points in FP32, once per launch: every block streams them all in every
+// pass.  S^2: (x, y, z, w); S^3: the four coordinates.
+template <int D>
 __global__ __launch_bounds__(256) void k_sphere_pack(const double *pos, const double *w, int64_t n, float4 *pf)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) pf[i] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i], (float)w[i]);
+    if (i < n)
+        pf[i] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i],
+                            D == 2 ? (float)w[i] : (float)pos[3 * n + i]);
 }
 
-template <int L>
+template <int D, int L>
 hipError_t launch_l(const SphereArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sphere_pack, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n, a.pf);
+    hipLaunchKernelGGL(k_sphere_pack<D>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n, a.pf);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
-    hipLaunchKernelGGL(k_sphere<L>, dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
+    hipLaunchKernelGGL((k_sphere<D, L>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
     return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_d(int L, const SphereArgs &a, hipStream_t s)
+{
+    switch (L) {
+    case 0: return launch_l<D, 0>(a, s);
+    case 1: return launch_l<D, 1>(a, s);
+    case 2: return launch_l<D, 2>(a, s);
+    case 3: return launch_l<D, 3>(a, s);
+    case 4: return launch_l<D, 4>(a, s);
+    case 5: return launch_l<D, 5>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_sphere(int L, const SphereArgs &a, hipStream_t s)
+hipError_t launch_sphere(int D, int L, const SphereArgs &a, hipStream_t s)
 {
-    switch (L) {
-    case 0: return launch_l<0>(a, s);
-    case 1: return launch_l<1>(a, s);
-    case 2: return launch_l<2>(a, s);
-    case 3: return launch_l<3>(a, s);
-    case 4: return launch_l<4>(a, s);
-    case 5: return launch_l<5>(a, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (a.n <= 0 || a.rows <= 0) return hipSuccess;
+    if (D == 2) return launch_d<2>(L, a, s);
+    if (D == 3) return launch_d<3>(L, a, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace npcf

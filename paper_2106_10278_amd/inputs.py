@@ -22,6 +22,9 @@ turbulence simulations); none of those data sets is used.  Recipes:
   P(k) ~ k^slope (random phases, unit variance), mapped to a log-normal
   contrast X = exp(sigma g - sigma^2 / 2) - 1, as a stand-in for the density
   of a turbulence simulation.
+* ``sphere_points`` / ``s3_points`` -- n points uniform on the unit 2- or
+  3-sphere (normalised Gaussian vectors); ``clustered_sphere`` -- Gaussian
+  blobs projected onto the sphere plus a uniform background.
 * ``vorticity_tracers`` (D = 2) -- points drawn with density proportional to
   exp(omega) for a random-phase field omega on a grid, whose per-mode
   amplitude falls as 1/|k| (shell energy spectrum ~ k^-3), normalised to
@@ -119,7 +122,7 @@ class Workload:
     note: str = ""
     Lmax: object = None      # line-of-sight basis (D = 3, N = 3): largest L; None: isotropic
     field: object = None     # gridded data: the field on the grid (pos and w are then its nodes)
-    sphere: bool = False     # points on the unit 2-sphere: pos [3][n] unit vectors, edges in radians
+    sphere: bool = False     # points on the unit D-sphere: pos [D + 1][n] unit vectors, edges in radians
 
 
 def c1_small_3pcf(seed: int = 1001) -> Workload:
@@ -260,3 +263,38 @@ def c9_sphere_4pcf(seed: int = 1009, n: int = 100_000) -> Workload:
     pos = sphere_points(rng, n)
     edges = np.arccos(np.linspace(0.5, -0.5, 11))
     return Workload(f"S2-N4-uniform-{n // 1000}k", 2, 4, 4, edges, [1.0, 1.0], pos, np.ones(n), n, sphere=True)
+
+
+def s3_points(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n points uniform on the unit 3-sphere: unit vectors [4][n] (normalised
+    Gaussian quadruples)."""
+    x = rng.normal(size=(4, n))
+    return x / np.linalg.norm(x, axis=0)
+
+
+def clustered_sphere(rng: np.random.Generator, D: int, n_blob: int, n_uniform: int, n_centres: int,
+                     sigma: float) -> np.ndarray:
+    """Points on the unit D-sphere [D + 1][n]: ``n_blob`` points, each a
+    uniform centre (one of ``n_centres``) offset by N(0, sigma^2) per
+    coordinate of R^{D+1} and projected back onto the sphere (blobs of
+    angular size about sigma), then ``n_uniform`` uniform points."""
+    c = s3_points(rng, n_centres) if D == 3 else sphere_points(rng, n_centres)
+    pick = rng.integers(0, n_centres, size=n_blob)
+    x = c[:, pick] + rng.normal(0.0, sigma, size=(D + 1, n_blob))
+    x /= np.linalg.norm(x, axis=0)
+    back = s3_points(rng, n_uniform) if D == 3 else sphere_points(rng, n_uniform)
+    return np.concatenate([x, back], axis=1)
+
+
+def c10_s3_4pcf(seed: int = 1010, n_blob: int = 90_000, n_uniform: int = 10_000) -> Workload:
+    """D=3, N=4 on the unit 3-sphere (curvature k = 1): 100k points, 90k in
+    50 blobs of angular size 0.2 rad and 10k uniform, w = 1, 10 bins equal in
+    geodesic angle over [pi/6, pi/2], lmax = 5 (the 111 components of the flat
+    D=3 4PCF workload).  The paper gives the constant-curvature estimator
+    without a timing test; this stands in for one, with bins as wide as the
+    sky test's and structure on the scale of the bins."""
+    rng = np.random.default_rng(seed)
+    pos = clustered_sphere(rng, 3, n_blob, n_uniform, 50, 0.2)
+    n = pos.shape[1]
+    edges = np.linspace(math.pi / 6, math.pi / 2, 11)
+    return Workload(f"S3-N4-clustered-{n // 1000}k", 3, 4, 5, edges, [1.0, 1.0, 1.0], pos, np.ones(n), n, sphere=True)

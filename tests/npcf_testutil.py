@@ -27,7 +27,10 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
     are judged against it where the multipole itself cancels."""
     sphere = getattr(wl, "sphere", False)
     a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic, sphere=sphere)
-    V = 4 * np.pi if sphere else float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
+    if sphere:
+        V = 4 * np.pi if wl.D == 2 else 2 * np.pi ** 2   # the unit 2- or 3-sphere's volume
+    else:
+        V = float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
     lam, s, c = oracle.coupling_terms(wl.D, wl.N, wl.lmax, Lmax)
     nb = len(wl.edges) - 1
     bts = oracle.btuple_labels(nb, wl.N, btuple_mode)

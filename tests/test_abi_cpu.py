@@ -54,6 +54,7 @@ def _plan(lib, **kw):
     cfg.btuple_mode = kw.get("btuple_mode", 0)
     cfg.precision = kw.get("precision", 0)
     cfg.norm = kw.get("norm", 0)
+    cfg.geometry = kw.get("geometry", 0)
     h = ctypes.c_void_p()
     st = lib.npcf_plan(ctypes.byref(cfg), None, kw.get("max_points", 100), ctypes.byref(h))
     if st == 0:
@@ -86,6 +87,13 @@ def _plan(lib, **kw):
     (dict(N=5, lmax=2, edges=[1.0, 1.5, 2.0, 3.0]), binding.NPCF_E_INVALID),
     (dict(N=4, edges=[1.0, 2.0, 3.0]), binding.NPCF_E_INVALID),
     (dict(N=3, edges=[1.0, 2.0]), binding.NPCF_E_INVALID),
+    # the unit D-sphere: D = 2 or 3, edges in (0, pi], cos(edges[0]) below 1
+    (dict(geometry=1, D=4), binding.NPCF_E_UNSUPPORTED),
+    (dict(geometry=1, D=3, lmax=6), binding.NPCF_E_UNSUPPORTED),
+    (dict(geometry=1, D=3, edges=[1.0, 2.0, 3.5]), binding.NPCF_E_INVALID),
+    (dict(geometry=1, D=3, edges=[1e-9, 1.0, 2.0]), binding.NPCF_E_INVALID),
+    (dict(geometry=1, D=2, edges=[1e-9, 1.0, 2.0]), binding.NPCF_E_INVALID),
+    (dict(geometry=2), binding.NPCF_E_INVALID),
 ])
 def test_plan_validation(lib, kw, expect):
     assert _plan(lib, **kw) == expect
@@ -106,6 +114,7 @@ def test_valid_plan_needs_a_device(lib):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _plan(lib) == binding.NPCF_E_DEVICE
+    assert _plan(lib, geometry=1, D=3, lmax=5, edges=[0.5, 1.0, 1.5]) == binding.NPCF_E_DEVICE
 
 
 def test_single_hip_runtime_per_process():

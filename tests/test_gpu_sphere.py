@@ -142,7 +142,9 @@ def test_sphere_rejects():
     from paper_2106_10278_amd import NPCF, NPCFError
     e = np.array([0.2, 0.5, 1.0])
     with pytest.raises(NPCFError):
-        NPCF(3, 3, 2, e, [1.0] * 3, max_points=50, sphere=True)       # the sphere takes D = 2
+        NPCF(4, 3, 2, e, [1.0] * 4, max_points=50, sphere=True)       # the sphere takes D = 2 or 3
+    with pytest.raises(NPCFError):
+        NPCF(2, 3, 2, np.array([1e-9, 0.5]), [1.0] * 2, max_points=50, sphere=True)   # cos(edges[0]) rounds to 1
     with pytest.raises(NPCFError):
         NPCF(2, 4, 6, e, [1.0] * 2, max_points=50, sphere=True)       # lmax above 5
     with pytest.raises(NPCFError):
