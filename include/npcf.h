@@ -229,7 +229,9 @@ npcf_status npcf_alm(npcf_plan_t plan, const double *pos, const double *w, int64
  * apart only by their weights.  All catalogues share one cell list (keys
  * catalogue-major) and run as one launch sequence: a persistent harmonic
  * kernel over rows of every catalogue, coupling blocks cut at catalogue
- * boundaries, one FP64 accumulator per catalogue.  The sequence is captured
+ * boundaries, one FP64 accumulator per catalogue.  Catalogues are taken
+ * smallest first (ascending n[c], ties in index order), so that most of them
+ * complete early (see npcf_finalize_batch's done_ms).  The sequence is captured
  * as a HIP graph the first time a shape (ncat, n[], pos[], w[]) is seen and
  * replayed afterwards; device workspace for the batch is allocated then
  * (independent of max_points).  Asynchronous: ordered after the plan's stream
@@ -308,13 +310,14 @@ npcf_status npcf_apply_tuning(npcf_plan_t plan, const npcf_tuning *t);
 /* Autotuner for the given catalogue (positions and weights as npcf_accumulate):
  *  - the cell subdivision s = 1..6 (1..4 for D = 4) and then the harmonic
  *    grid's blocks per CU (2, 3, 4, 6, 8), timing the harmonic stage with its
- *    cell list on `sample` primaries taken from four ranges spread over the
- *    catalogue;
+ *    cell list on four ranges spread over the catalogue of
+ *    max(sample / 4, min(n / 16, 131072)) primaries each: enough rows to
+ *    fill the persistent grid many times over, so that the timing follows
+ *    throughput rather than the latency of single rows;
  *  - the primaries per coupling block (the automatic rule, 256, 512, 1024,
  *    2048) and the chunk rows (the plan's largest, or n / 32), timing the
- *    coupling and the whole pass on a quarter of the catalogue in four spread
- *    ranges, so that the row blocks have their full size and fill the GPU as
- *    the whole catalogue does (a small sample would leave large blocks idle);
+ *    coupling and the whole pass on the whole catalogue, whose launches are
+ *    the ones tuned (on a part of it a block size gives another block count);
  *  each by the best of two runs (HIP events); a setting other than the
  *  default must win by 2%.  The choice is applied to the plan (read it with
  *  npcf_get_tuning).  With the environment variable NPCF_TUNE_CACHE naming a

@@ -516,6 +516,9 @@ npcf_status accumulate_impl(npcf_plan_s *p, Workspace &W, const double *pos, con
 //   quantise all catalogues into one array with cell key c * ncell + cell ->
 //   one counting sort (catalogue-major, so catalogue c occupies sorted
 //   positions [off[c], off[c+1]) and cells [c * ncell, (c+1) * ncell)) ->
+//   rows (primaries) taken catalogue by catalogue, smallest catalogue first
+//   (shortest job first: a catalogue's pair count grows as the square of its
+//   size, so most catalogues finish early in the batch) ->
 //   per chunk of rows: persistent harmonic launch over rows of any catalogue,
 //   coupling with row blocks cut at catalogue boundaries, FP64 reduction of
 //   each catalogue's blocks into its own accumulator, and a device-clock
@@ -541,6 +544,8 @@ struct BatchState {
     int ncat = 0;
     int64_t ntot = 0;
     std::vector<int64_t> n, off;
+    std::vector<int> order;             // catalogues in processing order (ascending size)
+    std::vector<int64_t> roff;          // rows of order[i] are [roff[i], roff[i+1]) of the row list
     std::vector<const double *> pos, w;
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell_cat = 1, ncell_tot = 1;
@@ -553,7 +558,8 @@ struct BatchState {
     double *wall = nullptr, *w64s = nullptr;
     uint32_t *cell = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *scan = nullptr;
     int64_t scan_len = 0;
-    int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr, *iota = nullptr;
+    int32_t *perm = nullptr, *perm_sorted = nullptr, *orig = nullptr;
+    int32_t *rowlist = nullptr;         // sorted positions of the primaries in processing order
     uint4 *rec = nullptr;
     float *ws = nullptr;
     double *acc = nullptr, *partial = nullptr;
@@ -614,6 +620,17 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
     b->ncell_tot = b->ncell_cat * ncat;
     if (b->ncell_tot + 1 >= (int64_t)UINT32_MAX) return NPCF_E_UNSUPPORTED;  // 32-bit cell keys
 
+    // processing order: ascending size (stable), and the row list in that
+    // order (catalogue c's primaries are the sorted positions off[c] ..)
+    b->order.resize(ncat);
+    for (int c = 0; c < ncat; c++) b->order[c] = c;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return n[x] < n[y]; });
+    b->roff.assign(ncat + 1, 0);
+    for (int i = 0; i < ncat; i++) b->roff[i + 1] = b->roff[i] + n[b->order[i]];
+    std::vector<int32_t> rows_h((size_t)b->ntot);
+    for (int i = 0; i < ncat; i++)
+        for (int64_t k = 0; k < n[b->order[i]]; k++) rows_h[(size_t)(b->roff[i] + k)] = (int32_t)(b->off[b->order[i]] + k);
+
     // chunks of rows and their row blocks (never straddling a catalogue)
     const int64_t cap = p->wk.rows_cap;
     b->rpb = couple_rows_per_block(p, std::min<int64_t>(cap, b->ntot));
@@ -623,8 +640,9 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
         ch.r0 = r0;
         ch.rows = (int)std::min<int64_t>(cap, b->ntot - r0);
         ch.rb_off = (int)rbb.size();
-        for (int c = 0; c < ncat; c++) {
-            const int64_t lo = std::max<int64_t>(b->off[c], r0), hi = std::min<int64_t>(b->off[c + 1], r0 + ch.rows);
+        for (int i = 0; i < ncat; i++) {
+            const int c = b->order[i];
+            const int64_t lo = std::max<int64_t>(b->roff[i], r0), hi = std::min<int64_t>(b->roff[i + 1], r0 + ch.rows);
             if (lo >= hi) continue;
             BatchSeg sg{c, (int)rbb.size() - ch.rb_off, 0};
             for (int64_t r = lo; r < hi; r += b->rpb) {
@@ -633,7 +651,7 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
             }
             sg.rb1 = (int)rbb.size() - ch.rb_off;
             ch.segs.push_back(sg);
-            if (b->off[c + 1] <= r0 + ch.rows) ch.ends.push_back(c);
+            if (b->roff[i + 1] <= r0 + ch.rows) ch.ends.push_back(c);
         }
         ch.nrb = (int)rbb.size() - ch.rb_off;
         b->chunks.push_back(ch);
@@ -659,7 +677,7 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
     b->perm = m.get<int32_t>(N);
     b->perm_sorted = m.get<int32_t>(N);
     b->orig = m.get<int32_t>(N);
-    b->iota = m.get<int32_t>(N);
+    b->rowlist = m.get<int32_t>(N);
     b->rec = m.get<uint4>(N);
     b->ws = m.get<float>(N);
     b->acc = m.get<double>((size_t)ncat * len);
@@ -684,7 +702,8 @@ npcf_status batch_setup(npcf_plan_s *p, int ncat, const double *const *pos, cons
         NPCF_TRY(hipMemcpyAsync(b->rb_begin, rbb.data(), rbb.size() * sizeof(int), hipMemcpyHostToDevice, s));
         NPCF_TRY(hipMemcpyAsync(b->rb_end, rbe.data(), rbe.size() * sizeof(int), hipMemcpyHostToDevice, s));
     }
-    NPCF_TRY(launch_iota_i32(b->iota, N, s));
+    if (b->ntot > 0)
+        NPCF_TRY(hipMemcpyAsync(b->rowlist, rows_h.data(), (size_t)b->ntot * sizeof(int32_t), hipMemcpyHostToDevice, s));
     NPCF_TRY(hipStreamSynchronize(s));
     return NPCF_OK;
 }
@@ -708,7 +727,7 @@ npcf_status batch_record(npcf_plan_s *p, hipStream_t s)
     NPCF_TRY(launch_gather(p->D, b->ntot, b->perm_sorted, b->qtmp, b->wall, b->rec, b->ws, b->w64s, b->orig, s));
     // chunks: harmonic over rows of any catalogue, coupling per catalogue
     for (const BatchChunk &ch : b->chunks) {
-        HarmArgs ha = harm_args(p, p->wk, ch.rows, b->iota + ch.r0, b->pairs);
+        HarmArgs ha = harm_args(p, p->wk, ch.rows, b->rowlist + ch.r0, b->pairs);
         ha.rec = b->rec;
         ha.w = b->ws;
         ha.cell_start = b->cell_start;
@@ -1706,15 +1725,22 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
     double h = 0.0, c = 0.0;
     st = measure(small, h, c);  // first launches (code loading) out of the way
     if (st != NPCF_OK) return st;
-    // harmonic stage with its cell list, on the primary sample: the cell
-    // subdivision, then the persistent grid's blocks per CU
+    // harmonic stage with its cell list: the cell subdivision, then the
+    // persistent grid's blocks per CU, on four spread ranges of up to 128k
+    // primaries (a quarter of the catalogue at most): enough rows to fill the
+    // persistent grid (8192 waves at 8 blocks per CU) many times over, so
+    // that the timing follows throughput; a few thousand primaries leave
+    // waves idle and rank the subdivisions by the latency of single rows
+    // (2M D = 4 points: s = 3 chosen on 4096 primaries, 211 ms per launch
+    // against 179 ms at s = 2)
+    const auto quarter = spread(std::max<int64_t>(sample / 4, std::min<int64_t>(n / 16, 131072)));
     int best_s = p->cell_subdiv;
     double best_h = 1e300;
     const int smax = p->D == 4 ? 4 : 6;
     for (int sdv = 1; sdv <= smax; sdv++) {
         st = npcf_set_tuning(p, sdv, 0, 0);
         if (st != NPCF_OK) return st;
-        st = measure(small, h, c);
+        st = measure(quarter, h, c);
         if (st != NPCF_OK) return st;
         if (h < best_h) {
             best_h = h;
@@ -1726,7 +1752,7 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
     int best_g = 8;
     for (int g : {2, 3, 4, 6, 8}) {
         p->harm_bpc = g;
-        st = measure(small, h, c);
+        st = measure(quarter, h, c);
         if (st != NPCF_OK) return st;
         if (h < best_h * (g == 8 ? 1.0 : 0.98)) {   // a different grid must win by 2%
             best_h = h;
@@ -1734,16 +1760,18 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
         }
     }
     p->harm_bpc = best_g;
-    // coupling block size and chunk rows, on a quarter of the catalogue in four
-    // spread ranges: full-size row blocks, as many blocks as fill the GPU the
-    // way the whole catalogue does (a primary sample leaves large blocks idle)
-    const auto quarter = spread(std::max<int64_t>(sample / 4, n / 16));
+    // coupling block size and chunk rows on the whole catalogue: the
+    // automatic block size and a fixed one give different block counts on a
+    // part of it than on the full launches (2M D = 4 points: 512 rows per
+    // block won on a quarter by more than 2% and lost on the whole, 59.3
+    // against 57.0 ms)
+    const std::vector<std::pair<int64_t, int64_t>> whole{{0, n}};
     int best_b = 0;
     double best_c = 1e300, best_q = 1e300;
     for (int b : {0, 256, 512, 1024, 2048}) {
         batch_release(p);
         p->couple_rows = b;
-        st = measure(quarter, h, c);
+        st = measure(whole, h, c);
         if (st != NPCF_OK) return st;
         if (c < best_c * (b == 0 ? 1.0 : 0.98)) {   // the automatic rule unless 2% slower
             best_c = c;
@@ -1758,7 +1786,7 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
         if (r > full_rows || r == best_r) continue;
         st = npcf_set_tuning(p, 0, 0, r);
         if (st != NPCF_OK) return st;
-        st = measure(quarter, h, c);
+        st = measure(whole, h, c);
         if (st != NPCF_OK) return st;
         if (h + c < 0.98 * best_q) {
             best_q = h + c;

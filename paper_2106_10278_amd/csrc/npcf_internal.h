@@ -249,7 +249,6 @@ hipError_t launch_quantize_batch(int D, int periodic, int ncat, const double *co
                                  int64_t ncell_cat, uint32_t *const qtmp[kMaxD], double *wall, uint32_t *cell,
                                  uint32_t *count, int *bad, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
-hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // device clock (constant-rate wall clock) at this point of the stream into *ts
 hipError_t launch_timestamp(unsigned long long *ts, hipStream_t s);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *scratch,

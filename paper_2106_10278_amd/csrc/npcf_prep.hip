@@ -136,12 +136,6 @@ __global__ void k_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n)
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
-__global__ void k_iota_i32(int32_t *p, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = (int32_t)i;
-}
-
 __global__ void k_timestamp(unsigned long long *ts)
 {
     if (threadIdx.x == 0) *ts = (unsigned long long)wall_clock64();
@@ -393,15 +387,6 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStr
     int64_t g = (n + kBlk - 1) / kBlk;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)g), dim3(kBlk), 0, s, dst, src, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    int64_t g = (n + kBlk - 1) / kBlk;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)g), dim3(kBlk), 0, s, p, n);
     return hipGetLastError();
 }
 
