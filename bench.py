@@ -285,19 +285,37 @@ def grid_stage_bytes(wl) -> float:
     return (36 + 32 * D + 16 + 8) * ng + (32 * D + 16 + 8) * nbs * ng
 
 
-def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None):
-    """Time the FP64 oracle on a bounded sample of primaries (both roles)."""
+def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None, target_s: float = 12.0):
+    """Time the FP64 oracle on a bounded sample of primaries (both roles):
+    first `sample_per_role` primaries per role, then, if that took well under
+    `target_s`, a sample scaled to about `target_s` of CPU work (at most each
+    role's size).  The GPU paths' errors are taken on the timed sample."""
     import oracle
     nd = wl.n_data
-    ranges = [(0, sample_per_role)]
-    if wl.pos.shape[1] > nd:
-        ranges.append((nd, nd + sample_per_role))
-    prims = np.concatenate([np.arange(a, b) for a, b in ranges])
-    t0 = time.perf_counter()
+    n = wl.pos.shape[1]
     Lmax = wl.Lmax
-    z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax,
-                           sphere=wl.sphere)
-    dt = time.perf_counter() - t0
+
+    def sample(per):
+        r = [(0, min(per, nd))]
+        if n > nd:
+            r.append((nd, nd + min(per, n - nd)))
+        return r
+
+    def timed(r):
+        prims = np.concatenate([np.arange(a, b) for a, b in r])
+        t0 = time.perf_counter()
+        z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax,
+                               sphere=wl.sphere)
+        return prims, z, pairs, time.perf_counter() - t0
+
+    ranges = sample(sample_per_role)
+    prims, z, pairs, dt = timed(ranges)
+    if dt < 0.5 * target_s:
+        per = int(sample_per_role * target_s / max(dt, 1e-3))
+        bigger = sample(per)
+        if sum(b - a for a, b in bigger) > len(prims):
+            ranges = bigger
+            prims, z, pairs, dt = timed(ranges)
     ref = oracle.reported_part(z, oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax), wl.D, wl.N, los=Lmax is not None)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     errs = {}
@@ -388,7 +406,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--cpu-sample", type=int, default=128, help="oracle primaries per role for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=int, default=128, help="oracle primaries per role for cpu_baseline "
+                    "(first sample; scaled up to about --cpu-seconds of CPU work)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU work the oracle sample is scaled to")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="mixed_fp16,mixed_bf16x6,plain,mixed_bf16")
     ap.add_argument("--batch-steps", type=int, default=1, help="timed passes of the batched workload (0: skip)")
@@ -452,7 +472,7 @@ def main():
     cpu = None
     errs = None
     if not args.no_cpu:
-        cpu, errs = cpu_baseline(wl, factory, pos, w, args.cpu_sample, field)
+        cpu, errs = cpu_baseline(wl, factory, pos, w, args.cpu_sample, field, args.cpu_seconds)
 
     # headline: the fastest split-precision path within 1e-5 of the oracle
     # (without the oracle check: the FP16 hi+lo path, which carries 22 bits)
