@@ -181,10 +181,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // with its coefficient for each l3, into that slot's S; each slot then takes
 // its MFMA slice against a_{l3 m3}[b3].  Two jobs per wave (paired by cost).
 // ---------------------------------------------------------------------------
-// One group (pair, m3) of a job with its NA active slots (the first NA):
-// S of every slot for this lane's 16-row tile row and its four primaries of
-// the step, then one MFMA slice per slot, folded into the FP64 accumulators.
-template <int PREC, int NA>
+// One group (pair, m3) of a job, slots [K0, K0 + NA) of its active ones:
+// S of every such slot for this lane's 16-row tile row and its four
+// primaries of the step, then one MFMA slice per slot, folded into the FP64
+// accumulators.  A group with more active slots than its precision's cap
+// takes several calls, forming its products again each time, so that the
+// kernel fits four waves per SIMD (Couple4fShape).  Each slot's sum sees
+// the same operations either way.
+template <int PREC, int NA, int K0>
 __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int g, const float *Ast, const float *wst,
                                                int rowlen, int st2, int kq, int n, int2 bb, bool rowok, bool colok,
                                                double (&acc)[kMaxSlots][4])
@@ -211,7 +215,7 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
         const bool conj1 = (dy & 0xFFu) != 0, conj2 = (dy & 0xFF00u) != 0;
         float c[NA];
 #pragma unroll
-        for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + t * kFCoefStride + k]);
+        for (int k = 0; k < NA; k++) c[k] = uni(coef[cb + t * kFCoefStride + K0 + k]);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const float *Ap = Ast + (4 * kq + q) * rowlen;
@@ -231,9 +235,10 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
 #pragma unroll
     for (int k = 0; k < NA; k++) {
         // s3[] read as dwords (scalar loads), as the product descriptors
-        const uint32_t s3w = ((const __attribute__((address_space(4))) uint32_t *)&groups[g].s3[0])[k >> 1];
-        const int s3 = uni((int)(int16_t)(s3w >> (16 * (k & 1))));
-        const int part = uni(pairs[pp].part[k]);
+        const int ks = K0 + k;
+        const uint32_t s3w = ((const __attribute__((address_space(4))) uint32_t *)&groups[g].s3[0])[ks >> 1];
+        const int s3 = uni((int)(int16_t)(s3w >> (16 * (ks & 1))));
+        const int part = uni(pairs[pp].part[ks]);
         float Av[8], Bv[8];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
@@ -252,12 +257,27 @@ __device__ __forceinline__ void couple4f_group(const CoupleArgs &a, int pp, int 
         double unscale;
         mfma_k32<PREC>(Av, Bv, cc, unscale);
 #pragma unroll
-        for (int v = 0; v < 4; v++) acc[k][v] += (double)cc[v] * unscale;
+        for (int v = 0; v < 4; v++) acc[K0 + k][v] += (double)cc[v] * unscale;
     }
 }
 
+// Active slots per pass and waves per SIMD of k_couple4f, per precision.
+// kCap 6: every group in one pass; kCap 4: groups of five or six active
+// slots in two passes (three, then the rest).  c2 coupling, ms per pass:
+//   plain      35.5 at 3 waves; 29.9 at 4 in one pass (a 28-byte spill); 31.2 in two passes
+//   BF16 x6    35.3 at 3 waves; 33.8 at 4 in one pass (80-byte spill); 33.3 in two (64 bytes);
+//              34.1 with passes of at most three
+//   BF16 hi+lo 33.7 at 3 waves; 31.2 at 4 in two passes
+//   FP16       43.0 at 3 waves; 48.4 at 4 in two passes (its per-tile scales need more
+//              registers: a 100-byte spill)
 template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple4f(CoupleArgs a, int njobs)
+struct Couple4fShape {
+    static constexpr int kCap = (PREC == 0 || PREC == 2) ? kMaxSlots : 4;
+    static constexpr int kWaves = PREC == 2 ? 3 : 4;
+};
+
+template <int PREC>
+__device__ __forceinline__ void couple4f_body(const CoupleArgs &a, int njobs)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
@@ -310,13 +330,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             const bool colok = n < a.nb;
             const int gb = uni(pairs[pp].grp_begin), ge = uni(pairs[pp].grp_end);
             for (int g = gb; g < ge; g++) {
-                switch (uni(groups[g].nact)) {
-                case 1: couple4f_group<PREC, 1>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
-                case 2: couple4f_group<PREC, 2>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
-                case 3: couple4f_group<PREC, 3>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
-                case 4: couple4f_group<PREC, 4>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
-                case 5: couple4f_group<PREC, 5>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
-                default: couple4f_group<PREC, kMaxSlots>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                const int nact = uni(groups[g].nact);
+                if constexpr (Couple4fShape<PREC>::kCap == kMaxSlots) {
+                    switch (nact) {
+                    case 1: couple4f_group<PREC, 1, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 2: couple4f_group<PREC, 2, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 3: couple4f_group<PREC, 3, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 4: couple4f_group<PREC, 4, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 5: couple4f_group<PREC, 5, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    default: couple4f_group<PREC, kMaxSlots, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    }
+                } else {
+                    static_assert(Couple4fShape<PREC>::kCap == 4 && kMaxSlots == 6, "five or six slots in two passes");
+                    switch (nact) {
+                    case 1: couple4f_group<PREC, 1, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 2: couple4f_group<PREC, 2, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 3: couple4f_group<PREC, 3, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 4: couple4f_group<PREC, 4, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc); break;
+                    case 5:
+                        couple4f_group<PREC, 3, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc);
+                        couple4f_group<PREC, 2, 3>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc);
+                        break;
+                    default:
+                        couple4f_group<PREC, 3, 0>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc);
+                        couple4f_group<PREC, 3, 3>(a, pp, g, Ast, wst, rowlen, st2, kq, n, bb, rowok, colok, acc);
+                        break;
+                    }
                 }
             }
         };
@@ -340,6 +379,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     };
     write_job(jobs[0], acc0);
     if (kFJobsPerWave > 1) write_job(jobs[1], acc1);
+}
+
+// the factorised kernel per precision, each with its waves per SIMD
+template <int PREC>
+__global__ void k_couple4f(CoupleArgs a, int njobs);
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Couple4fShape<0>::kWaves))) void k_couple4f<0>(CoupleArgs a, int njobs)
+{
+    couple4f_body<0>(a, njobs);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Couple4fShape<1>::kWaves))) void k_couple4f<1>(CoupleArgs a, int njobs)
+{
+    couple4f_body<1>(a, njobs);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Couple4fShape<2>::kWaves))) void k_couple4f<2>(CoupleArgs a, int njobs)
+{
+    couple4f_body<2>(a, njobs);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Couple4fShape<3>::kWaves))) void k_couple4f<3>(CoupleArgs a, int njobs)
+{
+    couple4f_body<3>(a, njobs);
 }
 
 // ---------------------------------------------------------------------------
