@@ -285,6 +285,22 @@ def grid_stage_bytes(wl) -> float:
     return (36 + 32 * D + 16 + 8) * ng + (32 * D + 16 + 8) * nbs * ng
 
 
+def mixed_vs_plain(results, head):
+    """The metric's comparison: the headline split-precision path against
+    plain FP32, per step and in the coupling stage (the only stage the split
+    changes), with which of the two is faster."""
+    if head == "plain" or "plain" not in results or head not in results:
+        return None
+    m, p = results[head], results["plain"]
+    return {"mixed_path": head, "mixed_ms_per_step": m["ms_per_step"], "plain_ms_per_step": p["ms_per_step"],
+            "speedup": p["ms_per_step"] / m["ms_per_step"],
+            "mixed_coupling_ms": m["stage_ms_per_step"]["coupling"],
+            "plain_coupling_ms": p["stage_ms_per_step"]["coupling"],
+            "faster": "mixed" if m["ms_per_step"] < p["ms_per_step"] else "plain",
+            "note": "the split changes only the coupling's MFMA slices; S is formed on the vector ALU in "
+                    "FP32 either way, and the split operands' extra registers cost occupancy"}
+
+
 def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None, target_s: float = 12.0):
     """Time the FP64 oracle on a bounded sample of primaries (both roles):
     first `sample_per_role` primaries per role, then, if that took well under
@@ -521,6 +537,7 @@ def main():
                    "parallelism": "single GPU"},
         "paths": results,
         "roofline": roof,
+        "mixed_vs_plain": mixed_vs_plain(results, head),
         "coupling_roofline": coupling_roofline(key, head, r["stage_ms_per_step"]["coupling"],
                                                coupling_useful_flops(wl, plan_labels)),
         "cpu_baseline": cpu,
