@@ -194,7 +194,7 @@ def coupling_terms(D: int, N: int, lmax: int, Lmax=None):
     return lam, s, c
 
 
-def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None, sphere=False):
+def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None, sphere=False, hyperbolic=False):
     edges = np.ascontiguousarray(edges, dtype=np.float64)
     cfg = _Cfg()
     cfg.D, cfg.N, cfg.lmax, cfg.nbins = D, N, lmax, len(edges) - 1
@@ -206,8 +206,9 @@ def _cfg(D, N, lmax, edges, box, periodic=True, btuple_mode=0, Lmax=None, sphere
     cfg.btuple_mode = btuple_mode
     cfg.basis = 0 if Lmax is None else 1
     cfg.Lmax = 0 if Lmax is None else int(Lmax)
-    # sphere: points on the unit D-sphere (D = 2: S^2 in R^3; D = 3: S^3 in R^4)
-    cfg.geometry = (D - 1) if sphere else 0
+    # sphere: points on the unit D-sphere (D = 2: S^2 in R^3; D = 3: S^3 in R^4);
+    # hyperbolic: points of H^D on the hyperboloid in R^{D,1}, box[0] = V
+    cfg.geometry = 3 if hyperbolic else ((D - 1) if sphere else 0)
     return cfg, edges
 
 
@@ -221,12 +222,14 @@ def _prep(pos, w, prims):
     return pos, w, n, prims
 
 
-def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True, sphere=False):
+def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True, sphere=False, hyperbolic=False):
     """a^b_[l](y_j) for the listed primaries: complex [nprim][nbins][nstates].
     sphere: points on the unit D-sphere (D = 2: pos [3][n], D = 3: pos [4][n]
-    unit vectors; edges in radians of geodesic angle)."""
+    unit vectors; edges in radians of geodesic angle).  hyperbolic: points of
+    H^D on the hyperboloid x0^2 - |x|^2 = 1 (pos [D+1][n]; edges in geodesic
+    distance; box[0] = V)."""
     lib = _load()
-    cfg, edges = _cfg(D, 3, lmax, edges, box, periodic, sphere=sphere)
+    cfg, edges = _cfg(D, 3, lmax, edges, box, periodic, sphere=sphere, hyperbolic=hyperbolic)
     pos, w, n, prims = _prep(pos, w, prims)
     nst = lib.oracle_num_states(D, lmax)
     out = np.zeros((len(prims), len(edges) - 1, nst, 2))
@@ -237,12 +240,14 @@ def alm(D, lmax, edges, box, pos, w, prims=None, periodic=True, sphere=False):
     return out[..., 0] + 1j * out[..., 1], int(pairs.value)
 
 
-def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0, Lmax=None, sphere=False):
+def npcf(D, N, lmax, edges, box, pos, w, prims=None, periodic=True, btuple_mode=0, Lmax=None, sphere=False,
+         hyperbolic=False):
     """Complex zeta^{Lambda,b} [nlambda][nbtuple] over the listed primaries
     (default: all) against all secondaries, plus the in-range pair count.
-    With Lmax (D = 3, N = 3): the line-of-sight basis P^{0L}, L <= Lmax."""
+    With Lmax (D = 3, N = 3): the line-of-sight basis P^{0L}, L <= Lmax.
+    sphere / hyperbolic: the curved geometries (see alm)."""
     lib = _load()
-    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode, Lmax, sphere)
+    cfg, edges = _cfg(D, N, lmax, edges, box, periodic, btuple_mode, Lmax, sphere, hyperbolic)
     pos, w, n, prims = _prep(pos, w, prims)
     nlam = len(lambda_labels(D, N, lmax, Lmax)) if Lmax is not None else lib.oracle_num_lambda(D, N, lmax)
     nbt = lib.oracle_num_btuples(len(edges) - 1, N, btuple_mode)

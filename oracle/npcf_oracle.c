@@ -75,9 +75,29 @@
  *    on the frame (a rotation of it rotates every direction at p alike); odd
  *    ones change sign with its orientation.
  *
+ *  - with cfg->geometry = 3 (D = 2 or 3), points of hyperbolic space H^D, the
+ *    constant-curvature space of section "Constant-Curvature Metric" with
+ *    k = -1, chi(r) = sinh r (eq. metric), in the hyperboloid model:
+ *    positions are points of R^{D,1} with x0^2 - x1^2 - .. - xD^2 = 1, x0 > 0
+ *    (pos[D+1][n]), and <x, y> = x0 y0 - x1 y1 - .. - xD yD; the radial
+ *    coordinate is the geodesic distance theta, cosh theta = <p, q>, binned
+ *    e_b <= theta < e_{b+1}, i.e. cosh(e_b) <= <p, q> < cosh(e_{b+1}) on the
+ *    FP64 product evaluated left to right; the direction is that of
+ *    q - <p, q> p in the tangent space at p, in the frame e_j(p) (j = 1..D)
+ *    that the Lorentz boost taking the origin (1, 0, .., 0) to p makes of the
+ *    coordinate axes: e_j(p) = (p_j, unit_j + p_j (p1, .., pD) / (1 + p0)),
+ *    orthonormal (<e_i, e_j> = -delta_ij), orthogonal to p and positively
+ *    oriented everywhere; components u_j = -<q, e_j(p)> over their norm
+ *    sqrt(<p, q>^2 - 1); the harmonics are the D-dimensional ones of u;
+ *    v_b = |S^{D-1}| int sinh^{D-1} r dr over the bin: D = 2:
+ *    2 pi (cosh e_{b+1} - cosh e_b); D = 3: 2 pi [cosh(e_b + e_{b+1}) sinh d
+ *    - d], d = e_{b+1} - e_b; V, the volume of the region the catalogue
+ *    fills, is given in box[0].  The self pair is excluded by index (<p, p>
+ *    rounds with an error that grows as cosh^2 r).
+ *
  * The unrestricted sum over secondaries k runs over all n points for every
  * primary (brute force, no cell grid); the self pair is excluded because
- * edges[0] > 0.
+ * edges[0] > 0 (flat and spheres) or by index (hyperbolic space).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -94,7 +114,8 @@ typedef struct {
     int btuple_mode;      /* 0: b1 < b2 < ... ; 1: every tuple */
     int basis;            /* 0: isotropic (vec L = 0); 1: line-of-sight P^{0L} (D = 3, N = 3) */
     int Lmax;             /* basis 1: largest L */
-    int geometry;         /* 0: flat box; 1: unit 2-sphere (D = 2); 2: unit 3-sphere (D = 3) */
+    int geometry;         /* 0: flat box; 1: unit 2-sphere (D = 2); 2: unit 3-sphere (D = 3);
+                             3: hyperbolic space H^D (D = 2, 3), V in box[0] */
 } oracle_cfg;
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EUNSUP = 2, OR_ENOMEM = 3 };
@@ -627,7 +648,16 @@ int oracle_coupling_terms_los(int lmax, int Lmax, int cap, int *lam, int *s, dou
 static int check_cfg(const oracle_cfg *cfg)
 {
     if (!cfg || !cfg->edges) return OR_EINVAL;
-    if (cfg->geometry < 0 || cfg->geometry > 2) return OR_EINVAL;
+    if (cfg->geometry < 0 || cfg->geometry > 3) return OR_EINVAL;
+    if (cfg->geometry == 3) {
+        if ((cfg->D != 2 && cfg->D != 3) || cfg->basis != 0 || cfg->N > 4) return OR_EUNSUP;
+        if (cfg->lmax < 0 || cfg->nbins < 1 || !(cfg->edges[0] > 0.0) || !(cosh(cfg->edges[0]) >= 1.0 + 1e-9) ||
+            !(cfg->box[0] > 0.0))
+            return OR_EINVAL;
+        for (int b = 0; b < cfg->nbins; b++)
+            if (!(cfg->edges[b + 1] > cfg->edges[b])) return OR_EINVAL;
+        return OR_OK;
+    }
     if (cfg->geometry != 0) {
         if (cfg->D != cfg->geometry + 1 || cfg->basis != 0 || cfg->N > 4) return OR_EUNSUP;
         /* bins are decided on cosines: cos(e_0) must stay below 1, so that the
@@ -750,6 +780,67 @@ static long harmonic_stage_s3(const oracle_cfg *cfg, const double *pos, const do
     return pairs;
 }
 
+/* Hyperbolic space H^D (cfg->geometry = 3): see the header.  a[b][s]
+ * divided by the bin volume |S^{D-1}| int_{e_b}^{e_{b+1}} sinh^{D-1} r dr. */
+static double hyp_bin_volume(int D, double e0, double e1)
+{
+    if (D == 2) return 2.0 * M_PI * (cosh(e1) - cosh(e0));
+    const double d = e1 - e0;
+    return 2.0 * M_PI * (cosh(e0 + e1) * sinh(d) - d);
+}
+
+static long harmonic_stage_hyp(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
+                               int nst, double *a, double *yre, double *yim)
+{
+    const int D = cfg->D, nb = cfg->nbins;
+    double p[4], e[3][4];
+    for (int x = 0; x <= D; x++) p[x] = pos[(size_t)x * n + j];
+    /* e_i(p) = (p_i, unit_i + p_i (p_1..p_D) / (1 + p0)) */
+    for (int i = 1; i <= D; i++) {
+        e[i - 1][0] = p[i];
+        for (int x = 1; x <= D; x++) e[i - 1][x] = (x == i ? 1.0 : 0.0) + p[i] * p[x] / (1.0 + p[0]);
+    }
+    double ce[nb + 1];   /* nbins is small: a variable-length array */
+    for (int b = 0; b <= nb; b++) ce[b] = cosh(cfg->edges[b]);
+    long pairs = 0;
+    for (long k = 0; k < n; k++) {
+        if (k == j) continue;
+        double q[4];
+        for (int x = 0; x <= D; x++) q[x] = pos[(size_t)x * n + k];
+        /* <p, q> left to right, every product and difference rounded */
+        volatile double c = p[0] * q[0];
+        for (int x = 1; x <= D; x++) {
+            volatile double t = p[x] * q[x];
+            c = c - t;
+        }
+        if (!(c >= ce[0] && c < ce[nb])) continue;
+        int b = 0;
+        while (b + 1 < nb && c >= ce[b + 1]) b++;
+        double u[3], tn = 0.0;
+        for (int i = 0; i < D; i++) {
+            double m = q[0] * e[i][0];
+            for (int x = 1; x <= D; x++) m -= q[x] * e[i][x];
+            u[i] = -m;      /* -<q, e_i> */
+            tn += u[i] * u[i];
+        }
+        tn = sqrt(tn);
+        if (!(tn > 0.0)) continue;
+        for (int i = 0; i < D; i++) u[i] /= tn;
+        pairs++;
+        oracle_harmonics(D, cfg->lmax, u, yre, yim);
+        double *ab = a + 2 * (size_t)b * nst;
+        for (int s = 0; s < nst; s++) {
+            ab[2 * s] += w[k] * yre[s];
+            ab[2 * s + 1] -= w[k] * yim[s];  /* conj(Y) */
+        }
+    }
+    for (int b = 0; b < nb; b++) {
+        const double vb = hyp_bin_volume(D, cfg->edges[b], cfg->edges[b + 1]);
+        for (int s = 0; s < 2 * nst; s++) a[2 * (size_t)b * nst + s] /= vb;
+    }
+    return pairs;
+}
+
 static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const double *w, long n, long j,
                            int nst, double *a, double *yre, double *yim)
 {
@@ -758,6 +849,7 @@ static long harmonic_stage(const oracle_cfg *cfg, const double *pos, const doubl
     long pairs = 0;
     if (cfg->geometry == 1) return harmonic_stage_sphere(cfg, pos, w, n, j, nst, a, yre, yim);
     if (cfg->geometry == 2) return harmonic_stage_s3(cfg, pos, w, n, j, nst, a, yre, yim);
+    if (cfg->geometry == 3) return harmonic_stage_hyp(cfg, pos, w, n, j, nst, a, yre, yim);
     double e2lo = cfg->edges[0] * cfg->edges[0];
     double e2hi = cfg->edges[nb] * cfg->edges[nb];
     for (long k = 0; k < n; k++) {
@@ -897,6 +989,7 @@ int oracle_npcf(const oracle_cfg *cfg, const double *pos, const double *w, long 
     for (int k = 0; k < D; k++) VD *= cfg->box[k];
     if (cfg->geometry == 1) VD = 4.0 * M_PI;   /* area of the unit 2-sphere */
     if (cfg->geometry == 2) VD = 2.0 * M_PI * M_PI;   /* volume of the unit 3-sphere */
+    if (cfg->geometry == 3) VD = cfg->box[0];         /* the region's volume, given */
     for (size_t i = 0; i < zlen; i++) {
         double s = 0.0;
         for (int t = 0; t < nthr; t++) s += part[(size_t)t * zlen + i];

@@ -844,7 +844,7 @@ def _sphere_points(n, seed):
 
 def _sphere_area_quad(e0, e1):
     from scipy.integrate import quad
-    return 2 * math.pi * quad(math.sin, e0, e1, epsabs=1e-14, epsrel=1e-14)[0]
+    return 2 * math.pi * quad(math.sin, e0, e1, epsabs=1e-13, epsrel=1e-12)[0]
 
 
 def _sphere_brute(pos, w, edges, N, lmax, btuple_mode):
@@ -969,7 +969,7 @@ def _s3_points(n, seed):
 def _s3_volume_quad(e0, e1):
     """|S^2| int sin^2 r dr over the bin, by quadrature (eq. metric's volume element)."""
     from scipy.integrate import quad
-    return 4 * math.pi * quad(lambda r: math.sin(r) ** 2, e0, e1, epsabs=1e-14, epsrel=1e-14)[0]
+    return 4 * math.pi * quad(lambda r: math.sin(r) ** 2, e0, e1, epsabs=1e-13, epsrel=1e-12)[0]
 
 
 def _second_frame(p):
@@ -1089,3 +1089,193 @@ def test_s3_bin_volumes_fill_the_sphere():
     assert pairs == 30 * 29
     with pytest.raises(ValueError):
         oracle.npcf(3, 3, 1, np.array([1e-9, 1.0]), [1.0] * 3, pos, w, sphere=True)
+
+
+# ---------------------------------------------------------------------------
+# Hyperbolic space H^D (section "Constant-Curvature Metric", k = -1,
+# chi(r) = sinh r), hyperboloid model in R^{D,1}.
+# ---------------------------------------------------------------------------
+
+def _mink(a, b):
+    """<a, b> = a0 b0 - a1 b1 - .. (columns of a against the vector b)."""
+    return a[0] * b[0] - np.tensordot(b[1:], a[1:], axes=(0, 0))
+
+
+def _h_points(D, n, seed, R=1.2):
+    """n points of H^D: tangent vectors at the origin with N(0, (R/2)^2)
+    coordinates, mapped by the exponential map to (cosh r, sinh r y/r)."""
+    rng = np.random.default_rng(seed)
+    y = rng.normal(0.0, R / 2, size=(D, n))
+    r = np.linalg.norm(y, axis=0)
+    return np.vstack([np.cosh(r), np.sinh(r) * y / r]), rng.uniform(-0.5, 1.5, size=n)
+
+
+def _h_volume_quad(D, e0, e1):
+    """|S^{D-1}| int sinh^{D-1} r dr over the bin, by quadrature (eq. metric's volume element)."""
+    from scipy.integrate import quad
+    area = 2 * math.pi if D == 2 else 4 * math.pi
+    return area * quad(lambda r: math.sinh(r) ** (D - 1), e0, e1, epsabs=1e-13, epsrel=1e-12)[0]
+
+
+def _h_second_frame(p, D):
+    """An orthonormal, positively oriented frame of the tangent space at p
+    (Gram-Schmidt in the Minkowski metric of the projected spatial axes),
+    unlike the oracle's boost frame."""
+    frame = []
+    for i in range(1, D + 1):
+        a = np.zeros(D + 1)
+        a[i] = 1.0
+        v = a - _mink(a[:, None], p)[0] * p
+        for e in frame:
+            v = v + _mink(v[:, None], e)[0] * e
+        frame.append(v / math.sqrt(-_mink(v[:, None], v)[0]))
+    if np.linalg.det(np.column_stack([p] + frame)) < 0:
+        frame[-1] = -frame[-1]
+    return frame
+
+
+def _h_brute(pos, w, edges, D, N, lmax, btuple_mode, V):
+    """Naive estimator in H^D: unrestricted (N-1)-tuples of secondaries in the
+    geodesic bins (theta = arccosh <p, q>), directions in the second frame,
+    basis from SciPy harmonics and SymPy coefficients, coefficients through
+    conj(P), bin volumes by quadrature, divided by V."""
+    nb = len(edges) - 1
+    vb = np.array([_h_volume_quad(D, edges[b], edges[b + 1]) for b in range(nb)])
+    labels = labels_indep.labels(D, N, lmax)
+    P = _indep_basis(D, N, lmax)
+    full = np.zeros((len(labels),) + (nb,) * (N - 1), dtype=complex)
+    for j in range(pos.shape[1]):
+        p = pos[:, j]
+        c = _mink(pos, p)
+        ang = np.arccosh(np.maximum(c, 1.0))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        idx = np.nonzero(ok)[0]
+        if len(idx) == 0:
+            continue
+        b = np.searchsorted(edges, ang[idx], side="right") - 1
+        t = np.column_stack([-_mink(pos[:, idx], e) for e in _h_second_frame(p, D)])
+        u = t / np.linalg.norm(t, axis=1, keepdims=True)
+        ww = w[idx] / vb[b]
+        pv = np.conj(P(*([u] * (N - 1))))
+        if N == 3:
+            contrib = pv * ww[None, :, None] * ww[None, None, :]
+            for i1 in range(len(idx)):
+                np.add.at(full, (slice(None), b[i1], b), w[j] * contrib[:, i1, :])
+        else:
+            contrib = pv * ww[None, :, None, None] * ww[None, None, :, None] * ww[None, None, None, :]
+            for i1 in range(len(idx)):
+                for i2 in range(len(idx)):
+                    np.add.at(full, (slice(None), b[i1], b[i2], b), w[j] * contrib[:, i1, i2, :])
+    full /= V
+    bt = oracle.btuple_labels(nb, N, btuple_mode)
+    return full[(slice(None),) + tuple(bt[:, k] for k in range(N - 1))]
+
+
+@pytest.mark.parametrize("D,N,lmax,mode,n", [(3, 3, 4, 1, 50), (3, 4, 3, 1, 28), (3, 4, 2, 0, 34),
+                                             (2, 3, 4, 1, 60), (2, 4, 3, 0, 40)])
+def test_hyp_separable_equals_naive(D, N, lmax, mode, n):
+    """The separable estimator in H^D equals the naive tuple sum built in
+    another tangent frame with an independent basis (isotropic components do
+    not depend on the frame)."""
+    edges = np.array([0.2, 0.5, 0.9, 1.4]) if mode == 1 else np.array([0.25, 0.5, 0.8, 1.1, 1.6])
+    pos, w = _h_points(D, n, 70 + 3 * D + N + lmax)
+    V = 7.5
+    ref = _h_brute(pos, w, edges, D, N, lmax, mode, V)
+    got, _ = oracle.npcf(D, N, lmax, edges, [V, 1.0, 1.0], pos, w, btuple_mode=mode, hyperbolic=True)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * scale)
+
+
+def _lorentz(D, rng):
+    """A random proper orthochronous Lorentz transformation of R^{D,1}: a
+    spatial rotation, then a boost of rapidity 0.7 along a random direction."""
+    Q, _ = np.linalg.qr(rng.normal(size=(D, D)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    Rt = np.eye(D + 1)
+    Rt[1:, 1:] = Q
+    nvec = rng.normal(size=D)
+    nvec /= np.linalg.norm(nvec)
+    phi = 0.7
+    B = np.eye(D + 1)
+    B[0, 0] = math.cosh(phi)
+    B[0, 1:] = B[1:, 0] = math.sinh(phi) * nvec
+    B[1:, 1:] += (math.cosh(phi) - 1.0) * np.outer(nvec, nvec)
+    return B @ Rt
+
+
+def test_hyp_isometry_invariance_parity_and_l0():
+    """A random isometry of H^3 (rotation and boost) leaves every isotropic
+    component unchanged; a reflection of one spatial axis keeps the
+    even-parity ones and flips the odd ones; the l = 0 row equals the weighted
+    triplet count sum_j w_j W_b1(j) W_b2(j) W_b3(j) / (V prod v_b (4 pi)^{3/2})
+    with bin volumes by quadrature."""
+    rng = np.random.default_rng(11)
+    pos, w = _h_points(3, 70, 12)
+    edges = np.array([0.3, 0.7, 1.1, 1.6])
+    V = 4.0
+    args = (3, 4, 3, edges, [V, 1.0, 1.0])
+    z0, p0 = oracle.npcf(*args, pos, w, btuple_mode=1, hyperbolic=True)
+    L = _lorentz(3, rng)
+    zr, pr = oracle.npcf(*args, L @ pos, w, btuple_mode=1, hyperbolic=True)
+    sc = np.max(np.abs(z0))
+    assert pr == p0
+    np.testing.assert_allclose(zr, z0, rtol=0, atol=1e-9 * sc)
+    F = np.diag([1.0, 1.0, 1.0, -1.0])
+    zf, _ = oracle.npcf(*args, F @ pos, w, btuple_mode=1, hyperbolic=True)
+    lab = oracle.lambda_labels(3, 4, 3)
+    odd = lab.sum(axis=1) % 2 == 1
+    np.testing.assert_allclose(zf[~odd], z0[~odd], rtol=0, atol=1e-11 * sc)
+    np.testing.assert_allclose(zf[odd], -z0[odd], rtol=0, atol=1e-11 * sc)
+    assert np.max(np.abs(z0[odd])) > 1e-6 * sc
+    nb = 3
+    vb = np.array([_h_volume_quad(3, edges[b], edges[b + 1]) for b in range(nb)])
+    Wb = np.zeros((pos.shape[1], nb))
+    for j in range(pos.shape[1]):
+        ang = np.arccosh(np.maximum(_mink(pos, pos[:, j]), 1.0))
+        ok = (ang >= edges[0]) & (ang < edges[-1])
+        ok[j] = False
+        b = np.searchsorted(edges, ang[ok], side="right") - 1
+        np.add.at(Wb[j], b, w[ok])
+    bt = oracle.btuple_labels(nb, 4, 1)
+    ref = np.array([np.sum(w * Wb[:, t[0]] * Wb[:, t[1]] * Wb[:, t[2]]) / (vb[t[0]] * vb[t[1]] * vb[t[2]])
+                    for t in bt]) / (V * (4 * math.pi) ** 1.5)
+    i0 = int(np.nonzero((lab == 0).all(axis=1))[0][0])
+    np.testing.assert_allclose(z0[i0].real, ref, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("D,N,lmax", [(3, 4, 3), (3, 3, 4), (2, 4, 4)])
+def test_hyp_flat_limit(D, N, lmax):
+    """Far below the curvature scale H^D is flat: a catalogue within 1e-3 of
+    the origin, lifted by the exponential map, gives the flat open-box
+    estimator of the tangent coordinates (the oracle's flat path, with the
+    same bins and V) up to relative corrections of order r^2 ~ 1e-6."""
+    eps = 1e-3
+    rng = np.random.default_rng(40 + D + N)
+    n = 60
+    y = rng.uniform(-eps, eps, size=(D, n))
+    w = rng.uniform(0.5, 1.5, size=n)
+    r = np.linalg.norm(y, axis=0)
+    pos = np.vstack([np.cosh(r), np.sinh(r) * y / r])
+    edges = eps * np.array([0.2, 0.5, 0.9, 1.4, 2.0])
+    box = 1.0
+    zh, ph = oracle.npcf(D, N, lmax, edges, [box ** D, 1.0, 1.0], pos, w, hyperbolic=True)
+    zf, pf = oracle.npcf(D, N, lmax, edges, [box] * D, y + box / 2, w, periodic=False)
+    assert ph == pf
+    np.testing.assert_allclose(zh, zf, rtol=0, atol=3e-5 * np.max(np.abs(zf)))
+
+
+def test_hyp_rejects_and_self_pair():
+    """Every distinct pair within range is counted once and the self pair
+    never (excluded by index); an innermost edge with cosh(e0) < 1 + 1e-9 and
+    a non-positive volume are rejected."""
+    pos, w = _h_points(3, 25, 5, R=0.5)
+    edges = np.array([1e-4, 0.5, 3.0, 6.0])
+    _, pairs = oracle.npcf(3, 3, 1, edges, [1.0, 1.0, 1.0], pos, w, hyperbolic=True)
+    assert pairs == 25 * 24
+    with pytest.raises(ValueError):
+        oracle.npcf(3, 3, 1, np.array([1e-6, 1.0]), [1.0] * 3, pos, w, hyperbolic=True)
+    with pytest.raises(ValueError):
+        oracle.npcf(3, 3, 1, np.array([0.1, 1.0]), [0.0, 1.0, 1.0], pos, w, hyperbolic=True)
