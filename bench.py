@@ -136,6 +136,8 @@ def make_workload(name: str):
         return inputs.c9_sphere_4pcf()
     if name == "c10":
         return inputs.c10_s3_4pcf()
+    if name == "c11":
+        return inputs.c11_h3_4pcf()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,7 +261,8 @@ def coupling_roofline(key: str, path: str, coupling_ms: float, useful=None):
 
 
 def sphere_flops(D: int, L: int, visited: float, pairs: float) -> float:
-    """FP32-equivalent operations of the sphere harmonic stage (FP64 counted
+    """FP32-equivalent operations of the curved-space harmonic stage (the
+    unit D-sphere and hyperbolic space alike; FP64 counted
     twice, the FP64 vector peak being half the FP32 one): every visited pair
     takes an FP64 dot product of the D + 1 coordinates (2D + 1 operations) for
     its bin; an in-range pair adds D FP64 tangent projections (2D + 1 each),
@@ -321,7 +324,7 @@ def cpu_baseline(wl, plan_factory, pos, w, sample_per_role: int, field=None, tar
         prims = np.concatenate([np.arange(a, b) for a, b in r])
         t0 = time.perf_counter()
         z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, Lmax=Lmax,
-                               sphere=wl.sphere)
+                               sphere=wl.sphere, hyperbolic=wl.hyperbolic)
         return prims, z, pairs, time.perf_counter() - t0
 
     ranges = sample(sample_per_role)
@@ -456,7 +459,7 @@ def main():
 
     def factory(prec):
         return NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, precision=prec, max_points=n,
-                    Lmax=wl.Lmax, sphere=wl.sphere)
+                    Lmax=wl.Lmax, sphere=wl.sphere, hyperbolic=wl.hyperbolic)
 
     results = {}
     plan_labels = None
@@ -506,7 +509,7 @@ def main():
             "traffic": load_traffic(key), "flops_per_pair": fpp,
             "flops_per_pair_instruction_level": flops_per_pair(wl.D, wl.lmax),
             "launch_ms": r["harmonic_ms_per_launch"]}
-    if wl.sphere:
+    if wl.sphere or wl.hyperbolic:
         # every pair is visited (no cell list): count the bin test of all of them
         fl = sphere_flops(wl.D, wl.lmax, float(n) * n, r["pairs_per_step"])
         ach = fl / (r["harmonic_ms_per_launch"] * 1e-3)
@@ -533,7 +536,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": key, "n_points": n, "n_data": wl.n_data, "D": wl.D, "N": wl.N, "lmax": wl.lmax,
                    "nbins": len(wl.edges) - 1, "r_range": [float(wl.edges[0]), float(wl.edges[-1])],
-                   "box": float(wl.box[0]), "geometry": f"unit {wl.D}-sphere" if wl.sphere else "flat",
+                   "box": float(wl.box[0]), "geometry": (f"unit {wl.D}-sphere" if wl.sphere else
+                                (f"hyperbolic {wl.D}-space" if wl.hyperbolic else "flat")),
                    "parallelism": "single GPU"},
         "paths": results,
         "roofline": roof,

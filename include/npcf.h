@@ -103,6 +103,22 @@ typedef enum {
                                     D = 2: 2 pi (cos e_b - cos e_{b+1}), V = 4 pi;
                                     D = 3: 2 pi (d - cos(e_b + e_{b+1}) sin d), d = e_{b+1} - e_b,
                                     V = 2 pi^2; box and periodic are ignored; every secondary is
+                                    visited (no cell list) */,
+    NPCF_GEOMETRY_HYPERBOLIC = 2 /* points of hyperbolic space H^D, the constant-curvature space of section
+                                    "Constant-Curvature Metric" with k = -1, chi(r) = sinh r (eq. metric),
+                                    on the hyperboloid of R^{D,1}: D = 2 or 3, N = 3 or 4, isotropic
+                                    basis, lmax <= 5; positions pos[D+1][n] with x0^2 - x1^2 - .. - xD^2
+                                    = 1, x0 > 0; <x, y> = x0 y0 - x1 y1 - .. - xD yD; edges are geodesic
+                                    distances, cosh(edges[0]) >= 1 + 1e-9, edges[nbins] <= 20; bins
+                                    e_b <= theta < e_{b+1}, cosh theta = <p, q>, decided on the FP64
+                                    product; the self pair is excluded by index; the direction of a
+                                    secondary is its tangent component at p in the frame e_j(p) =
+                                    (p_j, unit_j + p_j (p1..pD) / (1 + p0)) (the boost taking the origin to
+                                    p applied to the axes), u_j = -<q, e_j(p)>; v_b = |S^{D-1}|
+                                    int_{e_b}^{e_{b+1}} sinh^{D-1} r dr: D = 2: 2 pi (cosh e_{b+1} -
+                                    cosh e_b); D = 3: 2 pi (cosh(e_b + e_{b+1}) sinh d - d), d =
+                                    e_{b+1} - e_b; V = box[0], the volume of the region the catalogue
+                                    fills (given by the caller); periodic is ignored; every secondary is
                                     visited (no cell list) */
 } npcf_geometry;
 

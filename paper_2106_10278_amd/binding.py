@@ -139,7 +139,7 @@ class NPCF:
 
     def __init__(self, D: int, N: int, lmax: int, edges, box, periodic: bool = True, btuple_mode: int = 0,
                  precision: str = "plain", norm: str = "raw", max_points: int = 1 << 20, stream=None,
-                 Lmax=None, sphere: bool = False):
+                 Lmax=None, sphere: bool = False, hyperbolic: bool = False):
         lib = load_library()
         self.D, self.N, self.lmax = int(D), int(N), int(lmax)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -156,8 +156,9 @@ class NPCF:
         # Lmax given: the line-of-sight basis P^{0L}_{l1 l2} (D = 3, N = 3)
         cfg.basis = 0 if Lmax is None else 1
         cfg.Lmax = 0 if Lmax is None else int(Lmax)
-        # points on the unit D-sphere (D = 2 or 3): pos [D + 1][n] unit vectors, edges in radians
-        cfg.geometry = 1 if sphere else 0
+        # points on the unit D-sphere (D = 2 or 3): pos [D + 1][n] unit vectors, edges in radians;
+        # hyperbolic: points of H^D on the hyperboloid (pos [D + 1][n]), box[0] = the region's volume
+        cfg.geometry = 2 if hyperbolic else (1 if sphere else 0)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

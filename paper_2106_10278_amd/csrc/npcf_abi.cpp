@@ -463,6 +463,7 @@ npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const do
     a.pos = pos;
     a.w = w;
     a.pf = reinterpret_cast<float4 *>(W.rec);   // the flat path's record buffer (max_points x 16 B), unused here
+    a.x0max = W.flag;                           // the flat path's primary flags, unused here: one word
     a.n = n;
     a.p0 = p0;
     a.rows = rows;
@@ -476,7 +477,7 @@ npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const do
         npcf_status st = timer_begin(p, 0, t);
         if (st != NPCF_OK) return st;
     }
-    NPCF_TRY(launch_sphere(p->D, p->L, a, p->stream));
+    NPCF_TRY(launch_sphere(p->D, p->L, p->t.curv, a, p->stream));
     if (W.timed) {
         NPCF_TRY(hipEventRecord(t.b, p->stream));
         p->timers[0].push_back(t);

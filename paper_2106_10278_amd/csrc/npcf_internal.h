@@ -221,14 +221,15 @@ struct GridArgs {
 // ---------------------------------------------------------------------------
 constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
 struct SphereArgs {
-    const double *pos;          // [D + 1][n] unit vectors
+    const double *pos;          // [D + 1][n] unit vectors (sphere) or hyperboloid points (H^D)
     const double *w;            // [n]
     float4 *pf;                 // scratch [n]: S^2 (x, y, z, w), S^3 the coordinates, in FP32, written by launch_sphere
     int64_t n;
     int64_t p0;                 // primary of row 0
     int rows;
     int nb;
-    double cedge[kMaxBins + 1]; // cos of the edges (decreasing)
+    double cedge[kMaxBins + 1]; // the edges' cosines: cos e (sphere) or -cosh e (H^D), decreasing
+    unsigned *x0max;            // scratch word: largest x0 of the catalogue (H^D), written by launch_sphere
     float *A;                   // out: [rows][nb][2 nstate]
     float *wrow;                // out: [rows]
     unsigned long long *pairs;  // in-range pair counter
@@ -288,7 +289,7 @@ hipError_t launch_grid_weights(const double *field, int64_t ng, double dV, doubl
 hipError_t launch_grid_rows(const double2 *a, int64_t ng, int nbs, int nst, const uint8_t *sreal, const float *w32,
                             int64_t r0, int rows, float *A, float *wrow, hipStream_t s);
 hipError_t launch_add_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
-hipError_t launch_sphere(int D, int L, const SphereArgs &a, hipStream_t s);
+hipError_t launch_sphere(int D, int L, int K, const SphereArgs &a, hipStream_t s);
 // finalize from an accumulator index per output (N = 5): out[lam * nbt + t] =
 // acc[idx[lam * nbt + t]] * sign[lam] * bt_scale[t] (optionally over the randoms' Lambda = 0)
 hipError_t launch_finalize_idx(const double *acc, const double *acc_rand, const int *idx, const double *sign,
@@ -321,8 +322,9 @@ struct Tables {
     float bucket_lo = 0.f, bucket_inv = 0.f;
     float e2lo_f = 0.f, e2hi_f = 0.f;
     std::vector<double> vb;            // bin volumes (sphere: annulus areas)
-    bool sphere = false;               // points on the unit 2-sphere
-    std::vector<double> cedge;         // sphere: cos of the edges
+    bool sphere = false;               // a curved space, every secondary visited (no cell list)
+    int curv = 0;                      // its curvature sign: +1 the unit D-sphere, -1 hyperbolic space H^D
+    std::vector<double> cedge;         // curved: the edges' cosines, cos e or -cosh e (decreasing)
     int lam0 = 0;
     // factorised N = 4, D = 3 coupling (empty otherwise)
     std::vector<FPair> fpairs;

@@ -82,9 +82,17 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     if (!(cfg.edges[0] > 0.0)) { err = "edges[0] must be > 0"; return NPCF_E_INVALID; }
     for (int b = 0; b < nb; b++)
         if (!(cfg.edges[b + 1] > cfg.edges[b])) { err = "edges must increase strictly"; return NPCF_E_INVALID; }
-    if (cfg.geometry != NPCF_GEOMETRY_FLAT && cfg.geometry != NPCF_GEOMETRY_SPHERE) { err = "unknown geometry"; return NPCF_E_INVALID; }
-    t.sphere = cfg.geometry == NPCF_GEOMETRY_SPHERE;
-    if (t.sphere) {
+    if (cfg.geometry != NPCF_GEOMETRY_FLAT && cfg.geometry != NPCF_GEOMETRY_SPHERE &&
+        cfg.geometry != NPCF_GEOMETRY_HYPERBOLIC) { err = "unknown geometry"; return NPCF_E_INVALID; }
+    t.sphere = cfg.geometry != NPCF_GEOMETRY_FLAT;
+    t.curv = cfg.geometry == NPCF_GEOMETRY_SPHERE ? 1 : (cfg.geometry == NPCF_GEOMETRY_HYPERBOLIC ? -1 : 0);
+    if (t.curv < 0) {
+        if ((D != 2 && D != 3) || N > 4 || cfg.basis != NPCF_BASIS_ISOTROPIC) { err = "hyperbolic space needs D = 2 or 3, N = 3 or 4 and the isotropic basis"; return NPCF_E_UNSUPPORTED; }
+        if (L > kLmaxSphere) { err = "lmax above 5 in hyperbolic space"; return NPCF_E_UNSUPPORTED; }
+        if (!(std::cosh(cfg.edges[0]) >= 1.0 + 1e-9)) { err = "hyperbolic edges[0] too small: cosh(edges[0]) must be at least 1 + 1e-9"; return NPCF_E_INVALID; }
+        if (!(cfg.edges[nb] <= 20.0)) { err = "hyperbolic edges must not exceed 20"; return NPCF_E_INVALID; }
+        if (!(cfg.box[0] > 0.0) || !std::isfinite(cfg.box[0])) { err = "hyperbolic space needs the region's volume V > 0 in box[0]"; return NPCF_E_INVALID; }
+    } else if (t.sphere) {
         if ((D != 2 && D != 3) || N > 4 || cfg.basis != NPCF_BASIS_ISOTROPIC) { err = "the sphere needs D = 2 or 3, N = 3 or 4 and the isotropic basis"; return NPCF_E_UNSUPPORTED; }
         if (L > kLmaxSphere) { err = "lmax above 5 on the sphere"; return NPCF_E_UNSUPPORTED; }
         if (!(cfg.edges[nb] <= M_PI)) { err = "sphere edges must not exceed pi"; return NPCF_E_INVALID; }
@@ -229,7 +237,22 @@ npcf_status build_tables(const npcf_config &cfg, Tables &t, std::string &err)
     for (int b = 0; b < nb; b++) t.vb[b] = area * (std::pow(cfg.edges[b + 1], D) - std::pow(cfg.edges[b], D)) / D;
     double VD = 1.0;
     for (int k = 0; k < D; k++) VD *= cfg.box[k];
-    if (t.sphere) {
+    if (t.curv < 0) {
+        // bin volumes |S^{D-1}| int sinh^{D-1} r dr and the region's volume
+        t.cedge.resize(nb + 1);
+        for (int b = 0; b <= nb; b++) t.cedge[b] = -std::cosh(cfg.edges[b]);
+        for (int b = 0; b < nb; b++) {
+            if (D == 2) {
+                t.vb[b] = 2.0 * M_PI * (std::cosh(cfg.edges[b + 1]) - std::cosh(cfg.edges[b]));
+            } else {
+                // 4 pi int sinh^2 = 2 pi ((sinh 2 e1 - sinh 2 e0) / 2 - d), with the
+                // difference of sines as 2 cosh(e0 + e1) sinh d
+                const double d = cfg.edges[b + 1] - cfg.edges[b];
+                t.vb[b] = 2.0 * M_PI * (std::cosh(cfg.edges[b] + cfg.edges[b + 1]) * std::sinh(d) - d);
+            }
+        }
+        VD = cfg.box[0];
+    } else if (t.sphere) {
         // bin volumes |S^{D-1}| int sin^{D-1} r dr and the sphere's volume
         t.cedge.resize(nb + 1);
         for (int b = 0; b <= nb; b++) t.cedge[b] = std::cos(cfg.edges[b]);

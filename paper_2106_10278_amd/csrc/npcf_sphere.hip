@@ -1,25 +1,37 @@
-// Harmonic stage for points on the unit D-sphere, the constant-curvature
-// space of section "Constant-Curvature Metric" with k = 1 and chi(r) = sin r
-// (eq. metric): D = 2 is the unit 2-sphere of section "Cosmic Microwave
-// Background", D = 3 the unit 3-sphere.  The radial coordinate of a pair is
-// the geodesic angle theta_pq, the direction that of q in an orthonormal
-// tangent frame at p, and
+// Harmonic stage for points of a constant-curvature space (section
+// "Constant-Curvature Metric", eq. metric): K = +1, the unit D-sphere
+// (chi(r) = sin r; D = 2 is the sky of section "Cosmic Microwave Background",
+// D = 3 the unit 3-sphere), and K = -1, hyperbolic space H^D (chi(r) =
+// sinh r) on the hyperboloid x0^2 - x1^2 - .. - xD^2 = 1 of R^{D,1}.  The
+// radial coordinate of a pair is the geodesic distance theta_pq, the
+// direction that of q in an orthonormal tangent frame at p, and
 //   a^b_[l](p) = sum_q w_q conj(Y_[l](u_pq)) Theta^b(theta_pq)
 // (1/v_b at finalize, as on the flat path), for every secondary q: the bins of
 // the paper's CMB test reach 120 degrees, so a cell list would prune little.
-//  - theta: e_b <= theta < e_{b+1}  <=>  cos e_{b+1} < p.q <= cos e_b, on an
-//    FP64 dot product evaluated without contraction (the comparison matches a
-//    plain FP64 evaluation bit for bit);
+//  - theta: the kernel's "cosine" c is p.q on the sphere and -<p, q> =
+//    -p0 q0 + p1 q1 + .. in H^D (both fall as theta grows), and
+//    e_b <= theta < e_{b+1}  <=>  ce_{b+1} < c <= ce_b with ce_b = cos e_b
+//    or -cosh e_b, on an FP64 product evaluated left to right without
+//    contraction (negation is exact and rounding symmetric, so -<p, q>
+//    rounds to minus the oracle's <p, q> and the comparison matches a plain
+//    FP64 evaluation bit for bit);
 //  - frame, D = 2: e1 = unit(z x p) (unit(x x p) when |p_z| > 0.9), e2 = p x e1;
 //    D = 3, p = a + b i + c j + d k a unit quaternion: e1, e2, e3 = p i, p j,
 //    p k, i.e. (-b, a, d, -c), (-c, -d, a, b), (-d, c, -b, a), orthonormal,
 //    orthogonal to p and positively oriented everywhere;
-//    u = (q.e1, .., q.eD) / |(q.e1, .., q.eD)|.
+//    u = (q.e1, .., q.eD) / |(q.e1, .., q.eD)|;
+//  - frame in H^D: the Lorentz boost taking the origin to p applied to the
+//    coordinate axes, e_j(p) = (p_j, unit_j + p_j (p1..pD) / (1 + p0)), and
+//    u_j = -<q, e_j(p)>, i.e. the Euclidean product of q with e_j(p) whose
+//    time component is negated; the self pair is excluded by index (<p, p>
+//    rounds with an error that grows as cosh^2 r).
 // A block is 8 waves, one primary each; secondaries come through LDS in FP32
 // tiles (the points are packed to FP32 once per launch).  The FP32 cosine
 // decides the bin (through a bucket table where no edge is near, else against
-// the edge cosines) unless it lies within 1e-6 of an edge (its error is below
-// (D + 3) 2^-24 < 4e-7 for unit vectors), where the FP64 dot product decides, so the decisions
+// the edge cosines) unless it lies within a guard band of an edge: 1e-6 on the
+// sphere (the FP32 error is below (D + 3) 2^-24 < 4e-7 for unit vectors),
+// 1.5 x 2 (D + 3) 2^-24 x0max^2 in H^D (the terms sum to at most 2 p0 q0),
+// where the FP64 product decides, so the decisions
 // equal the FP64 ones.  In-range pairs are queued by catalogue index; the
 // harmonics take the tangent components from the FP64 positions in an FP64
 // frame, normalised in FP64 and rounded once to FP32.  As many bins as fit a
@@ -38,7 +50,7 @@ namespace {
 constexpr int kSphTile = 512;
 constexpr int kSphWaves = 8;
 constexpr int kSphFold = 4;         // tiles between folds of the lanes' FP32 sums
-constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64
+constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64 (at least)
 
 // real slots per bin: 2 per stored state (the imaginary slots of real states stay 0)
 __host__ __device__ constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * (L + 2); }
@@ -66,11 +78,21 @@ __device__ __forceinline__ double dot_rn(const double (&p)[D + 1], const double 
     return c;
 }
 
-// Orthonormal tangent frame at the unit vector p (rows e[0..D-1]), see the header.
-template <int D>
+// Orthonormal tangent frame at p (rows e[0..D-1]), see the header; in H^D
+// the rows carry their time component negated, so that a component of q is
+// the Euclidean product q . e[j].
+template <int D, int K>
 __device__ __forceinline__ void tangent_frame(const double (&p)[D + 1], double (&e)[D][D + 1])
 {
-    if constexpr (D == 2) {
+    if constexpr (K < 0) {
+        const double s = 1.0 / (1.0 + p[0]);
+#pragma unroll
+        for (int j = 1; j <= D; j++) {
+            e[j - 1][0] = -p[j];
+#pragma unroll
+            for (int x = 1; x <= D; x++) e[j - 1][x] = (x == j ? 1.0 : 0.0) + p[j] * p[x] * s;
+        }
+    } else if constexpr (D == 2) {
         double ax = 0.0, ay = 0.0, az = 1.0;
         if (fabs(p[2]) > 0.9) {
             ax = 1.0;
@@ -160,7 +182,7 @@ __device__ __forceinline__ void fold_lanes(const float *x, int lane, float &y0, 
     y1 = x0[1];
 }
 
-template <int D, int L>
+template <int D, int L, int K>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
     __shared__ float4 tile[kSphTile];
@@ -190,8 +212,18 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 #pragma unroll
     for (int x = 0; x <= D; x++) p[x] = a.pos[x * a.n + pi];
     double e[D][D + 1];
-    tangent_frame<D>(p, e);
-    float pf32[4] = {(float)p[0], (float)p[1], (float)p[2], D == 3 ? (float)p[D] : 0.f};
+    tangent_frame<D, K>(p, e);
+    // the "cosine" c = pc . q: p itself on the sphere, (-p0, p1, .., pD) in H^D
+    double pc[D + 1];
+#pragma unroll
+    for (int x = 0; x <= D; x++) pc[x] = (K < 0 && x == 0) ? -p[0] : p[x];
+    float pf32[4] = {(float)pc[0], (float)pc[1], (float)pc[2], D == 3 ? (float)pc[D] : 0.f};
+    // guard band of the FP32 cosine (see the header)
+    float guard = kSphGuard;
+    if constexpr (K < 0) {
+        const float xm = __uint_as_float(*a.x0max);
+        guard = fmaxf(kSphGuard, 1.5f * 2.f * (D + 3) * 5.9604645e-8f * xm * xm);
+    }
 
     unsigned long long cnt_pairs = 0;   // wave-uniform
     for (int b0 = 0; b0 < a.nb; b0 += G) {
@@ -208,8 +240,8 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         __syncthreads();
         for (int g = threadIdx.x; g <= ng; g += blockDim.x) sce[g] = (float)a.cedge[b0 + g];
         for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) {
-            const double lo = (double)clof + (k - 1) * (double)bw - 2.0 * kSphGuard;
-            const double hi = (double)clof + (k + 2) * (double)bw + 2.0 * kSphGuard;
+            const double lo = (double)clof + (k - 1) * (double)bw - 2.0 * guard;
+            const double hi = (double)clof + (k + 2) * (double)bw + 2.0 * guard;
             const double mid = (double)clof + (k + 0.5) * (double)bw;
             const float ck = clof + (k + 1) * bw;   // upper end of bucket k
             bool edge = false;
@@ -290,7 +322,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         // is always within the guard of it and decided in FP64
                         // (chif + guard rounded in FP32 would admit cosines up to
                         // one rounding beyond the guard)
-                        if (c32 - chif <= kSphGuard && clof - c32 < kSphGuard) {
+                        if (c32 - chif <= guard && clof - c32 < guard) {
                             // bin from the bucket table; near an edge, from the FP32
                             // cosine against the edges, and within the guard band of
                             // an edge from the FP64 dot product
@@ -303,16 +335,17 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                             if (ent & 0x80) {
                                 while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
                                 while (bl > 0 && c32 > sce[bl]) bl--;
-                                near = fabsf(c32 - sce[bl]) <= kSphGuard || fabsf(c32 - sce[bl + 1]) <= kSphGuard;
+                                near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
                             }
                             if (near) {
-                                const double c = dot_rn<D>(p, a.pos, a.n, t0 + i);
+                                const double c = dot_rn<D>(pc, a.pos, a.n, t0 + i);
                                 valid = c <= chi && c > clo;
                                 bl = 0;
                                 while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
                             }
                         }
                     }
+                    if constexpr (K < 0) valid = valid && (t0 + i != pi);   // the self pair, by index
                     const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
                     const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
@@ -381,46 +414,65 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 }
 
 // the points in FP32, once per launch: every block streams them all in every
-// pass.  S^2: (x, y, z, w); S^3: the four coordinates.
-template <int D>
-__global__ __launch_bounds__(256) void k_sphere_pack(const double *pos, const double *w, int64_t n, float4 *pf)
+// pass.  S^2 and H^2: (x0, x1, x2, w); S^3 and H^3: the four coordinates.  In
+// H^D also the largest x0 of the catalogue (as bits of a positive float,
+// whose order is the integers'), for the guard band.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_sphere_pack(const double *pos, const double *w, int64_t n, float4 *pf,
+                                                     unsigned *x0max)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
+    if (i < n) {
         pf[i] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i],
                             D == 2 ? (float)w[i] : (float)pos[3 * n + i]);
+        if constexpr (K < 0) {
+            // rounded up, so that the guard is never below the true one
+            const float x0 = __double2float_ru(pos[i]);
+            atomicMax(x0max, __float_as_uint(x0));
+        }
+    }
 }
 
-template <int D, int L>
+template <int D, int L, int K>
 hipError_t launch_l(const SphereArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sphere_pack<D>, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n, a.pf);
+    if (K < 0) {
+        hipError_t e = launch_fill_u32(a.x0max, 0u, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_sphere_pack<D, K>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n,
+                       a.pf, a.x0max);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
-    hipLaunchKernelGGL((k_sphere<D, L>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
+    hipLaunchKernelGGL((k_sphere<D, L, K>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 
-template <int D>
+template <int D, int K>
 hipError_t launch_d(int L, const SphereArgs &a, hipStream_t s)
 {
     switch (L) {
-    case 0: return launch_l<D, 0>(a, s);
-    case 1: return launch_l<D, 1>(a, s);
-    case 2: return launch_l<D, 2>(a, s);
-    case 3: return launch_l<D, 3>(a, s);
-    case 4: return launch_l<D, 4>(a, s);
-    case 5: return launch_l<D, 5>(a, s);
+    case 0: return launch_l<D, 0, K>(a, s);
+    case 1: return launch_l<D, 1, K>(a, s);
+    case 2: return launch_l<D, 2, K>(a, s);
+    case 3: return launch_l<D, 3, K>(a, s);
+    case 4: return launch_l<D, 4, K>(a, s);
+    case 5: return launch_l<D, 5, K>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_sphere(int D, int L, const SphereArgs &a, hipStream_t s)
+hipError_t launch_sphere(int D, int L, int K, const SphereArgs &a, hipStream_t s)
 {
     if (a.n <= 0 || a.rows <= 0) return hipSuccess;
-    if (D == 2) return launch_d<2>(L, a, s);
-    if (D == 3) return launch_d<3>(L, a, s);
+    if (K > 0) {
+        if (D == 2) return launch_d<2, 1>(L, a, s);
+        if (D == 3) return launch_d<3, 1>(L, a, s);
+    } else {
+        if (D == 2) return launch_d<2, -1>(L, a, s);
+        if (D == 3) return launch_d<3, -1>(L, a, s);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -25,6 +25,11 @@ turbulence simulations); none of those data sets is used.  Recipes:
 * ``sphere_points`` / ``s3_points`` -- n points uniform on the unit 2- or
   3-sphere (normalised Gaussian vectors); ``clustered_sphere`` -- Gaussian
   blobs projected onto the sphere plus a uniform background.
+* ``hyperbolic_ball`` / ``hyperbolic_clustered`` -- points of hyperbolic space
+  H^D on the hyperboloid x0^2 - |x|^2 = 1: uniform in a geodesic ball about
+  the origin (radius by inverse transform of the tabulated radial law
+  sinh^{D-1} r), and Gaussian blobs of tangent vectors at ball-uniform
+  centres carried there by the boost that moves the origin to the centre.
 * ``vorticity_tracers`` (D = 2) -- points drawn with density proportional to
   exp(omega) for a random-phase field omega on a grid, whose per-mode
   amplitude falls as 1/|k| (shell energy spectrum ~ k^-3), normalised to
@@ -123,6 +128,7 @@ class Workload:
     Lmax: object = None      # line-of-sight basis (D = 3, N = 3): largest L; None: isotropic
     field: object = None     # gridded data: the field on the grid (pos and w are then its nodes)
     sphere: bool = False     # points on the unit D-sphere: pos [D + 1][n] unit vectors, edges in radians
+    hyperbolic: bool = False  # points of H^D on the hyperboloid: pos [D + 1][n], box[0] = the region's volume
 
 
 def c1_small_3pcf(seed: int = 1001) -> Workload:
@@ -298,3 +304,61 @@ def c10_s3_4pcf(seed: int = 1010, n_blob: int = 90_000, n_uniform: int = 10_000)
     n = pos.shape[1]
     edges = np.linspace(math.pi / 6, math.pi / 2, 11)
     return Workload(f"S3-N4-clustered-{n // 1000}k", 3, 4, 5, edges, [1.0, 1.0, 1.0], pos, np.ones(n), n, sphere=True)
+
+
+def hyperbolic_ball(rng: np.random.Generator, D: int, n: int, R: float) -> np.ndarray:
+    """n points uniform (in the volume element sinh^{D-1} r dr dOmega) in the
+    geodesic ball of radius R about the origin of H^D: [D + 1][n] hyperboloid
+    coordinates (cosh r, sinh r * direction)."""
+    grid = np.linspace(0.0, R, 4097)
+    dens = np.sinh(grid) ** (D - 1)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (dens[1:] + dens[:-1]) * np.diff(grid))])
+    r = np.interp(rng.uniform(0.0, cdf[-1], size=n), cdf, grid)
+    d = rng.normal(size=(D, n))
+    d /= np.linalg.norm(d, axis=0)
+    return np.vstack([np.cosh(r), np.sinh(r) * d])
+
+
+def _boost_to(c: np.ndarray) -> np.ndarray:
+    """The Lorentz boost of R^{D,1} that takes the origin (1, 0, .., 0) to the
+    hyperboloid point c."""
+    D = len(c) - 1
+    B = np.eye(D + 1)
+    B[0, 0] = c[0]
+    B[0, 1:] = B[1:, 0] = c[1:]
+    B[1:, 1:] += np.outer(c[1:], c[1:]) / (1.0 + c[0])
+    return B
+
+
+def hyperbolic_clustered(rng: np.random.Generator, D: int, n_blob: int, n_uniform: int, n_centres: int,
+                         sigma: float, R: float) -> np.ndarray:
+    """Points of H^D: ``n_blob`` in blobs (a ball-uniform centre, one of
+    ``n_centres``, and a tangent vector with N(0, sigma^2) coordinates taken
+    along the geodesics from the centre), then ``n_uniform`` ball-uniform
+    points (radius R)."""
+    centres = hyperbolic_ball(rng, D, n_centres, R)
+    pick = rng.integers(0, n_centres, size=n_blob)
+    t = rng.normal(0.0, sigma, size=(D, n_blob))
+    r = np.linalg.norm(t, axis=0)
+    local = np.vstack([np.cosh(r), np.sinh(r) * t / r])
+    blob = np.empty_like(local)
+    for c in range(n_centres):
+        sel = pick == c
+        blob[:, sel] = _boost_to(centres[:, c]) @ local[:, sel]
+    return np.concatenate([blob, hyperbolic_ball(rng, D, n_uniform, R)], axis=1)
+
+
+def c11_h3_4pcf(seed: int = 1011, n_blob: int = 80_000, n_uniform: int = 20_000) -> Workload:
+    """D=3, N=4 in hyperbolic space H^3 (curvature k = -1): 100k points, 80k in
+    40 blobs of 0.15 and 20k uniform in the geodesic ball of radius 1.5, w = 1,
+    10 bins equal in geodesic distance over [0.1, 0.9], lmax = 5; V = the
+    ball's volume pi (sinh 3 - 3).  Defined here: the paper gives the
+    constant-curvature estimator without a workload on it."""
+    rng = np.random.default_rng(seed)
+    R = 1.5
+    pos = hyperbolic_clustered(rng, 3, n_blob, n_uniform, 40, 0.15, R)
+    n = pos.shape[1]
+    V = math.pi * (math.sinh(2 * R) - 2 * R)
+    edges = np.linspace(0.1, 0.9, 11)
+    return Workload(f"H3-N4-clustered-{n // 1000}k", 3, 4, 5, edges, [V, 1.0, 1.0], pos, np.ones(n), n,
+                    hyperbolic=True)

@@ -26,8 +26,12 @@ def condition_scale(wl, btuple_mode=0, prims=None, periodic=True, Lmax=None):
     roundoff u has forward error bounded by about u times this scale, so errors
     are judged against it where the multipole itself cancels."""
     sphere = getattr(wl, "sphere", False)
-    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic, sphere=sphere)
-    if sphere:
+    hyp = getattr(wl, "hyperbolic", False)
+    a, _ = oracle.alm(wl.D, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims, periodic=periodic, sphere=sphere,
+                      hyperbolic=hyp)
+    if hyp:
+        V = float(wl.box[0])   # the region's volume
+    elif sphere:
         V = 4 * np.pi if wl.D == 2 else 2 * np.pi ** 2   # the unit 2- or 3-sphere's volume
     else:
         V = float(np.prod(np.asarray(wl.box, dtype=np.float64)[: wl.D]))
@@ -66,7 +70,8 @@ def conditioned_error(got, ref, scale):
 
 def oracle_reported(wl, prims=None, btuple_mode=0, Lmax=None):
     z, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, prims=prims,
-                           btuple_mode=btuple_mode, Lmax=Lmax, sphere=getattr(wl, "sphere", False))
+                           btuple_mode=btuple_mode, Lmax=Lmax, sphere=getattr(wl, "sphere", False),
+                           hyperbolic=getattr(wl, "hyperbolic", False))
     labels = oracle.lambda_labels(wl.D, wl.N, wl.lmax, Lmax)
     return oracle.reported_part(z, labels, wl.D, wl.N, los=Lmax is not None), pairs, z
 
@@ -79,7 +84,8 @@ def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", 
     n = wl.pos.shape[1]
     if plan is None:
         plan = NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, btuple_mode=btuple_mode, precision=precision,
-                    max_points=n, Lmax=Lmax, sphere=getattr(wl, "sphere", False))
+                    max_points=n, Lmax=Lmax, sphere=getattr(wl, "sphere", False),
+                    hyperbolic=getattr(wl, "hyperbolic", False))
     if ranges is None:
         ranges = [(0, n)]
     for a, b in ranges:
@@ -89,7 +95,7 @@ def gpu_run(wl, ranges=None, precision="plain", btuple_mode=0, device="cuda:0", 
     return out, pairs, plan
 
 
-def alm_error(got, ref, wl, prims, D, lmax, sphere=False):
+def alm_error(got, ref, wl, prims, D, lmax, sphere=False, hyperbolic=False):
     """Largest |got - ref| of a^b_[l] values, each over a bound on the sum of
     the magnitudes of its terms: |w_k conj(Y_s)| <= |w_k| sqrt(dim_l / |S^{D-1}|)
     (the addition theorem bounds every harmonic of order l), so with
@@ -99,7 +105,8 @@ def alm_error(got, ref, wl, prims, D, lmax, sphere=False):
     own scale rather than to the largest |a|.  `got` and `ref` are in the
     library's stored-state order, [prim][bin][state]."""
     from paper_2106_10278_amd import stored_state_labels
-    a_abs, _ = oracle.alm(D, lmax, wl.edges, wl.box, wl.pos, np.abs(wl.w), prims=prims, sphere=sphere)
+    a_abs, _ = oracle.alm(D, lmax, wl.edges, wl.box, wl.pos, np.abs(wl.w), prims=prims, sphere=sphere,
+                          hyperbolic=hyperbolic)
     olab = [tuple(int(x) for x in r) for r in oracle.state_labels(D, lmax)]
     zero = (0,) if D == 2 else ((0, 0) if D == 3 else (0, 0, 0))
     A0 = np.abs(a_abs[:, :, olab.index(zero)])

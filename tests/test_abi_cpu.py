@@ -93,7 +93,13 @@ def _plan(lib, **kw):
     (dict(geometry=1, D=3, edges=[1.0, 2.0, 3.5]), binding.NPCF_E_INVALID),
     (dict(geometry=1, D=3, edges=[1e-9, 1.0, 2.0]), binding.NPCF_E_INVALID),
     (dict(geometry=1, D=2, edges=[1e-9, 1.0, 2.0]), binding.NPCF_E_INVALID),
-    (dict(geometry=2), binding.NPCF_E_INVALID),
+    # hyperbolic space: D = 2 or 3, cosh(edges[0]) >= 1 + 1e-9, edges up to 20, V = box[0] > 0
+    (dict(geometry=2, D=4), binding.NPCF_E_UNSUPPORTED),
+    (dict(geometry=2, D=3, lmax=6), binding.NPCF_E_UNSUPPORTED),
+    (dict(geometry=2, D=3, edges=[1e-6, 1.0, 2.0]), binding.NPCF_E_INVALID),
+    (dict(geometry=2, D=3, edges=[1.0, 2.0, 25.0]), binding.NPCF_E_INVALID),
+    (dict(geometry=2, D=3, box=[0.0, 1.0, 1.0, 1.0]), binding.NPCF_E_INVALID),
+    (dict(geometry=3), binding.NPCF_E_INVALID),
 ])
 def test_plan_validation(lib, kw, expect):
     assert _plan(lib, **kw) == expect
@@ -115,6 +121,7 @@ def test_valid_plan_needs_a_device(lib):
         pytest.skip("a GPU is present")
     assert _plan(lib) == binding.NPCF_E_DEVICE
     assert _plan(lib, geometry=1, D=3, lmax=5, edges=[0.5, 1.0, 1.5]) == binding.NPCF_E_DEVICE
+    assert _plan(lib, geometry=2, D=3, lmax=5, edges=[0.5, 1.0, 1.5]) == binding.NPCF_E_DEVICE
 
 
 def test_single_hip_runtime_per_process():
