@@ -69,6 +69,10 @@ struct Workspace {
     double *partial = nullptr;
     int64_t partial_len = 0;
     unsigned int *work = nullptr;
+    // curved spaces: the secondaries in spatial order and their tile caps
+    double *pos64 = nullptr;  // [4][max_points]
+    float *caps = nullptr;    // [tiles][8]
+    unsigned *bbox = nullptr; // [8] key-axis bounds, [8] the largest x0 (H^D)
     int64_t rows_cap = 0;    // primaries per chunk (rows of a held at once)
     bool growable = true;    // the partial buffer may be re-allocated (plan-owned set only)
     bool timed = true;       // record stage events (the static path creates none)
@@ -105,6 +109,7 @@ struct npcf_plan_s {
     int harm_bpc = 0;     // persistent harmonic grid: blocks per compute unit (0: automatic, 8)
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
+    int curved_bits = 0;       // curved spaces: bits per axis of the Morton cells of the spatial sort
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
@@ -179,6 +184,16 @@ hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s)
 
 void compute_grid(npcf_plan_s *p)
 {
+    if (p->t.sphere) {
+        // no cell list: the Morton cells that put the secondaries in spatial
+        // order, 2^14 to 2^16 of them over the key axes (all D + 1
+        // coordinates on the sphere, the D spatial ones in H^D)
+        const int axes = p->t.curv > 0 ? p->D + 1 : p->D;
+        p->curved_bits = axes == 2 ? 7 : (axes == 3 ? 5 : 4);
+        p->ncell = (int64_t)1 << (p->curved_bits * axes);
+        for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
+        return;
+    }
     const double rmax = p->edges[p->nb];
     int64_t total = 1;
     for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
@@ -463,7 +478,24 @@ npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const do
     a.pos = pos;
     a.w = w;
     a.pf = reinterpret_cast<float4 *>(W.rec);   // the flat path's record buffer (max_points x 16 B), unused here
-    a.x0max = W.flag;                           // the flat path's primary flags, unused here: one word
+    a.x0max = W.bbox + 8;
+    a.spos = W.pos64;
+    a.sw = W.w64s;
+    a.sorig = W.orig;
+    a.caps = W.caps;
+    a.key = W.cell;
+    a.count = W.count;
+    a.cell_start = W.cell_start;
+    a.cursor = W.cursor;
+    a.scan = W.scan_scratch;
+    a.scan_len = W.scan_scratch_len;
+    a.perm = W.perm;
+    a.bbox = W.bbox;
+    a.prim = W.prim;
+    a.pflag = W.flag;
+    a.ppos = W.flagpos;
+    a.ncell_bits = p->curved_bits;
+    for (int b = 0; b <= p->nb; b++) a.erad[b] = (float)p->edges[b];
     a.n = n;
     a.p0 = p0;
     a.rows = rows;
@@ -1234,6 +1266,11 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->wk.prim = m.get<int32_t>(max_points);
     p->wk.ws = m.get<float>(max_points);
     p->wk.w64s = m.get<double>(max_points);
+    if (t.sphere) {
+        p->wk.pos64 = m.get<double>((size_t)4 * max_points);
+        p->wk.caps = m.get<float>((size_t)8 * ((max_points + kSphTile - 1) / kSphTile + 1));
+        p->wk.bbox = m.get<unsigned>(12);   // key-axis bounds [8], then the largest x0
+    }
     p->wk.flag = m.get<uint32_t>(max_points);
     p->wk.flagpos = m.get<uint32_t>(max_points);
     const int64_t rowbytes = (int64_t)p->nb * 2 * t.nstate * sizeof(float);

@@ -220,16 +220,37 @@ struct GridArgs {
 // Points on the unit 2-sphere (npcf_sphere.hip).
 // ---------------------------------------------------------------------------
 constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
+// curved spaces: secondaries per LDS tile of the all-pairs kernel (and per tile cap)
+constexpr int kSphTile = 512;
+
 struct SphereArgs {
     const double *pos;          // [D + 1][n] unit vectors (sphere) or hyperboloid points (H^D)
     const double *w;            // [n]
     float4 *pf;                 // scratch [n]: S^2 (x, y, z, w), S^3 the coordinates, in FP32, written by launch_sphere
     int64_t n;
-    int64_t p0;                 // primary of row 0
+    int64_t p0;                 // primary of row 0: rows [0, rows) are primaries p0 + [0, rows)
     int rows;
     int nb;
     double cedge[kMaxBins + 1]; // the edges' cosines: cos e (sphere) or -cosh e (H^D), decreasing
     unsigned *x0max;            // scratch word: largest x0 of the catalogue (H^D), written by launch_sphere
+    // secondaries in spatial order (Morton cells), written by launch_sphere:
+    // FP64 coordinates [D + 1][n], FP64 weights, original index, and per tile
+    // of kSphTile points a bounding cap (centre [4], radius in geodesic distance)
+    double *spos;
+    double *sw;
+    int32_t *sorig;
+    float *caps;                // [ntiles][8]
+    uint32_t *key, *count, *cell_start, *cursor, *scan;  // sort scratch (cells: ncell + 1)
+    int32_t *perm;
+    int64_t scan_len;
+    int ncell_bits;             // bits per axis of the Morton cells
+    unsigned *bbox;             // [8] ordered-float min/max of the key axes (H^D)
+    // the primaries p0 + [0, rows) in the same spatial order (positions in it),
+    // so that the waves of a block take nearby primaries and meet similar
+    // tiles: prim [rows], and the compaction's flags and offsets [n]
+    int32_t *prim;
+    uint32_t *pflag, *ppos;
+    float erad[kMaxBins + 1];   // the edges (geodesic distance), for the tile test
     float *A;                   // out: [rows][nb][2 nstate]
     float *wrow;                // out: [rows]
     unsigned long long *pairs;  // in-range pair counter

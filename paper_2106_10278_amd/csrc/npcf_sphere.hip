@@ -26,20 +26,28 @@
 //    time component is negated; the self pair is excluded by index (<p, p>
 //    rounds with an error that grows as cosh^2 r).
 // A block is 8 waves, one primary each; secondaries come through LDS in FP32
-// tiles (the points are packed to FP32 once per launch).  The FP32 cosine
+// tiles.  Once per launch the secondaries are put in spatial order (a counting
+// sort by Morton cell of the embedding coordinates: all D + 1 on the sphere,
+// the D spatial ones in H^D, ranked within a cell by catalogue index) and
+// packed to FP32, and every tile gets a bounding cap (centre, largest
+// distance r); a wave skips a tile when the cap's distance range [d - r,
+// d + r] from its primary misses the pass's bins by more than a margin that
+// covers the FP32 errors of d and r.  The primaries of the launch take the
+// same order, so that the waves of a block (which load each tile together)
+// have nearby primaries and skip and fill the same tiles.  The FP32 cosine
 // decides the bin (through a bucket table where no edge is near, else against
 // the edge cosines) unless it lies within a guard band of an edge: 1e-6 on the
 // sphere (the FP32 error is below (D + 3) 2^-24 < 4e-7 for unit vectors),
 // 1.5 x 2 (D + 3) 2^-24 x0max^2 in H^D (the terms sum to at most 2 p0 q0),
 // where the FP64 product decides, so the decisions
-// equal the FP64 ones.  In-range pairs are queued by catalogue index; the
+// equal the FP64 ones.  In-range pairs are queued by sorted index; the
 // harmonics take the tangent components from the FP64 positions in an FP64
 // frame, normalised in FP64 and rounded once to FP32.  As many bins as fit a
 // register budget are taken per pass (more passes rescan the points, but
 // fewer registers let more waves share a SIMD and each queued pair feeds
 // fewer masked sums); each lane sums harmonics in FP32 (a 0/1 mask per bin)
-// and every few tiles the wave reduces its lanes into FP64 values held one or
-// two per lane.
+// and every few batches the wave reduces its lanes into FP64 values held one
+// or two per lane.
 #include "npcf_internal.h"
 #include "npcf_harmonics.h"
 
@@ -47,9 +55,13 @@ namespace npcf {
 
 namespace {
 
-constexpr int kSphTile = 512;
 constexpr int kSphWaves = 8;
-constexpr int kSphFold = 4;         // tiles between folds of the lanes' FP32 sums
+// queued batches between folds of the lanes' FP32 sums into FP64.  In
+// spatial order the pairs of a run of batches share bin and sign, so a
+// rounding in the fold weighs on the whole run: the fold comes after a fixed
+// number of batches (not of tiles, which can each hold several), and its
+// top steps add in FP64.
+constexpr int kSphFoldBatches = 4;
 constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64 (at least)
 
 // real slots per bin: 2 per stored state (the imaginary slots of real states stay 0)
@@ -148,14 +160,34 @@ __device__ __forceinline__ void fold_step(const float *v, float *out, bool bit)
     }
 }
 
+// The same step on FP64 values: the lane keeps one of each pair and adds the
+// partner's copy of it, moved by DPP as two 32-bit halves
+template <int N, int CTRL>
+__device__ __forceinline__ void fold_step64(const double *v, double *out, bool bit)
+{
+    constexpr int H = N / 4;
+#pragma unroll
+    for (int q = 0; q < N / 2; q++) {
+        const int lo = (q & (H - 1)) | ((q & ~(H - 1)) << 1);
+        const double keep = bit ? v[lo + H] : v[lo], send = bit ? v[lo] : v[lo + H];
+        const unsigned long long sb = (unsigned long long)__double_as_longlong(send);
+        const unsigned plo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)sb, CTRL, 0xF, 0xF, false);
+        const unsigned phi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(sb >> 32), CTRL, 0xF, 0xF, false);
+        out[q] = keep + __longlong_as_double((long long)(((unsigned long long)phi << 32) | plo));
+    }
+}
+
 // Sum of each of the NG (<= 128) values x[j] over the 64 lanes of the wave,
 // scattered: lane l receives the totals of values l (y0) and l + 64 (y1; zero
 // past NG).  A butterfly that halves the values at each step: lane bit 5
 // through v_permlane32_swap, bit 4 through v_permlane16_swap, bits 3 to 0
 // through DPP.  At each step the lane keeps the values whose index bit
 // matches its lane bit, so after six steps lane l holds value l and l + 64.
+// The last three steps add in FP64: in spatial order the lanes' sums of one
+// bin share their sign, and a rounding in the top steps, where one or two
+// partial sums carry the whole total, weighs most on it.
 template <int NG>
-__device__ __forceinline__ void fold_lanes(const float *x, int lane, float &y0, float &y1)
+__device__ __forceinline__ void fold_lanes(const float *x, int lane, double &y0, double &y1)
 {
     static_assert(NG <= 128, "at most two values per lane");
     float z[64];
@@ -173,13 +205,179 @@ __device__ __forceinline__ void fold_lanes(const float *x, int lane, float &y0, 
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(z[i]), __float_as_uint(z[i + 16]), false, false);
         w[q] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    float x3[16], x2[8], x1[4], x0[2];
+    float x3[16];
     fold_step<32, 0x128>(w, x3, (lane & 8) != 0);    // row_ror:8
-    fold_step<16, 0x141>(x3, x2, (lane & 4) != 0);   // row_half_mirror
-    fold_step<8, 0x4E>(x2, x1, (lane & 2) != 0);     // quad_perm [2,3,0,1]
-    fold_step<4, 0xB1>(x1, x0, (lane & 1) != 0);     // quad_perm [1,0,3,2]
+    double d3[16], x2[8], x1[4], x0[2];
+#pragma unroll
+    for (int q = 0; q < 16; q++) d3[q] = (double)x3[q];
+    fold_step64<16, 0x141>(d3, x2, (lane & 4) != 0);   // row_half_mirror
+    fold_step64<8, 0x4E>(x2, x1, (lane & 2) != 0);     // quad_perm [2,3,0,1]
+    fold_step64<4, 0xB1>(x1, x0, (lane & 1) != 0);     // quad_perm [1,0,3,2]
     y0 = x0[0];
     y1 = x0[1];
+}
+
+// ---- spatial order and tile caps -------------------------------------------
+
+// the key axes: every coordinate on the sphere, the spatial ones in H^D
+template <int D, int K>
+__host__ __device__ constexpr int key_axes() { return K > 0 ? D + 1 : D; }
+
+// float bits whose unsigned order is the order of the floats
+__device__ __forceinline__ unsigned ord_bits(float f)
+{
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_float(unsigned u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// H^D: per-axis minimum and maximum of the spatial coordinates (bbox[a],
+// bbox[4 + a], as ordered bits), reduced over the block before the atomics
+template <int D>
+__global__ __launch_bounds__(256) void k_curved_bounds(const double *pos, int64_t n, unsigned *bbox)
+{
+    __shared__ unsigned smin[4][256], smax[4][256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const unsigned o = i < n ? ord_bits((float)pos[(a + 1) * n + i]) : 0u;
+        smin[a][threadIdx.x] = i < n ? o : 0xFFFFFFFFu;
+        smax[a][threadIdx.x] = o;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int a = 0; a < D; a++) {
+                smin[a][threadIdx.x] = min(smin[a][threadIdx.x], smin[a][threadIdx.x + h]);
+                smax[a][threadIdx.x] = max(smax[a][threadIdx.x], smax[a][threadIdx.x + h]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            atomicMin(&bbox[a], smin[a][0]);
+            atomicMax(&bbox[4 + a], smax[a][0]);
+        }
+}
+
+// Morton cell of every point (bits per axis over [-1, 1] on the sphere, over
+// the bounding box in H^D) and the cells' histogram
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_curved_keys(const double *pos, int64_t n, const unsigned *bbox, int bits,
+                                                     uint32_t *key, uint32_t *count)
+{
+    constexpr int A = key_axes<D, K>();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = 1 << bits;
+    uint32_t k = 0;
+#pragma unroll
+    for (int a = 0; a < A; a++) {
+        const float x = (float)pos[(K > 0 ? a : a + 1) * n + i];
+        const float lo = K > 0 ? -1.f : ord_float(bbox[a]);
+        const float hi = K > 0 ? 1.f : ord_float(bbox[4 + a]);
+        const float span = hi > lo ? hi - lo : 1.f;
+        int c = (int)((x - lo) / span * (float)m);
+        c = c < 0 ? 0 : (c >= m ? m - 1 : c);
+        for (int b = 0; b < bits; b++) k |= (uint32_t)((c >> b) & 1) << (b * A + a);
+    }
+    key[i] = k;
+    atomicAdd(&count[k], 1u);
+}
+
+// the sorted copies: FP64 coordinates and weights, FP32 packed points (S^2 and H^2: (x0, x1, x2, w); D = 3: the four coordinates);
+// in H^D also the largest x0 (rounded up, reduced over the block first)
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_curved_gather(const double *pos, const double *w, int64_t n,
+                                                       const int32_t *perm_sorted, double *spos, double *sw,
+                                                       float4 *pf, unsigned *x0max)
+{
+    __shared__ unsigned smax[256];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned mx = 0;
+    if (j < n) {
+        const int64_t i = perm_sorted[j];
+#pragma unroll
+        for (int x = 0; x <= D; x++) spos[x * n + j] = pos[x * n + i];
+        sw[j] = w[i];
+        pf[j] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i],
+                            D == 2 ? (float)w[i] : (float)pos[3 * n + i]);
+        if constexpr (K < 0) mx = __float_as_uint(__double2float_ru(pos[i]));
+    }
+    if constexpr (K < 0) {
+        smax[threadIdx.x] = mx;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + h]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) atomicMax(x0max, smax[0]);
+    }
+}
+
+// one block per tile of kSphTile sorted points: the cap's centre (the
+// normalised sum, Euclidean on the sphere, Minkowski in H^D) and its largest
+// geodesic distance from the centre
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n, float *caps)
+{
+    __shared__ float red[4][256];
+    const int64_t t0 = (int64_t)blockIdx.x * kSphTile;
+    const int cnt = (int)(n - t0 < kSphTile ? n - t0 : kSphTile);
+    float sum[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const float4 q = pf[t0 + i];
+        sum[0] += q.x;
+        sum[1] += q.y;
+        sum[2] += q.z;
+        if (D == 3) sum[3] += q.w;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; x++) red[x][threadIdx.x] = sum[x];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int x = 0; x < 4; x++) red[x][threadIdx.x] += red[x][threadIdx.x + h];
+        __syncthreads();
+    }
+    float c[4] = {red[0][0], red[1][0], red[2][0], red[3][0]};
+    float nn;
+    if constexpr (K > 0) nn = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3];
+    else nn = c[0] * c[0] - c[1] * c[1] - c[2] * c[2] - c[3] * c[3];
+    const float inv = nn > 0.f ? rsqrtf(nn) : 0.f;
+#pragma unroll
+    for (int x = 0; x < 4; x++) c[x] *= inv;
+    __syncthreads();
+    // the extreme "cosine": min c.q on the sphere, max <c, q> in H^D
+    float ext = K > 0 ? 1.f : 1.f;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const float4 q = pf[t0 + i];
+        const float q3 = D == 3 ? q.w : 0.f;
+        if constexpr (K > 0) ext = fminf(ext, c[0] * q.x + c[1] * q.y + c[2] * q.z + c[3] * q3);
+        else ext = fmaxf(ext, c[0] * q.x - c[1] * q.y - c[2] * q.z - c[3] * q3);
+    }
+    red[0][threadIdx.x] = ext;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[0][threadIdx.x] = K > 0 ? fminf(red[0][threadIdx.x], red[0][threadIdx.x + h])
+                                        : fmaxf(red[0][threadIdx.x], red[0][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float *cp = caps + blockIdx.x * 8;
+#pragma unroll
+        for (int x = 0; x < 4; x++) cp[x] = c[x];
+        const float e = red[0][0];
+        cp[4] = (inv > 0.f) ? (K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, e))) : acoshf(fmaxf(1.f, e))) : 1e30f;
+        cp[5] = cp[6] = cp[7] = 0.f;
+    }
 }
 
 template <int D, int L, int K>
@@ -207,10 +405,14 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * kSphWaves + wave;
     const bool active = row < a.rows;
-    const int64_t pi = a.p0 + (active ? row : 0);
+    // the primary: its place in the spatial order, its catalogue index and
+    // its output row
+    const int64_t js = active ? a.prim[row] : 0;
+    const int64_t pi = a.sorig[js];
+    const int64_t orow = pi - a.p0;
     double p[D + 1];
 #pragma unroll
-    for (int x = 0; x <= D; x++) p[x] = a.pos[x * a.n + pi];
+    for (int x = 0; x <= D; x++) p[x] = a.spos[x * a.n + js];
     double e[D][D + 1];
     tangent_frame<D, K>(p, e);
     // the "cosine" c = pc . q: p itself on the sphere, (-p0, p1, .., pD) in H^D
@@ -224,12 +426,18 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         const float xm = __uint_as_float(*a.x0max);
         guard = fmaxf(kSphGuard, 1.5f * 2.f * (D + 3) * 5.9604645e-8f * xm * xm);
     }
+    // margin of the tile test: the FP32 "cosines" of d and of the cap radius
+    // err by at most the guard, and acos / acosh turn an error g near the
+    // ends of their range into at most sqrt(2 g) in distance (plus the
+    // functions' own few ulps)
+    const float cull_margin = 2e-3f + 2.f * sqrtf(2.f * guard);
 
     unsigned long long cnt_pairs = 0;   // wave-uniform
     for (int b0 = 0; b0 < a.nb; b0 += G) {
         const int ng = min(G, a.nb - b0);
         const double chi = a.cedge[b0], clo = a.cedge[b0 + ng];
         const float chif = (float)chi, clof = (float)clo;
+        const float dlo = a.erad[b0] - cull_margin, dhi = a.erad[b0 + ng] + cull_margin;
         double acc0 = 0.0, acc1 = 0.0;   // FP64 sums of values lane and lane + 64
         float fs[G][NV];
 #pragma unroll
@@ -257,8 +465,20 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             sbk[k] = (unsigned char)(edge ? (0x80 | bg) : b);
         }
         __syncthreads();
-        int tiles = 0;
-        int qn = 0;   // queued pairs (wave-uniform)
+        int batches = 0;   // batches since the last fold (wave-uniform)
+        int qn = 0;        // queued pairs (wave-uniform)
+        // the lanes' FP32 sums into the FP64 values
+        auto fold = [&]() {
+            double y0, y1;
+            fold_lanes<NG>(&fs[0][0], lane, y0, y1);
+            acc0 += y0;
+            acc1 += y1;
+#pragma unroll
+            for (int g = 0; g < G; g++)
+#pragma unroll
+                for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
+            batches = 0;
+        };
         // harmonics of the first cnt queued pairs, one per lane, into the bin sums
         auto process = [&](int cnt) {
             const bool live = lane < cnt;
@@ -269,10 +489,10 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             // enters the l-th harmonic about l times)
             double q[D + 1];
 #pragma unroll
-            for (int x = 0; x <= D; x++) q[x] = live ? a.pos[x * a.n + k] : 0.0;
+            for (int x = 0; x <= D; x++) q[x] = live ? a.spos[x * a.n + k] : 0.0;
             float wq = 0.f;
             if constexpr (D == 2) wq = live ? qw[wave][lane] : 0.f;
-            else wq = live ? (float)a.w[k] : 0.f;
+            else wq = live ? (float)a.sw[k] : 0.f;
             double t[D];
             double tn2 = 0.0;
 #pragma unroll
@@ -306,7 +526,16 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
             __syncthreads();
             for (int i = threadIdx.x; i < cnt_t; i += blockDim.x) tile[i] = a.pf[t0 + i];
             __syncthreads();
-            if (active) {
+            // the tile's cap against this pass's distances (wave-uniform)
+            bool reach = true;
+            {
+                const float *cp = a.caps + (t0 / kSphTile) * 8;
+                const float cd = pf32[0] * cp[0] + pf32[1] * cp[1] + pf32[2] * cp[2] + pf32[3] * cp[3];
+                const float d = K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, cd))) : acoshf(fmaxf(1.f, -cd));
+                const float r = cp[4];
+                reach = !(d - r > dhi || d + r < dlo);
+            }
+            if (active && reach) {
                 // scan: bin of every point; in-range pairs go to the wave's queue
                 for (int i0 = 0; i0 < cnt_t; i0 += 64) {
                     const int i = i0 + lane;
@@ -338,14 +567,14 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                                 near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
                             }
                             if (near) {
-                                const double c = dot_rn<D>(pc, a.pos, a.n, t0 + i);
+                                const double c = dot_rn<D>(pc, a.spos, a.n, t0 + i);
                                 valid = c <= chi && c > clo;
                                 bl = 0;
                                 while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
                             }
                         }
                     }
-                    if constexpr (K < 0) valid = valid && (t0 + i != pi);   // the self pair, by index
+                    if constexpr (K < 0) valid = valid && (t0 + i != js);   // the self pair, by index
                     const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
                     const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
@@ -374,26 +603,19 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                             qbin[wave][lane] = mb;
                         }
                         qn = rest;
+                        if (++batches == kSphFoldBatches) fold();
                     }
                 }
             }
-            // every kSphFold tiles and at the end: lanes' FP32 sums into the FP64 values
+            // at the end: the last queued pairs, and the last fold
             const bool last = t0 + kSphTile >= a.n;
-            if (last && active && qn > 0) {
-                NPCF_SPH_WAVE_SYNC();
-                process(qn);
-                qn = 0;
-            }
-            if (++tiles == kSphFold || last) {
-                tiles = 0;
-                float y0, y1;
-                fold_lanes<NG>(&fs[0][0], lane, y0, y1);
-                acc0 += (double)y0;
-                acc1 += (double)y1;
-#pragma unroll
-                for (int g = 0; g < G; g++)
-#pragma unroll
-                    for (int v = 0; v < NV; v++) fs[g][v] = 0.f;
+            if (last && active) {
+                if (qn > 0) {
+                    NPCF_SPH_WAVE_SYNC();
+                    process(qn);
+                    qn = 0;
+                }
+                fold();
             }
         }
         if (active) {
@@ -402,46 +624,41 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                 const int j = lane + 64 * h;
                 if (j < NG) {
                     const int g = j / NV, v = j - g * NV;
-                    if (g < ng) a.A[((int64_t)row * a.nb + b0 + g) * NV + v] = (float)(h ? acc1 : acc0);
+                    if (g < ng) a.A[(orow * a.nb + b0 + g) * NV + v] = (float)(h ? acc1 : acc0);
                 }
             }
         }
     }
     if (active && lane == 0) {
         atomicAdd(a.pairs, cnt_pairs);
-        a.wrow[row] = (float)a.w[pi];
-    }
-}
-
-// the points in FP32, once per launch: every block streams them all in every
-// pass.  S^2 and H^2: (x0, x1, x2, w); S^3 and H^3: the four coordinates.  In
-// H^D also the largest x0 of the catalogue (as bits of a positive float,
-// whose order is the integers'), for the guard band.
-template <int D, int K>
-__global__ __launch_bounds__(256) void k_sphere_pack(const double *pos, const double *w, int64_t n, float4 *pf,
-                                                     unsigned *x0max)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        pf[i] = make_float4((float)pos[i], (float)pos[n + i], (float)pos[2 * n + i],
-                            D == 2 ? (float)w[i] : (float)pos[3 * n + i]);
-        if constexpr (K < 0) {
-            // rounded up, so that the guard is never below the true one
-            const float x0 = __double2float_ru(pos[i]);
-            atomicMax(x0max, __float_as_uint(x0));
-        }
+        a.wrow[orow] = (float)a.w[pi];
     }
 }
 
 template <int D, int L, int K>
 hipError_t launch_l(const SphereArgs &a, hipStream_t s)
 {
-    if (K < 0) {
-        hipError_t e = launch_fill_u32(a.x0max, 0u, 1, s);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_sphere_pack<D, K>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a.pos, a.w, a.n,
-                       a.pf, a.x0max);
+    constexpr int A = key_axes<D, K>();
+    const int64_t ncell = (int64_t)1 << (a.ncell_bits * A);
+    const unsigned g = (unsigned)((a.n + 255) / 256);
+    hipError_t e = launch_fill_u32(a.count, 0u, ncell + 1, s);
+    if (e == hipSuccess && K < 0) e = launch_fill_u32(a.x0max, 0u, 1, s);
+    if (e == hipSuccess && K < 0) e = launch_fill_u32(a.bbox, 0xFFFFFFFFu, 4, s);
+    if (e == hipSuccess && K < 0) e = launch_fill_u32(a.bbox + 4, 0u, 4, s);
+    if (e != hipSuccess) return e;
+    if (K < 0) hipLaunchKernelGGL((k_curved_bounds<D>), dim3(g), dim3(256), 0, s, a.pos, a.n, a.bbox);
+    hipLaunchKernelGGL((k_curved_keys<D, K>), dim3(g), dim3(256), 0, s, a.pos, a.n, a.bbox, a.ncell_bits, a.key, a.count);
+    e = launch_exclusive_scan(a.count, a.cell_start, ncell + 1, a.scan, a.scan_len, s);
+    if (e == hipSuccess) e = launch_copy_u32(a.cursor, a.cell_start, ncell + 1, s);
+    if (e == hipSuccess) e = launch_scatter_perm(a.n, a.key, a.cursor, a.perm, s);
+    if (e == hipSuccess) e = launch_cellsort(a.n, a.key, a.cell_start, a.perm, a.sorig, s);   // sorig: sorted -> catalogue
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_curved_gather<D, K>), dim3(g), dim3(256), 0, s, a.pos, a.w, a.n, (const int32_t *)a.sorig,
+                       a.spos, a.sw, a.pf, a.x0max);
+    e = launch_primlist(a.n, a.sorig, a.p0, a.p0 + a.rows, a.pflag, a.ppos, a.prim, a.scan, a.scan_len, s);
+    if (e != hipSuccess) return e;
+    const unsigned ntiles = (unsigned)((a.n + kSphTile - 1) / kSphTile);
+    hipLaunchKernelGGL((k_curved_caps<D, K>), dim3(ntiles), dim3(256), 0, s, a.pf, a.n, a.caps);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
     hipLaunchKernelGGL((k_sphere<D, L, K>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
     return hipGetLastError();
