@@ -260,18 +260,20 @@ def coupling_roofline(key: str, path: str, coupling_ms: float, useful=None):
     return out
 
 
-def sphere_flops(D: int, L: int, visited: float, pairs: float) -> float:
+def sphere_flops(D: int, L: int, pairs: float) -> float:
     """FP32-equivalent operations of the curved-space harmonic stage (the
-    unit D-sphere and hyperbolic space alike; FP64 counted
-    twice, the FP64 vector peak being half the FP32 one): every visited pair
-    takes an FP64 dot product of the D + 1 coordinates (2D + 1 operations) for
-    its bin; an in-range pair adds D FP64 tangent projections (2D + 1 each),
-    the squared norm (2D - 1) and its reciprocal square root, then the
-    harmonics and their accumulation as flops_per_pair counts them past the
-    geometry (D = 2: 6 per azimuthal step, 2 per real output)."""
+    unit D-sphere and hyperbolic space alike; FP64 counted twice, the FP64
+    vector peak being half the FP32 one) over its in-range pairs: an FP64 dot
+    product of the D + 1 coordinates (2D + 1 operations) for the bin, D FP64
+    tangent projections (2D + 1 each), the squared norm (2D - 1) and its
+    reciprocal square root, then the harmonics and their accumulation as
+    flops_per_pair counts them past the geometry (D = 2: 6 per azimuthal
+    step, 2 per real output).  Pairs beyond the bins count nothing, as on the
+    flat path: tiles out of reach are skipped whole and the rest fail an FP32
+    pre-test."""
     geo_flat = D + D + (2 * D - 1) + 1 + D
     harm = flops_per_pair(D, L) - geo_flat
-    return 2.0 * (2 * D + 1) * visited + (2 * (D * (2 * D + 1) + (2 * D - 1)) + 1 + harm) * pairs
+    return (2.0 * (2 * D + 1) + 2 * (D * (2 * D + 1) + (2 * D - 1)) + 1 + harm) * pairs
 
 
 def grid_stage_bytes(wl) -> float:
@@ -510,8 +512,7 @@ def main():
             "flops_per_pair_instruction_level": flops_per_pair(wl.D, wl.lmax),
             "launch_ms": r["harmonic_ms_per_launch"]}
     if wl.sphere or wl.hyperbolic:
-        # every pair is visited (no cell list): count the bin test of all of them
-        fl = sphere_flops(wl.D, wl.lmax, float(n) * n, r["pairs_per_step"])
+        fl = sphere_flops(wl.D, wl.lmax, r["pairs_per_step"])
         ach = fl / (r["harmonic_ms_per_launch"] * 1e-3)
         roof = {"kernel": "k_sphere", "bound": "alu", "achieved": ach / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach / FP32_VECTOR_PEAK, "traffic": None,

@@ -312,6 +312,9 @@ typedef struct {
     int couple_block;            /* primaries per coupling block (multiple of 16; 0: the automatic rule) */
     int64_t chunk_rows;          /* primaries per chunk (rows of a held at once) */
     int harmonic_blocks_per_cu;  /* persistent harmonic grid: blocks of four waves per compute unit, 1..32 */
+    int curved_bins_per_pass;    /* curved geometries: radial bins per pass of the all-pairs kernel, one of the
+                                    two widths compiled for the plan's D and lmax (npcf_get_tuning reports the
+                                    current one; 0 on the flat geometry, and 0 keeps it) */
 } npcf_tuning;
 
 /* The plan's current tuning (the automatic values where nothing was set).
@@ -319,17 +322,20 @@ typedef struct {
 npcf_status npcf_get_tuning(npcf_plan_t plan, npcf_tuning *out);
 
 /* Set every knob of `t` that is non-zero (as npcf_set_tuning, plus the
- * harmonic grid).  Synchronises.  Errors: NPCF_E_INVALID (out of range),
- * NPCF_E_NOMEM. */
+ * harmonic grid and the curved-space bins per pass).  Synchronises.  Errors:
+ * NPCF_E_INVALID (out of range; bins per pass on a flat plan or not one of
+ * the plan's two widths), NPCF_E_NOMEM. */
 npcf_status npcf_apply_tuning(npcf_plan_t plan, const npcf_tuning *t);
 
 /* Autotuner for the given catalogue (positions and weights as npcf_accumulate):
- *  - the cell subdivision s = 1..6 (1..4 for D = 4) and then the harmonic
+ *  - flat geometry: the cell subdivision s = 1..6 (1..4 for D = 4) and then the harmonic
  *    grid's blocks per CU (2, 3, 4, 6, 8), timing the harmonic stage with its
  *    cell list on four ranges spread over the catalogue of
  *    max(sample / 4, min(n / 16, 131072)) primaries each: enough rows to
  *    fill the persistent grid many times over, so that the timing follows
  *    throughput rather than the latency of single rows;
+ *  - curved geometries (no cell grid): the bins per pass of the all-pairs
+ *    kernel, its two widths timed on the whole catalogue;
  *  - the primaries per coupling block (the automatic rule, 256, 512, 1024,
  *    2048) and the chunk rows (the plan's largest, or n / 32), timing the
  *    coupling and the whole pass on the whole catalogue, whose launches are
@@ -338,12 +344,11 @@ npcf_status npcf_apply_tuning(npcf_plan_t plan, const npcf_tuning *t);
  *  default must win by 2%.  The choice is applied to the plan (read it with
  *  npcf_get_tuning).  With the environment variable NPCF_TUNE_CACHE naming a
  *  file, a tuning stored there for the same problem (D, N, lmax, bins, r_max,
- *  n, box, precision, b-tuple mode, basis, periodicity, CU count) is applied
+ *  n, box, precision, b-tuple mode, basis, periodicity, geometry, CU count) is applied
  *  without timing, and a new one is written to it (JSON).  Resets the
  *  accumulators.  Outputs (may be NULL): the chosen subdivision, block size
- *  (0: the automatic rule) and the timed ms of harmonic + coupling.  On the
- *  sphere geometry (no cell grid) nothing is tuned.  Errors as
- *  npcf_accumulate. */
+ *  (0: the automatic rule) and the timed ms of harmonic + coupling.  Errors
+ *  as npcf_accumulate. */
 npcf_status npcf_autotune(npcf_plan_t plan, const double *pos, const double *w, int64_t n, int64_t sample,
                           int *cell_subdiv, int *couple_block, double *best_ms);
 

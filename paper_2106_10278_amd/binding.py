@@ -50,7 +50,7 @@ class _Config(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("cell_subdiv", ctypes.c_int), ("couple_block", ctypes.c_int), ("chunk_rows", ctypes.c_int64),
-                ("harmonic_blocks_per_cu", ctypes.c_int)]
+                ("harmonic_blocks_per_cu", ctypes.c_int), ("curved_bins_per_pass", ctypes.c_int)]
 
 
 _lib = None
@@ -280,10 +280,10 @@ class NPCF:
                "npcf_set_tuning")
 
     def autotune(self, pos, w, sample: int = 8192):
-        """Tune the cell subdivision, the harmonic grid, the coupling block
-        size and the chunk rows on this catalogue (npcf_autotune; resets the
-        accumulators).  Returns every knob of the resulting tuning and the
-        timed ms."""
+        """Tune the cell subdivision and the harmonic grid (flat geometry) or
+        the bins per pass (curved geometries), the coupling block size and the
+        chunk rows on this catalogue (npcf_autotune; resets the accumulators).
+        Returns every knob of the resulting tuning and the timed ms."""
         cs, cb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(load_library().npcf_autotune(self._h, _dptr(pos), _dptr(w), int(w.shape[0]), int(sample),
                                             ctypes.byref(cs), ctypes.byref(cb), ctypes.byref(ms)), "npcf_autotune")
@@ -293,10 +293,12 @@ class NPCF:
         t = _Tuning()
         _check(load_library().npcf_get_tuning(self._h, ctypes.byref(t)), "npcf_get_tuning")
         return {"cell_subdiv": t.cell_subdiv, "couple_block": t.couple_block, "chunk_rows": t.chunk_rows,
-                "harmonic_blocks_per_cu": t.harmonic_blocks_per_cu}
+                "harmonic_blocks_per_cu": t.harmonic_blocks_per_cu, "curved_bins_per_pass": t.curved_bins_per_pass}
 
-    def apply_tuning(self, cell_subdiv=0, couple_block=0, chunk_rows=0, harmonic_blocks_per_cu=0):
-        t = _Tuning(int(cell_subdiv), int(couple_block), int(chunk_rows), int(harmonic_blocks_per_cu))
+    def apply_tuning(self, cell_subdiv=0, couple_block=0, chunk_rows=0, harmonic_blocks_per_cu=0,
+                     curved_bins_per_pass=0):
+        t = _Tuning(int(cell_subdiv), int(couple_block), int(chunk_rows), int(harmonic_blocks_per_cu),
+                    int(curved_bins_per_pass))
         _check(load_library().npcf_apply_tuning(self._h, ctypes.byref(t)), "npcf_apply_tuning")
 
     def reset(self):

@@ -110,6 +110,7 @@ struct npcf_plan_s {
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
     int curved_bits = 0;       // curved spaces: bits per axis of the Morton cells of the spatial sort
+    int curved_group = 0;      // curved spaces: bins per pass of the all-pairs kernel (a sph_group value)
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
@@ -190,6 +191,7 @@ void compute_grid(npcf_plan_s *p)
         // coordinates on the sphere, the D spatial ones in H^D)
         const int axes = p->t.curv > 0 ? p->D + 1 : p->D;
         p->curved_bits = axes == 2 ? 7 : (axes == 3 ? 5 : 4);
+        if (p->curved_group == 0) p->curved_group = sph_group(p->D, p->L, false);
         p->ncell = (int64_t)1 << (p->curved_bits * axes);
         for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
         return;
@@ -500,6 +502,7 @@ npcf_status run_sphere(npcf_plan_s *p, Workspace &W, const double *pos, const do
     a.p0 = p0;
     a.rows = rows;
     a.nb = p->nb;
+    a.group = p->curved_group;
     for (int b = 0; b <= p->nb; b++) a.cedge[b] = p->t.cedge[b];
     a.A = W.A;
     a.wrow = W.wrow;
@@ -919,7 +922,7 @@ npcf_status grid_accumulate(npcf_plan_s *p, const double *field, int64_t p0, int
 // ---------------------------------------------------------------------------
 // Autotuner cache: a JSON file of tuned knobs keyed by the problem's shape
 //   {"npcf_tuning": 1, "entries": {"<key>": {"cell_subdiv": s, "couple_block": b,
-//    "chunk_rows": r, "harmonic_blocks_per_cu": g, "ms": t}, ...}}
+//    "chunk_rows": r, "harmonic_blocks_per_cu": g, "curved_bins_per_pass": c, "ms": t}, ...}}
 // ---------------------------------------------------------------------------
 std::string tune_key(const npcf_plan_s *p, int64_t n)
 {
@@ -931,8 +934,8 @@ std::string tune_key(const npcf_plan_s *p, int64_t n)
         std::snprintf(buf, sizeof(buf), "x%.9g", p->cfg.box[d]);
         k += buf;
     }
-    std::snprintf(buf, sizeof(buf), "-rmax%.9g-prec%d-mode%d-basis%d-per%d-cu%d", p->edges[p->nb], p->cfg.precision,
-                  p->cfg.btuple_mode, p->cfg.basis, p->cfg.periodic, p->ncu);
+    std::snprintf(buf, sizeof(buf), "-rmax%.9g-prec%d-mode%d-basis%d-per%d-geo%d-cu%d", p->edges[p->nb],
+                  p->cfg.precision, p->cfg.btuple_mode, p->cfg.basis, p->cfg.periodic, (int)p->cfg.geometry, p->ncu);
     return k + buf;
 }
 
@@ -989,6 +992,7 @@ bool tune_cache_lookup(const char *path, const std::string &key, npcf_tuning &t,
         t.couple_block = (int)json_number(e.second, "couple_block", 0);
         t.chunk_rows = (int64_t)json_number(e.second, "chunk_rows", 0);
         t.harmonic_blocks_per_cu = (int)json_number(e.second, "harmonic_blocks_per_cu", 0);
+        t.curved_bins_per_pass = (int)json_number(e.second, "curved_bins_per_pass", 0);
         ms = json_number(e.second, "ms", 0.0);
         return t.cell_subdiv > 0;
     }
@@ -1001,8 +1005,9 @@ void tune_cache_store(const char *path, const std::string &key, const npcf_tunin
     char obj[256];
     std::snprintf(obj, sizeof(obj),
                   "{\"cell_subdiv\": %d, \"couple_block\": %d, \"chunk_rows\": %lld, \"harmonic_blocks_per_cu\": %d, "
-                  "\"ms\": %.6g}",
-                  t.cell_subdiv, t.couple_block, (long long)t.chunk_rows, t.harmonic_blocks_per_cu, ms);
+                  "\"curved_bins_per_pass\": %d, \"ms\": %.6g}",
+                  t.cell_subdiv, t.couple_block, (long long)t.chunk_rows, t.harmonic_blocks_per_cu,
+                  t.curved_bins_per_pass, ms);
     bool found = false;
     for (auto &e : entries) {
         if (e.first == key) {
@@ -1691,6 +1696,7 @@ npcf_status npcf_get_tuning(npcf_plan_t p, npcf_tuning *out)
     out->couple_block = p->couple_rows;
     out->chunk_rows = p->wk.rows_cap;
     out->harmonic_blocks_per_cu = p->harm_bpc > 0 ? p->harm_bpc : 8;
+    out->curved_bins_per_pass = p->t.sphere ? p->curved_group : 0;
     return NPCF_OK;
 }
 
@@ -1698,9 +1704,16 @@ npcf_status npcf_apply_tuning(npcf_plan_t p, const npcf_tuning *t)
 {
     if (!p || !t) return NPCF_E_INVALID;
     if (t->harmonic_blocks_per_cu < 0 || t->harmonic_blocks_per_cu > 32) return NPCF_E_INVALID;
+    const int g = t->curved_bins_per_pass;
+    if (g != 0 && (!p->t.sphere || (g != sph_group(p->D, p->L, false) && g != sph_group(p->D, p->L, true)))) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "npcf_apply_tuning: curved_bins_per_pass %d is not one of the kernel's widths for this plan", g);
+        return NPCF_E_INVALID;
+    }
     npcf_status st = npcf_set_tuning(p, t->cell_subdiv, t->couple_block, t->chunk_rows);
     if (st != NPCF_OK) return st;
     if (t->harmonic_blocks_per_cu > 0) p->harm_bpc = t->harmonic_blocks_per_cu;
+    if (g != 0) p->curved_group = g;
     return NPCF_OK;
 }
 
@@ -1709,13 +1722,6 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
 {
     npcf_status st = check_inputs(p, pos, w, n, 0, n);
     if (st != NPCF_OK) return st;
-    if (p->t.sphere) {
-        // no cell grid on the sphere: keep the automatic coupling block
-        if (cell_subdiv) *cell_subdiv = p->cell_subdiv;
-        if (couple_block) *couple_block = 0;
-        if (best_ms) *best_ms = 0.0;
-        return NPCF_OK;
-    }
     const std::string key = tune_key(p, n);
     const char *cache = std::getenv("NPCF_TUNE_CACHE");
     npcf_tuning cached{};
@@ -1760,50 +1766,71 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
         return NPCF_OK;
     };
     const auto small = spread(sample / 4);
+    const std::vector<std::pair<int64_t, int64_t>> whole{{0, n}};
     double h = 0.0, c = 0.0;
     st = measure(small, h, c);  // first launches (code loading) out of the way
     if (st != NPCF_OK) return st;
-    // harmonic stage with its cell list: the cell subdivision, then the
-    // persistent grid's blocks per CU, on four spread ranges of up to 128k
-    // primaries (a quarter of the catalogue at most): enough rows to fill the
-    // persistent grid (8192 waves at 8 blocks per CU) many times over, so
-    // that the timing follows throughput; a few thousand primaries leave
-    // waves idle and rank the subdivisions by the latency of single rows
-    // (2M D = 4 points: s = 3 chosen on 4096 primaries, 211 ms per launch
-    // against 179 ms at s = 2)
-    const auto quarter = spread(std::max<int64_t>(sample / 4, std::min<int64_t>(n / 16, 131072)));
     int best_s = p->cell_subdiv;
     double best_h = 1e300;
-    const int smax = p->D == 4 ? 4 : 6;
-    for (int sdv = 1; sdv <= smax; sdv++) {
-        st = npcf_set_tuning(p, sdv, 0, 0);
-        if (st != NPCF_OK) return st;
-        st = measure(quarter, h, c);
-        if (st != NPCF_OK) return st;
-        if (h < best_h) {
-            best_h = h;
-            best_s = sdv;
+    if (p->t.sphere) {
+        // curved spaces (no cell grid): the all-pairs kernel's two widths,
+        // on the whole catalogue (which of them wins depends on the share of
+        // visited pairs in the bins, which a part of the catalogue need not
+        // have); the wide one unless the narrow one wins by 2%
+        const int gw = sph_group(p->D, p->L, false), gn = sph_group(p->D, p->L, true);
+        std::vector<int> widths{gw};
+        if (gn != gw) widths.push_back(gn);
+        int best_w = gw;
+        for (int g : widths) {
+            p->curved_group = g;
+            st = measure(whole, h, c);
+            if (st != NPCF_OK) return st;
+            if (h < best_h * (g == gw ? 1.0 : 0.98)) {
+                best_h = h;
+                best_w = g;
+            }
         }
-    }
-    st = npcf_set_tuning(p, best_s, 0, 0);
-    if (st != NPCF_OK) return st;
-    int best_g = 8;
-    for (int g : {2, 3, 4, 6, 8}) {
-        p->harm_bpc = g;
-        st = measure(quarter, h, c);
-        if (st != NPCF_OK) return st;
-        if (h < best_h * (g == 8 ? 1.0 : 0.98)) {   // a different grid must win by 2%
-            best_h = h;
-            best_g = g;
+        p->curved_group = best_w;
+    } else {
+        // harmonic stage with its cell list: the cell subdivision, then the
+        // persistent grid's blocks per CU, on four spread ranges of up to 128k
+        // primaries (a quarter of the catalogue at most): enough rows to fill the
+        // persistent grid (8192 waves at 8 blocks per CU) many times over, so
+        // that the timing follows throughput; a few thousand primaries leave
+        // waves idle and rank the subdivisions by the latency of single rows
+        // (2M D = 4 points: s = 3 chosen on 4096 primaries, 211 ms per launch
+        // against 179 ms at s = 2)
+        const auto quarter = spread(std::max<int64_t>(sample / 4, std::min<int64_t>(n / 16, 131072)));
+        const int smax = p->D == 4 ? 4 : 6;
+        for (int sdv = 1; sdv <= smax; sdv++) {
+            st = npcf_set_tuning(p, sdv, 0, 0);
+            if (st != NPCF_OK) return st;
+            st = measure(quarter, h, c);
+            if (st != NPCF_OK) return st;
+            if (h < best_h) {
+                best_h = h;
+                best_s = sdv;
+            }
         }
+        st = npcf_set_tuning(p, best_s, 0, 0);
+        if (st != NPCF_OK) return st;
+        int best_g = 8;
+        for (int g : {2, 3, 4, 6, 8}) {
+            p->harm_bpc = g;
+            st = measure(quarter, h, c);
+            if (st != NPCF_OK) return st;
+            if (h < best_h * (g == 8 ? 1.0 : 0.98)) {   // a different grid must win by 2%
+                best_h = h;
+                best_g = g;
+            }
+        }
+        p->harm_bpc = best_g;
     }
-    p->harm_bpc = best_g;
     // coupling block size and chunk rows on the whole catalogue: the
     // automatic block size and a fixed one give different block counts on a
     // part of it than on the full launches (2M D = 4 points: 512 rows per
     // block won on a quarter by more than 2% and lost on the whole, 59.3
     // against 57.0 ms)
-    const std::vector<std::pair<int64_t, int64_t>> whole{{0, n}};
     int best_b = 0;
     double best_c = 1e300, best_q = 1e300;
     for (int b : {0, 256, 512, 1024, 2048}) {

@@ -223,6 +223,27 @@ constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
 // curved spaces: secondaries per LDS tile of the all-pairs kernel (and per tile cap)
 constexpr int kSphTile = 512;
 
+// real slots per bin of the all-pairs kernel: 2 per stored state (the
+// imaginary slots of real states stay 0)
+constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * (L + 2); }
+
+// bins per pass of the all-pairs kernel: as many as keep the lanes' FP32 sums
+// (one per slot and bin) within a register budget, at least 1, at most 16 and
+// at most 128 values in all (two per lane after the fold).  Two budgets, one
+// kernel each, chosen per plan: wide (50 values on D = 2, 128 on D = 3; fewer
+// passes, so fewer scans of the points) and narrow (20 and 42; fewer masked
+// sums per pair and more waves per SIMD, for catalogues where most visited
+// pairs fall in the bins).  Measured with tile culling: the wide rule on the
+// uniform 2-sphere (38.3 against 52.1 ms) and in H^3 (85.7 against 161.6 ms),
+// the narrow one on the clustered 3-sphere (113.0 against 134.2 ms).
+constexpr int sph_group(int D, int L, bool narrow)
+{
+    const int budget = narrow ? (D == 2 ? 20 : 42) : (D == 2 ? 50 : 128);
+    const int g = budget / sph_slots(D, L);
+    const int g1 = g < 1 ? 1 : (g > 16 ? 16 : g);
+    return g1 * sph_slots(D, L) <= 128 ? g1 : 128 / sph_slots(D, L);
+}
+
 struct SphereArgs {
     const double *pos;          // [D + 1][n] unit vectors (sphere) or hyperboloid points (H^D)
     const double *w;            // [n]
@@ -231,6 +252,7 @@ struct SphereArgs {
     int64_t p0;                 // primary of row 0: rows [0, rows) are primaries p0 + [0, rows)
     int rows;
     int nb;
+    int group;                  // bins per pass: sph_group(D, L, false) or sph_group(D, L, true)
     double cedge[kMaxBins + 1]; // the edges' cosines: cos e (sphere) or -cosh e (H^D), decreasing
     unsigned *x0max;            // scratch word: largest x0 of the catalogue (H^D), written by launch_sphere
     // secondaries in spatial order (Morton cells), written by launch_sphere:

@@ -64,22 +64,6 @@ constexpr int kSphWaves = 8;
 constexpr int kSphFoldBatches = 4;
 constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64 (at least)
 
-// real slots per bin: 2 per stored state (the imaginary slots of real states stay 0)
-__host__ __device__ constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * (L + 2); }
-
-// bins per pass: as many as keep the lanes' FP32 sums within the register
-// budget (50 on S^2; 128 on S^3, whose 42 slots per bin at lmax 5 would
-// otherwise take one bin per pass: three bins per pass there ran faster at
-// two waves per SIMD than one or two bins at three or four), at least 1, at
-// most 16, and at most 128 values in all (two per lane after the fold)
-__host__ __device__ constexpr int sph_group(int D, int L)
-{
-    const int budget = D == 2 ? 50 : 128;
-    const int g = budget / sph_slots(D, L);
-    const int g1 = g < 1 ? 1 : (g > 16 ? 16 : g);
-    return g1 * sph_slots(D, L) <= 128 ? g1 : 128 / sph_slots(D, L);
-}
-
 // p.q in FP64, left to right with every product and sum rounded (no contraction)
 template <int D>
 __device__ __forceinline__ double dot_rn(const double (&p)[D + 1], const double *pos, int64_t n, int64_t k)
@@ -380,7 +364,7 @@ __global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n
     }
 }
 
-template <int D, int L, int K>
+template <int D, int L, int K, int G>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
     __shared__ float4 tile[kSphTile];
@@ -400,7 +384,6 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
     __shared__ float sce[kMaxBins + 1];
     __shared__ unsigned char sbk[kBuckets];
     constexpr int NV = sph_slots(D, L);
-    constexpr int G = sph_group(D, L);
     constexpr int NG = G * NV;        // values per pass, <= 128: lane j keeps values j and j + 64 in FP64
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * kSphWaves + wave;
@@ -638,6 +621,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 template <int D, int L, int K>
 hipError_t launch_l(const SphereArgs &a, hipStream_t s)
 {
+    if (a.group != sph_group(D, L, false) && a.group != sph_group(D, L, true)) return hipErrorInvalidValue;
     constexpr int A = key_axes<D, K>();
     const int64_t ncell = (int64_t)1 << (a.ncell_bits * A);
     const unsigned g = (unsigned)((a.n + 255) / 256);
@@ -660,7 +644,9 @@ hipError_t launch_l(const SphereArgs &a, hipStream_t s)
     const unsigned ntiles = (unsigned)((a.n + kSphTile - 1) / kSphTile);
     hipLaunchKernelGGL((k_curved_caps<D, K>), dim3(ntiles), dim3(256), 0, s, a.pf, a.n, a.caps);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
-    hipLaunchKernelGGL((k_sphere<D, L, K>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
+    constexpr int GW = sph_group(D, L, false), GN = sph_group(D, L, true);
+    if (a.group == GW) hipLaunchKernelGGL((k_sphere<D, L, K, GW>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
+    else hipLaunchKernelGGL((k_sphere<D, L, K, GN>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 
