@@ -1273,7 +1273,7 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
     p->wk.w64s = m.get<double>(max_points);
     if (t.sphere) {
         p->wk.pos64 = m.get<double>((size_t)4 * max_points);
-        p->wk.caps = m.get<float>((size_t)8 * ((max_points + kSphTile - 1) / kSphTile + 1));
+        p->wk.caps = m.get<float>((size_t)8 * ((max_points + kSphChunk - 1) / kSphChunk + 1));
         p->wk.bbox = m.get<unsigned>(12);   // key-axis bounds [8], then the largest x0
     }
     p->wk.flag = m.get<uint32_t>(max_points);

@@ -220,8 +220,9 @@ struct GridArgs {
 // Points on the unit 2-sphere (npcf_sphere.hip).
 // ---------------------------------------------------------------------------
 constexpr int kLmaxSphere = 5;   // larger l would spill the per-lane bin sums
-// curved spaces: secondaries per LDS tile of the all-pairs kernel (and per tile cap)
-constexpr int kSphTile = 512;
+// curved spaces: sorted secondaries per chunk (one per lane) of the all-pairs
+// kernel's scan, each with a bounding cap
+constexpr int kSphChunk = 64;
 
 // real slots per bin of the all-pairs kernel: 2 per stored state (the
 // imaginary slots of real states stay 0)
@@ -257,7 +258,7 @@ struct SphereArgs {
     unsigned *x0max;            // scratch word: largest x0 of the catalogue (H^D), written by launch_sphere
     // secondaries in spatial order (Morton cells), written by launch_sphere:
     // FP64 coordinates [D + 1][n], FP64 weights, original index, and per tile
-    // of kSphTile points a bounding cap (centre [4], radius in geodesic distance)
+    // of kSphChunk points a bounding cap (centre [4], radius in geodesic distance)
     double *spos;
     double *sw;
     int32_t *sorig;

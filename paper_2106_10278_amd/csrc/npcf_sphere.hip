@@ -25,16 +25,19 @@
 //    u_j = -<q, e_j(p)>, i.e. the Euclidean product of q with e_j(p) whose
 //    time component is negated; the self pair is excluded by index (<p, p>
 //    rounds with an error that grows as cosh^2 r).
-// A block is 8 waves, one primary each; secondaries come through LDS in FP32
-// tiles.  Once per launch the secondaries are put in spatial order (a counting
-// sort by Morton cell of the embedding coordinates: all D + 1 on the sphere,
-// the D spatial ones in H^D, ranked within a cell by catalogue index) and
-// packed to FP32, and every tile gets a bounding cap (centre, largest
-// distance r); a wave skips a tile when the cap's distance range [d - r,
-// d + r] from its primary misses the pass's bins by more than a margin that
-// covers the FP32 errors of d and r.  The primaries of the launch take the
-// same order, so that the waves of a block (which load each tile together)
-// have nearby primaries and skip and fill the same tiles.  The FP32 cosine
+// A block is 8 waves, one primary each.  Once per launch the secondaries are
+// put in spatial order (a counting sort by Morton cell of the embedding
+// coordinates: all D + 1 on the sphere, the D spatial ones in H^D, ranked
+// within a cell by catalogue index) and packed to FP32, and every chunk of 64
+// sorted points gets a bounding cap (centre, largest distance r).  Per pass
+// each wave tests 64 caps at a time, one per lane, and scans only the chunks
+// whose distance range [d - r, d + r] from its primary meets the pass's bins
+// widened by a margin that covers the FP32 errors of d and r; a chunk's
+// points come straight from memory, one per lane (1.6 MB per 100k points,
+// held in L2), the next chunk's in flight while one is scanned, so the waves
+// of a block never wait for each other inside a pass.  The primaries of the
+// launch take the same order (neighbouring waves then read the same chunks
+// from L2).  The FP32 cosine
 // decides the bin (through a bucket table where no edge is near, else against
 // the edge cosines) unless it lies within a guard band of an edge: 1e-6 on the
 // sphere (the FP32 error is below (D + 3) 2^-24 < 4e-7 for unit vectors),
@@ -304,62 +307,46 @@ __global__ __launch_bounds__(256) void k_curved_gather(const double *pos, const 
     }
 }
 
-// one block per tile of kSphTile sorted points: the cap's centre (the
+// one wave per chunk of kSphChunk sorted points: the cap's centre (the
 // normalised sum, Euclidean on the sphere, Minkowski in H^D) and its largest
 // geodesic distance from the centre
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n, float *caps)
 {
-    __shared__ float red[4][256];
-    const int64_t t0 = (int64_t)blockIdx.x * kSphTile;
-    const int cnt = (int)(n - t0 < kSphTile ? n - t0 : kSphTile);
-    float sum[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const float4 q = pf[t0 + i];
-        sum[0] += q.x;
-        sum[1] += q.y;
-        sum[2] += q.z;
-        if (D == 3) sum[3] += q.w;
-    }
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t t0 = c * kSphChunk;
+    if (t0 >= n) return;   // the whole wave
+    const bool live = t0 + lane < n;
+    const float4 q = live ? pf[t0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float q3 = D == 3 ? q.w : 0.f;
+    float cv[4] = {q.x, q.y, q.z, q3};
 #pragma unroll
-    for (int x = 0; x < 4; x++) red[x][threadIdx.x] = sum[x];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
+    for (int x = 0; x < 4; x++)
 #pragma unroll
-            for (int x = 0; x < 4; x++) red[x][threadIdx.x] += red[x][threadIdx.x + h];
-        __syncthreads();
-    }
-    float c[4] = {red[0][0], red[1][0], red[2][0], red[3][0]};
+        for (int m = 32; m > 0; m >>= 1) cv[x] += __shfl_xor(cv[x], m, 64);
     float nn;
-    if constexpr (K > 0) nn = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3];
-    else nn = c[0] * c[0] - c[1] * c[1] - c[2] * c[2] - c[3] * c[3];
+    if constexpr (K > 0) nn = cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2] + cv[3] * cv[3];
+    else nn = cv[0] * cv[0] - cv[1] * cv[1] - cv[2] * cv[2] - cv[3] * cv[3];
     const float inv = nn > 0.f ? rsqrtf(nn) : 0.f;
 #pragma unroll
-    for (int x = 0; x < 4; x++) c[x] *= inv;
-    __syncthreads();
+    for (int x = 0; x < 4; x++) cv[x] *= inv;
     // the extreme "cosine": min c.q on the sphere, max <c, q> in H^D
-    float ext = K > 0 ? 1.f : 1.f;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const float4 q = pf[t0 + i];
-        const float q3 = D == 3 ? q.w : 0.f;
-        if constexpr (K > 0) ext = fminf(ext, c[0] * q.x + c[1] * q.y + c[2] * q.z + c[3] * q3);
-        else ext = fmaxf(ext, c[0] * q.x - c[1] * q.y - c[2] * q.z - c[3] * q3);
+    float ext = 1.f;
+    if (live) {
+        if constexpr (K > 0) ext = cv[0] * q.x + cv[1] * q.y + cv[2] * q.z + cv[3] * q3;
+        else ext = cv[0] * q.x - cv[1] * q.y - cv[2] * q.z - cv[3] * q3;
     }
-    red[0][threadIdx.x] = ext;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            red[0][threadIdx.x] = K > 0 ? fminf(red[0][threadIdx.x], red[0][threadIdx.x + h])
-                                        : fmaxf(red[0][threadIdx.x], red[0][threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        float *cp = caps + blockIdx.x * 8;
 #pragma unroll
-        for (int x = 0; x < 4; x++) cp[x] = c[x];
-        const float e = red[0][0];
-        cp[4] = (inv > 0.f) ? (K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, e))) : acoshf(fmaxf(1.f, e))) : 1e30f;
+    for (int m = 32; m > 0; m >>= 1) {
+        const float o = __shfl_xor(ext, m, 64);
+        ext = K > 0 ? fminf(ext, o) : fmaxf(ext, o);
+    }
+    if (lane == 0) {
+        float *cp = caps + c * 8;
+#pragma unroll
+        for (int x = 0; x < 4; x++) cp[x] = cv[x];
+        cp[4] = (inv > 0.f) ? (K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, ext))) : acoshf(fmaxf(1.f, ext))) : 1e30f;
         cp[5] = cp[6] = cp[7] = 0.f;
     }
 }
@@ -367,7 +354,6 @@ __global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n
 template <int D, int L, int K, int G>
 __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
 {
-    __shared__ float4 tile[kSphTile];
     // per wave: in-range pairs waiting for the harmonics (catalogue index,
     // weight (S^2; the FP64 weight is read at the harmonics on S^3), bin)
     __shared__ int qidx[kSphWaves][128];
@@ -504,102 +490,117 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                 for (int g = 0; g < G; g++) fs[g][slot] = fmaf(m[g], v, fs[g][slot]);
             });
         };
-        for (int64_t t0 = 0; t0 < a.n; t0 += kSphTile) {
-            const int cnt_t = (int)(a.n - t0 < kSphTile ? a.n - t0 : kSphTile);
-            __syncthreads();
-            for (int i = threadIdx.x; i < cnt_t; i += blockDim.x) tile[i] = a.pf[t0 + i];
-            __syncthreads();
-            // the tile's cap against this pass's distances (wave-uniform)
-            bool reach = true;
-            {
-                const float *cp = a.caps + (t0 / kSphTile) * 8;
-                const float cd = pf32[0] * cp[0] + pf32[1] * cp[1] + pf32[2] * cp[2] + pf32[3] * cp[3];
-                const float d = K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, cd))) : acoshf(fmaxf(1.f, -cd));
-                const float r = cp[4];
-                reach = !(d - r > dhi || d + r < dlo);
-            }
-            if (active && reach) {
-                // scan: bin of every point; in-range pairs go to the wave's queue
-                for (int i0 = 0; i0 < cnt_t; i0 += 64) {
-                    const int i = i0 + lane;
-                    bool valid = false;
-                    int bl = 0;
-                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (i < cnt_t) {
-                        q = tile[i];
-                        float c32 = pf32[0] * q.x + pf32[1] * q.y + pf32[2] * q.z;
-                        if constexpr (D == 3) c32 += pf32[3] * q.w;
-                        // range prefilter on the same FP32 differences as the guard
-                        // test below, so that a cosine admitted beyond an outer edge
-                        // is always within the guard of it and decided in FP64
-                        // (chif + guard rounded in FP32 would admit cosines up to
-                        // one rounding beyond the guard)
-                        if (c32 - chif <= guard && clof - c32 < guard) {
-                            // bin from the bucket table; near an edge, from the FP32
-                            // cosine against the edges, and within the guard band of
-                            // an edge from the FP64 dot product
-                            int kb = (int)((c32 - clof) * ibw);
-                            kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
-                            const int ent = sbk[kb];
-                            bl = ent & 0x7F;
-                            valid = true;
-                            bool near = false;
-                            if (ent & 0x80) {
-                                while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
-                                while (bl > 0 && c32 > sce[bl]) bl--;
-                                near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
-                            }
-                            if (near) {
-                                const double c = dot_rn<D>(pc, a.spos, a.n, t0 + i);
-                                valid = c <= chi && c > clo;
-                                bl = 0;
-                                while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
-                            }
-                        }
-                    }
-                    if constexpr (K < 0) valid = valid && (t0 + i != js);   // the self pair, by index
-                    const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
-                    const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
-                                                                         __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
-                    if (valid) {
-                        qidx[wave][slot] = (int)(t0 + i);
-                        if constexpr (D == 2) qw[wave][slot] = q.w;
-                        qbin[wave][slot] = bl;
-                    }
-                    qn += __popcll(vm);
-                    if (qn >= 64) {
-                        NPCF_SPH_WAVE_SYNC();
-                        process(64);
-                        // move the rest (< 64) to the front
-                        const int rest = qn - 64;
-                        int mi = 0, mb = 0;
-                        float mw = 0.f;
-                        if (lane < rest) {
-                            mi = qidx[wave][64 + lane];
-                            if constexpr (D == 2) mw = qw[wave][64 + lane];
-                            mb = qbin[wave][64 + lane];
-                        }
-                        NPCF_SPH_WAVE_SYNC();
-                        if (lane < rest) {
-                            qidx[wave][lane] = mi;
-                            if constexpr (D == 2) qw[wave][lane] = mw;
-                            qbin[wave][lane] = mb;
-                        }
-                        qn = rest;
-                        if (++batches == kSphFoldBatches) fold();
-                    }
+        // the chunks of kSphChunk sorted points whose cap reaches this pass's
+        // bins, in order: each lane tests one chunk of a group of 64, and the
+        // ballot's bits are taken one by one (wave-uniform)
+        const int64_t nch = (a.n + kSphChunk - 1) / kSphChunk;
+        int64_t g0 = -64;
+        unsigned long long gm = 0;
+        auto next_chunk = [&]() -> int64_t {
+            while (gm == 0) {
+                g0 += 64;
+                if (g0 >= nch) return -1;
+                const int64_t c = g0 + lane;
+                bool reach = false;
+                if (c < nch) {
+                    const float4 cc = reinterpret_cast<const float4 *>(a.caps)[2 * c];
+                    const float r = a.caps[8 * c + 4];
+                    const float cd = pf32[0] * cc.x + pf32[1] * cc.y + pf32[2] * cc.z + pf32[3] * cc.w;
+                    const float d = K > 0 ? acosf(fmaxf(-1.f, fminf(1.f, cd))) : acoshf(fmaxf(1.f, -cd));
+                    reach = !(d - r > dhi || d + r < dlo);
                 }
+                gm = __builtin_amdgcn_ballot_w64(reach);
+            }
+            const int bit = __builtin_ctzll(gm);
+            gm &= gm - 1;
+            return g0 + bit;
+        };
+        if (active) {
+            // one chunk's points in flight while the previous one is scanned
+            int64_t cur = next_chunk();
+            float4 qcur = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (cur >= 0 && cur * kSphChunk + lane < a.n) qcur = a.pf[cur * kSphChunk + lane];
+            while (cur >= 0) {
+                const int64_t nxt = next_chunk();
+                float4 qnxt = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (nxt >= 0 && nxt * kSphChunk + lane < a.n) qnxt = a.pf[nxt * kSphChunk + lane];
+                // scan: bin of every point; in-range pairs go to the wave's queue
+                const int64_t t = cur * kSphChunk + lane;   // this lane's point (sorted index)
+                bool valid = false;
+                int bl = 0;
+                if (t < a.n) {
+                    const float4 q = qcur;
+                    float c32 = pf32[0] * q.x + pf32[1] * q.y + pf32[2] * q.z;
+                    if constexpr (D == 3) c32 += pf32[3] * q.w;
+                    // range prefilter on the same FP32 differences as the guard
+                    // test below, so that a cosine admitted beyond an outer edge
+                    // is always within the guard of it and decided in FP64
+                    // (chif + guard rounded in FP32 would admit cosines up to
+                    // one rounding beyond the guard)
+                    if (c32 - chif <= guard && clof - c32 < guard) {
+                        // bin from the bucket table; near an edge, from the FP32
+                        // cosine against the edges, and within the guard band of
+                        // an edge from the FP64 dot product
+                        int kb = (int)((c32 - clof) * ibw);
+                        kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
+                        const int ent = sbk[kb];
+                        bl = ent & 0x7F;
+                        valid = true;
+                        bool near = false;
+                        if (ent & 0x80) {
+                            while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
+                            while (bl > 0 && c32 > sce[bl]) bl--;
+                            near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
+                        }
+                        if (near) {
+                            const double c = dot_rn<D>(pc, a.spos, a.n, t);
+                            valid = c <= chi && c > clo;
+                            bl = 0;
+                            while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
+                        }
+                    }
+                    if constexpr (K < 0) valid = valid && (t != js);   // the self pair, by index
+                }
+                const unsigned long long vm = __builtin_amdgcn_ballot_w64(valid);
+                const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
+                if (valid) {
+                    qidx[wave][slot] = (int)t;
+                    if constexpr (D == 2) qw[wave][slot] = qcur.w;
+                    qbin[wave][slot] = bl;
+                }
+                qn += __popcll(vm);
+                if (qn >= 64) {
+                    NPCF_SPH_WAVE_SYNC();
+                    process(64);
+                    // move the rest (< 64) to the front
+                    const int rest = qn - 64;
+                    int mi = 0, mb = 0;
+                    float mw = 0.f;
+                    if (lane < rest) {
+                        mi = qidx[wave][64 + lane];
+                        if constexpr (D == 2) mw = qw[wave][64 + lane];
+                        mb = qbin[wave][64 + lane];
+                    }
+                    NPCF_SPH_WAVE_SYNC();
+                    if (lane < rest) {
+                        qidx[wave][lane] = mi;
+                        if constexpr (D == 2) qw[wave][lane] = mw;
+                        qbin[wave][lane] = mb;
+                    }
+                    qn = rest;
+                    if (++batches == kSphFoldBatches) fold();
+                }
+                cur = nxt;
+                qcur = qnxt;
             }
             // at the end: the last queued pairs, and the last fold
-            const bool last = t0 + kSphTile >= a.n;
-            if (last && active) {
-                if (qn > 0) {
-                    NPCF_SPH_WAVE_SYNC();
-                    process(qn);
-                    qn = 0;
-                }
-                fold();
+            if (qn > 0) {
+                NPCF_SPH_WAVE_SYNC();
+                process(qn);
+                qn = 0;
             }
+            fold();
         }
         if (active) {
 #pragma unroll
@@ -641,8 +642,8 @@ hipError_t launch_l(const SphereArgs &a, hipStream_t s)
                        a.spos, a.sw, a.pf, a.x0max);
     e = launch_primlist(a.n, a.sorig, a.p0, a.p0 + a.rows, a.pflag, a.ppos, a.prim, a.scan, a.scan_len, s);
     if (e != hipSuccess) return e;
-    const unsigned ntiles = (unsigned)((a.n + kSphTile - 1) / kSphTile);
-    hipLaunchKernelGGL((k_curved_caps<D, K>), dim3(ntiles), dim3(256), 0, s, a.pf, a.n, a.caps);
+    const int64_t nch = (a.n + kSphChunk - 1) / kSphChunk;
+    hipLaunchKernelGGL((k_curved_caps<D, K>), dim3((unsigned)((nch + 3) / 4)), dim3(256), 0, s, a.pf, a.n, a.caps);
     const int blocks = (a.rows + kSphWaves - 1) / kSphWaves;
     constexpr int GW = sph_group(D, L, false), GN = sph_group(D, L, true);
     if (a.group == GW) hipLaunchKernelGGL((k_sphere<D, L, K, GW>), dim3((unsigned)blocks), dim3(kSphWaves * 64), 0, s, a);
