@@ -109,7 +109,7 @@ struct npcf_plan_s {
     int harm_bpc = 0;     // persistent harmonic grid: blocks per compute unit (0: automatic, 8)
     int ncs[kMaxD] = {1, 1, 1, 1};
     int64_t ncell = 1;
-    int curved_bits = 0;       // curved spaces: bits per axis of the Morton cells of the spatial sort
+    int curved_bits = 0;       // curved spaces: bits per axis of the Hilbert cells of the spatial sort
     int curved_group = 0;      // curved spaces: bins per pass of the all-pairs kernel (a sph_group value)
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
@@ -186,11 +186,13 @@ hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s)
 void compute_grid(npcf_plan_s *p)
 {
     if (p->t.sphere) {
-        // no cell list: the Morton cells that put the secondaries in spatial
-        // order, 2^14 to 2^16 of them over the key axes (all D + 1
-        // coordinates on the sphere, the D spatial ones in H^D)
+        // no cell list: the Hilbert cells that put the secondaries in spatial
+        // order, 2^20 or 2^21 of them over the key axes (all D + 1
+        // coordinates on the sphere, the D spatial ones in H^D): about one
+        // point per occupied cell at 1e5-1e6 points, so the order within a
+        // cell hardly matters
         const int axes = p->t.curv > 0 ? p->D + 1 : p->D;
-        p->curved_bits = axes == 2 ? 7 : (axes == 3 ? 5 : 4);
+        p->curved_bits = axes == 2 ? 10 : (axes == 3 ? 7 : 5);
         if (p->curved_group == 0) p->curved_group = sph_group(p->D, p->L, false);
         p->ncell = (int64_t)1 << (p->curved_bits * axes);
         for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;

@@ -256,7 +256,7 @@ struct SphereArgs {
     int group;                  // bins per pass: sph_group(D, L, false) or sph_group(D, L, true)
     double cedge[kMaxBins + 1]; // the edges' cosines: cos e (sphere) or -cosh e (H^D), decreasing
     unsigned *x0max;            // scratch word: largest x0 of the catalogue (H^D), written by launch_sphere
-    // secondaries in spatial order (Morton cells), written by launch_sphere:
+    // secondaries in spatial order (Hilbert cells), written by launch_sphere:
     // FP64 coordinates [D + 1][n], FP64 weights, original index, and per tile
     // of kSphChunk points a bounding cap (centre [4], radius in geodesic distance)
     double *spos;
@@ -266,7 +266,7 @@ struct SphereArgs {
     uint32_t *key, *count, *cell_start, *cursor, *scan;  // sort scratch (cells: ncell + 1)
     int32_t *perm;
     int64_t scan_len;
-    int ncell_bits;             // bits per axis of the Morton cells
+    int ncell_bits;             // bits per axis of the Hilbert cells
     unsigned *bbox;             // [8] ordered-float min/max of the key axes (H^D)
     // the primaries p0 + [0, rows) in the same spatial order (positions in it),
     // so that the waves of a block take nearby primaries and meet similar

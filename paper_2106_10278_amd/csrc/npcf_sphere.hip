@@ -26,7 +26,7 @@
 //    time component is negated; the self pair is excluded by index (<p, p>
 //    rounds with an error that grows as cosh^2 r).
 // A block is 8 waves, one primary each.  Once per launch the secondaries are
-// put in spatial order (a counting sort by Morton cell of the embedding
+// put in spatial order (a counting sort by Hilbert cell of the embedding
 // coordinates: all D + 1 on the sphere, the D spatial ones in H^D, ranked
 // within a cell by catalogue index) and packed to FP32, and every chunk of 64
 // sorted points gets a bounding cap (centre, largest distance r).  Per pass
@@ -252,7 +252,44 @@ __global__ __launch_bounds__(256) void k_curved_bounds(const double *pos, int64_
         }
 }
 
-// Morton cell of every point (bits per axis over [-1, 1] on the sphere, over
+// Position along the Hilbert curve of the grid cell x[0..A-1] (bits per
+// axis): Skilling's transform of the coordinates into the transposed Hilbert
+// index (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707,
+// 2004), whose bits are then interleaved, most significant first.  Cells
+// consecutive on the curve are face neighbours, so runs of sorted points are
+// compact (a Morton order jumps between octants).
+template <int A>
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t (&x)[A], int bits)
+{
+    const uint32_t top = 1u << (bits - 1);
+    for (uint32_t q = top; q > 1; q >>= 1) {
+        const uint32_t lowm = q - 1;
+#pragma unroll
+        for (int i = 0; i < A; i++) {
+            if (x[i] & q) {
+                x[0] ^= lowm;   // invert
+            } else {
+                const uint32_t t = (x[0] ^ x[i]) & lowm;   // exchange
+                x[0] ^= t;
+                x[i] ^= t;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 1; i < A; i++) x[i] ^= x[i - 1];
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (x[A - 1] & q) t ^= q - 1;
+#pragma unroll
+    for (int i = 0; i < A; i++) x[i] ^= t;
+    uint32_t h = 0;
+    for (int b = bits - 1; b >= 0; b--)
+#pragma unroll
+        for (int i = 0; i < A; i++) h = (h << 1) | ((x[i] >> b) & 1u);
+    return h;
+}
+
+// Hilbert cell of every point (bits per axis over [-1, 1] on the sphere, over
 // the bounding box in H^D) and the cells' histogram
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_curved_keys(const double *pos, int64_t n, const unsigned *bbox, int bits,
@@ -262,17 +299,17 @@ __global__ __launch_bounds__(256) void k_curved_keys(const double *pos, int64_t 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int m = 1 << bits;
-    uint32_t k = 0;
+    uint32_t c[A];
 #pragma unroll
     for (int a = 0; a < A; a++) {
         const float x = (float)pos[(K > 0 ? a : a + 1) * n + i];
         const float lo = K > 0 ? -1.f : ord_float(bbox[a]);
         const float hi = K > 0 ? 1.f : ord_float(bbox[4 + a]);
         const float span = hi > lo ? hi - lo : 1.f;
-        int c = (int)((x - lo) / span * (float)m);
-        c = c < 0 ? 0 : (c >= m ? m - 1 : c);
-        for (int b = 0; b < bits; b++) k |= (uint32_t)((c >> b) & 1) << (b * A + a);
+        int ca = (int)((x - lo) / span * (float)m);
+        c[a] = (uint32_t)(ca < 0 ? 0 : (ca >= m ? m - 1 : ca));
     }
+    const uint32_t k = hilbert_index<A>(c, bits);
     key[i] = k;
     atomicAdd(&count[k], 1u);
 }
