@@ -434,7 +434,8 @@ def main():
     ap.add_argument("--precisions", default="mixed_fp16,mixed_bf16x6,plain,mixed_bf16")
     ap.add_argument("--batch-steps", type=int, default=1, help="timed passes of the batched workload (0: skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes (no autotuner)")
-    ap.add_argument("--tuning", default="", help="fixed 'cell_subdiv,couple_block' instead of the autotuner")
+    ap.add_argument("--tuning", default="",
+                    help="fixed 'cell_subdiv,couple_block[,curved_bins_per_pass]' instead of the autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -469,8 +470,10 @@ def main():
         plan = factory(prec)
         plan_labels = plan.lambda_labels
         if args.tuning:
-            sdv, blk = (int(x) for x in args.tuning.split(","))
-            plan.set_tuning(cell_subdiv=sdv, couple_block=blk)
+            knobs = [int(x) for x in args.tuning.split(",")]
+            plan.set_tuning(cell_subdiv=knobs[0], couple_block=knobs[1])
+            if len(knobs) > 2:
+                plan.apply_tuning(curved_bins_per_pass=knobs[2])
             tuning = plan.tuning() | {"fixed": True}
         elif field is None:
             tuning = plan.autotune(pos, w) if not args.no_tune else None
