@@ -233,10 +233,10 @@ constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * 
 // at most 128 values in all (two per lane after the fold).  Two budgets, one
 // kernel each, chosen per plan: wide (50 values on D = 2, 128 on D = 3; fewer
 // passes, so fewer scans of the points) and narrow (20 and 42; fewer masked
-// sums per pair and more waves per SIMD, for catalogues where most visited
-// pairs fall in the bins).  Measured with tile culling: the wide rule on the
-// uniform 2-sphere (38.3 against 52.1 ms) and in H^3 (85.7 against 161.6 ms),
-// the narrow one on the clustered 3-sphere (113.0 against 134.2 ms).
+// sums per pair, more waves per SIMD, and at one bin per pass no bucket
+// table).  Which wins depends on the catalogue and the bins; the autotuner
+// times both (in the current kernel: the wide one on the uniform 2-sphere,
+// the narrow one on the clustered 3-sphere and in H^3).
 constexpr int sph_group(int D, int L, bool narrow)
 {
     const int budget = narrow ? (D == 2 ? 20 : 42) : (D == 2 ? 50 : 128);

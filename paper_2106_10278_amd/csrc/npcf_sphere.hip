@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         const float bw = (chif - clof) / kBuckets, ibw = bw > 0.f ? 1.f / bw : 0.f;
         __syncthreads();
         for (int g = threadIdx.x; g <= ng; g += blockDim.x) sce[g] = (float)a.cedge[b0 + g];
-        for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) {
+        for (int k = threadIdx.x; k < (G > 1 ? kBuckets : 0); k += blockDim.x) {
             const double lo = (double)clof + (k - 1) * (double)bw - 2.0 * guard;
             const double hi = (double)clof + (k + 2) * (double)bw + 2.0 * guard;
             const double mid = (double)clof + (k + 0.5) * (double)bw;
@@ -491,7 +491,8 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
         auto process = [&](int cnt) {
             const bool live = lane < cnt;
             const int k = live ? qidx[wave][lane] : 0;
-            const int bl = live ? qbin[wave][lane] : 0;
+            int bl = 0;
+            if constexpr (G > 1) bl = live ? qbin[wave][lane] : 0;
             // tangent components from the FP64 positions and frame, normalised
             // in FP64 and rounded once to FP32 (each rounding of the direction
             // enters the l-th harmonic about l times)
@@ -577,25 +578,33 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                     // (chif + guard rounded in FP32 would admit cosines up to
                     // one rounding beyond the guard)
                     if (c32 - chif <= guard && clof - c32 < guard) {
-                        // bin from the bucket table; near an edge, from the FP32
-                        // cosine against the edges, and within the guard band of
-                        // an edge from the FP64 dot product
-                        int kb = (int)((c32 - clof) * ibw);
-                        kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
-                        const int ent = sbk[kb];
-                        bl = ent & 0x7F;
                         valid = true;
-                        bool near = false;
-                        if (ent & 0x80) {
-                            while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
-                            while (bl > 0 && c32 > sce[bl]) bl--;
-                            near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
-                        }
-                        if (near) {
-                            const double c = dot_rn<D>(pc, a.spos, a.n, t);
-                            valid = c <= chi && c > clo;
-                            bl = 0;
-                            while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
+                        if constexpr (G == 1) {
+                            // one bin per pass: only its two edges, no table
+                            if (fabsf(c32 - chif) <= guard || fabsf(c32 - clof) <= guard) {
+                                const double c = dot_rn<D>(pc, a.spos, a.n, t);
+                                valid = c <= chi && c > clo;
+                            }
+                        } else {
+                            // bin from the bucket table; near an edge, from the FP32
+                            // cosine against the edges, and within the guard band of
+                            // an edge from the FP64 dot product
+                            int kb = (int)((c32 - clof) * ibw);
+                            kb = kb < 0 ? 0 : (kb >= kBuckets ? kBuckets - 1 : kb);
+                            const int ent = sbk[kb];
+                            bl = ent & 0x7F;
+                            bool near = false;
+                            if (ent & 0x80) {
+                                while (bl + 1 < ng && c32 <= sce[bl + 1]) bl++;
+                                while (bl > 0 && c32 > sce[bl]) bl--;
+                                near = fabsf(c32 - sce[bl]) <= guard || fabsf(c32 - sce[bl + 1]) <= guard;
+                            }
+                            if (near) {
+                                const double c = dot_rn<D>(pc, a.spos, a.n, t);
+                                valid = c <= chi && c > clo;
+                                bl = 0;
+                                while (bl + 1 < ng && c <= a.cedge[b0 + bl + 1]) bl++;
+                            }
                         }
                     }
                     if constexpr (K < 0) valid = valid && (t != js);   // the self pair, by index
@@ -606,7 +615,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                 if (valid) {
                     qidx[wave][slot] = (int)t;
                     if constexpr (D == 2) qw[wave][slot] = qcur.w;
-                    qbin[wave][slot] = bl;
+                    if constexpr (G > 1) qbin[wave][slot] = bl;
                 }
                 qn += __popcll(vm);
                 if (qn >= 64) {
@@ -619,13 +628,13 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                     if (lane < rest) {
                         mi = qidx[wave][64 + lane];
                         if constexpr (D == 2) mw = qw[wave][64 + lane];
-                        mb = qbin[wave][64 + lane];
+                        if constexpr (G > 1) mb = qbin[wave][64 + lane];
                     }
                     NPCF_SPH_WAVE_SYNC();
                     if (lane < rest) {
                         qidx[wave][lane] = mi;
                         if constexpr (D == 2) qw[wave][lane] = mw;
-                        qbin[wave][lane] = mb;
+                        if constexpr (G > 1) qbin[wave][lane] = mb;
                     }
                     qn = rest;
                     if (++batches == kSphFoldBatches) fold();

@@ -131,3 +131,32 @@ def strict_where_well_conditioned(got, ref, scale, kappa_max=3.0):
     _, errs = per_multipole_error(got, ref)
     sel = kappa <= kappa_max
     return (float(np.max(errs[sel])) if np.any(sel) else 0.0), int(np.sum(sel)), kappa
+
+
+def curved_widths(plan):
+    """The bins per pass a curved-space plan accepts (its kernel's two widths,
+    or one when they coincide), found by trying every value: the rule stays
+    in the library.  The plan keeps its default afterwards."""
+    from paper_2106_10278_amd.binding import NPCFError
+    default = plan.tuning()["curved_bins_per_pass"]
+    ok = []
+    for g in range(1, 17):
+        try:
+            plan.apply_tuning(curved_bins_per_pass=g)
+            ok.append(g)
+        except NPCFError:
+            pass
+    plan.apply_tuning(curved_bins_per_pass=default)
+    return ok
+
+
+def curved_plan(wl, width):
+    """A plan for a curved-space workload at its kernel's wide (default) or
+    narrow width."""
+    from paper_2106_10278_amd import NPCF
+    plan = NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, max_points=wl.pos.shape[1],
+                sphere=getattr(wl, "sphere", False), hyperbolic=getattr(wl, "hyperbolic", False))
+    if width == "narrow":
+        plan.apply_tuning(curved_bins_per_pass=min(curved_widths(plan)))
+    return plan
+

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2106_10278_amd import inputs
-from npcf_testutil import (alm_error, condition_scale, conditioned_error, gpu_run, oracle_reported,
+from npcf_testutil import (alm_error, condition_scale, conditioned_error, curved_plan, gpu_run, oracle_reported,
                            per_multipole_error, strict_where_well_conditioned)
 
 pytestmark = pytest.mark.gpu
@@ -73,11 +73,14 @@ def _window_points(D, edges, rng):
     return np.array(pts).T
 
 
+@pytest.mark.parametrize("width", ["wide", "narrow"])
 @pytest.mark.parametrize("D", [2, 3])
-def test_hyp_edge_windows(D):
+def test_hyp_edge_windows(D, width):
     """Points planted at the bin edges' distances from the origin, within and
     beyond the FP32 guard band: pair counts exact and results as the
-    oracle's.  11 bins take several passes."""
+    oracle's.  11 bins take several passes, at both kernel widths (one bin
+    per pass at the narrow one in H^3, which decides against the pass's two
+    edges without the bucket table)."""
     rng = np.random.default_rng(91 + D)
     edges = np.linspace(0.2, 2.0, 12)
     planted = _window_points(D, edges, rng)
@@ -87,12 +90,12 @@ def test_hyp_edge_windows(D):
     n = pos.shape[1]
     wl = inputs.Workload(f"h{D}-windows", D, 4, 4 if D == 3 else 3, edges, [_ball_volume(D, 2.0), 1.0, 1.0], pos,
                          rng.uniform(0.5, 1.5, size=n), n, hyperbolic=True)
-    print(f"[case] hyp edge windows D={D} n={n}", flush=True)
+    print(f"[case] hyp edge windows D={D} n={n} {width}", flush=True)
     ref, pairs_ref, _ = oracle_reported(wl)
-    got, pairs, _ = gpu_run(wl)
+    got, pairs, _ = gpu_run(wl, plan=curved_plan(wl, width))
     assert pairs == pairs_ref
     cerr, _ = conditioned_error(got, ref, condition_scale(wl))
-    print(f"[err] hyp edge windows D={D}: conditioned {cerr:.3e}", flush=True)
+    print(f"[err] hyp edge windows D={D} {width}: conditioned {cerr:.3e}", flush=True)
     assert cerr <= TOL["plain"]
 
 
@@ -176,21 +179,21 @@ def test_hyp_rejects():
         NPCF(3, 3, 2, e, [0.0, 1.0, 1.0], max_points=50, hyperbolic=True)  # V must be positive
 
 
-def test_h3_full_pair_count():
-    """Every ordered pair of the 100k-point H^3 catalogue (1e10 visited): the
-    number in the bins equals the FP64 oracle's count in
-    tests/golden/h3_pairs.json, written by make_h3_pairs.py, exactly."""
+@pytest.mark.parametrize("width", ["wide", "narrow"])
+def test_h3_full_pair_count(width):
+    """Every ordered pair of the 100k-point H^3 catalogue (1e10 visited), at
+    both kernel widths: the number in the bins equals the FP64 oracle's count
+    in tests/golden/h3_pairs.json, written by make_h3_pairs.py, exactly."""
     import json
     import os
     import torch
-    from paper_2106_10278_amd import NPCF
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "h3_pairs.json")))
     wl = inputs.c11_h3_4pcf()
     assert gold["workload"] == wl.name and gold["n"] == wl.pos.shape[1]
-    print("[case] h3 full pair count lmax=5", flush=True)
+    print(f"[case] h3 full pair count lmax=5 {width}", flush=True)
     pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).cuda()
     w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()
-    plan = NPCF(3, 4, 5, wl.edges, wl.box, max_points=wl.pos.shape[1], hyperbolic=True)
+    plan = curved_plan(wl, width)
     plan.accumulate(pos, w)
     assert plan.pair_count()[0] == gold["pairs"]
 
@@ -198,7 +201,7 @@ def test_h3_full_pair_count():
 _C11 = {}
 
 
-@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6"])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-narrow"])
 def test_h3_full_sampled(precision):
     """The H^3 workload at full size (100k clustered points): 32 primaries
     against every point, against the oracle on the same primaries, per
@@ -211,7 +214,11 @@ def test_h3_full_sampled(precision):
         _C11.update(wl=wl, ref=ref, pairs=pairs_ref, scale=condition_scale(wl, prims=prims))
     wl, ref, scale = _C11["wl"], _C11["ref"], _C11["scale"]
     print(f"[case] h3 full sampled {precision}", flush=True)
-    got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)
+    if precision == "plain-narrow":   # one bin per pass
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "narrow"))
+        precision = "plain"
+    else:
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)
     assert pairs == _C11["pairs"]
     err, _ = per_multipole_error(got, ref)
     cerr, _ = conditioned_error(got, ref, scale)

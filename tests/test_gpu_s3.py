@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2106_10278_amd import inputs
-from npcf_testutil import (alm_error, condition_scale, conditioned_error, gpu_run, oracle_reported,
+from npcf_testutil import (alm_error, condition_scale, conditioned_error, curved_plan, gpu_run, oracle_reported,
                            per_multipole_error, strict_where_well_conditioned)
 
 pytestmark = pytest.mark.gpu
@@ -77,11 +77,13 @@ def _window_points(cos_edges, rng):
     return np.array(pts).T
 
 
-def test_s3_edge_rounding_windows():
+@pytest.mark.parametrize("width", ["wide", "narrow"])
+def test_s3_edge_rounding_windows(width):
     """Cosines within the FP32 guard of a bin edge are decided in FP64, and
     ones just beyond an outer edge of a pass are not admitted: pair counts and
     results match the oracle on points planted at every edge.  11 bins at
-    lmax 4 take four passes of 3, 3, 3 and 2 bins."""
+    lmax 4 take four passes of 3, 3, 3 and 2 bins at the wide width, eleven
+    of one bin at the narrow one."""
     rng = np.random.default_rng(78)
     ce = np.array([0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2, 0.1, 0.0, -0.2, -0.4, -0.5])
     edges = np.arccos(ce)
@@ -89,12 +91,12 @@ def test_s3_edge_rounding_windows():
     pos = np.concatenate([np.array([[1.0], [0.0], [0.0], [0.0]]), planted, inputs.s3_points(rng, 150)], axis=1)
     n = pos.shape[1]
     wl = inputs.Workload("s3-windows", 3, 4, 4, edges, [1.0] * 3, pos, rng.uniform(0.5, 1.5, size=n), n, sphere=True)
-    print(f"[case] s3 edge windows n={n}", flush=True)
+    print(f"[case] s3 edge windows n={n} {width}", flush=True)
     ref, pairs_ref, _ = oracle_reported(wl)
-    got, pairs, _ = gpu_run(wl)
+    got, pairs, _ = gpu_run(wl, plan=curved_plan(wl, width))
     assert pairs == pairs_ref
     cerr, _ = conditioned_error(got, ref, condition_scale(wl))
-    print(f"[err] s3 edge windows plain: conditioned {cerr:.3e}", flush=True)
+    print(f"[err] s3 edge windows plain {width}: conditioned {cerr:.3e}", flush=True)
     assert cerr <= TOL["plain"]
 
 
@@ -144,22 +146,23 @@ def test_s3_rotation_invariance():
     assert cerr <= 1e-5
 
 
-def test_s3_full_pair_count():
-    """Every ordered pair of the 100k-point 3-sphere catalogue (1e10 visited,
-    five passes of two bins at lmax 5): the number in the bins equals the FP64
-    oracle's count in tests/golden/s3_pairs.json, written by
+@pytest.mark.parametrize("width", ["wide", "narrow"])
+def test_s3_full_pair_count(width):
+    """Every ordered pair of the 100k-point 3-sphere catalogue (1e10 visited;
+    four passes of up to three bins at lmax 5 at the wide width, ten of one
+    at the narrow one, the autotuner's choice here): the number in the bins
+    equals the FP64 oracle's count in tests/golden/s3_pairs.json, written by
     make_s3_pairs.py, exactly."""
     import json
     import os
     import torch
-    from paper_2106_10278_amd import NPCF
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "s3_pairs.json")))
     wl = inputs.c10_s3_4pcf()
     assert gold["workload"] == wl.name and gold["n"] == wl.pos.shape[1]
-    print("[case] s3 full pair count lmax=5", flush=True)
+    print(f"[case] s3 full pair count lmax=5 {width}", flush=True)
     pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).cuda()
     w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()
-    plan = NPCF(3, 4, 5, wl.edges, wl.box, max_points=wl.pos.shape[1], sphere=True)
+    plan = curved_plan(wl, width)
     plan.accumulate(pos, w)
     assert plan.pair_count()[0] == gold["pairs"]
 
@@ -167,7 +170,7 @@ def test_s3_full_pair_count():
 _C10 = {}
 
 
-@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6"])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-narrow"])
 def test_s3_full_sampled(precision):
     """The 3-sphere workload at full size (100k clustered points): 32
     primaries against every point, against the oracle on the same primaries,
@@ -182,7 +185,11 @@ def test_s3_full_sampled(precision):
         _C10.update(wl=wl, ref=ref, pairs=pairs_ref, scale=condition_scale(wl, prims=prims))
     wl, ref, scale = _C10["wl"], _C10["ref"], _C10["scale"]
     print(f"[case] s3 full sampled {precision}", flush=True)
-    got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)
+    if precision == "plain-narrow":   # one bin per pass, the width the autotuner takes here
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "narrow"))
+        precision = "plain"
+    else:
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)
     assert pairs == _C10["pairs"]
     err, _ = per_multipole_error(got, ref)
     cerr, _ = conditioned_error(got, ref, scale)

@@ -7,7 +7,8 @@ import pytest
 
 import oracle
 from paper_2106_10278_amd import inputs
-from npcf_testutil import alm_error, condition_scale, conditioned_error, gpu_run, oracle_reported, per_multipole_error
+from npcf_testutil import (alm_error, condition_scale, conditioned_error, curved_plan, gpu_run, oracle_reported,
+                           per_multipole_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -70,12 +71,14 @@ def _window_points(cos_edges, rng):
     return np.array(pts).T
 
 
-def test_sphere_edge_rounding_windows():
+@pytest.mark.parametrize("width", ["wide", "narrow"])
+def test_sphere_edge_rounding_windows(width):
     """Cosines beyond an outer edge of a pass by more than the guard but no
     more than one FP32 rounding of (edge + guard): the FP32 range prefilter
     must not admit them without the FP64 decision (regression: such pairs
     were counted, twice at a boundary between passes).  11 bins at lmax 4
-    take three passes of 5, 5 and 1 bins."""
+    take three passes of 5, 5 and 1 bins at the wide width, six of at most
+    2 at the narrow one."""
     rng = np.random.default_rng(77)
     ce = np.array([0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2, 0.1, 0.0, -0.2, -0.4, -0.5])
     edges = np.arccos(ce)
@@ -83,12 +86,12 @@ def test_sphere_edge_rounding_windows():
     pos = np.concatenate([np.array([[0.0], [0.0], [1.0]]), planted, inputs.sphere_points(rng, 150)], axis=1)
     n = pos.shape[1]
     wl = inputs.Workload("s2-windows", 2, 4, 4, edges, [1.0, 1.0], pos, rng.uniform(0.5, 1.5, size=n), n, sphere=True)
-    print(f"[case] sphere edge windows n={n}", flush=True)
+    print(f"[case] sphere edge windows n={n} {width}", flush=True)
     ref, pairs_ref, _ = oracle_reported(wl)
-    got, pairs, _ = gpu_run(wl)
+    got, pairs, _ = gpu_run(wl, plan=curved_plan(wl, width))
     assert pairs == pairs_ref
     cerr, _ = conditioned_error(got, ref, condition_scale(wl))
-    print(f"[err] sphere edge windows plain: conditioned {cerr:.3e}", flush=True)
+    print(f"[err] sphere edge windows plain {width}: conditioned {cerr:.3e}", flush=True)
     assert cerr <= TOL["plain"]
 
 
