@@ -232,14 +232,15 @@ constexpr int sph_slots(int D, int L) { return D == 2 ? 2 * (L + 1) : (L + 1) * 
 // (one per slot and bin) within a register budget, at least 1, at most 16 and
 // at most 128 values in all (two per lane after the fold).  Two budgets, one
 // kernel each, chosen per plan: wide (50 values on D = 2, 128 on D = 3; fewer
-// passes, so fewer scans of the points) and narrow (20 and 42; fewer masked
+// passes, so fewer scans of the points) and narrow (10 and 42, one bin per
+// pass from lmax 2 on D = 2 and lmax 5 on D = 3; fewer masked
 // sums per pair, more waves per SIMD, and at one bin per pass no bucket
 // table).  Which wins depends on the catalogue and the bins; the autotuner
-// times both (in the current kernel: the wide one on the uniform 2-sphere,
-// the narrow one on the clustered 3-sphere and in H^3).
+// times both (in the current kernel the narrow one wins on the uniform
+// 2-sphere, 25.6 against 27.2 ms, the clustered 3-sphere and H^3).
 constexpr int sph_group(int D, int L, bool narrow)
 {
-    const int budget = narrow ? (D == 2 ? 20 : 42) : (D == 2 ? 50 : 128);
+    const int budget = narrow ? (D == 2 ? 10 : 42) : (D == 2 ? 50 : 128);
     const int g = budget / sph_slots(D, L);
     const int g1 = g < 1 ? 1 : (g > 16 ? 16 : g);
     return g1 * sph_slots(D, L) <= 128 ? g1 : 128 / sph_slots(D, L);

@@ -38,7 +38,7 @@ def _wl(geo, seed):
 
 
 # (wide, narrow) bins per pass: S^2 / H^2 at lmax 4 (10 slots a bin), S^3 / H^3 at lmax 5 (42)
-WIDTHS = {"s2": (5, 2), "s3": (3, 1), "h2": (5, 2), "h3": (3, 1)}
+WIDTHS = {"s2": (5, 1), "s3": (3, 1), "h2": (5, 1), "h3": (3, 1)}
 
 
 @pytest.mark.parametrize("geo", list(WIDTHS))

@@ -77,8 +77,8 @@ def test_sphere_edge_rounding_windows(width):
     more than one FP32 rounding of (edge + guard): the FP32 range prefilter
     must not admit them without the FP64 decision (regression: such pairs
     were counted, twice at a boundary between passes).  11 bins at lmax 4
-    take three passes of 5, 5 and 1 bins at the wide width, six of at most
-    2 at the narrow one."""
+    take three passes of 5, 5 and 1 bins at the wide width, eleven of one
+    at the narrow one."""
     rng = np.random.default_rng(77)
     ce = np.array([0.5, 0.45, 0.4, 0.35, 0.3, 0.25, 0.2, 0.1, 0.0, -0.2, -0.4, -0.5])
     edges = np.arccos(ce)
