@@ -313,8 +313,9 @@ typedef struct {
     int64_t chunk_rows;          /* primaries per chunk (rows of a held at once) */
     int harmonic_blocks_per_cu;  /* persistent harmonic grid: blocks of four waves per compute unit, 1..32 */
     int curved_bins_per_pass;    /* curved geometries: radial bins per pass of the all-pairs kernel, one of the
-                                    two widths compiled for the plan's D and lmax (npcf_get_tuning reports the
-                                    current one; 0 on the flat geometry, and 0 keeps it) */
+                                    two widths compiled for the plan's D and lmax, the narrower by default
+                                    (npcf_get_tuning reports the current one; 0 on the flat geometry, and 0
+                                    keeps it) */
 } npcf_tuning;
 
 /* The plan's current tuning (the automatic values where nothing was set).

@@ -193,7 +193,8 @@ void compute_grid(npcf_plan_s *p)
         // cell hardly matters
         const int axes = p->t.curv > 0 ? p->D + 1 : p->D;
         p->curved_bits = axes == 2 ? 10 : (axes == 3 ? 7 : 5);
-        if (p->curved_group == 0) p->curved_group = sph_group(p->D, p->L, false);
+        // the narrow kernel by default: it won on every curved workload measured
+        if (p->curved_group == 0) p->curved_group = sph_group(p->D, p->L, true);
         p->ncell = (int64_t)1 << (p->curved_bits * axes);
         for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
         return;
@@ -1778,16 +1779,16 @@ npcf_status npcf_autotune(npcf_plan_t p, const double *pos, const double *w, int
         // curved spaces (no cell grid): the all-pairs kernel's two widths,
         // on the whole catalogue (which of them wins depends on the share of
         // visited pairs in the bins, which a part of the catalogue need not
-        // have); the wide one unless the narrow one wins by 2%
+        // have); the narrow one (the default) unless the wide one wins by 2%
         const int gw = sph_group(p->D, p->L, false), gn = sph_group(p->D, p->L, true);
-        std::vector<int> widths{gw};
-        if (gn != gw) widths.push_back(gn);
-        int best_w = gw;
+        std::vector<int> widths{gn};
+        if (gw != gn) widths.push_back(gw);
+        int best_w = gn;
         for (int g : widths) {
             p->curved_group = g;
             st = measure(whole, h, c);
             if (st != NPCF_OK) return st;
-            if (h < best_h * (g == gw ? 1.0 : 0.98)) {
+            if (h < best_h * (g == gn ? 1.0 : 0.98)) {
                 best_h = h;
                 best_w = g;
             }

@@ -151,12 +151,12 @@ def curved_widths(plan):
 
 
 def curved_plan(wl, width):
-    """A plan for a curved-space workload at its kernel's wide (default) or
-    narrow width."""
+    """A plan for a curved-space workload at its kernel's wide or narrow
+    (default) width."""
     from paper_2106_10278_amd import NPCF
     plan = NPCF(wl.D, wl.N, wl.lmax, wl.edges, wl.box, max_points=wl.pos.shape[1],
                 sphere=getattr(wl, "sphere", False), hyperbolic=getattr(wl, "hyperbolic", False))
-    if width == "narrow":
-        plan.apply_tuning(curved_bins_per_pass=min(curved_widths(plan)))
+    widths = curved_widths(plan)
+    plan.apply_tuning(curved_bins_per_pass=min(widths) if width == "narrow" else max(widths))
     return plan
 

@@ -56,7 +56,7 @@ def test_widths_match_oracle(geo):
                     hyperbolic=wl.hyperbolic)
 
     p = plan()
-    assert p.tuning()["curved_bins_per_pass"] == WIDTHS[geo][0]   # the wide kernel by default
+    assert p.tuning()["curved_bins_per_pass"] == WIDTHS[geo][1]   # the narrow kernel by default
     for g in WIDTHS[geo]:
         p = plan()
         p.apply_tuning(curved_bins_per_pass=g)
@@ -70,7 +70,7 @@ def test_widths_match_oracle(geo):
     p = plan()
     with pytest.raises(NPCFError):
         p.apply_tuning(curved_bins_per_pass=4)
-    assert p.tuning()["curved_bins_per_pass"] == WIDTHS[geo][0]
+    assert p.tuning()["curved_bins_per_pass"] == WIDTHS[geo][1]
     # the autotuner picks one of the two; results unchanged
     pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).cuda()
     w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()

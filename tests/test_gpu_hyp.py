@@ -201,7 +201,7 @@ def test_h3_full_pair_count(width):
 _C11 = {}
 
 
-@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-narrow"])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-wide"])
 def test_h3_full_sampled(precision):
     """The H^3 workload at full size (100k clustered points): 32 primaries
     against every point, against the oracle on the same primaries, per
@@ -214,8 +214,8 @@ def test_h3_full_sampled(precision):
         _C11.update(wl=wl, ref=ref, pairs=pairs_ref, scale=condition_scale(wl, prims=prims))
     wl, ref, scale = _C11["wl"], _C11["ref"], _C11["scale"]
     print(f"[case] h3 full sampled {precision}", flush=True)
-    if precision == "plain-narrow":   # one bin per pass
-        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "narrow"))
+    if precision == "plain-wide":   # three bins per pass (the default is one)
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "wide"))
         precision = "plain"
     else:
         got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)

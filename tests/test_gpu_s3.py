@@ -25,7 +25,8 @@ def _s3_wl(N, lmax, n, seed, edges, weights="mixed"):
                            n, sphere=True)
 
 
-# lmax 5 takes 2 bins per pass, lmax 4 three, lmax 2 seven, lmax 1 all 11
+# at the default (narrow) width lmax 5 and 4 take one bin per pass, lmax 3 two,
+# lmax 2 three and lmax 1 seven; test_gpu_curved_tuning.py covers the wide one
 CASES = {
     "n4-l5": (4, 5, 500, np.linspace(0.3, 1.5, 6), 0),
     "n4-l4-full": (4, 4, 400, np.array([0.2, 0.6, 1.1, 1.7]), 1),
@@ -170,7 +171,7 @@ def test_s3_full_pair_count(width):
 _C10 = {}
 
 
-@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-narrow"])
+@pytest.mark.parametrize("precision", ["plain", "mixed_bf16x6", "plain-wide"])
 def test_s3_full_sampled(precision):
     """The 3-sphere workload at full size (100k clustered points): 32
     primaries against every point, against the oracle on the same primaries,
@@ -185,8 +186,8 @@ def test_s3_full_sampled(precision):
         _C10.update(wl=wl, ref=ref, pairs=pairs_ref, scale=condition_scale(wl, prims=prims))
     wl, ref, scale = _C10["wl"], _C10["ref"], _C10["scale"]
     print(f"[case] s3 full sampled {precision}", flush=True)
-    if precision == "plain-narrow":   # one bin per pass, the width the autotuner takes here
-        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "narrow"))
+    if precision == "plain-wide":   # three bins per pass (the default is one)
+        got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], plan=curved_plan(wl, "wide"))
         precision = "plain"
     else:
         got, pairs, _ = gpu_run(wl, ranges=[(0, 32)], precision=precision)

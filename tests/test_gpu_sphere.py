@@ -95,23 +95,25 @@ def test_sphere_edge_rounding_windows(width):
     assert cerr <= TOL["plain"]
 
 
+@pytest.mark.parametrize("width", ["wide", "narrow"])
 @pytest.mark.parametrize("lmax", [1, 4, 5])
-def test_c9_full_pair_count(lmax):
+def test_c9_full_pair_count(lmax, width):
     """Every ordered pair of the 100k-point catalogue (1e10 visited): the
     number in the bins equals the FP64 oracle's count, stored in
     tests/golden/c9_sphere_pairs.json by make_c9_sphere_pairs.py, exactly.
-    lmax 1, 4 and 5 take the 10 bins in one, two and three passes."""
+    At the wide width lmax 1, 4 and 5 take the 10 bins in one, two and three
+    passes; at the narrow one in five, ten and ten."""
     import json
     import os
     import torch
-    from paper_2106_10278_amd import NPCF
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c9_sphere_pairs.json")))
     wl = inputs.c9_sphere_4pcf()
     assert gold["workload"] == wl.name and gold["n"] == wl.pos.shape[1]
-    print(f"[case] c9 full pair count lmax={lmax}", flush=True)
+    print(f"[case] c9 full pair count lmax={lmax} {width}", flush=True)
     pos = torch.from_numpy(np.ascontiguousarray(wl.pos)).cuda()
     w = torch.from_numpy(np.ascontiguousarray(wl.w)).cuda()
-    plan = NPCF(2, 4, lmax, wl.edges, wl.box, max_points=wl.pos.shape[1], sphere=True)
+    wl.lmax = lmax
+    plan = curved_plan(wl, width)
     plan.accumulate(pos, w)
     assert plan.pair_count()[0] == gold["pairs"]
 
