@@ -63,10 +63,14 @@ constexpr int kSphWaves = 8;
 // spatial order the pairs of a run of batches share bin and sign, so a
 // rounding in the fold weighs on the whole run: the fold comes after a fixed
 // number of batches, and its top steps add in FP64.  Measured on the
-// full-size 2-sphere, 3-sphere and H^3 workloads (32 primaries, strict
-// per-multipole error of the 2-sphere's): every 4 batches 4.2e-7, 8 4.7e-7,
-// 16 5.8e-7, for 2-sphere passes of 30.7, 27.4 and 25.8 ms
+// full-size 2-sphere workload (32 primaries, strict per-multipole error),
+// five bins per pass: every 4 batches 4.2e-7, 8 4.7e-7, 16 5.8e-7 (passes of
+// 30.7, 27.4 and 25.8 ms); one bin per pass, whose runs of one bin are
+// longer: every 8 batches 6.8e-7, every 4 4.8e-7 (25.8 and 27.2 ms).  Every
+// 8 batches, and every 4 at one bin per pass (where a fold is cheap).
 constexpr int kSphFoldBatches = 8;
+template <int G>
+constexpr int sph_fold_batches() { return G == 1 ? 4 : kSphFoldBatches; }
 constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are decided in FP64 (at least)
 
 // p.q in FP64, left to right with every product and sum rounded (no contraction)
@@ -637,7 +641,7 @@ __global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
                         if constexpr (G > 1) qbin[wave][lane] = mb;
                     }
                     qn = rest;
-                    if (++batches == kSphFoldBatches) fold();
+                    if (++batches == sph_fold_batches<G>()) fold();
                 }
                 cur = nxt;
                 qcur = qnxt;
