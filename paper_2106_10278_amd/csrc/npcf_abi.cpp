@@ -111,6 +111,7 @@ struct npcf_plan_s {
     int64_t ncell = 1;
     int curved_bits = 0;       // curved spaces: bits per axis of the Hilbert cells of the spatial sort
     int curved_group = 0;      // curved spaces: bins per pass of the all-pairs kernel (a sph_group value)
+    int harm_pass = 0;         // flat harmonic stage: 1 = one pass per radial bin, 0 = bin-sorted staging
     int64_t rows_cap_max = 0;  // rows the a buffer was sized for
     int njobs = 0;
     int max_block_terms = 0;  // N = 4: coupling terms one coupling block copies to LDS
@@ -336,6 +337,7 @@ HarmArgs harm_args(const npcf_plan_s *p, const Workspace &W, int rows, const int
     a.pairs = pairs;
     a.work = W.work;
     a.periodic = p->cfg.periodic;
+    a.per_bin = p->harm_pass;
     return a;
 }
 
@@ -1249,12 +1251,14 @@ npcf_status npcf_plan(const npcf_config *cfg, void *stream, int64_t max_points, 
         // the per-bin queue harmonic kernel is switched off (its first run
         // did not finish; no cause found yet): asking for it is an error
         const char *hv = std::getenv("NPCF_HARMONIC");
-        if (hv && std::strcmp(hv, "stage") != 0) {
+        if (hv && std::strcmp(hv, "stage") != 0 && std::strcmp(hv, "pass") != 0) {
             std::snprintf(g_last_error, sizeof(g_last_error),
-                          "NPCF_HARMONIC=%s: only 'stage' (bin-sorted staging) is available", hv);
+                          "NPCF_HARMONIC=%s: 'stage' (bin-sorted staging) or 'pass' (one pass per bin)", hv);
             delete p;
             return NPCF_E_UNSUPPORTED;
         }
+        // one pass per bin by default (where the instance has it: D = 2, 3)
+        p->harm_pass = !(hv && std::strcmp(hv, "stage") == 0);
     }
     {
         const int L = p->L;

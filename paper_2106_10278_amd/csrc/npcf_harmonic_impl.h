@@ -31,6 +31,7 @@
 //    bursts of one bin into a batch), and the summation order is fixed.
 #pragma once
 #include "npcf_harmonic_scan.h"
+#include "npcf_harmonic_pass.h"
 
 namespace npcf {
 namespace harm {
@@ -380,6 +381,23 @@ int lds_bytes() { return Cfg<D, L>::LDS_BYTES; }
 template <int D, int L>
 hipError_t launch_dl(const HarmArgs &a, int grid, hipStream_t s)
 {
+    if constexpr (pass_supported<D, L>()) {
+        if (a.per_bin) {
+            const int lds = pass_lds_bytes<D, L>();
+            if (a.periodic) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, true>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_harmonic_pass<D, L, true>), dim3(grid), dim3(256), lds, s, a);
+            } else {
+                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, false>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_harmonic_pass<D, L, false>), dim3(grid), dim3(256), lds, s, a);
+            }
+            return hipGetLastError();
+        }
+    }
     const int lds = lds_bytes<D, L>();
     if (a.periodic) {
         hipError_t e = hipFuncSetAttribute((const void *)k_harmonic<D, L, true>,

@@ -73,6 +73,7 @@ struct HarmArgs {
     const int64_t *cat_begin;
     int ncat;
     int64_t ncell_cat;
+    int per_bin;              // 1: one pass per radial bin (k_harmonic_pass) where the instance has it
 };
 
 // ---------------------------------------------------------------------------
