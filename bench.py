@@ -190,7 +190,18 @@ def _sources_hash(files) -> str:
 
 
 def kernel_source_hash() -> str:
-    return _sources_hash(("npcf_harmonic_impl.h", "npcf_harmonic_scan.h", "npcf_harmonics.h"))
+    return _sources_hash(("npcf_harmonic_impl.h", "npcf_harmonic_pass.h", "npcf_harmonic_scan.h", "npcf_harmonics.h",
+                          "npcf_lanefold.h"))
+
+
+def harmonic_kernel_name(D: int, lmax: int) -> str:
+    """The flat harmonic-stage kernel a plan launches: one pass per radial
+    bin where the instance has it (D = 2 and 3, at most 128 slots per bin),
+    else the bin-sorted staging kernel; NPCF_HARMONIC=stage picks the latter."""
+    slots = 2 * (lmax + 1 if D == 2 else ((lmax + 1) * (lmax + 2) // 2 if D == 3 else 10 ** 9))
+    if os.environ.get("NPCF_HARMONIC") == "stage" or D > 3 or slots > 128:
+        return "k_harmonic"
+    return "k_harmonic_pass"
 
 
 def load_traffic(key: str):
@@ -509,7 +520,7 @@ def main():
     key = f"D{wl.D}-N{wl.N}-lmax{wl.lmax}-{wl.name}"
     fpp = scope_flops_per_pair(wl.D, wl.lmax)
     achieved = fpp * r["pairs_per_step"] / (r["harmonic_ms_per_launch"] * 1e-3)
-    roof = {"kernel": "k_harmonic", "bound": "alu", "achieved": achieved / 1e12,
+    roof = {"kernel": harmonic_kernel_name(wl.D, wl.lmax), "bound": "alu", "achieved": achieved / 1e12,
             "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
             "traffic": load_traffic(key), "flops_per_pair": fpp,
             "flops_per_pair_instruction_level": flops_per_pair(wl.D, wl.lmax),

@@ -348,6 +348,27 @@ def test_harmonic_kernels_agree(name, monkeypatch):
     assert cerr <= 2e-6
 
 
+@pytest.mark.parametrize("name", ["D3N4", "D2N4", "D3N3", "D3N4L6", "D3N4dense"])
+def test_harmonic_pass_and_stage_agree(name, monkeypatch):
+    """The two flat harmonic-stage kernels (one pass per radial bin, the
+    default; bin-sorted staging, NPCF_HARMONIC=stage) give the oracle's pair
+    counts and agree with it and with each other, on the tiny cases and on a
+    dense catalogue with many batches per bin."""
+    wl = _case(*(TINY[name] if name in TINY else MANY_PAIRS["D3N4dense"]))
+    print(f"[case] harmonic pass and stage {name}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    scale = condition_scale(wl)
+    monkeypatch.setenv("NPCF_HARMONIC", "stage")
+    st, ps, _ = gpu_run(wl)
+    monkeypatch.setenv("NPCF_HARMONIC", "pass")
+    pa, pp, _ = gpu_run(wl)
+    assert ps == pp == pairs_ref
+    _check(st, ref, "plain", scale, f"{name} staging", strict=False)
+    _check(pa, ref, "plain", scale, f"{name} per-bin passes", strict=False)
+    cerr, _ = conditioned_error(st, pa, scale)
+    assert cerr <= 2e-6
+
+
 MANY_PAIRS = {
     # about 900-1200 pairs per primary: many 64-pair batches per primary with
     # bursts of one bin, up to 16 bins
