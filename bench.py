@@ -196,10 +196,11 @@ def kernel_source_hash() -> str:
 
 def harmonic_kernel_name(D: int, lmax: int) -> str:
     """The flat harmonic-stage kernel a plan launches: one pass per radial
-    bin where the instance has it (D = 2 and 3, at most 128 slots per bin),
-    else the bin-sorted staging kernel; NPCF_HARMONIC=stage picks the latter."""
-    slots = 2 * (lmax + 1 if D == 2 else ((lmax + 1) * (lmax + 2) // 2 if D == 3 else 10 ** 9))
-    if os.environ.get("NPCF_HARMONIC") == "stage" or D > 3 or slots > 128:
+    bin where the instance has it (at most 128 slots per bin: D = 4 up to
+    lmax 5), else the bin-sorted staging kernel; NPCF_HARMONIC=stage picks the
+    latter."""
+    states = {2: lmax + 1, 3: (lmax + 1) * (lmax + 2) // 2, 4: (lmax + 1) * (lmax + 2) * (lmax + 3) // 6}[D]
+    if os.environ.get("NPCF_HARMONIC") == "stage" or 2 * states > 128:
         return "k_harmonic"
     return "k_harmonic_pass"
 

@@ -10,7 +10,8 @@
 // is in the pass's bin or rejected by the FP64 test, so each lane adds the
 // harmonics it emits straight into its own FP32 sums (one register per slot,
 // no sorting by bin, no staging), and every few batches the wave folds its
-// lanes into FP64 values held one or two per lane.  The FP32 pre-test on
+// lanes into FP64 values held one or two per lane.  D = 4 keeps its weight
+// beside the record (in the queue too).  The FP32 pre-test on
 // r^2 is widened by 1e-5 relative at both edges of the pass, and the FP64
 // r^2 with the definition's arithmetic decides, as in the staged kernel.
 #pragma once
@@ -21,7 +22,11 @@ namespace npcf {
 namespace harm {
 
 constexpr int kPassSegCap = 256;      // candidate segments per 64 stencil rows (up to four per row)
-constexpr int kPassFoldBatches = 4;   // queued batches between folds of the lanes' sums
+// queued batches between folds of the lanes' sums.  c2 (32 + 32 sampled
+// primaries, plain strict / conditioned per-multipole error; harmonic ms):
+// every 2 batches 5.7e-7 / 6.5e-8, 130.2 ms; 4: 8.0e-7 / 6.7e-8, 112.6 ms;
+// 8: 6.4e-7 / 1.2e-7, 104.6 ms
+constexpr int kPassFoldBatches = 8;
 
 // Candidates of the shell rlo2 <= r^2 < rhi2 (physical units, FP64; rlo2 and
 // rhi2 taken slightly wide by the caller) through the cell list, tested
@@ -194,15 +199,24 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
         };
         uint32_t pb = cb0, pe = ce0;
         uint4 pr = make_uint4(0, 0, 0, 0);
-        if (cb0 + (uint32_t)lane < ce0) pr = a.rec[cb0 + lane];
+        float pw = 0.f;   // D = 4: the weight beside the record
+        if (cb0 + (uint32_t)lane < ce0) {
+            pr = a.rec[cb0 + lane];
+            if (D == 4) pw = a.w[cb0 + lane];
+        }
         advance();
         while (pb < pe) {
             const uint4 cur = pr;
+            const float curw = pw;
             const uint32_t b0 = pb, s1 = pe;
             pb = cb0;
             pe = ce0;
             pr = make_uint4(0, 0, 0, 0);
-            if (cb0 + (uint32_t)lane < ce0) pr = a.rec[cb0 + lane];
+            pw = 0.f;
+            if (cb0 + (uint32_t)lane < ce0) {
+                pr = a.rec[cb0 + lane];
+                if (D == 4) pw = a.w[cb0 + lane];
+            }
             advance();
             bool inr = false;
             int dq[D];
@@ -226,21 +240,24 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
                 }
                 inr = fits && r2f >= flo && r2f < fhi;
             }
-            take(inr, dq, cur, 0.f);
+            take(inr, dq, cur, curw);
         }
     }
 }
 
 // Values per lane of the per-bin kernel: every slot of a bin (the imaginary
-// slots of real states stay zero), at most 128 (two per lane after the fold)
+// slots of real states stay zero), at most 128 (two per lane after the fold).
+// D = 4 at lmax 6 has 168: its 168 register sums next to the recurrences'
+// registers would leave one wave per SIMD (256 VGPRs), and it keeps the
+// staging kernel (two waves).
 template <int D, int L>
-constexpr bool pass_supported() { return D <= 3 && 2 * stored_states(D, L) <= 128; }
+constexpr bool pass_supported() { return 2 * stored_states(D, L) <= 128; }
 
 template <int D, int L, bool PER>
 __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
 {
     constexpr int SLOTS = 2 * stored_states(D, L);
-    constexpr int WAVE_BYTES = kQCap * 16 + kPassSegCap * 8;
+    constexpr int WAVE_BYTES = kQCap * (D == 4 ? 20 : 16) + kPassSegCap * 8;
     extern __shared__ __align__(16) char smem[];
     const int nb = a.nb;
     const int lane = (int)lane_id();
@@ -248,8 +265,9 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
     double *e2 = reinterpret_cast<double *>(smem);
     for (int t = threadIdx.x; t <= nb; t += blockDim.x) e2[t] = a.e2[t];
     char *wb = smem + kTableBytes + wave * WAVE_BYTES;
-    int4 *q4 = reinterpret_cast<int4 *>(wb);                       // [kQCap]
-    uint2 *segs = reinterpret_cast<uint2 *>(wb + kQCap * 16);      // [kPassSegCap]
+    int4 *q4 = reinterpret_cast<int4 *>(wb);                                   // [kQCap]
+    float *qwx = reinterpret_cast<float *>(wb + kQCap * 16);                   // [kQCap] (D = 4 weight)
+    uint2 *segs = reinterpret_cast<uint2 *>(wb + kQCap * (D == 4 ? 20 : 16));  // [kPassSegCap]
     __syncthreads();
     const int nacc = nb * SLOTS;
 
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
         uint32_t qi[D];
 #pragma unroll
         for (int k = 0; k < D; k++) qi[k] = rec_coord<D>(ri, k);
-        const float wi = D == 3 ? __int_as_float((int)ri.w) : __int_as_float((int)ri.z);
+        const float wi = D == 4 ? a.w[ip] : (D == 3 ? __int_as_float((int)ri.w) : __int_as_float((int)ri.z));
         float *Arow = a.A + (size_t)row * nacc;
 
         for (int b = 0; b < nb; b++) {
@@ -305,7 +323,12 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
                     dq[0] = e.x;
                     dq[1] = e.y;
                     if (D >= 3) dq[2] = e.z;
-                    wk = __int_as_float(D == 3 ? e.w : e.z);
+                    if (D == 4) {
+                        dq[3] = e.w;
+                        wk = live ? qwx[lane] : 0.f;
+                    } else {
+                        wk = __int_as_float(D == 3 ? e.w : e.z);
+                    }
                 }
                 // r^2 summed axis by axis without contraction (the definition's
                 // arithmetic), the unit vector normalised in FP64 and rounded
@@ -331,11 +354,14 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
             scan_shell<D, PER>(a, cs, qi, segs, lane, elo * (1.0 - 1e-9), ehi * (1.0 + 1e-9),
                                (float)(elo * (1.0 - 1e-5)), (float)(ehi * (1.0 + 1e-5)),
                                [&](bool inr, const int (&dq)[D], const uint4 &cur, float curw) __attribute__((always_inline)) {
-                queue_append<D>(inr, dq, cur, curw, q4, nullptr, qn);
+                queue_append<D>(inr, dq, cur, curw, q4, qwx, qn);
                 if (qn >= 64) {
                     process(64);
                     const int rest = qn - 64;
-                    if (lane < rest) q4[lane] = q4[64 + lane];
+                    if (lane < rest) {
+                        q4[lane] = q4[64 + lane];
+                        if (D == 4) qwx[lane] = qwx[64 + lane];
+                    }
                     qn = rest;
                     NPCF_WAVE_SYNC();
                 }
@@ -351,7 +377,7 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
 }
 
 template <int D, int L>
-constexpr int pass_lds_bytes() { return kTableBytes + 4 * (kQCap * 16 + kPassSegCap * 8); }
+constexpr int pass_lds_bytes() { return kTableBytes + 4 * (kQCap * (D == 4 ? 20 : 16) + kPassSegCap * 8); }
 
 }  // namespace harm
 }  // namespace npcf

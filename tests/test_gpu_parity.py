@@ -348,7 +348,7 @@ def test_harmonic_kernels_agree(name, monkeypatch):
     assert cerr <= 2e-6
 
 
-@pytest.mark.parametrize("name", ["D3N4", "D2N4", "D3N3", "D3N4L6", "D3N4dense"])
+@pytest.mark.parametrize("name", ["D3N4", "D2N4", "D3N3", "D4N3", "D3N4L6", "D3N4dense"])
 def test_harmonic_pass_and_stage_agree(name, monkeypatch):
     """The two flat harmonic-stage kernels (one pass per radial bin, the
     default; bin-sorted staging, NPCF_HARMONIC=stage) give the oracle's pair
