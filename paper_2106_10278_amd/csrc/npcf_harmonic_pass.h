@@ -175,13 +175,17 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
         }
         NPCF_WAVE_SYNC();
 
-        // candidate batches of 64 over the segments, one batch of loads in flight
+        // candidate batches of 64 over the segments, one batch of loads in
+        // flight.  The segment bounds are the same for every lane (one LDS
+        // address); reading them through readfirstlane keeps them, the batch
+        // loop and the queue count in scalar registers, so the loop branches
+        // on scalars instead of masking lanes
         int ci = 0;
         uint32_t cb0 = 0, ce0 = 0;
         if (nseg > 0) {
             const uint2 sg = segs[0];
-            cb0 = sg.x;
-            ce0 = sg.y;
+            cb0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.x);
+            ce0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.y);
         }
         auto advance = [&]() __attribute__((always_inline)) {
             cb0 += 64;
@@ -189,21 +193,26 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
                 ci++;
                 if (ci < nseg) {
                     const uint2 sg = segs[ci];
-                    cb0 = sg.x;
-                    ce0 = sg.y;
+                    cb0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.x);
+                    ce0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.y);
                 } else {
                     cb0 = 0;
                     ce0 = 0;
                 }
             }
         };
+        // every lane loads: lanes past the batch's end read record 0 (there is
+        // at least the primary) and are masked at the test
+        auto load = [&](uint4 &r, float &w) __attribute__((always_inline)) {
+            const uint32_t g = cb0 + (uint32_t)lane;
+            const uint32_t idx = g < ce0 ? g : 0u;
+            r = a.rec[idx];
+            if (D == 4) w = a.w[idx];
+        };
         uint32_t pb = cb0, pe = ce0;
-        uint4 pr = make_uint4(0, 0, 0, 0);
+        uint4 pr;
         float pw = 0.f;   // D = 4: the weight beside the record
-        if (cb0 + (uint32_t)lane < ce0) {
-            pr = a.rec[cb0 + lane];
-            if (D == 4) pw = a.w[cb0 + lane];
-        }
+        load(pr, pw);
         advance();
         while (pb < pe) {
             const uint4 cur = pr;
@@ -211,35 +220,28 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
             const uint32_t b0 = pb, s1 = pe;
             pb = cb0;
             pe = ce0;
-            pr = make_uint4(0, 0, 0, 0);
-            pw = 0.f;
-            if (cb0 + (uint32_t)lane < ce0) {
-                pr = a.rec[cb0 + lane];
-                if (D == 4) pw = a.w[cb0 + lane];
-            }
+            load(pr, pw);
             advance();
-            bool inr = false;
+            // every lane holds a record, so the test needs no branch
             int dq[D];
-            if (b0 + (uint32_t)lane < s1) {
-                float r2f = 0.f;
-                bool fits = true;
+            float r2f = 0.f;
+            bool fits = true;
 #pragma unroll
-                for (int k = 0; k < D; k++) {
-                    const uint32_t qk = rec_coord<D>(cur, k);
-                    int d;
-                    if (PER) {
-                        d = (int)(qk - qi[k]);   // two's-complement wrap = minimum image
-                    } else {
-                        const long long dl = (long long)qk - (long long)qi[k];
-                        d = (int)dl;
-                        fits = fits && (long long)d == dl;
-                    }
-                    dq[k] = d;
-                    const float fv = (float)d * a.scale[k];
-                    r2f += fv * fv;
+            for (int k = 0; k < D; k++) {
+                const uint32_t qk = rec_coord<D>(cur, k);
+                int d;
+                if (PER) {
+                    d = (int)(qk - qi[k]);   // two's-complement wrap = minimum image
+                } else {
+                    const long long dl = (long long)qk - (long long)qi[k];
+                    d = (int)dl;
+                    fits = fits && (long long)d == dl;
                 }
-                inr = fits && r2f >= flo && r2f < fhi;
+                dq[k] = d;
+                const float fv = (float)d * a.scale[k];
+                r2f += fv * fv;
             }
+            const bool inr = b0 + (uint32_t)lane < s1 && fits && r2f >= flo && r2f < fhi;
             take(inr, dq, cur, curw);
         }
     }
@@ -315,17 +317,19 @@ __global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
             // harmonics of the pairs in it go into the lanes' sums
             auto process = [&](int cnt) __attribute__((always_inline)) {
                 NPCF_WAVE_SYNC();
+                // every lane reads its queue entry (stale past cnt, masked
+                // out by valid below: the harmonics see only valid values)
                 const bool live = lane < cnt;
                 int dq[D];
                 float wk;
                 {
-                    const int4 e = live ? q4[lane] : make_int4(0, 0, 0, 0);
+                    const int4 e = q4[lane];
                     dq[0] = e.x;
                     dq[1] = e.y;
                     if (D >= 3) dq[2] = e.z;
                     if (D == 4) {
                         dq[3] = e.w;
-                        wk = live ? qwx[lane] : 0.f;
+                        wk = qwx[lane];
                     } else {
                         wk = __int_as_float(D == 3 ? e.w : e.z);
                     }

@@ -218,12 +218,14 @@ __device__ __forceinline__ void scan_candidates(const HarmArgs &a, const uint32_
         // candidate batches of 64 over the chunk's segments, streamed
         // through kPrefetch loads in flight (across segment ends): batch p
         // holds records [pb[p], pe[p]) of one segment, pb == pe past the end
+        // The segment bounds are the same for every lane (one LDS address):
+        // readfirstlane keeps them and the batch loop in scalar registers.
         int ci = 0;
         uint32_t cb = 0, ce = 0;
         if (nseg > 0) {
             const uint2 sg = segs[0];
-            cb = sg.x;
-            ce = sg.y;
+            cb = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.x);
+            ce = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.y);
         }
         auto advance = [&]() __attribute__((always_inline)) {
             cb += 64;
@@ -231,13 +233,21 @@ __device__ __forceinline__ void scan_candidates(const HarmArgs &a, const uint32_
                 ci++;
                 if (ci < nseg) {
                     const uint2 sg = segs[ci];
-                    cb = sg.x;
-                    ce = sg.y;
+                    cb = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.x);
+                    ce = (uint32_t)__builtin_amdgcn_readfirstlane((int)sg.y);
                 } else {
                     cb = 0;
                     ce = 0;
                 }
             }
+        };
+        // every lane loads: lanes past the batch's end read record 0 (there is
+        // at least the primary) and are masked at the test
+        auto load = [&](uint4 &r, float &w) __attribute__((always_inline)) {
+            const uint32_t g = cb + (uint32_t)lane;
+            const uint32_t idx = g < ce ? g : 0u;
+            r = a.rec[idx];
+            w = D == 4 ? a.w[idx] : 0.f;
         };
         uint4 pr[kPrefetch];
         float pw[kPrefetch];
@@ -246,12 +256,7 @@ __device__ __forceinline__ void scan_candidates(const HarmArgs &a, const uint32_
         for (int p = 0; p < kPrefetch; p++) {
             pb[p] = cb;
             pe[p] = ce;
-            pr[p] = make_uint4(0, 0, 0, 0);
-            pw[p] = 0.f;
-            if (cb + (uint32_t)lane < ce) {
-                pr[p] = a.rec[cb + lane];
-                if (D == 4) pw[p] = a.w[cb + lane];
-            }
+            load(pr[p], pw[p]);
             advance();
         }
         while (pb[0] < pe[0]) {
@@ -268,36 +273,29 @@ __device__ __forceinline__ void scan_candidates(const HarmArgs &a, const uint32_
             }
             pb[kPrefetch - 1] = cb;
             pe[kPrefetch - 1] = ce;
-            pr[kPrefetch - 1] = make_uint4(0, 0, 0, 0);
-            pw[kPrefetch - 1] = 0.f;
-            if (cb + (uint32_t)lane < ce) {
-                pr[kPrefetch - 1] = a.rec[cb + lane];
-                if (D == 4) pw[kPrefetch - 1] = a.w[cb + lane];
-            }
+            load(pr[kPrefetch - 1], pw[kPrefetch - 1]);
             advance();
             {
-                bool inr = false;
+                // every lane holds a record, so the test needs no branch
                 int dq[D];
-                if (b0 + (uint32_t)lane < s1) {
-                    float r2f = 0.f;
-                    bool fits = true;
+                float r2f = 0.f;
+                bool fits = true;
 #pragma unroll
-                    for (int k = 0; k < D; k++) {
-                        const uint32_t qk = rec_coord<D>(cur, k);
-                        int d;
-                        if (PER) {
-                            d = (int)(qk - qi[k]);  // two's-complement wrap = minimum image
-                        } else {
-                            const long long dl = (long long)qk - (long long)qi[k];
-                            d = (int)dl;
-                            fits = fits && (long long)d == dl;
-                        }
-                        dq[k] = d;
-                        const float fv = (float)d * a.scale[k];
-                        r2f += fv * fv;
+                for (int k = 0; k < D; k++) {
+                    const uint32_t qk = rec_coord<D>(cur, k);
+                    int d;
+                    if (PER) {
+                        d = (int)(qk - qi[k]);  // two's-complement wrap = minimum image
+                    } else {
+                        const long long dl = (long long)qk - (long long)qi[k];
+                        d = (int)dl;
+                        fits = fits && (long long)d == dl;
                     }
-                    inr = fits && r2f >= e2lo_f && r2f < e2hi_f;
+                    dq[k] = d;
+                    const float fv = (float)d * a.scale[k];
+                    r2f += fv * fv;
                 }
+                const bool inr = b0 + (uint32_t)lane < s1 && fits && r2f >= e2lo_f && r2f < e2hi_f;
                 take(inr, dq, cur, curw);
             }
         }
