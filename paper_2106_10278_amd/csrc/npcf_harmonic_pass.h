@@ -255,8 +255,15 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
 template <int D, int L>
 constexpr bool pass_supported() { return 2 * stored_states(D, L) <= 128; }
 
+// Waves per SIMD the compiler is held to.  D = 3 at lmax 4 and 5 would take
+// 100 and 108 VGPRs, four waves per SIMD; at 96 they run five (two values of
+// lmax 5 spill outside the pair loop, reloaded once per 64 stencil rows):
+// c2 harmonic 95.2 -> 87.1 ms.  Elsewhere no bound beyond the block size's.
+template <int D, int L>
+constexpr int pass_waves() { return D == 3 && (L == 4 || L == 5) ? 5 : 1; }
+
 template <int D, int L, bool PER>
-__global__ __launch_bounds__(256) void k_harmonic_pass(HarmArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_waves<D, L>()))) void k_harmonic_pass(HarmArgs a)
 {
     constexpr int SLOTS = 2 * stored_states(D, L);
     constexpr int WAVE_BYTES = kQCap * (D == 4 ? 20 : 16) + kPassSegCap * 8;
