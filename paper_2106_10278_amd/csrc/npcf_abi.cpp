@@ -200,21 +200,31 @@ void compute_grid(npcf_plan_s *p)
         for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
         return;
     }
+    // Cells of side about rmax / s, except along x, the axis a stencil row
+    // of cells runs along: there they are kCellXSub times thinner, so a
+    // row's x range is cut to the sphere (and the inner sphere's cells left
+    // out) more tightly, with the same number of rows and the same per-row
+    // work.  c2 harmonic stage, s = 4: 87.3 ms with cubic cells, 82.5 / 80.2 /
+    // 78.7 / 77.9 ms at 2 / 4 / 8 / 16 thinner x cells (pair counts equal).
+    // Over 2^24 cells the x factor halves first, then s drops.
+    constexpr int kCellXSub = 8;
     const double rmax = p->edges[p->nb];
     int64_t total = 1;
     for (int k = 0; k < kMaxD; k++) p->ncs[k] = 1;
-    int s = p->cell_subdiv;
+    int s = p->cell_subdiv, xs = kCellXSub;
     for (;;) {
         total = 1;
         for (int k = 0; k < p->D; k++) {
             double c = std::floor(p->cfg.box[k] / (rmax / s));
             if (c < 1) c = 1;
+            if (k == 0) c *= xs;
             if (c > 4096) c = 4096;
             p->ncs[k] = (int)c;
             total *= p->ncs[k];
         }
-        if (total <= (1LL << 24) || s == 1) break;
-        s--;
+        if (total <= (1LL << 24) || (s == 1 && xs == 1)) break;
+        if (xs > 1) xs /= 2;
+        else s--;
     }
     p->ncell = total;
 }
