@@ -330,6 +330,8 @@ HarmArgs harm_args(const npcf_plan_s *p, const Workspace &W, int rows, const int
         a.scale[k] = (float)sc;
         a.rmax_lat[k] = p->edges[p->nb] / sc;
     }
+    a.cube = 1;
+    for (int k = 1; k < p->D; k++) a.cube = a.cube && a.scale64[k] == a.scale64[0];
     a.w = W.ws;
     a.cell_start = W.cell_start;
     a.prim = prim;

@@ -208,8 +208,8 @@ __global__ __launch_bounds__(256) void k_harmonic(HarmArgs a)
             double r2 = 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
-                v[k] = __dmul_rn((double)dq[k], a.scale64[k]);
-                r2 = __dadd_rn(r2, __dmul_rn(v[k], v[k]));
+                v[k] = mul_rn((double)dq[k], a.scale64[k]);
+                r2 = add_rn(r2, mul_rn(v[k], v[k]));
             }
             int bin;
             {
@@ -384,16 +384,23 @@ hipError_t launch_dl(const HarmArgs &a, int grid, hipStream_t s)
     if constexpr (pass_supported<D, L>()) {
         if (a.per_bin) {
             const int lds = pass_lds_bytes<D, L>();
-            if (a.periodic) {
-                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, true>,
+            // periodic cubes have their own instance (CUBE); open boxes take
+            // the general test whatever their shape
+            if (a.periodic && a.cube) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, true, true>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL((k_harmonic_pass<D, L, true>), dim3(grid), dim3(256), lds, s, a);
+                hipLaunchKernelGGL((k_harmonic_pass<D, L, true, true>), dim3(grid), dim3(256), lds, s, a);
+            } else if (a.periodic) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, true, false>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_harmonic_pass<D, L, true, false>), dim3(grid), dim3(256), lds, s, a);
             } else {
-                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, false>,
+                hipError_t e = hipFuncSetAttribute((const void *)k_harmonic_pass<D, L, false, false>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL((k_harmonic_pass<D, L, false>), dim3(grid), dim3(256), lds, s, a);
+                hipLaunchKernelGGL((k_harmonic_pass<D, L, false, false>), dim3(grid), dim3(256), lds, s, a);
             }
             return hipGetLastError();
         }

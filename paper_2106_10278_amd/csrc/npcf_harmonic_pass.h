@@ -31,12 +31,14 @@ constexpr int kPassFoldBatches = 8;
 // Candidates of the shell rlo2 <= r^2 < rhi2 (physical units, FP64; rlo2 and
 // rhi2 taken slightly wide by the caller) through the cell list, tested
 // against the FP32 bounds [flo, fhi) and handed to take() 64 at a time, as
-// scan_candidates does for the whole range.  Per stencil row the x range of
+// scan_candidates does for the whole range.  CUBE (every axis the same lattice
+// scale): the FP32 test sums the squared lattice differences and the bounds
+// come in squared lattice units, three multiplies fewer per candidate.  Per stencil row the x range of
 // cells is cut to the outer sphere, and the cells wholly inside the inner
 // sphere are left out (when no axis of the stencil wraps the whole periodic
 // box), so a row gives up to two intervals of cells, each split in two where
 // it wraps the periodic box.
-template <int D, bool PER, class Take>
+template <int D, bool PER, bool CUBE, class Take>
 __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs, const uint32_t (&qi)[D],
                                            uint2 *segs, int lane, double rlo2, double rhi2, float flo, float fhi,
                                            Take &&take)
@@ -202,25 +204,27 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
             }
         };
         // every lane loads: lanes past the batch's end read record 0 (there is
-        // at least the primary) and are masked at the test
-        auto load = [&](uint4 &r, float &w) __attribute__((always_inline)) {
+        // at least the primary) and are masked at the test by ok, which
+        // travels with the record as a lane mask
+        auto load = [&](uint4 &r, float &w, bool &ok) __attribute__((always_inline)) {
             const uint32_t g = cb0 + (uint32_t)lane;
-            const uint32_t idx = g < ce0 ? g : 0u;
+            ok = g < ce0;
+            const uint32_t idx = ok ? g : 0u;
             r = a.rec[idx];
             if (D == 4) w = a.w[idx];
         };
-        uint32_t pb = cb0, pe = ce0;
+        bool more = cb0 < ce0;   // the batch in flight holds records (wave-uniform)
         uint4 pr;
         float pw = 0.f;   // D = 4: the weight beside the record
-        load(pr, pw);
+        bool pok;
+        load(pr, pw, pok);
         advance();
-        while (pb < pe) {
+        while (more) {
             const uint4 cur = pr;
             const float curw = pw;
-            const uint32_t b0 = pb, s1 = pe;
-            pb = cb0;
-            pe = ce0;
-            load(pr, pw);
+            const bool curok = pok;
+            more = cb0 < ce0;
+            load(pr, pw, pok);
             advance();
             // every lane holds a record, so the test needs no branch
             int dq[D];
@@ -238,10 +242,10 @@ __device__ __forceinline__ void scan_shell(const HarmArgs &a, const uint32_t *cs
                     fits = fits && (long long)d == dl;
                 }
                 dq[k] = d;
-                const float fv = (float)d * a.scale[k];
+                const float fv = CUBE ? (float)d : (float)d * a.scale[k];
                 r2f += fv * fv;
             }
-            const bool inr = b0 + (uint32_t)lane < s1 && fits && r2f >= flo && r2f < fhi;
+            const bool inr = curok && fits && r2f >= flo && r2f < fhi;
             take(inr, dq, cur, curw);
         }
     }
@@ -262,7 +266,7 @@ constexpr bool pass_supported() { return 2 * stored_states(D, L) <= 128; }
 template <int D, int L>
 constexpr int pass_waves() { return D == 3 && (L == 4 || L == 5) ? 5 : 1; }
 
-template <int D, int L, bool PER>
+template <int D, int L, bool PER, bool CUBE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_waves<D, L>()))) void k_harmonic_pass(HarmArgs a)
 {
     constexpr int SLOTS = 2 * stored_states(D, L);
@@ -348,8 +352,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_waves<
                 double r2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < D; k++) {
-                    v[k] = __dmul_rn((double)dq[k], a.scale64[k]);
-                    r2 = __dadd_rn(r2, __dmul_rn(v[k], v[k]));
+                    v[k] = mul_rn((double)dq[k], a.scale64[k]);
+                    r2 = add_rn(r2, mul_rn(v[k], v[k]));
                 }
                 const bool valid = live && r2 >= elo && r2 < ehi;
                 row_pairs += (unsigned long long)__popcll(ballot(valid));
@@ -362,8 +366,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pass_waves<
                 harmonics<D, L>(u, valid ? wk : 0.f, [&](int slot, float val) { fs[slot] += val; });
                 if (++batches == kPassFoldBatches) fold();
             };
-            scan_shell<D, PER>(a, cs, qi, segs, lane, elo * (1.0 - 1e-9), ehi * (1.0 + 1e-9),
-                               (float)(elo * (1.0 - 1e-5)), (float)(ehi * (1.0 + 1e-5)),
+            // the FP32 bounds, in squared lattice units for a cube
+            const double fu = CUBE ? 1.0 / (a.scale64[0] * a.scale64[0]) : 1.0;
+            scan_shell<D, PER, CUBE>(a, cs, qi, segs, lane, elo * (1.0 - 1e-9), ehi * (1.0 + 1e-9),
+                                     (float)(elo * (1.0 - 1e-5) * fu), (float)(ehi * (1.0 + 1e-5) * fu),
                                [&](bool inr, const int (&dq)[D], const uint4 &cur, float curw) __attribute__((always_inline)) {
                 queue_append<D>(inr, dq, cur, curw, q4, qwx, qn);
                 if (qn >= 64) {

@@ -28,6 +28,23 @@ __host__ __device__ constexpr int stored_states(int D, int L)
                   : (L + 1) * (L + 2) * (L + 3) / 6;
 }
 
+// FP64 product and sum, each rounded on its own.  HIP's __dmul_rn and
+// __dadd_rn are the plain operators, which the compiler fuses into an FMA
+// under its default contraction; the pragma keeps these apart, so a squared
+// distance or a dot product takes the definition's arithmetic (as the FP64
+// oracle, built without FMA, does) and a bin is decided exactly as there.
+__device__ __forceinline__ double mul_rn(double x, double y)
+{
+#pragma clang fp contract(off)
+    return x * y;
+}
+
+__device__ __forceinline__ double add_rn(double x, double y)
+{
+#pragma clang fp contract(off)
+    return x + y;
+}
+
 // ---------------------------------------------------------------------------
 // Device workspace of one catalogue after the cell-list build.
 // ---------------------------------------------------------------------------
@@ -74,6 +91,7 @@ struct HarmArgs {
     int ncat;
     int64_t ncell_cat;
     int per_bin;              // 1: one pass per radial bin (k_harmonic_pass) where the instance has it
+    int cube;                 // 1: every axis has the same lattice scale (a periodic cube)
 };
 
 // ---------------------------------------------------------------------------

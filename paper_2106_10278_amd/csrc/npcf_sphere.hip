@@ -78,9 +78,9 @@ constexpr float kSphGuard = 1e-6f;  // FP32 cosines this close to an edge are de
 template <int D>
 __device__ __forceinline__ double dot_rn(const double (&p)[D + 1], const double *pos, int64_t n, int64_t k)
 {
-    double c = __dmul_rn(p[0], pos[k]);
+    double c = mul_rn(p[0], pos[k]);
 #pragma unroll
-    for (int x = 1; x <= D; x++) c = __dadd_rn(c, __dmul_rn(p[x], pos[x * n + k]));
+    for (int x = 1; x <= D; x++) c = add_rn(c, mul_rn(p[x], pos[x * n + k]));
     return c;
 }
 
