@@ -22,11 +22,13 @@ namespace npcf {
 namespace harm {
 
 constexpr int kPassSegCap = 256;      // candidate segments per 64 stencil rows (up to four per row)
-// queued batches between folds of the lanes' sums.  c2 (32 + 32 sampled
-// primaries, plain strict / conditioned per-multipole error; harmonic ms):
-// every 2 batches 5.7e-7 / 6.5e-8, 130.2 ms; 4: 8.0e-7 / 6.7e-8, 112.6 ms;
-// 8: 6.4e-7 / 1.2e-7, 104.6 ms
-constexpr int kPassFoldBatches = 8;
+// queued batches between folds of the lanes' sums (each lane adds one pair
+// per batch).  c2 (32 + 32 sampled primaries, plain strict / conditioned
+// per-multipole error; harmonic ms): every 2 batches 5.7e-7 / 6.5e-8, 130.2
+// ms; 4: 8.0e-7 / 6.7e-8, 112.6 ms; 8: 6.4e-7 / 1.2e-7, 104.6 ms.  With the
+// later scan changes: 8: 7.1e-7 / 1.0e-7, 75.5 ms; 16: 6.9e-7 / 1.6e-7,
+// 71.7 ms (c3 unchanged at 3.6e-7 strict)
+constexpr int kPassFoldBatches = 16;
 
 // Candidates of the shell rlo2 <= r^2 < rhi2 (physical units, FP64; rlo2 and
 // rhi2 taken slightly wide by the caller) through the cell list, tested
