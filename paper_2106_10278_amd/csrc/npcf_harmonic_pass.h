@@ -27,8 +27,10 @@ constexpr int kPassSegCap = 256;      // candidate segments per 64 stencil rows 
 // per-multipole error; harmonic ms): every 2 batches 5.7e-7 / 6.5e-8, 130.2
 // ms; 4: 8.0e-7 / 6.7e-8, 112.6 ms; 8: 6.4e-7 / 1.2e-7, 104.6 ms.  With the
 // later scan changes: 8: 7.1e-7 / 1.0e-7, 75.5 ms; 16: 6.9e-7 / 1.6e-7,
-// 71.7 ms (c3 unchanged at 3.6e-7 strict)
-constexpr int kPassFoldBatches = 16;
+// 71.7 ms, but on the bench's sample of 1054 primaries (half of them in the
+// clustered data, with more batches per bin) 16 gave 1.2e-6 strict against
+// 6.8e-7 at 8, over the plain bar of 1e-6: 8 stays
+constexpr int kPassFoldBatches = 8;
 
 // Candidates of the shell rlo2 <= r^2 < rhi2 (physical units, FP64; rlo2 and
 // rhi2 taken slightly wide by the caller) through the cell list, tested

@@ -25,7 +25,7 @@
 //    u_j = -<q, e_j(p)>, i.e. the Euclidean product of q with e_j(p) whose
 //    time component is negated; the self pair is excluded by index (<p, p>
 //    rounds with an error that grows as cosh^2 r).
-// A block is 8 waves, one primary each.  Once per launch the secondaries are
+// A block is 4 waves, one primary each.  Once per launch the secondaries are
 // put in spatial order (a counting sort by Hilbert cell of the embedding
 // coordinates: all D + 1 on the sphere, the D spatial ones in H^D, ranked
 // within a cell by catalogue index) and packed to FP32, and every chunk of 64
@@ -59,7 +59,10 @@ namespace npcf {
 
 namespace {
 
-constexpr int kSphWaves = 8;
+// waves per block, one primary each.  Blocks of 4 (was 8): c9 25.9 -> 25.2,
+// c10 57.6 -> 56.3, c11 22.9 -> 21.5 ms, and the 3-sphere kernel can then
+// run five waves per SIMD (sph_waves)
+constexpr int kSphWaves = 4;
 // queued batches between folds of the lanes' FP32 sums into FP64.  In
 // spatial order the pairs of a run of batches share bin and sign, so a
 // rounding in the fold weighs on the whole run: the fold comes after a fixed
@@ -314,8 +317,14 @@ __global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n
     }
 }
 
+// Waves per SIMD the compiler is held to: five for the one-bin 3-sphere
+// kernel (106 VGPRs become 96, eight values spill): c10 56.3 -> 51.0 ms.
+// In H^3 the same bound spills 29 values and gains nothing (21.5 -> 21.6).
+template <int D, int K, int G>
+constexpr int sph_waves() { return D == 3 && K > 0 && G == 1 ? 5 : 1; }
+
 template <int D, int L, int K, int G>
-__global__ __launch_bounds__(kSphWaves * 64) void k_sphere(SphereArgs a)
+__global__ __launch_bounds__(kSphWaves * 64) __attribute__((amdgpu_waves_per_eu(sph_waves<D, K, G>()))) void k_sphere(SphereArgs a)
 {
     // per wave: in-range pairs waiting for the harmonics (catalogue index,
     // weight (S^2; the FP64 weight is read at the harmonics on S^3), bin)

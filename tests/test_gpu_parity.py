@@ -492,3 +492,36 @@ def test_off_lattice_positions(D, N, lmax):
     if near == 0:
         assert pairs == pairs_ref
     _check(got, ref, "plain", condition_scale(wl2), f"off-lattice D={D} N={N}", strict=False)
+
+
+# periodic boxes with unequal sides: the flat kernels' general pre-test (a
+# scale per axis), not the instance for cubes, and the x cells sized from the
+# first side while the stencil rows run over the others
+NON_CUBIC = {
+    "D2": (2, 4, 4, [8.0, 11.0], 3.5, 5),
+    "D3": (3, 4, 3, [10.0, 14.0, 12.0], 4.5, 4),
+    "D3long": (3, 3, 4, [24.0, 10.0, 11.0], 4.5, 6),
+    "D4": (4, 3, 3, [9.0, 10.0, 11.0, 12.0], 4.0, 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NON_CUBIC))
+def test_non_cubic_periodic_box(name, monkeypatch):
+    """Pair counts equal the oracle's and the multipoles are within the plain
+    bar, on both flat harmonic kernels (per-bin passes and bin-sorted
+    staging)."""
+    D, N, lmax, box, rmax, nbins = NON_CUBIC[name]
+    rng = np.random.default_rng(500 + len(name) + D)
+    n = 500
+    pos = inputs.uniform(rng, n, box)
+    w = rng.uniform(-0.5, 1.5, size=n)
+    edges = np.linspace(rmax / (nbins + 1), rmax, nbins + 1)
+    wl = inputs.Workload(f"noncubic-{name}", D, N, lmax, edges, box, pos, w, n)
+    print(f"[case] non-cubic periodic box {name} {box}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    scale = condition_scale(wl)
+    for kernel in ("pass", "stage"):
+        monkeypatch.setenv("NPCF_HARMONIC", kernel)
+        got, pairs, _ = gpu_run(wl)
+        assert pairs == pairs_ref
+        _check(got, ref, "plain", scale, f"non-cubic {name} {kernel}", strict=False)
