@@ -196,11 +196,13 @@ def kernel_source_hash() -> str:
 
 def harmonic_kernel_name(D: int, lmax: int) -> str:
     """The flat harmonic-stage kernel a plan launches: one pass per radial
-    bin where the instance has it (at most 128 slots per bin: D = 4 up to
-    lmax 5), else the bin-sorted staging kernel; NPCF_HARMONIC=stage picks the
-    latter."""
+    bin by default for D = 2 and 3, the bin-sorted staging kernel for D = 4;
+    NPCF_HARMONIC=stage or =pass overrides (the per-bin kernel exists up to
+    128 slots per bin: D = 4 up to lmax 5)."""
     states = {2: lmax + 1, 3: (lmax + 1) * (lmax + 2) // 2, 4: (lmax + 1) * (lmax + 2) * (lmax + 3) // 6}[D]
-    if os.environ.get("NPCF_HARMONIC") == "stage" or 2 * states > 128:
+    env = os.environ.get("NPCF_HARMONIC")
+    per_bin = env == "pass" if env else D <= 3
+    if not per_bin or 2 * states > 128:
         return "k_harmonic"
     return "k_harmonic_pass"
 
