@@ -318,10 +318,12 @@ __global__ __launch_bounds__(256) void k_curved_caps(const float4 *pf, int64_t n
 }
 
 // Waves per SIMD the compiler is held to: five for the one-bin 3-sphere
-// kernel (106 VGPRs become 96, eight values spill): c10 56.3 -> 51.0 ms.
-// In H^3 the same bound spills 29 values and gains nothing (21.5 -> 21.6).
+// kernel (106 VGPRs become 96, eight values spill): c10 56.3 -> 51.0 ms;
+// eight for the one-bin 2-sphere kernel (78 VGPRs become 64, ten values
+// spill): c9 25.2 -> 23.4 ms (seven waves: 24.0 ms).  In H^3 five waves spill
+// 29 values and gain nothing (21.5 -> 21.6); H^2 keeps its own count too.
 template <int D, int K, int G>
-constexpr int sph_waves() { return D == 3 && K > 0 && G == 1 ? 5 : 1; }
+constexpr int sph_waves() { return K > 0 && G == 1 ? (D == 3 ? 5 : 8) : 1; }
 
 template <int D, int L, int K, int G>
 __global__ __launch_bounds__(kSphWaves * 64) __attribute__((amdgpu_waves_per_eu(sph_waves<D, K, G>()))) void k_sphere(SphereArgs a)
