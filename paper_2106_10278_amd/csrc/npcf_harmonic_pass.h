@@ -264,9 +264,10 @@ template <int D, int L>
 constexpr bool pass_supported() { return 2 * stored_states(D, L) <= 128; }
 
 // Waves per SIMD the compiler is held to.  D = 3 at lmax 4 and 5 would take
-// 100 and 108 VGPRs, four waves per SIMD; at 96 they run five (two values of
-// lmax 5 spill outside the pair loop, reloaded once per 64 stencil rows):
-// c2 harmonic 95.2 -> 87.1 ms.  Elsewhere no bound beyond the block size's.
+// 100 and 108 VGPRs, four waves per SIMD; at 96 they run five (at lmax 5 up
+// to four values spill, stored once per launch and reloaded per bin and per
+// 64 stencil rows, outside the pair loop): c2 harmonic 95.2 -> 87.1 ms.
+// Elsewhere no bound beyond the block size's.
 template <int D, int L>
 constexpr int pass_waves() { return D == 3 && (L == 4 || L == 5) ? 5 : 1; }
 
