@@ -160,3 +160,69 @@ def curved_plan(wl, width):
     plan.apply_tuning(curved_bins_per_pass=min(widths) if width == "narrow" else max(widths))
     return plan
 
+
+
+def _fma(a, b, c):
+    """a * b + c rounded once (exact rational arithmetic, then one rounding)."""
+    from fractions import Fraction
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def fused_distance_catalogue(seed=5, n_fill=200):
+    """A D = 3 periodic catalogue (box 1024, a power of two, so lattice offsets
+    times the lattice scale are exact in FP64) with one planted pair whose
+    squared distance, summed axis by axis with every product and sum rounded,
+    lies one ulp below the outermost squared edge, while the same sum with
+    the products fused into FMAs (the compiler's contraction of
+    x*x + y*y + z*z) lands on the edge: the definition counts the pair, the
+    fused form does not.  Returns (workload, r2 by the definition, r2 fused,
+    squared outer edge)."""
+    import math
+    from paper_2106_10278_amd import inputs
+    L = 1024.0
+    sc = L / 2.0 ** 32
+    rng = np.random.default_rng(seed)
+    for _ in range(100000):
+        d = rng.integers(2 ** 26, 2 ** 27, size=3) * rng.choice([-1, 1], size=3)
+        v = [float(x) * sc for x in d]
+        r2 = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]
+        r2f = _fma(v[2], v[2], _fma(v[1], v[1], v[0] * v[0]))
+        if not r2 < r2f:
+            continue
+        e = math.sqrt(r2f)
+        for step in (0, 1, -1, 2, -2):
+            ee = e
+            for _ in range(abs(step)):
+                ee = math.nextafter(ee, math.inf if step > 0 else -math.inf)
+            if ee * ee == r2f:
+                p = np.array([300.0, 400.0, 500.0])
+                q = p + np.array(v)
+                fill = inputs.uniform(rng, n_fill, [L] * 3)
+                pos = np.concatenate([p[:, None], q[:, None], fill], axis=1)
+                n = pos.shape[1]
+                w = rng.uniform(0.5, 1.5, size=n)
+                edges = np.array([ee / 3, 2 * ee / 3, ee])
+                wl = inputs.Workload("fused-distance", 3, 3, 2, edges, [L] * 3, pos, w, n)
+                return wl, r2, r2f, ee * ee
+    raise RuntimeError("no planted pair found")
+
+
+def pair_count_by_definition(wl):
+    """In-range ordered pairs (self pairs excluded) with the squared distance
+    summed axis by axis, every product and sum rounded (numpy applies no
+    contraction), minimum image in a periodic box."""
+    pos = np.asarray(wl.pos, dtype=np.float64)
+    box = np.asarray(wl.box, dtype=np.float64)
+    e2lo, e2hi = wl.edges[0] * wl.edges[0], wl.edges[-1] * wl.edges[-1]
+    n = pos.shape[1]
+    count = 0
+    for j in range(n):
+        r2 = np.zeros(n)
+        for k in range(wl.D):
+            v = pos[k] - pos[k, j]
+            v = v - box[k] * np.rint(v / box[k])
+            r2 = r2 + v * v
+        ok = (r2 >= e2lo) & (r2 < e2hi)
+        ok[j] = False
+        count += int(ok.sum())
+    return count

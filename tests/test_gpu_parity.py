@@ -525,3 +525,23 @@ def test_non_cubic_periodic_box(name, monkeypatch):
         got, pairs, _ = gpu_run(wl)
         assert pairs == pairs_ref
         _check(got, ref, "plain", scale, f"non-cubic {name} {kernel}", strict=False)
+
+
+def test_fp64_distance_not_fused(monkeypatch):
+    """The kernels' FP64 squared distance rounds every product and sum as the
+    definition (and the oracle) does: a planted pair one ulp inside the outer
+    edge by that arithmetic, and on the edge if the products were fused into
+    FMAs, is counted by both flat harmonic kernels (regression: the
+    compiler's default contraction had fused them)."""
+    from npcf_testutil import fused_distance_catalogue, pair_count_by_definition
+    wl, r2, r2f, e2 = fused_distance_catalogue()
+    assert r2 < e2 <= r2f
+    print(f"[case] fused distance r2 {r2!r} edge^2 {e2!r}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    assert pairs_ref == pair_count_by_definition(wl)
+    scale = condition_scale(wl)
+    for kernel in ("pass", "stage"):
+        monkeypatch.setenv("NPCF_HARMONIC", kernel)
+        got, pairs, _ = gpu_run(wl)
+        assert pairs == pairs_ref
+        _check(got, ref, "plain", scale, f"fused distance {kernel}", strict=False)

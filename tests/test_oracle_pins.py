@@ -1279,3 +1279,15 @@ def test_hyp_rejects_and_self_pair():
         oracle.npcf(3, 3, 1, np.array([1e-6, 1.0]), [1.0] * 3, pos, w, hyperbolic=True)
     with pytest.raises(ValueError):
         oracle.npcf(3, 3, 1, np.array([0.1, 1.0]), [0.0, 1.0, 1.0], pos, w, hyperbolic=True)
+
+
+def test_oracle_distance_is_not_fused():
+    """The oracle's squared distance rounds every product and sum (the
+    definition's arithmetic): on a planted pair whose fused sum lands on the
+    outer edge and whose rounded sum lies one ulp inside it, the oracle counts
+    the pair, as the plain numpy count does."""
+    from npcf_testutil import fused_distance_catalogue, pair_count_by_definition
+    wl, r2, r2f, e2 = fused_distance_catalogue()
+    assert r2 < e2 <= r2f   # the pair separates the two arithmetics
+    _, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w)
+    assert pairs == pair_count_by_definition(wl)
