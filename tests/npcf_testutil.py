@@ -226,3 +226,53 @@ def pair_count_by_definition(wl):
         ok[j] = False
         count += int(ok.sum())
     return count
+
+
+def fused_dot_sphere_catalogue(seed=9, n_fill=150):
+    """Points on the unit 2-sphere with one planted pair whose cosine, the
+    dot product summed left to right with every product and sum rounded,
+    lies one or more ulps above cos of the outermost edge, while the same sum
+    with the products fused into FMAs lands on it: the definition counts the
+    pair (cos e_last < c), the fused form does not.  Returns (workload,
+    cosine by the definition, fused cosine, cos of the outer edge)."""
+    import math
+    from paper_2106_10278_amd import inputs
+    rng = np.random.default_rng(seed)
+    for _ in range(100000):
+        p = inputs.sphere_points(rng, 1)[:, 0]
+        q = inputs.sphere_points(rng, 1)[:, 0]
+        c = (p[0] * q[0] + p[1] * q[1]) + p[2] * q[2]
+        cf = _fma(p[2], q[2], _fma(p[1], q[1], p[0] * q[0]))
+        if not (c > cf and -0.9 < cf < 0.5):
+            continue
+        e = math.acos(cf)
+        for step in (0, 1, -1, 2, -2, 3, -3):
+            ee = e
+            for _ in range(abs(step)):
+                ee = math.nextafter(ee, math.inf if step > 0 else -math.inf)
+            if math.cos(ee) == cf:
+                fill = inputs.sphere_points(rng, n_fill)
+                pos = np.concatenate([p[:, None], q[:, None], fill], axis=1)
+                n = pos.shape[1]
+                w = rng.uniform(0.5, 1.5, size=n)
+                edges = np.array([ee / 4, ee / 2, ee])
+                wl = inputs.Workload("fused-dot-sphere", 2, 3, 3, edges, [1.0, 1.0], pos, w, n, sphere=True)
+                return wl, c, cf, math.cos(ee)
+    raise RuntimeError("no planted pair found")
+
+
+def sphere_pair_count_by_definition(wl):
+    """In-range ordered pairs on the sphere (self pairs excluded): cosine
+    summed left to right with every product and sum rounded (numpy applies no
+    contraction), cos e_last < c <= cos e_0."""
+    import math
+    pos = np.asarray(wl.pos, dtype=np.float64)
+    chi, clo = math.cos(wl.edges[0]), math.cos(wl.edges[-1])
+    n = pos.shape[1]
+    count = 0
+    for j in range(n):
+        c = (pos[0, j] * pos[0] + pos[1, j] * pos[1]) + pos[2, j] * pos[2]
+        ok = (c <= chi) & (c > clo)
+        ok[j] = False
+        count += int(ok.sum())
+    return count

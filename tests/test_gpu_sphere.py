@@ -179,3 +179,21 @@ def test_c9_full_sphere_sampled(precision):
     assert cerr <= TOL[precision]
     # every c9 multipole has S/|zeta| <= 3.2: the strict bar holds on all of them
     assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("width", ["wide", "narrow"])
+def test_sphere_cosine_not_fused(width):
+    """The kernel's FP64 cosine rounds every product and sum as the definition
+    (and the oracle) does: a planted pair whose rounded cosine lies above cos
+    of the outer edge, and on it if the products were fused into FMAs, is
+    counted (regression: the compiler's default contraction had fused them)."""
+    from npcf_testutil import fused_dot_sphere_catalogue, sphere_pair_count_by_definition
+    wl, c, cf, clo = fused_dot_sphere_catalogue()
+    assert c > clo >= cf
+    print(f"[case] fused sphere cosine {width} c {c!r} cos(e_last) {clo!r}", flush=True)
+    ref, pairs_ref, _ = oracle_reported(wl)
+    assert pairs_ref == sphere_pair_count_by_definition(wl)
+    got, pairs, _ = gpu_run(wl, plan=curved_plan(wl, width))
+    assert pairs == pairs_ref
+    cerr, _ = conditioned_error(got, ref, condition_scale(wl))
+    assert cerr <= TOL["plain"]

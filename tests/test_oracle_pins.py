@@ -1291,3 +1291,14 @@ def test_oracle_distance_is_not_fused():
     assert r2 < e2 <= r2f   # the pair separates the two arithmetics
     _, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w)
     assert pairs == pair_count_by_definition(wl)
+
+
+def test_oracle_sphere_cosine_is_not_fused():
+    """The oracle's cosine on the sphere rounds every product and sum: a
+    planted pair whose rounded cosine lies above cos of the outer edge and
+    whose fused cosine lands on it is counted, as the plain numpy count does."""
+    from npcf_testutil import fused_dot_sphere_catalogue, sphere_pair_count_by_definition
+    wl, c, cf, clo = fused_dot_sphere_catalogue()
+    assert c > clo >= cf   # the pair separates the two arithmetics
+    _, pairs = oracle.npcf(wl.D, wl.N, wl.lmax, wl.edges, wl.box, wl.pos, wl.w, sphere=True)
+    assert pairs == sphere_pair_count_by_definition(wl)
