@@ -28,6 +28,7 @@ namespace npcf {
 namespace {
 
 constexpr int kJobsPerWave = 4;
+constexpr int kC3StageBytes = 48 * 1024;   // rows of a staged per step by the isotropic N = 3 kernel, at most
 
 // ---------------------------------------------------------------------------
 // N = 4
@@ -406,23 +407,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Couple4fSha
 }
 
 // ---------------------------------------------------------------------------
-// N = 3: job = (Lambda, part); part 0: Re, 1: Im (D = 2 only)
+// N = 3: job = (Lambda, part); part 0: Re, 1: Im (D = 2 only).  rs rows of a
+// per step (at most kRowsStep; fewer where rows are long, so that several
+// blocks share a CU's LDS) and jpw jobs per wave (at most kJobsPerWave; fewer
+// where there are few jobs, so that every wave of a block has work).
 // ---------------------------------------------------------------------------
 template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3(CoupleArgs a, int njobs, int nparts, const float *sfac)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3(CoupleArgs a, int njobs, int nparts, const float *sfac,
+                                                                                    int rs, int jpw)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
     float *Ast = reinterpret_cast<float *>(smem);
-    float *wst = Ast + kRowsStep * rowlen;
-    float *sfs = wst + kRowsStep;   // per-state factors, copied once (read per operand element)
-    const int njg = (njobs + 4 * kJobsPerWave - 1) / (4 * kJobsPerWave);
+    float *wst = Ast + rs * rowlen;
+    float *sfs = wst + rs;   // per-state factors, copied once (read per operand element)
+    const int njg = (njobs + 4 * jpw - 1) / (4 * jpw);
     int rb, jg;
     if (!block_work(a.n_rowblocks, njg, rb, jg)) return;
     for (int t = threadIdx.x; t < a.nstate; t += blockDim.x) sfs[t] = sfac[t];   // the row loop's first barrier orders it
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
-    const int job0 = jg * 4 * kJobsPerWave + wave * kJobsPerWave;
+    const int job0 = jg * 4 * jpw + wave * jpw;
 
     double acc64[kJobsPerWave][4];
 #pragma unroll
@@ -440,19 +445,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int kq = lane >> 4;
     const bool bok = n < a.nb;
 
-    for (int r0 = r_begin; r0 < r_end; r0 += kRowsStep) {
+    for (int r0 = r_begin; r0 < r_end; r0 += rs) {
         __syncthreads();
-        stage_rows(a, r0, r_end, Ast, wst);
+        stage_rows_n(a, r0, r_end, rs, Ast, wst);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kJobsPerWave; j++) {
             const int job = job0 + j;
-            if (job >= njobs) break;
+            if (j >= jpw || job >= njobs) break;
             const int lam = job / nparts;
             const int part_kind = (nparts == 2) ? (job % nparts) : 0;
             const CoupleGroup g = a.groups[a.lam_group_begin[lam]];
             const int kper = 2 * g.nst;   // K entries per primary: states x {re, im}
-            const int ktot = kRowsStep * kper;
+            const int ktot = rs * kper;
             for (int k0 = 0; k0 < ktot; k0 += 32) {
                 float Av[8], Bv[8];
 #pragma unroll
@@ -483,7 +488,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int j = 0; j < kJobsPerWave; j++) {
         const int job = job0 + j;
-        if (job >= njobs) break;
+        if (j >= jpw || job >= njobs) break;   // the next wave's jobs are not this wave's to write
         double *dst = a.partial + ((size_t)rb * njobs + job) * 256;
 #pragma unroll
         for (int v = 0; v < 4; v++) dst[(4 * kq + v) * 16 + n] = acc64[j][v];
@@ -723,11 +728,22 @@ hipError_t launch_couple_kernel(int N, int precision, const CoupleArgs &a, int n
         default: return hipErrorInvalidValue;
         }
     }
+    // isotropic N = 3: long rows (D = 4 at lmax 6: 6.7 KB per primary) stage
+    // fewer per step, so that three blocks (the kernel's three waves per SIMD)
+    // fit in a CU's LDS; few jobs (one per Lambda and part) spread over the
+    // block's four waves instead of filling the first ones
+    int rs = kRowsStep;
+    const int rowbytes = a.nb * 2 * a.nstate * 4;
+    while (rs > 1 && rs * rowbytes > kC3StageBytes) rs /= 2;
+    const int jpw = njobs <= 4 ? 1 : (njobs <= 8 ? 2 : kJobsPerWave);
+    const int njg3 = (njobs + 4 * jpw - 1) / (4 * jpw);
+    const int nblk3 = njg3 * ((a.n_rowblocks + kXcd - 1) / kXcd) * kXcd;
+    const int lds3 = lds - (kRowsStep - rs) * (rowbytes + 4);
     switch (precision) {
-    case 0: return launch_with_lds(k_couple3<0>, nblk, lds, s, a, njobs, nparts, sfac);
-    case 1: return launch_with_lds(k_couple3<1>, nblk, lds, s, a, njobs, nparts, sfac);
-    case 2: return launch_with_lds(k_couple3<2>, nblk, lds, s, a, njobs, nparts, sfac);
-    case 3: return launch_with_lds(k_couple3<3>, nblk, lds, s, a, njobs, nparts, sfac);
+    case 0: return launch_with_lds(k_couple3<0>, nblk3, lds3, s, a, njobs, nparts, sfac, rs, jpw);
+    case 1: return launch_with_lds(k_couple3<1>, nblk3, lds3, s, a, njobs, nparts, sfac, rs, jpw);
+    case 2: return launch_with_lds(k_couple3<2>, nblk3, lds3, s, a, njobs, nparts, sfac, rs, jpw);
+    case 3: return launch_with_lds(k_couple3<3>, nblk3, lds3, s, a, njobs, nparts, sfac, rs, jpw);
     default: return hipErrorInvalidValue;
     }
 }

@@ -169,6 +169,18 @@ __device__ __forceinline__ void stage_rows(const CoupleArgs &a, int r0, int r_en
     for (int t = threadIdx.x; t < kRowsStep; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
 }
 
+// The same for rs <= kRowsStep rows (kernels whose rows are long stage fewer
+// of them, so that more blocks fit in a CU's LDS).
+__device__ __forceinline__ void stage_rows_n(const CoupleArgs &a, int r0, int r_end, int rs, float *Ast, float *wst)
+{
+    const int rowlen = a.nb * 2 * a.nstate;
+    const int total = rs * rowlen;
+    const int r_lim = r_end - r0;
+    const float *src = a.A + (size_t)r0 * rowlen;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) Ast[t] = (t < r_lim * rowlen) ? src[t] : 0.f;
+    for (int t = threadIdx.x; t < rs; t += blockDim.x) wst[t] = (t < r_lim) ? a.wrow[r0 + t] : 0.f;
+}
+
 template <class T>
 __device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
 {
