@@ -298,8 +298,9 @@ npcf_status npcf_reset(npcf_plan_t plan);
 /* Release the plan and its device memory (synchronises first). NULL is a no-op. */
 npcf_status npcf_destroy(npcf_plan_t plan);
 
-/* Tuning knobs (0 keeps the current value): cell subdivision s (cells of
- * side >= r_max / s, 1..8), primaries per coupling block (rounded up to a
+/* Tuning knobs (0 keeps the current value): cell subdivision s (flat cells
+ * of side >= r_max / s, eight times thinner along x, the axis of a stencil
+ * row; 1..8), primaries per coupling block (rounded up to a
  * multiple of 16), and primaries per chunk (rows of a^b held at once; at most
  * the size chosen at plan time).  Synchronises; takes effect on the next
  * accumulate (a batch shape is captured again).  Errors: NPCF_E_INVALID
@@ -308,7 +309,7 @@ npcf_status npcf_set_tuning(npcf_plan_t plan, int cell_subdiv, int couple_block,
 
 /* Tile shapes and launch sizes of a plan (npcf_get_tuning, npcf_apply_tuning). */
 typedef struct {
-    int cell_subdiv;             /* cells of side >= r_max / s, 1..8 */
+    int cell_subdiv;             /* cells of side >= r_max / s (x eight times thinner), 1..8 */
     int couple_block;            /* primaries per coupling block (multiple of 16; 0: the automatic rule) */
     int64_t chunk_rows;          /* primaries per chunk (rows of a held at once) */
     int harmonic_blocks_per_cu;  /* persistent harmonic grid: blocks of four waves per compute unit, 1..32 */
