@@ -12,7 +12,8 @@ harmonic stage, coupling stage, FP64 reduction and finalisation
 Every coupling precision is timed on the same inputs: plain FP32, FP16 hi+lo
 (per-tile power-of-two scaling), BF16 hi+mid+lo and BF16 hi+lo.  The headline
 value is the fastest split-precision path whose per-multipole relative error
-against the FP64 oracle (on a sample of primaries) is within 1e-5; the plain
+against the FP64 oracle (on a sample of primaries) is within 1e-5, with a 10%
+margin for the sampling of primaries (at most 9e-6 on the sample); the plain
 path and the others are reported beside it with their errors.
 
 Prints one JSON line.
@@ -512,9 +513,11 @@ def main():
     if not args.no_cpu:
         cpu, errs = cpu_baseline(wl, factory, pos, w, args.cpu_sample, field, args.cpu_seconds)
 
-    # headline: the fastest split-precision path within 1e-5 of the oracle
-    # (without the oracle check: the FP16 hi+lo path, which carries 22 bits)
-    cands = [p for p in MIXED if p in results and (errs is None or errs[p]["max_rel_err"] <= 1e-5)]
+    # headline: the fastest split-precision path within 1e-5 of the oracle,
+    # with a 10% margin for the sample of primaries (BF16 hi+lo sits at the
+    # bar on c2: 9.4e-6 to 1.04e-5 over samples); without the oracle check,
+    # the FP16 hi+lo path, which carries 22 bits
+    cands = [p for p in MIXED if p in results and (errs is None or errs[p]["max_rel_err"] <= 0.9e-5)]
     if errs is None:
         cands = [p for p in ("mixed_fp16",) if p in results] or cands
     head = (max(cands, key=lambda p: results[p]["pairs_per_s"]) if cands
