@@ -84,8 +84,10 @@ __device__ __forceinline__ void part_operands(int part_kind, float2 s, float a3r
     }
 }
 
+// four waves per SIMD (FP16 took 134 VGPRs at three; at four it spills six
+// values): c3 coupling FP16 24.2 -> 20.2 ms, the others unchanged
 template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple4(CoupleArgs a, int njobs, int nparts)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_couple4(CoupleArgs a, int njobs, int nparts)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
@@ -500,8 +502,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // with part = Re (lam_part 0) or Im (1), the +-m terms of the basis folded
 // into c_t on the host, on MFMA with K = primaries x terms x {two real
 // products}.
+// four waves per SIMD (the BF16 x6 and FP16 forms took 130 and 128 VGPRs at
+// three): c6 coupling, fixed block size, BF16 x6 21.0 -> 17.9 ms
 template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_couple3t(CoupleArgs a, int njobs)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_couple3t(CoupleArgs a, int njobs)
 {
     extern __shared__ __align__(16) char smem[];
     const int rowlen = a.nb * 2 * a.nstate;
